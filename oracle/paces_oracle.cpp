@@ -1,0 +1,896 @@
+// paces_oracle.cpp -- plain FP64 CPU reference of the co-evolving-subspace
+// step for single-exciton Holstein lattices.
+//
+// TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the CPU
+// baseline of the benchmark.  It shares no code with the GPU library.  It is
+// written for obvious correctness, not speed: basis states are decoded into
+// (exciton site, occupation list) tuples, edited as tuples and re-packed;
+// sets are sorted key vectors with binary search; H_eff is CSR; the
+// propagator is a shifted Taylor series.
+//
+// Paper passages followed (cited by section / equation):
+//   model         Eqs. (tb), (holstein), extended to square and cubic lattices
+//                 as in Sec. "Application to vibronic nanoaggregates".
+//   neighbours    Eqs. (def_neighbor), (def_neighbor_k), (H_eff).
+//   truncation    Sec. "Truncation & post-adaptation detruncation".
+//   assembly      Sec. "Generating the effective Hamiltonian from the
+//                 effective Hilbert space".
+//   step          Sec. "Formal operator representation and notes on
+//                 parallelization": psi -> Q exp(-i P H P dt) psi.
+//   propagator    App. "The action of the exponential of a sparse matrix".
+//   key codec     App. "Lossless bit-level compression of state information".
+//   observables   Eq. (RMSD) populations; Eq. (init_state_spec) overlap.
+//
+// Where the paper leaves a choice open the reading taken is stated at the
+// point of use.
+#include "paces_oracle.h"
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace {
+
+using cplx = std::complex<double>;
+thread_local std::string g_err;
+
+int fail(const std::string& msg) {
+  g_err = msg;
+  return 1;
+}
+
+// ---------------------------------------------------------------------------
+// Bit-field codec (App. "Lossless bit-level compression of state
+// information").  A key is a B-bit unsigned integer held in W 64-bit words,
+// word 0 most significant.  Fields are listed most significant first and
+// packed without gaps, so the last field occupies the lowest bits.  A field
+// may straddle a word boundary; bits are moved one at a time so that no
+// special case is needed.
+// ---------------------------------------------------------------------------
+void set_bit(uint64_t* key, int W, int pos) {
+  key[W - 1 - pos / 64] |= (uint64_t(1) << (pos % 64));
+}
+int get_bit(const uint64_t* key, int W, int pos) {
+  return int((key[W - 1 - pos / 64] >> (pos % 64)) & 1u);
+}
+
+// offsets[f] = bit position (from the least significant end) of field f.
+void pack_bits(int nf, const int* widths, const int* offsets,
+               const uint64_t* values, int W, uint64_t* out) {
+  for (int w = 0; w < W; ++w) out[w] = 0;
+  for (int f = 0; f < nf; ++f)
+    for (int b = 0; b < widths[f]; ++b)
+      if ((values[f] >> b) & 1u) set_bit(out, W, offsets[f] + b);
+}
+
+uint64_t get_field(const uint64_t* key, int W, int off, int width) {
+  uint64_t v = 0;
+  for (int b = 0; b < width; ++b)
+    v |= uint64_t(get_bit(key, W, off + b)) << b;
+  return v;
+}
+
+int bits_for(int count) {  // smallest b with 2^b >= count
+  int b = 0;
+  while ((int64_t(1) << b) < count) ++b;
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+// Model: Eq. (holstein) on a lattice.  Sites are numbered row-major,
+// i = x + Lx*(y + Ly*z).  Each site carries V modes with cutoffs c_nu.
+// ---------------------------------------------------------------------------
+struct Model {
+  int ndim = 1, ext[3] = {1, 1, 1}, per[3] = {0, 0, 0};
+  int N = 1, V = 1, cut[4] = {0, 0, 0, 0};
+  double omega[4] = {0, 0, 0, 0}, g[4] = {0, 0, 0, 0}, J[3] = {0, 0, 0};
+  std::vector<double> eps;
+  // Key layout (reading of the compression appendix for this model):
+  // fields most significant first n_{0,0}..n_{0,V-1}, n_{1,0}, ...,
+  // n_{N-1,V-1}, then the exciton site j in the lowest bits.
+  int bnu[4] = {0, 0, 0, 0}, bj = 1, B = 0, W = 1, D = 0;
+  std::vector<int> nbr;  // [N][2*ndim]: +1 then -1 neighbour per axis, -1 none
+  std::vector<int> widths, offsets;  // per field, field order as above
+
+  int nfields() const { return N * V + 1; }
+  int slot_count() const { return 2 * ndim + 2 * V; }
+};
+
+struct State {  // decoded basis state
+  int j = 0;
+  std::vector<int> n;  // [N*V], site-major
+};
+
+void encode(const Model& m, const State& s, uint64_t* key) {
+  std::vector<uint64_t> vals(m.nfields());
+  for (int f = 0; f < m.N * m.V; ++f) vals[f] = uint64_t(s.n[f]);
+  vals[m.N * m.V] = uint64_t(s.j);
+  pack_bits(m.nfields(), m.widths.data(), m.offsets.data(), vals.data(), m.W,
+            key);
+}
+
+void decode(const Model& m, const uint64_t* key, State& s) {
+  s.n.assign(m.N * m.V, 0);
+  for (int f = 0; f < m.N * m.V; ++f)
+    s.n[f] = int(get_field(key, m.W, m.offsets[f], m.widths[f]));
+  s.j = int(get_field(key, m.W, m.offsets[m.N * m.V], m.widths[m.N * m.V]));
+}
+
+// Diagonal element eps_j + sum_nu omega_nu * T_nu with T_nu the total
+// occupation of mode nu (Eq. (holstein); no zero-point term), evaluated in
+// this order.
+double diagonal(const Model& m, const State& s) {
+  double d = m.eps[s.j];
+  for (int nu = 0; nu < m.V; ++nu) {
+    long T = 0;
+    for (int i = 0; i < m.N; ++i) T += s.n[i * m.V + nu];
+    d = d + m.omega[nu] * double(T);
+  }
+  return d;
+}
+
+// The D off-diagonal slots of a row, in a fixed order: for each axis the +1
+// hop then the -1 hop, then for each mode the lowering then the raising
+// term at the exciton site.  A slot exists iff its matrix element is
+// structurally nonzero (reading of Eq. (def_neighbor): "nonzero" is taken
+// structurally, so that the set does not depend on rounding).
+struct Slot {
+  bool exists = false;
+  State s;
+  double val = 0;
+};
+
+void slots_of(const Model& m, const State& s, std::vector<Slot>& out) {
+  out.assign(m.slot_count(), Slot());
+  int q = 0;
+  for (int a = 0; a < m.ndim; ++a)
+    for (int dir = 0; dir < 2; ++dir, ++q) {
+      int jn = m.nbr[s.j * 2 * m.ndim + 2 * a + dir];
+      if (jn < 0 || m.J[a] == 0.0) continue;
+      out[q].exists = true;
+      out[q].s = s;
+      out[q].s.j = jn;
+      out[q].val = m.J[a];  // Eq. (tb): J |j><j+1| + h.c.
+    }
+  for (int nu = 0; nu < m.V; ++nu) {
+    int n = s.n[s.j * m.V + nu];
+    // lowering: <n-1| a |n> = sqrt(n)
+    if (m.g[nu] != 0.0 && n > 0) {
+      out[q].exists = true;
+      out[q].s = s;
+      out[q].s.n[s.j * m.V + nu] = n - 1;
+      out[q].val = m.g[nu] * std::sqrt(double(n));
+    }
+    ++q;
+    // raising: <n+1| a^dag |n> = sqrt(n+1)
+    if (m.g[nu] != 0.0 && n < m.cut[nu]) {
+      out[q].exists = true;
+      out[q].s = s;
+      out[q].s.n[s.j * m.V + nu] = n + 1;
+      out[q].val = m.g[nu] * std::sqrt(double(n + 1));
+    }
+    ++q;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Key sets: flat arrays of W-word keys, compared as B-bit integers.
+// ---------------------------------------------------------------------------
+struct Keys {
+  int W = 1;
+  std::vector<uint64_t> d;
+  int64_t size() const { return int64_t(d.size()) / W; }
+  const uint64_t* at(int64_t i) const { return d.data() + i * W; }
+  void push(const uint64_t* k) { d.insert(d.end(), k, k + W); }
+};
+
+bool key_less(const uint64_t* a, const uint64_t* b, int W) {
+  for (int w = 0; w < W; ++w)
+    if (a[w] != b[w]) return a[w] < b[w];
+  return false;
+}
+bool key_eq(const uint64_t* a, const uint64_t* b, int W) {
+  for (int w = 0; w < W; ++w)
+    if (a[w] != b[w]) return false;
+  return true;
+}
+
+// Sorted permutation of k.
+std::vector<int64_t> sort_order(const Keys& k) {
+  std::vector<int64_t> idx(k.size());
+  for (int64_t i = 0; i < k.size(); ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+    return key_less(k.at(a), k.at(b), k.W);
+  });
+  return idx;
+}
+
+Keys sort_unique(const Keys& k) {
+  std::vector<int64_t> idx = sort_order(k);
+  Keys out;
+  out.W = k.W;
+  for (int64_t i = 0; i < int64_t(idx.size()); ++i)
+    if (i == 0 || !key_eq(k.at(idx[i]), k.at(idx[i - 1]), k.W))
+      out.push(k.at(idx[i]));
+  return out;
+}
+
+int64_t find_key(const Keys& sorted, const uint64_t* key) {
+  int64_t lo = 0, hi = sorted.size();
+  while (lo < hi) {
+    int64_t mid = (lo + hi) / 2;
+    if (key_less(sorted.at(mid), key, sorted.W))
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  if (lo < sorted.size() && key_eq(sorted.at(lo), key, sorted.W)) return lo;
+  return -1;
+}
+
+// Elements of sorted a that are not in sorted b.
+Keys set_minus(const Keys& a, const Keys& b) {
+  Keys out;
+  out.W = a.W;
+  for (int64_t i = 0; i < a.size(); ++i)
+    if (find_key(b, a.at(i)) < 0) out.push(a.at(i));
+  return out;
+}
+
+Keys set_union(const Keys& a, const Keys& b) {
+  Keys all;
+  all.W = a.W;
+  all.d = a.d;
+  all.d.insert(all.d.end(), b.d.begin(), b.d.end());
+  return sort_unique(all);
+}
+
+// ---------------------------------------------------------------------------
+// Neighbour ball: union over r = 0..k of N^(r)_M (Eqs. (def_neighbor_k),
+// (H_eff)) computed breadth first.  frontier[r] holds the states at graph
+// distance exactly r from M, so frontier[0] = M.
+// ---------------------------------------------------------------------------
+void expand(const Model& m, const Keys& M, int k, Keys& ball,
+            std::vector<Keys>& frontier) {
+  frontier.clear();
+  frontier.push_back(M);
+  ball = M;
+  const int D = m.slot_count(), W = m.W;
+  for (int r = 1; r <= k; ++r) {
+    const Keys& F = frontier.back();
+    Keys cand;
+    cand.W = W;
+    std::vector<uint64_t> buf(size_t(F.size()) * D * W, 0);
+    std::vector<uint8_t> ex(size_t(F.size()) * D, 0);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < F.size(); ++i) {
+      State s;
+      std::vector<Slot> sl;
+      decode(m, F.at(i), s);
+      slots_of(m, s, sl);
+      for (int q = 0; q < D; ++q)
+        if (sl[q].exists) {
+          ex[i * D + q] = 1;
+          encode(m, sl[q].s, &buf[(size_t(i) * D + q) * W]);
+        }
+    }
+    for (int64_t c = 0; c < int64_t(ex.size()); ++c)
+      if (ex[c]) cand.push(&buf[size_t(c) * W]);
+    Keys fresh = set_minus(sort_unique(cand), ball);
+    ball = set_union(ball, fresh);
+    frontier.push_back(fresh);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Effective Hamiltonian over a sorted set (Sec. "Generating the effective
+// Hamiltonian from the effective Hilbert space"): every row gets its
+// diagonal and one entry per existing slot whose target lies in the set.
+// Distinct slots of a row lead to distinct states, so no entry is
+// duplicated.  Columns are sorted within a row.
+// ---------------------------------------------------------------------------
+struct CSR {
+  int64_t n = 0;
+  std::vector<int64_t> rowptr, cols;
+  std::vector<double> vals;
+  double emin = 0, emax = 0;  // Gershgorin bounds of the spectrum
+};
+
+void build_csr(const Model& m, const Keys& S, CSR& H) {
+  const int D = m.slot_count();
+  const int64_t n = S.size();
+  H.n = n;
+  std::vector<std::vector<std::pair<int64_t, double>>> rows(n);
+  std::vector<double> lo(n), hi(n);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    State s;
+    std::vector<Slot> sl;
+    std::vector<uint64_t> key(m.W);
+    decode(m, S.at(i), s);
+    slots_of(m, s, sl);
+    const double d = diagonal(m, s);
+    rows[i].push_back({i, d});
+    double radius = 0;
+    for (int q = 0; q < D; ++q) {
+      if (!sl[q].exists) continue;
+      encode(m, sl[q].s, key.data());
+      int64_t c = find_key(S, key.data());
+      if (c < 0) continue;
+      rows[i].push_back({c, sl[q].val});
+      radius = radius + std::fabs(sl[q].val);
+    }
+    std::sort(rows[i].begin(), rows[i].end());
+    lo[i] = d - radius;
+    hi[i] = d + radius;
+  }
+  H.rowptr.assign(n + 1, 0);
+  H.cols.clear();
+  H.vals.clear();
+  for (int64_t i = 0; i < n; ++i) {
+    for (auto& e : rows[i]) {
+      H.cols.push_back(e.first);
+      H.vals.push_back(e.second);
+    }
+    H.rowptr[i + 1] = int64_t(H.cols.size());
+  }
+  // Gershgorin interval, widened by 1e-12 of its magnitude so that it
+  // strictly contains the spectrum (reading: the paper names no bound).
+  double emin = n ? lo[0] : 0.0, emax = n ? hi[0] : 0.0;
+  for (int64_t i = 1; i < n; ++i) {
+    emin = std::min(emin, lo[i]);
+    emax = std::max(emax, hi[i]);
+  }
+  const double pad = 1e-12 * (std::fabs(emax) + std::fabs(emin));
+  H.emin = emin - pad;
+  H.emax = emax + pad;
+}
+
+void spmv(const CSR& H, const std::vector<cplx>& x, std::vector<cplx>& y) {
+  y.assign(H.n, cplx(0, 0));
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < H.n; ++i) {
+    cplx acc(0, 0);
+    for (int64_t e = H.rowptr[i]; e < H.rowptr[i + 1]; ++e)
+      acc += H.vals[e] * x[H.cols[e]];
+    y[i] = acc;
+  }
+}
+
+double inf_norm(const std::vector<cplx>& v) {
+  double r = 0;
+  for (const cplx& z : v) r = std::max(r, std::abs(z));
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// exp(-i H dt) v by the Taylor series of App. "The action of the exponential
+// of a sparse matrix", applied term by term to the vector.  Two choices the
+// paper leaves open (it names only "a convergence criterion" and the
+// scaling of Al-Mohy & Higham):
+//   * H is shifted by sigma = (emax + emin)/2 and the step is split into
+//     ceil(a dt) substeps when a dt > 1, a = (emax - emin)/2, so that every
+//     substep's series converges fast;
+//   * a substep stops after the first term n with |term_n|_inf <=
+//     2^-60 |acc|_inf and |term_{n-1}|_inf <= 2^-50 |acc|_inf.
+// ---------------------------------------------------------------------------
+int expmv(const CSR& H, double dt, int max_terms, const std::vector<cplx>& v,
+          std::vector<cplx>& out, int& terms) {
+  const double sigma = 0.5 * (H.emax + H.emin);
+  const double a = 0.5 * (H.emax - H.emin);
+  int nsub = int(std::ceil(a * dt));
+  if (nsub < 1) nsub = 1;
+  const double h = dt / nsub;
+  std::vector<cplx> w = v, term, prev, y;
+  terms = 0;
+  for (int sub = 0; sub < nsub; ++sub) {
+    std::vector<cplx> acc = w;
+    term = w;
+    for (int n = 1;; ++n) {
+      if (n > max_terms)
+        return fail("Taylor series did not converge within max_terms");
+      prev = term;
+      spmv(H, term, y);
+      const cplx f(0.0, -h / n);
+      for (int64_t i = 0; i < H.n; ++i) {
+        term[i] = (y[i] - sigma * prev[i]) * f;
+        acc[i] += term[i];
+      }
+      ++terms;
+      const double an = inf_norm(acc);
+      if (inf_norm(term) <= std::ldexp(an, -60) &&
+          inf_norm(prev) <= std::ldexp(an, -50))
+        break;
+    }
+    w = acc;
+  }
+  const cplx phase = std::exp(cplx(0.0, -sigma * dt));
+  out.resize(H.n);
+  for (int64_t i = 0; i < H.n; ++i) out[i] = phase * w[i];
+  return 0;
+}
+
+// |c|^2 evaluated as fl(fl(re*re) + fl(im*im)); the build disables FMA
+// contraction so the threshold decision is reproducible.
+double weight(const cplx& c) {
+  const double a = c.real() * c.real();
+  const double b = c.imag() * c.imag();
+  return a + b;
+}
+
+struct Obs {
+  double f[ORC_OBS_NFIELDS];
+  std::vector<double> pop;
+};
+
+struct Params {
+  double dt = 0.01, theta = 0;
+  int k = 2, k_init = 2, max_terms = 200;
+};
+
+struct Sim {
+  const Model* m = nullptr;
+  Params p;
+  Keys S;                    // sorted current set
+  std::vector<cplx> psi;     // amplitudes aligned with S
+  Keys psi0_keys;            // sorted support of the initial state
+  std::vector<cplx> psi0;
+  int64_t steps = 0;
+  double t = 0, mass_total = 0;
+  bool fresh = true;         // next step is the first after init
+  // last step
+  Keys M;
+  std::vector<Keys> frontier;
+  std::vector<cplx> phi;
+  CSR H;
+  std::vector<Obs> obs;
+};
+
+// One step of Sec. "Formal operator representation and notes on
+// parallelization", with truncation placed before re-growth as in Sec.
+// "Truncation & post-adaptation detruncation":
+//   select M from psi (first step: all input states, order k_init; the
+//   paper grows the initial space with its own order m_init),
+//   S' = ball of radius k around M,
+//   phi = psi on S' (states of S outside S' are discarded, their weight
+//   is the step's discarded mass),
+//   psi' = exp(-i H_S' dt) phi.
+int sim_step(Sim& sim) {
+  const Model& m = *sim.m;
+  // select (threshold on |c|, as |c|^2 >= theta^2 in FP64)
+  Keys M;
+  M.W = m.W;
+  int k = sim.p.k;
+  if (sim.fresh) {
+    M = sim.S;
+    k = sim.p.k_init;
+  } else {
+    const double th2 = sim.p.theta * sim.p.theta;
+    for (int64_t i = 0; i < sim.S.size(); ++i)
+      if (weight(sim.psi[i]) >= th2) M.push(sim.S.at(i));
+  }
+  Keys ball;
+  std::vector<Keys> frontier;
+  expand(m, M, k, ball, frontier);
+  // transfer: post-adaptation detruncation
+  std::vector<cplx> phi(ball.size(), cplx(0, 0));
+  double mass = 0;
+  for (int64_t i = 0; i < sim.S.size(); ++i) {
+    int64_t r = find_key(ball, sim.S.at(i));
+    if (r >= 0)
+      phi[r] = sim.psi[i];
+    else
+      mass += weight(sim.psi[i]);
+  }
+  CSR H;
+  build_csr(m, ball, H);
+  std::vector<cplx> out;
+  int terms = 0;
+  if (expmv(H, sim.p.dt, sim.p.max_terms, phi, out, terms)) return 1;
+  sim.S = ball;
+  sim.psi = out;
+  sim.M = M;
+  sim.frontier = frontier;
+  sim.phi = phi;
+  sim.H = H;
+  sim.steps += 1;
+  sim.t = sim.t + sim.p.dt;
+  sim.mass_total += mass;
+  sim.fresh = false;
+  // observables at the new time
+  Obs o;
+  o.pop.assign(m.N, 0.0);
+  std::vector<cplx> hp;
+  spmv(H, out, hp);
+  double n2 = 0, en = 0;
+  for (int64_t i = 0; i < H.n; ++i) {
+    n2 += weight(out[i]);
+    en += (std::conj(out[i]) * hp[i]).real();
+    State s;
+    decode(m, ball.at(i), s);
+    o.pop[s.j] += weight(out[i]);
+  }
+  cplx a(0, 0);  // <psi0|psi(t)>, Eq. (init_state_spec) and below
+  for (int64_t i = 0; i < sim.psi0_keys.size(); ++i) {
+    int64_t r = find_key(ball, sim.psi0_keys.at(i));
+    if (r >= 0) a += std::conj(sim.psi0[i]) * out[r];
+  }
+  o.f[ORC_OBS_T] = sim.t;
+  o.f[ORC_OBS_NORM2] = n2;
+  o.f[ORC_OBS_ENERGY] = en;
+  o.f[ORC_OBS_A_RE] = a.real();
+  o.f[ORC_OBS_A_IM] = a.imag();
+  o.f[ORC_OBS_MASS_STEP] = mass;
+  o.f[ORC_OBS_MASS_TOTAL] = sim.mass_total;
+  o.f[ORC_OBS_NS] = double(ball.size());
+  o.f[ORC_OBS_NM] = double(M.size());
+  o.f[ORC_OBS_TERMS] = double(terms);
+  o.f[ORC_OBS_EMIN] = H.emin;
+  o.f[ORC_OBS_EMAX] = H.emax;
+  sim.obs.push_back(o);
+  return 0;
+}
+
+int load_state(const Model& m, int64_t n, const uint64_t* keys,
+               const double* amps, Keys& S, std::vector<cplx>& psi) {
+  Keys k;
+  k.W = m.W;
+  k.d.assign(keys, keys + n * m.W);
+  std::vector<int64_t> idx = sort_order(k);
+  S.W = m.W;
+  S.d.clear();
+  psi.clear();
+  for (int64_t i = 0; i < n; ++i) {
+    if (i > 0 && key_eq(k.at(idx[i]), k.at(idx[i - 1]), m.W))
+      return fail("duplicate basis state in the input");
+    S.push(k.at(idx[i]));
+    psi.push_back(cplx(amps[2 * idx[i]], amps[2 * idx[i] + 1]));
+  }
+  return 0;
+}
+
+int check_keys(const Model& m, int64_t n, const uint64_t* keys) {
+  // every field must decode to a valid value and no bit above B may be set
+  for (int64_t i = 0; i < n; ++i) {
+    const uint64_t* k = keys + i * m.W;
+    for (int pos = m.B; pos < 64 * m.W; ++pos)
+      if (get_bit(k, m.W, pos)) return fail("key has bits above B set");
+    State s;
+    decode(m, k, s);
+    if (s.j >= m.N) return fail("exciton site out of range");
+    for (int f = 0; f < m.N * m.V; ++f)
+      if (s.n[f] > m.cut[f % m.V]) return fail("occupation above cutoff");
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* orc_last_error(void) { return g_err.c_str(); }
+
+int orc_pack_fields(int32_t nfields, const int32_t* widths,
+                    const uint64_t* values, int32_t W, uint64_t* out) {
+  if (nfields < 0 || W < 1) return fail("bad arguments");
+  std::vector<int> wd(nfields), off(nfields);
+  int pos = 0;
+  for (int f = nfields - 1; f >= 0; --f) {
+    if (widths[f] < 0 || widths[f] > 64) return fail("bad field width");
+    if (widths[f] < 64 && (values[f] >> widths[f]) != 0)
+      return fail("value does not fit its field");
+    wd[f] = widths[f];
+    off[f] = pos;
+    pos += widths[f];
+  }
+  if (pos > 64 * W) return fail("fields do not fit in W words");
+  pack_bits(nfields, wd.data(), off.data(), values, W, out);
+  return 0;
+}
+
+int orc_model_create(const orc_model_desc* d, void** out) {
+  if (!d || !out) return fail("null argument");
+  Model* m = new Model();
+  m->ndim = d->ndim;
+  if (m->ndim < 1 || m->ndim > 3) {
+    delete m;
+    return fail("ndim must be 1..3");
+  }
+  m->N = 1;
+  for (int a = 0; a < 3; ++a) {
+    m->ext[a] = a < m->ndim ? d->extent[a] : 1;
+    m->per[a] = a < m->ndim ? (d->periodic[a] != 0) : 0;
+    m->J[a] = a < m->ndim ? d->J[a] : 0.0;
+    if (m->ext[a] < 1 || (m->per[a] && m->ext[a] < 3)) {
+      delete m;
+      return fail("extent must be >= 1, and >= 3 when periodic");
+    }
+    m->N *= m->ext[a];
+  }
+  if (m->N >= 65536) {
+    delete m;
+    return fail("too many sites");
+  }
+  m->V = d->n_modes;
+  if (m->V < 1 || m->V > 4) {
+    delete m;
+    return fail("n_modes must be 1..4");
+  }
+  for (int nu = 0; nu < m->V; ++nu) {
+    m->cut[nu] = d->cutoff[nu];
+    m->omega[nu] = d->omega[nu];
+    m->g[nu] = d->g[nu];
+    if (m->cut[nu] < 1 || m->cut[nu] > 255) {
+      delete m;
+      return fail("cutoff must be 1..255");
+    }
+    m->bnu[nu] = bits_for(m->cut[nu] + 1);
+  }
+  m->eps.assign(m->N, 0.0);
+  if (d->eps)
+    for (int i = 0; i < m->N; ++i) m->eps[i] = d->eps[i];
+  m->bj = std::max(1, bits_for(m->N));
+  // fields: occupations site-major most significant first, j last
+  m->widths.clear();
+  for (int i = 0; i < m->N; ++i)
+    for (int nu = 0; nu < m->V; ++nu) m->widths.push_back(m->bnu[nu]);
+  m->widths.push_back(m->bj);
+  m->offsets.assign(m->widths.size(), 0);
+  int pos = 0;
+  for (int f = int(m->widths.size()) - 1; f >= 0; --f) {
+    m->offsets[f] = pos;
+    pos += m->widths[f];
+  }
+  m->B = pos;
+  m->W = (m->B + 63) / 64;
+  m->D = m->slot_count();
+  // nearest neighbours per axis, +1 then -1
+  m->nbr.assign(size_t(m->N) * 2 * m->ndim, -1);
+  for (int i = 0; i < m->N; ++i) {
+    int c[3] = {i % m->ext[0], (i / m->ext[0]) % m->ext[1],
+                i / (m->ext[0] * m->ext[1])};
+    for (int a = 0; a < m->ndim; ++a)
+      for (int dir = 0; dir < 2; ++dir) {
+        int cc[3] = {c[0], c[1], c[2]};
+        cc[a] += dir == 0 ? 1 : -1;
+        if (cc[a] < 0 || cc[a] >= m->ext[a]) {
+          if (!m->per[a]) continue;
+          cc[a] = (cc[a] + m->ext[a]) % m->ext[a];
+        }
+        m->nbr[size_t(i) * 2 * m->ndim + 2 * a + dir] =
+            cc[0] + m->ext[0] * (cc[1] + m->ext[1] * cc[2]);
+      }
+  }
+  *out = m;
+  return 0;
+}
+
+void orc_model_destroy(void* m) { delete static_cast<Model*>(m); }
+
+int orc_model_info(const void* mp, int32_t* N, int32_t* W, int32_t* D,
+                   int32_t* B) {
+  const Model* m = static_cast<const Model*>(mp);
+  if (!m) return fail("null model");
+  if (N) *N = m->N;
+  if (W) *W = m->W;
+  if (D) *D = m->D;
+  if (B) *B = m->B;
+  return 0;
+}
+
+int orc_pack(const void* mp, int64_t n, const int32_t* exc,
+             const uint16_t* occ, uint64_t* keys) {
+  const Model* m = static_cast<const Model*>(mp);
+  if (!m || n < 0) return fail("bad arguments");
+  for (int64_t i = 0; i < n; ++i) {
+    State s;
+    s.j = exc[i];
+    if (s.j < 0 || s.j >= m->N) return fail("exciton site out of range");
+    s.n.resize(m->N * m->V);
+    for (int f = 0; f < m->N * m->V; ++f) {
+      s.n[f] = occ[i * m->N * m->V + f];
+      if (s.n[f] > m->cut[f % m->V]) return fail("occupation above cutoff");
+    }
+    encode(*m, s, keys + i * m->W);
+  }
+  return 0;
+}
+
+int orc_unpack(const void* mp, int64_t n, const uint64_t* keys, int32_t* exc,
+               uint16_t* occ) {
+  const Model* m = static_cast<const Model*>(mp);
+  if (!m || n < 0) return fail("bad arguments");
+  for (int64_t i = 0; i < n; ++i) {
+    State s;
+    decode(*m, keys + i * m->W, s);
+    exc[i] = s.j;
+    for (int f = 0; f < m->N * m->V; ++f)
+      occ[i * m->N * m->V + f] = uint16_t(s.n[f]);
+  }
+  return 0;
+}
+
+int orc_neighbors(const void* mp, int64_t n, const uint64_t* keys,
+                  uint64_t* keys_out, uint8_t* exists, double* vals,
+                  double* diag) {
+  const Model* m = static_cast<const Model*>(mp);
+  if (!m || n < 0) return fail("bad arguments");
+  if (check_keys(*m, n, keys)) return 1;
+  const int D = m->D, W = m->W;
+  for (int64_t i = 0; i < n; ++i) {
+    State s;
+    std::vector<Slot> sl;
+    decode(*m, keys + i * W, s);
+    slots_of(*m, s, sl);
+    diag[i] = diagonal(*m, s);
+    for (int q = 0; q < D; ++q) {
+      exists[i * D + q] = sl[q].exists ? 1 : 0;
+      vals[i * D + q] = sl[q].exists ? sl[q].val : 0.0;
+      uint64_t* k = keys_out + (i * D + q) * W;
+      for (int w = 0; w < W; ++w) k[w] = 0;
+      if (sl[q].exists) encode(*m, sl[q].s, k);
+    }
+  }
+  return 0;
+}
+
+int orc_sim_create(const void* mp, const orc_params* p, int64_t n,
+                   const int32_t* exc, const uint16_t* occ,
+                   const double* coef, void** out) {
+  const Model* m = static_cast<const Model*>(mp);
+  if (!m || !p || !out || n < 1) return fail("bad arguments");
+  if (p->k < 0 || p->k_init < 0 || !(p->dt > 0) || !(p->theta >= 0))
+    return fail("bad run parameters");
+  std::vector<uint64_t> keys(size_t(n) * m->W);
+  if (orc_pack(mp, n, exc, occ, keys.data())) return 1;
+  Sim* s = new Sim();
+  s->m = m;
+  s->p.dt = p->dt;
+  s->p.k = p->k;
+  s->p.k_init = p->k_init;
+  s->p.theta = p->theta;
+  s->p.max_terms = p->max_terms > 0 ? p->max_terms : 200;
+  if (load_state(*m, n, keys.data(), coef, s->S, s->psi)) {
+    delete s;
+    return 1;
+  }
+  s->psi0_keys = s->S;
+  s->psi0 = s->psi;
+  s->M.W = s->S.W = m->W;
+  *out = s;
+  return 0;
+}
+
+void orc_sim_destroy(void* s) { delete static_cast<Sim*>(s); }
+
+int orc_sim_step(void* sp, int64_t n_steps) {
+  Sim* s = static_cast<Sim*>(sp);
+  if (!s || n_steps < 0) return fail("bad arguments");
+  for (int64_t i = 0; i < n_steps; ++i)
+    if (sim_step(*s)) return 1;
+  return 0;
+}
+
+int orc_sim_set_state(void* sp, int64_t n, const uint64_t* keys,
+                      const double* amps, double t) {
+  Sim* s = static_cast<Sim*>(sp);
+  if (!s || n < 0) return fail("bad arguments");
+  if (check_keys(*s->m, n, keys)) return 1;
+  Keys S;
+  std::vector<cplx> psi;
+  if (load_state(*s->m, n, keys, amps, S, psi)) return 1;
+  s->S = S;
+  s->psi = psi;
+  s->t = t;
+  s->fresh = false;
+  return 0;
+}
+
+int orc_sim_size(const void* sp, int64_t* nS) {
+  const Sim* s = static_cast<const Sim*>(sp);
+  if (!s || !nS) return fail("bad arguments");
+  *nS = s->S.size();
+  return 0;
+}
+
+int orc_sim_get_state(const void* sp, uint64_t* keys, double* amps) {
+  const Sim* s = static_cast<const Sim*>(sp);
+  if (!s) return fail("bad arguments");
+  if (keys) std::memcpy(keys, s->S.d.data(), s->S.d.size() * 8);
+  if (amps)
+    for (int64_t i = 0; i < s->S.size(); ++i) {
+      amps[2 * i] = s->psi[i].real();
+      amps[2 * i + 1] = s->psi[i].imag();
+    }
+  return 0;
+}
+
+int orc_sim_get_phi(const void* sp, double* amps) {
+  const Sim* s = static_cast<const Sim*>(sp);
+  if (!s || !amps) return fail("bad arguments");
+  for (size_t i = 0; i < s->phi.size(); ++i) {
+    amps[2 * i] = s->phi[i].real();
+    amps[2 * i + 1] = s->phi[i].imag();
+  }
+  return 0;
+}
+
+int orc_sim_get_set(const void* sp, int32_t which, int32_t round, int64_t* n,
+                    uint64_t* keys) {
+  const Sim* s = static_cast<const Sim*>(sp);
+  if (!s || !n) return fail("bad arguments");
+  const Keys* k = nullptr;
+  if (which == ORC_SET_M)
+    k = &s->M;
+  else if (which == ORC_SET_S)
+    k = &s->S;
+  else if (which == ORC_SET_FRONTIER) {
+    if (round < 0 || round >= int(s->frontier.size()))
+      return fail("no such round");
+    k = &s->frontier[round];
+  } else
+    return fail("unknown set");
+  *n = k->size();
+  if (keys) std::memcpy(keys, k->d.data(), k->d.size() * 8);
+  return 0;
+}
+
+int orc_sim_num_obs(const void* sp, int64_t* n) {
+  const Sim* s = static_cast<const Sim*>(sp);
+  if (!s || !n) return fail("bad arguments");
+  *n = int64_t(s->obs.size());
+  return 0;
+}
+
+int orc_sim_obs(const void* sp, int64_t i, double* fields, double* pop) {
+  const Sim* s = static_cast<const Sim*>(sp);
+  if (!s || i < 0 || i >= int64_t(s->obs.size()))
+    return fail("bad arguments");
+  if (fields)
+    for (int f = 0; f < ORC_OBS_NFIELDS; ++f) fields[f] = s->obs[i].f[f];
+  if (pop)
+    for (size_t j = 0; j < s->obs[i].pop.size(); ++j) pop[j] = s->obs[i].pop[j];
+  return 0;
+}
+
+int orc_sim_csr(const void* sp, int64_t* nrows, int64_t* nnz, int64_t* rowptr,
+                int64_t* cols, double* vals) {
+  const Sim* s = static_cast<const Sim*>(sp);
+  if (!s) return fail("bad arguments");
+  if (nrows) *nrows = s->H.n;
+  if (nnz) *nnz = int64_t(s->H.cols.size());
+  if (rowptr)
+    std::memcpy(rowptr, s->H.rowptr.data(), s->H.rowptr.size() * 8);
+  if (cols) std::memcpy(cols, s->H.cols.data(), s->H.cols.size() * 8);
+  if (vals) std::memcpy(vals, s->H.vals.data(), s->H.vals.size() * 8);
+  return 0;
+}
+
+int orc_expmv(int64_t n, const int64_t* rowptr, const int64_t* cols,
+              const double* vals, double dt, double emin, double emax,
+              int32_t max_terms, const double* v_in, double* v_out,
+              int32_t* terms) {
+  CSR H;
+  H.n = n;
+  H.rowptr.assign(rowptr, rowptr + n + 1);
+  H.cols.assign(cols, cols + rowptr[n]);
+  H.vals.assign(vals, vals + rowptr[n]);
+  H.emin = emin;
+  H.emax = emax;
+  std::vector<cplx> v(n), out;
+  for (int64_t i = 0; i < n; ++i) v[i] = cplx(v_in[2 * i], v_in[2 * i + 1]);
+  int t = 0;
+  if (expmv(H, dt, max_terms > 0 ? max_terms : 200, v, out, t)) return 1;
+  for (int64_t i = 0; i < n; ++i) {
+    v_out[2 * i] = out[i].real();
+    v_out[2 * i + 1] = out[i].imag();
+  }
+  if (terms) *terms = t;
+  return 0;
+}
+
+}  // extern "C"
