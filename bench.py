@@ -1,0 +1,155 @@
+"""Benchmark of the co-evolving-subspace step on one MI355X.
+
+Workload: the 1D Holstein ring of 16 sites (one mode per site, omega 1,
+g 1.2, J -1, cutoff 12, k=0 Bloch start, dt 0.01, neighbour order 4,
+amplitude threshold 1e-8, complex128), synthetic inputs only.  A "step" is
+one full time step of the hot path: select, expand (4 rounds), merge,
+transfer, build, Chebyshev propagation and observables.  The run starts
+from the initial state; `--warmup` steps grow the subspace untimed, then
+exactly `--steps` steps are timed between stream synchronisations.
+
+value = sum over timed steps of |S| / wall time (basis-state updates/s).
+roofline: the middle Clenshaw term kernel (the dominant kernel), its
+algorithmic bytes per launch |S| (4A + 4D + 16) over its HIP-event
+duration on the step's stream.
+cpu_baseline: the CPU oracle continued from the GPU state at the start of
+the timed window, for a bounded number of steps.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--config", default="ring16")
+    ap.add_argument("--precision", type=int, default=64)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU "
+              "path (see DESIGN.md for how the step would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2603_07341_amd as P
+    import workloads as WL
+
+    torch.cuda.set_device(0)
+    cfg = dict(WL.CONFIGS[args.config])
+    cfg["precision"] = args.precision
+    params = WL.model_params(cfg)
+    run = WL.run_params(cfg)
+    exc, occ, coef = WL.initial_state(cfg)
+    model = P.Model(params)
+    stream = torch.cuda.current_stream()
+    sim = P.Sim(model, run, exc, occ, coef, stream=stream)
+    print("warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
+    sim.step(args.warmup, stream=stream)
+    torch.cuda.synchronize()
+    nS0 = sim.size(stream)
+    cpu_state = None
+    if not args.no_cpu:
+        cpu_state = sim.state(stream)
+    nrec0 = sim.num_records()
+    print("timing %d steps from |S| = %d" % (args.steps, nS0), file=sys.stderr,
+          flush=True)
+    sim.profile(True)
+    sim.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = sim.profile_get(stream)
+    sim.profile(False)
+    rec = sim.series(nrec0, args.steps, stream)
+    elapsed = t1 - t0
+    updates = float(rec[:, 7].sum())
+    value = updates / elapsed
+    A = 16 if args.precision == 64 else 8
+    D = model.D
+    n_term = prof["launches"]["term"]
+    term_ms = prof["ms"]["term"] / max(n_term, 1)
+    term_bytes = prof["term_bytes"] / max(n_term, 1)
+    achieved = term_bytes / (term_ms * 1e-3) / 1e9 if n_term else 0.0
+    stage_ms = {k: round(v, 3) for k, v in prof["ms"].items()}
+    out = {
+        "metric": "basis-state updates/s (|S|*steps/s)",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128" if args.precision == 64 else "c64",
+        "data": "synthetic",
+        "config": {"workload": "%s: %d-site Holstein ring, cutoff %d, g %g, "
+                               "J %g, k %d, theta %g, dt %g" % (
+                                   args.config, WL.n_sites(cfg), cfg["cutoff"][0],
+                                   cfg["g"][0], cfg["J"][0], cfg["k"],
+                                   cfg["theta"], cfg["dt"]),
+                   "timed_steps": [args.warmup, args.warmup + args.steps],
+                   "S_start": int(nS0), "S_end": int(rec[-1, 7]),
+                   "S_mean": updates / args.steps},
+        "roofline": {"bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_cheb_term (middle Clenshaw term)",
+                     "launches": n_term, "avg_ms": term_ms,
+                     "bytes_per_launch": term_bytes,
+                     "bytes_per_row": 4 * A + 4 * D + 16},
+        "stage_ms": stage_ms,
+        "terms_per_step": float(rec[:, 9].mean()),
+    }
+    if cpu_state is not None:
+        out["cpu_baseline"] = cpu_baseline(params, run, cpu_state, cfg,
+                                           args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(params, run, state, cfg, budget_s):
+    """The CPU oracle continued from the GPU state for as many whole steps
+    as fit in the budget (at least one)."""
+    from oracle import oracle as O
+    import workloads as WL
+    keys, amps = state
+    om = O.Model(params)
+    exc, occ, coef = WL.initial_state(cfg)
+    s = O.Sim(om, run, exc, occ, coef)
+    s.set_state(keys, amps, 0.0)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        s.step(1)
+        n += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    upd = sum(o["n_S"] for o in s.observations())
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": upd / el, "unit": "updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "%d step(s) continued from the GPU state at the start "
+                      "of the timed window (|S| %d -> %d), %.1f s" % (
+                          n, len(keys), int(s.observations()[-1]["n_S"]), el)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * paces.h -- C ABI of the MI355X co-evolving-subspace propagator.
+ *
+ * One time step of the method (paper: Sec. "Formal operator representation
+ * and notes on parallelization") maps a sparse state psi on a set S of basis
+ * states of a single-exciton Holstein lattice (Eqs. (tb), (holstein)) to
+ *
+ *     M    = { n in S : |psi_n| >= theta }             truncation
+ *     S'   = { states within graph distance k of M }   Eqs. (def_neighbor_k),
+ *                                                      (H_eff)
+ *     phi  = psi restricted to S'                       post-adaptation
+ *                                                      detruncation
+ *     psi' = exp(-i H_S' dt) phi                        exact in S'
+ *
+ * and records observables.  Every stage runs in hand-written HIP kernels on
+ * the GPU; nothing in this library falls back to the CPU.
+ *
+ * Conventions
+ *  - Every function returns paces_status; PACES_OK is 0.  The message of
+ *    the last failure on the calling thread is paces_last_error().
+ *  - Host arrays passed in are copied before the call returns; the library
+ *    keeps no caller pointer.  Host output arrays are sized by the caller.
+ *  - hip_stream is a hipStream_t passed as void* (NULL = default stream).
+ *    All device work of a sim is ordered on the stream given to each call.
+ *  - Keys at the boundary are canonical: W uint64 words per basis state,
+ *    word 0 most significant, fields most significant first
+ *    n_{0,0} .. n_{0,V-1}, n_{1,0}, .., n_{N-1,V-1}, then the exciton site
+ *    j; widths ceil(log2(cutoff+1)) per mode and max(1, ceil(log2 N)) for j
+ *    (App. "Lossless bit-level compression of state information").
+ *  - Amplitudes at the boundary are interleaved FP64 (re, im) pairs; in
+ *    FP32 mode they are widened on export and rounded on import.
+ *  - Row order of states returned by the library is unspecified but
+ *    deterministic; compare sets after sorting.
+ *  - Device errors (hash-table or capacity overflow, non-finite norm,
+ *    series longer than k_max_terms) are latched and reported by the next
+ *    call that synchronises; the sim then refuses further steps
+ *    (PACES_E_STATE) until paces_set_state.
+ *  - A sim is not thread-safe; distinct sims are independent.
+ */
+#ifndef PACES_H
+#define PACES_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PACES_ABI_VERSION 1
+
+typedef enum {
+  PACES_OK = 0,
+  PACES_E_ARG = 1,         /* invalid argument (synchronous)              */
+  PACES_E_OOM = 2,         /* device allocation failed                    */
+  PACES_E_CAPACITY = 3,    /* state or table capacity exceeded            */
+  PACES_E_NONFINITE = 4,   /* non-finite norm after propagation           */
+  PACES_E_PROPAGATOR = 5,  /* series needs more than k_max_terms terms    */
+  PACES_E_HIP = 6,         /* HIP runtime error                           */
+  PACES_E_STATE = 7,       /* sim is in an error state                    */
+  PACES_E_UNSUPPORTED = 8  /* valid request this build does not support   */
+} paces_status;
+
+const char* paces_last_error(void);
+int32_t paces_abi_version(void);
+
+typedef struct paces_model paces_model; /* immutable after load */
+typedef struct paces_sim paces_sim;     /* owns the device state of a run */
+
+/* Holstein lattice, Eq. (holstein) on 1D/2D/3D nearest-neighbour lattices
+ * with V modes per site (Sec. "Application to vibronic nanoaggregates"). */
+typedef struct {
+  int32_t ndim;        /* 1, 2 or 3                                        */
+  int32_t extent[3];   /* sites per axis; unused axes 1                    */
+  int32_t periodic[3]; /* wrap the axis; a periodic extent must be >= 3    */
+  int32_t n_modes;     /* V, 1..4                                          */
+  int32_t cutoff[4];   /* max occupation per mode, 1..255                  */
+  double omega[4];     /* mode frequencies                                 */
+  double g[4];         /* exciton-phonon couplings                         */
+  double J[3];         /* hopping per axis                                 */
+  const double* eps;   /* [N] site energies (host, copied); NULL = zeros   */
+} paces_model_desc;
+
+typedef struct {
+  double dt;           /* time step                                        */
+  int32_t k;           /* neighbour order of steps after the first (m)     */
+  int32_t k_init;      /* neighbour order of the first step (m_init)       */
+  double theta;        /* keep a row iff |c| >= theta, tested as
+                          re*re + im*im >= theta*theta in FP64, no FMA    */
+  int64_t cap_states;  /* initial row capacity hint (0 = automatic)        */
+  int32_t precision;   /* 64: complex128 amplitudes; 32: complex64 with
+                          FP64 scalars and reductions                      */
+  double tol;          /* series tail tolerance, 0 = 1e-16                 */
+  int32_t k_max_terms; /* limit on series terms, 0 = 128                   */
+  uint32_t obs_mask;   /* PACES_OBS_* bits; 0 = all                        */
+} paces_run_params;
+
+#define PACES_OBS_ENERGY 1u /* <psi|H_eff|psi> per step (one extra SpMV
+                               only when the series has a single term)    */
+
+typedef struct {
+  double t, norm2, energy, autocorr_re, autocorr_im, mass_step, mass_total;
+  int64_t n_S, n_M;
+  int32_t K;           /* Chebyshev terms used by the step                 */
+  double E_min, E_max; /* padded Gershgorin bounds of H_eff                */
+  const double* pop;   /* [N] exciton populations; owned by the sim,
+                          valid until the next call on it                  */
+} paces_obs;
+
+/* Number of doubles per record of paces_series: 12 scalars
+ * (t, norm2, energy, a_re, a_im, mass_step, mass_total, n_S, n_M, K,
+ * E_min, E_max) followed by the N populations. */
+int32_t paces_record_doubles(const paces_model* m);
+
+/* Load a model: validates the description and builds the neighbour table,
+ * the key layout and the g*sqrt(n) table on the host.  The tables are copied
+ * to the current device by the first paces_init_state on the model, so the
+ * host codec below works without a GPU. */
+paces_status paces_load_model(const paces_model_desc* desc, paces_model** out);
+paces_status paces_free_model(paces_model* m);
+/* N sites, W words per key, D slots per row, B key bits. */
+paces_status paces_model_info(const paces_model* m, int32_t* N, int32_t* W,
+                              int32_t* D, int32_t* B);
+/* Host codec: exc[n], occ[n*N*V] (site-major) <-> keys[n*W]. */
+paces_status paces_pack_keys(const paces_model* m, int64_t n,
+                             const int32_t* exc, const uint16_t* occ,
+                             uint64_t* keys);
+paces_status paces_unpack_keys(const paces_model* m, int64_t n,
+                               const uint64_t* keys, int32_t* exc,
+                               uint16_t* occ);
+
+/* Create a sim from an initial state given as an uncompressed occupation
+ * table (the paper's table A) plus coefficients coef[2*n] (re, im).
+ * Duplicate states are an error.  The first step uses every input state
+ * as M and grows it with k_init. */
+paces_status paces_init_state(const paces_model* m, const paces_run_params* p,
+                              int64_t n, const int32_t* exc,
+                              const uint16_t* occ, const double* coef,
+                              void* hip_stream, paces_sim** out);
+paces_status paces_free_sim(paces_sim* s);
+
+/* Advance n_steps time steps (asynchronous on the stream except where the
+ * host needs a device count to size the next launch). */
+paces_status paces_step(paces_sim* s, int64_t n_steps, void* hip_stream);
+/* Latest observation; synchronises the stream. */
+paces_status paces_observe(paces_sim* s, paces_obs* out, void* hip_stream);
+/* Number of recorded steps. */
+paces_status paces_num_records(paces_sim* s, int64_t* n);
+/* Copy records first..first+n-1 to host out[n*paces_record_doubles];
+ * synchronises. */
+paces_status paces_series(paces_sim* s, int64_t first, int64_t n,
+                          double* out, void* hip_stream);
+
+/* Current state: *n rows; keys[n*W], amps[2n] (host, may be NULL to query
+ * the size).  Synchronises. */
+paces_status paces_get_state(paces_sim* s, int64_t* n, uint64_t* keys,
+                             double* amps, void* hip_stream);
+/* Replace the current state (time t).  The next step selects from it with
+ * theta and grows M with k. */
+paces_status paces_set_state(paces_sim* s, int64_t n, const uint64_t* keys,
+                             const double* amps, double t, void* hip_stream);
+
+typedef enum {
+  PACES_SET_M = 0,        /* selected states of the last step            */
+  PACES_SET_S = 1,        /* current set                                 */
+  PACES_SET_FRONTIER = 2  /* states first reached in round r            */
+} paces_set;
+/* Keys of a set of the last step (keys NULL: size query).  Synchronises. */
+paces_status paces_get_set(paces_sim* s, int32_t which, int32_t round,
+                           int64_t* n, uint64_t* keys, void* hip_stream);
+/* phi of the last step (psi projected onto the new set), rows in the order
+ * of paces_get_set(PACES_SET_S); amps[2*nS].  Synchronises. */
+paces_status paces_get_phi(paces_sim* s, double* amps, void* hip_stream);
+
+/* Per-stage timing with HIP events recorded on the step's stream around
+ * every stage launch group.  Enabling costs a few microseconds per stage. */
+typedef enum {
+  PACES_STAGE_SELECT = 0,
+  PACES_STAGE_EXPAND = 1,   /* expansion rounds incl. the lookup pass     */
+  PACES_STAGE_TRANSFER = 2,
+  PACES_STAGE_BUILD = 3,    /* bounds + coefficients                      */
+  PACES_STAGE_PROPAGATE = 4,/* all Clenshaw launches                      */
+  PACES_STAGE_OBSERVE = 5,
+  PACES_STAGE_TERM = 6,     /* middle Clenshaw launches only              */
+  PACES_NUM_STAGES = 7
+} paces_stage;
+typedef struct {
+  double ms[PACES_NUM_STAGES];      /* summed event time                  */
+  int64_t launches[PACES_NUM_STAGES];
+  double term_bytes;                /* algorithmic bytes of the timed
+                                       middle Clenshaw launches          */
+  double rows_steps;                /* sum over steps of |S|              */
+} paces_profile;
+paces_status paces_profile_enable(paces_sim* s, int32_t on);
+/* Resolves pending events (synchronises) and returns the totals. */
+paces_status paces_profile_get(paces_sim* s, paces_profile* out,
+                               void* hip_stream);
+paces_status paces_profile_reset(paces_sim* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

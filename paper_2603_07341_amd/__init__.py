@@ -1,0 +1,287 @@
+"""MI355X co-evolving-subspace propagator: Python binding of libpaces.so.
+
+Argument marshalling only.  Every stage of the time step runs in the HIP
+kernels of the library; there is no CPU path.  torch is imported first so
+that the process uses the HIP runtime torch ships, and torch streams are
+passed to the library as plain hipStream_t handles.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+try:
+    import torch  # noqa: F401  (loads the HIP runtime before the library)
+except ImportError:  # pragma: no cover - torch is part of the image
+    torch = None
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpaces.so")
+
+OBS_FIELDS = ["t", "norm2", "energy", "a_re", "a_im", "mass_step",
+              "mass_total", "n_S", "n_M", "K", "E_min", "E_max"]
+SET_M, SET_S, SET_FRONTIER = 0, 1, 2
+STAGES = ["select", "expand", "transfer", "build", "propagate", "observe",
+          "term"]
+STATUS = {0: "OK", 1: "E_ARG", 2: "E_OOM", 3: "E_CAPACITY", 4: "E_NONFINITE",
+          5: "E_PROPAGATOR", 6: "E_HIP", 7: "E_STATE", 8: "E_UNSUPPORTED"}
+
+# Every symbol include/paces.h declares.
+EXPORTS = [
+    "paces_last_error", "paces_abi_version", "paces_record_doubles",
+    "paces_load_model", "paces_free_model", "paces_model_info",
+    "paces_pack_keys", "paces_unpack_keys", "paces_init_state",
+    "paces_free_sim", "paces_step", "paces_observe", "paces_num_records",
+    "paces_series", "paces_get_state", "paces_set_state", "paces_get_set",
+    "paces_get_phi", "paces_profile_enable", "paces_profile_get",
+    "paces_profile_reset",
+]
+
+
+class PacesError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class _Desc(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("extent", C.c_int32 * 3),
+                ("periodic", C.c_int32 * 3), ("n_modes", C.c_int32),
+                ("cutoff", C.c_int32 * 4), ("omega", C.c_double * 4),
+                ("g", C.c_double * 4), ("J", C.c_double * 3),
+                ("eps", C.POINTER(C.c_double))]
+
+
+class _Run(C.Structure):
+    _fields_ = [("dt", C.c_double), ("k", C.c_int32), ("k_init", C.c_int32),
+                ("theta", C.c_double), ("cap_states", C.c_int64),
+                ("precision", C.c_int32), ("tol", C.c_double),
+                ("k_max_terms", C.c_int32), ("obs_mask", C.c_uint32)]
+
+
+class _Obs(C.Structure):
+    _fields_ = [("t", C.c_double), ("norm2", C.c_double),
+                ("energy", C.c_double), ("autocorr_re", C.c_double),
+                ("autocorr_im", C.c_double), ("mass_step", C.c_double),
+                ("mass_total", C.c_double), ("n_S", C.c_int64),
+                ("n_M", C.c_int64), ("K", C.c_int32), ("E_min", C.c_double),
+                ("E_max", C.c_double), ("pop", C.POINTER(C.c_double))]
+
+
+class _Profile(C.Structure):
+    _fields_ = [("ms", C.c_double * 7), ("launches", C.c_int64 * 7),
+                ("term_bytes", C.c_double), ("rows_steps", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                "libpaces.so is not built; run __graft_entry__.build() or "
+                "python paper_2603_07341_amd/build.py")
+        _lib = C.CDLL(LIB_PATH)
+        _lib.paces_last_error.restype = C.c_char_p
+        _lib.paces_abi_version.restype = C.c_int32
+        _lib.paces_record_doubles.restype = C.c_int32
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise PacesError(rc, lib().paces_last_error().decode())
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def _stream(stream):
+    if stream is None:
+        if torch is not None and torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        return C.c_void_p(0)
+    if hasattr(stream, "cuda_stream"):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+class Model:
+    """A Holstein lattice (parameters as a plain dict, see workloads)."""
+
+    def __init__(self, params):
+        d = _Desc()
+        d.ndim = params["ndim"]
+        for a in range(3):
+            d.extent[a] = params["extent"][a]
+            d.periodic[a] = params["periodic"][a]
+            d.J[a] = params["J"][a]
+        d.n_modes = params["n_modes"]
+        for nu in range(4):
+            d.cutoff[nu] = params["cutoff"][nu]
+            d.omega[nu] = params["omega"][nu]
+            d.g[nu] = params["g"][nu]
+        self._eps = np.ascontiguousarray(params["eps"], dtype=np.float64)
+        d.eps = _p(self._eps, C.c_double)
+        h = C.c_void_p()
+        _check(lib().paces_load_model(C.byref(d), C.byref(h)))
+        self.h = h
+        N, W, D, B = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().paces_model_info(h, C.byref(N), C.byref(W), C.byref(D),
+                                      C.byref(B)))
+        self.N, self.W, self.D, self.B = N.value, W.value, D.value, B.value
+        self.V = params["n_modes"]
+        self.rec_doubles = lib().paces_record_doubles(h)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.paces_free_model(self.h)
+            self.h = None
+
+    def pack(self, exc, occ):
+        exc = np.ascontiguousarray(exc, dtype=np.int32)
+        occ = np.ascontiguousarray(occ, dtype=np.uint16)
+        n = len(exc)
+        keys = np.zeros(n * self.W, dtype=np.uint64)
+        _check(lib().paces_pack_keys(self.h, C.c_int64(n), _p(exc, C.c_int32),
+                                     _p(occ, C.c_uint16), _p(keys, C.c_uint64)))
+        return keys.reshape(n, self.W)
+
+    def unpack(self, keys):
+        keys = np.ascontiguousarray(keys, dtype=np.uint64).reshape(-1)
+        n = len(keys) // self.W
+        exc = np.zeros(n, dtype=np.int32)
+        occ = np.zeros(n * self.N * self.V, dtype=np.uint16)
+        _check(lib().paces_unpack_keys(self.h, C.c_int64(n),
+                                       _p(keys, C.c_uint64), _p(exc, C.c_int32),
+                                       _p(occ, C.c_uint16)))
+        return exc, occ.reshape(n, self.N * self.V)
+
+
+class Sim:
+    """Device state of one run on the current HIP device."""
+
+    def __init__(self, model, run, exc, occ, coef, stream=None, obs_mask=0,
+                 k_max_terms=0, tol=0.0):
+        self.model = model
+        r = _Run()
+        r.dt = run["dt"]
+        r.k = run["k"]
+        r.k_init = run["k_init"]
+        r.theta = run["theta"]
+        r.cap_states = int(run.get("cap_hint", 0))
+        r.precision = run.get("precision", 64)
+        r.tol = tol
+        r.k_max_terms = k_max_terms
+        r.obs_mask = obs_mask
+        exc = np.ascontiguousarray(exc, dtype=np.int32)
+        occ = np.ascontiguousarray(occ, dtype=np.uint16)
+        coef = np.ascontiguousarray(coef, dtype=np.float64)
+        h = C.c_void_p()
+        _check(lib().paces_init_state(model.h, C.byref(r), C.c_int64(len(exc)),
+                                      _p(exc, C.c_int32), _p(occ, C.c_uint16),
+                                      _p(coef, C.c_double), _stream(stream),
+                                      C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.paces_free_sim(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def step(self, n=1, stream=None):
+        _check(lib().paces_step(self.h, C.c_int64(n), _stream(stream)))
+
+    def observe(self, stream=None):
+        o = _Obs()
+        _check(lib().paces_observe(self.h, C.byref(o), _stream(stream)))
+        d = {f: getattr(o, f) for f in ["t", "norm2", "energy", "mass_step",
+                                        "mass_total", "n_S", "n_M", "K",
+                                        "E_min", "E_max"]}
+        d["a_re"], d["a_im"] = o.autocorr_re, o.autocorr_im
+        d["pop"] = np.ctypeslib.as_array(o.pop, shape=(self.model.N,)).copy()
+        return d
+
+    def num_records(self):
+        n = C.c_int64()
+        _check(lib().paces_num_records(self.h, C.byref(n)))
+        return n.value
+
+    def series(self, first=0, n=None, stream=None):
+        """Observation records as an array [n, 12 + N]."""
+        if n is None:
+            n = self.num_records() - first
+        out = np.zeros(n * self.model.rec_doubles, dtype=np.float64)
+        _check(lib().paces_series(self.h, C.c_int64(first), C.c_int64(n),
+                                  _p(out, C.c_double), _stream(stream)))
+        return out.reshape(n, self.model.rec_doubles)
+
+    def observations(self, stream=None):
+        """Per-step observation dicts, same fields as the oracle's."""
+        rec = self.series(stream=stream)
+        out = []
+        for r in rec:
+            d = dict(zip(OBS_FIELDS, r[:12].tolist()))
+            d["pop"] = r[12:].copy()
+            out.append(d)
+        return out
+
+    def size(self, stream=None):
+        n = C.c_int64()
+        _check(lib().paces_get_state(self.h, C.byref(n), None, None,
+                                     _stream(stream)))
+        return n.value
+
+    def state(self, stream=None):
+        """(keys [n, W] uint64 in row order, amplitudes [n] complex128)."""
+        n = self.size(stream)
+        keys = np.zeros(n * self.model.W, dtype=np.uint64)
+        amps = np.zeros(2 * n, dtype=np.float64)
+        nn = C.c_int64()
+        _check(lib().paces_get_state(self.h, C.byref(nn), _p(keys, C.c_uint64),
+                                     _p(amps, C.c_double), _stream(stream)))
+        return keys.reshape(n, self.model.W), amps.view(np.complex128)
+
+    def set_state(self, keys, amps, t=0.0, stream=None):
+        keys = np.ascontiguousarray(keys, dtype=np.uint64).reshape(-1)
+        amps = np.ascontiguousarray(np.asarray(amps, dtype=np.complex128)).view(np.float64)
+        n = len(keys) // self.model.W
+        _check(lib().paces_set_state(self.h, C.c_int64(n), _p(keys, C.c_uint64),
+                                     _p(amps, C.c_double), C.c_double(t),
+                                     _stream(stream)))
+
+    def get_set(self, which, rnd=0, stream=None):
+        n = C.c_int64()
+        _check(lib().paces_get_set(self.h, C.c_int32(which), C.c_int32(rnd),
+                                   C.byref(n), None, _stream(stream)))
+        keys = np.zeros(n.value * self.model.W, dtype=np.uint64)
+        _check(lib().paces_get_set(self.h, C.c_int32(which), C.c_int32(rnd),
+                                   C.byref(n), _p(keys, C.c_uint64),
+                                   _stream(stream)))
+        return keys.reshape(n.value, self.model.W)
+
+    def phi(self, stream=None):
+        n = self.size(stream)
+        amps = np.zeros(2 * n, dtype=np.float64)
+        _check(lib().paces_get_phi(self.h, _p(amps, C.c_double), _stream(stream)))
+        return amps.view(np.complex128)
+
+    def profile(self, on=True):
+        _check(lib().paces_profile_enable(self.h, C.c_int32(1 if on else 0)))
+
+    def profile_reset(self):
+        _check(lib().paces_profile_reset(self.h))
+
+    def profile_get(self, stream=None):
+        p = _Profile()
+        _check(lib().paces_profile_get(self.h, C.byref(p), _stream(stream)))
+        return {"ms": dict(zip(STAGES, list(p.ms))),
+                "launches": dict(zip(STAGES, list(p.launches))),
+                "term_bytes": p.term_bytes, "rows_steps": p.rows_steps}

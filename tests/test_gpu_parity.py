@@ -1,0 +1,149 @@
+"""GPU path vs CPU oracle, through the C ABI, on identical seeded inputs.
+
+Key sets (M, every frontier, S) must agree bit for bit; phi is a copy and
+must agree bit for bit; propagated amplitudes within 1e-10 relative (FP64)
+or 1e-5 (FP32); observables within tol * (|o| + scale)."""
+import numpy as np
+import pytest
+
+import paper_2603_07341_amd as P
+from oracle import oracle as O
+from tests.gpu_helpers import (assert_same_set, check_obs, make_pair,
+                               oracle_state, rel_err, sort_rows)
+import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+
+def step_both(gs, os_, keys, amps, t, k):
+    gs.set_state(keys, amps, t)
+    os_.set_state(keys, amps, t)
+    gs.step(1)
+    os_.step(1)
+    for which in (O.SET_M, O.SET_S):
+        assert_same_set(gs.get_set(which), os_.get_set(which), "set %d" % which)
+    for r in range(k + 1):
+        assert_same_set(gs.get_set(P.SET_FRONTIER, r),
+                        os_.get_set(O.SET_FRONTIER, r), "frontier %d" % r)
+    gk, ga = gs.state()
+    gphi = gs.phi()
+    ok, oa = os_.state()
+    ophi = os_.phi()
+    gk, ga, gphi = sort_rows(gk, ga, gphi)
+    assert np.array_equal(gk, ok)
+    # phi is a pure copy of psi entries: bit for bit
+    assert np.array_equal(gphi, ophi)
+    return ga, oa
+
+
+def test_ring4_full_run_matches_oracle():
+    cfg, gm, om, gs, os_ = make_pair("ring4")
+    steps = cfg["steps"]
+    gs.step(steps)
+    os_.step(steps)
+    gobs, oobs = gs.observations(), os_.observations()
+    assert len(gobs) == len(oobs) == steps
+    for g, o in zip(gobs, oobs):
+        check_obs(g, o, 1e-10, width=o["E_max"] - o["E_min"])
+        assert g["t"] == o["t"]
+        assert g["E_min"] == pytest.approx(o["E_min"], rel=1e-13, abs=1e-13)
+        assert g["E_max"] == pytest.approx(o["E_max"], rel=1e-13, abs=1e-13)
+    gk, ga = gs.state()
+    ok, oa = os_.state()
+    gk, ga = sort_rows(gk, ga)
+    assert np.array_equal(gk, ok)
+    assert rel_err(ga, oa) <= 1e-10
+    assert len(gk) == 2500  # the run reaches the whole sector
+
+
+@pytest.mark.parametrize("name,steps", [("ring16", 12), ("ring12", 10),
+                                        ("sq6x6", 4), ("cube4", 3)])
+def test_single_step_parity(name, steps):
+    keys, amps, t = oracle_state(name, steps)
+    cfg, gm, om, gs, os_ = make_pair(name, precision=64)
+    ga, oa = step_both(gs, os_, keys, amps, t, cfg["k"])
+    assert rel_err(ga, oa) <= 1e-10
+    go, oo = gs.observations()[-1], os_.observations()[-1]
+    check_obs(go, oo, 1e-10, width=oo["E_max"] - oo["E_min"])
+
+
+@pytest.mark.parametrize("name,steps", [("ring16", 12), ("sq6x6", 4),
+                                        ("cube4", 3)])
+def test_single_step_parity_fp32(name, steps):
+    # complex64 amplitudes, FP64 scalars and reductions; inputs chosen
+    # representable in FP32 so both sides select from identical weights
+    keys, amps, t = oracle_state(name, steps)
+    amps = amps.astype(np.complex64).astype(np.complex128)
+    cfg, gm, om, gs, os_ = make_pair(name, precision=32)
+    ga, oa = step_both(gs, os_, keys, amps, t, cfg["k"])
+    assert rel_err(ga, oa) <= 1e-5
+    go, oo = gs.observations()[-1], os_.observations()[-1]
+    check_obs(go, oo, 1e-5, width=oo["E_max"] - oo["E_min"])
+
+
+@pytest.mark.parametrize("theta", [0.0, 1e-6, 1e-3])
+@pytest.mark.parametrize("k", [0, 1, 3])
+def test_threshold_and_order_edge_cases(theta, k):
+    keys, amps, t = oracle_state("ring16", 8)
+    cfg, gm, om, gs, os_ = make_pair("ring16", theta=theta, k=k)
+    ga, oa = step_both(gs, os_, keys, amps, t, k)
+    assert rel_err(ga, oa) <= 1e-10
+
+
+def test_everything_truncated():
+    # theta above every amplitude: M and S are empty, all weight discarded
+    keys, amps, t = oracle_state("ring16", 5)
+    cfg, gm, om, gs, os_ = make_pair("ring16", theta=10.0)
+    gs.set_state(keys, amps, t)
+    os_.set_state(keys, amps, t)
+    gs.step(1)
+    os_.step(1)
+    assert gs.size() == 0 and os_.size() == 0
+    go, oo = gs.observations()[-1], os_.observations()[-1]
+    assert go["norm2"] == 0.0
+    assert go["mass_step"] == pytest.approx(oo["mass_step"], rel=1e-12)
+
+
+def test_single_state_and_long_run_parity():
+    cfg, gm, om, gs, os_ = make_pair("ring16")
+    for _ in range(4):
+        gs.step(10)
+        os_.step(10)
+        gk, ga = gs.state()
+        ok, oa = os_.state()
+        gk, ga = sort_rows(gk, ga)
+        assert np.array_equal(gk, ok)
+        assert rel_err(ga, oa) <= 1e-10
+    for g, o in zip(gs.observations(), os_.observations()):
+        check_obs(g, o, 1e-10, width=o["E_max"] - o["E_min"])
+
+
+def test_two_runs_are_bitwise_identical():
+    outs = []
+    for _ in range(2):
+        cfg, gm, om, gs, os_ = make_pair("ring16")
+        gs.step(15)
+        outs.append(gs.state())
+    assert np.array_equal(outs[0][0], outs[1][0])  # same row order too
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_series_limit_latches_error():
+    cfg = WL.CONFIGS["ring4"]
+    gm = P.Model(WL.model_params(cfg))
+    exc, occ, coef = WL.initial_state(cfg)
+    gs = P.Sim(gm, WL.run_params(cfg), exc, occ, coef, k_max_terms=2)
+    with pytest.raises(P.PacesError) as ei:
+        gs.step(1)
+    assert ei.value.status == 5
+    with pytest.raises(P.PacesError) as ei:
+        gs.step(1)
+    assert ei.value.status == 7
+
+
+def test_duplicate_input_rejected():
+    cfg = WL.CONFIGS["ring4"]
+    gm = P.Model(WL.model_params(cfg))
+    with pytest.raises(P.PacesError) as ei:
+        P.Sim(gm, WL.run_params(cfg), [0, 0], [0] * 8, [0.6, 0, 0.8, 0])
+    assert ei.value.status == 1

@@ -1,0 +1,67 @@
+"""Host-side checks of the GPU library that need no GPU: the shared object
+loads, exports every symbol of include/paces.h, and its host codec and
+model validation agree with the oracle.  No kernel is launched."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2603_07341_amd as P
+from oracle import oracle as O
+from tests import brute
+import workloads as WL
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "paces.h")).read()
+    return sorted(set(re.findall(r"\b(paces_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.lib()
+    declared = header_symbols()
+    assert declared, "no declarations found"
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(P.EXPORTS) == declared
+    assert lib.paces_abi_version() == 1
+
+
+@pytest.mark.parametrize("name", ["ring4", "ring16", "sq6x6", "cube4", "ring12"])
+def test_host_codec_matches_oracle(name):
+    cfg = WL.CONFIGS[name]
+    p = WL.model_params(cfg)
+    gm, om = P.Model(p), O.Model(p)
+    assert (gm.N, gm.W, gm.D, gm.B) == (om.N, om.W, om.D, om.B)
+    rng = np.random.default_rng(1)
+    n, V, N = 300, p["n_modes"], brute.sites(p)
+    exc = rng.integers(0, N, n)
+    occ = np.stack([rng.integers(0, p["cutoff"][f % V] + 1, n)
+                    for f in range(N * V)], axis=1)
+    k1, k2 = gm.pack(exc, occ), om.pack(exc, occ)
+    assert np.array_equal(k1, k2)
+    e, o = gm.unpack(k1)
+    assert np.array_equal(e, exc) and np.array_equal(o, occ)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(ndim=0), dict(ndim=1, extent=[2, 1, 1], periodic=[1, 0, 0]),
+    dict(n_modes=5), dict(cutoff=[0, 0, 0, 0]), dict(cutoff=[300, 0, 0, 0]),
+])
+def test_model_validation_rejects(bad):
+    p = WL.model_params(WL.CONFIGS["ring4"])
+    p.update(bad)
+    with pytest.raises(P.PacesError) as ei:
+        P.Model(p)
+    assert ei.value.status == 1
+
+
+def test_pack_rejects_out_of_range():
+    gm = P.Model(WL.model_params(WL.CONFIGS["ring4"]))
+    with pytest.raises(P.PacesError):
+        gm.pack([4], [0, 0, 0, 0])
+    with pytest.raises(P.PacesError):
+        gm.pack([0], [0, 5, 0, 0])
