@@ -36,6 +36,9 @@ def main():
     ap.add_argument("--precision", type=int, default=64)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (a "
+                         "known-size reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU "
@@ -49,6 +52,13 @@ def main():
     import workloads as WL
 
     torch.cuda.set_device(0)
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg = dict(WL.CONFIGS[args.config])
     cfg["precision"] = args.precision
     params = WL.model_params(cfg)
@@ -114,7 +124,7 @@ def main():
                      "kernel": "k_cheb_term (middle Clenshaw term)",
                      "launches": n_term, "avg_ms": term_ms,
                      "bytes_per_launch": term_bytes,
-                     "bytes_per_row": 4 * A + 4 * D + 16},
+                     "bytes_per_row": 4 * A + 4 * D + (8 if model.V <= 2 else 16)},
         "stage_ms": stage_ms,
         "terms_per_step": float(rec[:, 9].mean()),
     }

@@ -28,7 +28,8 @@ enum : int {
   kErrTableFull = 1,
   kErrCapacity = 2,
   kErrNonFinite = 4,
-  kErrTerms = 8,
+  kErrTerms = 8,       // series longer than the allowed maximum
+  kErrNeedTerms = 16,  // more series launches needed than enqueued
 };
 
 // Model constants passed by value to every kernel.
@@ -47,20 +48,37 @@ struct DevModel {
   uint32_t eph_mask;    // bit nu set iff g[nu] != 0
 };
 
-// Per-row payload: exciton site (bits 0..15) and the occupations of each
-// mode at the exciton site (8 bits per mode from bit 16).
-__device__ __forceinline__ int pay_site(uint64_t p) { return int(p & 0xFFFFu); }
+// Per-row payload, one 64-bit word: exciton site j in bits 0..11, the
+// occupation of each mode at the exciton site in 8-bit fields from bit 12,
+// and, for at most two modes, the total occupation T_nu of each mode in
+// 16-bit fields from bit 28.  With more modes the totals live in a second
+// word per row (16 bits per mode).  The diagonal eps_j + sum_nu omega_nu T_nu
+// is recomputed from these integers wherever it is needed.
+constexpr int kPaySiteBits = 12;
+__device__ __forceinline__ int pay_site(uint64_t p) { return int(p & 0xFFFu); }
 __device__ __forceinline__ int pay_occ(uint64_t p, int nu) {
-  return int((p >> (16 + 8 * nu)) & 0xFFu);
+  return int((p >> (12 + 8 * nu)) & 0xFFu);
 }
-__device__ __forceinline__ uint64_t make_pay(int j, const int* nj, int V) {
-  uint64_t p = uint64_t(j);
-  for (int nu = 0; nu < V; ++nu) p |= uint64_t(nj[nu]) << (16 + 8 * nu);
-  return p;
-}
-// Per-row total occupation of each mode, 16 bits per mode.
 __device__ __forceinline__ int tot_of(uint64_t t, int nu) {
   return int((t >> (16 * nu)) & 0xFFFFu);
+}
+// Total occupation of mode nu: from the payload (V <= 2) or the totals word.
+__device__ __forceinline__ int row_total(int V, uint64_t pay, uint64_t tot,
+                                         int nu) {
+  return V <= 2 ? int((pay >> (28 + 16 * nu)) & 0xFFFFu) : tot_of(tot, nu);
+}
+__device__ __forceinline__ uint64_t make_pay(int V, int j, const int* nj,
+                                             const int* T) {
+  uint64_t p = uint64_t(j);
+  for (int nu = 0; nu < V; ++nu) p |= uint64_t(nj[nu]) << (12 + 8 * nu);
+  if (V <= 2)
+    for (int nu = 0; nu < V; ++nu) p |= uint64_t(T[nu]) << (28 + 16 * nu);
+  return p;
+}
+__device__ __forceinline__ uint64_t make_tot(int V, const int* T) {
+  uint64_t t = 0;
+  for (int nu = 0; nu < V; ++nu) t |= uint64_t(T[nu]) << (16 * nu);
+  return t;
 }
 
 // Bit offset (from the least significant end) of field (site i, mode nu).
@@ -200,31 +218,32 @@ __device__ __forceinline__ void slot_row_info(const DevModel& m,
                                               uint64_t pay, uint64_t tot, int s,
                                               uint64_t& pay_out,
                                               uint64_t& tot_out) {
-  int nj[kMaxV];
+  int nj[kMaxV], T[kMaxV];
+  for (int nu = 0; nu < m.V; ++nu) T[nu] = row_total(m.V, pay, tot, nu);
+  int j = pay_site(pay);
   if (s < 2 * m.ndim) {
-    const int jn = int(target[W - 1] & ((uint64_t(1) << m.bj) - 1));
+    j = int(target[W - 1] & ((uint64_t(1) << m.bj) - 1));
     for (int nu = 0; nu < m.V; ++nu)
-      nj[nu] = int(get_field<W>(target, field_off(m, jn, nu), m.bnu[nu]));
-    pay_out = make_pay(jn, nj, m.V);
-    tot_out = tot;
-    return;
+      nj[nu] = int(get_field<W>(target, field_off(m, j, nu), m.bnu[nu]));
+  } else {
+    const int e = s - 2 * m.ndim, nu = e >> 1;
+    const int delta = (e & 1) ? 1 : -1;
+    for (int q = 0; q < m.V; ++q) nj[q] = pay_occ(pay, q);
+    nj[nu] += delta;
+    T[nu] += delta;
   }
-  const int e = s - 2 * m.ndim, nu = e >> 1;
-  const int delta = (e & 1) ? 1 : -1;
-  for (int q = 0; q < m.V; ++q) nj[q] = pay_occ(pay, q);
-  nj[nu] += delta;
-  pay_out = make_pay(pay_site(pay), nj, m.V);
-  tot_out = uint64_t(int64_t(tot) + (int64_t(delta) << (16 * nu)));
+  pay_out = make_pay(m.V, j, nj, T);
+  tot_out = make_tot(m.V, T);
 }
 
 // Diagonal eps_j + sum_nu omega_nu * T_nu, evaluated in this order with
-// separately rounded products (no contraction), like Eq. (holstein) read
+// separately rounded products (no contraction), as Eq. (holstein) reads
 // term by term.
 __device__ __forceinline__ double row_diag(const DevModel& m, uint64_t pay,
                                            uint64_t tot) {
   double d = m.eps[pay_site(pay)];
   for (int nu = 0; nu < m.V; ++nu)
-    d = __dadd_rn(d, __dmul_rn(m.omega[nu], double(tot_of(tot, nu))));
+    d = __dadd_rn(d, __dmul_rn(m.omega[nu], double(row_total(m.V, pay, tot, nu))));
   return d;
 }
 

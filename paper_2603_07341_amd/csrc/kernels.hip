@@ -1,10 +1,14 @@
 // kernels.hip -- HIP kernels of one co-evolving-subspace step on gfx950.
 //
-// The step is sparse, memory-bound gather/scatter: every kernel streams
-// rows with one row (or one row slot) per lane, wave64, 256-lane blocks,
-// and no matrix cores.  Reductions are deterministic: fixed lane-to-row
-// mapping, wave shuffles in a fixed order, and per-block partials summed in
-// block order by a single block.
+// The step is sparse, memory-bound gather/scatter: kernels stream rows with
+// one row (or one row slot) per lane, wave64, 256-lane blocks, and no
+// matrix cores.  Row counts live in device memory (StepCtl); kernels run on
+// grid-stride grids, clamp counts to the allocated capacity and latch
+// overflows, and every kernel after a latching one returns at once when the
+// latch is set, so a failed step touches nothing out of bounds and leaves
+// the previous state intact for a retry.  Reductions are deterministic:
+// fixed lane-to-row mapping, wave shuffles in a fixed order, per-block
+// partials summed in block order.
 //
 // Stages (paper: Sec. "Formal operator representation and notes on
 // parallelization"):
@@ -25,6 +29,7 @@
 //              names series of SpMVs; Chebyshev replaces Taylor here)
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "kernels.hpp"
@@ -35,13 +40,25 @@ namespace {
 
 constexpr int kItems = 8;
 constexpr int kTile = kBlock * kItems;
+constexpr int kMaxGrid = kMaxPartials;
+constexpr int kFold = 256;  // blocks of the second reduction level
 
-inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) {
+  return (a + b - 1) / b;
+}
 
-inline int grid_for(int64_t n, int64_t cap = 1 << 20) {
-  int64_t g = cdiv(n, kBlock);
+// Grid for a grid-stride kernel over at most `bound` items.
+inline int grid_for(int64_t bound, int64_t cap = kMaxGrid) {
+  int64_t g = cdiv(bound, kBlock);
   if (g < 1) g = 1;
   if (g > cap) g = cap;
+  return int(g);
+}
+// Grid for a kernel striding over tiles of kTile items.
+inline int tiles_for(int64_t bound) {
+  int64_t g = cdiv(bound, kTile);
+  if (g < 1) g = 1;
+  if (g > 2048) g = 2048;
   return int(g);
 }
 
@@ -126,37 +143,46 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v,
   return base + x - v;
 }
 
-// ---- fills ------------------------------------------------------------------
+// ---- fills and step control -------------------------------------------------
 __global__ void __launch_bounds__(kBlock)
     k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
   for (int64_t i = gtid(); i < n; i += gstride()) p[i] = v;
 }
-__global__ void __launch_bounds__(kBlock)
-    k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
-  for (int64_t i = gtid(); i < n; i += gstride()) p[i] = v;
-}
-__global__ void __launch_bounds__(kBlock) k_iota_u32(uint32_t* p, int64_t n) {
-  for (int64_t i = gtid(); i < n; i += gstride()) p[i] = uint32_t(i);
+
+__global__ void k_begin_step(StepCtl* ctl, int* err) {
+  *err = 0;
+  ctl->fstart[0] = 0;
+  ctl->nM = 0;
+  ctl->n_new = 0;
 }
 
-// ---- scan -------------------------------------------------------------------
-// Tile t covers elements [t*kTile, (t+1)*kTile); lane l of the block owns the
-// kItems consecutive elements starting at t*kTile + l*kItems.
+// ---- scan over a device-sized array ----------------------------------------
+// Tile t covers elements [t*kTile, (t+1)*kTile); lane l owns the kItems
+// consecutive elements from t*kTile + l*kItems.  Blocks stride over tiles.
 __global__ void __launch_bounds__(kBlock)
-    k_scan_reduce(const uint32_t* in, int64_t n, uint32_t* bsum) {
-  const int64_t base = int64_t(blockIdx.x) * kTile + threadIdx.x * kItems;
-  uint32_t v = 0;
+    k_scan_reduce(const uint32_t* in, const uint32_t* nptr, uint32_t* bsum,
+                  const int* err) {
+  if (*err) return;
+  const int64_t n = *nptr, ntiles = cdiv(n, kTile);
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t base = t * kTile + threadIdx.x * kItems;
+    uint32_t v = 0;
 #pragma unroll
-  for (int q = 0; q < kItems; ++q)
-    if (base + q < n) v += in[base + q];
-  uint32_t tot;
-  block_excl_scan(v, &tot);
-  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+    for (int q = 0; q < kItems; ++q)
+      if (base + q < n) v += in[base + q];
+    uint32_t tot;
+    block_excl_scan(v, &tot);
+    if (threadIdx.x == 0) bsum[t] = tot;
+  }
 }
 
-// Single block: exclusive scan of nb block sums in place, grand total out.
+// Single block: exclusive scan of the tile sums in place; the grand total
+// goes to *out1 (and *out2 when given).
 __global__ void __launch_bounds__(kBlock)
-    k_scan_bsum(uint32_t* bsum, int64_t nb, uint32_t* total) {
+    k_scan_bsum(uint32_t* bsum, const uint32_t* nptr, uint32_t* out1,
+                uint32_t* out2, const int* err) {
+  if (*err) return;
+  const int64_t nb = cdiv(int64_t(*nptr), kTile);
   uint32_t carry = 0;
   for (int64_t c = 0; c < nb; c += kTile) {
     const int64_t base = c + threadIdx.x * kItems;
@@ -177,26 +203,33 @@ __global__ void __launch_bounds__(kBlock)
     carry += tot;
     __syncthreads();
   }
-  if (threadIdx.x == 0) *total = carry;
+  if (threadIdx.x == 0) {
+    *out1 = carry;
+    if (out2) *out2 = carry;
+  }
 }
 
 __global__ void __launch_bounds__(kBlock)
-    k_scan_apply(const uint32_t* in, int64_t n, const uint32_t* bsum,
-                 uint32_t* out) {
-  const int64_t base = int64_t(blockIdx.x) * kTile + threadIdx.x * kItems;
-  uint32_t loc[kItems];
-  uint32_t v = 0;
+    k_scan_apply(const uint32_t* in, const uint32_t* nptr,
+                 const uint32_t* bsum, uint32_t* out, const int* err) {
+  if (*err) return;
+  const int64_t n = *nptr, ntiles = cdiv(n, kTile);
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t base = t * kTile + threadIdx.x * kItems;
+    uint32_t loc[kItems];
+    uint32_t v = 0;
 #pragma unroll
-  for (int q = 0; q < kItems; ++q) {
-    loc[q] = (base + q < n) ? in[base + q] : 0u;
-    v += loc[q];
-  }
-  uint32_t tot;
-  uint32_t off = block_excl_scan(v, &tot) + bsum[blockIdx.x];
+    for (int q = 0; q < kItems; ++q) {
+      loc[q] = (base + q < n) ? in[base + q] : 0u;
+      v += loc[q];
+    }
+    uint32_t tot;
+    uint32_t off = block_excl_scan(v, &tot) + bsum[t];
 #pragma unroll
-  for (int q = 0; q < kItems; ++q) {
-    if (base + q < n) out[base + q] = off;
-    off += loc[q];
+    for (int q = 0; q < kItems; ++q) {
+      if (base + q < n) out[base + q] = off;
+      off += loc[q];
+    }
   }
 }
 
@@ -213,85 +246,106 @@ __device__ __forceinline__ double weight(float2 c) {
 
 template <typename Amp>
 __global__ void __launch_bounds__(kBlock)
-    k_select_count(const Amp* psi, int64_t n, double th2, uint32_t* bsum) {
-  const int64_t base = int64_t(blockIdx.x) * kTile + threadIdx.x * kItems;
-  uint32_t v = 0;
+    k_select_count(const Amp* psi, const StepCtl* ctl, double th2,
+                   uint32_t* bsum) {
+  const int64_t n = ctl->n_old, ntiles = cdiv(n, kTile);
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t base = t * kTile + threadIdx.x * kItems;
+    uint32_t v = 0;
 #pragma unroll
-  for (int q = 0; q < kItems; ++q)
-    if (base + q < n && weight(psi[base + q]) >= th2) ++v;
-  uint32_t tot;
-  block_excl_scan(v, &tot);
-  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+    for (int q = 0; q < kItems; ++q)
+      if (base + q < n && weight(psi[base + q]) >= th2) ++v;
+    uint32_t tot;
+    block_excl_scan(v, &tot);
+    if (threadIdx.x == 0) bsum[t] = tot;
+  }
 }
 
 template <typename Amp>
 __global__ void __launch_bounds__(kBlock)
-    k_select_write(const Amp* psi, int64_t n, double th2, const uint32_t* bsum,
-                   uint32_t* midx) {
-  const int64_t base = int64_t(blockIdx.x) * kTile + threadIdx.x * kItems;
-  bool keep[kItems];
-  uint32_t v = 0;
+    k_select_write(const Amp* psi, const StepCtl* ctl, double th2,
+                   const uint32_t* bsum, uint32_t* midx) {
+  const int64_t n = ctl->n_old, ntiles = cdiv(n, kTile);
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t base = t * kTile + threadIdx.x * kItems;
+    bool keep[kItems];
+    uint32_t v = 0;
 #pragma unroll
-  for (int q = 0; q < kItems; ++q) {
-    keep[q] = base + q < n && weight(psi[base + q]) >= th2;
-    v += keep[q] ? 1u : 0u;
+    for (int q = 0; q < kItems; ++q) {
+      keep[q] = base + q < n && weight(psi[base + q]) >= th2;
+      v += keep[q] ? 1u : 0u;
+    }
+    uint32_t tot;
+    uint32_t off = block_excl_scan(v, &tot) + bsum[t];
+#pragma unroll
+    for (int q = 0; q < kItems; ++q)
+      if (keep[q]) midx[off++] = uint32_t(base + q);
   }
-  uint32_t tot;
-  uint32_t off = block_excl_scan(v, &tot) + bsum[blockIdx.x];
-#pragma unroll
-  for (int q = 0; q < kItems; ++q)
-    if (keep[q]) midx[off++] = uint32_t(base + q);
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_select_all(StepCtl* ctl, uint32_t* midx) {
+  const int64_t n = ctl->n_old;
+  for (int64_t i = gtid(); i < n; i += gstride()) midx[i] = uint32_t(i);
+  if (gtid() == 0) {
+    ctl->nM = uint32_t(n);
+    ctl->fstart[1] = uint32_t(n);
+  }
 }
 
 // ---- row metadata from keys -------------------------------------------------
 template <int W>
 __global__ void __launch_bounds__(kBlock)
     k_row_info(DevModel m, const uint64_t* keys, int64_t n, uint64_t* pay,
-               uint64_t* tot, double* diag) {
+               uint64_t* tot) {
   for (int64_t r = gtid(); r < n; r += gstride()) {
     uint64_t k[W];
     load_key<W>(keys, r, k);
     const int j = int(k[W - 1] & ((uint64_t(1) << m.bj) - 1));
-    int nj[kMaxV];
-    uint64_t t = 0;
+    int nj[kMaxV], T[kMaxV];
     for (int nu = 0; nu < m.V; ++nu) {
       nj[nu] = int(get_field<W>(k, field_off(m, j, nu), m.bnu[nu]));
-      uint32_t T = 0;
+      int s = 0;
       for (int i = 0; i < m.N; ++i)
-        T += get_field<W>(k, field_off(m, i, nu), m.bnu[nu]);
-      t |= uint64_t(T) << (16 * nu);
+        s += int(get_field<W>(k, field_off(m, i, nu), m.bnu[nu]));
+      T[nu] = s;
     }
-    const uint64_t p = make_pay(j, nj, m.V);
-    pay[r] = p;
-    tot[r] = t;
-    diag[r] = row_diag(m, p, t);
+    pay[r] = make_pay(m.V, j, nj, T);
+    tot[r] = make_tot(m.V, T);
   }
 }
 
-// ---- insert the selected rows as rows 0..nM-1 of the new set ----------------
+// ---- insert rows into the cleared table -------------------------------------
+// Row i of the new set is row midx[i] of the old one (keys_o given) or is
+// already in place (rehash after growth, keys_o null).
 template <int W>
 __global__ void __launch_bounds__(kBlock)
     k_insert_rows(DevModel m, const uint64_t* keys_o, const uint64_t* pay_o,
-                  const uint64_t* tot_o, const double* diag_o,
-                  const uint32_t* midx, int64_t nM, uint64_t* keys_n,
-                  uint64_t* pay_n, uint64_t* tot_n, double* diag_n,
-                  uint64_t* table, uint64_t mask, int* err) {
+                  const uint64_t* tot_o, const uint32_t* midx,
+                  const uint32_t* nptr, int64_t n_fixed, uint64_t* keys_n,
+                  uint64_t* pay_n, uint64_t* tot_n, uint64_t* table,
+                  uint64_t mask, int* err) {
+  if (*err) return;
+  const int64_t nM = nptr ? int64_t(*nptr) : n_fixed;
   for (int64_t i = gtid(); i < nM; i += gstride()) {
-    const int64_t r = midx[i];
     uint64_t k[W];
-    load_key<W>(keys_o, r, k);
-    store_key<W>(keys_n, i, k);
-    pay_n[i] = pay_o[r];
-    tot_n[i] = tot_o[r];
-    diag_n[i] = diag_o[r];
+    if (keys_o) {
+      const int64_t r = midx[i];
+      load_key<W>(keys_o, r, k);
+      store_key<W>(keys_n, i, k);
+      pay_n[i] = pay_o[r];
+      tot_n[i] = tot_o[r];
+    } else {
+      load_key<W>(keys_n, i, k);
+    }
     const uint64_t h = key_hash<W>(m, k);
     const uint64_t mine = (uint64_t(hash_tag(h)) << 32) | uint64_t(i);
     uint64_t s = h & mask;
     bool done = false;
     for (uint64_t p = 0; p <= mask; ++p) {
-      if (table[s] == kEmpty && atomicCAS((unsigned long long*)(table + s),
-                                          (unsigned long long)kEmpty,
-                                          (unsigned long long)mine) == kEmpty) {
+      if (table[s] == kEmpty &&
+          atomicCAS((unsigned long long*)(table + s), (unsigned long long)kEmpty,
+                    (unsigned long long)mine) == kEmpty) {
         done = true;
         break;
       }
@@ -302,178 +356,209 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ---- expansion round --------------------------------------------------------
-// Candidate c = (parent f0 + c / D, slot c % D) of the current chunk.
-//
-// Probe: insert-if-absent.  A slot holds (tag << 32 | ref); ref is a row of
-// the new set or, during the round, kCand | candidate id.  Candidates with
-// equal keys meet in one slot and keep the smallest candidate id (atomicMin:
-// equal keys share the tag, so the minimum is over the id).  Entries only
-// move EMPTY -> CAND(x) -> CAND(y < x) inside this kernel, so a stale read is
-// repaired by the compare-and-swap or is harmless.
+// Parameters of round r: frontier r-1 and the row count so far.
+__global__ void k_round_prep(StepCtl* ctl, int r, int D, int64_t cand_cap,
+                             int* err) {
+  if (*err) return;
+  const uint32_t f0 = ctl->fstart[r - 1];
+  int64_t rows = int64_t(ctl->fstart[r]) - f0;
+  if (rows * D > cand_cap) {
+    atomicOr(err, kErrCapacity);
+    rows = cand_cap / D;
+  }
+  ctl->r_f0 = f0;
+  ctl->r_rows = uint32_t(rows);
+  ctl->r_ncand = uint32_t(rows * D);
+  ctl->r_ntiles = uint32_t(cdiv(rows * D, kBlock));
+  ctl->r_ncur = ctl->fstart[r];
+  ctl->r_total = 0;
+}
+
+__global__ void k_round_finish(StepCtl* ctl, int r, int64_t cap, int* err) {
+  if (*err) return;
+  int64_t n = int64_t(ctl->r_ncur) + ctl->r_total;
+  if (n > cap) {
+    atomicOr(err, kErrCapacity);
+    n = cap;
+  }
+  ctl->fstart[r + 1] = uint32_t(n);
+}
+
+// Probe: insert-if-absent of candidate c = (parent f0 + c / D, slot c % D).
+// A table slot holds (tag << 32 | ref); ref is a row of the new set or,
+// during the round, kCand | candidate id.  The candidate whose
+// compare-and-swap fills an empty slot owns that key.  Entries only move
+// EMPTY -> CAND(owner) inside this kernel, so a stale read is repaired by
+// the compare-and-swap.  Outcomes per candidate:
+//   structural zero      col = -1
+//   key already a row    col = that row
+//   owner                c_ref = kOwner, c_slot = table slot
+//   key owned by c2      c_ref = c2 (column linked after the commit)
+// Candidates are processed in tiles of one block; the owners of each tile
+// are counted into tile_cnt so that new rows are numbered by a scan.
+constexpr uint32_t kOwner = 0xFFFFFFFEu;
+
 template <int W>
 __global__ void __launch_bounds__(kBlock)
     k_expand_probe(DevModel m, const uint64_t* keys, const uint64_t* pay,
-                   int64_t f0, int64_t rows, uint64_t* table, uint64_t mask,
-                   uint32_t* c_slot, uint32_t* c_ref, int* err) {
+                   const StepCtl* ctl, int64_t cap, uint64_t* table,
+                   uint64_t mask, uint32_t* c_slot, uint32_t* c_ref,
+                   uint32_t* tile_cnt, int32_t* col, int* err) {
+  if (*err) return;
   const int D = m.D;
-  const int64_t nc = rows * D;
-  for (int64_t c = gtid(); c < nc; c += gstride()) {
-    const int64_t p = f0 + c / D;
-    const int s = int(c % D);
-    uint64_t par[W], k[W];
-    load_key<W>(keys, p, par);
-    const uint64_t py = pay[p];
-    if (!slot_target<W>(m, par, py, s, k)) {
-      c_slot[c] = kNone;
-      c_ref[c] = kNone;
-      continue;
-    }
-    const uint64_t h = key_hash<W>(m, k);
-    const uint32_t tag = hash_tag(h);
-    const uint64_t mine = (uint64_t(tag) << 32) | uint64_t(kCand | uint32_t(c));
-    uint64_t i = h & mask;
-    uint32_t rslot = kNone, rref = kNone;
-    for (uint64_t probes = 0; probes <= mask; ++probes) {
-      uint64_t e = table[i];
-      if (e == kEmpty) {
-        const uint64_t old = atomicCAS((unsigned long long*)(table + i),
-                                       (unsigned long long)kEmpty,
-                                       (unsigned long long)mine);
-        if (old == kEmpty) {
-          rslot = uint32_t(i);
-          rref = kCand;
-          break;
-        }
-        e = old;
-      }
-      if (uint32_t(e >> 32) == tag) {
-        const uint32_t r = uint32_t(e);
-        bool same;
-        if (r & kCand) {
-          const int64_t c2 = int64_t(r & ~kCand);
-          uint64_t par2[W], k2[W];
-          load_key<W>(keys, f0 + c2 / D, par2);
-          slot_target<W>(m, par2, pay[f0 + c2 / D], int(c2 % D), k2);
-          same = true;
-#pragma unroll
-          for (int q = 0; q < W; ++q) same &= (k2[q] == k[q]);
-        } else {
-          same = key_eq<W>(k, keys + int64_t(r) * W);
-        }
-        if (same) {
-          if (r & kCand) {
-            atomicMin((unsigned long long*)(table + i),
-                      (unsigned long long)mine);
-            rslot = uint32_t(i);
-            rref = kCand;
-          } else {
-            rref = r;
+  const int64_t f0 = ctl->r_f0, nc = ctl->r_ncand;
+  const int64_t ntiles = cdiv(nc, kBlock);
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t c = tile * kBlock + threadIdx.x;
+    uint32_t owner = 0;
+    if (c < nc) {
+      const int64_t p = f0 + c / D;
+      const int s = int(c % D);
+      uint64_t par[W], k[W];
+      load_key<W>(keys, p, par);
+      const uint64_t py = pay[p];
+      uint32_t rref = kNone;
+      if (!slot_target<W>(m, par, py, s, k)) {
+        col[int64_t(s) * cap + p] = -1;
+      } else {
+        const uint64_t h = key_hash<W>(m, k);
+        const uint32_t tag = hash_tag(h);
+        const uint64_t mine =
+            (uint64_t(tag) << 32) | uint64_t(kCand | uint32_t(c));
+        uint64_t i = h & mask;
+        bool done = false;
+        for (uint64_t probes = 0; probes <= mask; ++probes) {
+          uint64_t e = table[i];
+          if (e == kEmpty) {
+            const uint64_t old = atomicCAS((unsigned long long*)(table + i),
+                                           (unsigned long long)kEmpty,
+                                           (unsigned long long)mine);
+            if (old == kEmpty) {
+              rref = kOwner;
+              c_slot[c] = uint32_t(i);
+              owner = 1;
+              done = true;
+              break;
+            }
+            e = old;
           }
-          break;
+          if (uint32_t(e >> 32) == tag) {
+            const uint32_t r = uint32_t(e);
+            bool same;
+            if (r & kCand) {
+              const int64_t c2 = int64_t(r & ~kCand);
+              uint64_t par2[W], k2[W];
+              load_key<W>(keys, f0 + c2 / D, par2);
+              slot_target<W>(m, par2, pay[f0 + c2 / D], int(c2 % D), k2);
+              same = true;
+#pragma unroll
+              for (int q = 0; q < W; ++q) same &= (k2[q] == k[q]);
+            } else {
+              same = key_eq<W>(k, keys + int64_t(r) * W);
+            }
+            if (same) {
+              if (r & kCand)
+                rref = r & ~kCand;
+              else
+                col[int64_t(s) * cap + p] = int32_t(r);
+              done = true;
+              break;
+            }
+          }
+          i = (i + 1) & mask;
         }
+        if (!done) atomicOr(err, kErrTableFull);
       }
-      i = (i + 1) & mask;
+      c_ref[c] = rref;
     }
-    if (rref == kNone) atomicOr(err, kErrTableFull);
-    c_slot[c] = rslot;
-    c_ref[c] = rref;
+    uint32_t tot;
+    block_excl_scan(owner, &tot);
+    if (threadIdx.x == 0) tile_cnt[tile] = tot;
   }
 }
 
-// Resolve each pending candidate to its owner; count owners per parent.
-__global__ void __launch_bounds__(kBlock)
-    k_expand_resolve(int D, int64_t rows, const uint64_t* table,
-                     const uint32_t* c_slot, uint32_t* c_ref,
-                     uint32_t* rowcnt) {
-  for (int64_t p = gtid(); p < rows; p += gstride()) {
-    uint32_t cnt = 0;
-    for (int s = 0; s < D; ++s) {
-      const int64_t c = p * D + s;
-      if (c_ref[c] != kCand) continue;
-      const uint32_t owner = uint32_t(table[c_slot[c]]) & ~kCand;
-      c_ref[c] = kCand | owner;
-      if (int64_t(owner) == c) ++cnt;
-    }
-    rowcnt[p] = cnt;
-  }
-}
-
-// Owners append their key as a new row (numbered in candidate order), fix
-// the table slot to point at the row, and fill the parents' columns.
+// Owners append their key as a new row: row = n_cur + tile base + rank of
+// the owner inside its tile.  The table slot is pointed at the row.
 template <int W, typename Amp>
 __global__ void __launch_bounds__(kBlock)
     k_expand_commit(DevModel m, uint64_t* keys, uint64_t* pay, uint64_t* tot,
-                    double* diag, int64_t f0, int64_t rows, int64_t n_cur,
-                    uint64_t* table, const uint32_t* c_slot,
-                    const uint32_t* c_ref, const uint32_t* rowbase,
-                    uint32_t* crow, int32_t* col, int64_t stride, Amp* phi) {
+                    const StepCtl* ctl, int64_t cap, uint64_t* table,
+                    const uint32_t* c_slot, const uint32_t* c_ref,
+                    const uint32_t* tile_base, uint32_t* crow, int32_t* col,
+                    Amp* phi, int* err) {
+  if (*err) return;
   const int D = m.D;
-  for (int64_t pl = gtid(); pl < rows; pl += gstride()) {
-    const int64_t p = f0 + pl;
-    uint64_t par[W];
-    load_key<W>(keys, p, par);
-    const uint64_t py = pay[p], pt = tot[p];
-    uint32_t run = 0;
-    for (int s = 0; s < D; ++s) {
-      const int64_t c = pl * D + s;
-      const uint32_t r = c_ref[c];
-      if (r == kNone) {
-        col[int64_t(s) * stride + p] = -1;
-      } else if (r & kCand) {
-        if (int64_t(r & ~kCand) != c) continue;  // linked afterwards
-        const int64_t row = n_cur + rowbase[pl] + run++;
-        uint64_t k[W];
-        slot_target<W>(m, par, py, s, k);
-        store_key<W>(keys, row, k);
-        uint64_t np, nt;
-        slot_row_info<W>(m, k, py, pt, s, np, nt);
-        pay[row] = np;
-        tot[row] = nt;
-        diag[row] = row_diag(m, np, nt);
-        const uint64_t e = table[c_slot[c]];
-        table[c_slot[c]] = (e & 0xFFFFFFFF00000000ull) | uint64_t(row);
-        crow[c] = uint32_t(row);
-        col[int64_t(s) * stride + p] = int32_t(row);
-        Amp z;
-        z.x = 0;
-        z.y = 0;
-        phi[row] = z;
-      } else {
-        col[int64_t(s) * stride + p] = int32_t(r);
-      }
+  const int64_t f0 = ctl->r_f0, nc = ctl->r_ncand, n_cur = ctl->r_ncur;
+  const int64_t ntiles = cdiv(nc, kBlock);
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t c = tile * kBlock + threadIdx.x;
+    const bool own = c < nc && c_ref[c] == kOwner;
+    uint32_t tot_in_tile;
+    const uint32_t rank = block_excl_scan(own ? 1u : 0u, &tot_in_tile);
+    if (!own) continue;
+    const int64_t p = f0 + c / D;
+    const int s = int(c % D);
+    const int64_t row = n_cur + tile_base[tile] + rank;
+    if (row >= cap) {
+      atomicOr(err, kErrCapacity);
+      crow[c] = kNone;
+      col[int64_t(s) * cap + p] = -1;
+      continue;
     }
+    uint64_t par[W], k[W];
+    load_key<W>(keys, p, par);
+    const uint64_t py = pay[p];
+    slot_target<W>(m, par, py, s, k);
+    store_key<W>(keys, row, k);
+    uint64_t np, nt;
+    slot_row_info<W>(m, k, py, tot[p], s, np, nt);
+    pay[row] = np;
+    tot[row] = nt;
+    const uint64_t e = table[c_slot[c]];
+    table[c_slot[c]] = (e & 0xFFFFFFFF00000000ull) | uint64_t(row);
+    crow[c] = uint32_t(row);
+    col[int64_t(s) * cap + p] = int32_t(row);
+    Amp z;
+    z.x = 0;
+    z.y = 0;
+    phi[row] = z;
   }
 }
 
+// Candidates whose key another candidate owns take that candidate's row.
 __global__ void __launch_bounds__(kBlock)
-    k_expand_link(int D, int64_t f0, int64_t rows, const uint32_t* c_ref,
-                  const uint32_t* crow, int32_t* col, int64_t stride) {
-  const int64_t nc = rows * D;
+    k_expand_link(int D, const StepCtl* ctl, int64_t cap, const uint32_t* c_ref,
+                  const uint32_t* crow, int32_t* col, const int* err) {
+  if (*err) return;
+  const int64_t f0 = ctl->r_f0, nc = ctl->r_ncand;
   for (int64_t c = gtid(); c < nc; c += gstride()) {
     const uint32_t r = c_ref[c];
-    if (r == kNone || !(r & kCand)) continue;
-    const uint32_t owner = r & ~kCand;
-    if (int64_t(owner) == c) continue;
-    col[int64_t(c % D) * stride + f0 + c / D] = int32_t(crow[owner]);
+    if (r >= kOwner) continue;  // kOwner or kNone
+    const uint32_t row = crow[r];
+    col[int64_t(c % D) * cap + f0 + c / D] = row == kNone ? -1 : int32_t(row);
   }
 }
 
 template <int W>
 __global__ void __launch_bounds__(kBlock)
     k_lookup_cols(DevModel m, const uint64_t* keys, const uint64_t* pay,
-                  int64_t f0, int64_t rows, const uint64_t* table,
-                  uint64_t mask, int32_t* col, int64_t stride) {
+                  StepCtl* ctl, int k, const uint64_t* table, uint64_t mask,
+                  int32_t* col, int64_t cap, const int* err) {
+  if (*err) return;
   const int D = m.D;
-  const int64_t nc = rows * D;
+  const int64_t f0 = ctl->fstart[k];
+  const int64_t f1 = ctl->fstart[k + 1];
+  const int64_t nc = (f1 - f0) * D;
+  if (gtid() == 0) ctl->n_new = uint32_t(f1);
   for (int64_t c = gtid(); c < nc; c += gstride()) {
     const int64_t p = f0 + c / D;
     const int s = int(c % D);
-    uint64_t par[W], k[W];
+    uint64_t par[W], key[W];
     load_key<W>(keys, p, par);
     int32_t out = -1;
-    if (slot_target<W>(m, par, pay[p], s, k))
-      out = int32_t(table_find<W>(table, mask, keys, k, key_hash<W>(m, k)));
-    col[int64_t(s) * stride + p] = out;
+    if (slot_target<W>(m, par, pay[p], s, key))
+      out = int32_t(table_find<W>(table, mask, keys, key, key_hash<W>(m, key)));
+    col[int64_t(s) * cap + p] = out;
   }
 }
 
@@ -486,8 +571,11 @@ __device__ __forceinline__ double2 widen(float2 c) {
 template <int W, typename Amp>
 __global__ void __launch_bounds__(kBlock)
     k_transfer(DevModel m, const uint64_t* keys_o, const Amp* psi_o,
-               int64_t n_old, const uint64_t* table, uint64_t mask,
-               const uint64_t* keys_n, Amp* phi, double* mass_part) {
+               const StepCtl* ctl, const uint64_t* table, uint64_t mask,
+               const uint64_t* keys_n, Amp* phi, double* mass_part,
+               const int* err) {
+  if (*err) return;
+  const int64_t n_old = ctl->n_old;
   double lost = 0;
   for (int64_t i = gtid(); i < n_old; i += gstride()) {
     uint64_t k[W];
@@ -505,15 +593,18 @@ __global__ void __launch_bounds__(kBlock)
 
 // ---- Gershgorin bounds and Chebyshev coefficients ---------------------------
 __global__ void __launch_bounds__(kBlock)
-    k_bounds(DevModel m, const uint64_t* pay, const double* diag,
-             const int32_t* col, int64_t stride, int64_t n, double* part) {
+    k_bounds(DevModel m, const uint64_t* pay, const uint64_t* tot,
+             const int32_t* col, int64_t cap, const StepCtl* ctl,
+             double* part, const int* err) {
+  if (*err) return;
+  const int64_t n = ctl->n_new;
   double lo = INFINITY, hi = -INFINITY;
   for (int64_t r = gtid(); r < n; r += gstride()) {
     const uint64_t p = pay[r];
     double rad = 0;
     for (int s = 0; s < m.D; ++s)
-      if (col[int64_t(s) * stride + r] >= 0) rad += fabs(slot_value(m, p, s));
-    const double d = diag[r];
+      if (col[int64_t(s) * cap + r] >= 0) rad += fabs(slot_value(m, p, s));
+    const double d = row_diag(m, p, m.V > 2 ? tot[r] : 0);
     lo = fmin(lo, d - rad);
     hi = fmax(hi, d + rad);
   }
@@ -525,42 +616,37 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// J_k(x), k = 0..kmax: power series for x <= 2 (all terms shrink, no
-// cancellation), Miller's backward recurrence normalised by
-// J_0 + 2 sum_k J_2k = 1 above (Miller 1952; see Abramowitz & Stegun 9.12).
-__device__ void bessel_j(double x, int kmax, double* out) {
-  for (int k = 0; k <= kmax; ++k) out[k] = 0.0;
-  if (x == 0.0) {
-    out[0] = 1.0;
-    return;
+// J_k(x) by its power series sum_j (-1)^j (x/2)^(2j+k) / (j! (j+k)!); for
+// x <= 2 every term shrinks and no cancellation occurs.
+__device__ double bessel_series(double x, int k) {
+  const double h = 0.5 * x, h2 = h * h;
+  double lead = 1.0;
+  for (int q = 1; q <= k; ++q) lead *= h / q;
+  if (lead == 0.0) return 0.0;
+  double term = lead, sum = lead;
+  for (int j = 1; j < 60; ++j) {
+    term *= -h2 / (double(j) * double(j + k));
+    sum += term;
+    if (fabs(term) <= 1e-18 * fabs(sum)) break;
   }
-  if (x <= 2.0) {
-    const double h = 0.5 * x, h2 = h * h;
-    double lead = 1.0;  // (x/2)^k / k!
-    for (int k = 0; k <= kmax; ++k) {
-      if (k > 0) lead *= h / k;
-      if (lead == 0.0) break;
-      double term = lead, sum = lead;
-      for (int j = 1; j < 60; ++j) {
-        term *= -h2 / (double(j) * double(j + k));
-        sum += term;
-        if (fabs(term) <= 1e-18 * fabs(sum)) break;
-      }
-      out[k] = sum;
-    }
-    return;
-  }
+  return sum;
+}
+
+// J_0..J_kmax for x > 2: Miller's backward recurrence normalised by
+// J_0 + 2 sum_k J_2k = 1 (Miller 1952; Abramowitz & Stegun 9.12).
+__device__ void bessel_miller(double x, int kmax, double* out) {
   int start = kmax > int(x) ? kmax : int(x);
   start += 20 + int(sqrt(40.0 * start));
-  start += start & 1;  // even
+  start += start & 1;
   double fp1 = 0.0, f = 1e-280, norm = 0.0;
+  for (int k = 0; k <= kmax; ++k) out[k] = 0.0;
   for (int k = start; k >= 0; --k) {
     if (k <= kmax) out[k] = f;
     if ((k & 1) == 0) norm += (k == 0 ? 1.0 : 2.0) * f;
     const double fm1 = (k > 0) ? (2.0 * k / x) * f - fp1 : 0.0;
     fp1 = f;
     f = fm1;
-    if (fabs(f) > 1e250) {  // rescale everything kept so far
+    if (fabs(f) > 1e250) {
       f *= 1e-250;
       fp1 *= 1e-250;
       norm *= 1e-250;
@@ -572,7 +658,9 @@ __device__ void bessel_j(double x, int kmax, double* out) {
 
 __global__ void __launch_bounds__(kBlock)
     k_coef(const double* part, int nparts, double dt, double tol, int k_max,
-           ChebCoef* cc, int* err) {
+           int launched, ChebCoef* cc, int* err) {
+  __shared__ double J[kMaxTerms + 1];
+  if (*err) return;
   double lo = INFINITY, hi = -INFINITY;
   for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
     lo = fmin(lo, part[2 * i]);
@@ -580,7 +668,6 @@ __global__ void __launch_bounds__(kBlock)
   }
   lo = block_min(lo);
   hi = block_max(hi);
-  if (threadIdx.x != 0) return;
   if (lo > hi) lo = hi = 0.0;  // empty set
   // widen by 1e-12 of the magnitude so the interval strictly contains the
   // spectrum
@@ -589,46 +676,60 @@ __global__ void __launch_bounds__(kBlock)
   double a = 0.5 * (emax - emin);
   const double b = 0.5 * (emax + emin);
   if (!(a > 1e-300)) a = 1e-300;
-  cc->emin = emin;
-  cc->emax = emax;
-  cc->a = a;
-  cc->b = b;
-  cc->alpha = 1.0 / a;
-  cc->beta = -b / a;
-  double sn, cs;
-  sincos(b * dt, &sn, &cs);
-  cc->phase[0] = cs;
-  cc->phase[1] = -sn;
-  double J[kMaxTerms + 1];
-  int kcap = k_max < kMaxTerms ? k_max : kMaxTerms;
-  bessel_j(a * dt, kcap, J);
-  const double thresh = ldexp(tol, -8);
-  int K = 1;
-  for (int k = 0; k <= kcap; ++k)
-    if (fabs(J[k]) > thresh) K = k + 1;
-  if (K > kcap) {
-    atomicOr(err, kErrTerms);
-    K = kcap;
+  const double x = a * dt;
+  const int kcap = k_max < kMaxTerms ? k_max : kMaxTerms;
+  if (x <= 2.0) {
+    for (int k = threadIdx.x; k <= kcap; k += blockDim.x)
+      J[k] = bessel_series(x, k);
+  } else if (threadIdx.x == 0) {
+    bessel_miller(x, kcap, J);
   }
-  cc->K = K;
-  for (int k = 0; k < K; ++k) {
+  __syncthreads();
+  // K = 1 + the last k with |J_k| above tol * 2^-8 (beyond x the J_k
+  // decrease monotonically, so every later term is below it too)
+  const double thresh = ldexp(tol, -8);
+  double last = 0;
+  for (int k = threadIdx.x; k <= kcap; k += blockDim.x)
+    if (fabs(J[k]) > thresh) last = fmax(last, double(k));
+  last = block_max(last);
+  int K = int(last) + 1;
+  if (K > kcap) K = kcap + 1;
+  if (threadIdx.x == 0) {
+    if (K > kcap)
+      atomicOr(err, kErrTerms);
+    else if (K > launched)
+      atomicOr(err, kErrNeedTerms);
+    cc->emin = emin;
+    cc->emax = emax;
+    cc->a = a;
+    cc->b = b;
+    cc->alpha = 1.0 / a;
+    cc->beta = -b / a;
+    double sn, cs;
+    sincos(b * dt, &sn, &cs);
+    cc->phase[0] = cs;
+    cc->phase[1] = -sn;
+    cc->K = K;
+  }
+  for (int k = threadIdx.x; k < K && k < kMaxTerms; k += blockDim.x) {
     const double v = (k == 0 ? 1.0 : 2.0) * J[k];
-    // (-i)^k
-    const int q = k & 3;
+    const int q = k & 3;  // (-i)^k
     cc->c[k][0] = (q == 0) ? v : (q == 2 ? -v : 0.0);
     cc->c[k][1] = (q == 1) ? -v : (q == 3 ? v : 0.0);
   }
 }
 
 // ---- Clenshaw term ----------------------------------------------------------
-// For the series y = sum_{k<K} c_k T_k(H~) phi, Clenshaw's recurrence runs
-// b_k = c_k phi + 2 H~ b_{k+1} - b_{k+2} from k = K-1 down to 1 and ends with
-// y = c_0 phi + H~ b_1 - b_2.  One launch computes
-//   out = c[ck] phi + fac * s_in * H~(in) - s_prev * prev
-// with H~ = alpha H + beta, H applied as an ELL SpMV whose values follow
-// from the slot and the row payload.  Compared with the forward
-// three-term recurrence plus an accumulator this streams one vector less
-// per term.
+// y = sum_{k<K} c_k T_k(H~) phi by Clenshaw's recurrence
+//   b_k = c_k phi + 2 H~ b_{k+1} - b_{k+2}   (k = K-1 .. 1),
+//   y   = c_0 phi + H~ b_1 - b_2,
+// with b_K = b_{K+1} = 0 and b_{K-1} = c_{K-1} phi folded into the first
+// launch.  Launch kk computes b_kk into buffer kk & 1, in place over
+// b_{kk+2}; launches with kk > K-2 return at once, so the host enqueues a
+// fixed number of launches before K is known.  H~ = alpha H + beta; H is
+// applied as an ELL SpMV whose values follow from the slot and the row
+// payload.  Against the forward three-term recurrence plus an accumulator
+// this streams one vector less per term.
 template <typename R>
 struct VecT;
 template <>
@@ -642,42 +743,52 @@ struct VecT<float> {
 
 template <typename R, int ND, int NV>
 __global__ void __launch_bounds__(kBlock)
-    k_cheb_term(DevModel m, int64_t n, const int32_t* __restrict__ col,
-                int64_t stride, const uint64_t* __restrict__ pay,
-                const double* __restrict__ diag,
-                const ChebCoef* __restrict__ cc, TermArgs ta,
+    k_cheb_term(DevModel m, int kk, int want_energy,
+                const StepCtl* __restrict__ ctl, const int* __restrict__ err,
+                const int32_t* __restrict__ col, int64_t cap,
+                const uint64_t* __restrict__ pay,
+                const uint64_t* __restrict__ tot,
+                const ChebCoef* __restrict__ cc,
                 const typename VecT<R>::T* __restrict__ phi,
-                const typename VecT<R>::T* __restrict__ in,
-                const typename VecT<R>::T* prev, typename VecT<R>::T* out,
-                double* e_part, double* n2_part, double* pop_part) {
+                typename VecT<R>::T* b0, typename VecT<R>::T* b1,
+                double* e_part) {
   using Amp = typename VecT<R>::T;
   constexpr int D = 2 * ND + 2 * NV;
-  extern __shared__ double pop_lds[];
+  if (*err) return;
+  const int K = cc->K;
+  if (kk > K - 2 && !(K == 1 && kk == 0)) return;
+  const int64_t n = ctl->n_new;
+  const bool first = (kk == K - 2) || K == 1;
+  const bool fin = kk == 0;
+  const bool energy = first && want_energy;
+  const Amp* in = first ? phi : (((kk + 1) & 1) ? b1 : b0);
+  const Amp* prev = first ? nullptr : (kk == K - 3 ? phi : ((kk & 1) ? b1 : b0));
+  Amp* out = (kk & 1) ? b1 : b0;
   const R alpha = R(cc->alpha), beta = R(cc->beta);
-  const R ckr = R(cc->c[ta.ck][0]), cki = R(cc->c[ta.ck][1]);
-  R sir = R(ta.fac), sii = 0;
-  if (ta.in_coef >= 0) {
-    sir = R(ta.fac * cc->c[ta.in_coef][0]);
-    sii = R(ta.fac * cc->c[ta.in_coef][1]);
+  const R ckr = R(cc->c[kk][0]), cki = R(cc->c[kk][1]);
+  const double fac = fin ? 1.0 : 2.0;
+  R sir = R(fac), sii = 0;
+  if (first) {
+    sir = K == 1 ? R(0) : R(fac * cc->c[K - 1][0]);
+    sii = K == 1 ? R(0) : R(fac * cc->c[K - 1][1]);
   }
   R spr = 1, spi = 0;
-  if (ta.prev_coef >= 0) {
-    spr = R(cc->c[ta.prev_coef][0]);
-    spi = R(cc->c[ta.prev_coef][1]);
+  if (kk == K - 3) {
+    spr = R(cc->c[K - 1][0]);
+    spi = R(cc->c[K - 1][1]);
   }
-  const R phr = R(cc->phase[0]), phi_i = R(cc->phase[1]);
-  R jv[3], gv[NV][2];
+  // the final launch also applies exp(-i b dt)
+  const R phr = fin ? R(cc->phase[0]) : R(1), phim = fin ? R(cc->phase[1]) : R(0);
+  R jv[3] = {0, 0, 0};
 #pragma unroll
   for (int a = 0; a < ND; ++a) jv[a] = R(m.J[a]);
-  if (ta.final_)
-    for (int j = threadIdx.x; j < m.N; j += blockDim.x) pop_lds[j] = 0.0;
-  if (ta.final_) __syncthreads();
-  double esum = 0, n2 = 0;
+  double esum = 0;
   for (int64_t i = gtid(); i < n; i += gstride()) {
     const Amp xi = in[i];
     const uint64_t p = pay[i];
-    const R d = R(diag[i]);
+    const R d = R(row_diag(m, p, NV > 2 ? tot[i] : 0));
     R hr = d * xi.x, hi = d * xi.y;
+    R gv[NV][2];
 #pragma unroll
     for (int nu = 0; nu < NV; ++nu) {
       const int occ = pay_occ(p, nu);
@@ -686,7 +797,7 @@ __global__ void __launch_bounds__(kBlock)
     }
 #pragma unroll
     for (int s = 0; s < D; ++s) {
-      const int32_t c = col[int64_t(s) * stride + i];
+      const int32_t c = col[int64_t(s) * cap + i];
       if (c >= 0) {
         const R v = s < 2 * ND ? jv[s >> 1] : gv[(s - 2 * ND) >> 1][(s - 2 * ND) & 1];
         const Amp xj = in[c];
@@ -694,7 +805,7 @@ __global__ void __launch_bounds__(kBlock)
         hi += v * xj.y;
       }
     }
-    if (ta.energy) esum += double(xi.x) * double(hr) + double(xi.y) * double(hi);
+    if (energy) esum += double(xi.x) * double(hr) + double(xi.y) * double(hi);
     const R tr = alpha * hr + beta * xi.x, ti = alpha * hi + beta * xi.y;
     R yr = sir * tr - sii * ti, yi = sir * ti + sii * tr;
     const Amp f = phi[i];
@@ -705,57 +816,47 @@ __global__ void __launch_bounds__(kBlock)
       yr -= spr * q.x - spi * q.y;
       yi -= spr * q.y + spi * q.x;
     }
-    if (ta.final_) {
-      const R zr = phr * yr - phi_i * yi, zi = phr * yi + phi_i * yr;
-      yr = zr;
-      yi = zi;
-      Amp o;
-      o.x = yr;
-      o.y = yi;
-      const double w = weight(o);
-      n2 += w;
-      atomicAdd(&pop_lds[pay_site(p)], w);
-    }
     Amp o;
-    o.x = yr;
-    o.y = yi;
+    o.x = phr * yr - phim * yi;
+    o.y = phr * yi + phim * yr;
     out[i] = o;
   }
-  if (ta.energy) {
+  if (energy) {
     esum = block_sum(esum);
     if (threadIdx.x == 0) e_part[blockIdx.x] = esum;
   }
-  if (ta.final_) {
-    n2 = block_sum(n2);
-    if (threadIdx.x == 0) n2_part[blockIdx.x] = n2;
-    __syncthreads();
-    for (int j = threadIdx.x; j < m.N; j += blockDim.x)
-      pop_part[int64_t(blockIdx.x) * m.N + j] = pop_lds[j];
-  }
 }
 
+// Norm and exciton populations of psi as per-block partials (populations
+// binned in LDS).  Rows are visited in the select kernels' tile layout, so
+// the same pass also counts, per tile, the rows the next step will select.
 template <typename R>
 __global__ void __launch_bounds__(kBlock)
-    k_cheb_scale(int64_t n, const ChebCoef* cc,
-                 const typename VecT<R>::T* phi, typename VecT<R>::T* out,
-                 double* n2_part, double* pop_part, const uint64_t* pay,
-                 int N) {
-  using Amp = typename VecT<R>::T;
+    k_pop_norm(int N, double th2, const StepCtl* ctl,
+               const typename VecT<R>::T* psi, const uint64_t* pay,
+               double* n2_part, double* pop_part, uint32_t* sel_bsum,
+               const int* err) {
   extern __shared__ double pop_lds[];
+  if (*err) return;
+  const int64_t n = ctl->n_new, ntiles = cdiv(n, kTile);
   for (int j = threadIdx.x; j < N; j += blockDim.x) pop_lds[j] = 0.0;
   __syncthreads();
-  // c_0 * exp(-i b dt); c_0 is real
-  const R zr = R(cc->c[0][0] * cc->phase[0]), zi = R(cc->c[0][0] * cc->phase[1]);
   double n2 = 0;
-  for (int64_t i = gtid(); i < n; i += gstride()) {
-    const Amp f = phi[i];
-    Amp o;
-    o.x = zr * f.x - zi * f.y;
-    o.y = zr * f.y + zi * f.x;
-    out[i] = o;
-    const double w = weight(o);
-    n2 += w;
-    atomicAdd(&pop_lds[pay_site(pay[i])], w);
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t base = t * kTile + threadIdx.x * kItems;
+    uint32_t keep = 0;
+#pragma unroll
+    for (int q = 0; q < kItems; ++q) {
+      if (base + q < n) {
+        const double w = weight(psi[base + q]);
+        n2 += w;
+        keep += w >= th2 ? 1u : 0u;
+        atomicAdd(&pop_lds[pay_site(pay[base + q])], w);
+      }
+    }
+    uint32_t tot;
+    block_excl_scan(keep, &tot);
+    if (threadIdx.x == 0) sel_bsum[t] = tot;
   }
   n2 = block_sum(n2);
   if (threadIdx.x == 0) n2_part[blockIdx.x] = n2;
@@ -764,29 +865,33 @@ __global__ void __launch_bounds__(kBlock)
     pop_part[int64_t(blockIdx.x) * N + j] = pop_lds[j];
 }
 
-template <typename R>
+// Second level of a deterministic reduction: block b folds partials
+// b, b + gridDim.x, ... (sum, or min of even / max of odd entries).
 __global__ void __launch_bounds__(kBlock)
-    k_energy(DevModel m, int64_t n, const int32_t* col, int64_t stride,
-             const uint64_t* pay, const double* diag,
-             const typename VecT<R>::T* x, double* e_part) {
-  using Amp = typename VecT<R>::T;
-  double esum = 0;
-  for (int64_t i = gtid(); i < n; i += gstride()) {
-    const Amp xi = x[i];
-    const uint64_t p = pay[i];
-    double hr = diag[i] * double(xi.x), hi = diag[i] * double(xi.y);
-    for (int s = 0; s < m.D; ++s) {
-      const int32_t c = col[int64_t(s) * stride + i];
-      if (c >= 0) {
-        const double v = slot_value(m, p, s);
-        hr += v * double(x[c].x);
-        hi += v * double(x[c].y);
-      }
-    }
-    esum += double(xi.x) * hr + double(xi.y) * hi;
+    k_fold_sum(const double* in, int n, double* out, const int* err) {
+  if (*err) return;
+  double s = 0;
+  for (int i = blockIdx.x + gridDim.x * threadIdx.x; i < n;
+       i += gridDim.x * blockDim.x)
+    s += in[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+__global__ void __launch_bounds__(kBlock)
+    k_fold_minmax(const double* in, int n, double* out, const int* err) {
+  if (*err) return;
+  double lo = INFINITY, hi = -INFINITY;
+  for (int i = blockIdx.x + gridDim.x * threadIdx.x; i < n;
+       i += gridDim.x * blockDim.x) {
+    lo = fmin(lo, in[2 * i]);
+    hi = fmax(hi, in[2 * i + 1]);
   }
-  esum = block_sum(esum);
-  if (threadIdx.x == 0) e_part[blockIdx.x] = esum;
+  lo = block_min(lo);
+  hi = block_max(hi);
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = lo;
+    out[2 * blockIdx.x + 1] = hi;
+  }
 }
 
 // ---- autocorrelation <psi0|psi(t)> ------------------------------------------
@@ -794,7 +899,9 @@ template <int W, typename Amp>
 __global__ void __launch_bounds__(kBlock)
     k_autocorr(DevModel m, const uint64_t* keys0, const double* amps0,
                int64_t n0, const uint64_t* table, uint64_t mask,
-               const uint64_t* keys, const Amp* psi, double* out2) {
+               const uint64_t* keys, const Amp* psi, double* out2,
+               const int* err) {
+  if (*err) return;
   double re = 0, im = 0;
   for (int64_t i = threadIdx.x; i < n0; i += blockDim.x) {
     uint64_t k[W];
@@ -803,8 +910,7 @@ __global__ void __launch_bounds__(kBlock)
     if (r < 0) continue;
     const double2 v = widen(psi[r]);
     const double ar = amps0[2 * i], ai = amps0[2 * i + 1];
-    // conj(a0) * v
-    re += ar * v.x + ai * v.y;
+    re += ar * v.x + ai * v.y;  // conj(a0) * v
     im += ar * v.y - ai * v.x;
   }
   re = block_sum(re);
@@ -816,42 +922,59 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ---- observation record -----------------------------------------------------
+// Blocks 0..N-1 reduce one population each, block N the scalars; each block
+// sums the per-block partials with a fixed lane mapping.
 __global__ void __launch_bounds__(kBlock)
-    k_obs_final(ObsArgs oa, int nparts, const double* mass_part,
-                const double* n2_part, const double* e_part,
-                const double* pop_part, const double* a2, const ChebCoef* cc,
-                double* mass_total, double* rec, int* err) {
-  double ms = 0, n2 = 0, en = 0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
-    ms += mass_part[i];
-    n2 += n2_part[i];
-    if (oa.want_energy) en += e_part[i];
+    k_obs_final(int N, int want_energy, double dt, int n_mass, int n_e,
+                int n_pop, const double* mass_part, const double* n2_part,
+                const double* e_part, const double* pop_part, const double* a2,
+                const ChebCoef* cc, const StepCtl* ctl, double* ring,
+                int rec_doubles, int64_t ring_cap, int* err) {
+  if (*err) return;
+  if (int64_t(ctl->nrec) >= ring_cap) return;  // the host keeps room
+  double* rec = ring + int64_t(ctl->nrec) * rec_doubles;
+  if (int(blockIdx.x) < N) {
+    double s = 0;
+    for (int b = threadIdx.x; b < n_pop; b += blockDim.x)
+      s += pop_part[int64_t(b) * N + blockIdx.x];
+    s = block_sum(s);
+    if (threadIdx.x == 0) rec[kObsFields + blockIdx.x] = s;
+    return;
   }
+  double ms = 0, n2 = 0, en = 0;
+  for (int i = threadIdx.x; i < n_mass; i += blockDim.x) ms += mass_part[i];
+  for (int i = threadIdx.x; i < n_pop; i += blockDim.x) n2 += n2_part[i];
+  if (want_energy)
+    for (int i = threadIdx.x; i < n_e; i += blockDim.x) en += e_part[i];
   ms = block_sum(ms);
   n2 = block_sum(n2);
   en = block_sum(en);
-  for (int j = threadIdx.x; j < oa.N; j += blockDim.x) {
-    double s = 0;
-    for (int b = 0; b < nparts; ++b) s += pop_part[int64_t(b) * oa.N + j];
-    rec[kObsFields + j] = s;
-  }
   if (threadIdx.x == 0) {
-    const double tot = *mass_total + ms;
-    *mass_total = tot;
-    rec[0] = oa.t;
+    rec[0] = ctl->t + dt;
     rec[1] = n2;
-    rec[2] = oa.want_energy ? en : NAN;
+    rec[2] = want_energy ? en : NAN;
     rec[3] = a2[0];
     rec[4] = a2[1];
     rec[5] = ms;
-    rec[6] = tot;
-    rec[7] = oa.nS;
-    rec[8] = oa.nM;
+    rec[6] = ctl->mass_total + ms;
+    rec[7] = double(ctl->n_new);
+    rec[8] = double(ctl->nM);
     rec[9] = double(cc->K);
     rec[10] = cc->emin;
     rec[11] = cc->emax;
     if (!isfinite(n2)) atomicOr(err, kErrNonFinite);
   }
+}
+
+// Commit the step on the device.
+__global__ void k_end_step(StepCtl* ctl, const double* ring, int rec_doubles,
+                           const int* err) {
+  if (*err) return;
+  const double* rec = ring + int64_t(ctl->nrec) * rec_doubles;
+  ctl->t = rec[0];
+  ctl->mass_total = rec[6];
+  ctl->n_old = ctl->n_new;
+  ctl->nrec += 1;
 }
 
 // ---- precision conversion ---------------------------------------------------
@@ -880,8 +1003,10 @@ int supported_words(int W) {
   return 0;
 }
 
-#define PACES_DISPATCH_W(Wi, ...)          \
-  switch (Wi) {                            \
+int64_t scan_tmp_words(int64_t n) { return cdiv(n, kTile) + 16; }
+
+#define PACES_DISPATCH_W(Wi, ...)                           \
+  switch (Wi) {                                             \
     case 1: { constexpr int WW = 1; __VA_ARGS__; } break;   \
     case 2: { constexpr int WW = 2; __VA_ARGS__; } break;   \
     case 3: { constexpr int WW = 3; __VA_ARGS__; } break;   \
@@ -890,221 +1015,226 @@ int supported_words(int W) {
     case 8: { constexpr int WW = 8; __VA_ARGS__; } break;   \
     case 10: { constexpr int WW = 10; __VA_ARGS__; } break; \
     case 16: { constexpr int WW = 16; __VA_ARGS__; } break; \
-    default: break;                        \
+    default: break;                                         \
+  }
+
+#define PACES_DISPATCH_SHAPE(ND, NV, ...)                        \
+  switch ((ND) * 8 + (NV)) {                                     \
+    case 9: { constexpr int A = 1, B = 1; __VA_ARGS__; } break;  \
+    case 10: { constexpr int A = 1, B = 2; __VA_ARGS__; } break; \
+    case 11: { constexpr int A = 1, B = 3; __VA_ARGS__; } break; \
+    case 12: { constexpr int A = 1, B = 4; __VA_ARGS__; } break; \
+    case 17: { constexpr int A = 2, B = 1; __VA_ARGS__; } break; \
+    case 18: { constexpr int A = 2, B = 2; __VA_ARGS__; } break; \
+    case 19: { constexpr int A = 2, B = 3; __VA_ARGS__; } break; \
+    case 20: { constexpr int A = 2, B = 4; __VA_ARGS__; } break; \
+    case 25: { constexpr int A = 3, B = 1; __VA_ARGS__; } break; \
+    case 26: { constexpr int A = 3, B = 2; __VA_ARGS__; } break; \
+    case 27: { constexpr int A = 3, B = 3; __VA_ARGS__; } break; \
+    case 28: { constexpr int A = 3, B = 4; __VA_ARGS__; } break; \
+    default: break;                                              \
   }
 
 void fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
   if (n <= 0) return;
-  k_fill_u64<<<grid_for(n, 8192), kBlock, 0, s>>>(p, n, v);
-}
-void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
-  if (n <= 0) return;
-  k_fill_u32<<<grid_for(n, 8192), kBlock, 0, s>>>(p, n, v);
-}
-void iota_u32(uint32_t* p, int64_t n, hipStream_t s) {
-  if (n <= 0) return;
-  k_iota_u32<<<grid_for(n, 8192), kBlock, 0, s>>>(p, n);
+  k_fill_u64<<<grid_for(n), kBlock, 0, s>>>(p, n, v);
 }
 
-int64_t scan_tmp_words(int64_t n) { return cdiv(n, kTile) + 16; }
+void begin_step(StepCtl* ctl, int* err, hipStream_t s) {
+  k_begin_step<<<1, 1, 0, s>>>(ctl, err);
+}
 
-void exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n,
-                    uint32_t* tmp, uint32_t* total, hipStream_t s) {
-  const int64_t nb = cdiv(n, kTile);
-  if (n <= 0) {
-    k_fill_u32<<<1, kBlock, 0, s>>>(total, 1, 0u);
+void select_rows(int prec, const void* psi, double th2, bool select_all,
+                 bool counted, StepCtl* ctl, uint32_t* midx, uint32_t* tmp,
+                 int64_t cap, int* err, hipStream_t s) {
+  if (select_all) {
+    k_select_all<<<grid_for(cap), kBlock, 0, s>>>(ctl, midx);
     return;
   }
-  k_scan_reduce<<<int(nb), kBlock, 0, s>>>(in, n, tmp);
-  k_scan_bsum<<<1, kBlock, 0, s>>>(tmp, nb, total);
-  k_scan_apply<<<int(nb), kBlock, 0, s>>>(in, n, tmp, out);
-}
-
-void select_rows(int prec, const void* psi, int64_t n, double th2,
-                 uint32_t* midx, uint32_t* tmp, uint32_t* count,
-                 hipStream_t s) {
-  const int64_t nb = cdiv(n, kTile);
-  if (n <= 0) {
-    k_fill_u32<<<1, kBlock, 0, s>>>(count, 1, 0u);
-    return;
+  const int g = tiles_for(cap);
+  if (!counted) {
+    if (prec == 64)
+      k_select_count<double2><<<g, kBlock, 0, s>>>((const double2*)psi, ctl, th2, tmp);
+    else
+      k_select_count<float2><<<g, kBlock, 0, s>>>((const float2*)psi, ctl, th2, tmp);
   }
-  if (prec == 64) {
-    k_select_count<double2><<<int(nb), kBlock, 0, s>>>((const double2*)psi, n, th2, tmp);
-    k_scan_bsum<<<1, kBlock, 0, s>>>(tmp, nb, count);
-    k_select_write<double2><<<int(nb), kBlock, 0, s>>>((const double2*)psi, n, th2, tmp, midx);
-  } else {
-    k_select_count<float2><<<int(nb), kBlock, 0, s>>>((const float2*)psi, n, th2, tmp);
-    k_scan_bsum<<<1, kBlock, 0, s>>>(tmp, nb, count);
-    k_select_write<float2><<<int(nb), kBlock, 0, s>>>((const float2*)psi, n, th2, tmp, midx);
-  }
+  k_scan_bsum<<<1, kBlock, 0, s>>>(tmp, &ctl->n_old, &ctl->nM, &ctl->fstart[1],
+                                   err);
+  if (prec == 64)
+    k_select_write<double2><<<g, kBlock, 0, s>>>((const double2*)psi, ctl, th2, tmp, midx);
+  else
+    k_select_write<float2><<<g, kBlock, 0, s>>>((const float2*)psi, ctl, th2, tmp, midx);
 }
 
-void row_info(const DevModel& m, int Wi, const uint64_t* keys, int64_t n,
-              uint64_t* pay, uint64_t* tot, double* diag, hipStream_t s) {
-  if (n <= 0) return;
-  PACES_DISPATCH_W(Wi, k_row_info<WW><<<grid_for(n, 8192), kBlock, 0, s>>>(
-                           m, keys, n, pay, tot, diag));
+void insert_rows(const DevModel& m, int Wi, const Side& o, const Side& n,
+                 const uint32_t* midx, const StepCtl* ctl, uint64_t* table,
+                 uint64_t mask, int* err, hipStream_t s) {
+  const int g = grid_for(int64_t(mask + 1) / 2);
+  PACES_DISPATCH_W(Wi, k_insert_rows<WW><<<g, kBlock, 0, s>>>(
+                           m, o.keys, o.pay, o.tot, midx, &ctl->nM, 0, n.keys,
+                           n.pay, n.tot, table, mask, err));
 }
 
-void insert_rows(const DevModel& m, int Wi, const uint64_t* keys_o,
-                 const uint64_t* pay_o, const uint64_t* tot_o,
-                 const double* diag_o, const uint32_t* midx, int64_t nM,
-                 uint64_t* keys_n, uint64_t* pay_n, uint64_t* tot_n,
-                 double* diag_n, uint64_t* table, uint64_t mask, int* err,
+void rehash_rows(const DevModel& m, int Wi, const Side& n, uint32_t* midx,
+                 int64_t rows, uint64_t* table, uint64_t mask, int* err,
                  hipStream_t s) {
-  if (nM <= 0) return;
-  PACES_DISPATCH_W(Wi, k_insert_rows<WW><<<grid_for(nM), kBlock, 0, s>>>(
-                           m, keys_o, pay_o, tot_o, diag_o, midx, nM, keys_n,
-                           pay_n, tot_n, diag_n, table, mask, err));
+  (void)midx;
+  if (rows <= 0) return;
+  PACES_DISPATCH_W(Wi, k_insert_rows<WW><<<grid_for(rows), kBlock, 0, s>>>(
+                           m, nullptr, nullptr, nullptr, nullptr, nullptr,
+                           rows, n.keys, n.pay, n.tot, table, mask, err));
 }
 
-void expand_chunk(const DevModel& m, int Wi, int prec, uint64_t* keys,
-                  uint64_t* pay, uint64_t* tot, double* diag, int64_t f0,
-                  int64_t rows, int64_t n_cur, uint64_t* table, uint64_t mask,
-                  const RoundBufs& rb, int32_t* col, int64_t stride, void* phi,
+void expand_round(const DevModel& m, int Wi, int prec, const Side& n, int r,
+                  StepCtl* ctl, int64_t cap, int64_t est, uint64_t* table,
+                  uint64_t mask, const RoundBufs& rb, int32_t* col, void* phi,
                   int* err, hipStream_t s) {
-  if (rows <= 0) return;
-  const int64_t nc = rows * m.D;
-  PACES_DISPATCH_W(Wi, k_expand_probe<WW><<<grid_for(nc), kBlock, 0, s>>>(
-                           m, keys, pay, f0, rows, table, mask, rb.c_slot,
-                           rb.c_ref, err));
-  k_expand_resolve<<<grid_for(rows), kBlock, 0, s>>>(m.D, rows, table,
-                                                    rb.c_slot, rb.c_ref,
-                                                    rb.rowcnt);
-  exclusive_scan(rb.rowcnt, rb.rowbase, rows, rb.scan_tmp, rb.total, s);
+  const int D = m.D;
+  const int64_t nc_bound = std::min<int64_t>(rb.cand_cap, est * D);
+  const int g = grid_for(nc_bound);
+  k_round_prep<<<1, 1, 0, s>>>(ctl, r, D, rb.cand_cap, err);
+  PACES_DISPATCH_W(Wi, k_expand_probe<WW><<<g, kBlock, 0, s>>>(
+                           m, n.keys, n.pay, ctl, cap, table, mask, rb.c_slot,
+                           rb.c_ref, rb.tile_cnt, col, err));
+  const int gt = tiles_for(cdiv(nc_bound, kBlock));
+  k_scan_reduce<<<gt, kBlock, 0, s>>>(rb.tile_cnt, &ctl->r_ntiles, rb.scan_tmp,
+                                      err);
+  k_scan_bsum<<<1, kBlock, 0, s>>>(rb.scan_tmp, &ctl->r_ntiles, &ctl->r_total,
+                                   nullptr, err);
+  k_scan_apply<<<gt, kBlock, 0, s>>>(rb.tile_cnt, &ctl->r_ntiles, rb.scan_tmp,
+                                     rb.tile_base, err);
   if (prec == 64) {
-    PACES_DISPATCH_W(Wi, k_expand_commit<WW, double2><<<grid_for(rows), kBlock, 0, s>>>(
-                             m, keys, pay, tot, diag, f0, rows, n_cur, table,
-                             rb.c_slot, rb.c_ref, rb.rowbase, rb.crow, col,
-                             stride, (double2*)phi));
+    PACES_DISPATCH_W(Wi, k_expand_commit<WW, double2><<<g, kBlock, 0, s>>>(
+                             m, n.keys, n.pay, n.tot, ctl, cap, table,
+                             rb.c_slot, rb.c_ref, rb.tile_base, rb.crow, col,
+                             (double2*)phi, err));
   } else {
-    PACES_DISPATCH_W(Wi, k_expand_commit<WW, float2><<<grid_for(rows), kBlock, 0, s>>>(
-                             m, keys, pay, tot, diag, f0, rows, n_cur, table,
-                             rb.c_slot, rb.c_ref, rb.rowbase, rb.crow, col,
-                             stride, (float2*)phi));
+    PACES_DISPATCH_W(Wi, k_expand_commit<WW, float2><<<g, kBlock, 0, s>>>(
+                             m, n.keys, n.pay, n.tot, ctl, cap, table,
+                             rb.c_slot, rb.c_ref, rb.tile_base, rb.crow, col,
+                             (float2*)phi, err));
   }
-  k_expand_link<<<grid_for(nc), kBlock, 0, s>>>(m.D, f0, rows, rb.c_ref,
-                                               rb.crow, col, stride);
+  k_expand_link<<<g, kBlock, 0, s>>>(D, ctl, cap, rb.c_ref, rb.crow, col, err);
+  k_round_finish<<<1, 1, 0, s>>>(ctl, r, cap, err);
 }
 
-void lookup_cols(const DevModel& m, int Wi, const uint64_t* keys,
-                 const uint64_t* pay, int64_t f0, int64_t rows,
-                 const uint64_t* table, uint64_t mask, int32_t* col,
-                 int64_t stride, hipStream_t s) {
-  if (rows <= 0) return;
-  const int64_t nc = rows * m.D;
-  PACES_DISPATCH_W(Wi, k_lookup_cols<WW><<<grid_for(nc), kBlock, 0, s>>>(
-                           m, keys, pay, f0, rows, table, mask, col, stride));
+void lookup_last(const DevModel& m, int Wi, const Side& n, int k,
+                 StepCtl* ctl, int64_t est, const uint64_t* table,
+                 uint64_t mask, int32_t* col, int64_t cap, int* err,
+                 hipStream_t s) {
+  PACES_DISPATCH_W(Wi, k_lookup_cols<WW><<<grid_for(est * m.D), kBlock, 0, s>>>(
+                           m, n.keys, n.pay, ctl, k, table, mask, col, cap,
+                           err));
 }
 
-void transfer(const DevModel& m, int Wi, int prec, const uint64_t* keys_o,
-              const void* psi_o, int64_t n_old, const uint64_t* table,
-              uint64_t mask, const uint64_t* keys_n, void* phi,
-              double* mass_part, hipStream_t s) {
+int part_grid(int64_t rows) { return grid_for(rows); }
+
+int transfer(const DevModel& m, int Wi, int prec, const Side& o,
+             const void* psi_o, int64_t n_old, const StepCtl* ctl,
+             const uint64_t* table, uint64_t mask, const uint64_t* keys_n,
+             void* phi, double* mass_part, int* err, hipStream_t s) {
+  const int g = grid_for(n_old);
   if (prec == 64) {
-    PACES_DISPATCH_W(Wi, k_transfer<WW, double2><<<kPartBlocks, kBlock, 0, s>>>(
-                             m, keys_o, (const double2*)psi_o, n_old, table,
-                             mask, keys_n, (double2*)phi, mass_part));
+    PACES_DISPATCH_W(Wi, k_transfer<WW, double2><<<g, kBlock, 0, s>>>(
+                             m, o.keys, (const double2*)psi_o, ctl, table, mask,
+                             keys_n, (double2*)phi, mass_part, err));
   } else {
-    PACES_DISPATCH_W(Wi, k_transfer<WW, float2><<<kPartBlocks, kBlock, 0, s>>>(
-                             m, keys_o, (const float2*)psi_o, n_old, table,
-                             mask, keys_n, (float2*)phi, mass_part));
+    PACES_DISPATCH_W(Wi, k_transfer<WW, float2><<<g, kBlock, 0, s>>>(
+                             m, o.keys, (const float2*)psi_o, ctl, table, mask,
+                             keys_n, (float2*)phi, mass_part, err));
   }
+  return g;
 }
 
-void bounds_and_coef(const DevModel& m, const uint64_t* pay,
-                     const double* diag, const int32_t* col, int64_t stride,
-                     int64_t n, double dt, double tol, int k_max,
-                     double* part, ChebCoef* cc, int* err, hipStream_t s) {
-  k_bounds<<<kPartBlocks, kBlock, 0, s>>>(m, pay, diag, col, stride, n, part);
-  k_coef<<<1, kBlock, 0, s>>>(part, kPartBlocks, dt, tol, k_max, cc, err);
+void bounds_and_coef(const DevModel& m, const Side& n, const int32_t* col,
+                     int64_t cap, int64_t est, const StepCtl* ctl, double dt,
+                     double tol, int k_max, int launched, double* part,
+                     double* folded, ChebCoef* cc, int* err, hipStream_t s) {
+  const int g = grid_for(est);
+  k_bounds<<<g, kBlock, 0, s>>>(m, n.pay, n.tot, col, cap, ctl, part, err);
+  const int f = std::min(g, kFold);
+  k_fold_minmax<<<f, kBlock, 0, s>>>(part, g, folded, err);
+  k_coef<<<1, kBlock, 0, s>>>(folded, f, dt, tol, k_max, launched, cc, err);
 }
 
-#define PACES_DISPATCH_SHAPE(ND, NV, ...)                                 \
-  switch ((ND) * 8 + (NV)) {                                              \
-    case 9: { constexpr int A = 1, B = 1; __VA_ARGS__; } break;           \
-    case 10: { constexpr int A = 1, B = 2; __VA_ARGS__; } break;          \
-    case 11: { constexpr int A = 1, B = 3; __VA_ARGS__; } break;          \
-    case 12: { constexpr int A = 1, B = 4; __VA_ARGS__; } break;          \
-    case 17: { constexpr int A = 2, B = 1; __VA_ARGS__; } break;          \
-    case 18: { constexpr int A = 2, B = 2; __VA_ARGS__; } break;          \
-    case 19: { constexpr int A = 2, B = 3; __VA_ARGS__; } break;          \
-    case 20: { constexpr int A = 2, B = 4; __VA_ARGS__; } break;          \
-    case 25: { constexpr int A = 3, B = 1; __VA_ARGS__; } break;          \
-    case 26: { constexpr int A = 3, B = 2; __VA_ARGS__; } break;          \
-    case 27: { constexpr int A = 3, B = 3; __VA_ARGS__; } break;          \
-    case 28: { constexpr int A = 3, B = 4; __VA_ARGS__; } break;          \
-    default: break;                                                       \
-  }
+int fold_sum(const double* in, int n, double* out, int* err, hipStream_t s) {
+  const int f = std::max(1, std::min(n, kFold));
+  k_fold_sum<<<f, kBlock, 0, s>>>(in, n, out, err);
+  return f;
+}
 
-void cheb_term(const DevModel& m, int prec, int64_t n, const int32_t* col,
-               int64_t stride, const uint64_t* pay, const double* diag,
-               const ChebCoef* cc, const TermArgs& ta, const void* phi,
-               const void* in, const void* prev, void* out, double* e_part,
-               double* n2_part, double* pop_part, hipStream_t s) {
-  const size_t lds = ta.final_ ? sizeof(double) * m.N : 0;
-  const bool part = ta.final_ || ta.energy;
-  const int grid = part ? kPartBlocks : grid_for(n);
+int cheb_term(const DevModel& m, int prec, int kk, bool energy, int64_t est,
+              const StepCtl* ctl, const int32_t* col, int64_t cap,
+              const Side& n, const ChebCoef* cc, const void* phi, void* b0,
+              void* b1, double* e_part, int* err, hipStream_t s) {
+  const int e = energy ? 1 : 0;
+  const int g = grid_for(est);
   if (prec == 64) {
     PACES_DISPATCH_SHAPE(m.ndim, m.V,
-        k_cheb_term<double, A, B><<<grid, kBlock, lds, s>>>(
-            m, n, col, stride, pay, diag, cc, ta, (const double2*)phi,
-            (const double2*)in, (const double2*)prev, (double2*)out, e_part,
-            n2_part, pop_part));
+        k_cheb_term<double, A, B><<<g, kBlock, 0, s>>>(
+            m, kk, e, ctl, err, col, cap, n.pay, n.tot, cc,
+            (const double2*)phi, (double2*)b0, (double2*)b1, e_part));
   } else {
     PACES_DISPATCH_SHAPE(m.ndim, m.V,
-        k_cheb_term<float, A, B><<<grid, kBlock, lds, s>>>(
-            m, n, col, stride, pay, diag, cc, ta, (const float2*)phi,
-            (const float2*)in, (const float2*)prev, (float2*)out, e_part,
-            n2_part, pop_part));
+        k_cheb_term<float, A, B><<<g, kBlock, 0, s>>>(
+            m, kk, e, ctl, err, col, cap, n.pay, n.tot, cc,
+            (const float2*)phi, (float2*)b0, (float2*)b1, e_part));
   }
+  return g;
 }
 
-void cheb_scale(int prec, int64_t n, const ChebCoef* cc, const void* phi,
-                void* out, double* n2_part, double* pop_part,
-                const uint64_t* pay, int N, hipStream_t s) {
+int pop_norm(int prec, int N, double th2, int64_t est, const StepCtl* ctl,
+             const void* psi, const uint64_t* pay, double* n2_part,
+             double* pop_part, uint32_t* sel_bsum, int* err, hipStream_t s) {
   const size_t lds = sizeof(double) * N;
+  const int g = tiles_for(est);
   if (prec == 64)
-    k_cheb_scale<double><<<kPartBlocks, kBlock, lds, s>>>(
-        n, cc, (const double2*)phi, (double2*)out, n2_part, pop_part, pay, N);
+    k_pop_norm<double><<<g, kBlock, lds, s>>>(N, th2, ctl, (const double2*)psi,
+                                              pay, n2_part, pop_part, sel_bsum,
+                                              err);
   else
-    k_cheb_scale<float><<<kPartBlocks, kBlock, lds, s>>>(
-        n, cc, (const float2*)phi, (float2*)out, n2_part, pop_part, pay, N);
-}
-
-void energy_only(const DevModel& m, int prec, int64_t n, const int32_t* col,
-                 int64_t stride, const uint64_t* pay, const double* diag,
-                 const void* x, double* e_part, hipStream_t s) {
-  if (prec == 64)
-    k_energy<double><<<kPartBlocks, kBlock, 0, s>>>(m, n, col, stride, pay, diag,
-                                                    (const double2*)x, e_part);
-  else
-    k_energy<float><<<kPartBlocks, kBlock, 0, s>>>(m, n, col, stride, pay, diag,
-                                                   (const float2*)x, e_part);
+    k_pop_norm<float><<<g, kBlock, lds, s>>>(N, th2, ctl, (const float2*)psi,
+                                             pay, n2_part, pop_part, sel_bsum,
+                                             err);
+  return g;
 }
 
 void autocorr(const DevModel& m, int Wi, int prec, const uint64_t* keys0,
               const double* amps0, int64_t n0, const uint64_t* table,
               uint64_t mask, const uint64_t* keys, const void* psi,
-              double* out2, hipStream_t s) {
+              double* out2, int* err, hipStream_t s) {
   if (prec == 64) {
     PACES_DISPATCH_W(Wi, k_autocorr<WW, double2><<<1, kBlock, 0, s>>>(
                              m, keys0, amps0, n0, table, mask, keys,
-                             (const double2*)psi, out2));
+                             (const double2*)psi, out2, err));
   } else {
     PACES_DISPATCH_W(Wi, k_autocorr<WW, float2><<<1, kBlock, 0, s>>>(
                              m, keys0, amps0, n0, table, mask, keys,
-                             (const float2*)psi, out2));
+                             (const float2*)psi, out2, err));
   }
 }
 
-void obs_final(const ObsArgs& oa, const double* mass_part,
-               const double* n2_part, const double* e_part,
-               const double* pop_part, const double* a2, const ChebCoef* cc,
-               double* mass_total, double* rec, int* err, hipStream_t s) {
-  k_obs_final<<<1, kBlock, 0, s>>>(oa, kPartBlocks, mass_part, n2_part,
-                                   e_part, pop_part, a2, cc, mass_total, rec,
-                                   err);
+void end_step(StepCtl* ctl, const double* ring, int rec_doubles, int* err,
+              hipStream_t s) {
+  k_end_step<<<1, 1, 0, s>>>(ctl, ring, rec_doubles, err);
+}
+
+void obs_final(int N, int want_energy, double dt, int n_mass, int n_e,
+               int n_pop, const double* mass_part, const double* n2_part,
+               const double* e_part, const double* pop_part, const double* a2,
+               const ChebCoef* cc, StepCtl* ctl, double* ring, int rec_doubles,
+               int64_t ring_cap, int* err, hipStream_t s) {
+  k_obs_final<<<N + 1, kBlock, 0, s>>>(N, want_energy, dt, n_mass, n_e,
+                                       n_pop, mass_part, n2_part, e_part,
+                                       pop_part, a2, cc, ctl, ring, rec_doubles,
+                                       ring_cap, err);
+}
+
+void row_info(const DevModel& m, int Wi, const uint64_t* keys, int64_t n,
+              uint64_t* pay, uint64_t* tot, hipStream_t s) {
+  if (n <= 0) return;
+  PACES_DISPATCH_W(Wi, k_row_info<WW><<<grid_for(n), kBlock, 0, s>>>(
+                           m, keys, n, pay, tot));
 }
 
 void amps_to_f64(int prec, const void* src, double* dst, int64_t n,
@@ -1113,7 +1243,7 @@ void amps_to_f64(int prec, const void* src, double* dst, int64_t n,
   if (prec == 64)
     (void)hipMemcpyAsync(dst, src, size_t(n) * 16, hipMemcpyDeviceToDevice, s);
   else
-    k_f32_to_f64<<<grid_for(n, 8192), kBlock, 0, s>>>((const float2*)src, dst, n);
+    k_f32_to_f64<<<grid_for(n), kBlock, 0, s>>>((const float2*)src, dst, n);
 }
 void amps_from_f64(int prec, const double* src, void* dst, int64_t n,
                    hipStream_t s) {
@@ -1121,7 +1251,7 @@ void amps_from_f64(int prec, const double* src, void* dst, int64_t n,
   if (prec == 64)
     (void)hipMemcpyAsync(dst, src, size_t(n) * 16, hipMemcpyDeviceToDevice, s);
   else
-    k_f64_to_f32<<<grid_for(n, 8192), kBlock, 0, s>>>(src, (float2*)dst, n);
+    k_f64_to_f32<<<grid_for(n), kBlock, 0, s>>>(src, (float2*)dst, n);
 }
 
 }  // namespace paces

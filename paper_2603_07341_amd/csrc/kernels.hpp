@@ -1,4 +1,10 @@
 // kernels.hpp -- host-side launch wrappers of the step's HIP kernels.
+//
+// Row counts of a step live in device memory (StepCtl) and every kernel
+// reads them there, so a whole step is enqueued without the host waiting on
+// the GPU.  Kernels run on fixed grid-stride grids and clamp every count to
+// the allocated capacity; an overflow is latched and the host repeats the
+// step with larger buffers.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -7,7 +13,11 @@
 
 namespace paces {
 
-constexpr int kMaxTerms = 128;  // Chebyshev terms per step, hard limit
+constexpr int kMaxTerms = 128;   // Chebyshev terms per step, hard limit
+constexpr int kMaxRounds = 30;   // neighbour order per step, hard limit
+constexpr int kPartBlocks = 2048;  // grid of the population reduction
+constexpr int kMaxPartials = 1 << 18;  // per-block partials of row kernels
+constexpr int kObsFields = 12;
 
 // Chebyshev expansion of exp(-i H dt) on [E_min, E_max], computed on the
 // device from the Gershgorin bounds of the step.
@@ -21,125 +31,113 @@ struct ChebCoef {
   double c[kMaxTerms][2];  // c_k = (2 - delta_k0) (-i)^k J_k(a dt)
 };
 
-// Scalar results of one step, reduced on the device.
-struct StepScalars {
-  double mass;      // discarded weight of the transfer
-  double norm2;     // |psi|^2 after propagation
-  double energy;    // <phi|H|phi> = <psi|H|psi> up to the series error
-  double a[2];      // <psi0|psi(t)>
+// Device-resident counts of one step.
+struct StepCtl {
+  uint32_t n_old;                     // rows of the set the step starts from
+  uint32_t nM;                        // selected rows
+  uint32_t fstart[kMaxRounds + 2];    // frontier r: [fstart[r], fstart[r+1])
+  uint32_t n_new;                     // rows of the new set
+  // current expansion round
+  uint32_t r_f0, r_rows, r_ncand, r_ntiles, r_ncur, r_total;
+  uint32_t nrec;                      // observation records written
+  double t;                           // time after the last completed step
+  double mass_total;                  // cumulative discarded weight
 };
 
-// Per-step observation record in the device ring buffer (doubles):
-// [t, norm2, energy, a_re, a_im, mass_step, mass_total, nS, nM, K,
-//  E_min, E_max, pop[0..N-1]].
-constexpr int kObsFields = 12;
+// Buffers of one expansion round.
+struct RoundBufs {
+  uint32_t* c_slot;     // [cand] table slot of owning candidates
+  uint32_t* c_ref;      // [cand] outcome of the probe
+  uint32_t* crow;       // [cand] row of owning candidates
+  uint32_t* tile_cnt;   // [cand / 256] owners per tile of candidates
+  uint32_t* tile_base;  // [cand / 256] exclusive scan of tile_cnt
+  uint32_t* scan_tmp;
+  int64_t cand_cap;     // candidates the buffers hold
+};
 
-// Launch geometry of grid-stride kernels that write per-block partials.
-constexpr int kPartBlocks = 1024;
+struct Side {
+  uint64_t* keys;
+  uint64_t* pay;
+  uint64_t* tot;
+};
 
 int supported_words(int W);  // internal word count >= W, or 0
+int64_t scan_tmp_words(int64_t n);
 
 void fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
-void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
-void iota_u32(uint32_t* p, int64_t n, hipStream_t s);
 
-// Exclusive scan of n u32 values; tmp needs scan_tmp_words(n) u32.
-int64_t scan_tmp_words(int64_t n);
-void exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n,
-                    uint32_t* tmp, uint32_t* total, hipStream_t s);
-
-// Compaction of rows whose weight clears theta^2 (ascending row order).
-void select_rows(int prec, const void* psi, int64_t n, double th2,
-                 uint32_t* midx, uint32_t* tmp, uint32_t* count,
+// Start of a step: clear the latch, reset the round counters.
+void begin_step(StepCtl* ctl, int* err, hipStream_t s);
+// Rows of ctl->n_old with weight >= th2, ascending, into midx; ctl->nM.
+// select_all: the first step takes every row.
+// counted: tmp already holds the per-tile counts (from pop_norm).
+void select_rows(int prec, const void* psi, double th2, bool select_all,
+                 bool counted, StepCtl* ctl, uint32_t* midx, uint32_t* tmp,
+                 int64_t cap, int* err, hipStream_t s);
+// Rows 0..nM-1 of the new side are M; inserted into the cleared table.
+void insert_rows(const DevModel& m, int Wi, const Side& o, const Side& n,
+                 const uint32_t* midx, const StepCtl* ctl, uint64_t* table,
+                 uint64_t mask, int* err, hipStream_t s);
+// Rebuild the table from rows [0, n) of a side (after growth).
+void rehash_rows(const DevModel& m, int Wi, const Side& n, uint32_t* midx,
+                 int64_t rows, uint64_t* table, uint64_t mask, int* err,
                  hipStream_t s);
-
-void row_info(const DevModel& m, int Wi, const uint64_t* keys, int64_t n,
-              uint64_t* pay, uint64_t* tot, double* diag, hipStream_t s);
-
-void insert_rows(const DevModel& m, int Wi, const uint64_t* keys_o,
-                 const uint64_t* pay_o, const uint64_t* tot_o,
-                 const double* diag_o, const uint32_t* midx, int64_t nM,
-                 uint64_t* keys_n, uint64_t* pay_n, uint64_t* tot_n,
-                 double* diag_n, uint64_t* table, uint64_t mask, int* err,
-                 hipStream_t s);
-
-struct RoundBufs {
-  uint32_t* c_slot;  // [rows*D] table slot of each candidate
-  uint32_t* c_ref;   // [rows*D] resolved reference
-  uint32_t* crow;    // [rows*D] row of owning candidates
-  uint32_t* rowcnt;  // [rows] new rows per parent
-  uint32_t* rowbase; // [rows] exclusive scan of rowcnt
-  uint32_t* scan_tmp;
-  uint32_t* total;   // [1] device
-};
-
-// One chunk of an expansion round: parents [f0, f0+rows) emit their slots;
-// new states are appended from row n_cur.  Writes the ELL columns of the
-// parents and zeroes phi of the new rows.
-void expand_chunk(const DevModel& m, int Wi, int prec, uint64_t* keys,
-                  uint64_t* pay, uint64_t* tot, double* diag, int64_t f0,
-                  int64_t rows, int64_t n_cur, uint64_t* table, uint64_t mask,
-                  const RoundBufs& rb, int32_t* col, int64_t stride, void* phi,
+// Expansion round r (1..k): frontier r-1 emits its slots; new rows are
+// appended and become frontier r.  Writes the parents' ELL columns and
+// zeroes phi of the new rows.
+// est: host estimate of the new set's rows, used only to size grids.
+void expand_round(const DevModel& m, int Wi, int prec, const Side& n, int r,
+                  StepCtl* ctl, int64_t cap, int64_t est, uint64_t* table,
+                  uint64_t mask, const RoundBufs& rb, int32_t* col, void* phi,
                   int* err, hipStream_t s);
-
-// Columns of parents [f0, f0+rows) by lookup only (last frontier).
-void lookup_cols(const DevModel& m, int Wi, const uint64_t* keys,
-                 const uint64_t* pay, int64_t f0, int64_t rows,
-                 const uint64_t* table, uint64_t mask, int32_t* col,
-                 int64_t stride, hipStream_t s);
-
-// phi[row of key in new set] = psi_old; discarded weight to mass_part.
-void transfer(const DevModel& m, int Wi, int prec, const uint64_t* keys_o,
-              const void* psi_o, int64_t n_old, const uint64_t* table,
-              uint64_t mask, const uint64_t* keys_n, void* phi,
-              double* mass_part, hipStream_t s);
-
-// Gershgorin bounds + Chebyshev coefficients (device only).
-void bounds_and_coef(const DevModel& m, const uint64_t* pay,
-                     const double* diag, const int32_t* col, int64_t stride,
-                     int64_t n, double dt, double tol, int k_max,
-                     double* part, ChebCoef* cc, int* err, hipStream_t s);
-
-// One Clenshaw step of the Chebyshev series (see kernels.hip).
-struct TermArgs {
-  int in_coef;    // -1: SpMV input unscaled, else scaled by c[in_coef]
-  int prev_coef;  // -1: prev unscaled, else scaled by c[prev_coef]
-  int ck;         // coefficient index applied to phi
-  int fac;        // 1 or 2
-  int final_;     // multiply by exp(-i b dt), reduce norm and populations
-  int energy;     // reduce Re <in|H|in>
-};
-void cheb_term(const DevModel& m, int prec, int64_t n, const int32_t* col,
-               int64_t stride, const uint64_t* pay, const double* diag,
-               const ChebCoef* cc, const TermArgs& ta, const void* phi,
-               const void* in, const void* prev, void* out, double* e_part,
-               double* n2_part, double* pop_part, hipStream_t s);
-// out = c[0] * phase * phi (a one-term series).
-void cheb_scale(int prec, int64_t n, const ChebCoef* cc, const void* phi,
-                void* out, double* n2_part, double* pop_part,
-                const uint64_t* pay, int N, hipStream_t s);
-// Energy <x|H|x> partials when no series term computed it.
-void energy_only(const DevModel& m, int prec, int64_t n, const int32_t* col,
-                 int64_t stride, const uint64_t* pay, const double* diag,
-                 const void* x, double* e_part, hipStream_t s);
-
+// Columns of frontier k (lookup only); sets ctl->n_new.
+void lookup_last(const DevModel& m, int Wi, const Side& n, int k,
+                 StepCtl* ctl, int64_t est, const uint64_t* table,
+                 uint64_t mask, int32_t* col, int64_t cap, int* err,
+                 hipStream_t s);
+// Number of per-block partials written by a kernel over `rows` rows.
+int part_grid(int64_t rows);
+// Returns the number of mass partials written.
+int transfer(const DevModel& m, int Wi, int prec, const Side& o,
+             const void* psi_o, int64_t n_old, const StepCtl* ctl,
+             const uint64_t* table, uint64_t mask, const uint64_t* keys_n,
+             void* phi, double* mass_part, int* err, hipStream_t s);
+// Gershgorin bounds + Chebyshev coefficients; latches if K > launched.
+void bounds_and_coef(const DevModel& m, const Side& n, const int32_t* col,
+                     int64_t cap, int64_t est, const StepCtl* ctl, double dt,
+                     double tol, int k_max, int launched, double* part,
+                     double* folded, ChebCoef* cc, int* err, hipStream_t s);
+// Fold n per-block partials to at most 256 (deterministic); returns count.
+int fold_sum(const double* in, int n, double* out, int* err, hipStream_t s);
+// Clenshaw launch for index kk (see kernels.hip); buffers b[0], b[1].
+// Returns the number of energy partials (written by the first launch).
+int cheb_term(const DevModel& m, int prec, int kk, bool energy, int64_t est,
+              const StepCtl* ctl, const int32_t* col, int64_t cap,
+              const Side& n, const ChebCoef* cc, const void* phi, void* b0,
+              void* b1, double* e_part, int* err, hipStream_t s);
+// |psi|^2 and exciton populations as per-block partials (returns their
+// count, at most kPartBlocks), plus the next step's select counts.
+int pop_norm(int prec, int N, double th2, int64_t est, const StepCtl* ctl,
+             const void* psi, const uint64_t* pay, double* n2_part,
+             double* pop_part, uint32_t* sel_bsum, int* err, hipStream_t s);
 void autocorr(const DevModel& m, int Wi, int prec, const uint64_t* keys0,
               const double* amps0, int64_t n0, const uint64_t* table,
               uint64_t mask, const uint64_t* keys, const void* psi,
-              double* out2, hipStream_t s);
+              double* out2, int* err, hipStream_t s);
+// Commit a successful step on the device: time, discarded weight, record
+// count and the row count of the current set.
+void end_step(StepCtl* ctl, const double* ring, int rec_doubles, int* err,
+              hipStream_t s);
+// Reduce partials into observation record ctl->nrec (skipped when an error
+// is latched, so a repeated step records once).
+void obs_final(int N, int want_energy, double dt, int n_mass, int n_e,
+               int n_pop, const double* mass_part, const double* n2_part,
+               const double* e_part, const double* pop_part, const double* a2,
+               const ChebCoef* cc, StepCtl* ctl, double* ring, int rec_doubles,
+               int64_t ring_cap, int* err, hipStream_t s);
 
-// Final reductions of a step into an observation record.
-struct ObsArgs {
-  double t, nS, nM, dt;
-  int N, want_energy;
-};
-void obs_final(const ObsArgs& oa, const double* mass_part,
-               const double* n2_part, const double* e_part,
-               const double* pop_part, const double* a2, const ChebCoef* cc,
-               double* mass_total, double* rec, int* err, hipStream_t s);
-
-// Widen / narrow amplitudes between the boundary's interleaved FP64 and the
-// internal precision.
+void row_info(const DevModel& m, int Wi, const uint64_t* keys, int64_t n,
+              uint64_t* pay, uint64_t* tot, hipStream_t s);
 void amps_to_f64(int prec, const void* src, double* dst, int64_t n,
                  hipStream_t s);
 void amps_from_f64(int prec, const double* src, void* dst, int64_t n,

@@ -165,15 +165,9 @@ paces_status check_unique(const paces_model* m, int64_t n,
   return PACES_OK;
 }
 
-struct Side {
-  uint64_t* keys = nullptr;
-  uint64_t* pay = nullptr;
-  uint64_t* tot = nullptr;
-  double* diag = nullptr;
-};
-
 struct EventPair {
   int stage;
+  int kk;  // Clenshaw launch index (series launches only)
   hipEvent_t a, b;
   double bytes;
 };
@@ -188,82 +182,75 @@ struct paces_sim {
   double th2 = 0;
 
   int64_t cap = 0;  // row capacity of every row array
-  Side side[2];
+  Side side[2]{};
   int cur = 0;      // side holding the current set S
   void* vec[4] = {nullptr, nullptr, nullptr, nullptr};
-  int ipsi = 0, iphi = 1, ibA = 2, ibB = 3;
+  int ipsi = 0, iphi = 1, ib0 = 2, ib1 = 3;
   int32_t* col = nullptr;
   uint64_t* table = nullptr;
-  uint64_t tmask = 0;
+  uint64_t tmask = 0;        // probe mask of the current step
+  uint64_t tmask_alloc = 0;  // allocated table size - 1
   uint32_t* midx = nullptr;
-
-  int64_t cand_rows = 0;
+  uint32_t* scan_tmp = nullptr;  // select
   RoundBufs rb{};
-  uint32_t* scan_tmp = nullptr;  // for select
-  uint32_t* d_u32 = nullptr;     // [4] small device counters
-  double* parts = nullptr;       // partial sums
+
+  StepCtl* ctl = nullptr;
+  int* err = nullptr;
+  double* parts = nullptr;
   double *mass_part = nullptr, *n2_part = nullptr, *e_part = nullptr,
          *pop_part = nullptr, *bnd_part = nullptr;
+  double *mass_fold = nullptr, *e_fold = nullptr, *bnd_fold = nullptr;
   ChebCoef* cc = nullptr;
   double* a2 = nullptr;
-  double* mass_total = nullptr;
-  int* err = nullptr;
 
   uint64_t* keys0 = nullptr;
   double* amps0 = nullptr;
   int64_t n0 = 0;
 
   double* ring = nullptr;
-  int64_t ring_cap = 0, nrec = 0;
+  int64_t ring_cap = 0;
   int rec_doubles = 0;
 
-  // host-side state
-  int64_t nS = 0, nM = 0;
-  std::vector<int64_t> fstart;  // frontier r = rows [fstart[r], fstart[r+1])
-  double t = 0;
+  // host mirror of the device state after the last completed step
+  StepCtl h{};              // copy of *ctl
+  int64_t nS = 0;
   bool fresh = true;
+  bool have_sets = false;   // M / frontiers / phi describe the last step
+  bool counts_valid = false;  // scan_tmp holds the next select's counts
+  int launched = 32;        // Clenshaw launches enqueued per step
+  int K_last = 0;
+  int k_last = 0;           // neighbour order of the last step
   int latched = 0;
-  uint32_t* h_u32 = nullptr;  // pinned
-  int32_t* h_i32 = nullptr;   // pinned
+  StepCtl* h_ctl = nullptr;  // pinned
+  int* h_err = nullptr;      // pinned
+  int* h_K = nullptr;        // pinned
   std::vector<double> pop_host;
 
   bool prof = false;
-  std::vector<EventPair> events;
+  std::vector<EventPair> pending, events;
   paces_profile acc{};
 };
 
 namespace {
 
-paces_status sync_read_u32(paces_sim* s, const uint32_t* d, uint32_t* out,
-                           hipStream_t st) {
-  HIP_TRY(hipMemcpyAsync(s->h_u32, d, 4, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  *out = *s->h_u32;
-  return PACES_OK;
-}
-
-paces_status check_latch(paces_sim* s, hipStream_t st) {
-  HIP_TRY(hipMemcpyAsync(s->h_i32, s->err, 4, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  const int e = *s->h_i32;
+paces_status check_latch_code(paces_sim* s, int e) {
   if (!e) return PACES_OK;
   s->latched = e;
-  if (e & kErrTableFull)
-    return fail(PACES_E_CAPACITY, "hash table overflow");
-  if (e & kErrCapacity) return fail(PACES_E_CAPACITY, "row capacity exceeded");
   if (e & kErrTerms)
     return fail(PACES_E_PROPAGATOR, "series needs more than k_max_terms terms");
-  return fail(PACES_E_NONFINITE, "non-finite norm after propagation");
+  if (e & kErrNonFinite)
+    return fail(PACES_E_NONFINITE, "non-finite norm after propagation");
+  if (e & kErrTableFull) return fail(PACES_E_CAPACITY, "hash table overflow");
+  return fail(PACES_E_CAPACITY, "row capacity exceeded");
 }
 
 struct Stage {
   paces_sim* s;
-  int stage;
+  int stage, kk;
   hipStream_t st;
   hipEvent_t a{}, b{};
-  double bytes;
-  Stage(paces_sim* s_, int stage_, hipStream_t st_, double bytes_ = 0)
-      : s(s_), stage(stage_), st(st_), bytes(bytes_) {
+  Stage(paces_sim* s_, int stage_, hipStream_t st_, int kk_ = -1)
+      : s(s_), stage(stage_), kk(kk_), st(st_) {
     if (s->prof) {
       (void)hipEventCreate(&a);
       (void)hipEventCreate(&b);
@@ -273,17 +260,24 @@ struct Stage {
   ~Stage() {
     if (s->prof) {
       (void)hipEventRecord(b, st);
-      s->events.push_back({stage, a, b, bytes});
+      s->pending.push_back({stage, kk, a, b, 0.0});
     }
   }
 };
+
+void drop_pending(paces_sim* s) {
+  for (auto& e : s->pending) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  s->pending.clear();
+}
 
 void free_rows(paces_sim* s) {
   for (int q = 0; q < 2; ++q) {
     dfree(s->side[q].keys);
     dfree(s->side[q].pay);
     dfree(s->side[q].tot);
-    dfree(s->side[q].diag);
   }
   for (auto& v : s->vec) {
     if (v) (void)hipFree(v);
@@ -295,125 +289,144 @@ void free_rows(paces_sim* s) {
   dfree(s->scan_tmp);
 }
 
+void free_cand(paces_sim* s) {
+  dfree(s->rb.c_slot);
+  dfree(s->rb.c_ref);
+  dfree(s->rb.crow);
+  dfree(s->rb.tile_cnt);
+  dfree(s->rb.tile_base);
+  dfree(s->rb.scan_tmp);
+  s->rb.cand_cap = 0;
+}
+
 uint64_t table_size_for(int64_t cap) {
   uint64_t P = 1024;
   while (P < uint64_t(2 * cap)) P <<= 1;
   return P;
 }
 
-// Grow every row array to new_cap, keeping rows [0, n_cur_side) of side cur
-// (old set + psi) and [0, n_new) of the other side (phi, columns of parents
-// before col_rows), then rebuild the table from the new side's rows.
-paces_status grow(paces_sim* s, int64_t new_cap, int64_t n_new,
-                  int64_t col_rows, bool table_from_new, hipStream_t st) {
+// Reallocate every row array for new_cap rows, keeping the current set
+// (side cur, rows [0, nS)) and its amplitudes.  Everything else is rebuilt
+// by the next step.
+paces_status grow(paces_sim* s, int64_t new_cap, hipStream_t st) {
   const paces_model* m = s->m;
-  new_cap = (new_cap + 255) / 256 * 256;
-  paces_sim old;  // holds the old pointers only
-  for (int q = 0; q < 2; ++q) old.side[q] = s->side[q];
-  for (int v = 0; v < 4; ++v) old.vec[v] = s->vec[v];
-  old.col = s->col;
-  old.table = s->table;
-  old.midx = s->midx;
-  old.scan_tmp = s->scan_tmp;
-  const int64_t old_cap = s->cap;
-  const int64_t nvalid[2] = {s->cur == 0 ? s->nS : n_new,
-                             s->cur == 1 ? s->nS : n_new};
-
+  new_cap = std::min<int64_t>((new_cap + 255) / 256 * 256, (int64_t(1) << 31) - 256);
+  if (new_cap <= s->cap && s->cap > 0)
+    return fail(PACES_E_CAPACITY, "row capacity limit (2^31 rows) reached");
+  Side old = s->side[s->cur];
+  void* old_psi = s->vec[s->ipsi];
   for (int q = 0; q < 2; ++q) {
-    ST_TRY(dalloc(&s->side[q].keys, new_cap * m->Wi));
-    ST_TRY(dalloc(&s->side[q].pay, new_cap));
-    ST_TRY(dalloc(&s->side[q].tot, new_cap));
-    ST_TRY(dalloc(&s->side[q].diag, new_cap));
-    const int64_t nv = old_cap ? nvalid[q] : 0;
-    if (nv > 0) {
-      HIP_TRY(hipMemcpyAsync(s->side[q].keys, old.side[q].keys,
-                             size_t(nv) * m->Wi * 8, hipMemcpyDeviceToDevice, st));
-      HIP_TRY(hipMemcpyAsync(s->side[q].pay, old.side[q].pay, size_t(nv) * 8,
-                             hipMemcpyDeviceToDevice, st));
-      HIP_TRY(hipMemcpyAsync(s->side[q].tot, old.side[q].tot, size_t(nv) * 8,
-                             hipMemcpyDeviceToDevice, st));
-      HIP_TRY(hipMemcpyAsync(s->side[q].diag, old.side[q].diag, size_t(nv) * 8,
-                             hipMemcpyDeviceToDevice, st));
+    if (q == s->cur) continue;
+    dfree(s->side[q].keys);
+    dfree(s->side[q].pay);
+    dfree(s->side[q].tot);
+  }
+  for (int v = 0; v < 4; ++v)
+    if (v != s->ipsi && s->vec[v]) {
+      (void)hipFree(s->vec[v]);
+      s->vec[v] = nullptr;
     }
+  dfree(s->col);
+  dfree(s->table);
+  dfree(s->midx);
+  dfree(s->scan_tmp);
+  Side nsd[2]{};
+  for (int q = 0; q < 2; ++q) {
+    ST_TRY(dalloc(&nsd[q].keys, new_cap * m->Wi));
+    ST_TRY(dalloc(&nsd[q].pay, new_cap));
+    ST_TRY(dalloc(&nsd[q].tot, new_cap));
   }
   for (int v = 0; v < 4; ++v) {
-    HIP_TRY(hipMalloc(&s->vec[v], size_t(new_cap) * s->A));
-    int64_t nv = 0;
-    if (old_cap) {
-      if (v == s->ipsi) nv = s->nS;
-      if (v == s->iphi) nv = n_new;
+    void* q = nullptr;
+    HIP_TRY(hipMalloc(&q, size_t(new_cap) * s->A));
+    if (v == s->ipsi) {
+      if (s->nS > 0)
+        HIP_TRY(hipMemcpyAsync(q, old_psi, size_t(s->nS) * s->A,
+                               hipMemcpyDeviceToDevice, st));
     }
-    if (nv > 0)
-      HIP_TRY(hipMemcpyAsync(s->vec[v], old.vec[v], size_t(nv) * s->A,
-                             hipMemcpyDeviceToDevice, st));
+    s->vec[v] = q;
+  }
+  if (s->nS > 0) {
+    Side& c = nsd[s->cur];
+    HIP_TRY(hipMemcpyAsync(c.keys, old.keys, size_t(s->nS) * m->Wi * 8,
+                           hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c.pay, old.pay, size_t(s->nS) * 8,
+                           hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c.tot, old.tot, size_t(s->nS) * 8,
+                           hipMemcpyDeviceToDevice, st));
   }
   ST_TRY(dalloc(&s->col, new_cap * m->D));
-  if (old_cap && col_rows > 0)
-    HIP_TRY(hipMemcpy2DAsync(s->col, size_t(new_cap) * 4, old.col,
-                             size_t(old_cap) * 4, size_t(col_rows) * 4, m->D,
-                             hipMemcpyDeviceToDevice, st));
   const uint64_t P = table_size_for(new_cap);
   ST_TRY(dalloc(&s->table, int64_t(P)));
+  s->tmask_alloc = P - 1;
   s->tmask = P - 1;
-  fill_u64(s->table, int64_t(P), kEmpty, st);
+  s->counts_valid = false;
   ST_TRY(dalloc(&s->midx, new_cap));
   ST_TRY(dalloc(&s->scan_tmp, scan_tmp_words(new_cap)));
-  s->cap = new_cap;
-  if (table_from_new && n_new > 0) {
-    // rebuild the table from the new side's rows (identity selection)
-    Side& sn = s->side[1 - s->cur];
-    iota_u32(s->midx, n_new, st);
-    insert_rows(m->dm, m->Wi, sn.keys, sn.pay, sn.tot, sn.diag, s->midx, n_new,
-                sn.keys, sn.pay, sn.tot, sn.diag, s->table, s->tmask, s->err,
-                st);
-  }
   HIP_TRY(hipStreamSynchronize(st));
-  for (int q = 0; q < 2; ++q) {
-    dfree(old.side[q].keys);
-    dfree(old.side[q].pay);
-    dfree(old.side[q].tot);
-    dfree(old.side[q].diag);
+  dfree(old.keys);
+  dfree(old.pay);
+  dfree(old.tot);
+  if (old_psi) (void)hipFree(old_psi);
+  s->side[0] = nsd[0];
+  s->side[1] = nsd[1];
+  s->cap = new_cap;
+  // candidate buffers: half the worst case to start with; grown on demand
+  const int64_t want = std::min<int64_t>(std::max<int64_t>(new_cap * m->D / 2,
+                                                           int64_t(1) << 16),
+                                         (int64_t(1) << 31) - 1);
+  if (want > s->rb.cand_cap) {
+    free_cand(s);
+    const int64_t tiles = want / 256 + 2;
+    ST_TRY(dalloc(&s->rb.c_slot, want));
+    ST_TRY(dalloc(&s->rb.c_ref, want));
+    ST_TRY(dalloc(&s->rb.crow, want));
+    ST_TRY(dalloc(&s->rb.tile_cnt, tiles));
+    ST_TRY(dalloc(&s->rb.tile_base, tiles));
+    ST_TRY(dalloc(&s->rb.scan_tmp, scan_tmp_words(tiles)));
+    s->rb.cand_cap = want;
   }
-  for (auto& v : old.vec)
-    if (v) (void)hipFree(v);
-  dfree(old.col);
-  dfree(old.table);
-  dfree(old.midx);
-  dfree(old.scan_tmp);
   return PACES_OK;
 }
 
-paces_status ensure_cand(paces_sim* s, int64_t rows) {
-  if (rows <= s->cand_rows) return PACES_OK;
-  const int D = s->m->D;
-  dfree(s->rb.c_slot);
-  dfree(s->rb.c_ref);
-  dfree(s->rb.crow);
-  dfree(s->rb.rowcnt);
-  dfree(s->rb.rowbase);
-  dfree(s->rb.scan_tmp);
-  ST_TRY(dalloc(&s->rb.c_slot, rows * D));
-  ST_TRY(dalloc(&s->rb.c_ref, rows * D));
-  ST_TRY(dalloc(&s->rb.crow, rows * D));
-  ST_TRY(dalloc(&s->rb.rowcnt, rows));
-  ST_TRY(dalloc(&s->rb.rowbase, rows));
-  ST_TRY(dalloc(&s->rb.scan_tmp, scan_tmp_words(rows)));
-  s->cand_rows = rows;
+paces_status grow_cand(paces_sim* s, hipStream_t st) {
+  const int64_t want =
+      std::min<int64_t>(2 * s->rb.cand_cap, (int64_t(1) << 31) - 1);
+  if (want <= s->rb.cand_cap)
+    return fail(PACES_E_CAPACITY, "candidate capacity limit reached");
+  HIP_TRY(hipStreamSynchronize(st));
+  free_cand(s);
+  const int64_t tiles = want / 256 + 2;
+  ST_TRY(dalloc(&s->rb.c_slot, want));
+  ST_TRY(dalloc(&s->rb.c_ref, want));
+  ST_TRY(dalloc(&s->rb.crow, want));
+  ST_TRY(dalloc(&s->rb.tile_cnt, tiles));
+  ST_TRY(dalloc(&s->rb.tile_base, tiles));
+  ST_TRY(dalloc(&s->rb.scan_tmp, scan_tmp_words(tiles)));
+  s->rb.cand_cap = want;
   return PACES_OK;
 }
 
 paces_status ensure_ring(paces_sim* s, hipStream_t st) {
-  if (s->nrec < s->ring_cap) return PACES_OK;
+  if (int64_t(s->h.nrec) + 1 < s->ring_cap) return PACES_OK;
   const int64_t nc = std::max<int64_t>(1024, 2 * s->ring_cap);
   double* r = nullptr;
   ST_TRY(dalloc(&r, nc * s->rec_doubles));
-  if (s->nrec > 0)
-    HIP_TRY(hipMemcpyAsync(r, s->ring, size_t(s->nrec) * s->rec_doubles * 8,
+  if (s->h.nrec > 0)
+    HIP_TRY(hipMemcpyAsync(r, s->ring, size_t(s->h.nrec) * s->rec_doubles * 8,
                            hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
   dfree(s->ring);
   s->ring = r;
   s->ring_cap = nc;
+  return PACES_OK;
+}
+
+paces_status push_ctl(paces_sim* s, hipStream_t st) {
+  *s->h_ctl = s->h;
+  HIP_TRY(hipMemcpyAsync(s->ctl, s->h_ctl, sizeof(StepCtl),
+                         hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
   return PACES_OK;
 }
 
@@ -423,207 +436,179 @@ paces_status upload_state(paces_sim* s, int64_t n, const uint64_t* keys,
   const paces_model* m = s->m;
   if (n > s->cap) {
     s->nS = 0;
-    ST_TRY(grow(s, std::max<int64_t>(n, 2 * s->cap), 0, 0, false, st));
+    ST_TRY(grow(s, std::max<int64_t>(2 * n, 2 * s->cap), st));
   }
   std::vector<uint64_t> ik;
   to_internal(m, n, keys, ik);
   Side& sc = s->side[s->cur];
-  HIP_TRY(hipMemcpyAsync(sc.keys, ik.data(), ik.size() * 8,
-                         hipMemcpyHostToDevice, st));
-  double* tmp = nullptr;
-  ST_TRY(dalloc(&tmp, 2 * n));
-  HIP_TRY(hipMemcpyAsync(tmp, amps, size_t(n) * 16, hipMemcpyHostToDevice, st));
-  amps_from_f64(s->prec, tmp, s->vec[s->ipsi], n, st);
-  row_info(m->dm, m->Wi, sc.keys, n, sc.pay, sc.tot, sc.diag, st);
-  HIP_TRY(hipStreamSynchronize(st));
-  dfree(tmp);
+  if (n > 0) {
+    HIP_TRY(hipMemcpyAsync(sc.keys, ik.data(), ik.size() * 8,
+                           hipMemcpyHostToDevice, st));
+    double* tmp = nullptr;
+    ST_TRY(dalloc(&tmp, 2 * n));
+    HIP_TRY(hipMemcpyAsync(tmp, amps, size_t(n) * 16, hipMemcpyHostToDevice, st));
+    amps_from_f64(s->prec, tmp, s->vec[s->ipsi], n, st);
+    row_info(m->dm, m->Wi, sc.keys, n, sc.pay, sc.tot, st);
+    HIP_TRY(hipStreamSynchronize(st));
+    dfree(tmp);
+  }
   s->nS = n;
-  return PACES_OK;
+  s->h.n_old = uint32_t(n);
+  return push_ctl(s, st);
 }
 
-paces_status do_step(paces_sim* s, hipStream_t st) {
+// Enqueue one attempt of a step.  Nothing here waits on the GPU.  `est`
+// (the host's guess of the new set's size) only sizes launch grids; every
+// kernel strides over whatever the device counts say.
+void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st) {
   const paces_model* m = s->m;
   const DevModel& dm = m->dm;
-  const int D = m->D, Wi = m->Wi;
-  const int64_t n_old = s->nS;
+  const int Wi = m->Wi;
   const int old = s->cur, nw = 1 - s->cur;
-
-  // ---- select
-  int k = s->p.k;
+  const int k = s->fresh ? s->p.k_init : s->p.k;
+  const Side so = s->side[old], sn = s->side[nw];
+  begin_step(s->ctl, s->err, st);
   {
     Stage sg(s, PACES_STAGE_SELECT, st);
-    if (s->fresh) {
-      k = s->p.k_init;
-      s->nM = n_old;
-      iota_u32(s->midx, n_old, st);
-    } else {
-      select_rows(s->prec, s->vec[s->ipsi], n_old, s->th2, s->midx,
-                  s->scan_tmp, s->d_u32, st);
-    }
+    select_rows(s->prec, s->vec[s->ipsi], s->th2, s->fresh, counted, s->ctl,
+                s->midx, s->scan_tmp, std::max<int64_t>(s->nS, 1), s->err,
+                st);
   }
-  if (!s->fresh) {
-    uint32_t nm;
-    ST_TRY(sync_read_u32(s, s->d_u32, &nm, st));
-    s->nM = nm;
-  }
-
-  // ---- expand: rows 0..nM-1 of the new set are M in selection order
   {
     Stage sg(s, PACES_STAGE_EXPAND, st);
     fill_u64(s->table, int64_t(s->tmask + 1), kEmpty, st);
-    insert_rows(dm, Wi, s->side[old].keys, s->side[old].pay, s->side[old].tot,
-                s->side[old].diag, s->midx, s->nM, s->side[nw].keys,
-                s->side[nw].pay, s->side[nw].tot, s->side[nw].diag, s->table,
-                s->tmask, s->err, st);
+    insert_rows(dm, Wi, so, sn, s->midx, s->ctl, s->table, s->tmask, s->err,
+                st);
+    for (int r = 1; r <= k; ++r)
+      expand_round(dm, Wi, s->prec, sn, r, s->ctl, s->cap, est, s->table,
+                   s->tmask, s->rb, s->col, s->vec[s->iphi], s->err, st);
+    lookup_last(dm, Wi, sn, k, s->ctl, est, s->table, s->tmask, s->col,
+                s->cap, s->err, st);
   }
-  int64_t n_cur = s->nM;
-  s->fstart.assign(1, 0);
-  s->fstart.push_back(n_cur);
-  for (int r = 1; r <= k; ++r) {
-    const int64_t f0 = s->fstart[r - 1], f1 = s->fstart[r];
-    int64_t p0 = f0;
-    while (p0 < f1) {
-      int64_t rows = std::min<int64_t>(f1 - p0, int64_t(1) << 24);
-      // rows * D new states at most; shrink the chunk before growing
-      int64_t room = (s->cap - n_cur) / D;
-      if (room < rows && room < std::max<int64_t>(rows / 4, 65536)) {
-        ST_TRY(grow(s, std::max(2 * s->cap, n_cur + rows * D), n_cur, p0,
-                    true, st));
-        room = (s->cap - n_cur) / D;
-      }
-      rows = std::min(rows, room);
-      ST_TRY(ensure_cand(s, rows));
-      Side& sn = s->side[nw];
-      {
-        Stage sg(s, PACES_STAGE_EXPAND, st);
-        expand_chunk(dm, Wi, s->prec, sn.keys, sn.pay, sn.tot, sn.diag, p0,
-                     rows, n_cur, s->table, s->tmask, s->rb, s->col, s->cap,
-                     s->vec[s->iphi], s->err, st);
-      }
-      uint32_t added;
-      ST_TRY(sync_read_u32(s, s->rb.total, &added, st));
-      n_cur += added;
-      p0 += rows;
-    }
-    s->fstart.push_back(n_cur);
-  }
-  {
-    Stage sg(s, PACES_STAGE_EXPAND, st);
-    const int64_t f0 = s->fstart[k], f1 = s->fstart[k + 1];
-    lookup_cols(dm, Wi, s->side[nw].keys, s->side[nw].pay, f0, f1 - f0,
-                s->table, s->tmask, s->col, s->cap, st);
-  }
-  const int64_t nS = n_cur;
-
-  // ---- transfer
+  int n_mass = 0, n_e = 0;
   {
     Stage sg(s, PACES_STAGE_TRANSFER, st);
-    transfer(dm, Wi, s->prec, s->side[old].keys, s->vec[s->ipsi], n_old,
-             s->table, s->tmask, s->side[nw].keys, s->vec[s->iphi],
-             s->mass_part, st);
+    const int np = transfer(dm, Wi, s->prec, so, s->vec[s->ipsi], s->nS,
+                            s->ctl, s->table, s->tmask, sn.keys,
+                            s->vec[s->iphi], s->mass_part, s->err, st);
+    n_mass = fold_sum(s->mass_part, np, s->mass_fold, s->err, st);
   }
-  // ---- build: bounds and coefficients
   {
     Stage sg(s, PACES_STAGE_BUILD, st);
-    bounds_and_coef(dm, s->side[nw].pay, s->side[nw].diag, s->col, s->cap, nS,
-                    s->p.dt, s->p.tol, s->p.k_max_terms, s->bnd_part, s->cc,
-                    s->err, st);
+    bounds_and_coef(dm, sn, s->col, s->cap, est, s->ctl, s->p.dt, s->p.tol,
+                    s->p.k_max_terms, s->launched, s->bnd_part, s->bnd_fold,
+                    s->cc, s->err, st);
   }
-  HIP_TRY(hipMemcpyAsync(s->h_i32, &s->cc->K, 4, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  const int K = *s->h_i32;
-  if (K < 1 || K > kMaxTerms)
-    return fail(PACES_E_PROPAGATOR, "invalid number of series terms");
-
-  // ---- propagate
   const bool want_e = (s->p.obs_mask & PACES_OBS_ENERGY) != 0;
-  const Side& sn = s->side[nw];
-  int result = -1;
   {
     Stage sg(s, PACES_STAGE_PROPAGATE, st);
-    void* phi = s->vec[s->iphi];
-    if (K == 1) {
-      cheb_scale(s->prec, nS, s->cc, phi, s->vec[s->ibA], s->n2_part,
-                 s->pop_part, sn.pay, m->N, st);
-      if (want_e)
-        energy_only(dm, s->prec, nS, s->col, s->cap, sn.pay, sn.diag, phi,
-                    s->e_part, st);
-      result = s->ibA;
-    } else {
-      int cur = -1, prv = -1;
-      for (int kk = K - 2; kk >= 0; --kk) {
-        TermArgs ta{};
-        ta.ck = kk;
-        ta.fac = kk == 0 ? 1 : 2;
-        ta.final_ = kk == 0;
-        ta.energy = (kk == K - 2) && want_e;
-        ta.in_coef = -1;
-        ta.prev_coef = -1;
-        const void* in;
-        const void* prev;
-        int out;
-        if (kk == K - 2) {
-          in = phi;
-          ta.in_coef = K - 1;
-          prev = nullptr;
-          out = s->ibA;
-        } else if (kk == K - 3) {
-          in = s->vec[cur];
-          prev = phi;
-          ta.prev_coef = K - 1;
-          out = (cur == s->ibA) ? s->ibB : s->ibA;
-        } else {
-          in = s->vec[cur];
-          prev = s->vec[prv];
-          out = prv;
-        }
-        const bool middle = !ta.final_ && !ta.energy;
-        const double A = double(s->A);
-        const double bytes =
-            double(nS) * ((prev ? 4.0 : 3.0) * A + 4.0 * D + 16.0);
-        if (middle && s->prof) {
-          Stage tsg(s, PACES_STAGE_TERM, st, bytes);
-          cheb_term(dm, s->prec, nS, s->col, s->cap, sn.pay, sn.diag, s->cc,
-                    ta, phi, in, prev, s->vec[out], s->e_part, s->n2_part,
-                    s->pop_part, st);
-        } else {
-          cheb_term(dm, s->prec, nS, s->col, s->cap, sn.pay, sn.diag, s->cc,
-                    ta, phi, in, prev, s->vec[out], s->e_part, s->n2_part,
-                    s->pop_part, st);
-        }
-        prv = cur;
-        cur = out;
-      }
-      result = cur;
+    int np = 0;
+    for (int kk = s->launched - 1; kk >= 0; --kk) {
+      Stage tg(s, PACES_STAGE_TERM, st, kk);
+      np = cheb_term(dm, s->prec, kk, want_e, est, s->ctl, s->col, s->cap, sn,
+                     s->cc, s->vec[s->iphi], s->vec[s->ib0], s->vec[s->ib1],
+                     s->e_part, s->err, st);
     }
+    if (want_e) n_e = fold_sum(s->e_part, np, s->e_fold, s->err, st);
   }
-  // result buffer becomes psi
-  std::swap(s->ipsi, result == s->ibA ? s->ibA : s->ibB);
-  s->cur = nw;
-  s->nS = nS;
-  s->t = s->t + s->p.dt;
-  s->fresh = false;
-
-  // ---- observe
   {
     Stage sg(s, PACES_STAGE_OBSERVE, st);
-    ST_TRY(ensure_ring(s, st));
+    const int n_pop = pop_norm(s->prec, m->N, s->th2, est, s->ctl,
+                               s->vec[s->ib0], sn.pay, s->n2_part, s->pop_part,
+                               s->scan_tmp, s->err, st);
     autocorr(dm, Wi, s->prec, s->keys0, s->amps0, s->n0, s->table, s->tmask,
-             s->side[s->cur].keys, s->vec[s->ipsi], s->a2, st);
-    ObsArgs oa{};
-    oa.t = s->t;
-    oa.nS = double(nS);
-    oa.nM = double(s->nM);
-    oa.dt = s->p.dt;
-    oa.N = m->N;
-    oa.want_energy = want_e ? 1 : 0;
-    obs_final(oa, s->mass_part, s->n2_part, s->e_part, s->pop_part, s->a2,
-              s->cc, s->mass_total, s->ring + s->nrec * s->rec_doubles,
-              s->err, st);
-    s->nrec += 1;
+             sn.keys, s->vec[s->ib0], s->a2, s->err, st);
+    obs_final(m->N, want_e ? 1 : 0, s->p.dt, n_mass, n_e, n_pop, s->mass_fold,
+              s->n2_part, s->e_fold, s->pop_part, s->a2, s->cc, s->ctl,
+              s->ring, s->rec_doubles, s->ring_cap, s->err, st);
+    end_step(s->ctl, s->ring, s->rec_doubles, s->err, st);
   }
-  s->acc.rows_steps += double(nS);
-  return PACES_OK;
+}
+
+// One step: enqueue, read back the counts, repeat with more room when a
+// capacity was exceeded.
+paces_status do_step(paces_sim* s, hipStream_t st) {
+  const paces_model* m = s->m;
+  // keep room for the new set: growth of the set per step stays well below
+  // the factor used here in the workloads; an overflow is caught anyway
+  if (s->nS > s->cap / 2) ST_TRY(grow(s, 3 * s->nS, st));
+  ST_TRY(ensure_ring(s, st));
+  const int64_t est =
+      std::min<int64_t>(s->cap, std::max<int64_t>(s->nS + s->nS / 2, s->nS + 65536));
+  // probe only as much of the table as the step needs (load factor <= 1/2
+  // for a new set up to 1.5x the old one); the table clear costs with it
+  {
+    uint64_t P = 1024;
+    while (P < uint64_t(2 * est) && P <= s->tmask_alloc) P <<= 1;
+    s->tmask = std::min<uint64_t>(P - 1, s->tmask_alloc);
+  }
+  for (int attempt = 0; attempt < 40; ++attempt) {
+    enqueue_step(s, est, s->counts_valid && attempt == 0, st);
+    HIP_TRY(hipMemcpyAsync(s->h_ctl, s->ctl, sizeof(StepCtl),
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(s->h_err, s->err, sizeof(int), hipMemcpyDeviceToHost,
+                           st));
+    HIP_TRY(hipMemcpyAsync(s->h_K, &s->cc->K, sizeof(int),
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const int e = *s->h_err;
+    if (e == 0) {
+      const StepCtl& c = *s->h_ctl;
+      const int K = *s->h_K;
+      // classify the timed Clenshaw launches of this step
+      const double rowb = 4.0 * double(s->A) + 4.0 * m->D + (m->V > 2 ? 16 : 8);
+      for (auto& ev : s->pending) {
+        if (ev.stage == PACES_STAGE_TERM) {
+          if (ev.kk >= 1 && ev.kk <= K - 3) {
+            ev.bytes = double(c.n_new) * rowb;
+          } else {
+            (void)hipEventDestroy(ev.a);
+            (void)hipEventDestroy(ev.b);
+            ev.stage = -1;
+            continue;
+          }
+        }
+        s->events.push_back(ev);
+      }
+      s->pending.clear();
+      s->h = c;
+      s->nS = c.n_new;
+      s->cur = 1 - s->cur;
+      std::swap(s->ipsi, s->ib0);
+      s->k_last = s->fresh ? s->p.k_init : s->p.k;
+      s->fresh = false;
+      s->have_sets = true;
+      s->K_last = K;
+      s->launched = std::max(4, std::min(K + 2, kMaxTerms));
+      s->acc.rows_steps += double(c.n_new);
+      s->counts_valid = true;
+      return PACES_OK;
+    }
+    drop_pending(s);
+    if (e & (kErrTerms | kErrNonFinite)) return check_latch_code(s, e);
+    if (e & kErrNeedTerms) {
+      s->launched = std::min(*s->h_K + 2, kMaxTerms);
+      continue;
+    }
+    if (e & kErrTableFull) {
+      if (s->tmask < s->tmask_alloc)
+        s->tmask = 2 * s->tmask + 1;
+      else
+        ST_TRY(grow(s, 2 * s->cap, st));
+      continue;
+    }
+    if (e & kErrCapacity) {
+      // a clamped round or a full row array: grow whichever is short
+      const StepCtl& c = *s->h_ctl;
+      if (int64_t(c.r_rows) * m->D >= s->rb.cand_cap - m->D)
+        ST_TRY(grow_cand(s, st));
+      else
+        ST_TRY(grow(s, 2 * s->cap, st));
+      continue;
+    }
+    return check_latch_code(s, e);
+  }
+  return fail(PACES_E_CAPACITY, "step did not fit after repeated growth");
 }
 
 // Device copies of the model tables, made on first use so that loading a
@@ -827,15 +812,16 @@ paces_status paces_init_state(const paces_model* m, const paces_run_params* p,
   if (!m || !p || !out || n < 1 || !exc || !occ || !coef)
     return fail(PACES_E_ARG, "bad arguments");
   *out = nullptr;
-  if (!(p->dt > 0) || p->k < 0 || p->k_init < 0 || !(p->theta >= 0) ||
+  if (!(p->dt > 0) || p->k < 0 || p->k_init < 0 || p->k > kMaxRounds ||
+      p->k_init > kMaxRounds || !(p->theta >= 0) ||
       (p->precision != 64 && p->precision != 32) || p->k_max_terms < 0 ||
       p->k_max_terms > kMaxTerms || p->tol < 0 || p->cap_states < 0)
     return fail(PACES_E_ARG, "bad run parameters");
-  if (n > (int64_t(1) << 31) - 1) return fail(PACES_E_ARG, "too many states");
-  ST_TRY(ensure_device_tables(const_cast<paces_model*>(m)));
+  if (n > (int64_t(1) << 30)) return fail(PACES_E_ARG, "too many states");
   std::vector<uint64_t> keys(size_t(n) * m->W);
   ST_TRY(paces_pack_keys(m, n, exc, occ, keys.data()));
   ST_TRY(check_unique(m, n, keys.data()));
+  ST_TRY(ensure_device_tables(const_cast<paces_model*>(m)));
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   paces_sim* s = new paces_sim();
   s->m = m;
@@ -852,26 +838,32 @@ paces_status paces_init_state(const paces_model* m, const paces_run_params* p,
     paces_free_sim(s);
     return st_;
   };
-  if (hipHostMalloc(reinterpret_cast<void**>(&s->h_u32), 64) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&s->h_i32), 64) != hipSuccess)
+  if (hipHostMalloc(reinterpret_cast<void**>(&s->h_ctl), sizeof(StepCtl)) !=
+          hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&s->h_err), 64) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&s->h_K), 64) != hipSuccess)
     return cleanup(fail(PACES_E_OOM, "pinned host allocation failed"));
-  const int64_t nparts = 5 * kPartBlocks + int64_t(kPartBlocks) * m->N;
-  if (dalloc(&s->d_u32, 16) || dalloc(&s->parts, nparts) ||
-      dalloc(&s->cc, 1) || dalloc(&s->a2, 2) || dalloc(&s->mass_total, 1) ||
-      dalloc(&s->err, 1) || dalloc(&s->keys0, n * m->Wi) ||
-      dalloc(&s->amps0, 2 * n))
+  const int64_t nparts = 4 * int64_t(kMaxPartials) +
+                         int64_t(kPartBlocks) * (m->N + 1) + 4 * 256;
+  if (dalloc(&s->ctl, 1) || dalloc(&s->err, 1) || dalloc(&s->parts, nparts) ||
+      dalloc(&s->cc, 1) || dalloc(&s->a2, 2) ||
+      dalloc(&s->keys0, n * m->Wi) || dalloc(&s->amps0, 2 * n))
     return cleanup(PACES_E_OOM);
-  s->mass_part = s->parts;
-  s->n2_part = s->parts + kPartBlocks;
-  s->e_part = s->parts + 2 * kPartBlocks;
-  s->bnd_part = s->parts + 3 * kPartBlocks;  // (lo, hi) per block
-  s->pop_part = s->parts + 5 * kPartBlocks;  // N per block
+  s->mass_part = s->parts;                      // kMaxPartials
+  s->e_part = s->parts + kMaxPartials;           // kMaxPartials
+  s->bnd_part = s->parts + 2 * kMaxPartials;     // (lo, hi) per block
+  s->n2_part = s->parts + 4 * kMaxPartials;      // kPartBlocks
+  s->pop_part = s->n2_part + kPartBlocks;        // N per block
+  s->mass_fold = s->pop_part + int64_t(kPartBlocks) * m->N;  // 256
+  s->e_fold = s->mass_fold + 256;                             // 256
+  s->bnd_fold = s->e_fold + 256;                              // 2 x 256
   if (hipMemsetAsync(s->err, 0, 4, st) != hipSuccess ||
-      hipMemsetAsync(s->mass_total, 0, 8, st) != hipSuccess ||
       hipMemsetAsync(s->parts, 0, size_t(nparts) * 8, st) != hipSuccess)
     return cleanup(fail(PACES_E_HIP, "memset failed"));
   const int64_t cap0 = std::max<int64_t>({p->cap_states, 4 * n, 1 << 16});
-  paces_status g = grow(s, cap0, 0, 0, false, st);
+  paces_status g = grow(s, cap0, st);
+  if (g) return cleanup(g);
+  g = ensure_ring(s, st);
   if (g) return cleanup(g);
   std::vector<uint64_t> ik;
   to_internal(m, n, keys.data(), ik);
@@ -881,10 +873,10 @@ paces_status paces_init_state(const paces_model* m, const paces_run_params* p,
                      st) != hipSuccess)
     return cleanup(fail(PACES_E_HIP, "upload failed"));
   s->n0 = n;
+  std::memset(&s->h, 0, sizeof(s->h));
   g = upload_state(s, n, keys.data(), coef, st);
   if (g) return cleanup(g);
   s->fresh = true;
-  s->t = 0;
   *out = s;
   return PACES_OK;
 }
@@ -893,27 +885,23 @@ paces_status paces_free_sim(paces_sim* s) {
   if (!s) return PACES_OK;
   (void)hipDeviceSynchronize();
   free_rows(s);
-  dfree(s->rb.c_slot);
-  dfree(s->rb.c_ref);
-  dfree(s->rb.crow);
-  dfree(s->rb.rowcnt);
-  dfree(s->rb.rowbase);
-  dfree(s->rb.scan_tmp);
-  dfree(s->d_u32);
+  free_cand(s);
+  dfree(s->ctl);
+  dfree(s->err);
   dfree(s->parts);
   dfree(s->cc);
   dfree(s->a2);
-  dfree(s->mass_total);
-  dfree(s->err);
   dfree(s->keys0);
   dfree(s->amps0);
   dfree(s->ring);
+  drop_pending(s);
   for (auto& e : s->events) {
     (void)hipEventDestroy(e.a);
     (void)hipEventDestroy(e.b);
   }
-  if (s->h_u32) (void)hipHostFree(s->h_u32);
-  if (s->h_i32) (void)hipHostFree(s->h_i32);
+  if (s->h_ctl) (void)hipHostFree(s->h_ctl);
+  if (s->h_err) (void)hipHostFree(s->h_err);
+  if (s->h_K) (void)hipHostFree(s->h_K);
   delete s;
   return PACES_OK;
 }
@@ -922,33 +910,29 @@ paces_status paces_step(paces_sim* s, int64_t n_steps, void* hip_stream) {
   if (!s || n_steps < 0) return fail(PACES_E_ARG, "bad arguments");
   if (s->latched) return fail(PACES_E_STATE, "sim is in an error state");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  s->rb.total = s->d_u32 + 1;
   for (int64_t i = 0; i < n_steps; ++i) {
     paces_status r = do_step(s, st);
     if (r != PACES_OK) {
-      s->latched = s->latched ? s->latched : -1;
+      if (!s->latched) s->latched = -1;
       return r;
     }
-    // the step read device counts, so the stream is synchronised often;
-    // check the latch once per step at no extra cost
-    ST_TRY(check_latch(s, st));
   }
   return PACES_OK;
 }
 
 paces_status paces_observe(paces_sim* s, paces_obs* out, void* hip_stream) {
   if (!s || !out) return fail(PACES_E_ARG, "bad arguments");
+  if (s->latched) return fail(PACES_E_STATE, "sim is in an error state");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  ST_TRY(check_latch(s, st));
   std::memset(out, 0, sizeof(*out));
-  if (s->nrec == 0) {
-    out->t = s->t;
+  if (s->h.nrec == 0) {
+    out->t = s->h.t;
     out->n_S = s->nS;
     out->pop = s->pop_host.data();
     return PACES_OK;
   }
   std::vector<double> rec(s->rec_doubles);
-  HIP_TRY(hipMemcpyAsync(rec.data(), s->ring + (s->nrec - 1) * s->rec_doubles,
+  HIP_TRY(hipMemcpyAsync(rec.data(), s->ring + (s->h.nrec - 1) * s->rec_doubles,
                          rec.size() * 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   out->t = rec[0];
@@ -970,13 +954,14 @@ paces_status paces_observe(paces_sim* s, paces_obs* out, void* hip_stream) {
 
 paces_status paces_num_records(paces_sim* s, int64_t* n) {
   if (!s || !n) return fail(PACES_E_ARG, "bad arguments");
-  *n = s->nrec;
+  *n = s->h.nrec;
   return PACES_OK;
 }
 
 paces_status paces_series(paces_sim* s, int64_t first, int64_t n, double* out,
                           void* hip_stream) {
-  if (!s || first < 0 || n < 0 || first + n > s->nrec || (n && !out))
+  if (!s || first < 0 || n < 0 || first + n > int64_t(s->h.nrec) ||
+      (n && !out))
     return fail(PACES_E_ARG, "bad arguments");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   if (n == 0) return PACES_OK;
@@ -990,18 +975,18 @@ paces_status paces_series(paces_sim* s, int64_t first, int64_t n, double* out,
 paces_status paces_get_state(paces_sim* s, int64_t* n, uint64_t* keys,
                              double* amps, void* hip_stream) {
   if (!s || !n) return fail(PACES_E_ARG, "bad arguments");
+  if (s->latched) return fail(PACES_E_STATE, "sim is in an error state");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  ST_TRY(check_latch(s, st));
   *n = s->nS;
   const paces_model* m = s->m;
-  if (keys) {
+  if (keys && s->nS > 0) {
     std::vector<uint64_t> ik(size_t(s->nS) * m->Wi);
     HIP_TRY(hipMemcpyAsync(ik.data(), s->side[s->cur].keys, ik.size() * 8,
                            hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     to_canonical(m, s->nS, ik.data(), keys);
   }
-  if (amps) {
+  if (amps && s->nS > 0) {
     double* tmp = nullptr;
     ST_TRY(dalloc(&tmp, 2 * s->nS));
     amps_to_f64(s->prec, s->vec[s->ipsi], tmp, s->nS, st);
@@ -1017,16 +1002,17 @@ paces_status paces_set_state(paces_sim* s, int64_t n, const uint64_t* keys,
                              const double* amps, double t, void* hip_stream) {
   if (!s || n < 0 || (n > 0 && (!keys || !amps)))
     return fail(PACES_E_ARG, "bad arguments");
+  if (n > (int64_t(1) << 30)) return fail(PACES_E_ARG, "too many states");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   ST_TRY(check_keys(s->m, n, keys));
   ST_TRY(check_unique(s->m, n, keys));
   HIP_TRY(hipStreamSynchronize(st));
-  HIP_TRY(hipMemsetAsync(s->err, 0, 4, st));
   s->latched = 0;
+  s->h.t = t;
   ST_TRY(upload_state(s, n, keys, amps, st));
-  s->t = t;
   s->fresh = false;
-  s->fstart.clear();
+  s->have_sets = false;
+  s->counts_valid = false;
   return PACES_OK;
 }
 
@@ -1037,20 +1023,19 @@ paces_status paces_get_set(paces_sim* s, int32_t which, int32_t round,
   int64_t a = 0, b = 0;
   if (which == PACES_SET_S) {
     b = s->nS;
-  } else if (s->fstart.empty()) {
+  } else if (!s->have_sets) {
     return fail(PACES_E_STATE, "no step has run since the state was set");
   } else if (which == PACES_SET_M) {
-    b = s->nM;
+    b = s->h.nM;
   } else if (which == PACES_SET_FRONTIER) {
-    if (round < 0 || round + 1 >= int(s->fstart.size()))
-      return fail(PACES_E_ARG, "no such round");
-    a = s->fstart[round];
-    b = s->fstart[round + 1];
+    if (round < 0 || round > s->k_last) return fail(PACES_E_ARG, "no such round");
+    a = s->h.fstart[round];
+    b = s->h.fstart[round + 1];
   } else {
     return fail(PACES_E_ARG, "unknown set");
   }
   *n = b - a;
-  if (!keys) return PACES_OK;
+  if (!keys || b == a) return PACES_OK;
   const paces_model* m = s->m;
   std::vector<uint64_t> ik(size_t(b - a) * m->Wi);
   HIP_TRY(hipMemcpyAsync(ik.data(), s->side[s->cur].keys + a * m->Wi,
@@ -1062,9 +1047,10 @@ paces_status paces_get_set(paces_sim* s, int32_t which, int32_t round,
 
 paces_status paces_get_phi(paces_sim* s, double* amps, void* hip_stream) {
   if (!s || !amps) return fail(PACES_E_ARG, "bad arguments");
-  if (s->fstart.empty())
+  if (!s->have_sets)
     return fail(PACES_E_STATE, "no step has run since the state was set");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (s->nS == 0) return PACES_OK;
   double* tmp = nullptr;
   ST_TRY(dalloc(&tmp, 2 * s->nS));
   amps_to_f64(s->prec, s->vec[s->iphi], tmp, s->nS, st);
