@@ -30,8 +30,8 @@ HBM_PEAK_GBS = 8000.0
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=130)
     ap.add_argument("--config", default="ring16")
     ap.add_argument("--precision", type=int, default=64)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -97,6 +97,9 @@ def main():
     term_bytes = prof["term_bytes"] / max(n_term, 1)
     achieved = term_bytes / (term_ms * 1e-3) / 1e9 if n_term else 0.0
     stage_ms = {k: round(v, 3) for k, v in prof["ms"].items()}
+    row_bytes = 4 * A + 4 * D + (8 if model.V <= 2 else 16)
+    traffic = committed_traffic(args.config, args.precision,
+                                term_bytes / row_bytes if n_term else 0.0)
     out = {
         "metric": "basis-state updates/s (|S|*steps/s)",
         "value": value,
@@ -120,11 +123,11 @@ def main():
                    "S_mean": updates / args.steps},
         "roofline": {"bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_cheb_term (middle Clenshaw term)",
                      "launches": n_term, "avg_ms": term_ms,
                      "bytes_per_launch": term_bytes,
-                     "bytes_per_row": 4 * A + 4 * D + (8 if model.V <= 2 else 16)},
+                     "bytes_per_row": row_bytes},
         "stage_ms": stage_ms,
         "terms_per_step": float(rec[:, 9].mean()),
     }
@@ -132,6 +135,36 @@ def main():
         out["cpu_baseline"] = cpu_baseline(params, run, cpu_state, cfg,
                                            args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ["kernels.hip", "device.hpp", "kernels.hpp"]:
+        with open(os.path.join(ROOT, "paper_2603_07341_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(config, precision, rows_per_launch):
+    """HBM bytes per middle-term launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated with a plain copy), or None when
+    the kernel sources changed since the counters were taken or the
+    workload differs."""
+    path = os.path.join(ROOT, "profiles", "cheb_term_ring16_traffic.txt")
+    if config != "ring16" or precision != 64 or not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if "sha256[:16]" in line:
+                vals["sha"] = line.rsplit(":", 1)[1].strip()
+            elif line.startswith(("fetch_bytes_per_row:", "write_bytes_per_row:")):
+                k, v = line.split(":")
+                vals[k] = float(v)
+    if vals.get("sha") != source_hash() or len(vals) < 3:
+        return None
+    return (vals["fetch_bytes_per_row"] + vals["write_bytes_per_row"]) * rows_per_launch
 
 
 def cpu_baseline(params, run, state, cfg, budget_s):

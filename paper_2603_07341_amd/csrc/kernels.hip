@@ -157,19 +157,21 @@ __global__ void k_begin_step(StepCtl* ctl, int* err) {
 }
 
 // ---- scan over a device-sized array ----------------------------------------
-// Tile t covers elements [t*kTile, (t+1)*kTile); lane l owns the kItems
-// consecutive elements from t*kTile + l*kItems.  Blocks stride over tiles.
+// Tile t covers elements [t*kTile, (t+1)*kTile); element t*kTile + q*kBlock
+// + lane belongs to lane `lane` (q = 0..kItems-1), so every load of the block
+// is one contiguous run of kBlock elements.  Blocks stride over tiles.
 __global__ void __launch_bounds__(kBlock)
     k_scan_reduce(const uint32_t* in, const uint32_t* nptr, uint32_t* bsum,
                   const int* err) {
   if (*err) return;
   const int64_t n = *nptr, ntiles = cdiv(n, kTile);
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int64_t base = t * kTile + threadIdx.x * kItems;
     uint32_t v = 0;
 #pragma unroll
-    for (int q = 0; q < kItems; ++q)
-      if (base + q < n) v += in[base + q];
+    for (int q = 0; q < kItems; ++q) {
+      const int64_t e = t * kTile + q * kBlock + threadIdx.x;
+      if (e < n) v += in[e];
+    }
     uint32_t tot;
     block_excl_scan(v, &tot);
     if (threadIdx.x == 0) bsum[t] = tot;
@@ -184,24 +186,13 @@ __global__ void __launch_bounds__(kBlock)
   if (*err) return;
   const int64_t nb = cdiv(int64_t(*nptr), kTile);
   uint32_t carry = 0;
-  for (int64_t c = 0; c < nb; c += kTile) {
-    const int64_t base = c + threadIdx.x * kItems;
-    uint32_t loc[kItems];
-    uint32_t v = 0;
-#pragma unroll
-    for (int q = 0; q < kItems; ++q) {
-      loc[q] = (base + q < nb) ? bsum[base + q] : 0u;
-      v += loc[q];
-    }
+  for (int64_t c = 0; c < nb; c += kBlock) {
+    const int64_t e = c + threadIdx.x;
+    const uint32_t v = e < nb ? bsum[e] : 0u;
     uint32_t tot;
-    uint32_t off = block_excl_scan(v, &tot) + carry;
-#pragma unroll
-    for (int q = 0; q < kItems; ++q) {
-      if (base + q < nb) bsum[base + q] = off;
-      off += loc[q];
-    }
+    const uint32_t off = block_excl_scan(v, &tot) + carry;
+    if (e < nb) bsum[e] = off;
     carry += tot;
-    __syncthreads();
   }
   if (threadIdx.x == 0) {
     *out1 = carry;
@@ -215,20 +206,15 @@ __global__ void __launch_bounds__(kBlock)
   if (*err) return;
   const int64_t n = *nptr, ntiles = cdiv(n, kTile);
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int64_t base = t * kTile + threadIdx.x * kItems;
-    uint32_t loc[kItems];
-    uint32_t v = 0;
+    uint32_t run = bsum[t];
 #pragma unroll
     for (int q = 0; q < kItems; ++q) {
-      loc[q] = (base + q < n) ? in[base + q] : 0u;
-      v += loc[q];
-    }
-    uint32_t tot;
-    uint32_t off = block_excl_scan(v, &tot) + bsum[t];
-#pragma unroll
-    for (int q = 0; q < kItems; ++q) {
-      if (base + q < n) out[base + q] = off;
-      off += loc[q];
+      const int64_t e = t * kTile + q * kBlock + threadIdx.x;
+      const uint32_t v = e < n ? in[e] : 0u;
+      uint32_t tot;
+      const uint32_t off = block_excl_scan(v, &tot) + run;
+      if (e < n) out[e] = off;
+      run += tot;
     }
   }
 }
@@ -250,36 +236,36 @@ __global__ void __launch_bounds__(kBlock)
                    uint32_t* bsum) {
   const int64_t n = ctl->n_old, ntiles = cdiv(n, kTile);
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int64_t base = t * kTile + threadIdx.x * kItems;
     uint32_t v = 0;
 #pragma unroll
-    for (int q = 0; q < kItems; ++q)
-      if (base + q < n && weight(psi[base + q]) >= th2) ++v;
+    for (int q = 0; q < kItems; ++q) {
+      const int64_t e = t * kTile + q * kBlock + threadIdx.x;
+      if (e < n && weight(psi[e]) >= th2) ++v;
+    }
     uint32_t tot;
     block_excl_scan(v, &tot);
     if (threadIdx.x == 0) bsum[t] = tot;
   }
 }
 
+// Selected rows are written in ascending order: tile offset from the scan,
+// then one block scan per run of kBlock rows.
 template <typename Amp>
 __global__ void __launch_bounds__(kBlock)
     k_select_write(const Amp* psi, const StepCtl* ctl, double th2,
                    const uint32_t* bsum, uint32_t* midx) {
   const int64_t n = ctl->n_old, ntiles = cdiv(n, kTile);
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int64_t base = t * kTile + threadIdx.x * kItems;
-    bool keep[kItems];
-    uint32_t v = 0;
+    uint32_t run = bsum[t];
 #pragma unroll
     for (int q = 0; q < kItems; ++q) {
-      keep[q] = base + q < n && weight(psi[base + q]) >= th2;
-      v += keep[q] ? 1u : 0u;
+      const int64_t e = t * kTile + q * kBlock + threadIdx.x;
+      const bool keep = e < n && weight(psi[e]) >= th2;
+      uint32_t tot;
+      const uint32_t off = block_excl_scan(keep ? 1u : 0u, &tot) + run;
+      if (keep) midx[off] = uint32_t(e);
+      run += tot;
     }
-    uint32_t tot;
-    uint32_t off = block_excl_scan(v, &tot) + bsum[t];
-#pragma unroll
-    for (int q = 0; q < kItems; ++q)
-      if (keep[q]) midx[off++] = uint32_t(base + q);
   }
 }
 
@@ -741,7 +727,10 @@ struct VecT<float> {
   using T = float2;
 };
 
-template <typename R, int ND, int NV>
+// MID only names the launches the host expects to be middle terms (neither
+// first nor last for the previous step's K), so that profiles can tell them
+// apart; the code is the same and still decides its role from the device K.
+template <typename R, int ND, int NV, bool MID>
 __global__ void __launch_bounds__(kBlock)
     k_cheb_term(DevModel m, int kk, int want_energy,
                 const StepCtl* __restrict__ ctl, const int* __restrict__ err,
@@ -827,6 +816,18 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// Population bins in LDS: for up to kPrivBins sites every lane of a wave
+// owns a column (bin j, lane l at j*64 + l), so the four waves of a block
+// meet on an address at most four at a time; larger lattices share one bin
+// per site.
+constexpr int kPrivBins = 128;
+__device__ __forceinline__ void pop_add(double* lds, int N, int j, double w) {
+  if (N <= kPrivBins)
+    atomicAdd(&lds[j * 64 + (threadIdx.x & 63)], w);
+  else
+    atomicAdd(&lds[j], w);
+}
+
 // Norm and exciton populations of psi as per-block partials (populations
 // binned in LDS).  Rows are visited in the select kernels' tile layout, so
 // the same pass also counts, per tile, the rows the next step will select.
@@ -839,19 +840,20 @@ __global__ void __launch_bounds__(kBlock)
   extern __shared__ double pop_lds[];
   if (*err) return;
   const int64_t n = ctl->n_new, ntiles = cdiv(n, kTile);
-  for (int j = threadIdx.x; j < N; j += blockDim.x) pop_lds[j] = 0.0;
+  const int nbins = N <= kPrivBins ? N * 64 : N;
+  for (int j = threadIdx.x; j < nbins; j += blockDim.x) pop_lds[j] = 0.0;
   __syncthreads();
   double n2 = 0;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int64_t base = t * kTile + threadIdx.x * kItems;
     uint32_t keep = 0;
 #pragma unroll
     for (int q = 0; q < kItems; ++q) {
-      if (base + q < n) {
-        const double w = weight(psi[base + q]);
+      const int64_t e = t * kTile + q * kBlock + threadIdx.x;
+      if (e < n) {
+        const double w = weight(psi[e]);
         n2 += w;
         keep += w >= th2 ? 1u : 0u;
-        atomicAdd(&pop_lds[pay_site(pay[base + q])], w);
+        pop_add(pop_lds, N, pay_site(pay[e]), w);
       }
     }
     uint32_t tot;
@@ -861,8 +863,14 @@ __global__ void __launch_bounds__(kBlock)
   n2 = block_sum(n2);
   if (threadIdx.x == 0) n2_part[blockIdx.x] = n2;
   __syncthreads();
-  for (int j = threadIdx.x; j < N; j += blockDim.x)
-    pop_part[int64_t(blockIdx.x) * N + j] = pop_lds[j];
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    double v = 0;
+    if (N <= kPrivBins)
+      for (int l = 0; l < 64; ++l) v += pop_lds[j * 64 + l];
+    else
+      v = pop_lds[j];
+    pop_part[int64_t(blockIdx.x) * N + j] = v;
+  }
 }
 
 // Second level of a deterministic reduction: block b folds partials
@@ -1163,30 +1171,30 @@ int fold_sum(const double* in, int n, double* out, int* err, hipStream_t s) {
   return f;
 }
 
-int cheb_term(const DevModel& m, int prec, int kk, bool energy, int64_t est,
-              const StepCtl* ctl, const int32_t* col, int64_t cap,
+int cheb_term(const DevModel& m, int prec, int kk, bool energy, bool mid,
+              int64_t est, const StepCtl* ctl, const int32_t* col, int64_t cap,
               const Side& n, const ChebCoef* cc, const void* phi, void* b0,
               void* b1, double* e_part, int* err, hipStream_t s) {
   const int e = energy ? 1 : 0;
   const int g = grid_for(est);
+#define PACES_TERM(R, AMP, MIDV)                                              \
+  PACES_DISPATCH_SHAPE(m.ndim, m.V,                                           \
+      k_cheb_term<R, A, B, MIDV><<<g, kBlock, 0, s>>>(                        \
+          m, kk, e, ctl, err, col, cap, n.pay, n.tot, cc, (const AMP*)phi,    \
+          (AMP*)b0, (AMP*)b1, e_part))
   if (prec == 64) {
-    PACES_DISPATCH_SHAPE(m.ndim, m.V,
-        k_cheb_term<double, A, B><<<g, kBlock, 0, s>>>(
-            m, kk, e, ctl, err, col, cap, n.pay, n.tot, cc,
-            (const double2*)phi, (double2*)b0, (double2*)b1, e_part));
+    if (mid) { PACES_TERM(double, double2, true); } else { PACES_TERM(double, double2, false); }
   } else {
-    PACES_DISPATCH_SHAPE(m.ndim, m.V,
-        k_cheb_term<float, A, B><<<g, kBlock, 0, s>>>(
-            m, kk, e, ctl, err, col, cap, n.pay, n.tot, cc,
-            (const float2*)phi, (float2*)b0, (float2*)b1, e_part));
+    if (mid) { PACES_TERM(float, float2, true); } else { PACES_TERM(float, float2, false); }
   }
+#undef PACES_TERM
   return g;
 }
 
 int pop_norm(int prec, int N, double th2, int64_t est, const StepCtl* ctl,
              const void* psi, const uint64_t* pay, double* n2_part,
              double* pop_part, uint32_t* sel_bsum, int* err, hipStream_t s) {
-  const size_t lds = sizeof(double) * N;
+  const size_t lds = sizeof(double) * (N <= kPrivBins ? N * 64 : N);
   const int g = tiles_for(est);
   if (prec == 64)
     k_pop_norm<double><<<g, kBlock, lds, s>>>(N, th2, ctl, (const double2*)psi,

@@ -111,8 +111,9 @@ void bounds_and_coef(const DevModel& m, const Side& n, const int32_t* col,
 int fold_sum(const double* in, int n, double* out, int* err, hipStream_t s);
 // Clenshaw launch for index kk (see kernels.hip); buffers b[0], b[1].
 // Returns the number of energy partials (written by the first launch).
-int cheb_term(const DevModel& m, int prec, int kk, bool energy, int64_t est,
-              const StepCtl* ctl, const int32_t* col, int64_t cap,
+// mid: the launch is expected to be a middle term (selects a kernel name).
+int cheb_term(const DevModel& m, int prec, int kk, bool energy, bool mid,
+              int64_t est, const StepCtl* ctl, const int32_t* col, int64_t cap,
               const Side& n, const ChebCoef* cc, const void* phi, void* b0,
               void* b1, double* e_part, int* err, hipStream_t s);
 // |psi|^2 and exciton populations as per-block partials (returns their

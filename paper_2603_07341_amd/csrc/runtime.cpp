@@ -505,7 +505,8 @@ void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st) {
     int np = 0;
     for (int kk = s->launched - 1; kk >= 0; --kk) {
       Stage tg(s, PACES_STAGE_TERM, st, kk);
-      np = cheb_term(dm, s->prec, kk, want_e, est, s->ctl, s->col, s->cap, sn,
+      const bool mid = s->K_last >= 4 && kk >= 1 && kk <= s->K_last - 3;
+      np = cheb_term(dm, s->prec, kk, want_e, mid, est, s->ctl, s->col, s->cap, sn,
                      s->cc, s->vec[s->iphi], s->vec[s->ib0], s->vec[s->ib1],
                      s->e_part, s->err, st);
     }
