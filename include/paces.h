@@ -36,6 +36,17 @@
  *    call that synchronises; the sim then refuses further steps
  *    (PACES_E_STATE) until paces_set_state.
  *  - A sim is not thread-safe; distinct sims are independent.
+ *
+ * Batched disorder
+ *  A model may carry R independent realizations of the site energies
+ *  (paper: Sec. "Application to vibronic nanoaggregates", disorder
+ *  averages).  One sim then propagates R states in one set: every row
+ *  belongs to one realization, rows of different realizations never
+ *  couple, and each realization gets its own Gershgorin interval,
+ *  Chebyshev series and observation record.  The results of realization r
+ *  equal those of a sim of that realization alone (same sets, amplitudes
+ *  within rounding of the reductions).  Functions that return or accept
+ *  rows pair them with realization indices.
  */
 #ifndef PACES_H
 #define PACES_H
@@ -46,7 +57,7 @@
 extern "C" {
 #endif
 
-#define PACES_ABI_VERSION 1
+#define PACES_ABI_VERSION 2
 
 typedef enum {
   PACES_OK = 0,
@@ -73,11 +84,14 @@ typedef struct {
   int32_t extent[3];   /* sites per axis; unused axes 1                    */
   int32_t periodic[3]; /* wrap the axis; a periodic extent must be >= 3    */
   int32_t n_modes;     /* V, 1..4                                          */
-  int32_t cutoff[4];   /* max occupation per mode, 1..255                  */
+  int32_t cutoff[4];   /* max occupation per mode, 1..254                  */
   double omega[4];     /* mode frequencies                                 */
   double g[4];         /* exciton-phonon couplings                         */
   double J[3];         /* hopping per axis                                 */
-  const double* eps;   /* [N] site energies (host, copied); NULL = zeros   */
+  int32_t n_real;      /* R realizations of eps, 1..256 (0 = 1);
+                          R * (N + 3) <= 8064                              */
+  const double* eps;   /* [R][N] site energies (host, copied);
+                          NULL = zeros                                     */
 } paces_model_desc;
 
 typedef struct {
@@ -106,7 +120,8 @@ typedef struct {
                           valid until the next call on it                  */
 } paces_obs;
 
-/* Number of doubles per record of paces_series: 12 scalars
+/* Number of doubles per record of paces_series (one record per
+ * realization and step): 12 scalars
  * (t, norm2, energy, a_re, a_im, mass_step, mass_total, n_S, n_M, K,
  * E_min, E_max) followed by the N populations. */
 int32_t paces_record_doubles(const paces_model* m);
@@ -131,7 +146,8 @@ paces_status paces_unpack_keys(const paces_model* m, int64_t n,
 /* Create a sim from an initial state given as an uncompressed occupation
  * table (the paper's table A) plus coefficients coef[2*n] (re, im).
  * Duplicate states are an error.  The first step uses every input state
- * as M and grows it with k_init. */
+ * as M and grows it with k_init.  With R realizations every realization
+ * starts from this state (R*n rows). */
 paces_status paces_init_state(const paces_model* m, const paces_run_params* p,
                               int64_t n, const int32_t* exc,
                               const uint16_t* occ, const double* coef,
@@ -141,32 +157,39 @@ paces_status paces_free_sim(paces_sim* s);
 /* Advance n_steps time steps (asynchronous on the stream except where the
  * host needs a device count to size the next launch). */
 paces_status paces_step(paces_sim* s, int64_t n_steps, void* hip_stream);
-/* Latest observation; synchronises the stream. */
-paces_status paces_observe(paces_sim* s, paces_obs* out, void* hip_stream);
+/* Latest observation of one realization (0..R-1); synchronises the
+ * stream.  n_S and n_M of a record count the rows of that realization. */
+paces_status paces_observe(paces_sim* s, int32_t realization, paces_obs* out,
+                           void* hip_stream);
 /* Number of recorded steps. */
 paces_status paces_num_records(paces_sim* s, int64_t* n);
-/* Copy records first..first+n-1 to host out[n*paces_record_doubles];
- * synchronises. */
+/* Copy the records of steps first..first+n-1 to host
+ * out[n][R][paces_record_doubles]; synchronises. */
 paces_status paces_series(paces_sim* s, int64_t first, int64_t n,
                           double* out, void* hip_stream);
 
-/* Current state: *n rows; keys[n*W], amps[2n] (host, may be NULL to query
- * the size).  Synchronises. */
+/* Current state: *n rows; keys[n*W], amps[2n], real[n] the realization of
+ * each row (host; each may be NULL, all NULL to query the size).
+ * Synchronises. */
 paces_status paces_get_state(paces_sim* s, int64_t* n, uint64_t* keys,
-                             double* amps, void* hip_stream);
-/* Replace the current state (time t).  The next step selects from it with
- * theta and grows M with k. */
+                             double* amps, int32_t* real, void* hip_stream);
+/* Replace the current state (time t); real[n] gives each row's realization
+ * (NULL: realization 0).  A (realization, key) pair may appear once.  The
+ * next step selects from it with theta and grows M with k. */
 paces_status paces_set_state(paces_sim* s, int64_t n, const uint64_t* keys,
-                             const double* amps, double t, void* hip_stream);
+                             const double* amps, const int32_t* real, double t,
+                             void* hip_stream);
 
 typedef enum {
   PACES_SET_M = 0,        /* selected states of the last step            */
   PACES_SET_S = 1,        /* current set                                 */
   PACES_SET_FRONTIER = 2  /* states first reached in round r            */
 } paces_set;
-/* Keys of a set of the last step (keys NULL: size query).  Synchronises. */
+/* Keys (and realizations, real may be NULL) of a set of the last step
+ * (keys and real NULL: size query).  Synchronises. */
 paces_status paces_get_set(paces_sim* s, int32_t which, int32_t round,
-                           int64_t* n, uint64_t* keys, void* hip_stream);
+                           int64_t* n, uint64_t* keys, int32_t* real,
+                           void* hip_stream);
 /* phi of the last step (psi projected onto the new set), rows in the order
  * of paces_get_set(PACES_SET_S); amps[2*nS].  Synchronises. */
 paces_status paces_get_phi(paces_sim* s, double* amps, void* hip_stream);

@@ -49,7 +49,7 @@ class _Desc(C.Structure):
                 ("periodic", C.c_int32 * 3), ("n_modes", C.c_int32),
                 ("cutoff", C.c_int32 * 4), ("omega", C.c_double * 4),
                 ("g", C.c_double * 4), ("J", C.c_double * 3),
-                ("eps", C.POINTER(C.c_double))]
+                ("n_real", C.c_int32), ("eps", C.POINTER(C.c_double))]
 
 
 class _Run(C.Structure):
@@ -111,7 +111,11 @@ def _stream(stream):
 
 
 class Model:
-    """A Holstein lattice (parameters as a plain dict, see workloads)."""
+    """A Holstein lattice (parameters as a plain dict, see workloads).
+
+    params["n_real"] (default 1) realizations of the site energies share
+    one set; params["eps"] then holds n_real * N energies, realization-major.
+    """
 
     def __init__(self, params):
         d = _Desc()
@@ -125,7 +129,9 @@ class Model:
             d.cutoff[nu] = params["cutoff"][nu]
             d.omega[nu] = params["omega"][nu]
             d.g[nu] = params["g"][nu]
-        self._eps = np.ascontiguousarray(params["eps"], dtype=np.float64)
+        self.R = int(params.get("n_real", 1))
+        d.n_real = self.R
+        self._eps = np.ascontiguousarray(params["eps"], dtype=np.float64).reshape(-1)
         d.eps = _p(self._eps, C.c_double)
         h = C.c_void_p()
         _check(lib().paces_load_model(C.byref(d), C.byref(h)))
@@ -199,9 +205,10 @@ class Sim:
     def step(self, n=1, stream=None):
         _check(lib().paces_step(self.h, C.c_int64(n), _stream(stream)))
 
-    def observe(self, stream=None):
+    def observe(self, realization=0, stream=None):
         o = _Obs()
-        _check(lib().paces_observe(self.h, C.byref(o), _stream(stream)))
+        _check(lib().paces_observe(self.h, C.c_int32(realization), C.byref(o),
+                                   _stream(stream)))
         d = {f: getattr(o, f) for f in ["t", "norm2", "energy", "mass_step",
                                         "mass_total", "n_S", "n_M", "K",
                                         "E_min", "E_max"]}
@@ -215,17 +222,24 @@ class Sim:
         return n.value
 
     def series(self, first=0, n=None, stream=None):
-        """Observation records as an array [n, 12 + N]."""
+        """Observation records as an array [n, 12 + N], or [n, R, 12 + N]
+        for a batched model."""
         if n is None:
             n = self.num_records() - first
-        out = np.zeros(n * self.model.rec_doubles, dtype=np.float64)
+        R = self.model.R
+        out = np.zeros(n * R * self.model.rec_doubles, dtype=np.float64)
         _check(lib().paces_series(self.h, C.c_int64(first), C.c_int64(n),
                                   _p(out, C.c_double), _stream(stream)))
-        return out.reshape(n, self.model.rec_doubles)
+        if R == 1:
+            return out.reshape(n, self.model.rec_doubles)
+        return out.reshape(n, R, self.model.rec_doubles)
 
-    def observations(self, stream=None):
-        """Per-step observation dicts, same fields as the oracle's."""
+    def observations(self, realization=0, stream=None):
+        """Per-step observation dicts of one realization, same fields as
+        the oracle's."""
         rec = self.series(stream=stream)
+        if self.model.R > 1:
+            rec = rec[:, realization]
         out = []
         for r in rec:
             d = dict(zip(OBS_FIELDS, r[:12].tolist()))
@@ -235,37 +249,51 @@ class Sim:
 
     def size(self, stream=None):
         n = C.c_int64()
-        _check(lib().paces_get_state(self.h, C.byref(n), None, None,
+        _check(lib().paces_get_state(self.h, C.byref(n), None, None, None,
                                      _stream(stream)))
         return n.value
 
-    def state(self, stream=None):
-        """(keys [n, W] uint64 in row order, amplitudes [n] complex128)."""
+    def state(self, stream=None, with_real=False):
+        """(keys [n, W] uint64 in row order, amplitudes [n] complex128), plus
+        the realization of each row [n] int32 when with_real."""
         n = self.size(stream)
         keys = np.zeros(n * self.model.W, dtype=np.uint64)
         amps = np.zeros(2 * n, dtype=np.float64)
+        real = np.zeros(n, dtype=np.int32)
         nn = C.c_int64()
         _check(lib().paces_get_state(self.h, C.byref(nn), _p(keys, C.c_uint64),
-                                     _p(amps, C.c_double), _stream(stream)))
-        return keys.reshape(n, self.model.W), amps.view(np.complex128)
+                                     _p(amps, C.c_double), _p(real, C.c_int32),
+                                     _stream(stream)))
+        keys = keys.reshape(n, self.model.W)
+        if with_real:
+            return keys, amps.view(np.complex128), real
+        return keys, amps.view(np.complex128)
 
-    def set_state(self, keys, amps, t=0.0, stream=None):
+    def set_state(self, keys, amps, t=0.0, stream=None, real=None):
         keys = np.ascontiguousarray(keys, dtype=np.uint64).reshape(-1)
         amps = np.ascontiguousarray(np.asarray(amps, dtype=np.complex128)).view(np.float64)
         n = len(keys) // self.model.W
+        rp = None
+        if real is not None:
+            real = np.ascontiguousarray(real, dtype=np.int32)
+            rp = _p(real, C.c_int32)
         _check(lib().paces_set_state(self.h, C.c_int64(n), _p(keys, C.c_uint64),
-                                     _p(amps, C.c_double), C.c_double(t),
+                                     _p(amps, C.c_double), rp, C.c_double(t),
                                      _stream(stream)))
 
-    def get_set(self, which, rnd=0, stream=None):
+    def get_set(self, which, rnd=0, stream=None, with_real=False):
         n = C.c_int64()
         _check(lib().paces_get_set(self.h, C.c_int32(which), C.c_int32(rnd),
-                                   C.byref(n), None, _stream(stream)))
+                                   C.byref(n), None, None, _stream(stream)))
         keys = np.zeros(n.value * self.model.W, dtype=np.uint64)
+        real = np.zeros(n.value, dtype=np.int32)
         _check(lib().paces_get_set(self.h, C.c_int32(which), C.c_int32(rnd),
                                    C.byref(n), _p(keys, C.c_uint64),
-                                   _stream(stream)))
-        return keys.reshape(n.value, self.model.W)
+                                   _p(real, C.c_int32), _stream(stream)))
+        keys = keys.reshape(n.value, self.model.W)
+        if with_real:
+            return keys, real
+        return keys
 
     def phi(self, stream=None):
         n = self.size(stream)

@@ -35,6 +35,7 @@ enum : int {
 // Model constants passed by value to every kernel.
 struct DevModel {
   int N, V, ndim, D, W, B, bj, P;
+  int R, br;            // disorder realizations, bits of the realization id
   int bnu[kMaxV];       // bits per mode field
   int cut[kMaxV];       // occupation cutoffs
   int sub[kMaxV];       // offset of mode nu inside one site's bit group
@@ -43,36 +44,37 @@ struct DevModel {
   uint64_t mul[kMaxW];  // odd multipliers of the key hash
   const int32_t* nbr;   // [N][2*ndim] hop targets, -1 if absent
   const double* gsq;    // [V][kGsqStride]: g_nu * sqrt(n)
-  const double* eps;    // [N] site energies
+  const double* eps;    // [R][N] site energies
   uint32_t hop_mask;    // bit a set iff J[a] != 0
   uint32_t eph_mask;    // bit nu set iff g[nu] != 0
 };
 
 // Per-row payload, one 64-bit word: exciton site j in bits 0..11, the
 // occupation of each mode at the exciton site in 8-bit fields from bit 12,
-// and, for at most two modes, the total occupation T_nu of each mode in
-// 16-bit fields from bit 28.  With more modes the totals live in a second
-// word per row (16 bits per mode).  The diagonal eps_j + sum_nu omega_nu T_nu
-// is recomputed from these integers wherever it is needed.
-constexpr int kPaySiteBits = 12;
+// for at most two modes the total occupation T_nu of each mode in 14-bit
+// fields from bit 28, and the realization id in bits 56..63.  With more
+// modes the totals live in a second word per row (16 bits per mode).  The
+// diagonal eps_j + sum_nu omega_nu T_nu is recomputed from these integers
+// wherever it is needed.
 __device__ __forceinline__ int pay_site(uint64_t p) { return int(p & 0xFFFu); }
 __device__ __forceinline__ int pay_occ(uint64_t p, int nu) {
   return int((p >> (12 + 8 * nu)) & 0xFFu);
 }
+__device__ __forceinline__ int pay_real(uint64_t p) { return int(p >> 56); }
 __device__ __forceinline__ int tot_of(uint64_t t, int nu) {
   return int((t >> (16 * nu)) & 0xFFFFu);
 }
 // Total occupation of mode nu: from the payload (V <= 2) or the totals word.
 __device__ __forceinline__ int row_total(int V, uint64_t pay, uint64_t tot,
                                          int nu) {
-  return V <= 2 ? int((pay >> (28 + 16 * nu)) & 0xFFFFu) : tot_of(tot, nu);
+  return V <= 2 ? int((pay >> (28 + 14 * nu)) & 0x3FFFu) : tot_of(tot, nu);
 }
 __device__ __forceinline__ uint64_t make_pay(int V, int j, const int* nj,
-                                             const int* T) {
-  uint64_t p = uint64_t(j);
+                                             const int* T, int r) {
+  uint64_t p = uint64_t(j) | (uint64_t(r) << 56);
   for (int nu = 0; nu < V; ++nu) p |= uint64_t(nj[nu]) << (12 + 8 * nu);
   if (V <= 2)
-    for (int nu = 0; nu < V; ++nu) p |= uint64_t(T[nu]) << (28 + 16 * nu);
+    for (int nu = 0; nu < V; ++nu) p |= uint64_t(T[nu]) << (28 + 14 * nu);
   return p;
 }
 __device__ __forceinline__ uint64_t make_tot(int V, const int* T) {
@@ -146,6 +148,13 @@ __device__ __forceinline__ bool key_eq(const uint64_t (&a)[W],
 #pragma unroll
   for (int q = 0; q < W; ++q) eq &= (a[q] == b[q]);
   return eq;
+}
+
+// Realization id of a key: the br bits above the B bits of the state.
+template <int W>
+__device__ __forceinline__ int key_real(const DevModel& m,
+                                        const uint64_t (&k)[W]) {
+  return m.br ? int(get_field<W>(k, m.B, m.br)) : 0;
 }
 
 // 64-bit hash: a multiply-add over the words followed by the murmur3
@@ -232,7 +241,7 @@ __device__ __forceinline__ void slot_row_info(const DevModel& m,
     nj[nu] += delta;
     T[nu] += delta;
   }
-  pay_out = make_pay(m.V, j, nj, T);
+  pay_out = make_pay(m.V, j, nj, T, pay_real(pay));
   tot_out = make_tot(m.V, T);
 }
 
@@ -241,7 +250,7 @@ __device__ __forceinline__ void slot_row_info(const DevModel& m,
 // term by term.
 __device__ __forceinline__ double row_diag(const DevModel& m, uint64_t pay,
                                            uint64_t tot) {
-  double d = m.eps[pay_site(pay)];
+  double d = m.eps[pay_real(pay) * m.N + pay_site(pay)];
   for (int nu = 0; nu < m.V; ++nu)
     d = __dadd_rn(d, __dmul_rn(m.omega[nu], double(row_total(m.V, pay, tot, nu))));
   return d;

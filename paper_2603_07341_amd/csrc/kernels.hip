@@ -149,11 +149,15 @@ __global__ void __launch_bounds__(kBlock)
   for (int64_t i = gtid(); i < n; i += gstride()) p[i] = v;
 }
 
-__global__ void k_begin_step(StepCtl* ctl, int* err) {
-  *err = 0;
-  ctl->fstart[0] = 0;
-  ctl->nM = 0;
-  ctl->n_new = 0;
+__global__ void k_begin_step(StepCtl* ctl, int* err, uint32_t* cnt, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) cnt[i] = 0u;
+  if (threadIdx.x == 0) {
+    *err = 0;
+    ctl->fstart[0] = 0;
+    ctl->nM = 0;
+    ctl->n_new = 0;
+    ctl->kmax = 0;
+  }
 }
 
 // ---- scan over a device-sized array ----------------------------------------
@@ -296,9 +300,18 @@ __global__ void __launch_bounds__(kBlock)
         s += int(get_field<W>(k, field_off(m, i, nu), m.bnu[nu]));
       T[nu] = s;
     }
-    pay[r] = make_pay(m.V, j, nj, T);
+    pay[r] = make_pay(m.V, j, nj, T, key_real<W>(m, k));
     tot[r] = make_tot(m.V, T);
   }
+}
+
+// Per-realization integer counters (deterministic: integer sums commute):
+// LDS bins per block, one global add per nonzero bin.
+__device__ __forceinline__ void count_flush(int R, uint32_t* lds,
+                                            uint32_t* global) {
+  __syncthreads();
+  for (int r = threadIdx.x; r < R; r += blockDim.x)
+    if (lds[r]) atomicAdd(&global[r], lds[r]);
 }
 
 // ---- insert rows into the cleared table -------------------------------------
@@ -310,8 +323,11 @@ __global__ void __launch_bounds__(kBlock)
                   const uint64_t* tot_o, const uint32_t* midx,
                   const uint32_t* nptr, int64_t n_fixed, uint64_t* keys_n,
                   uint64_t* pay_n, uint64_t* tot_n, uint64_t* table,
-                  uint64_t mask, int* err) {
+                  uint64_t mask, uint32_t* cnt_r, int* err) {
+  __shared__ uint32_t bins[kMaxReal];
   if (*err) return;
+  for (int r = threadIdx.x; r < m.R; r += blockDim.x) bins[r] = 0;
+  __syncthreads();
   const int64_t nM = nptr ? int64_t(*nptr) : n_fixed;
   for (int64_t i = gtid(); i < nM; i += gstride()) {
     uint64_t k[W];
@@ -321,6 +337,7 @@ __global__ void __launch_bounds__(kBlock)
       store_key<W>(keys_n, i, k);
       pay_n[i] = pay_o[r];
       tot_n[i] = tot_o[r];
+      if (cnt_r) atomicAdd(&bins[pay_real(pay_o[r])], 1u);
     } else {
       load_key<W>(keys_n, i, k);
     }
@@ -339,6 +356,7 @@ __global__ void __launch_bounds__(kBlock)
     }
     if (!done) atomicOr(err, kErrTableFull);
   }
+  if (cnt_r) count_flush(m.R, bins, cnt_r);
 }
 
 // ---- expansion round --------------------------------------------------------
@@ -560,7 +578,13 @@ __global__ void __launch_bounds__(kBlock)
                const StepCtl* ctl, const uint64_t* table, uint64_t mask,
                const uint64_t* keys_n, Amp* phi, double* mass_part,
                const int* err) {
+  __shared__ double bins[kMaxReal];
   if (*err) return;
+  const int R = m.R;
+  if (R > 1) {
+    for (int r = threadIdx.x; r < R; r += blockDim.x) bins[r] = 0.0;
+    __syncthreads();
+  }
   const int64_t n_old = ctl->n_old;
   double lost = 0;
   for (int64_t i = gtid(); i < n_old; i += gstride()) {
@@ -570,19 +594,48 @@ __global__ void __launch_bounds__(kBlock)
     const Amp v = psi_o[i];
     if (r >= 0)
       phi[r] = v;
+    else if (R > 1)
+      atomicAdd(&bins[key_real<W>(m, k)], weight(v));
     else
       lost += weight(v);
   }
-  lost = block_sum(lost);
-  if (threadIdx.x == 0) mass_part[blockIdx.x] = lost;
+  if (R > 1) {
+    __syncthreads();
+    for (int r = threadIdx.x; r < R; r += blockDim.x)
+      mass_part[int64_t(blockIdx.x) * R + r] = bins[r];
+  } else {
+    lost = block_sum(lost);
+    if (threadIdx.x == 0) mass_part[blockIdx.x] = lost;
+  }
 }
 
 // ---- Gershgorin bounds and Chebyshev coefficients ---------------------------
+// Order-preserving map of doubles to signed 64-bit integers, so that
+// integer min / max (exact, order independent) give the double min / max.
+__device__ __forceinline__ long long ord_of(double x) {
+  const long long b = __double_as_longlong(x);
+  return b >= 0 ? b : (b ^ 0x7FFFFFFFFFFFFFFFll);
+}
+__device__ __forceinline__ double dbl_of(long long o) {
+  return __longlong_as_double(o >= 0 ? o : (o ^ 0x7FFFFFFFFFFFFFFFll));
+}
+
+// Gershgorin interval per realization: rows stride over a fixed grid; per
+// block the (lo, hi) of each realization go to part[block][r][2].
 __global__ void __launch_bounds__(kBlock)
     k_bounds(DevModel m, const uint64_t* pay, const uint64_t* tot,
              const int32_t* col, int64_t cap, const StepCtl* ctl,
              double* part, const int* err) {
+  __shared__ long long blo[kMaxReal], bhi[kMaxReal];
   if (*err) return;
+  const int R = m.R;
+  if (R > 1) {
+    for (int r = threadIdx.x; r < R; r += blockDim.x) {
+      blo[r] = ord_of(INFINITY);
+      bhi[r] = ord_of(-INFINITY);
+    }
+    __syncthreads();
+  }
   const int64_t n = ctl->n_new;
   double lo = INFINITY, hi = -INFINITY;
   for (int64_t r = gtid(); r < n; r += gstride()) {
@@ -591,14 +644,27 @@ __global__ void __launch_bounds__(kBlock)
     for (int s = 0; s < m.D; ++s)
       if (col[int64_t(s) * cap + r] >= 0) rad += fabs(slot_value(m, p, s));
     const double d = row_diag(m, p, m.V > 2 ? tot[r] : 0);
-    lo = fmin(lo, d - rad);
-    hi = fmax(hi, d + rad);
+    if (R > 1) {
+      atomicMin(&blo[pay_real(p)], ord_of(d - rad));
+      atomicMax(&bhi[pay_real(p)], ord_of(d + rad));
+    } else {
+      lo = fmin(lo, d - rad);
+      hi = fmax(hi, d + rad);
+    }
   }
-  lo = block_min(lo);
-  hi = block_max(hi);
-  if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = lo;
-    part[2 * blockIdx.x + 1] = hi;
+  if (R > 1) {
+    __syncthreads();
+    for (int r = threadIdx.x; r < R; r += blockDim.x) {
+      part[(int64_t(blockIdx.x) * R + r) * 2] = dbl_of(blo[r]);
+      part[(int64_t(blockIdx.x) * R + r) * 2 + 1] = dbl_of(bhi[r]);
+    }
+  } else {
+    lo = block_min(lo);
+    hi = block_max(hi);
+    if (threadIdx.x == 0) {
+      part[2 * blockIdx.x] = lo;
+      part[2 * blockIdx.x + 1] = hi;
+    }
   }
 }
 
@@ -642,15 +708,20 @@ __device__ void bessel_miller(double x, int kmax, double* out) {
   for (int k = 0; k <= kmax; ++k) out[k] /= norm;
 }
 
+// One block per realization: fold the per-block bounds, pad them, and
+// compute the Chebyshev coefficients and the number of terms K_r.
 __global__ void __launch_bounds__(kBlock)
-    k_coef(const double* part, int nparts, double dt, double tol, int k_max,
-           int launched, ChebCoef* cc, int* err) {
+    k_coef(const double* part, int nparts, int R, double dt, double tol,
+           int k_max, int launched, ChebCoef* cc_all, StepCtl* ctl,
+           int* err) {
   __shared__ double J[kMaxTerms + 1];
   if (*err) return;
+  const int rr = blockIdx.x;
+  ChebCoef* cc = cc_all + rr;
   double lo = INFINITY, hi = -INFINITY;
   for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
-    lo = fmin(lo, part[2 * i]);
-    hi = fmax(hi, part[2 * i + 1]);
+    lo = fmin(lo, part[(int64_t(i) * R + rr) * 2]);
+    hi = fmax(hi, part[(int64_t(i) * R + rr) * 2 + 1]);
   }
   lo = block_min(lo);
   hi = block_max(hi);
@@ -685,6 +756,7 @@ __global__ void __launch_bounds__(kBlock)
       atomicOr(err, kErrTerms);
     else if (K > launched)
       atomicOr(err, kErrNeedTerms);
+    atomicMax(&ctl->kmax, uint32_t(K));
     cc->emin = emin;
     cc->emax = emax;
     cc->a = a;
@@ -816,34 +888,129 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// Population bins in LDS: for up to kPrivBins sites every lane of a wave
-// owns a column (bin j, lane l at j*64 + l), so the four waves of a block
-// meet on an address at most four at a time; larger lattices share one bin
-// per site.
-constexpr int kPrivBins = 128;
-__device__ __forceinline__ void pop_add(double* lds, int N, int j, double w) {
-  if (N <= kPrivBins)
-    atomicAdd(&lds[j * 64 + (threadIdx.x & 63)], w);
-  else
-    atomicAdd(&lds[j], w);
+// Batched form of the Clenshaw launch: rows of different disorder
+// realizations carry their own spectral interval, coefficients and term
+// count K_r (cc_all[r]); each row takes its role from its own K_r, so a
+// realization's rows do exactly the arithmetic of a single-realization run
+// (neighbours of a row always belong to the same realization).  Launches
+// beyond a realization's K_r leave its rows untouched.  The energy term
+// <phi|H|phi> is left per row in e_row for a segmented reduction.
+template <typename R, int ND, int NV>
+__global__ void __launch_bounds__(kBlock)
+    k_cheb_batch(DevModel m, int kk, int want_energy,
+                 const StepCtl* __restrict__ ctl, const int* __restrict__ err,
+                 const int32_t* __restrict__ col, int64_t cap,
+                 const uint64_t* __restrict__ pay,
+                 const uint64_t* __restrict__ tot,
+                 const ChebCoef* __restrict__ cc_all,
+                 const typename VecT<R>::T* __restrict__ phi,
+                 typename VecT<R>::T* b0, typename VecT<R>::T* b1,
+                 double* e_row) {
+  using Amp = typename VecT<R>::T;
+  constexpr int D = 2 * ND + 2 * NV;
+  if (*err) return;
+  const int64_t n = ctl->n_new;
+  R jv[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < ND; ++a) jv[a] = R(m.J[a]);
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    const uint64_t p = pay[i];
+    const ChebCoef* cc = cc_all + pay_real(p);
+    const int K = cc->K;
+    if (kk > K - 2 && !(K == 1 && kk == 0)) continue;
+    const bool first = (kk == K - 2) || K == 1;
+    const bool fin = kk == 0;
+    const Amp* in = first ? phi : (((kk + 1) & 1) ? b1 : b0);
+    const Amp* prev = first ? nullptr : (kk == K - 3 ? phi : ((kk & 1) ? b1 : b0));
+    Amp* out = (kk & 1) ? b1 : b0;
+    const R alpha = R(cc->alpha), beta = R(cc->beta);
+    const R ckr = R(cc->c[kk][0]), cki = R(cc->c[kk][1]);
+    const double fac = fin ? 1.0 : 2.0;
+    R sir = R(fac), sii = 0;
+    if (first) {
+      sir = K == 1 ? R(0) : R(fac * cc->c[K - 1][0]);
+      sii = K == 1 ? R(0) : R(fac * cc->c[K - 1][1]);
+    }
+    R spr = 1, spi = 0;
+    if (kk == K - 3) {
+      spr = R(cc->c[K - 1][0]);
+      spi = R(cc->c[K - 1][1]);
+    }
+    const R phr = fin ? R(cc->phase[0]) : R(1), phim = fin ? R(cc->phase[1]) : R(0);
+    const Amp xi = in[i];
+    const R d = R(row_diag(m, p, NV > 2 ? tot[i] : 0));
+    R hr = d * xi.x, hi = d * xi.y;
+    R gv[NV][2];
+#pragma unroll
+    for (int nu = 0; nu < NV; ++nu) {
+      const int occ = pay_occ(p, nu);
+      gv[nu][0] = R(m.gsq[nu * kGsqStride + occ]);
+      gv[nu][1] = R(m.gsq[nu * kGsqStride + occ + 1]);
+    }
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+      const int32_t c = col[int64_t(s) * cap + i];
+      if (c >= 0) {
+        const R v = s < 2 * ND ? jv[s >> 1] : gv[(s - 2 * ND) >> 1][(s - 2 * ND) & 1];
+        const Amp xj = in[c];
+        hr += v * xj.x;
+        hi += v * xj.y;
+      }
+    }
+    if (first && want_energy)
+      e_row[i] = double(xi.x) * double(hr) + double(xi.y) * double(hi);
+    const R tr = alpha * hr + beta * xi.x, ti = alpha * hi + beta * xi.y;
+    R yr = sir * tr - sii * ti, yi = sir * ti + sii * tr;
+    const Amp f = phi[i];
+    yr += ckr * f.x - cki * f.y;
+    yi += ckr * f.y + cki * f.x;
+    if (prev) {
+      const Amp q = prev[i];
+      yr -= spr * q.x - spi * q.y;
+      yi -= spr * q.y + spi * q.x;
+    }
+    Amp o;
+    o.x = phr * yr - phim * yi;
+    o.y = phr * yi + phim * yr;
+    out[i] = o;
+  }
 }
 
-// Norm and exciton populations of psi as per-block partials (populations
-// binned in LDS).  Rows are visited in the select kernels' tile layout, so
-// the same pass also counts, per tile, the rows the next step will select.
+// Population bins in LDS: with one realization and up to kPrivBins sites
+// every lane of a wave owns a column (bin j, lane l at j*64 + l), so the
+// four waves of a block meet on an address at most four at a time; other
+// shapes share one bin per (realization, site).
+constexpr int kPrivBins = 120;  // N * 64 + 3 doubles fit in 64 KiB
+
+// Norm, exciton populations, row counts and (batched) energy of psi per
+// realization as per-block partials.  Rows are visited in the select
+// kernels' tile layout, so the same pass also counts, per tile, the rows
+// the next step will select.
 template <typename R>
 __global__ void __launch_bounds__(kBlock)
-    k_pop_norm(int N, double th2, const StepCtl* ctl,
+    k_pop_norm(int N, int Rn, double th2, const StepCtl* ctl,
                const typename VecT<R>::T* psi, const uint64_t* pay,
-               double* n2_part, double* pop_part, uint32_t* sel_bsum,
+               const double* e_row, double* n2_part, double* en_part,
+               double* pop_part, uint32_t* sel_bsum, uint32_t* cnt_s,
                const int* err) {
-  extern __shared__ double pop_lds[];
+  extern __shared__ double lds[];
   if (*err) return;
   const int64_t n = ctl->n_new, ntiles = cdiv(n, kTile);
-  const int nbins = N <= kPrivBins ? N * 64 : N;
-  for (int j = threadIdx.x; j < nbins; j += blockDim.x) pop_lds[j] = 0.0;
+  const bool priv = Rn == 1 && N <= kPrivBins;
+  const int npop = priv ? N * 64 : Rn * N;
+  double* pop_lds = lds;
+  double* n2_lds = lds + npop;          // Rn (batched only)
+  double* en_lds = n2_lds + Rn;         // Rn
+  uint32_t* cnt_lds = reinterpret_cast<uint32_t*>(en_lds + Rn);  // Rn
+  for (int j = threadIdx.x; j < npop; j += blockDim.x) pop_lds[j] = 0.0;
+  for (int j = threadIdx.x; j < Rn; j += blockDim.x) {
+    n2_lds[j] = 0.0;
+    en_lds[j] = 0.0;
+    cnt_lds[j] = 0u;
+  }
   __syncthreads();
   double n2 = 0;
+  uint32_t rows = 0;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     uint32_t keep = 0;
 #pragma unroll
@@ -851,30 +1018,59 @@ __global__ void __launch_bounds__(kBlock)
       const int64_t e = t * kTile + q * kBlock + threadIdx.x;
       if (e < n) {
         const double w = weight(psi[e]);
-        n2 += w;
+        const uint64_t p = pay[e];
         keep += w >= th2 ? 1u : 0u;
-        pop_add(pop_lds, N, pay_site(pay[e]), w);
+        if (Rn == 1) {
+          n2 += w;
+          ++rows;
+          if (priv)
+            atomicAdd(&pop_lds[pay_site(p) * 64 + (threadIdx.x & 63)], w);
+          else
+            atomicAdd(&pop_lds[pay_site(p)], w);
+        } else {
+          const int r = pay_real(p);
+          atomicAdd(&n2_lds[r], w);
+          atomicAdd(&cnt_lds[r], 1u);
+          atomicAdd(&pop_lds[r * N + pay_site(p)], w);
+          if (e_row) atomicAdd(&en_lds[r], e_row[e]);
+        }
       }
     }
     uint32_t tot;
     block_excl_scan(keep, &tot);
     if (threadIdx.x == 0) sel_bsum[t] = tot;
   }
-  n2 = block_sum(n2);
-  if (threadIdx.x == 0) n2_part[blockIdx.x] = n2;
-  __syncthreads();
-  for (int j = threadIdx.x; j < N; j += blockDim.x) {
-    double v = 0;
-    if (N <= kPrivBins)
-      for (int l = 0; l < 64; ++l) v += pop_lds[j * 64 + l];
-    else
-      v = pop_lds[j];
-    pop_part[int64_t(blockIdx.x) * N + j] = v;
+  if (Rn == 1) {
+    n2 = block_sum(n2);
+    uint32_t all;
+    block_excl_scan(rows, &all);
+    if (threadIdx.x == 0) {
+      n2_part[blockIdx.x] = n2;
+      if (all) atomicAdd(&cnt_s[0], all);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+      double v = 0;
+      if (priv)
+        for (int l = 0; l < 64; ++l) v += pop_lds[j * 64 + l];
+      else
+        v = pop_lds[j];
+      pop_part[int64_t(blockIdx.x) * N + j] = v;
+    }
+  } else {
+    __syncthreads();
+    for (int r = threadIdx.x; r < Rn; r += blockDim.x) {
+      n2_part[int64_t(blockIdx.x) * Rn + r] = n2_lds[r];
+      en_part[int64_t(blockIdx.x) * Rn + r] = en_lds[r];
+      if (cnt_lds[r]) atomicAdd(&cnt_s[r], cnt_lds[r]);
+    }
+    for (int j = threadIdx.x; j < Rn * N; j += blockDim.x)
+      pop_part[int64_t(blockIdx.x) * Rn * N + j] = pop_lds[j];
   }
 }
 
 // Second level of a deterministic reduction: block b folds partials
-// b, b + gridDim.x, ... (sum, or min of even / max of odd entries).
+// b, b + gridDim.x, ... into out[b].
 __global__ void __launch_bounds__(kBlock)
     k_fold_sum(const double* in, int n, double* out, const int* err) {
   if (*err) return;
@@ -885,24 +1081,9 @@ __global__ void __launch_bounds__(kBlock)
   s = block_sum(s);
   if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
-__global__ void __launch_bounds__(kBlock)
-    k_fold_minmax(const double* in, int n, double* out, const int* err) {
-  if (*err) return;
-  double lo = INFINITY, hi = -INFINITY;
-  for (int i = blockIdx.x + gridDim.x * threadIdx.x; i < n;
-       i += gridDim.x * blockDim.x) {
-    lo = fmin(lo, in[2 * i]);
-    hi = fmax(hi, in[2 * i + 1]);
-  }
-  lo = block_min(lo);
-  hi = block_max(hi);
-  if (threadIdx.x == 0) {
-    out[2 * blockIdx.x] = lo;
-    out[2 * blockIdx.x + 1] = hi;
-  }
-}
 
 // ---- autocorrelation <psi0|psi(t)> ------------------------------------------
+// Block r: the n0 initial states of realization r.
 template <int W, typename Amp>
 __global__ void __launch_bounds__(kBlock)
     k_autocorr(DevModel m, const uint64_t* keys0, const double* amps0,
@@ -910,8 +1091,9 @@ __global__ void __launch_bounds__(kBlock)
                const uint64_t* keys, const Amp* psi, double* out2,
                const int* err) {
   if (*err) return;
+  const int64_t base = int64_t(blockIdx.x) * n0;
   double re = 0, im = 0;
-  for (int64_t i = threadIdx.x; i < n0; i += blockDim.x) {
+  for (int64_t i = base + threadIdx.x; i < base + n0; i += blockDim.x) {
     uint64_t k[W];
     load_key<W>(keys0, i, k);
     const int64_t r = table_find<W>(table, mask, keys, k, key_hash<W>(m, k));
@@ -924,36 +1106,47 @@ __global__ void __launch_bounds__(kBlock)
   re = block_sum(re);
   im = block_sum(im);
   if (threadIdx.x == 0) {
-    out2[0] = re;
-    out2[1] = im;
+    out2[2 * blockIdx.x] = re;
+    out2[2 * blockIdx.x + 1] = im;
   }
 }
 
 // ---- observation record -----------------------------------------------------
-// Blocks 0..N-1 reduce one population each, block N the scalars; each block
-// sums the per-block partials with a fixed lane mapping.
+// Block (x, r): x < N reduces population (r, x), x = N the scalars of
+// realization r; each folds the per-block partials with a fixed lane
+// mapping.  Records of one step are stored realization after realization.
 __global__ void __launch_bounds__(kBlock)
-    k_obs_final(int N, int want_energy, double dt, int n_mass, int n_e,
+    k_obs_final(int N, int Rn, int want_energy, double dt, int n_mass, int n_e,
                 int n_pop, const double* mass_part, const double* n2_part,
-                const double* e_part, const double* pop_part, const double* a2,
-                const ChebCoef* cc, const StepCtl* ctl, double* ring,
-                int rec_doubles, int64_t ring_cap, int* err) {
+                const double* e_part, const double* en_part,
+                const double* pop_part, const double* a2, const ChebCoef* cc,
+                const StepCtl* ctl, const uint32_t* cnt,
+                const double* mass_tot, double* ring, int rec_doubles,
+                int64_t ring_cap, int* err) {
   if (*err) return;
-  if (int64_t(ctl->nrec) >= ring_cap) return;  // the host keeps room
-  double* rec = ring + int64_t(ctl->nrec) * rec_doubles;
+  if (int64_t(ctl->nrec) + 1 > ring_cap) return;  // the host keeps room
+  const int r = blockIdx.y;
+  double* rec = ring + (int64_t(ctl->nrec) * Rn + r) * rec_doubles;
   if (int(blockIdx.x) < N) {
     double s = 0;
     for (int b = threadIdx.x; b < n_pop; b += blockDim.x)
-      s += pop_part[int64_t(b) * N + blockIdx.x];
+      s += pop_part[(int64_t(b) * Rn + r) * N + blockIdx.x];
     s = block_sum(s);
     if (threadIdx.x == 0) rec[kObsFields + blockIdx.x] = s;
     return;
   }
   double ms = 0, n2 = 0, en = 0;
-  for (int i = threadIdx.x; i < n_mass; i += blockDim.x) ms += mass_part[i];
-  for (int i = threadIdx.x; i < n_pop; i += blockDim.x) n2 += n2_part[i];
-  if (want_energy)
-    for (int i = threadIdx.x; i < n_e; i += blockDim.x) en += e_part[i];
+  for (int i = threadIdx.x; i < n_mass; i += blockDim.x)
+    ms += mass_part[int64_t(i) * Rn + r];
+  for (int i = threadIdx.x; i < n_pop; i += blockDim.x)
+    n2 += n2_part[int64_t(i) * Rn + r];
+  if (want_energy) {
+    if (Rn == 1)
+      for (int i = threadIdx.x; i < n_e; i += blockDim.x) en += e_part[i];
+    else
+      for (int i = threadIdx.x; i < n_pop; i += blockDim.x)
+        en += en_part[int64_t(i) * Rn + r];
+  }
   ms = block_sum(ms);
   n2 = block_sum(n2);
   en = block_sum(en);
@@ -961,28 +1154,33 @@ __global__ void __launch_bounds__(kBlock)
     rec[0] = ctl->t + dt;
     rec[1] = n2;
     rec[2] = want_energy ? en : NAN;
-    rec[3] = a2[0];
-    rec[4] = a2[1];
+    rec[3] = a2[2 * r];
+    rec[4] = a2[2 * r + 1];
     rec[5] = ms;
-    rec[6] = ctl->mass_total + ms;
-    rec[7] = double(ctl->n_new);
-    rec[8] = double(ctl->nM);
-    rec[9] = double(cc->K);
-    rec[10] = cc->emin;
-    rec[11] = cc->emax;
+    rec[6] = mass_tot[r] + ms;
+    rec[7] = double(cnt[Rn + r]);
+    rec[8] = double(cnt[r]);
+    rec[9] = double(cc[r].K);
+    rec[10] = cc[r].emin;
+    rec[11] = cc[r].emax;
     if (!isfinite(n2)) atomicOr(err, kErrNonFinite);
   }
 }
 
-// Commit the step on the device.
-__global__ void k_end_step(StepCtl* ctl, const double* ring, int rec_doubles,
-                           const int* err) {
+// Commit the step on the device: time, cumulative discarded weight per
+// realization, record count and the row count of the current set.
+__global__ void k_end_step(StepCtl* ctl, int Rn, const double* ring,
+                           int rec_doubles, double* mass_tot, const int* err) {
   if (*err) return;
-  const double* rec = ring + int64_t(ctl->nrec) * rec_doubles;
+  const double* rec = ring + int64_t(ctl->nrec) * Rn * rec_doubles;
+  for (int r = 0; r < Rn; ++r) mass_tot[r] = rec[int64_t(r) * rec_doubles + 6];
   ctl->t = rec[0];
-  ctl->mass_total = rec[6];
   ctl->n_old = ctl->n_new;
   ctl->nrec += 1;
+}
+
+__global__ void k_clear_u32(uint32_t* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
 // ---- precision conversion ---------------------------------------------------
@@ -1048,8 +1246,9 @@ void fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
   k_fill_u64<<<grid_for(n), kBlock, 0, s>>>(p, n, v);
 }
 
-void begin_step(StepCtl* ctl, int* err, hipStream_t s) {
-  k_begin_step<<<1, 1, 0, s>>>(ctl, err);
+void begin_step(StepCtl* ctl, int* err, uint32_t* cnt, int R,
+                hipStream_t s) {
+  k_begin_step<<<1, kBlock, 0, s>>>(ctl, err, cnt, 2 * R);
 }
 
 void select_rows(int prec, const void* psi, double th2, bool select_all,
@@ -1076,11 +1275,11 @@ void select_rows(int prec, const void* psi, double th2, bool select_all,
 
 void insert_rows(const DevModel& m, int Wi, const Side& o, const Side& n,
                  const uint32_t* midx, const StepCtl* ctl, uint64_t* table,
-                 uint64_t mask, int* err, hipStream_t s) {
+                 uint64_t mask, uint32_t* cnt_m, int* err, hipStream_t s) {
   const int g = grid_for(int64_t(mask + 1) / 2);
   PACES_DISPATCH_W(Wi, k_insert_rows<WW><<<g, kBlock, 0, s>>>(
                            m, o.keys, o.pay, o.tot, midx, &ctl->nM, 0, n.keys,
-                           n.pay, n.tot, table, mask, err));
+                           n.pay, n.tot, table, mask, cnt_m, err));
 }
 
 void rehash_rows(const DevModel& m, int Wi, const Side& n, uint32_t* midx,
@@ -1090,7 +1289,8 @@ void rehash_rows(const DevModel& m, int Wi, const Side& n, uint32_t* midx,
   if (rows <= 0) return;
   PACES_DISPATCH_W(Wi, k_insert_rows<WW><<<grid_for(rows), kBlock, 0, s>>>(
                            m, nullptr, nullptr, nullptr, nullptr, nullptr,
-                           rows, n.keys, n.pay, n.tot, table, mask, err));
+                           rows, n.keys, n.pay, n.tot, table, mask, nullptr,
+                           err));
 }
 
 void expand_round(const DevModel& m, int Wi, int prec, const Side& n, int r,
@@ -1141,7 +1341,7 @@ int transfer(const DevModel& m, int Wi, int prec, const Side& o,
              const void* psi_o, int64_t n_old, const StepCtl* ctl,
              const uint64_t* table, uint64_t mask, const uint64_t* keys_n,
              void* phi, double* mass_part, int* err, hipStream_t s) {
-  const int g = grid_for(n_old);
+  const int g = m.R > 1 ? std::min(grid_for(n_old), kPartBlocks) : grid_for(n_old);
   if (prec == 64) {
     PACES_DISPATCH_W(Wi, k_transfer<WW, double2><<<g, kBlock, 0, s>>>(
                              m, o.keys, (const double2*)psi_o, ctl, table, mask,
@@ -1155,14 +1355,13 @@ int transfer(const DevModel& m, int Wi, int prec, const Side& o,
 }
 
 void bounds_and_coef(const DevModel& m, const Side& n, const int32_t* col,
-                     int64_t cap, int64_t est, const StepCtl* ctl, double dt,
+                     int64_t cap, int64_t est, StepCtl* ctl, double dt,
                      double tol, int k_max, int launched, double* part,
-                     double* folded, ChebCoef* cc, int* err, hipStream_t s) {
-  const int g = grid_for(est);
+                     ChebCoef* cc, int* err, hipStream_t s) {
+  const int g = m.R > 1 ? std::min(grid_for(est), kPartBlocks) : grid_for(est);
   k_bounds<<<g, kBlock, 0, s>>>(m, n.pay, n.tot, col, cap, ctl, part, err);
-  const int f = std::min(g, kFold);
-  k_fold_minmax<<<f, kBlock, 0, s>>>(part, g, folded, err);
-  k_coef<<<1, kBlock, 0, s>>>(folded, f, dt, tol, k_max, launched, cc, err);
+  k_coef<<<m.R, kBlock, 0, s>>>(part, g, m.R, dt, tol, k_max, launched, cc,
+                                ctl, err);
 }
 
 int fold_sum(const double* in, int n, double* out, int* err, hipStream_t s) {
@@ -1174,9 +1373,24 @@ int fold_sum(const double* in, int n, double* out, int* err, hipStream_t s) {
 int cheb_term(const DevModel& m, int prec, int kk, bool energy, bool mid,
               int64_t est, const StepCtl* ctl, const int32_t* col, int64_t cap,
               const Side& n, const ChebCoef* cc, const void* phi, void* b0,
-              void* b1, double* e_part, int* err, hipStream_t s) {
+              void* b1, double* e_part, double* e_row, int* err,
+              hipStream_t s) {
   const int e = energy ? 1 : 0;
   const int g = grid_for(est);
+  if (m.R > 1) {
+    if (prec == 64) {
+      PACES_DISPATCH_SHAPE(m.ndim, m.V,
+          k_cheb_batch<double, A, B><<<g, kBlock, 0, s>>>(
+              m, kk, e, ctl, err, col, cap, n.pay, n.tot, cc,
+              (const double2*)phi, (double2*)b0, (double2*)b1, e_row));
+    } else {
+      PACES_DISPATCH_SHAPE(m.ndim, m.V,
+          k_cheb_batch<float, A, B><<<g, kBlock, 0, s>>>(
+              m, kk, e, ctl, err, col, cap, n.pay, n.tot, cc,
+              (const float2*)phi, (float2*)b0, (float2*)b1, e_row));
+    }
+    return g;
+  }
 #define PACES_TERM(R, AMP, MIDV)                                              \
   PACES_DISPATCH_SHAPE(m.ndim, m.V,                                           \
       k_cheb_term<R, A, B, MIDV><<<g, kBlock, 0, s>>>(                        \
@@ -1191,19 +1405,23 @@ int cheb_term(const DevModel& m, int prec, int kk, bool energy, bool mid,
   return g;
 }
 
-int pop_norm(int prec, int N, double th2, int64_t est, const StepCtl* ctl,
-             const void* psi, const uint64_t* pay, double* n2_part,
-             double* pop_part, uint32_t* sel_bsum, int* err, hipStream_t s) {
-  const size_t lds = sizeof(double) * (N <= kPrivBins ? N * 64 : N);
-  const int g = tiles_for(est);
+int pop_norm(int prec, int N, int R, double th2, int64_t est,
+             const StepCtl* ctl, const void* psi, const uint64_t* pay,
+             const double* e_row, double* n2_part, double* en_part,
+             double* pop_part, uint32_t* sel_bsum, uint32_t* cnt_s, int* err,
+             hipStream_t s) {
+  const bool priv = R == 1 && N <= kPrivBins;
+  const size_t lds = sizeof(double) * ((priv ? N * 64 : R * N) + 3 * R);
+  // batched partials hold R * N populations per block: fewer blocks
+  const int g = R > 1 ? std::min(tiles_for(est), 1024) : tiles_for(est);
   if (prec == 64)
-    k_pop_norm<double><<<g, kBlock, lds, s>>>(N, th2, ctl, (const double2*)psi,
-                                              pay, n2_part, pop_part, sel_bsum,
-                                              err);
+    k_pop_norm<double><<<g, kBlock, lds, s>>>(
+        N, R, th2, ctl, (const double2*)psi, pay, e_row, n2_part, en_part,
+        pop_part, sel_bsum, cnt_s, err);
   else
-    k_pop_norm<float><<<g, kBlock, lds, s>>>(N, th2, ctl, (const float2*)psi,
-                                             pay, n2_part, pop_part, sel_bsum,
-                                             err);
+    k_pop_norm<float><<<g, kBlock, lds, s>>>(
+        N, R, th2, ctl, (const float2*)psi, pay, e_row, n2_part, en_part,
+        pop_part, sel_bsum, cnt_s, err);
   return g;
 }
 
@@ -1212,30 +1430,32 @@ void autocorr(const DevModel& m, int Wi, int prec, const uint64_t* keys0,
               uint64_t mask, const uint64_t* keys, const void* psi,
               double* out2, int* err, hipStream_t s) {
   if (prec == 64) {
-    PACES_DISPATCH_W(Wi, k_autocorr<WW, double2><<<1, kBlock, 0, s>>>(
+    PACES_DISPATCH_W(Wi, k_autocorr<WW, double2><<<m.R, kBlock, 0, s>>>(
                              m, keys0, amps0, n0, table, mask, keys,
                              (const double2*)psi, out2, err));
   } else {
-    PACES_DISPATCH_W(Wi, k_autocorr<WW, float2><<<1, kBlock, 0, s>>>(
+    PACES_DISPATCH_W(Wi, k_autocorr<WW, float2><<<m.R, kBlock, 0, s>>>(
                              m, keys0, amps0, n0, table, mask, keys,
                              (const float2*)psi, out2, err));
   }
 }
 
-void end_step(StepCtl* ctl, const double* ring, int rec_doubles, int* err,
-              hipStream_t s) {
-  k_end_step<<<1, 1, 0, s>>>(ctl, ring, rec_doubles, err);
+void end_step(StepCtl* ctl, int R, const double* ring, int rec_doubles,
+              double* mass_tot, int* err, hipStream_t s) {
+  k_end_step<<<1, 1, 0, s>>>(ctl, R, ring, rec_doubles, mass_tot, err);
 }
 
-void obs_final(int N, int want_energy, double dt, int n_mass, int n_e,
+void obs_final(int N, int R, int want_energy, double dt, int n_mass, int n_e,
                int n_pop, const double* mass_part, const double* n2_part,
-               const double* e_part, const double* pop_part, const double* a2,
-               const ChebCoef* cc, StepCtl* ctl, double* ring, int rec_doubles,
+               const double* e_part, const double* en_part,
+               const double* pop_part, const double* a2, const ChebCoef* cc,
+               const StepCtl* ctl, const uint32_t* cnt,
+               const double* mass_tot, double* ring, int rec_doubles,
                int64_t ring_cap, int* err, hipStream_t s) {
-  k_obs_final<<<N + 1, kBlock, 0, s>>>(N, want_energy, dt, n_mass, n_e,
-                                       n_pop, mass_part, n2_part, e_part,
-                                       pop_part, a2, cc, ctl, ring, rec_doubles,
-                                       ring_cap, err);
+  k_obs_final<<<dim3(N + 1, R), kBlock, 0, s>>>(
+      N, R, want_energy, dt, n_mass, n_e, n_pop, mass_part, n2_part, e_part,
+      en_part, pop_part, a2, cc, ctl, cnt, mass_tot, ring, rec_doubles,
+      ring_cap, err);
 }
 
 void row_info(const DevModel& m, int Wi, const uint64_t* keys, int64_t n,

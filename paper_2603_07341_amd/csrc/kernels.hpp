@@ -18,6 +18,7 @@ constexpr int kMaxRounds = 30;   // neighbour order per step, hard limit
 constexpr int kPartBlocks = 2048;  // grid of the population reduction
 constexpr int kMaxPartials = 1 << 18;  // per-block partials of row kernels
 constexpr int kObsFields = 12;
+constexpr int kMaxReal = 256;      // disorder realizations per sim
 
 // Chebyshev expansion of exp(-i H dt) on [E_min, E_max], computed on the
 // device from the Gershgorin bounds of the step.
@@ -39,9 +40,9 @@ struct StepCtl {
   uint32_t n_new;                     // rows of the new set
   // current expansion round
   uint32_t r_f0, r_rows, r_ncand, r_ntiles, r_ncur, r_total;
-  uint32_t nrec;                      // observation records written
+  uint32_t kmax;                      // largest K over realizations
+  uint32_t nrec;                      // steps recorded (R records each)
   double t;                           // time after the last completed step
-  double mass_total;                  // cumulative discarded weight
 };
 
 // Buffers of one expansion round.
@@ -66,8 +67,9 @@ int64_t scan_tmp_words(int64_t n);
 
 void fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
 
-// Start of a step: clear the latch, reset the round counters.
-void begin_step(StepCtl* ctl, int* err, hipStream_t s);
+// Start of a step: clear the latch, reset the counters (cnt: 2R
+// per-realization row counts, |M_r| then |S_r|).
+void begin_step(StepCtl* ctl, int* err, uint32_t* cnt, int R, hipStream_t s);
 // Rows of ctl->n_old with weight >= th2, ascending, into midx; ctl->nM.
 // select_all: the first step takes every row.
 // counted: tmp already holds the per-tile counts (from pop_norm).
@@ -77,7 +79,7 @@ void select_rows(int prec, const void* psi, double th2, bool select_all,
 // Rows 0..nM-1 of the new side are M; inserted into the cleared table.
 void insert_rows(const DevModel& m, int Wi, const Side& o, const Side& n,
                  const uint32_t* midx, const StepCtl* ctl, uint64_t* table,
-                 uint64_t mask, int* err, hipStream_t s);
+                 uint64_t mask, uint32_t* cnt_m, int* err, hipStream_t s);
 // Rebuild the table from rows [0, n) of a side (after growth).
 void rehash_rows(const DevModel& m, int Wi, const Side& n, uint32_t* midx,
                  int64_t rows, uint64_t* table, uint64_t mask, int* err,
@@ -102,39 +104,46 @@ int transfer(const DevModel& m, int Wi, int prec, const Side& o,
              const void* psi_o, int64_t n_old, const StepCtl* ctl,
              const uint64_t* table, uint64_t mask, const uint64_t* keys_n,
              void* phi, double* mass_part, int* err, hipStream_t s);
-// Gershgorin bounds + Chebyshev coefficients; latches if K > launched.
+// Gershgorin bounds + Chebyshev coefficients per realization (cc[R]);
+// latches if some K_r exceeds the launches enqueued.
 void bounds_and_coef(const DevModel& m, const Side& n, const int32_t* col,
-                     int64_t cap, int64_t est, const StepCtl* ctl, double dt,
+                     int64_t cap, int64_t est, StepCtl* ctl, double dt,
                      double tol, int k_max, int launched, double* part,
-                     double* folded, ChebCoef* cc, int* err, hipStream_t s);
+                     ChebCoef* cc, int* err, hipStream_t s);
 // Fold n per-block partials to at most 256 (deterministic); returns count.
 int fold_sum(const double* in, int n, double* out, int* err, hipStream_t s);
 // Clenshaw launch for index kk (see kernels.hip); buffers b[0], b[1].
 // Returns the number of energy partials (written by the first launch).
 // mid: the launch is expected to be a middle term (selects a kernel name).
+// Batched sims (R > 1) leave the energy per row in e_row.
 int cheb_term(const DevModel& m, int prec, int kk, bool energy, bool mid,
               int64_t est, const StepCtl* ctl, const int32_t* col, int64_t cap,
               const Side& n, const ChebCoef* cc, const void* phi, void* b0,
-              void* b1, double* e_part, int* err, hipStream_t s);
+              void* b1, double* e_part, double* e_row, int* err,
+              hipStream_t s);
 // |psi|^2 and exciton populations as per-block partials (returns their
 // count, at most kPartBlocks), plus the next step's select counts.
-int pop_norm(int prec, int N, double th2, int64_t est, const StepCtl* ctl,
-             const void* psi, const uint64_t* pay, double* n2_part,
-             double* pop_part, uint32_t* sel_bsum, int* err, hipStream_t s);
+int pop_norm(int prec, int N, int R, double th2, int64_t est,
+             const StepCtl* ctl, const void* psi, const uint64_t* pay,
+             const double* e_row, double* n2_part, double* en_part,
+             double* pop_part, uint32_t* sel_bsum, uint32_t* cnt_s, int* err,
+             hipStream_t s);
 void autocorr(const DevModel& m, int Wi, int prec, const uint64_t* keys0,
               const double* amps0, int64_t n0, const uint64_t* table,
               uint64_t mask, const uint64_t* keys, const void* psi,
               double* out2, int* err, hipStream_t s);
-// Commit a successful step on the device: time, discarded weight, record
-// count and the row count of the current set.
-void end_step(StepCtl* ctl, const double* ring, int rec_doubles, int* err,
-              hipStream_t s);
+// Commit a successful step on the device: time, discarded weight per
+// realization, record count and the row count of the current set.
+void end_step(StepCtl* ctl, int R, const double* ring, int rec_doubles,
+              double* mass_tot, int* err, hipStream_t s);
 // Reduce partials into observation record ctl->nrec (skipped when an error
 // is latched, so a repeated step records once).
-void obs_final(int N, int want_energy, double dt, int n_mass, int n_e,
+void obs_final(int N, int R, int want_energy, double dt, int n_mass, int n_e,
                int n_pop, const double* mass_part, const double* n2_part,
-               const double* e_part, const double* pop_part, const double* a2,
-               const ChebCoef* cc, StepCtl* ctl, double* ring, int rec_doubles,
+               const double* e_part, const double* en_part,
+               const double* pop_part, const double* a2, const ChebCoef* cc,
+               const StepCtl* ctl, const uint32_t* cnt,
+               const double* mass_tot, double* ring, int rec_doubles,
                int64_t ring_cap, int* err, hipStream_t s);
 
 void row_info(const DevModel& m, int Wi, const uint64_t* keys, int64_t n,

@@ -89,6 +89,7 @@ struct paces_model {
   double omega[4] = {0, 0, 0, 0}, g[4] = {0, 0, 0, 0}, J[3] = {0, 0, 0};
   std::vector<double> eps;
   int bj = 1, bnu[4] = {0, 0, 0, 0}, P = 0, B = 0, W = 1, D = 0, Wi = 1;
+  int R = 1, br = 0;  // disorder realizations and bits of the id
   std::vector<int32_t> nbr;
   std::vector<double> gsq;
   int32_t* d_nbr = nullptr;
@@ -99,20 +100,41 @@ struct paces_model {
 
 namespace {
 
-// Canonical <-> internal keys: internal rows carry Wi >= W words, the extra
-// leading words are zero.
+// Canonical <-> internal keys: internal rows carry Wi >= W words; the
+// realization id sits in the br bits above the B bits of the state, the
+// remaining leading bits are zero.
+void set_ibit(const paces_model* m, uint64_t* key, int pos) {
+  key[m->Wi - 1 - pos / 64] |= uint64_t(1) << (pos % 64);
+}
+int internal_real(const paces_model* m, const uint64_t* key) {
+  int r = 0;
+  for (int b = 0; b < m->br; ++b) {
+    const int pos = m->B + b;
+    r |= int((key[m->Wi - 1 - pos / 64] >> (pos % 64)) & 1u) << b;
+  }
+  return r;
+}
+// real: realization of each row (NULL: all rows in realization 0).
 void to_internal(const paces_model* m, int64_t n, const uint64_t* in,
-                 std::vector<uint64_t>& out) {
-  out.assign(size_t(n) * m->Wi, 0);
-  for (int64_t i = 0; i < n; ++i)
-    for (int w = 0; w < m->W; ++w)
-      out[size_t(i) * m->Wi + (m->Wi - m->W) + w] = in[size_t(i) * m->W + w];
+                 const int32_t* real, uint64_t* out) {
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t* k = out + size_t(i) * m->Wi;
+    for (int w = 0; w < m->Wi; ++w) k[w] = 0;
+    for (int w = 0; w < m->W; ++w) k[(m->Wi - m->W) + w] = in[size_t(i) * m->W + w];
+    const int r = real ? real[i] : 0;
+    for (int b = 0; b < m->br; ++b)
+      if ((r >> b) & 1) set_ibit(m, k, m->B + b);
+  }
 }
 void to_canonical(const paces_model* m, int64_t n, const uint64_t* in,
-                  uint64_t* out) {
-  for (int64_t i = 0; i < n; ++i)
-    for (int w = 0; w < m->W; ++w)
-      out[size_t(i) * m->W + w] = in[size_t(i) * m->Wi + (m->Wi - m->W) + w];
+                  uint64_t* out, int32_t* real) {
+  for (int64_t i = 0; i < n; ++i) {
+    if (real) real[i] = internal_real(m, in + size_t(i) * m->Wi);
+    uint64_t* k = out + size_t(i) * m->W;
+    for (int w = 0; w < m->W; ++w) k[w] = in[size_t(i) * m->Wi + (m->Wi - m->W) + w];
+    for (int pos = m->B; pos < 64 * m->W; ++pos)
+      k[m->W - 1 - pos / 64] &= ~(uint64_t(1) << (pos % 64));
+  }
 }
 
 uint64_t field_get(const paces_model* m, const uint64_t* key, int off,
@@ -148,11 +170,9 @@ paces_status check_keys(const paces_model* m, int64_t n, const uint64_t* keys) {
   return PACES_OK;
 }
 
-paces_status check_unique(const paces_model* m, int64_t n,
-                          const uint64_t* keys) {
+paces_status check_unique(int W, int64_t n, const uint64_t* keys) {
   std::vector<int64_t> idx(n);
   std::iota(idx.begin(), idx.end(), 0);
-  const int W = m->W;
   auto less = [&](int64_t a, int64_t b) {
     return std::lexicographical_compare(keys + a * W, keys + a * W + W,
                                         keys + b * W, keys + b * W + W);
@@ -198,10 +218,13 @@ struct paces_sim {
   int* err = nullptr;
   double* parts = nullptr;
   double *mass_part = nullptr, *n2_part = nullptr, *e_part = nullptr,
-         *pop_part = nullptr, *bnd_part = nullptr;
-  double *mass_fold = nullptr, *e_fold = nullptr, *bnd_fold = nullptr;
-  ChebCoef* cc = nullptr;
-  double* a2 = nullptr;
+         *en_part = nullptr, *pop_part = nullptr, *bnd_part = nullptr;
+  double *mass_fold = nullptr, *e_fold = nullptr;
+  double* e_row = nullptr;     // per-row energy terms (batched sims)
+  ChebCoef* cc = nullptr;      // [R]
+  double* a2 = nullptr;        // [R][2]
+  uint32_t* cnt = nullptr;     // [2R]: |M_r| then |S_r|
+  double* mass_tot = nullptr;  // [R] cumulative discarded weight
 
   uint64_t* keys0 = nullptr;
   double* amps0 = nullptr;
@@ -223,7 +246,6 @@ struct paces_sim {
   int latched = 0;
   StepCtl* h_ctl = nullptr;  // pinned
   int* h_err = nullptr;      // pinned
-  int* h_K = nullptr;        // pinned
   std::vector<double> pop_host;
 
   bool prof = false;
@@ -287,6 +309,7 @@ void free_rows(paces_sim* s) {
   dfree(s->table);
   dfree(s->midx);
   dfree(s->scan_tmp);
+  dfree(s->e_row);
 }
 
 void free_cand(paces_sim* s) {
@@ -330,6 +353,7 @@ paces_status grow(paces_sim* s, int64_t new_cap, hipStream_t st) {
   dfree(s->table);
   dfree(s->midx);
   dfree(s->scan_tmp);
+  dfree(s->e_row);
   Side nsd[2]{};
   for (int q = 0; q < 2; ++q) {
     ST_TRY(dalloc(&nsd[q].keys, new_cap * m->Wi));
@@ -363,6 +387,7 @@ paces_status grow(paces_sim* s, int64_t new_cap, hipStream_t st) {
   s->counts_valid = false;
   ST_TRY(dalloc(&s->midx, new_cap));
   ST_TRY(dalloc(&s->scan_tmp, scan_tmp_words(new_cap)));
+  if (m->R > 1) ST_TRY(dalloc(&s->e_row, new_cap));
   HIP_TRY(hipStreamSynchronize(st));
   dfree(old.keys);
   dfree(old.pay);
@@ -411,9 +436,10 @@ paces_status ensure_ring(paces_sim* s, hipStream_t st) {
   if (int64_t(s->h.nrec) + 1 < s->ring_cap) return PACES_OK;
   const int64_t nc = std::max<int64_t>(1024, 2 * s->ring_cap);
   double* r = nullptr;
-  ST_TRY(dalloc(&r, nc * s->rec_doubles));
+  const int64_t per_step = int64_t(s->m->R) * s->rec_doubles;
+  ST_TRY(dalloc(&r, nc * per_step));
   if (s->h.nrec > 0)
-    HIP_TRY(hipMemcpyAsync(r, s->ring, size_t(s->h.nrec) * s->rec_doubles * 8,
+    HIP_TRY(hipMemcpyAsync(r, s->ring, size_t(s->h.nrec) * per_step * 8,
                            hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
   dfree(s->ring);
@@ -430,16 +456,15 @@ paces_status push_ctl(paces_sim* s, hipStream_t st) {
   return PACES_OK;
 }
 
-// Upload a state given as canonical keys + FP64 amplitudes into side cur.
-paces_status upload_state(paces_sim* s, int64_t n, const uint64_t* keys,
-                          const double* amps, hipStream_t st) {
+// Upload a state given as internal keys + FP64 amplitudes into side cur.
+paces_status upload_state(paces_sim* s, int64_t n,
+                          const std::vector<uint64_t>& ik, const double* amps,
+                          hipStream_t st) {
   const paces_model* m = s->m;
   if (n > s->cap) {
     s->nS = 0;
     ST_TRY(grow(s, std::max<int64_t>(2 * n, 2 * s->cap), st));
   }
-  std::vector<uint64_t> ik;
-  to_internal(m, n, keys, ik);
   Side& sc = s->side[s->cur];
   if (n > 0) {
     HIP_TRY(hipMemcpyAsync(sc.keys, ik.data(), ik.size() * 8,
@@ -463,11 +488,11 @@ paces_status upload_state(paces_sim* s, int64_t n, const uint64_t* keys,
 void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st) {
   const paces_model* m = s->m;
   const DevModel& dm = m->dm;
-  const int Wi = m->Wi;
+  const int Wi = m->Wi, R = m->R;
   const int old = s->cur, nw = 1 - s->cur;
   const int k = s->fresh ? s->p.k_init : s->p.k;
   const Side so = s->side[old], sn = s->side[nw];
-  begin_step(s->ctl, s->err, st);
+  begin_step(s->ctl, s->err, s->cnt, R, st);
   {
     Stage sg(s, PACES_STAGE_SELECT, st);
     select_rows(s->prec, s->vec[s->ipsi], s->th2, s->fresh, counted, s->ctl,
@@ -477,8 +502,8 @@ void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st) {
   {
     Stage sg(s, PACES_STAGE_EXPAND, st);
     fill_u64(s->table, int64_t(s->tmask + 1), kEmpty, st);
-    insert_rows(dm, Wi, so, sn, s->midx, s->ctl, s->table, s->tmask, s->err,
-                st);
+    insert_rows(dm, Wi, so, sn, s->midx, s->ctl, s->table, s->tmask, s->cnt,
+                s->err, st);
     for (int r = 1; r <= k; ++r)
       expand_round(dm, Wi, s->prec, sn, r, s->ctl, s->cap, est, s->table,
                    s->tmask, s->rb, s->col, s->vec[s->iphi], s->err, st);
@@ -491,13 +516,13 @@ void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st) {
     const int np = transfer(dm, Wi, s->prec, so, s->vec[s->ipsi], s->nS,
                             s->ctl, s->table, s->tmask, sn.keys,
                             s->vec[s->iphi], s->mass_part, s->err, st);
-    n_mass = fold_sum(s->mass_part, np, s->mass_fold, s->err, st);
+    n_mass = R == 1 ? fold_sum(s->mass_part, np, s->mass_fold, s->err, st) : np;
   }
   {
     Stage sg(s, PACES_STAGE_BUILD, st);
     bounds_and_coef(dm, sn, s->col, s->cap, est, s->ctl, s->p.dt, s->p.tol,
-                    s->p.k_max_terms, s->launched, s->bnd_part, s->bnd_fold,
-                    s->cc, s->err, st);
+                    s->p.k_max_terms, s->launched, s->bnd_part, s->cc, s->err,
+                    st);
   }
   const bool want_e = (s->p.obs_mask & PACES_OBS_ENERGY) != 0;
   {
@@ -506,23 +531,26 @@ void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st) {
     for (int kk = s->launched - 1; kk >= 0; --kk) {
       Stage tg(s, PACES_STAGE_TERM, st, kk);
       const bool mid = s->K_last >= 4 && kk >= 1 && kk <= s->K_last - 3;
-      np = cheb_term(dm, s->prec, kk, want_e, mid, est, s->ctl, s->col, s->cap, sn,
-                     s->cc, s->vec[s->iphi], s->vec[s->ib0], s->vec[s->ib1],
-                     s->e_part, s->err, st);
+      np = cheb_term(dm, s->prec, kk, want_e, mid, est, s->ctl, s->col, s->cap,
+                     sn, s->cc, s->vec[s->iphi], s->vec[s->ib0],
+                     s->vec[s->ib1], s->e_part, s->e_row, s->err, st);
     }
-    if (want_e) n_e = fold_sum(s->e_part, np, s->e_fold, s->err, st);
+    if (want_e && R == 1) n_e = fold_sum(s->e_part, np, s->e_fold, s->err, st);
   }
   {
     Stage sg(s, PACES_STAGE_OBSERVE, st);
-    const int n_pop = pop_norm(s->prec, m->N, s->th2, est, s->ctl,
-                               s->vec[s->ib0], sn.pay, s->n2_part, s->pop_part,
-                               s->scan_tmp, s->err, st);
+    const int n_pop = pop_norm(s->prec, m->N, R, s->th2, est, s->ctl,
+                               s->vec[s->ib0], sn.pay,
+                               want_e && R > 1 ? s->e_row : nullptr,
+                               s->n2_part, s->en_part, s->pop_part,
+                               s->scan_tmp, s->cnt + R, s->err, st);
     autocorr(dm, Wi, s->prec, s->keys0, s->amps0, s->n0, s->table, s->tmask,
              sn.keys, s->vec[s->ib0], s->a2, s->err, st);
-    obs_final(m->N, want_e ? 1 : 0, s->p.dt, n_mass, n_e, n_pop, s->mass_fold,
-              s->n2_part, s->e_fold, s->pop_part, s->a2, s->cc, s->ctl,
-              s->ring, s->rec_doubles, s->ring_cap, s->err, st);
-    end_step(s->ctl, s->ring, s->rec_doubles, s->err, st);
+    obs_final(m->N, R, want_e ? 1 : 0, s->p.dt, n_mass, n_e, n_pop,
+              R == 1 ? s->mass_fold : s->mass_part, s->n2_part, s->e_fold,
+              s->en_part, s->pop_part, s->a2, s->cc, s->ctl, s->cnt,
+              s->mass_tot, s->ring, s->rec_doubles, s->ring_cap, s->err, st);
+    end_step(s->ctl, R, s->ring, s->rec_doubles, s->mass_tot, s->err, st);
   }
 }
 
@@ -549,13 +577,11 @@ paces_status do_step(paces_sim* s, hipStream_t st) {
                            hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(s->h_err, s->err, sizeof(int), hipMemcpyDeviceToHost,
                            st));
-    HIP_TRY(hipMemcpyAsync(s->h_K, &s->cc->K, sizeof(int),
-                           hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     const int e = *s->h_err;
     if (e == 0) {
       const StepCtl& c = *s->h_ctl;
-      const int K = *s->h_K;
+      const int K = int(c.kmax);
       // classify the timed Clenshaw launches of this step
       const double rowb = 4.0 * double(s->A) + 4.0 * m->D + (m->V > 2 ? 16 : 8);
       for (auto& ev : s->pending) {
@@ -588,7 +614,7 @@ paces_status do_step(paces_sim* s, hipStream_t st) {
     drop_pending(s);
     if (e & (kErrTerms | kErrNonFinite)) return check_latch_code(s, e);
     if (e & kErrNeedTerms) {
-      s->launched = std::min(*s->h_K + 2, kMaxTerms);
+      s->launched = std::min(int(s->h_ctl->kmax) + 2, kMaxTerms);
       continue;
     }
     if (e & kErrTableFull) {
@@ -618,7 +644,7 @@ paces_status ensure_device_tables(paces_model* m) {
   if (m->d_nbr) return PACES_OK;
   ST_TRY(dalloc(&m->d_nbr, int64_t(m->nbr.size())));
   ST_TRY(dalloc(&m->d_gsq, int64_t(m->gsq.size())));
-  ST_TRY(dalloc(&m->d_eps, int64_t(m->N)));
+  ST_TRY(dalloc(&m->d_eps, int64_t(m->R) * m->N));
   HIP_TRY(hipMemcpy(m->d_nbr, m->nbr.data(), m->nbr.size() * 4,
                     hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(m->d_gsq, m->gsq.data(), m->gsq.size() * 8,
@@ -676,17 +702,24 @@ paces_status paces_load_model(const paces_model_desc* d, paces_model** out) {
     m->bnu[nu] = bits_for(m->cut[nu] + 1);
     m->P += m->bnu[nu];
   }
-  if (int64_t(m->N) * m->cut[0] > 65535 ||
-      (m->V > 1 && int64_t(m->N) * std::max({m->cut[1], m->cut[2], m->cut[3]}) >
-                       65535))
-    return bad("N * cutoff must stay below 65536");
-  m->eps.assign(m->N, 0.0);
+  // total occupations are packed in 14 bits (two modes or fewer) or 16
+  const int64_t tot_max = m->V <= 2 ? 16383 : 65535;
+  for (int nu = 0; nu < m->V; ++nu)
+    if (int64_t(m->N) * m->cut[nu] > tot_max)
+      return bad("N * cutoff exceeds the packed total occupation");
+  m->R = d->n_real == 0 ? 1 : d->n_real;
+  if (m->R < 1 || m->R > kMaxReal) return bad("n_real must be 0..256");
+  // per-realization populations and sums of a block live in 64 KiB of LDS
+  if (int64_t(m->R) * (m->N + 3) > 8064)
+    return bad("n_real * (sites + 3) must not exceed 8064");
+  m->br = m->R > 1 ? bits_for(m->R) : 0;
+  m->eps.assign(size_t(m->R) * m->N, 0.0);
   if (d->eps)
-    for (int i = 0; i < m->N; ++i) m->eps[i] = d->eps[i];
+    for (size_t i = 0; i < m->eps.size(); ++i) m->eps[i] = d->eps[i];
   m->bj = std::max(1, bits_for(m->N));
   m->B = m->N * m->P + m->bj;
   m->W = (m->B + 63) / 64;
-  m->Wi = supported_words(m->W);
+  m->Wi = supported_words((m->B + m->br + 63) / 64);
   if (!m->Wi) return bad("key wider than 1024 bits");
   m->D = 2 * m->ndim + 2 * m->V;
   m->nbr.assign(size_t(m->N) * 2 * m->ndim, -1);
@@ -719,6 +752,8 @@ paces_status paces_load_model(const paces_model_desc* d, paces_model** out) {
   dm.D = m->D;
   dm.W = m->Wi;
   dm.B = m->B;
+  dm.R = m->R;
+  dm.br = m->br;
   dm.bj = m->bj;
   dm.P = m->P;
   for (int nu = 0; nu < m->V; ++nu) {
@@ -818,11 +853,26 @@ paces_status paces_init_state(const paces_model* m, const paces_run_params* p,
       (p->precision != 64 && p->precision != 32) || p->k_max_terms < 0 ||
       p->k_max_terms > kMaxTerms || p->tol < 0 || p->cap_states < 0)
     return fail(PACES_E_ARG, "bad run parameters");
-  if (n > (int64_t(1) << 30)) return fail(PACES_E_ARG, "too many states");
+  const int R = m->R;
+  if (n * R > (int64_t(1) << 30)) return fail(PACES_E_ARG, "too many states");
   std::vector<uint64_t> keys(size_t(n) * m->W);
   ST_TRY(paces_pack_keys(m, n, exc, occ, keys.data()));
-  ST_TRY(check_unique(m, n, keys.data()));
+  ST_TRY(check_unique(m->W, n, keys.data()));
   ST_TRY(ensure_device_tables(const_cast<paces_model*>(m)));
+  // every realization starts from the same state: rows r*n .. r*n+n-1
+  const int64_t nt = n * R;
+  std::vector<int32_t> real(nt);
+  std::vector<uint64_t> rk(size_t(nt) * m->W), ik(size_t(nt) * m->Wi);
+  std::vector<double> ra(size_t(nt) * 2);
+  for (int r = 0; r < R; ++r)
+    for (int64_t i = 0; i < n; ++i) {
+      real[r * n + i] = r;
+      std::memcpy(&rk[size_t(r * n + i) * m->W], &keys[size_t(i) * m->W],
+                  size_t(m->W) * 8);
+      ra[2 * (r * n + i)] = coef[2 * i];
+      ra[2 * (r * n + i) + 1] = coef[2 * i + 1];
+    }
+  to_internal(m, nt, rk.data(), real.data(), ik.data());
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   paces_sim* s = new paces_sim();
   s->m = m;
@@ -841,41 +891,46 @@ paces_status paces_init_state(const paces_model* m, const paces_run_params* p,
   };
   if (hipHostMalloc(reinterpret_cast<void**>(&s->h_ctl), sizeof(StepCtl)) !=
           hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&s->h_err), 64) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&s->h_K), 64) != hipSuccess)
+      hipHostMalloc(reinterpret_cast<void**>(&s->h_err), 64) != hipSuccess)
     return cleanup(fail(PACES_E_OOM, "pinned host allocation failed"));
-  const int64_t nparts = 4 * int64_t(kMaxPartials) +
-                         int64_t(kPartBlocks) * (m->N + 1) + 4 * 256;
+  // per-block partials of the row kernels (layouts in kernels.hpp)
+  const int64_t blk = R == 1 ? kMaxPartials : int64_t(kPartBlocks) * R;
+  const int64_t sz_mass = blk, sz_e = R == 1 ? kMaxPartials : 0,
+                sz_bnd = 2 * blk, sz_pop = int64_t(kPartBlocks) * R;
+  const int64_t nparts = sz_mass + sz_e + sz_bnd + 2 * sz_pop +
+                         sz_pop * m->N + 2 * 256;
   if (dalloc(&s->ctl, 1) || dalloc(&s->err, 1) || dalloc(&s->parts, nparts) ||
-      dalloc(&s->cc, 1) || dalloc(&s->a2, 2) ||
-      dalloc(&s->keys0, n * m->Wi) || dalloc(&s->amps0, 2 * n))
+      dalloc(&s->cc, R) || dalloc(&s->a2, 2 * R) || dalloc(&s->cnt, 2 * R) ||
+      dalloc(&s->mass_tot, R) || dalloc(&s->keys0, nt * m->Wi) ||
+      dalloc(&s->amps0, 2 * nt))
     return cleanup(PACES_E_OOM);
-  s->mass_part = s->parts;                      // kMaxPartials
-  s->e_part = s->parts + kMaxPartials;           // kMaxPartials
-  s->bnd_part = s->parts + 2 * kMaxPartials;     // (lo, hi) per block
-  s->n2_part = s->parts + 4 * kMaxPartials;      // kPartBlocks
-  s->pop_part = s->n2_part + kPartBlocks;        // N per block
-  s->mass_fold = s->pop_part + int64_t(kPartBlocks) * m->N;  // 256
-  s->e_fold = s->mass_fold + 256;                             // 256
-  s->bnd_fold = s->e_fold + 256;                              // 2 x 256
+  double* q = s->parts;
+  s->mass_part = q;  q += sz_mass;
+  s->e_part = q;     q += sz_e;
+  s->bnd_part = q;   q += sz_bnd;
+  s->n2_part = q;    q += sz_pop;
+  s->en_part = q;    q += sz_pop;
+  s->pop_part = q;   q += sz_pop * m->N;
+  s->mass_fold = q;  q += 256;
+  s->e_fold = q;
   if (hipMemsetAsync(s->err, 0, 4, st) != hipSuccess ||
-      hipMemsetAsync(s->parts, 0, size_t(nparts) * 8, st) != hipSuccess)
+      hipMemsetAsync(s->parts, 0, size_t(nparts) * 8, st) != hipSuccess ||
+      hipMemsetAsync(s->mass_tot, 0, size_t(R) * 8, st) != hipSuccess ||
+      hipMemsetAsync(s->cnt, 0, size_t(2 * R) * 4, st) != hipSuccess)
     return cleanup(fail(PACES_E_HIP, "memset failed"));
-  const int64_t cap0 = std::max<int64_t>({p->cap_states, 4 * n, 1 << 16});
+  const int64_t cap0 = std::max<int64_t>({p->cap_states, 4 * nt, 1 << 16});
   paces_status g = grow(s, cap0, st);
   if (g) return cleanup(g);
   g = ensure_ring(s, st);
   if (g) return cleanup(g);
-  std::vector<uint64_t> ik;
-  to_internal(m, n, keys.data(), ik);
   if (hipMemcpyAsync(s->keys0, ik.data(), ik.size() * 8, hipMemcpyHostToDevice,
                      st) != hipSuccess ||
-      hipMemcpyAsync(s->amps0, coef, size_t(n) * 16, hipMemcpyHostToDevice,
+      hipMemcpyAsync(s->amps0, ra.data(), ra.size() * 8, hipMemcpyHostToDevice,
                      st) != hipSuccess)
     return cleanup(fail(PACES_E_HIP, "upload failed"));
   s->n0 = n;
   std::memset(&s->h, 0, sizeof(s->h));
-  g = upload_state(s, n, keys.data(), coef, st);
+  g = upload_state(s, nt, ik, ra.data(), st);
   if (g) return cleanup(g);
   s->fresh = true;
   *out = s;
@@ -892,6 +947,8 @@ paces_status paces_free_sim(paces_sim* s) {
   dfree(s->parts);
   dfree(s->cc);
   dfree(s->a2);
+  dfree(s->cnt);
+  dfree(s->mass_tot);
   dfree(s->keys0);
   dfree(s->amps0);
   dfree(s->ring);
@@ -902,7 +959,6 @@ paces_status paces_free_sim(paces_sim* s) {
   }
   if (s->h_ctl) (void)hipHostFree(s->h_ctl);
   if (s->h_err) (void)hipHostFree(s->h_err);
-  if (s->h_K) (void)hipHostFree(s->h_K);
   delete s;
   return PACES_OK;
 }
@@ -921,19 +977,23 @@ paces_status paces_step(paces_sim* s, int64_t n_steps, void* hip_stream) {
   return PACES_OK;
 }
 
-paces_status paces_observe(paces_sim* s, paces_obs* out, void* hip_stream) {
-  if (!s || !out) return fail(PACES_E_ARG, "bad arguments");
+paces_status paces_observe(paces_sim* s, int32_t realization, paces_obs* out,
+                           void* hip_stream) {
+  if (!s || !out || realization < 0 || realization >= s->m->R)
+    return fail(PACES_E_ARG, "bad arguments");
   if (s->latched) return fail(PACES_E_STATE, "sim is in an error state");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   std::memset(out, 0, sizeof(*out));
   if (s->h.nrec == 0) {
     out->t = s->h.t;
     out->n_S = s->nS;
+    std::fill(s->pop_host.begin(), s->pop_host.end(), 0.0);
     out->pop = s->pop_host.data();
     return PACES_OK;
   }
   std::vector<double> rec(s->rec_doubles);
-  HIP_TRY(hipMemcpyAsync(rec.data(), s->ring + (s->h.nrec - 1) * s->rec_doubles,
+  const int64_t at = (int64_t(s->h.nrec) - 1) * s->m->R + realization;
+  HIP_TRY(hipMemcpyAsync(rec.data(), s->ring + at * s->rec_doubles,
                          rec.size() * 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   out->t = rec[0];
@@ -966,26 +1026,27 @@ paces_status paces_series(paces_sim* s, int64_t first, int64_t n, double* out,
     return fail(PACES_E_ARG, "bad arguments");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   if (n == 0) return PACES_OK;
-  HIP_TRY(hipMemcpyAsync(out, s->ring + first * s->rec_doubles,
-                         size_t(n) * s->rec_doubles * 8, hipMemcpyDeviceToHost,
-                         st));
+  const int64_t per = int64_t(s->m->R) * s->rec_doubles;
+  HIP_TRY(hipMemcpyAsync(out, s->ring + first * per, size_t(n * per) * 8,
+                         hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   return PACES_OK;
 }
 
 paces_status paces_get_state(paces_sim* s, int64_t* n, uint64_t* keys,
-                             double* amps, void* hip_stream) {
+                             double* amps, int32_t* real, void* hip_stream) {
   if (!s || !n) return fail(PACES_E_ARG, "bad arguments");
   if (s->latched) return fail(PACES_E_STATE, "sim is in an error state");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   *n = s->nS;
   const paces_model* m = s->m;
-  if (keys && s->nS > 0) {
-    std::vector<uint64_t> ik(size_t(s->nS) * m->Wi);
+  if ((keys || real) && s->nS > 0) {
+    std::vector<uint64_t> ik(size_t(s->nS) * m->Wi), ck;
     HIP_TRY(hipMemcpyAsync(ik.data(), s->side[s->cur].keys, ik.size() * 8,
                            hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    to_canonical(m, s->nS, ik.data(), keys);
+    if (!keys) ck.resize(size_t(s->nS) * m->W);
+    to_canonical(m, s->nS, ik.data(), keys ? keys : ck.data(), real);
   }
   if (amps && s->nS > 0) {
     double* tmp = nullptr;
@@ -1000,17 +1061,25 @@ paces_status paces_get_state(paces_sim* s, int64_t* n, uint64_t* keys,
 }
 
 paces_status paces_set_state(paces_sim* s, int64_t n, const uint64_t* keys,
-                             const double* amps, double t, void* hip_stream) {
+                             const double* amps, const int32_t* real, double t,
+                             void* hip_stream) {
   if (!s || n < 0 || (n > 0 && (!keys || !amps)))
     return fail(PACES_E_ARG, "bad arguments");
   if (n > (int64_t(1) << 30)) return fail(PACES_E_ARG, "too many states");
+  const paces_model* m = s->m;
+  if (real)
+    for (int64_t i = 0; i < n; ++i)
+      if (real[i] < 0 || real[i] >= m->R)
+        return fail(PACES_E_ARG, "realization index out of range");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  ST_TRY(check_keys(s->m, n, keys));
-  ST_TRY(check_unique(s->m, n, keys));
+  ST_TRY(check_keys(m, n, keys));
+  std::vector<uint64_t> ik(size_t(n) * m->Wi);
+  to_internal(m, n, keys, real, ik.data());
+  ST_TRY(check_unique(m->Wi, n, ik.data()));
   HIP_TRY(hipStreamSynchronize(st));
   s->latched = 0;
   s->h.t = t;
-  ST_TRY(upload_state(s, n, keys, amps, st));
+  ST_TRY(upload_state(s, n, ik, amps, st));
   s->fresh = false;
   s->have_sets = false;
   s->counts_valid = false;
@@ -1018,7 +1087,8 @@ paces_status paces_set_state(paces_sim* s, int64_t n, const uint64_t* keys,
 }
 
 paces_status paces_get_set(paces_sim* s, int32_t which, int32_t round,
-                           int64_t* n, uint64_t* keys, void* hip_stream) {
+                           int64_t* n, uint64_t* keys, int32_t* real,
+                           void* hip_stream) {
   if (!s || !n) return fail(PACES_E_ARG, "bad arguments");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   int64_t a = 0, b = 0;
@@ -1036,13 +1106,14 @@ paces_status paces_get_set(paces_sim* s, int32_t which, int32_t round,
     return fail(PACES_E_ARG, "unknown set");
   }
   *n = b - a;
-  if (!keys || b == a) return PACES_OK;
+  if ((!keys && !real) || b == a) return PACES_OK;
   const paces_model* m = s->m;
-  std::vector<uint64_t> ik(size_t(b - a) * m->Wi);
+  std::vector<uint64_t> ik(size_t(b - a) * m->Wi), ck;
   HIP_TRY(hipMemcpyAsync(ik.data(), s->side[s->cur].keys + a * m->Wi,
                          ik.size() * 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  to_canonical(m, b - a, ik.data(), keys);
+  if (!keys) ck.resize(size_t(b - a) * m->W);
+  to_canonical(m, b - a, ik.data(), keys ? keys : ck.data(), real);
   return PACES_OK;
 }
 

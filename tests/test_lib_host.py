@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(lib, name), name
     assert sorted(P.EXPORTS) == declared
-    assert lib.paces_abi_version() == 1
+    assert lib.paces_abi_version() == 2
 
 
 @pytest.mark.parametrize("name", ["ring4", "ring16", "sq6x6", "cube4", "ring12"])
@@ -50,6 +50,11 @@ def test_host_codec_matches_oracle(name):
 @pytest.mark.parametrize("bad", [
     dict(ndim=0), dict(ndim=1, extent=[2, 1, 1], periodic=[1, 0, 0]),
     dict(n_modes=5), dict(cutoff=[0, 0, 0, 0]), dict(cutoff=[300, 0, 0, 0]),
+    dict(n_real=257), dict(n_real=-1),
+    # R * (N + 3) above the LDS budget of the batched reductions
+    dict(extent=[64, 1, 1], n_real=128),
+    # N * cutoff above the 14-bit packed total occupation
+    dict(extent=[2048, 1, 1], cutoff=[10, 0, 0, 0]),
 ])
 def test_model_validation_rejects(bad):
     p = WL.model_params(WL.CONFIGS["ring4"])
@@ -65,3 +70,14 @@ def test_pack_rejects_out_of_range():
         gm.pack([4], [0, 0, 0, 0])
     with pytest.raises(P.PacesError):
         gm.pack([0], [0, 5, 0, 0])
+
+
+def test_batched_model_accepts_eps_per_realization():
+    cfg = WL.CONFIGS["sq6x6"]
+    p = WL.batch_params(cfg)
+    gm = P.Model(p)
+    assert gm.R == 64 and len(p["eps"]) == 64 * 36
+    # the realization id lives above the canonical key bits: the canonical
+    # layout (and so the host codec) is unchanged by batching
+    single = P.Model(WL.model_params(cfg))
+    assert (gm.N, gm.W, gm.D, gm.B) == (single.N, single.W, single.D, single.B)

@@ -114,6 +114,22 @@ def model_params(cfg, realization=0, **override):
     }
 
 
+def batch_params(cfg, n_real=None, first=0, **override):
+    """Model parameters of a batched run: realizations first .. first +
+    n_real - 1 of the workload's disorder, their site energies concatenated
+    realization-major."""
+    c = dict(cfg)
+    c.update(override)
+    R = c["n_real"] if n_real is None else n_real
+    p = model_params(c, first)
+    eps = []
+    for r in range(first, first + R):
+        eps += site_energies(c, r)
+    p["eps"] = eps
+    p["n_real"] = R
+    return p
+
+
 def initial_state(cfg, kind=None, site=0):
     """(exc, occ, coef) of the initial state.
 
