@@ -227,3 +227,70 @@ def expmv(rowptr, cols, vals, dt, emin, emax, v, max_terms=200):
                            _p(np.ascontiguousarray(vin), C.c_double),
                            _p(vout, C.c_double), C.byref(terms)))
     return vout.view(np.complex128), terms.value
+
+
+def param_names(model_params):
+    """Names of the gradient entries: J per axis, g and omega per mode,
+    eps per site."""
+    nd, V = model_params["ndim"], model_params["n_modes"]
+    ext = model_params["extent"]
+    N = ext[0] * ext[1] * ext[2]
+    return (["J%d" % a for a in range(nd)] + ["g%d" % v for v in range(V)]
+            + ["omega%d" % v for v in range(V)] + ["eps%d" % i for i in range(N)])
+
+
+class Frozen:
+    """A recorded run whose sets are held fixed for the adjoint gradient."""
+
+    def __init__(self, model, run, exc, occ, coef, steps, max_terms=200):
+        p = _Params()
+        p.dt = run["dt"]
+        p.k = run["k"]
+        p.k_init = run["k_init"]
+        p.theta = run["theta"]
+        p.max_terms = max_terms
+        exc = np.ascontiguousarray(exc, dtype=np.int32)
+        occ = np.ascontiguousarray(occ, dtype=np.uint16)
+        coef = np.ascontiguousarray(coef, dtype=np.float64)
+        h = C.c_void_p()
+        _check(lib().orc_frozen_record(model.h, C.byref(p), C.c_int64(len(exc)),
+                                       _p(exc, C.c_int32), _p(occ, C.c_uint16),
+                                       _p(coef, C.c_double), C.c_int64(steps),
+                                       C.byref(h)))
+        self.h = h
+        self.model = model
+        n, P = C.c_int64(), C.c_int32()
+        _check(lib().orc_frozen_info(h, C.byref(n), C.byref(P), None))
+        self.steps, self.n_params = n.value, P.value
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.orc_frozen_destroy(self.h)
+            self.h = None
+
+    def sizes(self):
+        out = np.zeros(self.steps + 1, dtype=np.int64)
+        _check(lib().orc_frozen_info(self.h, None, None, _p(out, C.c_int64)))
+        return out
+
+    def get_set(self, step):
+        n = int(self.sizes()[step])
+        keys = np.zeros(n * self.model.W, dtype=np.uint64)
+        _check(lib().orc_frozen_get_set(self.h, C.c_int64(step),
+                                        _p(keys, C.c_uint64)))
+        return keys.reshape(n, self.model.W)
+
+    def eval(self, model):
+        """a[s] = <psi0|psi_s>, s = 0..steps, replayed with `model`."""
+        a = np.zeros(2 * (self.steps + 1), dtype=np.float64)
+        _check(lib().orc_frozen_eval(self.h, model.h, _p(a, C.c_double)))
+        return a.view(np.complex128)
+
+    def grad(self, model, gbar):
+        """(a, dL/dtheta) for gbar[s] = dL/d conj(a_s)."""
+        gb = np.ascontiguousarray(np.asarray(gbar, dtype=np.complex128)).view(np.float64)
+        a = np.zeros(2 * (self.steps + 1), dtype=np.float64)
+        g = np.zeros(self.n_params, dtype=np.float64)
+        _check(lib().orc_frozen_grad(self.h, model.h, _p(gb, C.c_double),
+                                     _p(a, C.c_double), _p(g, C.c_double)))
+        return a.view(np.complex128), g

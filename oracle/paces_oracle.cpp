@@ -568,6 +568,246 @@ int check_keys(const Model& m, int64_t n, const uint64_t* keys) {
   return 0;
 }
 
+
+// ---------------------------------------------------------------------------
+// Gradient of a loss of the autocorrelation (Form (3); the paper has no
+// adjoint).  The sets S_0 (support of psi0), S_1, .., S_n of a recorded run
+// are held fixed, and every step is the linear map
+//     psi_{s+1} = U_s T_s psi_s,   U_s = exp(-i H_{s+1} dt) on S_{s+1},
+// with T_s the restriction from S_s to S_{s+1} (post-adaptation
+// detruncation).  For a real loss L of a_s = <psi0|psi_s> with
+// gbar_s = dL/d conj(a_s), the discrete adjoint
+//     lambda_n = gbar_n psi0,
+//     lambda_s = T_s^T U_s^dag lambda_{s+1} + gbar_s psi0
+// gives  dL/dtheta_p = sum_s 2 Re <lambda_{s+1} | (dU_s/dtheta_p) T_s psi_s>.
+// H is linear in theta = (J_axis, g_nu, omega_nu, eps_n) (Eq. (holstein));
+// dU/dtheta_p v is the Frechet derivative of exp at A = -i H dt in the
+// direction E = -i dt dH/dtheta_p, the top block of
+// exp([[A, E], [0, A]]) [0; v] (Van Loan 1978), evaluated with the same
+// Taylor routine on the doubled system.
+// ---------------------------------------------------------------------------
+
+// Matrix elements of dH/dtheta_p between s and the states it couples to.
+// Edges count whenever the lattice has them, whatever the parameter's
+// value, so the derivative also exists at a parameter equal to zero.
+void dH_entries(const Model& m, const State& s, int p,
+                std::vector<std::pair<State, double>>& out) {
+  out.clear();
+  const int nJ = m.ndim, nG = m.V, nW = m.V;
+  if (p < nJ) {  // J along axis p: 1 on both hops of that axis
+    for (int dir = 0; dir < 2; ++dir) {
+      const int jn = m.nbr[s.j * 2 * m.ndim + 2 * p + dir];
+      if (jn < 0) continue;
+      State t = s;
+      t.j = jn;
+      out.push_back({t, 1.0});
+    }
+    return;
+  }
+  p -= nJ;
+  if (p < nG) {  // g_nu: sqrt(n) / sqrt(n+1) on the e-ph slots of mode nu
+    const int n = s.n[s.j * m.V + p];
+    if (n > 0) {
+      State t = s;
+      t.n[s.j * m.V + p] = n - 1;
+      out.push_back({t, std::sqrt(double(n))});
+    }
+    if (n < m.cut[p]) {
+      State t = s;
+      t.n[s.j * m.V + p] = n + 1;
+      out.push_back({t, std::sqrt(double(n + 1))});
+    }
+    return;
+  }
+  p -= nG;
+  if (p < nW) {  // omega_nu: total occupation T_nu on the diagonal
+    long T = 0;
+    for (int i = 0; i < m.N; ++i) T += s.n[i * m.V + p];
+    if (T) out.push_back({s, double(T)});
+    return;
+  }
+  p -= nW;  // eps_p: 1 on the diagonal of rows with the exciton at site p
+  if (s.j == p) out.push_back({s, 1.0});
+}
+
+int num_params(const Model& m) { return m.ndim + 2 * m.V + m.N; }
+
+// CSR of dH/dtheta_p over the sorted set S.
+void build_dH(const Model& m, const Keys& S, int p, CSR& E) {
+  const int64_t n = S.size();
+  E.n = n;
+  E.rowptr.assign(n + 1, 0);
+  E.cols.clear();
+  E.vals.clear();
+  std::vector<std::pair<State, double>> ent;
+  std::vector<uint64_t> key(m.W);
+  for (int64_t i = 0; i < n; ++i) {
+    State s;
+    decode(m, S.at(i), s);
+    dH_entries(m, s, p, ent);
+    std::vector<std::pair<int64_t, double>> row;
+    for (auto& e : ent) {
+      encode(m, e.first, key.data());
+      const int64_t c = find_key(S, key.data());
+      if (c >= 0) row.push_back({c, e.second});
+    }
+    std::sort(row.begin(), row.end());
+    for (auto& e : row) {
+      E.cols.push_back(e.first);
+      E.vals.push_back(e.second);
+    }
+    E.rowptr[i + 1] = int64_t(E.cols.size());
+  }
+}
+
+// (dU/dtheta_p) v for U = exp(-i H dt): top block of exp(-i dt [[H, E],
+// [0, H]]) [0; v].  The doubled matrix is block triangular, so its
+// spectrum is that of H and H's bounds serve the series' shift.
+int frechet_apply(const CSR& H, const CSR& E, double dt, int max_terms,
+                  const std::vector<cplx>& v, std::vector<cplx>& out) {
+  const int64_t n = H.n;
+  CSR B;
+  B.n = 2 * n;
+  B.rowptr.assign(2 * n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t e = H.rowptr[i]; e < H.rowptr[i + 1]; ++e) {
+      B.cols.push_back(H.cols[e]);
+      B.vals.push_back(H.vals[e]);
+    }
+    for (int64_t e = E.rowptr[i]; e < E.rowptr[i + 1]; ++e) {
+      B.cols.push_back(n + E.cols[e]);
+      B.vals.push_back(E.vals[e]);
+    }
+    B.rowptr[i + 1] = int64_t(B.cols.size());
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t e = H.rowptr[i]; e < H.rowptr[i + 1]; ++e) {
+      B.cols.push_back(n + H.cols[e]);
+      B.vals.push_back(H.vals[e]);
+    }
+    B.rowptr[n + i + 1] = int64_t(B.cols.size());
+  }
+  B.emin = H.emin;
+  B.emax = H.emax;
+  std::vector<cplx> w(2 * n, cplx(0, 0)), r;
+  for (int64_t i = 0; i < n; ++i) w[n + i] = v[i];
+  int terms = 0;
+  if (expmv(B, dt, max_terms, w, r, terms)) return 1;
+  out.assign(r.begin(), r.begin() + n);
+  return 0;
+}
+
+// A recorded run: the initial state and the set of every step.
+struct Frozen {
+  const Model* m = nullptr;
+  Params p;
+  Keys S0;                   // sorted support of psi0
+  std::vector<cplx> psi0;    // aligned with S0
+  std::vector<Keys> S;       // S[s] = set after step s+1
+};
+
+bool same_shape(const Model& a, const Model& b) {
+  if (a.ndim != b.ndim || a.N != b.N || a.V != b.V) return false;
+  for (int x = 0; x < 3; ++x)
+    if (a.ext[x] != b.ext[x] || a.per[x] != b.per[x]) return false;
+  for (int nu = 0; nu < a.V; ++nu)
+    if (a.cut[nu] != b.cut[nu]) return false;
+  return true;
+}
+
+// v on set `from` restricted to set `to` (both sorted).
+std::vector<cplx> restrict_to(const Keys& from, const std::vector<cplx>& v,
+                              const Keys& to) {
+  std::vector<cplx> r(to.size(), cplx(0, 0));
+  for (int64_t i = 0; i < from.size(); ++i) {
+    const int64_t k = find_key(to, from.at(i));
+    if (k >= 0) r[k] = v[i];
+  }
+  return r;
+}
+
+cplx overlap0(const Frozen& f, const Keys& S, const std::vector<cplx>& v) {
+  cplx a(0, 0);
+  for (int64_t i = 0; i < f.S0.size(); ++i) {
+    const int64_t r = find_key(S, f.S0.at(i));
+    if (r >= 0) a += std::conj(f.psi0[i]) * v[r];
+  }
+  return a;
+}
+
+// Replay of the recorded sets with model m: a[0..n] and, if wanted, every
+// psi_s.
+int frozen_forward(const Frozen& f, const Model& m, std::vector<cplx>& a,
+                   std::vector<std::vector<cplx>>* states) {
+  const int64_t n = int64_t(f.S.size());
+  a.assign(n + 1, cplx(0, 0));
+  std::vector<cplx> psi = f.psi0;
+  a[0] = overlap0(f, f.S0, psi);
+  if (states) states->assign(1, psi);
+  const Keys* prev = &f.S0;
+  for (int64_t s = 0; s < n; ++s) {
+    std::vector<cplx> phi = restrict_to(*prev, psi, f.S[s]);
+    CSR H;
+    build_csr(m, f.S[s], H);
+    int terms = 0;
+    if (expmv(H, f.p.dt, f.p.max_terms, phi, psi, terms)) return 1;
+    a[s + 1] = overlap0(f, f.S[s], psi);
+    if (states) states->push_back(psi);
+    prev = &f.S[s];
+  }
+  return 0;
+}
+
+int frozen_gradient(const Frozen& f, const Model& m,
+                    const std::vector<cplx>& gbar, std::vector<cplx>& a,
+                    std::vector<double>& grad) {
+  std::vector<std::vector<cplx>> psi;
+  if (frozen_forward(f, m, a, &psi)) return 1;
+  const int64_t n = int64_t(f.S.size());
+  const int P = num_params(m);
+  grad.assign(P, 0.0);
+  // lambda_n = gbar_n psi0 on S_n
+  auto psi0_on = [&](const Keys& S, cplx c) {
+    std::vector<cplx> r = restrict_to(f.S0, f.psi0, S);
+    for (auto& z : r) z *= c;
+    return r;
+  };
+  const Keys& last = n ? f.S[n - 1] : f.S0;
+  std::vector<cplx> lam = psi0_on(last, gbar[n]);
+  for (int64_t s = n - 1; s >= 0; --s) {
+    const Keys& from = s ? f.S[s - 1] : f.S0;
+    const Keys& to = f.S[s];
+    const std::vector<cplx> phi = restrict_to(from, psi[s], to);
+    CSR H;
+    build_csr(m, to, H);
+    for (int p = 0; p < P; ++p) {
+      CSR E;
+      build_dH(m, to, p, E);
+      std::vector<cplx> x;
+      if (frechet_apply(H, E, f.p.dt, f.p.max_terms, phi, x)) return 1;
+      cplx ip(0, 0);
+      for (int64_t i = 0; i < to.size(); ++i) ip += std::conj(lam[i]) * x[i];
+      grad[p] += 2.0 * ip.real();
+    }
+    // mu = U^dag lambda = conj(U conj(lambda)) since H is real
+    std::vector<cplx> cl(lam.size()), mu;
+    for (size_t i = 0; i < lam.size(); ++i) cl[i] = std::conj(lam[i]);
+    int terms = 0;
+    if (expmv(H, f.p.dt, f.p.max_terms, cl, mu, terms)) return 1;
+    for (auto& z : mu) z = std::conj(z);
+    // lambda_s = T_s^T mu + gbar_s psi0 on S_s
+    std::vector<cplx> back(from.size(), cplx(0, 0));
+    for (int64_t i = 0; i < from.size(); ++i) {
+      const int64_t k = find_key(to, from.at(i));
+      if (k >= 0) back[i] = mu[k];
+    }
+    std::vector<cplx> add = psi0_on(from, gbar[s]);
+    for (int64_t i = 0; i < from.size(); ++i) back[i] += add[i];
+    lam.swap(back);
+  }
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -890,6 +1130,88 @@ int orc_expmv(int64_t n, const int64_t* rowptr, const int64_t* cols,
     v_out[2 * i + 1] = out[i].imag();
   }
   if (terms) *terms = t;
+  return 0;
+}
+
+int orc_frozen_record(const void* mp, const orc_params* p, int64_t n,
+                      const int32_t* exc, const uint16_t* occ,
+                      const double* coef, int64_t n_steps, void** out) {
+  if (!mp || !out || n_steps < 0) return fail("bad arguments");
+  void* sp = nullptr;
+  if (orc_sim_create(mp, p, n, exc, occ, coef, &sp)) return 1;
+  Sim* sim = static_cast<Sim*>(sp);
+  Frozen* f = new Frozen();
+  f->m = sim->m;
+  f->p = sim->p;
+  f->S0 = sim->S;
+  f->psi0 = sim->psi;
+  for (int64_t s = 0; s < n_steps; ++s) {
+    if (sim_step(*sim)) {
+      delete sim;
+      delete f;
+      return 1;
+    }
+    f->S.push_back(sim->S);
+  }
+  delete sim;
+  *out = f;
+  return 0;
+}
+
+void orc_frozen_destroy(void* f) { delete static_cast<Frozen*>(f); }
+
+int orc_frozen_info(const void* fp, int64_t* n_steps, int32_t* n_params,
+                    int64_t* sizes) {
+  const Frozen* f = static_cast<const Frozen*>(fp);
+  if (!f) return fail("null argument");
+  if (n_steps) *n_steps = int64_t(f->S.size());
+  if (n_params) *n_params = num_params(*f->m);
+  if (sizes) {
+    sizes[0] = f->S0.size();
+    for (size_t s = 0; s < f->S.size(); ++s) sizes[s + 1] = f->S[s].size();
+  }
+  return 0;
+}
+
+int orc_frozen_get_set(const void* fp, int64_t step, uint64_t* keys) {
+  const Frozen* f = static_cast<const Frozen*>(fp);
+  if (!f || step < 0 || step > int64_t(f->S.size())) return fail("bad step");
+  const Keys& k = step ? f->S[step - 1] : f->S0;
+  std::copy(k.d.begin(), k.d.end(), keys);
+  return 0;
+}
+
+int orc_frozen_eval(const void* fp, const void* mp, double* a_out) {
+  const Frozen* f = static_cast<const Frozen*>(fp);
+  const Model* m = static_cast<const Model*>(mp);
+  if (!f || !m || !a_out) return fail("null argument");
+  if (!same_shape(*f->m, *m)) return fail("model shape differs from the record");
+  std::vector<cplx> a;
+  if (frozen_forward(*f, *m, a, nullptr)) return 1;
+  for (size_t s = 0; s < a.size(); ++s) {
+    a_out[2 * s] = a[s].real();
+    a_out[2 * s + 1] = a[s].imag();
+  }
+  return 0;
+}
+
+int orc_frozen_grad(const void* fp, const void* mp, const double* gbar,
+                    double* a_out, double* grad) {
+  const Frozen* f = static_cast<const Frozen*>(fp);
+  const Model* m = static_cast<const Model*>(mp);
+  if (!f || !m || !gbar || !grad) return fail("null argument");
+  if (!same_shape(*f->m, *m)) return fail("model shape differs from the record");
+  const size_t n = f->S.size() + 1;
+  std::vector<cplx> gb(n), a;
+  for (size_t s = 0; s < n; ++s) gb[s] = cplx(gbar[2 * s], gbar[2 * s + 1]);
+  std::vector<double> g;
+  if (frozen_gradient(*f, *m, gb, a, g)) return 1;
+  if (a_out)
+    for (size_t s = 0; s < n; ++s) {
+      a_out[2 * s] = a[s].real();
+      a_out[2 * s + 1] = a[s].imag();
+    }
+  std::copy(g.begin(), g.end(), grad);
   return 0;
 }
 

@@ -118,6 +118,27 @@ int orc_expmv(int64_t n, const int64_t* rowptr, const int64_t* cols,
               int32_t max_terms, const double* v_in, double* v_out,
               int32_t* terms);
 
+/* Adjoint gradient on a frozen sequence of sets (Form (3)).
+ * orc_frozen_record runs n_steps ordinary steps from the initial state and
+ * keeps S_0 (the support of psi0) and the set of every step.  With those
+ * sets held fixed, orc_frozen_eval replays the run with any model of the
+ * same shape and returns a[s] = <psi0|psi_s>, s = 0..n_steps, interleaved
+ * (re, im); orc_frozen_grad also returns, for gbar[s] = dL/d conj(a_s) of a
+ * real loss L, grad[p] = dL/dtheta_p with theta = (J per axis, g per mode,
+ * omega per mode, eps per site). */
+int orc_frozen_record(const void* m, const orc_params* p, int64_t n,
+                      const int32_t* exc, const uint16_t* occ,
+                      const double* coef, int64_t n_steps, void** out);
+void orc_frozen_destroy(void* f);
+/* sizes[n_steps + 1]: |S_0| .. |S_n| (may be NULL). */
+int orc_frozen_info(const void* f, int64_t* n_steps, int32_t* n_params,
+                    int64_t* sizes);
+/* Sorted keys of S_step. */
+int orc_frozen_get_set(const void* f, int64_t step, uint64_t* keys);
+int orc_frozen_eval(const void* f, const void* m, double* a);
+int orc_frozen_grad(const void* f, const void* m, const double* gbar,
+                    double* a, double* grad);
+
 #ifdef __cplusplus
 }
 #endif
