@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define PACES_ABI_VERSION 2
+#define PACES_ABI_VERSION 3
 
 typedef enum {
   PACES_OK = 0,
@@ -218,6 +218,30 @@ paces_status paces_profile_enable(paces_sim* s, int32_t on);
 paces_status paces_profile_get(paces_sim* s, paces_profile* out,
                                void* hip_stream);
 paces_status paces_profile_reset(paces_sim* s);
+
+/* Launch tuning.  Results do not depend on it: per-key amplitudes, sets
+ * and counts are identical for every setting (sums only to rounding of
+ * their reduction order). */
+typedef struct {
+  int32_t graph;       /* 1: capture each step's launch sequence once as a
+                          HIP graph and replay it (graphs are keyed by
+                          bucketed sizes and rebuilt when buffers move);
+                          ignored while profiling is enabled              */
+  int32_t table_shift; /* hash table probed over >= est * 2^shift entries
+                          (1..3; load factor at most 2^-shift)            */
+  int32_t term_rows;   /* rows per thread of the Clenshaw grid: 1,2,4,8  */
+} paces_tuning;
+/* Default {0, 1, 1}. */
+paces_status paces_get_tuning(paces_sim* s, paces_tuning* out);
+/* May reallocate the hash table (synchronises). */
+paces_status paces_set_tuning(paces_sim* s, const paces_tuning* t,
+                              void* hip_stream);
+/* Time 1 + steps trial steps from the current state for each setting of
+ * {graph 0/1} x {table_shift 1, 2} x {term_rows 1, 2, 4}, keep the fastest,
+ * and restore the state as it was (records of the trials are discarded;
+ * the sets of the last step are no longer available).  steps 1..64. */
+paces_status paces_autotune(paces_sim* s, int32_t steps, paces_tuning* chosen,
+                            void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -34,7 +34,8 @@ EXPORTS = [
     "paces_free_sim", "paces_step", "paces_observe", "paces_num_records",
     "paces_series", "paces_get_state", "paces_set_state", "paces_get_set",
     "paces_get_phi", "paces_profile_enable", "paces_profile_get",
-    "paces_profile_reset",
+    "paces_profile_reset", "paces_get_tuning", "paces_set_tuning",
+    "paces_autotune",
 ]
 
 
@@ -71,6 +72,11 @@ class _Obs(C.Structure):
 class _Profile(C.Structure):
     _fields_ = [("ms", C.c_double * 7), ("launches", C.c_int64 * 7),
                 ("term_bytes", C.c_double), ("rows_steps", C.c_double)]
+
+
+class _Tuning(C.Structure):
+    _fields_ = [("graph", C.c_int32), ("table_shift", C.c_int32),
+                ("term_rows", C.c_int32)]
 
 
 _lib = None
@@ -313,3 +319,27 @@ class Sim:
         return {"ms": dict(zip(STAGES, list(p.ms))),
                 "launches": dict(zip(STAGES, list(p.launches))),
                 "term_bytes": p.term_bytes, "rows_steps": p.rows_steps}
+
+    def tuning(self):
+        t = _Tuning()
+        _check(lib().paces_get_tuning(self.h, C.byref(t)))
+        return {"graph": t.graph, "table_shift": t.table_shift,
+                "term_rows": t.term_rows}
+
+    def set_tuning(self, graph=None, table_shift=None, term_rows=None,
+                   stream=None):
+        cur = self.tuning()
+        t = _Tuning()
+        t.graph = cur["graph"] if graph is None else int(graph)
+        t.table_shift = cur["table_shift"] if table_shift is None else table_shift
+        t.term_rows = cur["term_rows"] if term_rows is None else term_rows
+        _check(lib().paces_set_tuning(self.h, C.byref(t), _stream(stream)))
+
+    def autotune(self, steps=3, stream=None):
+        """Pick the fastest launch tuning on trial steps from the current
+        state; the state is left as it was.  Returns the chosen tuning."""
+        t = _Tuning()
+        _check(lib().paces_autotune(self.h, C.c_int32(steps), C.byref(t),
+                                    _stream(stream)))
+        return {"graph": t.graph, "table_shift": t.table_shift,
+                "term_rows": t.term_rows}

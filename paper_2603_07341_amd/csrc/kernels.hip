@@ -32,116 +32,12 @@
 #include <algorithm>
 #include <cmath>
 
+#include "common.hpp"
 #include "kernels.hpp"
 
 namespace paces {
 
 namespace {
-
-constexpr int kItems = 8;
-constexpr int kTile = kBlock * kItems;
-constexpr int kMaxGrid = kMaxPartials;
-constexpr int kFold = 256;  // blocks of the second reduction level
-
-__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) {
-  return (a + b - 1) / b;
-}
-
-// Grid for a grid-stride kernel over at most `bound` items.
-inline int grid_for(int64_t bound, int64_t cap = kMaxGrid) {
-  int64_t g = cdiv(bound, kBlock);
-  if (g < 1) g = 1;
-  if (g > cap) g = cap;
-  return int(g);
-}
-// Grid for a kernel striding over tiles of kTile items.
-inline int tiles_for(int64_t bound) {
-  int64_t g = cdiv(bound, kTile);
-  if (g < 1) g = 1;
-  if (g > 2048) g = 2048;
-  return int(g);
-}
-
-__device__ __forceinline__ int64_t gtid() {
-  return int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-}
-__device__ __forceinline__ int64_t gstride() {
-  return int64_t(gridDim.x) * blockDim.x;
-}
-
-// ---- deterministic block reductions ---------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-  return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
-}
-// Sum over the block; every lane gets the result.
-__device__ __forceinline__ double block_sum(double v) {
-  __shared__ double s[kBlock / 64];
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) s[wid] = v;
-  __syncthreads();
-  double r = 0;
-  for (int w = 0; w < kBlock / 64; ++w) r += s[w];
-  return r;
-}
-__device__ __forceinline__ double block_min(double v) {
-  __shared__ double s[kBlock / 64];
-  v = wave_min(v);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) s[wid] = v;
-  __syncthreads();
-  double r = s[0];
-  for (int w = 1; w < kBlock / 64; ++w) r = fmin(r, s[w]);
-  return r;
-}
-__device__ __forceinline__ double block_max(double v) {
-  __shared__ double s[kBlock / 64];
-  v = wave_max(v);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) s[wid] = v;
-  __syncthreads();
-  double r = s[0];
-  for (int w = 1; w < kBlock / 64; ++w) r = fmax(r, s[w]);
-  return r;
-}
-
-// Exclusive scan over the block of one u32 per lane; total to *tot.
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v,
-                                                    uint32_t* tot) {
-  __shared__ uint32_t s[kBlock / 64];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  uint32_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
-  __syncthreads();
-  if (lane == 63) s[wid] = x;
-  __syncthreads();
-  uint32_t base = 0, all = 0;
-  for (int w = 0; w < kBlock / 64; ++w) {
-    if (w < wid) base += s[w];
-    all += s[w];
-  }
-  *tot = all;
-  return base + x - v;
-}
 
 // ---- fills and step control -------------------------------------------------
 __global__ void __launch_bounds__(kBlock)
@@ -577,7 +473,7 @@ __global__ void __launch_bounds__(kBlock)
     k_transfer(DevModel m, const uint64_t* keys_o, const Amp* psi_o,
                const StepCtl* ctl, const uint64_t* table, uint64_t mask,
                const uint64_t* keys_n, Amp* phi, double* mass_part,
-               const int* err) {
+               int32_t* tmap, const int* err) {
   __shared__ double bins[kMaxReal];
   if (*err) return;
   const int R = m.R;
@@ -592,6 +488,7 @@ __global__ void __launch_bounds__(kBlock)
     load_key<W>(keys_o, i, k);
     const int64_t r = table_find<W>(table, mask, keys_n, k, key_hash<W>(m, k));
     const Amp v = psi_o[i];
+    if (tmap) tmap[i] = int32_t(r);
     if (r >= 0)
       phi[r] = v;
     else if (R > 1)
@@ -666,46 +563,6 @@ __global__ void __launch_bounds__(kBlock)
       part[2 * blockIdx.x + 1] = hi;
     }
   }
-}
-
-// J_k(x) by its power series sum_j (-1)^j (x/2)^(2j+k) / (j! (j+k)!); for
-// x <= 2 every term shrinks and no cancellation occurs.
-__device__ double bessel_series(double x, int k) {
-  const double h = 0.5 * x, h2 = h * h;
-  double lead = 1.0;
-  for (int q = 1; q <= k; ++q) lead *= h / q;
-  if (lead == 0.0) return 0.0;
-  double term = lead, sum = lead;
-  for (int j = 1; j < 60; ++j) {
-    term *= -h2 / (double(j) * double(j + k));
-    sum += term;
-    if (fabs(term) <= 1e-18 * fabs(sum)) break;
-  }
-  return sum;
-}
-
-// J_0..J_kmax for x > 2: Miller's backward recurrence normalised by
-// J_0 + 2 sum_k J_2k = 1 (Miller 1952; Abramowitz & Stegun 9.12).
-__device__ void bessel_miller(double x, int kmax, double* out) {
-  int start = kmax > int(x) ? kmax : int(x);
-  start += 20 + int(sqrt(40.0 * start));
-  start += start & 1;
-  double fp1 = 0.0, f = 1e-280, norm = 0.0;
-  for (int k = 0; k <= kmax; ++k) out[k] = 0.0;
-  for (int k = start; k >= 0; --k) {
-    if (k <= kmax) out[k] = f;
-    if ((k & 1) == 0) norm += (k == 0 ? 1.0 : 2.0) * f;
-    const double fm1 = (k > 0) ? (2.0 * k / x) * f - fp1 : 0.0;
-    fp1 = f;
-    f = fm1;
-    if (fabs(f) > 1e250) {
-      f *= 1e-250;
-      fp1 *= 1e-250;
-      norm *= 1e-250;
-      for (int q = k; q <= kmax; ++q) out[q] *= 1e-250;
-    }
-  }
-  for (int k = 0; k <= kmax; ++k) out[k] /= norm;
 }
 
 // One block per realization: fold the per-block bounds, pad them, and
@@ -1089,7 +946,7 @@ __global__ void __launch_bounds__(kBlock)
     k_autocorr(DevModel m, const uint64_t* keys0, const double* amps0,
                int64_t n0, const uint64_t* table, uint64_t mask,
                const uint64_t* keys, const Amp* psi, double* out2,
-               const int* err) {
+               int32_t* p0map, const int* err) {
   if (*err) return;
   const int64_t base = int64_t(blockIdx.x) * n0;
   double re = 0, im = 0;
@@ -1097,6 +954,7 @@ __global__ void __launch_bounds__(kBlock)
     uint64_t k[W];
     load_key<W>(keys0, i, k);
     const int64_t r = table_find<W>(table, mask, keys, k, key_hash<W>(m, k));
+    if (p0map) p0map[i] = int32_t(r);
     if (r < 0) continue;
     const double2 v = widen(psi[r]);
     const double ar = amps0[2 * i], ai = amps0[2 * i + 1];
@@ -1340,16 +1198,17 @@ int part_grid(int64_t rows) { return grid_for(rows); }
 int transfer(const DevModel& m, int Wi, int prec, const Side& o,
              const void* psi_o, int64_t n_old, const StepCtl* ctl,
              const uint64_t* table, uint64_t mask, const uint64_t* keys_n,
-             void* phi, double* mass_part, int* err, hipStream_t s) {
+             void* phi, double* mass_part, int32_t* tmap, int* err,
+             hipStream_t s) {
   const int g = m.R > 1 ? std::min(grid_for(n_old), kPartBlocks) : grid_for(n_old);
   if (prec == 64) {
     PACES_DISPATCH_W(Wi, k_transfer<WW, double2><<<g, kBlock, 0, s>>>(
                              m, o.keys, (const double2*)psi_o, ctl, table, mask,
-                             keys_n, (double2*)phi, mass_part, err));
+                             keys_n, (double2*)phi, mass_part, tmap, err));
   } else {
     PACES_DISPATCH_W(Wi, k_transfer<WW, float2><<<g, kBlock, 0, s>>>(
                              m, o.keys, (const float2*)psi_o, ctl, table, mask,
-                             keys_n, (float2*)phi, mass_part, err));
+                             keys_n, (float2*)phi, mass_part, tmap, err));
   }
   return g;
 }
@@ -1428,15 +1287,15 @@ int pop_norm(int prec, int N, int R, double th2, int64_t est,
 void autocorr(const DevModel& m, int Wi, int prec, const uint64_t* keys0,
               const double* amps0, int64_t n0, const uint64_t* table,
               uint64_t mask, const uint64_t* keys, const void* psi,
-              double* out2, int* err, hipStream_t s) {
+              double* out2, int32_t* p0map, int* err, hipStream_t s) {
   if (prec == 64) {
     PACES_DISPATCH_W(Wi, k_autocorr<WW, double2><<<m.R, kBlock, 0, s>>>(
                              m, keys0, amps0, n0, table, mask, keys,
-                             (const double2*)psi, out2, err));
+                             (const double2*)psi, out2, p0map, err));
   } else {
     PACES_DISPATCH_W(Wi, k_autocorr<WW, float2><<<m.R, kBlock, 0, s>>>(
                              m, keys0, amps0, n0, table, mask, keys,
-                             (const float2*)psi, out2, err));
+                             (const float2*)psi, out2, p0map, err));
   }
 }
 

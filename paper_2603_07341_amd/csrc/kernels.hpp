@@ -99,11 +99,13 @@ void lookup_last(const DevModel& m, int Wi, const Side& n, int k,
                  hipStream_t s);
 // Number of per-block partials written by a kernel over `rows` rows.
 int part_grid(int64_t rows);
-// Returns the number of mass partials written.
+// Returns the number of mass partials written.  tmap (may be null) gets
+// the new row of every old row, -1 if dropped.
 int transfer(const DevModel& m, int Wi, int prec, const Side& o,
              const void* psi_o, int64_t n_old, const StepCtl* ctl,
              const uint64_t* table, uint64_t mask, const uint64_t* keys_n,
-             void* phi, double* mass_part, int* err, hipStream_t s);
+             void* phi, double* mass_part, int32_t* tmap, int* err,
+             hipStream_t s);
 // Gershgorin bounds + Chebyshev coefficients per realization (cc[R]);
 // latches if some K_r exceeds the launches enqueued.
 void bounds_and_coef(const DevModel& m, const Side& n, const int32_t* col,
@@ -128,10 +130,12 @@ int pop_norm(int prec, int N, int R, double th2, int64_t est,
              const double* e_row, double* n2_part, double* en_part,
              double* pop_part, uint32_t* sel_bsum, uint32_t* cnt_s, int* err,
              hipStream_t s);
+// <psi0|psi> per realization; p0map (may be null) gets the row of every
+// initial state, -1 if absent.
 void autocorr(const DevModel& m, int Wi, int prec, const uint64_t* keys0,
               const double* amps0, int64_t n0, const uint64_t* table,
               uint64_t mask, const uint64_t* keys, const void* psi,
-              double* out2, int* err, hipStream_t s);
+              double* out2, int32_t* p0map, int* err, hipStream_t s);
 // Commit a successful step on the device: time, discarded weight per
 // realization, record count and the row count of the current set.
 void end_step(StepCtl* ctl, int R, const double* ring, int rec_doubles,

@@ -8,9 +8,11 @@
 //   select -> insert M -> k expansion rounds (+ lookup pass of the last
 //   frontier) -> transfer -> bounds and coefficients -> Clenshaw terms ->
 //   observables.
-// The host reads back the few counts it needs to size the next launch (nM,
-// new rows per chunk, the number of series terms); everything else stays on
-// the device.
+// Sizes live on the device; the host enqueues a whole step, reads the
+// counts and the error latch once, and repeats the step with more room if
+// a capacity was exceeded.  A step's launch sequence can be captured once
+// as a HIP graph and replayed (grid sizes are bucketed so consecutive steps
+// share a graph).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -251,6 +253,18 @@ struct paces_sim {
   bool prof = false;
   std::vector<EventPair> pending, events;
   paces_profile acc{};
+
+  // launch tuning and captured step graphs
+  paces_tuning tune{0, 1, 1};
+  hipStream_t cap_stream = nullptr;  // capture only; never runs work
+  uint64_t gen = 0;                  // bumped whenever a buffer moves
+  struct GraphEntry {
+    std::vector<int64_t> key;
+    hipGraphExec_t exec;
+    uint64_t used;
+  };
+  std::vector<GraphEntry> graphs;
+  uint64_t graph_clock = 0;
 };
 
 namespace {
@@ -322,10 +336,26 @@ void free_cand(paces_sim* s) {
   s->rb.cand_cap = 0;
 }
 
-uint64_t table_size_for(int64_t cap) {
+uint64_t table_size_for(int64_t cap, int shift) {
   uint64_t P = 1024;
-  while (P < uint64_t(2 * cap)) P <<= 1;
+  while (P < (uint64_t(cap) << shift)) P <<= 1;
   return P;
+}
+
+// Round a row count up to a quarter octave (4, 5, 6 or 7 times a power of
+// two): launch grids sized from bucketed counts repeat from step to step,
+// so captured graphs can be replayed.
+int64_t bucket(int64_t x) {
+  if (x <= 64) return 64;
+  int e = 0;
+  while ((x >> e) > 7) ++e;
+  int64_t m = (x + (int64_t(1) << e) - 1) >> e;  // 4..8
+  return m << e;
+}
+
+void drop_graphs(paces_sim* s) {
+  for (auto& g : s->graphs) (void)hipGraphExecDestroy(g.exec);
+  s->graphs.clear();
 }
 
 // Reallocate every row array for new_cap rows, keeping the current set
@@ -333,6 +363,8 @@ uint64_t table_size_for(int64_t cap) {
 // by the next step.
 paces_status grow(paces_sim* s, int64_t new_cap, hipStream_t st) {
   const paces_model* m = s->m;
+  drop_graphs(s);
+  ++s->gen;
   new_cap = std::min<int64_t>((new_cap + 255) / 256 * 256, (int64_t(1) << 31) - 256);
   if (new_cap <= s->cap && s->cap > 0)
     return fail(PACES_E_CAPACITY, "row capacity limit (2^31 rows) reached");
@@ -380,7 +412,7 @@ paces_status grow(paces_sim* s, int64_t new_cap, hipStream_t st) {
                            hipMemcpyDeviceToDevice, st));
   }
   ST_TRY(dalloc(&s->col, new_cap * m->D));
-  const uint64_t P = table_size_for(new_cap);
+  const uint64_t P = table_size_for(new_cap, s->tune.table_shift);
   ST_TRY(dalloc(&s->table, int64_t(P)));
   s->tmask_alloc = P - 1;
   s->tmask = P - 1;
@@ -415,6 +447,8 @@ paces_status grow(paces_sim* s, int64_t new_cap, hipStream_t st) {
 }
 
 paces_status grow_cand(paces_sim* s, hipStream_t st) {
+  drop_graphs(s);
+  ++s->gen;
   const int64_t want =
       std::min<int64_t>(2 * s->rb.cand_cap, (int64_t(1) << 31) - 1);
   if (want <= s->rb.cand_cap)
@@ -442,6 +476,8 @@ paces_status ensure_ring(paces_sim* s, hipStream_t st) {
     HIP_TRY(hipMemcpyAsync(r, s->ring, size_t(s->h.nrec) * per_step * 8,
                            hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
+  drop_graphs(s);
+  ++s->gen;
   dfree(s->ring);
   s->ring = r;
   s->ring_cap = nc;
@@ -496,7 +532,7 @@ void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st) {
   {
     Stage sg(s, PACES_STAGE_SELECT, st);
     select_rows(s->prec, s->vec[s->ipsi], s->th2, s->fresh, counted, s->ctl,
-                s->midx, s->scan_tmp, std::max<int64_t>(s->nS, 1), s->err,
+                s->midx, s->scan_tmp, std::min(bucket(s->nS), s->cap), s->err,
                 st);
   }
   {
@@ -513,9 +549,10 @@ void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st) {
   int n_mass = 0, n_e = 0;
   {
     Stage sg(s, PACES_STAGE_TRANSFER, st);
-    const int np = transfer(dm, Wi, s->prec, so, s->vec[s->ipsi], s->nS,
-                            s->ctl, s->table, s->tmask, sn.keys,
-                            s->vec[s->iphi], s->mass_part, s->err, st);
+    const int np = transfer(dm, Wi, s->prec, so, s->vec[s->ipsi],
+                            bucket(s->nS), s->ctl, s->table, s->tmask, sn.keys,
+                            s->vec[s->iphi], s->mass_part, nullptr, s->err,
+                            st);
     n_mass = R == 1 ? fold_sum(s->mass_part, np, s->mass_fold, s->err, st) : np;
   }
   {
@@ -531,7 +568,9 @@ void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st) {
     for (int kk = s->launched - 1; kk >= 0; --kk) {
       Stage tg(s, PACES_STAGE_TERM, st, kk);
       const bool mid = s->K_last >= 4 && kk >= 1 && kk <= s->K_last - 3;
-      np = cheb_term(dm, s->prec, kk, want_e, mid, est, s->ctl, s->col, s->cap,
+      np = cheb_term(dm, s->prec, kk, want_e, mid,
+                     std::max<int64_t>(1, est / s->tune.term_rows), s->ctl,
+                     s->col, s->cap,
                      sn, s->cc, s->vec[s->iphi], s->vec[s->ib0],
                      s->vec[s->ib1], s->e_part, s->e_row, s->err, st);
     }
@@ -545,13 +584,55 @@ void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st) {
                                s->n2_part, s->en_part, s->pop_part,
                                s->scan_tmp, s->cnt + R, s->err, st);
     autocorr(dm, Wi, s->prec, s->keys0, s->amps0, s->n0, s->table, s->tmask,
-             sn.keys, s->vec[s->ib0], s->a2, s->err, st);
+             sn.keys, s->vec[s->ib0], s->a2, nullptr, s->err, st);
     obs_final(m->N, R, want_e ? 1 : 0, s->p.dt, n_mass, n_e, n_pop,
               R == 1 ? s->mass_fold : s->mass_part, s->n2_part, s->e_fold,
               s->en_part, s->pop_part, s->a2, s->cc, s->ctl, s->cnt,
               s->mass_tot, s->ring, s->rec_doubles, s->ring_cap, s->err, st);
     end_step(s->ctl, R, s->ring, s->rec_doubles, s->mass_tot, s->err, st);
   }
+}
+
+// Replay the captured graph of this step's launch sequence, capturing it
+// first if no graph matches.  Everything a launch takes from the host is in
+// the key; buffer moves bump s->gen (and drop every graph).
+paces_status launch_step_graph(paces_sim* s, int64_t est, bool counted,
+                               hipStream_t st) {
+  const std::vector<int64_t> key = {
+      int64_t(s->gen), s->cur, s->ipsi, s->iphi, s->ib0, s->ib1,
+      s->fresh ? 1 : 0, counted ? 1 : 0, s->fresh ? s->p.k_init : s->p.k,
+      s->launched, s->K_last, est, std::min(bucket(s->nS), s->cap),
+      int64_t(s->tmask), s->tune.term_rows};
+  for (auto& g : s->graphs)
+    if (g.key == key) {
+      g.used = ++s->graph_clock;
+      HIP_TRY(hipGraphLaunch(g.exec, st));
+      return PACES_OK;
+    }
+  if (!s->cap_stream)
+    HIP_TRY(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+  enqueue_step(s, est, counted, s->cap_stream);
+  hipGraph_t graph = nullptr;
+  HIP_TRY(hipStreamEndCapture(s->cap_stream, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess)
+    return fail(PACES_E_HIP, std::string("graph instantiation: ") +
+                                 hipGetErrorString(e));
+  if (s->graphs.size() >= 32) {
+    auto old = std::min_element(
+        s->graphs.begin(), s->graphs.end(),
+        [](const paces_sim::GraphEntry& a, const paces_sim::GraphEntry& b) {
+          return a.used < b.used;
+        });
+    (void)hipGraphExecDestroy(old->exec);
+    s->graphs.erase(old);
+  }
+  s->graphs.push_back({key, exec, ++s->graph_clock});
+  HIP_TRY(hipGraphLaunch(exec, st));
+  return PACES_OK;
 }
 
 // One step: enqueue, read back the counts, repeat with more room when a
@@ -562,17 +643,24 @@ paces_status do_step(paces_sim* s, hipStream_t st) {
   // the factor used here in the workloads; an overflow is caught anyway
   if (s->nS > s->cap / 2) ST_TRY(grow(s, 3 * s->nS, st));
   ST_TRY(ensure_ring(s, st));
-  const int64_t est =
-      std::min<int64_t>(s->cap, std::max<int64_t>(s->nS + s->nS / 2, s->nS + 65536));
-  // probe only as much of the table as the step needs (load factor <= 1/2
-  // for a new set up to 1.5x the old one); the table clear costs with it
+  const int64_t est = std::min<int64_t>(
+      s->cap, bucket(std::max<int64_t>(s->nS + s->nS / 2, s->nS + 65536)));
+  // probe only as much of the table as the step needs (load factor at most
+  // 2^-table_shift for a new set up to the estimate); the table clear
+  // costs with it
   {
     uint64_t P = 1024;
-    while (P < uint64_t(2 * est) && P <= s->tmask_alloc) P <<= 1;
+    while (P < (uint64_t(est) << s->tune.table_shift) && P <= s->tmask_alloc)
+      P <<= 1;
     s->tmask = std::min<uint64_t>(P - 1, s->tmask_alloc);
   }
+  const bool graph = s->tune.graph && !s->prof;
   for (int attempt = 0; attempt < 40; ++attempt) {
-    enqueue_step(s, est, s->counts_valid && attempt == 0, st);
+    const bool counted = s->counts_valid && attempt == 0;
+    if (graph && attempt == 0)
+      ST_TRY(launch_step_graph(s, est, counted, st));
+    else
+      enqueue_step(s, est, counted, st);
     HIP_TRY(hipMemcpyAsync(s->h_ctl, s->ctl, sizeof(StepCtl),
                            hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(s->h_err, s->err, sizeof(int), hipMemcpyDeviceToHost,
@@ -636,6 +724,107 @@ paces_status do_step(paces_sim* s, hipStream_t st) {
     return check_latch_code(s, e);
   }
   return fail(PACES_E_CAPACITY, "step did not fit after repeated growth");
+}
+
+// Copy of the current state and the host mirror, for trial steps.
+struct Snapshot {
+  int64_t n = 0;
+  uint64_t *keys = nullptr, *pay = nullptr, *tot = nullptr;
+  void* psi = nullptr;
+  double* mass_tot = nullptr;
+  StepCtl h{};
+  bool fresh = false;
+  int launched = 0, K_last = 0, k_last = 0;
+  ~Snapshot() {
+    dfree(keys);
+    dfree(pay);
+    dfree(tot);
+    if (psi) (void)hipFree(psi);
+    dfree(mass_tot);
+  }
+};
+
+paces_status take_snapshot(paces_sim* s, Snapshot& z, hipStream_t st) {
+  const paces_model* m = s->m;
+  const int64_t n = std::max<int64_t>(s->nS, 1);
+  ST_TRY(dalloc(&z.keys, n * m->Wi));
+  ST_TRY(dalloc(&z.pay, n));
+  ST_TRY(dalloc(&z.tot, n));
+  ST_TRY(dalloc(&z.mass_tot, m->R));
+  HIP_TRY(hipMalloc(&z.psi, size_t(n) * s->A));
+  const Side& c = s->side[s->cur];
+  z.n = s->nS;
+  if (s->nS > 0) {
+    HIP_TRY(hipMemcpyAsync(z.keys, c.keys, size_t(s->nS) * m->Wi * 8,
+                           hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(z.pay, c.pay, size_t(s->nS) * 8,
+                           hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(z.tot, c.tot, size_t(s->nS) * 8,
+                           hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(z.psi, s->vec[s->ipsi], size_t(s->nS) * s->A,
+                           hipMemcpyDeviceToDevice, st));
+  }
+  HIP_TRY(hipMemcpyAsync(z.mass_tot, s->mass_tot, size_t(m->R) * 8,
+                         hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  z.h = s->h;
+  z.fresh = s->fresh;
+  z.launched = s->launched;
+  z.K_last = s->K_last;
+  z.k_last = s->k_last;
+  return PACES_OK;
+}
+
+paces_status restore_snapshot(paces_sim* s, const Snapshot& z,
+                              hipStream_t st) {
+  const paces_model* m = s->m;
+  if (z.n > s->cap) ST_TRY(grow(s, 2 * z.n, st));
+  const Side& c = s->side[s->cur];
+  if (z.n > 0) {
+    HIP_TRY(hipMemcpyAsync(c.keys, z.keys, size_t(z.n) * m->Wi * 8,
+                           hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c.pay, z.pay, size_t(z.n) * 8,
+                           hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c.tot, z.tot, size_t(z.n) * 8,
+                           hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->vec[s->ipsi], z.psi, size_t(z.n) * s->A,
+                           hipMemcpyDeviceToDevice, st));
+  }
+  HIP_TRY(hipMemcpyAsync(s->mass_tot, z.mass_tot, size_t(m->R) * 8,
+                         hipMemcpyDeviceToDevice, st));
+  s->h = z.h;
+  s->nS = z.n;
+  s->fresh = z.fresh;
+  s->launched = z.launched;
+  s->K_last = z.K_last;
+  s->k_last = z.k_last;
+  s->have_sets = false;
+  s->counts_valid = false;
+  s->latched = 0;
+  return push_ctl(s, st);
+}
+
+// Resize the table for a new table_shift (keeps rows and amplitudes).
+paces_status resize_table(paces_sim* s, hipStream_t st) {
+  const uint64_t P = table_size_for(s->cap, s->tune.table_shift);
+  if (P - 1 == s->tmask_alloc) return PACES_OK;
+  HIP_TRY(hipStreamSynchronize(st));
+  drop_graphs(s);
+  ++s->gen;
+  dfree(s->table);
+  ST_TRY(dalloc(&s->table, int64_t(P)));
+  s->tmask_alloc = P - 1;
+  s->tmask = P - 1;
+  return PACES_OK;
+}
+
+paces_status check_tuning(const paces_tuning* t) {
+  if (!t || (t->graph != 0 && t->graph != 1) || t->table_shift < 1 ||
+      t->table_shift > 3 ||
+      (t->term_rows != 1 && t->term_rows != 2 && t->term_rows != 4 &&
+       t->term_rows != 8))
+    return fail(PACES_E_ARG, "bad tuning");
+  return PACES_OK;
 }
 
 // Device copies of the model tables, made on first use so that loading a
@@ -959,6 +1148,8 @@ paces_status paces_free_sim(paces_sim* s) {
   }
   if (s->h_ctl) (void)hipHostFree(s->h_ctl);
   if (s->h_err) (void)hipHostFree(s->h_err);
+  drop_graphs(s);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   delete s;
   return PACES_OK;
 }
@@ -1162,6 +1353,76 @@ paces_status paces_profile_reset(paces_sim* s) {
   if (!s) return fail(PACES_E_ARG, "bad arguments");
   paces_profile z{};
   s->acc = z;
+  return PACES_OK;
+}
+
+paces_status paces_get_tuning(paces_sim* s, paces_tuning* out) {
+  if (!s || !out) return fail(PACES_E_ARG, "bad arguments");
+  *out = s->tune;
+  return PACES_OK;
+}
+
+paces_status paces_set_tuning(paces_sim* s, const paces_tuning* t,
+                              void* hip_stream) {
+  if (!s) return fail(PACES_E_ARG, "bad arguments");
+  ST_TRY(check_tuning(t));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (t->term_rows != s->tune.term_rows || t->graph != s->tune.graph)
+    drop_graphs(s);
+  s->tune = *t;
+  return resize_table(s, st);
+}
+
+paces_status paces_autotune(paces_sim* s, int32_t steps, paces_tuning* chosen,
+                            void* hip_stream) {
+  if (!s || steps < 1 || steps > 64) return fail(PACES_E_ARG, "bad arguments");
+  if (s->latched) return fail(PACES_E_STATE, "sim is in an error state");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const bool prof = s->prof;
+  s->prof = false;
+  Snapshot z;
+  paces_status r = take_snapshot(s, z, st);
+  const paces_tuning start = s->tune;
+  paces_tuning best = start;
+  float best_ms = INFINITY;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (r == PACES_OK && (hipEventCreate(&a) != hipSuccess ||
+                        hipEventCreate(&b) != hipSuccess))
+    r = fail(PACES_E_HIP, "event creation failed");
+  for (int g = 0; g < 2 && r == PACES_OK; ++g)
+    for (int sh = 1; sh <= 2 && r == PACES_OK; ++sh)
+      for (int tr : {1, 2, 4}) {
+        paces_tuning t{g, sh, tr};
+        r = paces_set_tuning(s, &t, hip_stream);
+        if (r == PACES_OK) r = restore_snapshot(s, z, st);
+        // one untimed step (captures the graph), then the timed ones
+        if (r == PACES_OK) r = do_step(s, st);
+        if (r == PACES_OK && hipEventRecord(a, st) != hipSuccess)
+          r = fail(PACES_E_HIP, "event record failed");
+        for (int i = 0; i < steps && r == PACES_OK; ++i) r = do_step(s, st);
+        if (r != PACES_OK) break;
+        float ms = 0;
+        if (hipEventRecord(b, st) != hipSuccess ||
+            hipEventSynchronize(b) != hipSuccess ||
+            hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+          r = fail(PACES_E_HIP, "event timing failed");
+          break;
+        }
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = t;
+        }
+      }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (r == PACES_OK) r = paces_set_tuning(s, &best, hip_stream);
+  if (r == PACES_OK) r = restore_snapshot(s, z, st);
+  s->prof = prof;
+  if (r != PACES_OK) {
+    s->tune = start;
+    return r;
+  }
+  if (chosen) *chosen = best;
   return PACES_OK;
 }
 

@@ -1,0 +1,113 @@
+"""Launch tuning, graph replay and the autotuner leave results unchanged.
+
+A graph-replayed step runs the same kernels with the same launch shapes as
+an eager step, so states and records must agree bit for bit; other tunings
+change grids and probe lengths only, so sets and per-key amplitudes must
+agree bit for bit.  Graph replays are interleaved with eager work and
+synchronisations (state reads), and every replay is checked."""
+import numpy as np
+import pytest
+
+import paper_2603_07341_amd as P
+from tests.gpu_helpers import sort_rows
+import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+
+EXACT = [0, 7, 8, 9, 10, 11]  # t, n_S, n_M, K, E_min, E_max
+
+
+def sim_of(name, R=1, **over):
+    cfg = dict(WL.CONFIGS[name])
+    cfg.update(over)
+    params = WL.batch_params(cfg, R) if R > 1 else WL.model_params(cfg)
+    m = P.Model(params)
+    exc, occ, coef = WL.initial_state(cfg)
+    return m, P.Sim(m, WL.run_params(cfg), exc, occ, coef)
+
+
+def sorted_state(s):
+    k, a, r = s.state(with_real=True)
+    full = np.concatenate([r[:, None].astype(np.uint64), k], axis=1)
+    return sort_rows(full, a)
+
+
+@pytest.mark.parametrize("name,R,steps", [("ring16", 1, 40), ("sq6x6", 4, 12)])
+def test_graph_replay_equals_eager(name, R, steps):
+    me, e = sim_of(name, R)
+    mg, g = sim_of(name, R)
+    g.set_tuning(graph=1)
+    assert g.tuning()["graph"] == 1
+    for i in range(steps):
+        e.step(1)
+        g.step(1)
+        # every replay checked; reading the state synchronises and runs
+        # eager copies between replays.  Time, counts, K and bounds are
+        # exact; sums agree to rounding (P(j) bins are LDS atomics, whose
+        # order within a block is not fixed, eager or not)
+        re_, rg = e.series(i, 1), g.series(i, 1)
+        assert np.array_equal(re_[..., EXACT], rg[..., EXACT]), i
+        assert np.allclose(re_, rg, rtol=1e-13, atol=1e-15), i
+        if i % 5 == 4 or i == steps - 1:
+            ke, ae = sorted_state(e)
+            kg, ag = sorted_state(g)
+            assert np.array_equal(ke, kg), i
+            assert np.array_equal(ae, ag), i
+
+
+@pytest.mark.parametrize("tune", [dict(table_shift=2), dict(term_rows=4),
+                                  dict(table_shift=3, term_rows=8, graph=1)])
+def test_tunings_give_identical_amplitudes(tune):
+    m0, a = sim_of("ring16")
+    m1, b = sim_of("ring16")
+    b.set_tuning(**tune)
+    a.step(25)
+    b.step(25)
+    ka, aa = sorted_state(a)
+    kb, ab = sorted_state(b)
+    assert np.array_equal(ka, kb)
+    assert np.array_equal(aa, ab)
+    ra, rb = a.series(), b.series()
+    # counts, K, bounds and time exact; sums to rounding
+    assert np.array_equal(ra[..., EXACT], rb[..., EXACT])
+    assert np.allclose(ra, rb, rtol=1e-13, atol=1e-15)
+
+
+def test_autotune_restores_state_and_keeps_results():
+    m0, a = sim_of("ring16")
+    m1, b = sim_of("ring16")
+    a.step(20)
+    b.step(20)
+    before = sorted_state(b)
+    n_rec = b.num_records()
+    chosen = b.autotune(steps=2)
+    assert chosen["graph"] in (0, 1)
+    assert chosen["table_shift"] in (1, 2)
+    assert chosen["term_rows"] in (1, 2, 4)
+    assert b.tuning() == chosen
+    after = sorted_state(b)
+    assert np.array_equal(before[0], after[0])
+    assert np.array_equal(before[1], after[1])
+    assert b.num_records() == n_rec
+    a.step(10)
+    b.step(10)
+    ka, aa = sorted_state(a)
+    kb, ab = sorted_state(b)
+    assert np.array_equal(ka, kb)
+    assert np.array_equal(aa, ab)
+    ra, rb = a.series(), b.series()
+    assert ra.shape == rb.shape
+    assert np.array_equal(ra[..., EXACT], rb[..., EXACT])
+    assert np.allclose(ra, rb, rtol=1e-13, atol=1e-15)
+
+
+def test_tuning_validation():
+    m, s = sim_of("ring4")
+    for bad in (dict(table_shift=0), dict(table_shift=4), dict(term_rows=3),
+                dict(graph=2)):
+        with pytest.raises(P.PacesError) as ei:
+            s.set_tuning(**bad)
+        assert ei.value.status == 1
+    with pytest.raises(P.PacesError):
+        s.autotune(steps=0)
