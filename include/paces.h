@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define PACES_ABI_VERSION 3
+#define PACES_ABI_VERSION 4
 
 typedef enum {
   PACES_OK = 0,
@@ -218,6 +218,37 @@ paces_status paces_profile_enable(paces_sim* s, int32_t on);
 paces_status paces_profile_get(paces_sim* s, paces_profile* out,
                                void* hip_stream);
 paces_status paces_profile_reset(paces_sim* s);
+
+/* Form (3): adjoint gradient.  For a real loss L of the autocorrelation
+ * a_s = <psi0|psi_s>, s = 0..n (s = 0 the initial state), the gradient
+ * dL/dtheta with theta = (J per axis, g per mode, omega per mode, eps per
+ * site), paces_num_params entries in that order.  The sets of the recorded
+ * run are held fixed (each step is then linear in psi); the gradient is
+ * the discrete adjoint of that frozen-set propagation.  Needs one
+ * realization, FP64 amplitudes and every J_axis, g_nu nonzero (so that the
+ * ELL holds every lattice edge); otherwise PACES_E_UNSUPPORTED. */
+int32_t paces_num_params(const paces_model* m);
+/* Run n_steps steps from a new sim (no step taken yet), keeping the
+ * selected set of every step and the state every ckpt_every steps (device
+ * memory: about |M| key words per step plus one state per checkpoint).
+ * a[2*(n_steps+1)]: a_s as (re, im), host, may be NULL.  Synchronises. */
+paces_status paces_adjoint_forward(paces_sim* s, int64_t n_steps,
+                                   int32_t ckpt_every, double* a,
+                                   void* hip_stream);
+/* Replay the recorded run on its frozen sets with model m (NULL: the
+ * sim's own; otherwise a model of the same shape, e.g. with perturbed
+ * parameters) and return a[2*(n+1)].  The sim's state is left as after the
+ * forward run.  Synchronises. */
+paces_status paces_adjoint_replay(paces_sim* s, const paces_model* m,
+                                  double* a, void* hip_stream);
+/* gbar[2*(n+1)]: dL/d conj(a_s) as (re, im) (half of what torch passes
+ * as the gradient of a complex output); grad[paces_num_params]: dL/dtheta.
+ * Replays each checkpoint segment once, then sweeps it in reverse; the
+ * Frechet derivative of each step's exponential is integrated with
+ * Gauss-Legendre nodes.  The sim's state is left as after the forward run.
+ * Synchronises. */
+paces_status paces_adjoint_backward(paces_sim* s, const double* gbar,
+                                    double* grad, void* hip_stream);
 
 /* Launch tuning.  Results do not depend on it: per-key amplitudes, sets
  * and counts are identical for every setting (sums only to rounding of

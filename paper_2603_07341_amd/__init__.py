@@ -35,7 +35,8 @@ EXPORTS = [
     "paces_series", "paces_get_state", "paces_set_state", "paces_get_set",
     "paces_get_phi", "paces_profile_enable", "paces_profile_get",
     "paces_profile_reset", "paces_get_tuning", "paces_set_tuning",
-    "paces_autotune",
+    "paces_autotune", "paces_num_params", "paces_adjoint_forward",
+    "paces_adjoint_replay", "paces_adjoint_backward",
 ]
 
 
@@ -94,6 +95,7 @@ def lib():
         _lib.paces_last_error.restype = C.c_char_p
         _lib.paces_abi_version.restype = C.c_int32
         _lib.paces_record_doubles.restype = C.c_int32
+        _lib.paces_num_params.restype = C.c_int32
     return _lib
 
 
@@ -148,6 +150,7 @@ class Model:
         self.N, self.W, self.D, self.B = N.value, W.value, D.value, B.value
         self.V = params["n_modes"]
         self.rec_doubles = lib().paces_record_doubles(h)
+        self.n_params = lib().paces_num_params(h)
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -343,3 +346,79 @@ class Sim:
                                     _stream(stream)))
         return {"graph": t.graph, "table_shift": t.table_shift,
                 "term_rows": t.term_rows}
+
+    # ---- adjoint gradient (Form (3)) ----
+    def adjoint_forward(self, steps, ckpt_every=50, stream=None):
+        """Run `steps` steps from a new sim keeping what the adjoint needs;
+        returns a[s] = <psi0|psi_s>, s = 0..steps (complex128)."""
+        a = np.zeros(2 * (steps + 1), dtype=np.float64)
+        _check(lib().paces_adjoint_forward(self.h, C.c_int64(steps),
+                                           C.c_int32(ckpt_every),
+                                           _p(a, C.c_double), _stream(stream)))
+        self._adj_steps = steps
+        return a.view(np.complex128)
+
+    def adjoint_replay(self, model=None, stream=None):
+        """a[s] of the recorded run replayed on its frozen sets with
+        `model` (default: the sim's own)."""
+        a = np.zeros(2 * (self._adj_steps + 1), dtype=np.float64)
+        _check(lib().paces_adjoint_replay(self.h, model.h if model else None,
+                                          _p(a, C.c_double), _stream(stream)))
+        return a.view(np.complex128)
+
+    def adjoint_backward(self, gbar, stream=None):
+        """dL/dtheta (theta = J per axis, g and omega per mode, eps per
+        site) for gbar[s] = dL/d conj(a_s)."""
+        gb = np.ascontiguousarray(np.asarray(gbar, dtype=np.complex128)).view(np.float64)
+        if len(gb) != 2 * (self._adj_steps + 1):
+            raise ValueError("gbar needs one entry per recorded a_s")
+        g = np.zeros(self.model.n_params, dtype=np.float64)
+        _check(lib().paces_adjoint_backward(self.h, _p(gb, C.c_double),
+                                            _p(g, C.c_double), _stream(stream)))
+        return g
+
+
+def theta_of(params):
+    """theta = (J per axis, g per mode, omega per mode, eps per site)."""
+    nd, V = params["ndim"], params["n_modes"]
+    return np.array(list(params["J"][:nd]) + list(params["g"][:V])
+                    + list(params["omega"][:V]) + list(params["eps"]),
+                    dtype=np.float64)
+
+
+def params_with_theta(params, theta):
+    """Copy of the model parameters with theta substituted."""
+    nd, V = params["ndim"], params["n_modes"]
+    t = [float(x) for x in theta]
+    p = dict(params)
+    p["J"] = t[:nd] + list(params["J"][nd:])
+    p["g"] = t[nd:nd + V] + list(params["g"][V:])
+    p["omega"] = t[nd + V:nd + 2 * V] + list(params["omega"][V:])
+    p["eps"] = t[nd + 2 * V:]
+    return p
+
+
+if torch is not None:
+    class AutocorrFn(torch.autograd.Function):
+        """a = AutocorrFn.apply(theta, params, run, init, steps, ckpt_every):
+        the autocorrelation a_s = <psi0|psi_s>, s = 0..steps (complex128,
+        on the CPU), of a run with model parameters theta (float64 [P]:
+        J per axis, g and omega per mode, eps per site).  Backward is the
+        adjoint gradient on the forward run's frozen sets."""
+
+        @staticmethod
+        def forward(ctx, theta, params, run, init, steps, ckpt_every=50):
+            p = params_with_theta(params, theta.detach().cpu().numpy())
+            model = Model(p)
+            exc, occ, coef = init
+            sim = Sim(model, run, exc, occ, coef)
+            a = sim.adjoint_forward(steps, ckpt_every)
+            ctx.sim, ctx.model = sim, model
+            return torch.from_numpy(a.copy())
+
+        @staticmethod
+        def backward(ctx, grad_a):
+            # torch passes 2 dL/d conj(a) for a complex output
+            gbar = grad_a.detach().cpu().numpy().astype(np.complex128) / 2
+            g = ctx.sim.adjoint_backward(gbar)
+            return (torch.from_numpy(g), None, None, None, None, None)

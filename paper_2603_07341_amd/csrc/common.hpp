@@ -9,6 +9,38 @@
 
 #include "kernels.hpp"
 
+// Compile-time dispatch over the internal key word count and over the
+// lattice shape (axes, modes per site).
+#define PACES_DISPATCH_W(Wi, ...)                           \
+  switch (Wi) {                                             \
+    case 1: { constexpr int WW = 1; __VA_ARGS__; } break;   \
+    case 2: { constexpr int WW = 2; __VA_ARGS__; } break;   \
+    case 3: { constexpr int WW = 3; __VA_ARGS__; } break;   \
+    case 4: { constexpr int WW = 4; __VA_ARGS__; } break;   \
+    case 6: { constexpr int WW = 6; __VA_ARGS__; } break;   \
+    case 8: { constexpr int WW = 8; __VA_ARGS__; } break;   \
+    case 10: { constexpr int WW = 10; __VA_ARGS__; } break; \
+    case 16: { constexpr int WW = 16; __VA_ARGS__; } break; \
+    default: break;                                         \
+  }
+
+#define PACES_DISPATCH_SHAPE(ND, NV, ...)                        \
+  switch ((ND) * 8 + (NV)) {                                     \
+    case 9: { constexpr int A = 1, B = 1; __VA_ARGS__; } break;  \
+    case 10: { constexpr int A = 1, B = 2; __VA_ARGS__; } break; \
+    case 11: { constexpr int A = 1, B = 3; __VA_ARGS__; } break; \
+    case 12: { constexpr int A = 1, B = 4; __VA_ARGS__; } break; \
+    case 17: { constexpr int A = 2, B = 1; __VA_ARGS__; } break; \
+    case 18: { constexpr int A = 2, B = 2; __VA_ARGS__; } break; \
+    case 19: { constexpr int A = 2, B = 3; __VA_ARGS__; } break; \
+    case 20: { constexpr int A = 2, B = 4; __VA_ARGS__; } break; \
+    case 25: { constexpr int A = 3, B = 1; __VA_ARGS__; } break; \
+    case 26: { constexpr int A = 3, B = 2; __VA_ARGS__; } break; \
+    case 27: { constexpr int A = 3, B = 3; __VA_ARGS__; } break; \
+    case 28: { constexpr int A = 3, B = 4; __VA_ARGS__; } break; \
+    default: break;                                              \
+  }
+
 namespace paces {
 namespace {
 

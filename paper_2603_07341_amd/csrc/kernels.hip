@@ -1069,36 +1069,6 @@ int supported_words(int W) {
 
 int64_t scan_tmp_words(int64_t n) { return cdiv(n, kTile) + 16; }
 
-#define PACES_DISPATCH_W(Wi, ...)                           \
-  switch (Wi) {                                             \
-    case 1: { constexpr int WW = 1; __VA_ARGS__; } break;   \
-    case 2: { constexpr int WW = 2; __VA_ARGS__; } break;   \
-    case 3: { constexpr int WW = 3; __VA_ARGS__; } break;   \
-    case 4: { constexpr int WW = 4; __VA_ARGS__; } break;   \
-    case 6: { constexpr int WW = 6; __VA_ARGS__; } break;   \
-    case 8: { constexpr int WW = 8; __VA_ARGS__; } break;   \
-    case 10: { constexpr int WW = 10; __VA_ARGS__; } break; \
-    case 16: { constexpr int WW = 16; __VA_ARGS__; } break; \
-    default: break;                                         \
-  }
-
-#define PACES_DISPATCH_SHAPE(ND, NV, ...)                        \
-  switch ((ND) * 8 + (NV)) {                                     \
-    case 9: { constexpr int A = 1, B = 1; __VA_ARGS__; } break;  \
-    case 10: { constexpr int A = 1, B = 2; __VA_ARGS__; } break; \
-    case 11: { constexpr int A = 1, B = 3; __VA_ARGS__; } break; \
-    case 12: { constexpr int A = 1, B = 4; __VA_ARGS__; } break; \
-    case 17: { constexpr int A = 2, B = 1; __VA_ARGS__; } break; \
-    case 18: { constexpr int A = 2, B = 2; __VA_ARGS__; } break; \
-    case 19: { constexpr int A = 2, B = 3; __VA_ARGS__; } break; \
-    case 20: { constexpr int A = 2, B = 4; __VA_ARGS__; } break; \
-    case 25: { constexpr int A = 3, B = 1; __VA_ARGS__; } break; \
-    case 26: { constexpr int A = 3, B = 2; __VA_ARGS__; } break; \
-    case 27: { constexpr int A = 3, B = 3; __VA_ARGS__; } break; \
-    case 28: { constexpr int A = 3, B = 4; __VA_ARGS__; } break; \
-    default: break;                                              \
-  }
-
 void fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
   if (n <= 0) return;
   k_fill_u64<<<grid_for(n), kBlock, 0, s>>>(p, n, v);

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "../../include/paces.h"
+#include "adjoint.hpp"
 #include "kernels.hpp"
 
 using namespace paces;
@@ -196,6 +197,8 @@ struct EventPair {
 
 }  // namespace
 
+struct AdjRecord;  // recorded run of the adjoint gradient
+
 struct paces_sim {
   const paces_model* m = nullptr;
   paces_run_params p{};
@@ -231,6 +234,8 @@ struct paces_sim {
   uint64_t* keys0 = nullptr;
   double* amps0 = nullptr;
   int64_t n0 = 0;
+  int32_t* p0_last = nullptr;  // [R][n0] rows of the initial states in S
+  AdjRecord* adj = nullptr;
 
   double* ring = nullptr;
   int64_t ring_cap = 0;
@@ -521,25 +526,47 @@ paces_status upload_state(paces_sim* s, int64_t n,
 // Enqueue one attempt of a step.  Nothing here waits on the GPU.  `est`
 // (the host's guess of the new set's size) only sizes launch grids; every
 // kernel strides over whatever the device counts say.
-void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st) {
+// A frozen step (adjoint replay) takes M from a record instead of the
+// threshold, and keeps the row maps the backward pass needs.
+struct FrozenStep {
+  const uint64_t* mkeys;  // nM internal keys
+  int64_t nM;
+  int k;
+  int32_t* tmap;   // [old rows] new row of every old row (may be null)
+  int32_t* p0map;  // [n0] rows of the initial states (may be null)
+};
+
+void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st,
+                  const FrozenStep* fz = nullptr) {
   const paces_model* m = s->m;
   const DevModel& dm = m->dm;
   const int Wi = m->Wi, R = m->R;
   const int old = s->cur, nw = 1 - s->cur;
-  const int k = s->fresh ? s->p.k_init : s->p.k;
+  const int k = fz ? fz->k : (s->fresh ? s->p.k_init : s->p.k);
   const Side so = s->side[old], sn = s->side[nw];
   begin_step(s->ctl, s->err, s->cnt, R, st);
   {
     Stage sg(s, PACES_STAGE_SELECT, st);
-    select_rows(s->prec, s->vec[s->ipsi], s->th2, s->fresh, counted, s->ctl,
-                s->midx, s->scan_tmp, std::min(bucket(s->nS), s->cap), s->err,
-                st);
+    if (fz)
+      adj_set_frozen(s->ctl, s->cnt, uint32_t(fz->nM), s->err, st);
+    else
+      select_rows(s->prec, s->vec[s->ipsi], s->th2, s->fresh, counted,
+                  s->ctl, s->midx, s->scan_tmp,
+                  std::min(bucket(s->nS), s->cap), s->err, st);
   }
   {
     Stage sg(s, PACES_STAGE_EXPAND, st);
     fill_u64(s->table, int64_t(s->tmask + 1), kEmpty, st);
-    insert_rows(dm, Wi, so, sn, s->midx, s->ctl, s->table, s->tmask, s->cnt,
-                s->err, st);
+    if (fz) {
+      if (fz->nM > 0)
+        (void)hipMemcpyAsync(sn.keys, fz->mkeys, size_t(fz->nM) * Wi * 8,
+                             hipMemcpyDeviceToDevice, st);
+      row_info(dm, Wi, sn.keys, fz->nM, sn.pay, sn.tot, st);
+      rehash_rows(dm, Wi, sn, nullptr, fz->nM, s->table, s->tmask, s->err, st);
+    } else {
+      insert_rows(dm, Wi, so, sn, s->midx, s->ctl, s->table, s->tmask,
+                  s->cnt, s->err, st);
+    }
     for (int r = 1; r <= k; ++r)
       expand_round(dm, Wi, s->prec, sn, r, s->ctl, s->cap, est, s->table,
                    s->tmask, s->rb, s->col, s->vec[s->iphi], s->err, st);
@@ -551,8 +578,8 @@ void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st) {
     Stage sg(s, PACES_STAGE_TRANSFER, st);
     const int np = transfer(dm, Wi, s->prec, so, s->vec[s->ipsi],
                             bucket(s->nS), s->ctl, s->table, s->tmask, sn.keys,
-                            s->vec[s->iphi], s->mass_part, nullptr, s->err,
-                            st);
+                            s->vec[s->iphi], s->mass_part,
+                            fz ? fz->tmap : nullptr, s->err, st);
     n_mass = R == 1 ? fold_sum(s->mass_part, np, s->mass_fold, s->err, st) : np;
   }
   {
@@ -584,7 +611,8 @@ void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st) {
                                s->n2_part, s->en_part, s->pop_part,
                                s->scan_tmp, s->cnt + R, s->err, st);
     autocorr(dm, Wi, s->prec, s->keys0, s->amps0, s->n0, s->table, s->tmask,
-             sn.keys, s->vec[s->ib0], s->a2, nullptr, s->err, st);
+             sn.keys, s->vec[s->ib0], s->a2, fz ? fz->p0map : s->p0_last,
+             s->err, st);
     obs_final(m->N, R, want_e ? 1 : 0, s->p.dt, n_mass, n_e, n_pop,
               R == 1 ? s->mass_fold : s->mass_part, s->n2_part, s->e_fold,
               s->en_part, s->pop_part, s->a2, s->cc, s->ctl, s->cnt,
@@ -637,7 +665,8 @@ paces_status launch_step_graph(paces_sim* s, int64_t est, bool counted,
 
 // One step: enqueue, read back the counts, repeat with more room when a
 // capacity was exceeded.
-paces_status do_step(paces_sim* s, hipStream_t st) {
+paces_status do_step(paces_sim* s, hipStream_t st,
+                     const FrozenStep* fz = nullptr) {
   const paces_model* m = s->m;
   // keep room for the new set: growth of the set per step stays well below
   // the factor used here in the workloads; an overflow is caught anyway
@@ -654,13 +683,13 @@ paces_status do_step(paces_sim* s, hipStream_t st) {
       P <<= 1;
     s->tmask = std::min<uint64_t>(P - 1, s->tmask_alloc);
   }
-  const bool graph = s->tune.graph && !s->prof;
+  const bool graph = s->tune.graph && !s->prof && !fz;
   for (int attempt = 0; attempt < 40; ++attempt) {
-    const bool counted = s->counts_valid && attempt == 0;
+    const bool counted = s->counts_valid && attempt == 0 && !fz;
     if (graph && attempt == 0)
       ST_TRY(launch_step_graph(s, est, counted, st));
     else
-      enqueue_step(s, est, counted, st);
+      enqueue_step(s, est, counted, st, fz);
     HIP_TRY(hipMemcpyAsync(s->h_ctl, s->ctl, sizeof(StepCtl),
                            hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(s->h_err, s->err, sizeof(int), hipMemcpyDeviceToHost,
@@ -690,7 +719,7 @@ paces_status do_step(paces_sim* s, hipStream_t st) {
       s->nS = c.n_new;
       s->cur = 1 - s->cur;
       std::swap(s->ipsi, s->ib0);
-      s->k_last = s->fresh ? s->p.k_init : s->p.k;
+      s->k_last = fz ? fz->k : (s->fresh ? s->p.k_init : s->p.k);
       s->fresh = false;
       s->have_sets = true;
       s->K_last = K;
@@ -827,6 +856,187 @@ paces_status check_tuning(const paces_tuning* t) {
   return PACES_OK;
 }
 
+
+}  // namespace
+
+// ---- adjoint gradient on a recorded run (Form (3)) -------------------------
+// The forward pass runs ordinary steps and keeps, per step, the selected set
+// M (so that a replay reproduces every set exactly, whatever the model
+// parameters) and, every C steps, the whole state.  The backward pass
+// replays one segment of C steps from its checkpoint, keeping per step the
+// ELL columns, payload, phi = T_s psi_s, the row maps and the Chebyshev
+// interval, then walks the segment in reverse.
+struct AdjStep {
+  int64_t nM = 0, n_new = 0, moff = 0;
+  int k = 0, K = 0;
+  double emin = 0, emax = 0;
+};
+
+struct AdjRecord {
+  int C = 50;
+  int64_t n = 0;
+  std::vector<AdjStep> steps;
+  uint64_t* mkeys = nullptr;  // M keys of every step, internal words
+  int64_t mcap = 0, mused = 0;
+  std::vector<Snapshot*> ck;        // state before step q*C
+  std::vector<int32_t*> ck_p0;      // rows of the initial states there
+  Snapshot* fin = nullptr;          // state after the last step
+  std::vector<double> a;            // a_0 .. a_n, (re, im)
+  ~AdjRecord() {
+    dfree(mkeys);
+    for (auto* c : ck) delete c;
+    for (auto* p : ck_p0) dfree(p);
+    delete fin;
+  }
+};
+
+namespace {
+
+paces_status adj_supported(const paces_sim* s) {
+  const paces_model* m = s->m;
+  if (m->R != 1 || s->prec != 64)
+    return fail(PACES_E_UNSUPPORTED,
+                "the adjoint needs one realization and FP64 amplitudes");
+  for (int a = 0; a < m->ndim; ++a)
+    if (m->J[a] == 0.0)
+      return fail(PACES_E_UNSUPPORTED, "the adjoint needs every J_axis != 0");
+  for (int nu = 0; nu < m->V; ++nu)
+    if (m->g[nu] == 0.0)
+      return fail(PACES_E_UNSUPPORTED, "the adjoint needs every g_nu != 0");
+  return PACES_OK;
+}
+
+bool same_shape(const paces_model* a, const paces_model* b) {
+  if (a->ndim != b->ndim || a->N != b->N || a->V != b->V || a->R != b->R ||
+      a->Wi != b->Wi || a->D != b->D)
+    return false;
+  for (int x = 0; x < 3; ++x)
+    if (a->ext[x] != b->ext[x] || a->per[x] != b->per[x]) return false;
+  for (int nu = 0; nu < a->V; ++nu)
+    if (a->cut[nu] != b->cut[nu]) return false;
+  return true;
+}
+
+// Append the nM keys of rows [0, nM) of the current side (the selected set
+// of the step just made) to the record.
+paces_status adj_keep_m(paces_sim* s, int64_t nM, hipStream_t st) {
+  AdjRecord& R = *s->adj;
+  const int Wi = s->m->Wi;
+  if (R.mused + nM > R.mcap) {
+    const int64_t nc = std::max<int64_t>(2 * R.mcap, R.mused + nM + 4096);
+    uint64_t* q = nullptr;
+    ST_TRY(dalloc(&q, nc * Wi));
+    if (R.mused > 0)
+      HIP_TRY(hipMemcpyAsync(q, R.mkeys, size_t(R.mused) * Wi * 8,
+                             hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    dfree(R.mkeys);
+    R.mkeys = q;
+    R.mcap = nc;
+  }
+  if (nM > 0)
+    HIP_TRY(hipMemcpyAsync(R.mkeys + R.mused * Wi, s->side[s->cur].keys,
+                           size_t(nM) * Wi * 8, hipMemcpyDeviceToDevice, st));
+  R.mused += nM;
+  return PACES_OK;
+}
+
+paces_status adj_frozen_step(paces_sim* s, int64_t i, int32_t* tmap,
+                             int32_t* p0map, hipStream_t st) {
+  const AdjRecord& R = *s->adj;
+  const AdjStep& a = R.steps[i];
+  const FrozenStep fz{R.mkeys + a.moff * s->m->Wi, a.nM, a.k, tmap, p0map};
+  ST_TRY(do_step(s, st, &fz));
+  if (s->nS != a.n_new)
+    return fail(PACES_E_STATE, "replay did not reproduce the recorded set");
+  return PACES_OK;
+}
+
+// a of the records [first, first + n) into out (2 doubles per record).
+paces_status adj_read_a(paces_sim* s, int64_t first, int64_t n, double* out,
+                        hipStream_t st) {
+  if (n <= 0) return PACES_OK;
+  std::vector<double> rec(size_t(n) * s->rec_doubles);
+  HIP_TRY(hipMemcpyAsync(rec.data(), s->ring + first * s->rec_doubles,
+                         rec.size() * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int64_t i = 0; i < n; ++i) {
+    out[2 * i] = rec[size_t(i) * s->rec_doubles + 3];
+    out[2 * i + 1] = rec[size_t(i) * s->rec_doubles + 4];
+  }
+  return PACES_OK;
+}
+
+// Gauss-Legendre nodes and weights on [0, 1] (roots of P_n by Newton's
+// method from the usual cosine guesses).
+void legendre(int n, double x, double& pn, double& dp) {
+  double p0 = 1, p1 = x;
+  for (int k = 2; k <= n; ++k) {
+    const double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  pn = p1;
+  dp = n * (x * p1 - p0) / (x * x - 1);
+}
+void gauss_legendre(int n, double* tau, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(M_PI * (i + 0.75) / (n + 0.5)), pn, dp;
+    for (int it = 0; it < 100; ++it) {
+      legendre(n, x, pn, dp);
+      const double dx = pn / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    legendre(n, x, pn, dp);
+    tau[i] = 0.5 * (1 - x);
+    w[i] = 1.0 / ((1 - x * x) * dp * dp);  // 2 / (...) halved for [0, 1]
+  }
+}
+
+// Nodes so that the Gauss-Legendre error bound for exp(i w tau) on [0, 1],
+// w^{2n} (n!)^4 / ((2n+1) ((2n)!)^3), is below 1e-17.
+int nodes_for(double wdt) {
+  for (int n = 2; n <= kMaxNodes; ++n) {
+    double f = 1, f2 = 1;
+    for (int k = 2; k <= n; ++k) f *= k;
+    for (int k = 2; k <= 2 * n; ++k) f2 *= k;
+    const double b = std::pow(wdt, 2 * n) * std::pow(f, 4) /
+                     ((2 * n + 1) * f2 * f2 * f2);
+    if (b < 1e-17) return n;
+  }
+  return 0;
+}
+
+// Per-step slice of the segment store.
+struct SegSlot {
+  int32_t* col;
+  uint64_t *pay, *tot;
+  double2* phi;
+  int32_t *tmap, *p0;
+  ChebCoef* cc;
+};
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Device buffers freed together when the owner goes out of scope.
+struct WorkSpace {
+  std::vector<void*> p;
+  ~WorkSpace() {
+    for (void* q : p) (void)hipFree(q);
+  }
+  template <typename T>
+  paces_status get(T** out, int64_t count) {
+    *out = nullptr;
+    ST_TRY(dalloc(out, std::max<int64_t>(count, 1)));
+    p.push_back(*out);
+    return PACES_OK;
+  }
+};
+
+}  // namespace
+
+namespace {
 // Device copies of the model tables, made on first use so that loading a
 // model and the host codec need no GPU.
 paces_status ensure_device_tables(paces_model* m) {
@@ -1090,7 +1300,8 @@ paces_status paces_init_state(const paces_model* m, const paces_run_params* p,
                          sz_pop * m->N + 2 * 256;
   if (dalloc(&s->ctl, 1) || dalloc(&s->err, 1) || dalloc(&s->parts, nparts) ||
       dalloc(&s->cc, R) || dalloc(&s->a2, 2 * R) || dalloc(&s->cnt, 2 * R) ||
-      dalloc(&s->mass_tot, R) || dalloc(&s->keys0, nt * m->Wi) ||
+      dalloc(&s->mass_tot, R) || dalloc(&s->p0_last, nt) ||
+      dalloc(&s->keys0, nt * m->Wi) ||
       dalloc(&s->amps0, 2 * nt))
     return cleanup(PACES_E_OOM);
   double* q = s->parts;
@@ -1138,6 +1349,7 @@ paces_status paces_free_sim(paces_sim* s) {
   dfree(s->a2);
   dfree(s->cnt);
   dfree(s->mass_tot);
+  dfree(s->p0_last);
   dfree(s->keys0);
   dfree(s->amps0);
   dfree(s->ring);
@@ -1150,6 +1362,7 @@ paces_status paces_free_sim(paces_sim* s) {
   if (s->h_err) (void)hipHostFree(s->h_err);
   drop_graphs(s);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  delete s->adj;
   delete s;
   return PACES_OK;
 }
@@ -1354,6 +1567,302 @@ paces_status paces_profile_reset(paces_sim* s) {
   paces_profile z{};
   s->acc = z;
   return PACES_OK;
+}
+
+int32_t paces_num_params(const paces_model* m) {
+  return m ? m->ndim + 2 * m->V + m->N : 0;
+}
+
+paces_status paces_adjoint_forward(paces_sim* s, int64_t n_steps,
+                                   int32_t ckpt_every, double* a_out,
+                                   void* hip_stream) {
+  if (!s || n_steps < 1 || ckpt_every < 1 || n_steps > (int64_t(1) << 24))
+    return fail(PACES_E_ARG, "bad arguments");
+  if (s->latched) return fail(PACES_E_STATE, "sim is in an error state");
+  if (!s->fresh || s->h.nrec != 0)
+    return fail(PACES_E_STATE, "the adjoint forward starts from a new sim");
+  ST_TRY(adj_supported(s));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  delete s->adj;
+  s->adj = new AdjRecord();
+  AdjRecord& R = *s->adj;
+  R.C = ckpt_every;
+  R.n = n_steps;
+  R.steps.assign(n_steps, AdjStep());
+  R.a.assign(2 * (n_steps + 1), 0.0);
+  auto bail = [&](paces_status e) {
+    delete s->adj;
+    s->adj = nullptr;
+    return e;
+  };
+  // a_0 = <psi0|psi0>
+  {
+    std::vector<double> a0(2 * s->n0);
+    HIP_TRY(hipMemcpy(a0.data(), s->amps0, a0.size() * 8,
+                      hipMemcpyDeviceToHost));
+    double acc = 0;
+    for (int64_t i = 0; i < s->n0; ++i)
+      acc += a0[2 * i] * a0[2 * i] + a0[2 * i + 1] * a0[2 * i + 1];
+    R.a[0] = acc;
+  }
+  for (int64_t i = 0; i < n_steps; ++i) {
+    if (i % R.C == 0) {
+      Snapshot* z = new Snapshot();
+      R.ck.push_back(z);
+      paces_status e = take_snapshot(s, *z, st);
+      int32_t* p0 = nullptr;
+      if (!e) e = dalloc(&p0, s->n0);
+      R.ck_p0.push_back(p0);
+      if (e) return bail(e);
+      if (i == 0) {
+        // the initial state sits in input order
+        std::vector<int32_t> id(s->n0);
+        std::iota(id.begin(), id.end(), 0);
+        if (hipMemcpy(p0, id.data(), id.size() * 4, hipMemcpyHostToDevice) !=
+            hipSuccess)
+          return bail(fail(PACES_E_HIP, "upload failed"));
+      } else if (hipMemcpyAsync(p0, s->p0_last, size_t(s->n0) * 4,
+                                hipMemcpyDeviceToDevice, st) != hipSuccess) {
+        return bail(fail(PACES_E_HIP, "copy failed"));
+      }
+    }
+    paces_status e = do_step(s, st);
+    if (e) return bail(e);
+    AdjStep& a = R.steps[i];
+    a.nM = s->h.nM;
+    a.k = s->k_last;
+    a.n_new = s->nS;
+    a.K = s->K_last;
+    a.moff = R.mused;
+    e = adj_keep_m(s, a.nM, st);
+    if (e) return bail(e);
+  }
+  R.fin = new Snapshot();
+  paces_status e = take_snapshot(s, *R.fin, st);
+  if (e) return bail(e);
+  // a_1..a_n and the spectral intervals from the records
+  std::vector<double> rec(size_t(n_steps) * s->rec_doubles);
+  if (hipMemcpyAsync(rec.data(), s->ring, rec.size() * 8,
+                     hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return bail(fail(PACES_E_HIP, "record read failed"));
+  for (int64_t i = 0; i < n_steps; ++i) {
+    const double* r = rec.data() + size_t(i) * s->rec_doubles;
+    R.a[2 * (i + 1)] = r[3];
+    R.a[2 * (i + 1) + 1] = r[4];
+    R.steps[i].emin = r[10];
+    R.steps[i].emax = r[11];
+  }
+  if (a_out) std::copy(R.a.begin(), R.a.end(), a_out);
+  return PACES_OK;
+}
+
+paces_status paces_adjoint_replay(paces_sim* s, const paces_model* model,
+                                  double* a_out, void* hip_stream) {
+  if (!s || !a_out) return fail(PACES_E_ARG, "bad arguments");
+  if (!s->adj) return fail(PACES_E_STATE, "no adjoint record");
+  const paces_model* own = s->m;
+  if (!model) model = own;
+  if (!same_shape(own, model))
+    return fail(PACES_E_ARG, "model shape differs from the recorded run");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  ST_TRY(ensure_device_tables(const_cast<paces_model*>(model)));
+  AdjRecord& R = *s->adj;
+  paces_status e = restore_snapshot(s, *R.ck[0], st);
+  s->m = model;
+  const int64_t first = s->h.nrec;
+  for (int64_t i = 0; i < R.n && !e; ++i)
+    e = adj_frozen_step(s, i, nullptr, nullptr, st);
+  if (!e) e = adj_read_a(s, first, R.n, a_out + 2, st);
+  s->m = own;
+  a_out[0] = R.a[0];
+  a_out[1] = R.a[1];
+  paces_status e2 = restore_snapshot(s, *R.fin, st);
+  return e ? e : e2;
+}
+
+paces_status paces_adjoint_backward(paces_sim* s, const double* gbar,
+                                    double* grad_out, void* hip_stream) {
+  if (!s || !gbar || !grad_out) return fail(PACES_E_ARG, "bad arguments");
+  if (!s->adj) return fail(PACES_E_STATE, "no adjoint record");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  AdjRecord& R = *s->adj;
+  const paces_model* m = s->m;
+  const DevModel& dm = m->dm;
+  const int P = paces_num_params(m), D = m->D, V = m->V;
+  const int64_t n0 = s->n0, nseg = (R.n + R.C - 1) / R.C;
+  // sizes and node counts
+  int64_t maxn = R.ck[0]->n;
+  int nqmax = 1;
+  std::vector<int> nq(R.n);
+  for (int64_t i = 0; i < R.n; ++i) {
+    maxn = std::max(maxn, R.steps[i].n_new);
+    nq[i] = nodes_for((R.steps[i].emax - R.steps[i].emin) * s->p.dt);
+    if (!nq[i])
+      return fail(PACES_E_UNSUPPORTED,
+                  "spectral width times dt too large for the quadrature");
+    nqmax = std::max(nqmax, nq[i]);
+  }
+  WorkSpace buf;  // freed on return
+  double2 *lamA, *lamB, *b0, *b1, *tx1, *ty1, *accx, *accy, *cn;
+  double *part, *grad, *tau, *w;
+  ChebCoef* ccj;
+  ST_TRY(buf.get(&lamA, maxn));
+  ST_TRY(buf.get(&lamB, maxn));
+  ST_TRY(buf.get(&b0, maxn));
+  ST_TRY(buf.get(&b1, maxn));
+  ST_TRY(buf.get(&tx1, maxn));
+  ST_TRY(buf.get(&ty1, maxn));
+  ST_TRY(buf.get(&accx, int64_t(nqmax) * maxn));
+  ST_TRY(buf.get(&accy, int64_t(nqmax) * maxn));
+  ST_TRY(buf.get(&cn, int64_t(kMaxNodes) * kMaxTerms));
+  ST_TRY(buf.get(&part, int64_t(1024) * P));
+  ST_TRY(buf.get(&grad, P));
+  ST_TRY(buf.get(&tau, int64_t(kMaxNodes + 1) * kMaxNodes));
+  ST_TRY(buf.get(&w, int64_t(kMaxNodes + 1) * kMaxNodes));
+  ST_TRY(buf.get(&ccj, 1));
+  {
+    std::vector<double> ht((kMaxNodes + 1) * kMaxNodes, 0.0), hw(ht.size(), 0.0);
+    for (int q = 1; q <= kMaxNodes; ++q)
+      gauss_legendre(q, &ht[q * kMaxNodes], &hw[q * kMaxNodes]);
+    HIP_TRY(hipMemcpy(tau, ht.data(), ht.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(w, hw.data(), hw.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemsetAsync(grad, 0, size_t(P) * 8, st));
+  }
+  uint8_t* store = nullptr;
+  size_t store_cap = 0;
+  auto release_store = [&]() {
+    if (store) (void)hipFree(store);
+    store = nullptr;
+  };
+  paces_status e = PACES_OK;
+  const bool totw = V > 2;
+  for (int64_t q = nseg - 1; q >= 0 && !e; --q) {
+    const int64_t start = q * R.C, end = std::min(R.n, start + R.C);
+    // lay out the segment store
+    std::vector<SegSlot> slot(end - start);
+    std::vector<size_t> off(end - start);
+    size_t tot_bytes = 0;
+    for (int64_t i = start; i < end; ++i) {
+      const int64_t n1 = R.steps[i].n_new;
+      const int64_t ns = i ? R.steps[i - 1].n_new : R.ck[0]->n;
+      off[i - start] = tot_bytes;
+      tot_bytes += align256(size_t(D) * n1 * 4) + align256(size_t(n1) * 8) +
+                   (totw ? align256(size_t(n1) * 8) : 0) +
+                   align256(size_t(n1) * 16) + align256(size_t(ns) * 4) +
+                   align256(size_t(n0) * 4) + align256(sizeof(ChebCoef));
+    }
+    if (tot_bytes > store_cap) {
+      release_store();
+      if (hipMalloc(&store, tot_bytes) != hipSuccess) {
+        e = fail(PACES_E_OOM, "segment store allocation failed");
+        break;
+      }
+      store_cap = tot_bytes;
+    }
+    for (int64_t i = start; i < end; ++i) {
+      const int64_t n1 = R.steps[i].n_new;
+      const int64_t ns = i ? R.steps[i - 1].n_new : R.ck[0]->n;
+      uint8_t* b = store + off[i - start];
+      SegSlot& z = slot[i - start];
+      z.col = reinterpret_cast<int32_t*>(b);
+      b += align256(size_t(D) * n1 * 4);
+      z.pay = reinterpret_cast<uint64_t*>(b);
+      b += align256(size_t(n1) * 8);
+      z.tot = nullptr;
+      if (totw) {
+        z.tot = reinterpret_cast<uint64_t*>(b);
+        b += align256(size_t(n1) * 8);
+      }
+      z.phi = reinterpret_cast<double2*>(b);
+      b += align256(size_t(n1) * 16);
+      z.tmap = reinterpret_cast<int32_t*>(b);
+      b += align256(size_t(ns) * 4);
+      z.p0 = reinterpret_cast<int32_t*>(b);
+      b += align256(size_t(n0) * 4);
+      z.cc = reinterpret_cast<ChebCoef*>(b);
+    }
+    // replay the segment from its checkpoint, keeping what the reverse
+    // sweep needs
+    e = restore_snapshot(s, *R.ck[q], st);
+    for (int64_t i = start; i < end && !e; ++i) {
+      SegSlot& z = slot[i - start];
+      e = adj_frozen_step(s, i, z.tmap, z.p0, st);
+      if (e) break;
+      const int64_t n1 = s->nS;
+      for (int sl = 0; sl < D && !e; ++sl)
+        if (hipMemcpyAsync(z.col + int64_t(sl) * n1, s->col + int64_t(sl) * s->cap,
+                           size_t(n1) * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
+          e = fail(PACES_E_HIP, "copy failed");
+      const Side& c = s->side[s->cur];
+      if (!e && (hipMemcpyAsync(z.pay, c.pay, size_t(n1) * 8,
+                                hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                 (totw && hipMemcpyAsync(z.tot, c.tot, size_t(n1) * 8,
+                                         hipMemcpyDeviceToDevice, st) != hipSuccess) ||
+                 hipMemcpyAsync(z.phi, s->vec[s->iphi], size_t(n1) * 16,
+                                hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                 hipMemcpyAsync(z.cc, s->cc, sizeof(ChebCoef),
+                                hipMemcpyDeviceToDevice, st) != hipSuccess))
+        e = fail(PACES_E_HIP, "copy failed");
+    }
+    if (e) break;
+    // lambda at the end of the segment, in the replay's row order
+    const int64_t nend = R.steps[end - 1].n_new;
+    if (q == nseg - 1) {
+      adj_zero(lamA, nend, st);
+      adj_add_psi0(n0, slot[end - 1 - start].p0, s->amps0, gbar[2 * R.n],
+                   gbar[2 * R.n + 1], lamA, s->err, st);
+    } else {
+      // lamA holds lambda_end in the order of checkpoint q+1
+      adj_permute(dm, m->Wi, R.ck[q + 1]->keys, nend, s->table, s->tmask,
+                  s->side[s->cur].keys, lamA, lamB, s->err, st);
+      std::swap(lamA, lamB);
+    }
+    // reverse sweep
+    for (int64_t i = end - 1; i >= start; --i) {
+      const SegSlot& z = slot[i - start];
+      const AdjStep& a = R.steps[i];
+      const int64_t n1 = a.n_new;
+      const int64_t ns = i ? R.steps[i - 1].n_new : R.ck[0]->n;
+      const Side sd{nullptr, z.pay, z.tot};
+      // mu = exp(+i H dt) lambda_{i+1}
+      adj_set_rows(s->ctl, uint32_t(n1), st);
+      adj_conj_coef(z.cc, ccj, st);
+      for (int kk = a.K - 1; kk >= 0; --kk)
+        cheb_term(dm, 64, kk, false, false, n1, s->ctl, z.col, n1, sd, ccj,
+                  lamA, b0, b1, nullptr, nullptr, s->err, st);
+      // lambda_i = T_i^T mu + gbar_i psi0
+      adj_back(ns, z.tmap, b0, lamB, s->err, st);
+      const int32_t* p0 = i == start ? R.ck_p0[q] : slot[i - 1 - start].p0;
+      adj_add_psi0(n0, p0, s->amps0, gbar[2 * i], gbar[2 * i + 1], lamB,
+                   s->err, st);
+      // mu and phi at the quadrature nodes, contracted with dH/dtheta
+      const int nqi = nq[i];
+      adj_node_coef(z.cc, s->p.dt, tau + nqi * kMaxNodes, nqi, s->p.tol, cn,
+                    s->err, st);
+      for (int kk = 0; kk < a.K; ++kk)
+        adj_nodes(dm, kk, a.K, n1, z.col, z.pay, z.tot, z.cc, cn, nqi, b0,
+                  tx1, z.phi, ty1, accx, accy, s->err, st);
+      const int nb = adj_contract(dm, n1, z.col, z.pay, z.tot, nqi,
+                                  w + nqi * kMaxNodes, accx, accy, part,
+                                  s->err, st);
+      adj_fold(part, nb, P, 2.0 * s->p.dt, grad, s->err, st);
+      std::swap(lamA, lamB);
+    }
+    // lamA: lambda_start in the order of checkpoint q
+    HIP_TRY(hipMemcpyAsync(s->h_err, s->err, sizeof(int),
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (*s->h_err) e = fail(PACES_E_STATE, "device error in the adjoint sweep");
+  }
+  if (!e) {
+    HIP_TRY(hipMemcpyAsync(grad_out, grad, size_t(P) * 8,
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  release_store();
+  paces_status e2 = restore_snapshot(s, *R.fin, st);
+  return e ? e : e2;
 }
 
 paces_status paces_get_tuning(paces_sim* s, paces_tuning* out) {
