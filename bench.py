@@ -14,6 +14,11 @@ algorithmic bytes per launch |S| (4A + 4D + 16) over its HIP-event
 duration on the step's stream.
 cpu_baseline: the CPU oracle continued from the GPU state at the start of
 the timed window, for a bounded number of steps.
+forms: the three extra forms against plain FP64 single-realization runs on
+the same GPU: complex64 amplitudes on the same window; 64 disorder
+realizations of the 6x6 lattice in one sim against realizations run one
+after another; the adjoint gradient of the 12-site ring against its plain
+forward run (time ratio).
 """
 import argparse
 import json
@@ -36,6 +41,10 @@ def main():
     ap.add_argument("--precision", type=int, default=64)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=40)
+    ap.add_argument("--batch-singles", type=int, default=8)
+    ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (a "
                          "known-size reference for hardware byte counters)")
@@ -131,10 +140,121 @@ def main():
         "stage_ms": stage_ms,
         "terms_per_step": float(rec[:, 9].mean()),
     }
+    if not args.no_forms and args.config == "ring16" and args.precision == 64:
+        del sim
+        out["forms"] = {
+            "fp32": form_fp32(args, rec, elapsed, stream),
+            "batched": form_batched(args, stream),
+            "adjoint": form_adjoint(args, stream),
+        }
     if cpu_state is not None:
         out["cpu_baseline"] = cpu_baseline(params, run, cpu_state, cfg,
                                            args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, time.perf_counter() - t0
+
+
+def form_fp32(args, rec64, el64, stream):
+    """The same window with complex64 amplitudes (FP64 scalars and sums);
+    errors of a(t) and the norm against the FP64 run."""
+    import numpy as np
+    import paper_2603_07341_amd as P
+    import workloads as WL
+    cfg = dict(WL.CONFIGS["ring16"], precision=32)
+    m = P.Model(WL.model_params(cfg))
+    s = P.Sim(m, WL.run_params(cfg), *WL.initial_state(cfg), stream=stream)
+    print("fp32: warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
+    s.step(args.warmup, stream=stream)
+    n0 = s.num_records()
+    _, el = timed(lambda: s.step(args.steps, stream=stream))
+    rec = s.series(n0, args.steps, stream)
+    a32 = rec[:, 3] + 1j * rec[:, 4]
+    a64 = rec64[:, 3] + 1j * rec64[:, 4]
+    return {"value": float(rec[:, 7].sum()) / el, "unit": "updates/s",
+            "ms_per_step": el * 1e3 / args.steps,
+            "speedup_vs_fp64": el64 / el,
+            "max_abs_err_autocorr_vs_fp64": float(np.max(np.abs(a32 - a64))),
+            "max_rel_err_norm_vs_fp64": float(np.max(np.abs(rec[:, 1] / rec64[:, 1] - 1))),
+            "S_mean_fp32_over_fp64": float(rec[:, 7].sum() / rec64[:, 7].sum())}
+
+
+def form_batched(args, stream):
+    """64 disorder realizations of the 6x6 lattice (complex64) in one sim,
+    against single-realization sims of the first few realizations run one
+    after another, both from the initial state for the same steps."""
+    import paper_2603_07341_amd as P
+    import workloads as WL
+    cfg = WL.CONFIGS["sq6x6"]
+    n = args.batch_steps
+    bm = P.Model(WL.batch_params(cfg))
+    b = P.Sim(bm, WL.run_params(cfg), *WL.initial_state(cfg), stream=stream)
+    print("batched: %d realizations x %d steps" % (bm.R, n), file=sys.stderr,
+          flush=True)
+    _, el_b = timed(lambda: b.step(n, stream=stream))
+    rb = b.series(0, n, stream)
+    upd_b = float(rb[:, :, 7].sum())
+    del b
+    el_s, upd_s = 0.0, 0.0
+    for r in range(args.batch_singles):
+        m = P.Model(WL.model_params(cfg, r))
+        s = P.Sim(m, WL.run_params(cfg), *WL.initial_state(cfg), stream=stream)
+        _, el = timed(lambda: s.step(n, stream=stream))
+        el_s += el
+        upd_s += float(s.series(0, n, stream)[:, 7].sum())
+    per_real_single = el_s / args.batch_singles
+    return {"realizations": bm.R, "steps": n,
+            "value": upd_b / el_b, "unit": "updates/s",
+            "ms_per_step": el_b * 1e3 / n,
+            "single_value": upd_s / el_s,
+            "single_ms_per_step_per_realization": per_real_single * 1e3 / n,
+            "speedup_vs_sequential": per_real_single * bm.R / el_b,
+            "S_final_total": int(rb[-1, :, 7].sum()),
+            "S_final_min_max": [int(rb[-1, :, 7].min()), int(rb[-1, :, 7].max())]}
+
+
+def form_adjoint(args, stream):
+    """Adjoint gradient of L = sum_t |a(t) - tau(t)|^2 on the 12-site ring
+    (2000 steps, checkpoint every 50): time of the recorded forward and of
+    the backward sweep (segment replays included) against a plain forward
+    run of the same steps."""
+    import numpy as np
+    import paper_2603_07341_amd as P
+    import workloads as WL
+    cfg = WL.CONFIGS["ring12"]
+    n, ck = args.adjoint_steps, cfg["ckpt_every"]
+    p = WL.model_params(cfg)
+    init = WL.initial_state(cfg)
+    print("adjoint: %d steps, checkpoint every %d" % (n, ck), file=sys.stderr,
+          flush=True)
+    s0 = P.Sim(P.Model(p), WL.run_params(cfg), *init, stream=stream)
+    _, el_plain = timed(lambda: s0.step(n, stream=stream))
+    S_end = int(s0.observe(stream=stream)["n_S"])
+    print("adjoint: plain forward %.2f s, |S| %d" % (el_plain, S_end),
+          file=sys.stderr, flush=True)
+    del s0
+    m = P.Model(p)
+    s = P.Sim(m, WL.run_params(cfg), *init, stream=stream)
+    a, el_fwd = timed(lambda: s.adjoint_forward(n, ck, stream=stream))
+    print("adjoint: recorded forward %.2f s" % el_fwd, file=sys.stderr,
+          flush=True)
+    rng = np.random.default_rng(43)
+    tau = a * np.exp(1j * 0.05 * rng.standard_normal(len(a)))
+    g, el_bwd = timed(lambda: s.adjoint_backward(a - tau, stream=stream))
+    print("adjoint: backward %.2f s" % el_bwd, file=sys.stderr, flush=True)
+    return {"steps": n, "ckpt_every": ck, "S_end": S_end,
+            "plain_forward_s": el_plain, "recorded_forward_s": el_fwd,
+            "backward_s": el_bwd,
+            "adjoint_over_forward": el_bwd / el_plain,
+            "forward_plus_backward_over_forward": (el_fwd + el_bwd) / el_plain,
+            "grad_inf_norm": float(np.max(np.abs(g)))}
 
 
 def source_hash():
