@@ -44,7 +44,7 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=40)
     ap.add_argument("--batch-singles", type=int, default=8)
-    ap.add_argument("--adjoint-steps", type=int, default=2000)
+    ap.add_argument("--adjoint-steps", type=int, default=200)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (a "
                          "known-size reference for hardware byte counters)")
@@ -222,9 +222,10 @@ def form_batched(args, stream):
 
 def form_adjoint(args, stream):
     """Adjoint gradient of L = sum_t |a(t) - tau(t)|^2 on the 12-site ring
-    (2000 steps, checkpoint every 50): time of the recorded forward and of
-    the backward sweep (segment replays included) against a plain forward
-    run of the same steps."""
+    (checkpoint every 50; 200 steps by default, by which |S| passes 9e6 and
+    keeps growing): time of the recorded forward and of the backward sweep
+    (segment replays included) against a plain forward run of the same
+    steps, and a central-difference check of two gradient entries."""
     import numpy as np
     import paper_2603_07341_amd as P
     import workloads as WL
@@ -249,12 +250,25 @@ def form_adjoint(args, stream):
     tau = a * np.exp(1j * 0.05 * rng.standard_normal(len(a)))
     g, el_bwd = timed(lambda: s.adjoint_backward(a - tau, stream=stream))
     print("adjoint: backward %.2f s" % el_bwd, file=sys.stderr, flush=True)
+    # self-check on this run: central differences of the frozen-set replay
+    # along J and eps_0 against the adjoint gradient
+    loss = lambda aa: float(np.sum(np.abs(aa - tau) ** 2))
+    theta = P.theta_of(p)
+    fd_err = {}
+    for k, name in ((0, "J0"), (len(theta) - m.N, "eps0")):
+        h = 1e-4
+        lp = loss(s.adjoint_replay(P.Model(P.params_with_theta(
+            p, theta + h * (np.arange(len(theta)) == k))), stream=stream))
+        lm = loss(s.adjoint_replay(P.Model(P.params_with_theta(
+            p, theta - h * (np.arange(len(theta)) == k))), stream=stream))
+        fd_err[name] = abs((lp - lm) / (2 * h) - g[k]) / max(abs(g[k]), 1e-300)
     return {"steps": n, "ckpt_every": ck, "S_end": S_end,
             "plain_forward_s": el_plain, "recorded_forward_s": el_fwd,
             "backward_s": el_bwd,
             "adjoint_over_forward": el_bwd / el_plain,
             "forward_plus_backward_over_forward": (el_fwd + el_bwd) / el_plain,
-            "grad_inf_norm": float(np.max(np.abs(g)))}
+            "grad_inf_norm": float(np.max(np.abs(g))),
+            "fd_rel_err": fd_err}
 
 
 def source_hash():

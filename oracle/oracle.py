@@ -26,7 +26,8 @@ class _Desc(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("k", C.c_int32), ("k_init", C.c_int32),
-                ("theta", C.c_double), ("max_terms", C.c_int32)]
+                ("theta", C.c_double), ("max_terms", C.c_int32),
+                ("max_states", C.c_int64)]
 
 
 _lib = None
@@ -132,6 +133,7 @@ class Sim:
         p.k_init = run["k_init"]
         p.theta = run["theta"]
         p.max_terms = max_terms
+        p.max_states = int(run.get("max_states", 0))
         exc = np.ascontiguousarray(exc, dtype=np.int32)
         occ = np.ascontiguousarray(occ, dtype=np.uint16)
         coef = np.ascontiguousarray(coef, dtype=np.float64)
@@ -249,6 +251,7 @@ class Frozen:
         p.k_init = run["k_init"]
         p.theta = run["theta"]
         p.max_terms = max_terms
+        p.max_states = int(run.get("max_states", 0))
         exc = np.ascontiguousarray(exc, dtype=np.int32)
         occ = np.ascontiguousarray(occ, dtype=np.uint16)
         coef = np.ascontiguousarray(coef, dtype=np.float64)

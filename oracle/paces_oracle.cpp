@@ -430,7 +430,36 @@ struct Obs {
 struct Params {
   double dt = 0.01, theta = 0;
   int k = 2, k_init = 2, max_terms = 200;
+  int64_t max_states = 0;  // cap on |S| (0 = none)
 };
+
+// ---------------------------------------------------------------------------
+// State cap (reading of the cube4 workload's "capped by the HBM budget";
+// the paper itself keeps a fixed number q_nom of the largest amplitudes,
+// Sec. "Truncation & post-adaptation detruncation", with a pseudo-random
+// tie-break against ordering bias).  When the ball of M exceeds the cap,
+// M is cut to its q heaviest rows, ordered by weight descending, then by a
+// splitmix64 hash of the key ascending, then by the key ascending, with
+// q = floor(cap * |M_prev| / |S_prev|) (q = floor(cap / (D+1)) on the first
+// step or after an empty M) and, while the ball of the cut set still
+// exceeds the cap, q <- floor(9 min(q, |M|) cap / (10 |ball|)).
+// ---------------------------------------------------------------------------
+
+// splitmix64 output function (Steele, Lea & Flood 2014) of a 64-bit value.
+uint64_t splitmix_mix(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Tie-break hash of a canonical key: h = mix(h ^ word) over the words,
+// most significant first, from h = 0.
+uint64_t tiebreak_hash(const uint64_t* key, int W) {
+  uint64_t h = 0;
+  for (int w = 0; w < W; ++w) h = splitmix_mix(h ^ key[w]);
+  return h;
+}
 
 struct Sim {
   const Model* m = nullptr;
@@ -442,6 +471,7 @@ struct Sim {
   int64_t steps = 0;
   double t = 0, mass_total = 0;
   bool fresh = true;         // next step is the first after init
+  int64_t prev_nS = 0, prev_nM = 0;  // counts of the last step (cap rule)
   // last step
   Keys M;
   std::vector<Keys> frontier;
@@ -476,6 +506,40 @@ int sim_step(Sim& sim) {
   Keys ball;
   std::vector<Keys> frontier;
   expand(m, M, k, ball, frontier);
+  const int64_t cap = sim.p.max_states;
+  if (cap > 0 && ball.size() > cap) {
+    // order M by (weight desc, tie-break hash asc, key asc)
+    std::vector<int64_t> order(M.size());
+    std::vector<double> wM(M.size());
+    std::vector<uint64_t> hM(M.size());
+    for (int64_t i = 0; i < M.size(); ++i) {
+      order[i] = i;
+      wM[i] = weight(sim.psi[find_key(sim.S, M.at(i))]);
+      hM[i] = tiebreak_hash(M.at(i), m.W);
+    }
+    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+      if (wM[a] != wM[b]) return wM[a] > wM[b];
+      if (hM[a] != hM[b]) return hM[a] < hM[b];
+      return key_less(M.at(a), M.at(b), m.W);
+    });
+    const int64_t nMfull = M.size();
+    int64_t q = (sim.fresh || sim.prev_nM == 0 || sim.prev_nS == 0)
+                    ? cap / (m.slot_count() + 1)
+                    : cap * sim.prev_nM / sim.prev_nS;
+    for (;;) {
+      const int64_t qe = std::min(q, nMfull);
+      Keys cut;
+      cut.W = m.W;
+      for (int64_t i = 0; i < qe; ++i) cut.push(M.at(order[i]));
+      Keys Mq = sort_unique(cut);
+      expand(m, Mq, k, ball, frontier);
+      if (ball.size() <= cap) {
+        M = Mq;
+        break;
+      }
+      q = 9 * qe * cap / (10 * ball.size());
+    }
+  }
   // transfer: post-adaptation detruncation
   std::vector<cplx> phi(ball.size(), cplx(0, 0));
   double mass = 0;
@@ -501,6 +565,8 @@ int sim_step(Sim& sim) {
   sim.t = sim.t + sim.p.dt;
   sim.mass_total += mass;
   sim.fresh = false;
+  sim.prev_nS = ball.size();
+  sim.prev_nM = M.size();
   // observables at the new time
   Obs o;
   o.pop.assign(m.N, 0.0);
@@ -994,6 +1060,11 @@ int orc_sim_create(const void* mp, const orc_params* p, int64_t n,
   s->p.k_init = p->k_init;
   s->p.theta = p->theta;
   s->p.max_terms = p->max_terms > 0 ? p->max_terms : 200;
+  if (p->max_states < 0) {
+    delete s;
+    return fail("bad state cap");
+  }
+  s->p.max_states = p->max_states;
   if (load_state(*m, n, keys.data(), coef, s->S, s->psi)) {
     delete s;
     return 1;

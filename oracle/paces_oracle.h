@@ -49,6 +49,9 @@ typedef struct {
   int32_t k_init;        /* neighbour order of the first step               */
   double theta;          /* keep a row iff |c| >= theta                     */
   int32_t max_terms;     /* error when the series needs more terms          */
+  int64_t max_states;    /* cap on |S|: when the ball of M exceeds it, M is
+                            cut to its heaviest rows (see the source); 0 =
+                            no cap                                          */
 } orc_params;
 
 /* Observables recorded after each step (field order of orc_sim_obs). */

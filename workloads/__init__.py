@@ -61,27 +61,27 @@ CONFIGS = {
         _lattice(1, [4], [1]), n_modes=1, cutoff=[4], omega=[1.0], g=[1.0],
         J=[-0.5], eps_sigma=0.0, eps_seed=None, n_real=1,
         dt=0.01, steps=500, k=4, k_init=4, theta=1e-10, precision=64,
-        init="local", cap_states=0),
+        init="local", max_states=0),
     "ring16": dict(
         _lattice(1, [16], [1]), n_modes=1, cutoff=[12], omega=[1.0], g=[1.2],
         J=[-1.0], eps_sigma=0.0, eps_seed=None, n_real=1,
         dt=0.01, steps=4000, k=4, k_init=4, theta=1e-8, precision=64,
-        init="bloch", cap_states=0),
+        init="bloch", max_states=0),
     "sq6x6": dict(
         _lattice(2, [6, 6], [1, 1]), n_modes=1, cutoff=[15], omega=[1.0],
         g=[1.0], J=[-0.8, -0.8], eps_sigma=0.2, eps_seed=1000, n_real=64,
         dt=0.02, steps=2000, k=2, k_init=2, theta=1e-7, precision=32,
-        init="bloch", cap_states=10_000_000),
+        init="bloch", max_states=10_000_000),
     "cube4": dict(
         _lattice(3, [4, 4, 4], [1, 1, 1]), n_modes=2, cutoff=[15, 31],
         omega=[1.0, 0.2], g=[1.0, 0.5], J=[-0.5, -0.5, -0.5], eps_sigma=0.0,
         eps_seed=None, n_real=1, dt=0.01, steps=3000, k=2, k_init=2,
-        theta=1e-7, precision=32, init="local", cap_states=500_000_000),
+        theta=1e-7, precision=32, init="local", max_states=500_000_000),
     "ring12": dict(
         _lattice(1, [12], [1]), n_modes=1, cutoff=[10], omega=[1.0], g=[1.0],
         J=[-1.0], eps_sigma=0.1, eps_seed=42, n_real=1,
         dt=0.01, steps=2000, k=4, k_init=4, theta=1e-8, precision=64,
-        init="bloch", cap_states=0, ckpt_every=50),
+        init="bloch", max_states=0, ckpt_every=50),
 }
 
 
@@ -159,7 +159,7 @@ def run_params(cfg, **override):
     c.update(override)
     return {"dt": c["dt"], "k": c["k"], "k_init": c["k_init"],
             "theta": c["theta"], "precision": c["precision"],
-            "cap_states": c.get("cap_states", 0)}
+            "max_states": c.get("max_states", 0)}
 
 
 def random_amplitudes(seed, n):
