@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define PACES_ABI_VERSION 4
+#define PACES_ABI_VERSION 5
 
 typedef enum {
   PACES_OK = 0,
@@ -106,6 +106,15 @@ typedef struct {
   double tol;          /* series tail tolerance, 0 = 1e-16                 */
   int32_t k_max_terms; /* limit on series terms, 0 = 128                   */
   uint32_t obs_mask;   /* PACES_OBS_* bits; 0 = all                        */
+  int64_t max_states;  /* cap on |S| per realization, 0 = none.  When the
+                          new set of a realization would exceed it, its
+                          selection M is cut to the q heaviest rows
+                          (weight descending, then a splitmix64 hash of
+                          the canonical key, then the key), q =
+                          floor(cap |M_prev| / |S_prev|) from its last
+                          record (floor(cap / (D+1)) without one), and
+                          while the set still exceeds the cap
+                          q <- floor(9 min(q, |M|) cap / (10 |S|))       */
 } paces_run_params;
 
 #define PACES_OBS_ENERGY 1u /* <psi|H_eff|psi> per step (one extra SpMV

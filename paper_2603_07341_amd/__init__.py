@@ -58,7 +58,8 @@ class _Run(C.Structure):
     _fields_ = [("dt", C.c_double), ("k", C.c_int32), ("k_init", C.c_int32),
                 ("theta", C.c_double), ("cap_states", C.c_int64),
                 ("precision", C.c_int32), ("tol", C.c_double),
-                ("k_max_terms", C.c_int32), ("obs_mask", C.c_uint32)]
+                ("k_max_terms", C.c_int32), ("obs_mask", C.c_uint32),
+                ("max_states", C.c_int64)]
 
 
 class _Obs(C.Structure):
@@ -193,6 +194,7 @@ class Sim:
         r.tol = tol
         r.k_max_terms = k_max_terms
         r.obs_mask = obs_mask
+        r.max_states = int(run.get("max_states", 0))
         exc = np.ascontiguousarray(exc, dtype=np.int32)
         occ = np.ascontiguousarray(occ, dtype=np.uint16)
         coef = np.ascontiguousarray(coef, dtype=np.float64)

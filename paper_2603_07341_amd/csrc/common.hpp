@@ -68,6 +68,20 @@ inline int tiles_for(int64_t bound) {
   return int(g);
 }
 
+// |c|^2 as fl(fl(re*re) + fl(im*im)) in FP64 (FP32 amplitudes widened
+// first), compared with theta^2: the same predicate on every path.
+__device__ __forceinline__ double weight(double2 c) {
+  return __dadd_rn(__dmul_rn(c.x, c.x), __dmul_rn(c.y, c.y));
+}
+__device__ __forceinline__ double weight(float2 c) {
+  const double x = c.x, y = c.y;
+  return __dadd_rn(__dmul_rn(x, x), __dmul_rn(y, y));
+}
+__device__ __forceinline__ double2 widen(double2 c) { return c; }
+__device__ __forceinline__ double2 widen(float2 c) {
+  return make_double2(c.x, c.y);
+}
+
 __device__ __forceinline__ int64_t gtid() {
   return int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
 }

@@ -30,6 +30,7 @@ enum : int {
   kErrNonFinite = 4,
   kErrTerms = 8,       // series longer than the allowed maximum
   kErrNeedTerms = 16,  // more series launches needed than enqueued
+  kErrCap = 32,        // a realization's new set exceeds the state cap
 };
 
 // Model constants passed by value to every kernel.

@@ -120,15 +120,6 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ---- select -----------------------------------------------------------------
-// |c|^2 as fl(fl(re*re) + fl(im*im)) in FP64 (FP32 amplitudes widened
-// first), compared with theta^2: the same predicate on every path.
-__device__ __forceinline__ double weight(double2 c) {
-  return __dadd_rn(__dmul_rn(c.x, c.x), __dmul_rn(c.y, c.y));
-}
-__device__ __forceinline__ double weight(float2 c) {
-  const double x = c.x, y = c.y;
-  return __dadd_rn(__dmul_rn(x, x), __dmul_rn(y, y));
-}
 
 template <typename Amp>
 __global__ void __launch_bounds__(kBlock)
@@ -164,6 +155,41 @@ __global__ void __launch_bounds__(kBlock)
       uint32_t tot;
       const uint32_t off = block_excl_scan(keep ? 1u : 0u, &tot) + run;
       if (keep) midx[off] = uint32_t(e);
+      run += tot;
+    }
+  }
+}
+
+// Selection given as one flag per old row (state cap): same tile layout.
+__global__ void __launch_bounds__(kBlock)
+    k_flag_count(const uint8_t* keep, const StepCtl* ctl, uint32_t* bsum) {
+  const int64_t n = ctl->n_old, ntiles = cdiv(n, kTile);
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int q = 0; q < kItems; ++q) {
+      const int64_t e = t * kTile + q * kBlock + threadIdx.x;
+      if (e < n && keep[e]) ++v;
+    }
+    uint32_t tot;
+    block_excl_scan(v, &tot);
+    if (threadIdx.x == 0) bsum[t] = tot;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_flag_write(const uint8_t* keep, const StepCtl* ctl,
+                 const uint32_t* bsum, uint32_t* midx) {
+  const int64_t n = ctl->n_old, ntiles = cdiv(n, kTile);
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    uint32_t run = bsum[t];
+#pragma unroll
+    for (int q = 0; q < kItems; ++q) {
+      const int64_t e = t * kTile + q * kBlock + threadIdx.x;
+      const bool k = e < n && keep[e];
+      uint32_t tot;
+      const uint32_t off = block_excl_scan(k ? 1u : 0u, &tot) + run;
+      if (k) midx[off] = uint32_t(e);
       run += tot;
     }
   }
@@ -463,10 +489,6 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ---- transfer ---------------------------------------------------------------
-__device__ __forceinline__ double2 widen(double2 c) { return c; }
-__device__ __forceinline__ double2 widen(float2 c) {
-  return make_double2(c.x, c.y);
-}
 
 template <int W, typename Amp>
 __global__ void __launch_bounds__(kBlock)
@@ -1099,6 +1121,15 @@ void select_rows(int prec, const void* psi, double th2, bool select_all,
     k_select_write<double2><<<g, kBlock, 0, s>>>((const double2*)psi, ctl, th2, tmp, midx);
   else
     k_select_write<float2><<<g, kBlock, 0, s>>>((const float2*)psi, ctl, th2, tmp, midx);
+}
+
+void select_flags(const uint8_t* keep, StepCtl* ctl, uint32_t* midx,
+                  uint32_t* tmp, int64_t cap, int* err, hipStream_t s) {
+  const int g = tiles_for(cap);
+  k_flag_count<<<g, kBlock, 0, s>>>(keep, ctl, tmp);
+  k_scan_bsum<<<1, kBlock, 0, s>>>(tmp, &ctl->n_old, &ctl->nM, &ctl->fstart[1],
+                                   err);
+  k_flag_write<<<g, kBlock, 0, s>>>(keep, ctl, tmp, midx);
 }
 
 void insert_rows(const DevModel& m, int Wi, const Side& o, const Side& n,

@@ -76,6 +76,9 @@ void begin_step(StepCtl* ctl, int* err, uint32_t* cnt, int R, hipStream_t s);
 void select_rows(int prec, const void* psi, double th2, bool select_all,
                  bool counted, StepCtl* ctl, uint32_t* midx, uint32_t* tmp,
                  int64_t cap, int* err, hipStream_t s);
+// Rows of ctl->n_old with keep[row] != 0, ascending, into midx; ctl->nM.
+void select_flags(const uint8_t* keep, StepCtl* ctl, uint32_t* midx,
+                  uint32_t* tmp, int64_t cap, int* err, hipStream_t s);
 // Rows 0..nM-1 of the new side are M; inserted into the cleared table.
 void insert_rows(const DevModel& m, int Wi, const Side& o, const Side& n,
                  const uint32_t* midx, const StepCtl* ctl, uint64_t* table,

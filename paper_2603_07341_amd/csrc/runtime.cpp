@@ -25,6 +25,7 @@
 
 #include "../../include/paces.h"
 #include "adjoint.hpp"
+#include "cap.hpp"
 #include "kernels.hpp"
 
 using namespace paces;
@@ -236,6 +237,21 @@ struct paces_sim {
   int64_t n0 = 0;
   int32_t* p0_last = nullptr;  // [R][n0] rows of the initial states in S
   AdjRecord* adj = nullptr;
+
+  // state cap (max_states per realization)
+  uint32_t* ball = nullptr;       // [R] rows of the new set per realization
+  bool cap_active = false;        // the step runs with a cut selection
+  int64_t cap_buf = 0;            // rows the buffers below hold
+  uint8_t* keep = nullptr;        // [rows] selection flags over old rows
+  uint32_t* midx_full = nullptr;  // [rows] the step's full selection
+  int64_t nM_full = 0;
+  uint64_t *cap_w = nullptr, *cap_h = nullptr;  // [rows] sort keys
+  uint8_t* cap_status = nullptr;  // [rows] 0 open, 1 kept, 2 dropped
+  uint32_t* cap_hist = nullptr;   // [R][256]
+  int32_t *cap_mode = nullptr, *cap_dstar = nullptr;  // [R]
+  int8_t* cap_capped = nullptr;   // [R]
+  std::vector<int64_t> cap_q, cap_nM;
+  std::vector<int8_t> cap_on;
 
   double* ring = nullptr;
   int64_t ring_cap = 0;
@@ -549,6 +565,9 @@ void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st,
     Stage sg(s, PACES_STAGE_SELECT, st);
     if (fz)
       adj_set_frozen(s->ctl, s->cnt, uint32_t(fz->nM), s->err, st);
+    else if (s->cap_active)
+      select_flags(s->keep, s->ctl, s->midx, s->scan_tmp,
+                   std::min(bucket(s->nS), s->cap), s->err, st);
     else
       select_rows(s->prec, s->vec[s->ipsi], s->th2, s->fresh, counted,
                   s->ctl, s->midx, s->scan_tmp,
@@ -572,6 +591,9 @@ void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st,
                    s->tmask, s->rb, s->col, s->vec[s->iphi], s->err, st);
     lookup_last(dm, Wi, sn, k, s->ctl, est, s->table, s->tmask, s->col,
                 s->cap, s->err, st);
+    if (s->p.max_states > 0)
+      cap_check(dm, s->ctl, sn.pay, est, s->p.max_states, s->ball, s->err,
+                st);
   }
   int n_mass = 0, n_e = 0;
   {
@@ -663,6 +685,136 @@ paces_status launch_step_graph(paces_sim* s, int64_t est, bool counted,
   return PACES_OK;
 }
 
+// State cap: some realization's new set exceeds max_states.  Cut its
+// selection to the q heaviest rows (weight descending, splitmix64 key hash
+// ascending, key ascending) with q = floor(cap |M_prev| / |S_prev|) from
+// the last record (floor(cap / (D+1)) without one), and on every further
+// overflow q <- floor(9 min(q, |M|) cap / (10 |ball|)); the full selection
+// of the step is kept for the repeated cuts.
+paces_status cap_select(paces_sim* s, hipStream_t st) {
+  const paces_model* m = s->m;
+  const int R = m->R;
+  const int64_t cap = s->p.max_states;
+  std::vector<uint32_t> ball(R), cnt(R);
+  HIP_TRY(hipMemcpyAsync(ball.data(), s->ball, size_t(R) * 4,
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(cnt.data(), s->cnt, size_t(R) * 4,
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (!s->cap_active) {
+    if (s->cap_buf < s->cap) {
+      dfree(s->keep);
+      dfree(s->midx_full);
+      dfree(s->cap_w);
+      dfree(s->cap_h);
+      dfree(s->cap_status);
+      ST_TRY(dalloc(&s->keep, s->cap));
+      ST_TRY(dalloc(&s->midx_full, s->cap));
+      ST_TRY(dalloc(&s->cap_w, s->cap));
+      ST_TRY(dalloc(&s->cap_h, s->cap));
+      ST_TRY(dalloc(&s->cap_status, s->cap));
+      s->cap_buf = s->cap;
+    }
+    if (!s->cap_hist) {
+      ST_TRY(dalloc(&s->cap_hist, int64_t(R) * 256));
+      ST_TRY(dalloc(&s->cap_mode, R));
+      ST_TRY(dalloc(&s->cap_dstar, R));
+      ST_TRY(dalloc(&s->cap_capped, R));
+    }
+    s->nM_full = s->h_ctl->nM;
+    if (s->nM_full > 0)
+      HIP_TRY(hipMemcpyAsync(s->midx_full, s->midx, size_t(s->nM_full) * 4,
+                             hipMemcpyDeviceToDevice, st));
+    s->cap_nM.assign(cnt.begin(), cnt.end());
+    s->cap_on.assign(R, 0);
+    s->cap_q.assign(R, 0);
+  }
+  // counts of the last recorded step per realization
+  std::vector<double> prev;
+  if (!s->fresh && s->h.nrec > 0) {
+    prev.resize(size_t(R) * s->rec_doubles);
+    HIP_TRY(hipMemcpyAsync(prev.data(),
+                           s->ring + (int64_t(s->h.nrec) - 1) * R * s->rec_doubles,
+                           prev.size() * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  for (int r = 0; r < R; ++r) {
+    if (int64_t(ball[r]) <= cap) continue;
+    if (!s->cap_on[r]) {
+      s->cap_on[r] = 1;
+      const int64_t nSp = prev.empty() ? 0 : int64_t(prev[size_t(r) * s->rec_doubles + 7]);
+      const int64_t nMp = prev.empty() ? 0 : int64_t(prev[size_t(r) * s->rec_doubles + 8]);
+      s->cap_q[r] = (nSp > 0 && nMp > 0) ? cap * nMp / nSp : cap / (m->D + 1);
+    } else {
+      const int64_t qe = std::min(s->cap_q[r], s->cap_nM[r]);
+      s->cap_q[r] = 9 * qe * cap / (10 * int64_t(ball[r]));
+    }
+  }
+  // radix select over the capped realizations
+  const int Wi = m->Wi, W = m->W;
+  const Side& so = s->side[s->cur];
+  std::vector<int8_t> capped(s->cap_on.begin(), s->cap_on.end());
+  HIP_TRY(hipMemcpyAsync(s->cap_capped, capped.data(), size_t(R),
+                         hipMemcpyHostToDevice, st));
+  cap_prepare(m->dm, Wi, W, s->prec, s->midx_full, s->nM_full, so.keys,
+              so.pay, s->vec[s->ipsi], s->cap_capped, s->cap_w, s->cap_h,
+              s->cap_status, st);
+  std::vector<int64_t> need(R, 0);
+  std::vector<int32_t> mode(R, kCapSkip), dstar(R, 0);
+  std::vector<char> open(R, 0);
+  for (int r = 0; r < R; ++r) {
+    if (!s->cap_on[r]) continue;
+    need[r] = std::min(s->cap_q[r], s->cap_nM[r]);
+    if (need[r] == 0)
+      mode[r] = kCapDrop;
+    else if (need[r] == s->cap_nM[r])
+      mode[r] = kCapKeep;
+    else
+      open[r] = 1;
+  }
+  std::vector<uint32_t> hist(size_t(R) * 256);
+  for (int pass = 0; pass <= cap_passes(W); ++pass) {
+    HIP_TRY(hipMemcpyAsync(s->cap_mode, mode.data(), size_t(R) * 4,
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->cap_dstar, dstar.data(), size_t(R) * 4,
+                           hipMemcpyHostToDevice, st));
+    cap_apply(m->dm, Wi, W, std::max(pass - 1, 0), s->midx_full, s->nM_full,
+              so.keys, so.pay, s->cap_w, s->cap_h, s->cap_mode, s->cap_dstar,
+              s->cap_status, st);
+    std::fill(mode.begin(), mode.end(), int32_t(kCapSkip));
+    if (std::find(open.begin(), open.end(), 1) == open.end()) break;
+    if (pass == cap_passes(W))
+      return fail(PACES_E_STATE, "state cap: rows left undecided");
+    HIP_TRY(hipMemsetAsync(s->cap_hist, 0, hist.size() * 4, st));
+    cap_hist(m->dm, Wi, W, pass, s->midx_full, s->nM_full, so.keys, so.pay,
+             s->cap_w, s->cap_h, s->cap_status, s->cap_hist, st);
+    HIP_TRY(hipMemcpyAsync(hist.data(), s->cap_hist, hist.size() * 4,
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int r = 0; r < R; ++r) {
+      if (!open[r]) continue;
+      const uint32_t* h = hist.data() + size_t(r) * 256;
+      int64_t below = 0;
+      int d = 0;
+      for (; d < 255; ++d) {
+        if (below + h[d] >= need[r]) break;
+        below += h[d];
+      }
+      need[r] -= below;
+      dstar[r] = d;
+      if (need[r] == int64_t(h[d])) {
+        mode[r] = kCapCut;
+        open[r] = 0;
+      } else {
+        mode[r] = kCapSplit;
+      }
+    }
+  }
+  cap_flags(s->midx_full, s->nM_full, s->cap_status, s->keep, s->nS, st);
+  s->cap_active = true;
+  return PACES_OK;
+}
+
 // One step: enqueue, read back the counts, repeat with more room when a
 // capacity was exceeded.
 paces_status do_step(paces_sim* s, hipStream_t st,
@@ -684,8 +836,10 @@ paces_status do_step(paces_sim* s, hipStream_t st,
     s->tmask = std::min<uint64_t>(P - 1, s->tmask_alloc);
   }
   const bool graph = s->tune.graph && !s->prof && !fz;
+  s->cap_active = false;
   for (int attempt = 0; attempt < 40; ++attempt) {
-    const bool counted = s->counts_valid && attempt == 0 && !fz;
+    const bool counted = s->counts_valid && attempt == 0 && !fz &&
+                         !s->cap_active;
     if (graph && attempt == 0)
       ST_TRY(launch_step_graph(s, est, counted, st));
     else
@@ -726,9 +880,14 @@ paces_status do_step(paces_sim* s, hipStream_t st,
       s->launched = std::max(4, std::min(K + 2, kMaxTerms));
       s->acc.rows_steps += double(c.n_new);
       s->counts_valid = true;
+      s->cap_active = false;
       return PACES_OK;
     }
     drop_pending(s);
+    if (e == kErrCap) {
+      ST_TRY(cap_select(s, st));
+      continue;
+    }
     if (e & (kErrTerms | kErrNonFinite)) return check_latch_code(s, e);
     if (e & kErrNeedTerms) {
       s->launched = std::min(int(s->h_ctl->kmax) + 2, kMaxTerms);
@@ -1250,7 +1409,8 @@ paces_status paces_init_state(const paces_model* m, const paces_run_params* p,
   if (!(p->dt > 0) || p->k < 0 || p->k_init < 0 || p->k > kMaxRounds ||
       p->k_init > kMaxRounds || !(p->theta >= 0) ||
       (p->precision != 64 && p->precision != 32) || p->k_max_terms < 0 ||
-      p->k_max_terms > kMaxTerms || p->tol < 0 || p->cap_states < 0)
+      p->k_max_terms > kMaxTerms || p->tol < 0 || p->cap_states < 0 ||
+      p->max_states < 0 || p->max_states >= (int64_t(1) << 31))
     return fail(PACES_E_ARG, "bad run parameters");
   const int R = m->R;
   if (n * R > (int64_t(1) << 30)) return fail(PACES_E_ARG, "too many states");
@@ -1301,6 +1461,7 @@ paces_status paces_init_state(const paces_model* m, const paces_run_params* p,
   if (dalloc(&s->ctl, 1) || dalloc(&s->err, 1) || dalloc(&s->parts, nparts) ||
       dalloc(&s->cc, R) || dalloc(&s->a2, 2 * R) || dalloc(&s->cnt, 2 * R) ||
       dalloc(&s->mass_tot, R) || dalloc(&s->p0_last, nt) ||
+      dalloc(&s->ball, R) ||
       dalloc(&s->keys0, nt * m->Wi) ||
       dalloc(&s->amps0, 2 * nt))
     return cleanup(PACES_E_OOM);
@@ -1350,6 +1511,16 @@ paces_status paces_free_sim(paces_sim* s) {
   dfree(s->cnt);
   dfree(s->mass_tot);
   dfree(s->p0_last);
+  dfree(s->ball);
+  dfree(s->keep);
+  dfree(s->midx_full);
+  dfree(s->cap_w);
+  dfree(s->cap_h);
+  dfree(s->cap_status);
+  dfree(s->cap_hist);
+  dfree(s->cap_mode);
+  dfree(s->cap_dstar);
+  dfree(s->cap_capped);
   dfree(s->keys0);
   dfree(s->amps0);
   dfree(s->ring);

@@ -1,0 +1,103 @@
+"""State cap (max_states) on the GPU vs the oracle, through the C ABI.
+
+When a realization's new set would exceed the cap, both sides cut its
+selection to the same heaviest prefix (weight, splitmix64 key hash, key);
+sets must agree bit for bit at every step, amplitudes within 1e-10.  Ties
+of equal weights (translation-invariant ring, Bloch start) exercise the
+hash tie-break; the batched case cuts only the realizations that overflow.
+"""
+import numpy as np
+import pytest
+
+import paper_2603_07341_amd as P
+from oracle import oracle as O
+from tests.gpu_helpers import assert_same_set, check_obs, rel_err, sort_rows
+import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+BASE = dict(extent=[6, 1, 1], cutoff=[4], theta=1e-6, k=2, k_init=2)
+
+
+def pair(cap, **over):
+    cfg = dict(WL.CONFIGS["ring12"])
+    cfg.update(BASE)
+    cfg.update(over)
+    p = WL.model_params(cfg)
+    run = WL.run_params(cfg)
+    run["max_states"] = cap
+    init = WL.initial_state(cfg)
+    return (cfg, P.Sim(P.Model(p), run, *init), O.Sim(O.Model(p), run, *init))
+
+
+@pytest.mark.parametrize("cap,over", [
+    (400, {}),                                  # local start
+    (300, dict(init="bloch", eps_sigma=0.0)),   # ties on ring orbits
+    (900, dict(extent=[3, 3, 1], ndim=2, periodic=[1, 1, 0], J=[-0.8, -0.6],
+               cutoff=[2], theta=1e-5)),
+])
+def test_capped_steps_match_oracle(cap, over):
+    cfg, gs, os_ = pair(cap, **over)
+    _, _, free = pair(0, **over)
+    free.step(12)
+    assert max(o["n_S"] for o in free.observations()) > cap  # the cap binds
+    for step in range(12):
+        gs.step(1)
+        os_.step(1)
+        go, oo = gs.observations()[-1], os_.observations()[-1]
+        assert go["n_S"] <= cap
+        for which in (O.SET_M, O.SET_S):
+            assert_same_set(gs.get_set(which), os_.get_set(which),
+                            "step %d set %d" % (step, which))
+        gk, ga = sort_rows(*gs.state())
+        ok, oa = os_.state()
+        assert np.array_equal(gk, ok)
+        assert rel_err(ga, oa) <= 1e-10
+        check_obs(go, oo, 1e-10, width=oo["E_max"] - oo["E_min"])
+
+
+def test_cap_binds_and_matches_uncapped_until_it_does():
+    cfg, gs, os_ = pair(400)
+    _, free, _ = pair(0)
+    bound = False
+    for step in range(10):
+        gs.step(1)
+        free.step(1)
+        if free.observations()[-1]["n_S"] > 400:
+            bound = True
+            assert gs.observations()[-1]["n_S"] <= 400
+        elif not bound:
+            a = sort_rows(*gs.state())
+            b = sort_rows(*free.state())
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert bound
+
+
+def test_batched_cap_cuts_each_realization_like_the_oracle():
+    cfg = dict(WL.CONFIGS["ring12"])
+    cfg.update(BASE)
+    cfg.update(eps_sigma=0.5, eps_seed=77)
+    R, cap, steps = 3, 350, 8
+    run = WL.run_params(cfg)
+    run["max_states"] = cap
+    init = WL.initial_state(cfg)
+    bs = P.Sim(P.Model(WL.batch_params(cfg, R)), run, *init)
+    bs.step(steps)
+    bk, ba, br = bs.state(with_real=True)
+    for r in range(R):
+        os_ = O.Sim(O.Model(WL.model_params(cfg, r)), run, *init)
+        os_.step(steps)
+        ok, oa = os_.state()
+        rk, ra = sort_rows(bk[br == r], ba[br == r])
+        assert np.array_equal(rk, ok), r
+        assert rel_err(ra, oa) <= 1e-10
+        for g, o in zip(bs.observations(r), os_.observations()):
+            assert g["n_S"] == o["n_S"] and g["n_M"] == o["n_M"]
+
+
+def test_tiny_cap_truncates_everything():
+    cfg, gs, os_ = pair(1)
+    gs.step(2)
+    os_.step(2)
+    assert gs.size() == os_.size() <= 1
+    assert gs.observations()[-1]["n_S"] == os_.observations()[-1]["n_S"]
