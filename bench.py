@@ -42,6 +42,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--tune", default="auto", choices=["auto", "none"],
+                    help="run the library's launch autotuner on the warmed-up "
+                         "state before timing (results do not depend on it)")
     ap.add_argument("--batch-steps", type=int, default=40)
     ap.add_argument("--batch-singles", type=int, default=8)
     ap.add_argument("--adjoint-steps", type=int, default=200)
@@ -78,6 +81,8 @@ def main():
     sim = P.Sim(model, run, exc, occ, coef, stream=stream)
     print("warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
     sim.step(args.warmup, stream=stream)
+    torch.cuda.synchronize()
+    tuning = sim.autotune(steps=2, stream=stream) if args.tune == "auto" else sim.tuning()
     torch.cuda.synchronize()
     nS0 = sim.size(stream)
     cpu_state = None
@@ -138,6 +143,7 @@ def main():
                      "bytes_per_launch": term_bytes,
                      "bytes_per_row": row_bytes},
         "stage_ms": stage_ms,
+        "tuning": tuning,
         "terms_per_step": float(rec[:, 9].mean()),
     }
     if not args.no_forms and args.config == "ring16" and args.precision == 64:
@@ -274,7 +280,7 @@ def form_adjoint(args, stream):
 def source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ["kernels.hip", "device.hpp", "kernels.hpp"]:
+    for f in ["kernels.hip", "device.hpp", "kernels.hpp", "common.hpp"]:
         with open(os.path.join(ROOT, "paper_2603_07341_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -268,7 +268,9 @@ typedef struct {
                           bucketed sizes and rebuilt when buffers move);
                           ignored while profiling is enabled              */
   int32_t table_shift; /* hash table probed over >= est * 2^shift entries
-                          (1..3; load factor at most 2^-shift)            */
+                          (0..3), est = 1.5 x the current set: a smaller
+                          table stays in the last-level cache, a larger
+                          one shortens probe chains                       */
   int32_t term_rows;   /* rows per thread of the Clenshaw grid: 1,2,4,8  */
 } paces_tuning;
 /* Default {0, 1, 1}. */
@@ -277,7 +279,7 @@ paces_status paces_get_tuning(paces_sim* s, paces_tuning* out);
 paces_status paces_set_tuning(paces_sim* s, const paces_tuning* t,
                               void* hip_stream);
 /* Time 1 + steps trial steps from the current state for each setting of
- * {graph 0/1} x {table_shift 1, 2} x {term_rows 1, 2, 4}, keep the fastest,
+ * {graph 0/1} x {table_shift 0, 1, 2} x {term_rows 1, 2, 4}, keep the fastest,
  * and restore the state as it was (records of the trials are discarded;
  * the sets of the last step are no longer available).  steps 1..64. */
 paces_status paces_autotune(paces_sim* s, int32_t steps, paces_tuning* chosen,

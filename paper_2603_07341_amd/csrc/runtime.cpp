@@ -1007,7 +1007,7 @@ paces_status resize_table(paces_sim* s, hipStream_t st) {
 }
 
 paces_status check_tuning(const paces_tuning* t) {
-  if (!t || (t->graph != 0 && t->graph != 1) || t->table_shift < 1 ||
+  if (!t || (t->graph != 0 && t->graph != 1) || t->table_shift < 0 ||
       t->table_shift > 3 ||
       (t->term_rows != 1 && t->term_rows != 2 && t->term_rows != 4 &&
        t->term_rows != 8))
@@ -2070,7 +2070,7 @@ paces_status paces_autotune(paces_sim* s, int32_t steps, paces_tuning* chosen,
                         hipEventCreate(&b) != hipSuccess))
     r = fail(PACES_E_HIP, "event creation failed");
   for (int g = 0; g < 2 && r == PACES_OK; ++g)
-    for (int sh = 1; sh <= 2 && r == PACES_OK; ++sh)
+    for (int sh = 0; sh <= 2 && r == PACES_OK; ++sh)
       for (int tr : {1, 2, 4}) {
         paces_tuning t{g, sh, tr};
         r = paces_set_tuning(s, &t, hip_stream);
