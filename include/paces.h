@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define PACES_ABI_VERSION 5
+#define PACES_ABI_VERSION 7
 
 typedef enum {
   PACES_OK = 0,
@@ -115,6 +115,11 @@ typedef struct {
                           record (floor(cap / (D+1)) without one), and
                           while the set still exceeds the cap
                           q <- floor(9 min(q, |M|) cap / (10 |S|))       */
+  int64_t q_nom;       /* fixed-size truncation (the paper's q_nom), 0 =
+                          off: after the first step M is the q_nom
+                          heaviest rows of each realization's set in the
+                          same order as the state cap, and theta is not
+                          used.  Exclusive with max_states.               */
 } paces_run_params;
 
 #define PACES_OBS_ENERGY 1u /* <psi|H_eff|psi> per step (one extra SpMV
@@ -135,6 +140,19 @@ typedef struct {
  * E_min, E_max) followed by the N populations. */
 int32_t paces_record_doubles(const paces_model* m);
 
+/* Device memory of the library (set tables, vectors, hash table,
+ * records) from the caller's allocator: alloc(bytes, stream, user) returns
+ * device memory or NULL, release(ptr, stream, user) frees it; stream is
+ * passed as NULL (the library synchronises its stream before it frees).
+ * Both NULL restores hipMalloc / hipFree.  Only while the library holds no
+ * device memory (else PACES_E_STATE): set it before the first
+ * paces_init_state. */
+paces_status paces_set_allocator(void* (*alloc)(size_t bytes, void* stream,
+                                                void* user),
+                                 void (*release)(void* ptr, void* stream,
+                                                 void* user),
+                                 void* user);
+
 /* Load a model: validates the description and builds the neighbour table,
  * the key layout and the g*sqrt(n) table on the host.  The tables are copied
  * to the current device by the first paces_init_state on the model, so the
@@ -144,6 +162,8 @@ paces_status paces_free_model(paces_model* m);
 /* N sites, W words per key, D slots per row, B key bits. */
 paces_status paces_model_info(const paces_model* m, int32_t* N, int32_t* W,
                               int32_t* D, int32_t* B);
+/* W: 64-bit words per canonical key. */
+paces_status paces_model_key_words(const paces_model* m, int32_t* W);
 /* Host codec: exc[n], occ[n*N*V] (site-major) <-> keys[n*W]. */
 paces_status paces_pack_keys(const paces_model* m, int64_t n,
                              const int32_t* exc, const uint16_t* occ,
@@ -176,6 +196,12 @@ paces_status paces_num_records(paces_sim* s, int64_t* n);
  * out[n][R][paces_record_doubles]; synchronises. */
 paces_status paces_series(paces_sim* s, int64_t first, int64_t n,
                           double* out, void* hip_stream);
+
+/* One field (0 .. paces_record_doubles - 1) of the records of steps
+ * first..first+n-1 into device memory dev_out[n][R] (f64), asynchronous
+ * on the stream (e.g. straight into a torch tensor). */
+paces_status paces_series_field(paces_sim* s, int32_t field, void* dev_out,
+                                int64_t first, int64_t n, void* hip_stream);
 
 /* Current state: *n rows; keys[n*W], amps[2n], real[n] the realization of
  * each row (host; each may be NULL, all NULL to query the size).

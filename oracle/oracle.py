@@ -27,7 +27,7 @@ class _Desc(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("k", C.c_int32), ("k_init", C.c_int32),
                 ("theta", C.c_double), ("max_terms", C.c_int32),
-                ("max_states", C.c_int64)]
+                ("max_states", C.c_int64), ("q_nom", C.c_int64)]
 
 
 _lib = None
@@ -134,6 +134,7 @@ class Sim:
         p.theta = run["theta"]
         p.max_terms = max_terms
         p.max_states = int(run.get("max_states", 0))
+        p.q_nom = int(run.get("q_nom", 0))
         exc = np.ascontiguousarray(exc, dtype=np.int32)
         occ = np.ascontiguousarray(occ, dtype=np.uint16)
         coef = np.ascontiguousarray(coef, dtype=np.float64)
@@ -252,6 +253,7 @@ class Frozen:
         p.theta = run["theta"]
         p.max_terms = max_terms
         p.max_states = int(run.get("max_states", 0))
+        p.q_nom = int(run.get("q_nom", 0))
         exc = np.ascontiguousarray(exc, dtype=np.int32)
         occ = np.ascontiguousarray(occ, dtype=np.uint16)
         coef = np.ascontiguousarray(coef, dtype=np.float64)

@@ -431,6 +431,7 @@ struct Params {
   double dt = 0.01, theta = 0;
   int k = 2, k_init = 2, max_terms = 200;
   int64_t max_states = 0;  // cap on |S| (0 = none)
+  int64_t q_nom = 0;       // fixed-size truncation (0 = threshold)
 };
 
 // ---------------------------------------------------------------------------
@@ -498,6 +499,25 @@ int sim_step(Sim& sim) {
   if (sim.fresh) {
     M = sim.S;
     k = sim.p.k_init;
+  } else if (sim.p.q_nom > 0) {
+    // the paper's fixed-size truncation: the q_nom heaviest rows, ties by
+    // the splitmix64 key hash, then the key
+    std::vector<int64_t> order(sim.S.size());
+    std::vector<double> w(sim.S.size());
+    std::vector<uint64_t> hs(sim.S.size());
+    for (int64_t i = 0; i < sim.S.size(); ++i) {
+      order[i] = i;
+      w[i] = weight(sim.psi[i]);
+      hs[i] = tiebreak_hash(sim.S.at(i), m.W);
+    }
+    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+      if (w[a] != w[b]) return w[a] > w[b];
+      if (hs[a] != hs[b]) return hs[a] < hs[b];
+      return a < b;  // S is sorted: row order is key order
+    });
+    const int64_t q = std::min<int64_t>(sim.p.q_nom, sim.S.size());
+    std::sort(order.begin(), order.begin() + q);
+    for (int64_t i = 0; i < q; ++i) M.push(sim.S.at(order[i]));
   } else {
     const double th2 = sim.p.theta * sim.p.theta;
     for (int64_t i = 0; i < sim.S.size(); ++i)
@@ -1065,6 +1085,11 @@ int orc_sim_create(const void* mp, const orc_params* p, int64_t n,
     return fail("bad state cap");
   }
   s->p.max_states = p->max_states;
+  if (p->q_nom < 0 || (p->q_nom > 0 && p->max_states > 0)) {
+    delete s;
+    return fail("bad q_nom");
+  }
+  s->p.q_nom = p->q_nom;
   if (load_state(*m, n, keys.data(), coef, s->S, s->psi)) {
     delete s;
     return 1;

@@ -52,6 +52,9 @@ typedef struct {
   int64_t max_states;    /* cap on |S|: when the ball of M exceeds it, M is
                             cut to its heaviest rows (see the source); 0 =
                             no cap                                          */
+  int64_t q_nom;         /* > 0: after the first step M is the q_nom
+                            heaviest rows (same order as the cap) instead
+                            of the threshold; exclusive with max_states     */
 } orc_params;
 
 /* Observables recorded after each step (field order of orc_sim_obs). */

@@ -36,7 +36,8 @@ EXPORTS = [
     "paces_get_phi", "paces_profile_enable", "paces_profile_get",
     "paces_profile_reset", "paces_get_tuning", "paces_set_tuning",
     "paces_autotune", "paces_num_params", "paces_adjoint_forward",
-    "paces_adjoint_replay", "paces_adjoint_backward",
+    "paces_adjoint_replay", "paces_adjoint_backward", "paces_set_allocator",
+    "paces_model_key_words", "paces_series_field",
 ]
 
 
@@ -59,7 +60,7 @@ class _Run(C.Structure):
                 ("theta", C.c_double), ("cap_states", C.c_int64),
                 ("precision", C.c_int32), ("tol", C.c_double),
                 ("k_max_terms", C.c_int32), ("obs_mask", C.c_uint32),
-                ("max_states", C.c_int64)]
+                ("max_states", C.c_int64), ("q_nom", C.c_int64)]
 
 
 class _Obs(C.Structure):
@@ -98,6 +99,35 @@ def lib():
         _lib.paces_record_doubles.restype = C.c_int32
         _lib.paces_num_params.restype = C.c_int32
     return _lib
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+_allocator_refs = None
+
+
+def use_torch_allocator(on=True):
+    """Take the library's device memory from torch's caching allocator
+    (on=True) or from hipMalloc (on=False).  Only while no model tables or
+    sims hold device memory."""
+    global _allocator_refs
+    if not on:
+        _check(lib().paces_set_allocator(None, None, None))
+        _allocator_refs = None
+        return
+
+    def _alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except Exception:  # out of memory: the library reports E_OOM
+            return None
+
+    def _free(ptr, stream, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    refs = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+    _check(lib().paces_set_allocator(refs[0], refs[1], None))
+    _allocator_refs = refs
 
 
 def _check(rc):
@@ -195,6 +225,7 @@ class Sim:
         r.k_max_terms = k_max_terms
         r.obs_mask = obs_mask
         r.max_states = int(run.get("max_states", 0))
+        r.q_nom = int(run.get("q_nom", 0))
         exc = np.ascontiguousarray(exc, dtype=np.int32)
         occ = np.ascontiguousarray(occ, dtype=np.uint16)
         coef = np.ascontiguousarray(coef, dtype=np.float64)
@@ -226,6 +257,22 @@ class Sim:
         d["a_re"], d["a_im"] = o.autocorr_re, o.autocorr_im
         d["pop"] = np.ctypeslib.as_array(o.pop, shape=(self.model.N,)).copy()
         return d
+
+    def series_field(self, field, out, first=0, n=None, stream=None):
+        """Copy one record field (index into OBS_FIELDS, or 12 + site for a
+        population) of steps first..first+n-1 into the float64 CUDA tensor
+        `out` ([n * R]), asynchronously on the stream."""
+        if n is None:
+            n = self.num_records() - first
+        if isinstance(field, str):
+            field = OBS_FIELDS.index(field)
+        if out.numel() < n * self.model.R or out.dtype != torch.float64:
+            raise ValueError("out needs n * R float64 entries")
+        _check(lib().paces_series_field(self.h, C.c_int32(field),
+                                        C.c_void_p(out.data_ptr()),
+                                        C.c_int64(first), C.c_int64(n),
+                                        _stream(stream)))
+        return out
 
     def num_records(self):
         n = C.c_int64()

@@ -73,6 +73,23 @@ __global__ void __launch_bounds__(kBlock)
     if (bins[r]) atomicAdd(&ball[r], bins[r]);
 }
 
+__global__ void __launch_bounds__(kBlock)
+    k_count_real(DevModel m, const uint64_t* pay, int64_t n, uint32_t* out) {
+  __shared__ uint32_t bins[kMaxReal];
+  for (int r = threadIdx.x; r < m.R; r += blockDim.x) bins[r] = 0;
+  __syncthreads();
+  for (int64_t i = gtid(); i < n; i += gstride())
+    atomicAdd(&bins[pay_real(pay[i])], 1u);
+  __syncthreads();
+  for (int r = threadIdx.x; r < m.R; r += blockDim.x)
+    if (bins[r]) atomicAdd(&out[r], bins[r]);
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_iota_u32(uint32_t* p, int64_t n) {
+  for (int64_t i = gtid(); i < n; i += gstride()) p[i] = uint32_t(i);
+}
+
 __global__ void k_cap_judge(const uint32_t* ball, int R, int64_t cap,
                             int* err) {
   if (*err) return;
@@ -175,6 +192,18 @@ void cap_check(const DevModel& m, const StepCtl* ctl, const uint64_t* pay,
   const int g = m.R == 1 ? 1 : std::min(grid_for(est), 2048);
   k_cap_count<<<g, kBlock, 0, s>>>(m, ctl, pay, ball, err);
   k_cap_judge<<<1, kBlock, 0, s>>>(ball, m.R, cap, err);
+}
+
+void count_per_real(const DevModel& m, const uint64_t* pay, int64_t n,
+                    uint32_t* out, hipStream_t s) {
+  (void)hipMemsetAsync(out, 0, size_t(m.R) * 4, s);
+  if (n <= 0) return;
+  k_count_real<<<std::min(grid_for(n), 2048), kBlock, 0, s>>>(m, pay, n, out);
+}
+
+void iota_u32(uint32_t* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_iota_u32<<<grid_for(n), kBlock, 0, s>>>(p, n);
 }
 
 void cap_prepare(const DevModel& m, int Wi, int W, int prec,

@@ -20,6 +20,12 @@ inline int cap_passes(int W) { return 16 + 8 * W; }
 void cap_check(const DevModel& m, const StepCtl* ctl, const uint64_t* pay,
                int64_t est, int64_t cap, uint32_t* ball, int* err,
                hipStream_t s);
+// Rows of a set per realization (out[R], cleared first; eager use only:
+// the clear is a memset).
+void count_per_real(const DevModel& m, const uint64_t* pay, int64_t n,
+                    uint32_t* out, hipStream_t s);
+// p[i] = i for i < n.
+void iota_u32(uint32_t* p, int64_t n, hipStream_t s);
 // Per selected row j (row midx[j] of the old side): status 1 (kept) for
 // realizations not capped, 0 (undecided) otherwise; the weight key and the
 // tie-break hash.

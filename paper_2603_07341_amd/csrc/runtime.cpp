@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -33,6 +34,9 @@ using namespace paces;
 namespace {
 
 thread_local std::string g_err;
+
+paces_status dev_alloc(void** p, size_t bytes);
+void dev_free(void* p);
 
 paces_status fail(paces_status st, const std::string& msg) {
   g_err = msg;
@@ -64,17 +68,49 @@ paces_status dalloc(T** p, int64_t count) {
   *p = nullptr;
   if (count <= 0) count = 1;
   void* q = nullptr;
-  hipError_t e = hipMalloc(&q, size_t(count) * sizeof(T));
-  if (e != hipSuccess)
-    return fail(PACES_E_OOM, std::string("hipMalloc failed: ") +
-                                 hipGetErrorString(e));
+  const paces_status e = dev_alloc(&q, size_t(count) * sizeof(T));
+  if (e) return e;
   *p = static_cast<T*>(q);
   return PACES_OK;
 }
 template <typename T>
 void dfree(T*& p) {
-  if (p) (void)hipFree(p);
+  if (p) dev_free(p);
   p = nullptr;
+}
+
+// Device memory: the caller's allocator if one is registered, else
+// hipMalloc.  Every allocation of the library goes through here; the count
+// of live blocks guards allocator changes.
+struct DevAllocator {
+  void* (*alloc)(size_t, void*, void*) = nullptr;
+  void (*release)(void*, void*, void*) = nullptr;
+  void* user = nullptr;
+};
+DevAllocator g_allocator;
+std::atomic<int64_t> g_live_blocks{0};
+
+paces_status dev_alloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (g_allocator.alloc) {
+    *p = g_allocator.alloc(bytes, nullptr, g_allocator.user);
+    if (!*p) return fail(PACES_E_OOM, "registered allocator returned NULL");
+  } else {
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess)
+      return fail(PACES_E_OOM, std::string("hipMalloc failed: ") +
+                                   hipGetErrorString(e));
+  }
+  ++g_live_blocks;
+  return PACES_OK;
+}
+void dev_free(void* p) {
+  if (!p) return;
+  if (g_allocator.release)
+    g_allocator.release(p, nullptr, g_allocator.user);
+  else
+    (void)hipFree(p);
+  --g_live_blocks;
 }
 
 uint64_t splitmix_next(uint64_t& s) {
@@ -337,7 +373,7 @@ void free_rows(paces_sim* s) {
     dfree(s->side[q].tot);
   }
   for (auto& v : s->vec) {
-    if (v) (void)hipFree(v);
+    if (v) dev_free(v);
     v = nullptr;
   }
   dfree(s->col);
@@ -399,7 +435,7 @@ paces_status grow(paces_sim* s, int64_t new_cap, hipStream_t st) {
   }
   for (int v = 0; v < 4; ++v)
     if (v != s->ipsi && s->vec[v]) {
-      (void)hipFree(s->vec[v]);
+      dev_free(s->vec[v]);
       s->vec[v] = nullptr;
     }
   dfree(s->col);
@@ -415,7 +451,7 @@ paces_status grow(paces_sim* s, int64_t new_cap, hipStream_t st) {
   }
   for (int v = 0; v < 4; ++v) {
     void* q = nullptr;
-    HIP_TRY(hipMalloc(&q, size_t(new_cap) * s->A));
+    ST_TRY(dev_alloc(&q, size_t(new_cap) * s->A));
     if (v == s->ipsi) {
       if (s->nS > 0)
         HIP_TRY(hipMemcpyAsync(q, old_psi, size_t(s->nS) * s->A,
@@ -445,7 +481,7 @@ paces_status grow(paces_sim* s, int64_t new_cap, hipStream_t st) {
   dfree(old.keys);
   dfree(old.pay);
   dfree(old.tot);
-  if (old_psi) (void)hipFree(old_psi);
+  if (old_psi) dev_free(old_psi);
   s->side[0] = nsd[0];
   s->side[1] = nsd[1];
   s->cap = new_cap;
@@ -685,6 +721,56 @@ paces_status launch_step_graph(paces_sim* s, int64_t est, bool counted,
   return PACES_OK;
 }
 
+paces_status cap_buffers(paces_sim* s) {
+  const int R = s->m->R;
+  if (s->cap_buf < s->cap) {
+    dfree(s->keep);
+    dfree(s->midx_full);
+    dfree(s->cap_w);
+    dfree(s->cap_h);
+    dfree(s->cap_status);
+    ST_TRY(dalloc(&s->keep, s->cap));
+    ST_TRY(dalloc(&s->midx_full, s->cap));
+    ST_TRY(dalloc(&s->cap_w, s->cap));
+    ST_TRY(dalloc(&s->cap_h, s->cap));
+    ST_TRY(dalloc(&s->cap_status, s->cap));
+    s->cap_buf = s->cap;
+  }
+  if (!s->cap_hist) {
+    ST_TRY(dalloc(&s->cap_hist, int64_t(R) * 256));
+    ST_TRY(dalloc(&s->cap_mode, R));
+    ST_TRY(dalloc(&s->cap_dstar, R));
+    ST_TRY(dalloc(&s->cap_capped, R));
+  }
+  return PACES_OK;
+}
+
+paces_status topq_cut(paces_sim* s, hipStream_t st);
+
+// Fixed-size truncation: M = the q_nom heaviest rows of every
+// realization's set, ties broken as for the state cap.
+paces_status qnom_select(paces_sim* s, hipStream_t st) {
+  const paces_model* m = s->m;
+  const int R = m->R;
+  ST_TRY(cap_buffers(s));
+  s->nM_full = s->nS;
+  iota_u32(s->midx_full, s->nS, st);
+  std::vector<uint32_t> cnt(R, 0);
+  if (R == 1) {
+    cnt[0] = uint32_t(s->nS);
+  } else {
+    count_per_real(m->dm, s->side[s->cur].pay, s->nS, s->ball, st);
+    HIP_TRY(hipMemcpyAsync(cnt.data(), s->ball, size_t(R) * 4,
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  s->cap_nM.assign(cnt.begin(), cnt.end());
+  s->cap_on.assign(R, 0);
+  s->cap_q.assign(R, s->p.q_nom);
+  for (int r = 0; r < R; ++r) s->cap_on[r] = int64_t(cnt[r]) > s->p.q_nom;
+  return topq_cut(s, st);
+}
+
 // State cap: some realization's new set exceeds max_states.  Cut its
 // selection to the q heaviest rows (weight descending, splitmix64 key hash
 // ascending, key ascending) with q = floor(cap |M_prev| / |S_prev|) from
@@ -702,25 +788,7 @@ paces_status cap_select(paces_sim* s, hipStream_t st) {
                          hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   if (!s->cap_active) {
-    if (s->cap_buf < s->cap) {
-      dfree(s->keep);
-      dfree(s->midx_full);
-      dfree(s->cap_w);
-      dfree(s->cap_h);
-      dfree(s->cap_status);
-      ST_TRY(dalloc(&s->keep, s->cap));
-      ST_TRY(dalloc(&s->midx_full, s->cap));
-      ST_TRY(dalloc(&s->cap_w, s->cap));
-      ST_TRY(dalloc(&s->cap_h, s->cap));
-      ST_TRY(dalloc(&s->cap_status, s->cap));
-      s->cap_buf = s->cap;
-    }
-    if (!s->cap_hist) {
-      ST_TRY(dalloc(&s->cap_hist, int64_t(R) * 256));
-      ST_TRY(dalloc(&s->cap_mode, R));
-      ST_TRY(dalloc(&s->cap_dstar, R));
-      ST_TRY(dalloc(&s->cap_capped, R));
-    }
+    ST_TRY(cap_buffers(s));
     s->nM_full = s->h_ctl->nM;
     if (s->nM_full > 0)
       HIP_TRY(hipMemcpyAsync(s->midx_full, s->midx, size_t(s->nM_full) * 4,
@@ -750,7 +818,16 @@ paces_status cap_select(paces_sim* s, hipStream_t st) {
       s->cap_q[r] = 9 * qe * cap / (10 * int64_t(ball[r]));
     }
   }
-  // radix select over the capped realizations
+  return topq_cut(s, st);
+}
+
+// Cut the selection midx_full of every realization r with cap_on[r] to its
+// cap_q[r] heaviest rows (weight descending, splitmix64 key hash ascending,
+// key ascending) by an MSD radix select, leaving the result as row flags
+// for a preset-selection attempt.
+paces_status topq_cut(paces_sim* s, hipStream_t st) {
+  const paces_model* m = s->m;
+  const int R = m->R;
   const int Wi = m->Wi, W = m->W;
   const Side& so = s->side[s->cur];
   std::vector<int8_t> capped(s->cap_on.begin(), s->cap_on.end());
@@ -835,8 +912,9 @@ paces_status do_step(paces_sim* s, hipStream_t st,
       P <<= 1;
     s->tmask = std::min<uint64_t>(P - 1, s->tmask_alloc);
   }
-  const bool graph = s->tune.graph && !s->prof && !fz;
   s->cap_active = false;
+  if (s->p.q_nom > 0 && !s->fresh && !fz) ST_TRY(qnom_select(s, st));
+  const bool graph = s->tune.graph && !s->prof && !fz && !s->cap_active;
   for (int attempt = 0; attempt < 40; ++attempt) {
     const bool counted = s->counts_valid && attempt == 0 && !fz &&
                          !s->cap_active;
@@ -927,7 +1005,7 @@ struct Snapshot {
     dfree(keys);
     dfree(pay);
     dfree(tot);
-    if (psi) (void)hipFree(psi);
+    if (psi) dev_free(psi);
     dfree(mass_tot);
   }
 };
@@ -939,7 +1017,7 @@ paces_status take_snapshot(paces_sim* s, Snapshot& z, hipStream_t st) {
   ST_TRY(dalloc(&z.pay, n));
   ST_TRY(dalloc(&z.tot, n));
   ST_TRY(dalloc(&z.mass_tot, m->R));
-  HIP_TRY(hipMalloc(&z.psi, size_t(n) * s->A));
+  ST_TRY(dev_alloc(&z.psi, size_t(n) * s->A));
   const Side& c = s->side[s->cur];
   z.n = s->nS;
   if (s->nS > 0) {
@@ -1182,7 +1260,7 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 struct WorkSpace {
   std::vector<void*> p;
   ~WorkSpace() {
-    for (void* q : p) (void)hipFree(q);
+    for (void* q : p) dev_free(q);
   }
   template <typename T>
   paces_status get(T** out, int64_t count) {
@@ -1410,7 +1488,9 @@ paces_status paces_init_state(const paces_model* m, const paces_run_params* p,
       p->k_init > kMaxRounds || !(p->theta >= 0) ||
       (p->precision != 64 && p->precision != 32) || p->k_max_terms < 0 ||
       p->k_max_terms > kMaxTerms || p->tol < 0 || p->cap_states < 0 ||
-      p->max_states < 0 || p->max_states >= (int64_t(1) << 31))
+      p->max_states < 0 || p->max_states >= (int64_t(1) << 31) ||
+      p->q_nom < 0 || p->q_nom >= (int64_t(1) << 31) ||
+      (p->q_nom > 0 && p->max_states > 0))
     return fail(PACES_E_ARG, "bad run parameters");
   const int R = m->R;
   if (n * R > (int64_t(1) << 30)) return fail(PACES_E_ARG, "too many states");
@@ -1740,6 +1820,40 @@ paces_status paces_profile_reset(paces_sim* s) {
   return PACES_OK;
 }
 
+paces_status paces_set_allocator(void* (*alloc)(size_t, void*, void*),
+                                 void (*release)(void*, void*, void*),
+                                 void* user) {
+  if ((alloc == nullptr) != (release == nullptr))
+    return fail(PACES_E_ARG, "allocator needs both functions or neither");
+  if (g_live_blocks.load() != 0)
+    return fail(PACES_E_STATE,
+                "device memory of the library is still allocated");
+  g_allocator.alloc = alloc;
+  g_allocator.release = release;
+  g_allocator.user = user;
+  return PACES_OK;
+}
+
+paces_status paces_model_key_words(const paces_model* m, int32_t* W) {
+  if (!m || !W) return fail(PACES_E_ARG, "bad arguments");
+  *W = m->W;
+  return PACES_OK;
+}
+
+paces_status paces_series_field(paces_sim* s, int32_t field, void* dev_out,
+                                int64_t first, int64_t n, void* hip_stream) {
+  if (!s || !dev_out || field < 0 || field >= s->rec_doubles || first < 0 ||
+      n < 0 || first + n > int64_t(s->h.nrec))
+    return fail(PACES_E_ARG, "bad arguments");
+  if (n == 0) return PACES_OK;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int64_t R = s->m->R, pitch = int64_t(s->rec_doubles) * 8;
+  HIP_TRY(hipMemcpy2DAsync(dev_out, 8, s->ring + first * R * s->rec_doubles + field,
+                           size_t(pitch), 8, size_t(n * R),
+                           hipMemcpyDeviceToDevice, st));
+  return PACES_OK;
+}
+
 int32_t paces_num_params(const paces_model* m) {
   return m ? m->ndim + 2 * m->V + m->N : 0;
 }
@@ -1903,7 +2017,7 @@ paces_status paces_adjoint_backward(paces_sim* s, const double* gbar,
   uint8_t* store = nullptr;
   size_t store_cap = 0;
   auto release_store = [&]() {
-    if (store) (void)hipFree(store);
+    if (store) dev_free(store);
     store = nullptr;
   };
   paces_status e = PACES_OK;
@@ -1925,10 +2039,10 @@ paces_status paces_adjoint_backward(paces_sim* s, const double* gbar,
     }
     if (tot_bytes > store_cap) {
       release_store();
-      if (hipMalloc(&store, tot_bytes) != hipSuccess) {
-        e = fail(PACES_E_OOM, "segment store allocation failed");
-        break;
-      }
+      void* q = nullptr;
+      e = dev_alloc(&q, tot_bytes);
+      if (e) break;
+      store = static_cast<uint8_t*>(q);
       store_cap = tot_bytes;
     }
     for (int64_t i = start; i < end; ++i) {

@@ -1,0 +1,64 @@
+"""Boundary features beyond the step: device-side record copies into
+torch tensors, and device memory from torch's caching allocator."""
+import gc
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2603_07341_amd as P
+from tests.gpu_helpers import sort_rows
+import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+
+def test_series_field_copies_records_to_device():
+    cfg = dict(WL.CONFIGS["ring12"], eps_sigma=0.2)
+    R, steps = 3, 7
+    m = P.Model(WL.batch_params(cfg, R))
+    s = P.Sim(m, WL.run_params(cfg), *WL.initial_state(cfg))
+    s.step(steps)
+    host = s.series()  # [steps, R, rec]
+    for field in ("norm2", "a_re", "n_S", "E_max"):
+        out = torch.full((steps * R,), -1.0, dtype=torch.float64, device="cuda")
+        s.series_field(field, out)
+        torch.cuda.synchronize()
+        k = P.OBS_FIELDS.index(field)
+        assert np.array_equal(out.cpu().numpy().reshape(steps, R), host[:, :, k])
+    out = torch.zeros(2 * R, dtype=torch.float64, device="cuda")
+    s.series_field(12 + 5, out, first=3, n=2)  # population of site 5
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().reshape(2, R), host[3:5, :, 17])
+
+
+def run_ring(steps):
+    cfg = WL.CONFIGS["ring16"]
+    m = P.Model(WL.model_params(cfg))
+    s = P.Sim(m, WL.run_params(cfg), *WL.initial_state(cfg))
+    s.step(steps)
+    k, a = sort_rows(*s.state())
+    return m, s, k, a
+
+
+def test_torch_caching_allocator_gives_identical_results():
+    gc.collect()
+    torch.cuda.synchronize()
+    _, _, k0, a0 = run_ring(12)
+    gc.collect()
+    before = torch.cuda.memory_allocated()
+    P.use_torch_allocator(True)
+    try:
+        m, s, k1, a1 = run_ring(12)
+        assert torch.cuda.memory_allocated() > before + (1 << 20)
+        assert np.array_equal(k0, k1) and np.array_equal(a0, a1)
+        # changing the allocator while memory is held is refused
+        with pytest.raises(P.PacesError) as ei:
+            P.use_torch_allocator(False)
+        assert ei.value.status == 7
+        del m, s
+        gc.collect()
+    finally:
+        P.use_torch_allocator(False)
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == before

@@ -101,3 +101,28 @@ def test_tiny_cap_truncates_everything():
     os_.step(2)
     assert gs.size() == os_.size() <= 1
     assert gs.observations()[-1]["n_S"] == os_.observations()[-1]["n_S"]
+
+
+@pytest.mark.parametrize("over,R", [({}, 1), (dict(init="bloch", eps_sigma=0.0), 1),
+                                    (dict(eps_sigma=0.4, eps_seed=5), 2)])
+def test_fixed_size_truncation_matches_oracle(over, R):
+    cfg = dict(WL.CONFIGS["ring12"])
+    cfg.update(BASE)
+    cfg.update(over)
+    run = WL.run_params(cfg)
+    run["q_nom"] = 70
+    init = WL.initial_state(cfg)
+    params = WL.batch_params(cfg, R) if R > 1 else WL.model_params(cfg)
+    gs = P.Sim(P.Model(params), run, *init)
+    steps = 8
+    gs.step(steps)
+    gk, ga, gr = gs.state(with_real=True)
+    for r in range(R):
+        os_ = O.Sim(O.Model(WL.model_params(cfg, r)), run, *init)
+        os_.step(steps)
+        ok, oa = os_.state()
+        rk, ra = sort_rows(gk[gr == r], ga[gr == r])
+        assert np.array_equal(rk, ok), r
+        assert rel_err(ra, oa) <= 1e-10
+        for g, o in zip(gs.observations(r), os_.observations()):
+            assert g["n_M"] == o["n_M"] and g["n_S"] == o["n_S"]

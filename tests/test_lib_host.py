@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(lib, name), name
     assert sorted(P.EXPORTS) == declared
-    assert lib.paces_abi_version() == 5
+    assert lib.paces_abi_version() == 7
 
 
 @pytest.mark.parametrize("name", ["ring4", "ring16", "sq6x6", "cube4", "ring12"])
@@ -81,3 +81,18 @@ def test_batched_model_accepts_eps_per_realization():
     # layout (and so the host codec) is unchanged by batching
     single = P.Model(WL.model_params(cfg))
     assert (gm.N, gm.W, gm.D, gm.B) == (single.N, single.W, single.D, single.B)
+
+
+def test_model_key_words_matches_info():
+    import ctypes as C
+    for name in ("ring4", "sq6x6", "cube4"):
+        gm = P.Model(WL.model_params(WL.CONFIGS[name]))
+        W = C.c_int32()
+        assert P.lib().paces_model_key_words(gm.h, C.byref(W)) == 0
+        assert W.value == gm.W
+
+
+def test_allocator_needs_both_functions():
+    import ctypes as C
+    f = P._ALLOC_FN(lambda n, s, u: None)
+    assert P.lib().paces_set_allocator(f, None, None) == 1

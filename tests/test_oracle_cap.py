@@ -102,3 +102,28 @@ def test_cap_that_never_binds_changes_nothing():
 def test_cap_smaller_than_any_ball_truncates_everything():
     s, _ = run_case(1, 2)
     assert s.observations()[-1]["n_S"] <= 1
+
+
+@pytest.mark.parametrize("over", [{}, dict(init="bloch", eps_sigma=0.0)])
+def test_fixed_size_truncation_keeps_the_heaviest_q(over):
+    """q_nom mode (the paper's fixed number of retained amplitudes): after
+    the first step M is the q heaviest rows of the previous set, in the
+    same order as the cap, whatever the threshold."""
+    cfg = dict(WL.CONFIGS["ring12"])
+    cfg.update(dict(extent=[6, 1, 1], cutoff=[4], theta=0.5, k=2, k_init=2))
+    cfg.update(over)
+    run = WL.run_params(cfg)
+    q = 60
+    run["q_nom"] = q
+    s = O.Sim(O.Model(WL.model_params(cfg)), run, *WL.initial_state(cfg))
+    s.step(1)
+    for step in range(6):
+        keys, amps = s.state()
+        w = amps.real * amps.real + amps.imag * amps.imag
+        s.step(1)
+        M = s.get_set(O.SET_M)
+        assert len(M) == min(q, len(keys))
+        order = sorted(range(len(keys)), key=lambda i: (
+            -w[i], key_hash(keys[i]), tuple(int(x) for x in keys[i])))
+        kept = {tuple(int(x) for x in keys[i]) for i in order[:len(M)]}
+        assert kept == {tuple(int(x) for x in k) for k in M}, step
