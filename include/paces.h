@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define PACES_ABI_VERSION 7
+#define PACES_ABI_VERSION 8
 
 typedef enum {
   PACES_OK = 0,
@@ -186,6 +186,12 @@ paces_status paces_free_sim(paces_sim* s);
 /* Advance n_steps time steps (asynchronous on the stream except where the
  * host needs a device count to size the next launch). */
 paces_status paces_step(paces_sim* s, int64_t n_steps, void* hip_stream);
+/* Piecewise-constant H(t): later steps of the sim use model m, which must
+ * have the sim's shape (lattice, modes, cutoffs, realizations); only J,
+ * g, omega and eps may differ.  The caller keeps m alive while the sim
+ * uses it.  Drops a recorded adjoint run. */
+paces_status paces_set_model(paces_sim* s, const paces_model* m);
+
 /* Latest observation of one realization (0..R-1); synchronises the
  * stream.  n_S and n_M of a record count the rows of that realization. */
 paces_status paces_observe(paces_sim* s, int32_t realization, paces_obs* out,

@@ -152,6 +152,10 @@ class Sim:
     def step(self, n=1):
         _check(lib().orc_sim_step(self.h, C.c_int64(n)))
 
+    def set_model(self, model):
+        _check(lib().orc_sim_set_model(self.h, model.h))
+        self.model = model
+
     def size(self):
         n = C.c_int64()
         _check(lib().orc_sim_size(self.h, C.byref(n)))

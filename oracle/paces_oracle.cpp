@@ -1256,6 +1256,15 @@ int orc_frozen_record(const void* mp, const orc_params* p, int64_t n,
 
 void orc_frozen_destroy(void* f) { delete static_cast<Frozen*>(f); }
 
+int orc_sim_set_model(void* sp, const void* mp) {
+  Sim* s = static_cast<Sim*>(sp);
+  const Model* m = static_cast<const Model*>(mp);
+  if (!s || !m) return fail("null argument");
+  if (!same_shape(*s->m, *m)) return fail("model shape differs");
+  s->m = m;
+  return 0;
+}
+
 int orc_frozen_info(const void* fp, int64_t* n_steps, int32_t* n_params,
                     int64_t* sizes) {
   const Frozen* f = static_cast<const Frozen*>(fp);

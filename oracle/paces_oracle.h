@@ -97,6 +97,9 @@ int orc_sim_create(const void* m, const orc_params* p, int64_t n,
                    const double* coef, void** out);
 void orc_sim_destroy(void* s);
 int orc_sim_step(void* s, int64_t n_steps);
+/* Later steps use model m (same lattice, modes and cutoffs): a
+ * piecewise-constant Hamiltonian.  The caller keeps m alive. */
+int orc_sim_set_model(void* s, const void* m);
 /* Replace the current state: sorted or not, duplicates are an error.  The
  * next step selects from it with the threshold and neighbour order k. */
 int orc_sim_set_state(void* s, int64_t n, const uint64_t* keys,

@@ -37,7 +37,7 @@ EXPORTS = [
     "paces_profile_reset", "paces_get_tuning", "paces_set_tuning",
     "paces_autotune", "paces_num_params", "paces_adjoint_forward",
     "paces_adjoint_replay", "paces_adjoint_backward", "paces_set_allocator",
-    "paces_model_key_words", "paces_series_field",
+    "paces_model_key_words", "paces_series_field", "paces_set_model",
 ]
 
 
@@ -243,6 +243,12 @@ class Sim:
 
     def __del__(self):
         self.close()
+
+    def set_model(self, model):
+        """Later steps use `model` (same shape, other J, g, omega, eps):
+        a piecewise-constant Hamiltonian."""
+        _check(lib().paces_set_model(self.h, model.h))
+        self.model = model
 
     def step(self, n=1, stream=None):
         _check(lib().paces_step(self.h, C.c_int64(n), _stream(stream)))

@@ -1834,6 +1834,20 @@ paces_status paces_set_allocator(void* (*alloc)(size_t, void*, void*),
   return PACES_OK;
 }
 
+paces_status paces_set_model(paces_sim* s, const paces_model* m) {
+  if (!s || !m) return fail(PACES_E_ARG, "bad arguments");
+  if (!same_shape(s->m, m))
+    return fail(PACES_E_ARG, "model shape differs from the sim's");
+  ST_TRY(ensure_device_tables(const_cast<paces_model*>(m)));
+  if (m != s->m) {
+    drop_graphs(s);  // kernels take the model's values by value
+    delete s->adj;   // a recorded adjoint run assumes one model
+    s->adj = nullptr;
+  }
+  s->m = m;
+  return PACES_OK;
+}
+
 paces_status paces_model_key_words(const paces_model* m, int32_t* W) {
   if (!m || !W) return fail(PACES_E_ARG, "bad arguments");
   *W = m->W;

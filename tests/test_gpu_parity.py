@@ -151,3 +151,31 @@ def test_duplicate_input_rejected():
     with pytest.raises(P.PacesError) as ei:
         P.Sim(gm, WL.run_params(cfg), [0, 0], [0] * 8, [0.6, 0, 0.8, 0])
     assert ei.value.status == 1
+
+
+def test_piecewise_constant_hamiltonian_matches_oracle():
+    cfg = dict(WL.CONFIGS["ring12"])
+    cfg.update(extent=[6, 1, 1], cutoff=[4], theta=1e-6)
+    pa = WL.model_params(cfg)
+    pb = dict(pa, J=[-0.6, 0.0, 0.0], g=[1.3, 0, 0, 0],
+              eps=list(np.asarray(pa["eps"]) + 0.05))
+    run = WL.run_params(cfg)
+    init = WL.initial_state(cfg)
+    ga, gb = P.Model(pa), P.Model(pb)
+    oa, ob = O.Model(pa), O.Model(pb)
+    gs = P.Sim(ga, run, *init)
+    os_ = O.Sim(oa, run, *init)
+    gs.step(5)
+    os_.step(5)
+    gs.set_model(gb)
+    os_.set_model(ob)
+    gs.step(5)
+    os_.step(5)
+    gk, gv = sort_rows(*gs.state())
+    ok, ov = os_.state()
+    assert np.array_equal(gk, ok)
+    assert rel_err(gv, ov) <= 1e-10
+    for g, o in zip(gs.observations(), os_.observations()):
+        check_obs(g, o, 1e-10, width=o["E_max"] - o["E_min"])
+    with pytest.raises(P.PacesError):
+        gs.set_model(P.Model(WL.model_params(dict(cfg, extent=[7, 1, 1]))))

@@ -186,3 +186,34 @@ def test_independent_boson_two_modes_factorize():
             S = (gg / ww) ** 2
             ref *= cmath.exp(1j * S * ww * t - S * (1 - cmath.exp(-1j * ww * t)))
         assert abs(complex(o["a_re"], o["a_im"]) - ref) <= 1e-11
+
+
+def test_piecewise_constant_hamiltonian_matches_dense_products():
+    """Switching the model between steps (same shape): on a space reached
+    whole, psi = exp(-i H_B n2 dt) exp(-i H_A n1 dt) psi0 with the dense
+    Kronecker-product Hamiltonians."""
+    import scipy.linalg as sla
+    from tests import brute
+    cfg = dict(WL.CONFIGS["ring12"])
+    cfg.update(extent=[3, 1, 1], cutoff=[2], theta=0.0, k=30, k_init=30,
+               init="local", eps_sigma=0.3)
+    pa = WL.model_params(cfg)
+    pb = dict(pa, J=[0.7, 0.0, 0.0], g=[1.4, 0, 0, 0], omega=[0.8, 0, 0, 0],
+              eps=[0.1, -0.2, 0.05])
+    ma, mb = O.Model(pa), O.Model(pb)
+    s = O.Sim(ma, WL.run_params(cfg), *WL.initial_state(cfg))
+    s.step(4)
+    s.set_model(mb)
+    s.step(3)
+    keys, amps = s.state()
+    n = brute.dense_hamiltonian(pa).shape[0]
+    assert len(keys) == n
+    psi0 = np.zeros(n, complex)
+    psi0[brute.state_index(pa, 0, [0, 0, 0])] = 1
+    dt = cfg["dt"]
+    ref = sla.expm(-1j * brute.dense_hamiltonian(pb) * 3 * dt) @ (
+        sla.expm(-1j * brute.dense_hamiltonian(pa) * 4 * dt) @ psi0)
+    # oracle rows are sorted keys; map them to the dense index order
+    exc, occ = ma.unpack(keys)
+    idx = [brute.state_index(pa, int(j), list(o)) for j, o in zip(exc, occ)]
+    assert np.max(np.abs(amps - ref[idx])) <= 1e-12
