@@ -65,6 +65,10 @@ __global__ void __launch_bounds__(kBlock)
   const int q = blockIdx.x;
   const double x = cc->a * tau[q] * dt;
   const int kcap = kMaxTerms - 1;
+  if (!(x <= double(kcap))) {  // the step itself had a finite, smaller x
+    if (threadIdx.x == 0) atomicOr(err, kErrTerms);
+    return;
+  }
   if (x <= 2.0) {
     for (int k = threadIdx.x; k <= kcap; k += blockDim.x)
       J[k] = bessel_series(x, k);

@@ -614,6 +614,12 @@ __global__ void __launch_bounds__(kBlock)
   if (!(a > 1e-300)) a = 1e-300;
   const double x = a * dt;
   const int kcap = k_max < kMaxTerms ? k_max : kMaxTerms;
+  // the series needs more than x terms: a spectrum too wide for the step
+  // (or not finite) is reported before any Bessel recurrence runs
+  if (!(x <= double(kcap))) {
+    if (threadIdx.x == 0) atomicOr(err, isfinite(x) ? kErrTerms : kErrNonFinite);
+    return;
+  }
   if (x <= 2.0) {
     for (int k = threadIdx.x; k <= kcap; k += blockDim.x)
       J[k] = bessel_series(x, k);
@@ -723,7 +729,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
   for (int a = 0; a < ND; ++a) jv[a] = R(m.J[a]);
   double esum = 0;
-  for (int64_t i = gtid(); i < n; i += gstride()) {
+  for (int64_t i = xcd_gtid(); i < n; i += gstride()) {
     const Amp xi = in[i];
     const uint64_t p = pay[i];
     const R d = R(row_diag(m, p, NV > 2 ? tot[i] : 0));
@@ -792,7 +798,7 @@ __global__ void __launch_bounds__(kBlock)
   R jv[3] = {0, 0, 0};
 #pragma unroll
   for (int a = 0; a < ND; ++a) jv[a] = R(m.J[a]);
-  for (int64_t i = gtid(); i < n; i += gstride()) {
+  for (int64_t i = xcd_gtid(); i < n; i += gstride()) {
     const uint64_t p = pay[i];
     const ChebCoef* cc = cc_all + pay_real(p);
     const int K = cc->K;

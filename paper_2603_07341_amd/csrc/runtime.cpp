@@ -1352,6 +1352,14 @@ paces_status paces_load_model(const paces_model_desc* d, paces_model** out) {
   m->eps.assign(size_t(m->R) * m->N, 0.0);
   if (d->eps)
     for (size_t i = 0; i < m->eps.size(); ++i) m->eps[i] = d->eps[i];
+  {
+    bool finite = true;
+    for (double v : m->eps) finite &= std::isfinite(v);
+    for (int nu = 0; nu < m->V; ++nu)
+      finite &= std::isfinite(m->omega[nu]) && std::isfinite(m->g[nu]);
+    for (int a = 0; a < 3; ++a) finite &= std::isfinite(m->J[a]);
+    if (!finite) return bad("model parameters must be finite");
+  }
   m->bj = std::max(1, bits_for(m->N));
   m->B = m->N * m->P + m->bj;
   m->W = (m->B + 63) / 64;
@@ -1494,6 +1502,9 @@ paces_status paces_init_state(const paces_model* m, const paces_run_params* p,
     return fail(PACES_E_ARG, "bad run parameters");
   const int R = m->R;
   if (n * R > (int64_t(1) << 30)) return fail(PACES_E_ARG, "too many states");
+  for (int64_t i = 0; i < 2 * n; ++i)
+    if (!std::isfinite(coef[i]))
+      return fail(PACES_E_ARG, "coefficients must be finite");
   std::vector<uint64_t> keys(size_t(n) * m->W);
   ST_TRY(paces_pack_keys(m, n, exc, occ, keys.data()));
   ST_TRY(check_unique(m->W, n, keys.data()));
@@ -1726,6 +1737,9 @@ paces_status paces_set_state(paces_sim* s, int64_t n, const uint64_t* keys,
     for (int64_t i = 0; i < n; ++i)
       if (real[i] < 0 || real[i] >= m->R)
         return fail(PACES_E_ARG, "realization index out of range");
+  for (int64_t i = 0; i < 2 * n; ++i)
+    if (!std::isfinite(amps[i]))
+      return fail(PACES_E_ARG, "amplitudes must be finite");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   ST_TRY(check_keys(m, n, keys));
   std::vector<uint64_t> ik(size_t(n) * m->Wi);

@@ -179,3 +179,33 @@ def test_piecewise_constant_hamiltonian_matches_oracle():
         check_obs(g, o, 1e-10, width=o["E_max"] - o["E_min"])
     with pytest.raises(P.PacesError):
         gs.set_model(P.Model(WL.model_params(dict(cfg, extent=[7, 1, 1]))))
+
+
+def test_non_finite_inputs_and_overflow_latch():
+    """Non-finite amplitudes are refused at the boundary; a spectrum whose
+    width overflows FP64 (site energies +-1e308) latches a non-finite
+    norm, after which steps are refused until the state is set again."""
+    cfg = dict(WL.CONFIGS["ring4"])
+    p = WL.model_params(cfg)
+    run = WL.run_params(cfg)
+    exc, occ, coef = WL.initial_state(cfg)
+    with pytest.raises(P.PacesError) as ei:
+        P.Sim(P.Model(p), run, exc, occ, [float("nan"), 0.0])
+    assert ei.value.status == 1
+    s = P.Sim(P.Model(p), run, exc, occ, coef)
+    s.step(2)
+    keys, amps = s.state()
+    bad = amps.copy()
+    bad[0] = complex(float("inf"), 0)
+    with pytest.raises(P.PacesError) as ei:
+        s.set_state(keys, bad, 0.0)
+    assert ei.value.status == 1
+    q = dict(p, eps=[1e308, -1e308, 0.0, 0.0])
+    s = P.Sim(P.Model(q), run, exc, occ, coef)
+    with pytest.raises(P.PacesError) as ei:
+        s.step(1)
+    assert ei.value.status == 4
+    with pytest.raises(P.PacesError) as ei:
+        s.step(1)
+    assert ei.value.status == 7
+    s.set_state(keys, amps, 0.0)  # clears the latch

@@ -55,6 +55,9 @@ def test_host_codec_matches_oracle(name):
     dict(extent=[64, 1, 1], n_real=128),
     # N * cutoff above the 14-bit packed total occupation
     dict(extent=[2048, 1, 1], cutoff=[10, 0, 0, 0]),
+    # parameters must be finite
+    dict(J=[float("nan"), 0, 0]), dict(g=[float("inf"), 0, 0, 0]),
+    dict(eps=[0.0, float("nan"), 0.0, 0.0]),
 ])
 def test_model_validation_rejects(bad):
     p = WL.model_params(WL.CONFIGS["ring4"])
