@@ -184,7 +184,10 @@ paces_status paces_init_state(const paces_model* m, const paces_run_params* p,
 paces_status paces_free_sim(paces_sim* s);
 
 /* Advance n_steps time steps (asynchronous on the stream except where the
- * host needs a device count to size the next launch). */
+ * host needs a device count to size the next launch).  With the
+ * environment variable PACES_LOG set to a file name (1: paces_log.csv),
+ * every step's records are appended to it as CSV lines
+ * "step,realization,<12 fields>,<N populations>". */
 paces_status paces_step(paces_sim* s, int64_t n_steps, void* hip_stream);
 /* Piecewise-constant H(t): later steps of the sim use model m, which must
  * have the sim's shape (lattice, modes, cutoffs, realizations); only J,

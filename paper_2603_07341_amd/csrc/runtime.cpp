@@ -19,6 +19,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -1274,6 +1275,29 @@ struct WorkSpace {
 }  // namespace
 
 namespace {
+// PACES_LOG=<file> (or 1 for paces_log.csv): append the records of every
+// step as CSV lines "step,realization,<fields>,<populations>", read at the
+// step's synchronisation point.
+paces_status log_step(paces_sim* s, const char* where, hipStream_t st) {
+  const int R = s->m->R;
+  const int64_t step = int64_t(s->h.nrec) - 1;
+  std::vector<double> rec(size_t(R) * s->rec_doubles);
+  HIP_TRY(hipMemcpyAsync(rec.data(), s->ring + step * R * s->rec_doubles,
+                         rec.size() * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const char* path = std::strcmp(where, "1") == 0 ? "paces_log.csv" : where;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return fail(PACES_E_ARG, std::string("cannot open log ") + path);
+  for (int r = 0; r < R; ++r) {
+    std::fprintf(f, "%lld,%d", (long long)step, r);
+    for (int q = 0; q < s->rec_doubles; ++q)
+      std::fprintf(f, ",%.17g", rec[size_t(r) * s->rec_doubles + q]);
+    std::fprintf(f, "\n");
+  }
+  std::fclose(f);
+  return PACES_OK;
+}
+
 // Device copies of the model tables, made on first use so that loading a
 // model and the host codec need no GPU.
 paces_status ensure_device_tables(paces_model* m) {
@@ -1633,12 +1657,14 @@ paces_status paces_step(paces_sim* s, int64_t n_steps, void* hip_stream) {
   if (!s || n_steps < 0) return fail(PACES_E_ARG, "bad arguments");
   if (s->latched) return fail(PACES_E_STATE, "sim is in an error state");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const char* log = std::getenv("PACES_LOG");
   for (int64_t i = 0; i < n_steps; ++i) {
     paces_status r = do_step(s, st);
     if (r != PACES_OK) {
       if (!s->latched) s->latched = -1;
       return r;
     }
+    if (log && *log && std::strcmp(log, "0") != 0) ST_TRY(log_step(s, log, st));
   }
   return PACES_OK;
 }

@@ -62,3 +62,20 @@ def test_torch_caching_allocator_gives_identical_results():
         P.use_torch_allocator(False)
     torch.cuda.synchronize()
     assert torch.cuda.memory_allocated() == before
+
+
+def test_step_log_writes_every_record(tmp_path, monkeypatch):
+    path = tmp_path / "log.csv"
+    monkeypatch.setenv("PACES_LOG", str(path))
+    cfg = dict(WL.CONFIGS["ring12"], eps_sigma=0.2)
+    m = P.Model(WL.batch_params(cfg, 2))
+    s = P.Sim(m, WL.run_params(cfg), *WL.initial_state(cfg))
+    s.step(4)
+    monkeypatch.delenv("PACES_LOG")
+    s.step(1)
+    rows = np.loadtxt(path, delimiter=",")
+    rec = s.series()
+    assert rows.shape == (8, 2 + m.rec_doubles)
+    for line in rows:
+        step, r = int(line[0]), int(line[1])
+        assert np.array_equal(line[2:], rec[step, r])
