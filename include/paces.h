@@ -144,9 +144,9 @@ int32_t paces_record_doubles(const paces_model* m);
  * records) from the caller's allocator: alloc(bytes, stream, user) returns
  * device memory or NULL, release(ptr, stream, user) frees it; stream is
  * passed as NULL (the library synchronises its stream before it frees).
- * Both NULL restores hipMalloc / hipFree.  Only while the library holds no
- * device memory (else PACES_E_STATE): set it before the first
- * paces_init_state. */
+ * Both NULL restores hipMalloc / hipFree.  Applies to later allocations;
+ * every block goes back to the allocator that made it, so the functions
+ * must stay valid while blocks they made are alive. */
 paces_status paces_set_allocator(void* (*alloc)(size_t bytes, void* stream,
                                                 void* user),
                                  void (*release)(void* ptr, void* stream,

@@ -103,17 +103,15 @@ def lib():
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 _FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
-_allocator_refs = None
+_allocator_refs = []  # callbacks stay alive: their blocks may outlive a switch
 
 
 def use_torch_allocator(on=True):
-    """Take the library's device memory from torch's caching allocator
-    (on=True) or from hipMalloc (on=False).  Only while no model tables or
-    sims hold device memory."""
-    global _allocator_refs
+    """Take later device allocations of the library from torch's caching
+    allocator (on=True) or from hipMalloc (on=False); blocks already made
+    are returned to the allocator that made them."""
     if not on:
         _check(lib().paces_set_allocator(None, None, None))
-        _allocator_refs = None
         return
 
     def _alloc(nbytes, stream, user):
@@ -127,7 +125,7 @@ def use_torch_allocator(on=True):
 
     refs = (_ALLOC_FN(_alloc), _FREE_FN(_free))
     _check(lib().paces_set_allocator(refs[0], refs[1], None))
-    _allocator_refs = refs
+    _allocator_refs.append(refs)
 
 
 def _check(rc):

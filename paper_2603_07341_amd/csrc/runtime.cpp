@@ -16,7 +16,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <atomic>
+#include <mutex>
+#include <unordered_map>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -81,37 +82,49 @@ void dfree(T*& p) {
 }
 
 // Device memory: the caller's allocator if one is registered, else
-// hipMalloc.  Every allocation of the library goes through here; the count
-// of live blocks guards allocator changes.
+// hipMalloc.  Every allocation of the library goes through here, and each
+// block is returned to the allocator that made it, so the allocator may
+// change while blocks are alive.
 struct DevAllocator {
   void* (*alloc)(size_t, void*, void*) = nullptr;
   void (*release)(void*, void*, void*) = nullptr;
   void* user = nullptr;
 };
 DevAllocator g_allocator;
-std::atomic<int64_t> g_live_blocks{0};
+std::mutex g_blocks_mu;
+std::unordered_map<void*, DevAllocator> g_blocks;  // blocks of an allocator
 
 paces_status dev_alloc(void** p, size_t bytes) {
   *p = nullptr;
-  if (g_allocator.alloc) {
-    *p = g_allocator.alloc(bytes, nullptr, g_allocator.user);
+  const DevAllocator a = g_allocator;
+  if (a.alloc) {
+    *p = a.alloc(bytes, nullptr, a.user);
     if (!*p) return fail(PACES_E_OOM, "registered allocator returned NULL");
+    std::lock_guard<std::mutex> lk(g_blocks_mu);
+    g_blocks[*p] = a;
   } else {
     const hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess)
       return fail(PACES_E_OOM, std::string("hipMalloc failed: ") +
                                    hipGetErrorString(e));
   }
-  ++g_live_blocks;
   return PACES_OK;
 }
 void dev_free(void* p) {
   if (!p) return;
-  if (g_allocator.release)
-    g_allocator.release(p, nullptr, g_allocator.user);
+  DevAllocator a;
+  {
+    std::lock_guard<std::mutex> lk(g_blocks_mu);
+    auto it = g_blocks.find(p);
+    if (it != g_blocks.end()) {
+      a = it->second;
+      g_blocks.erase(it);
+    }
+  }
+  if (a.release)
+    a.release(p, nullptr, a.user);
   else
     (void)hipFree(p);
-  --g_live_blocks;
 }
 
 uint64_t splitmix_next(uint64_t& s) {
@@ -1865,9 +1878,6 @@ paces_status paces_set_allocator(void* (*alloc)(size_t, void*, void*),
                                  void* user) {
   if ((alloc == nullptr) != (release == nullptr))
     return fail(PACES_E_ARG, "allocator needs both functions or neither");
-  if (g_live_blocks.load() != 0)
-    return fail(PACES_E_STATE,
-                "device memory of the library is still allocated");
   g_allocator.alloc = alloc;
   g_allocator.release = release;
   g_allocator.user = user;
