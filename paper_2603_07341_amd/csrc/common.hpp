@@ -89,20 +89,6 @@ __device__ __forceinline__ int64_t gstride() {
   return int64_t(gridDim.x) * blockDim.x;
 }
 
-// Workgroups are dealt to the 8 XCDs of the chip round robin (block b to
-// XCD b % 8), each XCD with its own L2.  xcd_gtid() renumbers blocks so
-// that every XCD walks one contiguous range of rows: neighbouring rows, and
-// gathers that land near the row being processed, share that XCD's L2.
-// The map is a bijection of [0, gridDim.x) for any grid size.
-constexpr int kXcds = 8;
-__device__ __forceinline__ int64_t xcd_gtid() {
-  const int nb = gridDim.x, b = blockIdx.x;
-  const int q = nb / kXcds, r = nb % kXcds;
-  const int x = b % kXcds, k = b / kXcds;
-  const int lb = x * q + (x < r ? x : r) + k;
-  return int64_t(lb) * blockDim.x + threadIdx.x;
-}
-
 // ---- deterministic block reductions ---------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

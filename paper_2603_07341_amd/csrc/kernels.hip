@@ -729,7 +729,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
   for (int a = 0; a < ND; ++a) jv[a] = R(m.J[a]);
   double esum = 0;
-  for (int64_t i = xcd_gtid(); i < n; i += gstride()) {
+  for (int64_t i = gtid(); i < n; i += gstride()) {
     const Amp xi = in[i];
     const uint64_t p = pay[i];
     const R d = R(row_diag(m, p, NV > 2 ? tot[i] : 0));
@@ -798,7 +798,7 @@ __global__ void __launch_bounds__(kBlock)
   R jv[3] = {0, 0, 0};
 #pragma unroll
   for (int a = 0; a < ND; ++a) jv[a] = R(m.J[a]);
-  for (int64_t i = xcd_gtid(); i < n; i += gstride()) {
+  for (int64_t i = gtid(); i < n; i += gstride()) {
     const uint64_t p = pay[i];
     const ChebCoef* cc = cc_all + pay_real(p);
     const int K = cc->K;
