@@ -82,6 +82,23 @@ __device__ __forceinline__ double2 widen(float2 c) {
   return make_double2(c.x, c.y);
 }
 
+// Loads of streams read once per launch, with the non-temporal hint, so
+// that they do not push the gathered vector out of the caches.
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+  const double* q = reinterpret_cast<const double*>(p);
+  return make_double2(__builtin_nontemporal_load(q),
+                      __builtin_nontemporal_load(q + 1));
+}
+__device__ __forceinline__ float2 ld_stream(const float2* p) {
+  const float* q = reinterpret_cast<const float*>(p);
+  return make_float2(__builtin_nontemporal_load(q),
+                     __builtin_nontemporal_load(q + 1));
+}
+
 __device__ __forceinline__ int64_t gtid() {
   return int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
 }

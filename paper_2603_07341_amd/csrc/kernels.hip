@@ -731,8 +731,8 @@ __global__ void __launch_bounds__(kBlock)
   double esum = 0;
   for (int64_t i = gtid(); i < n; i += gstride()) {
     const Amp xi = in[i];
-    const uint64_t p = pay[i];
-    const R d = R(row_diag(m, p, NV > 2 ? tot[i] : 0));
+    const uint64_t p = ld_stream(pay + i);
+    const R d = R(row_diag(m, p, NV > 2 ? ld_stream(tot + i) : 0));
     R hr = d * xi.x, hi = d * xi.y;
     R gv[NV][2];
 #pragma unroll
@@ -743,7 +743,7 @@ __global__ void __launch_bounds__(kBlock)
     }
 #pragma unroll
     for (int s = 0; s < D; ++s) {
-      const int32_t c = col[int64_t(s) * cap + i];
+      const int32_t c = ld_stream(col + int64_t(s) * cap + i);
       if (c >= 0) {
         const R v = s < 2 * ND ? jv[s >> 1] : gv[(s - 2 * ND) >> 1][(s - 2 * ND) & 1];
         const Amp xj = in[c];
@@ -754,11 +754,11 @@ __global__ void __launch_bounds__(kBlock)
     if (energy) esum += double(xi.x) * double(hr) + double(xi.y) * double(hi);
     const R tr = alpha * hr + beta * xi.x, ti = alpha * hi + beta * xi.y;
     R yr = sir * tr - sii * ti, yi = sir * ti + sii * tr;
-    const Amp f = phi[i];
+    const Amp f = ld_stream(phi + i);
     yr += ckr * f.x - cki * f.y;
     yi += ckr * f.y + cki * f.x;
     if (prev) {
-      const Amp q = prev[i];
+      const Amp q = ld_stream(prev + i);
       yr -= spr * q.x - spi * q.y;
       yi -= spr * q.y + spi * q.x;
     }
@@ -799,7 +799,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
   for (int a = 0; a < ND; ++a) jv[a] = R(m.J[a]);
   for (int64_t i = gtid(); i < n; i += gstride()) {
-    const uint64_t p = pay[i];
+    const uint64_t p = ld_stream(pay + i);
     const ChebCoef* cc = cc_all + pay_real(p);
     const int K = cc->K;
     if (kk > K - 2 && !(K == 1 && kk == 0)) continue;
@@ -823,7 +823,7 @@ __global__ void __launch_bounds__(kBlock)
     }
     const R phr = fin ? R(cc->phase[0]) : R(1), phim = fin ? R(cc->phase[1]) : R(0);
     const Amp xi = in[i];
-    const R d = R(row_diag(m, p, NV > 2 ? tot[i] : 0));
+    const R d = R(row_diag(m, p, NV > 2 ? ld_stream(tot + i) : 0));
     R hr = d * xi.x, hi = d * xi.y;
     R gv[NV][2];
 #pragma unroll
@@ -834,7 +834,7 @@ __global__ void __launch_bounds__(kBlock)
     }
 #pragma unroll
     for (int s = 0; s < D; ++s) {
-      const int32_t c = col[int64_t(s) * cap + i];
+      const int32_t c = ld_stream(col + int64_t(s) * cap + i);
       if (c >= 0) {
         const R v = s < 2 * ND ? jv[s >> 1] : gv[(s - 2 * ND) >> 1][(s - 2 * ND) & 1];
         const Amp xj = in[c];
@@ -846,11 +846,11 @@ __global__ void __launch_bounds__(kBlock)
       e_row[i] = double(xi.x) * double(hr) + double(xi.y) * double(hi);
     const R tr = alpha * hr + beta * xi.x, ti = alpha * hi + beta * xi.y;
     R yr = sir * tr - sii * ti, yi = sir * ti + sii * tr;
-    const Amp f = phi[i];
+    const Amp f = ld_stream(phi + i);
     yr += ckr * f.x - cki * f.y;
     yi += ckr * f.y + cki * f.x;
     if (prev) {
-      const Amp q = prev[i];
+      const Amp q = ld_stream(prev + i);
       yr -= spr * q.x - spi * q.y;
       yi -= spr * q.y + spi * q.x;
     }
