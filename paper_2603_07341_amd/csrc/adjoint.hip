@@ -113,7 +113,7 @@ __device__ __forceinline__ double2 h_row(const DevModel& m, int64_t i,
   double hr = d * xi.x, hi = d * xi.y;
 #pragma unroll
   for (int s = 0; s < D; ++s) {
-    const int32_t c = col[int64_t(s) * n + i];
+    const int32_t c = col[i * D + s];
     if (c >= 0) {
       const double val = slot_value(m, p, s);
       const double2 xj = v[c];
@@ -198,6 +198,7 @@ __global__ void __launch_bounds__(kBlock)
                    const int* err) {
   extern __shared__ double site_bins[];
   if (*err) return;
+  constexpr int D = 2 * ND + 2 * NV;
   const int N = m.N, P = ND + 2 * NV + N;
   for (int j = threadIdx.x; j < N; j += blockDim.x) site_bins[j] = 0.0;
   __syncthreads();
@@ -218,14 +219,14 @@ __global__ void __launch_bounds__(kBlock)
       diag += wq * im_cb(xi, yq[i]);
 #pragma unroll
       for (int s = 0; s < 2 * ND; ++s) {
-        const int32_t c = col[int64_t(s) * n + i];
+        const int32_t c = col[i * D + s];
         if (c >= 0) gJ[s >> 1] += wq * im_cb(xi, yq[c]);
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const int occ = pay_occ(p, v);
-        const int32_t cl = col[int64_t(2 * ND + 2 * v) * n + i];
-        const int32_t cr = col[int64_t(2 * ND + 2 * v + 1) * n + i];
+        const int32_t cl = col[i * D + 2 * ND + 2 * v];
+        const int32_t cr = col[i * D + 2 * ND + 2 * v + 1];
         double e = 0;
         if (cl >= 0) e += sqrt(double(occ)) * im_cb(xi, yq[cl]);
         if (cr >= 0) e += sqrt(double(occ + 1)) * im_cb(xi, yq[cr]);

@@ -99,6 +99,34 @@ __device__ __forceinline__ float2 ld_stream(const float2* p) {
                      __builtin_nontemporal_load(q + 1));
 }
 
+// The D ELL columns of one row (row-major, D int32 per row), read as a
+// stream with the widest aligned vector loads: rows start at multiples of
+// 16 bytes for D % 4 == 0 and of 8 bytes for even D.
+typedef int32_t v4i32 __attribute__((ext_vector_type(4)));
+typedef int32_t v2i32 __attribute__((ext_vector_type(2)));
+template <int D>
+__device__ __forceinline__ void load_cols(const int32_t* row, int32_t (&c)[D]) {
+  if constexpr (D % 4 == 0) {
+#pragma unroll
+    for (int q = 0; q < D / 4; ++q) {
+      const v4i32 v = __builtin_nontemporal_load(
+          reinterpret_cast<const v4i32*>(row) + q);
+      c[4 * q] = v.x;
+      c[4 * q + 1] = v.y;
+      c[4 * q + 2] = v.z;
+      c[4 * q + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < D / 2; ++q) {
+      const v2i32 v = __builtin_nontemporal_load(
+          reinterpret_cast<const v2i32*>(row) + q);
+      c[2 * q] = v.x;
+      c[2 * q + 1] = v.y;
+    }
+  }
+}
+
 __device__ __forceinline__ int64_t gtid() {
   return int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
 }

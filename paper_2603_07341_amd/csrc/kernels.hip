@@ -345,7 +345,7 @@ __global__ void __launch_bounds__(kBlock)
       const uint64_t py = pay[p];
       uint32_t rref = kNone;
       if (!slot_target<W>(m, par, py, s, k)) {
-        col[int64_t(s) * cap + p] = -1;
+        col[p * D + s] = -1;
       } else {
         const uint64_t h = key_hash<W>(m, k);
         const uint32_t tag = hash_tag(h);
@@ -386,7 +386,7 @@ __global__ void __launch_bounds__(kBlock)
               if (r & kCand)
                 rref = r & ~kCand;
               else
-                col[int64_t(s) * cap + p] = int32_t(r);
+                col[p * D + s] = int32_t(r);
               done = true;
               break;
             }
@@ -428,7 +428,7 @@ __global__ void __launch_bounds__(kBlock)
     if (row >= cap) {
       atomicOr(err, kErrCapacity);
       crow[c] = kNone;
-      col[int64_t(s) * cap + p] = -1;
+      col[p * D + s] = -1;
       continue;
     }
     uint64_t par[W], k[W];
@@ -443,7 +443,7 @@ __global__ void __launch_bounds__(kBlock)
     const uint64_t e = table[c_slot[c]];
     table[c_slot[c]] = (e & 0xFFFFFFFF00000000ull) | uint64_t(row);
     crow[c] = uint32_t(row);
-    col[int64_t(s) * cap + p] = int32_t(row);
+    col[p * D + s] = int32_t(row);
     Amp z;
     z.x = 0;
     z.y = 0;
@@ -461,7 +461,7 @@ __global__ void __launch_bounds__(kBlock)
     const uint32_t r = c_ref[c];
     if (r >= kOwner) continue;  // kOwner or kNone
     const uint32_t row = crow[r];
-    col[int64_t(c % D) * cap + f0 + c / D] = row == kNone ? -1 : int32_t(row);
+    col[f0 * D + c] = row == kNone ? -1 : int32_t(row);
   }
 }
 
@@ -484,7 +484,7 @@ __global__ void __launch_bounds__(kBlock)
     int32_t out = -1;
     if (slot_target<W>(m, par, pay[p], s, key))
       out = int32_t(table_find<W>(table, mask, keys, key, key_hash<W>(m, key)));
-    col[int64_t(s) * cap + p] = out;
+    col[p * D + s] = out;
   }
 }
 
@@ -561,7 +561,7 @@ __global__ void __launch_bounds__(kBlock)
     const uint64_t p = pay[r];
     double rad = 0;
     for (int s = 0; s < m.D; ++s)
-      if (col[int64_t(s) * cap + r] >= 0) rad += fabs(slot_value(m, p, s));
+      if (col[r * m.D + s] >= 0) rad += fabs(slot_value(m, p, s));
     const double d = row_diag(m, p, m.V > 2 ? tot[r] : 0);
     if (R > 1) {
       atomicMin(&blo[pay_real(p)], ord_of(d - rad));
@@ -741,9 +741,11 @@ __global__ void __launch_bounds__(kBlock)
       gv[nu][0] = R(m.gsq[nu * kGsqStride + occ]);
       gv[nu][1] = R(m.gsq[nu * kGsqStride + occ + 1]);
     }
+    int32_t cols[D];
+    load_cols<D>(col + i * D, cols);
 #pragma unroll
     for (int s = 0; s < D; ++s) {
-      const int32_t c = ld_stream(col + int64_t(s) * cap + i);
+      const int32_t c = cols[s];
       if (c >= 0) {
         const R v = s < 2 * ND ? jv[s >> 1] : gv[(s - 2 * ND) >> 1][(s - 2 * ND) & 1];
         const Amp xj = in[c];
@@ -832,9 +834,11 @@ __global__ void __launch_bounds__(kBlock)
       gv[nu][0] = R(m.gsq[nu * kGsqStride + occ]);
       gv[nu][1] = R(m.gsq[nu * kGsqStride + occ + 1]);
     }
+    int32_t cols[D];
+    load_cols<D>(col + i * D, cols);
 #pragma unroll
     for (int s = 0; s < D; ++s) {
-      const int32_t c = ld_stream(col + int64_t(s) * cap + i);
+      const int32_t c = cols[s];
       if (c >= 0) {
         const R v = s < 2 * ND ? jv[s >> 1] : gv[(s - 2 * ND) >> 1][(s - 2 * ND) & 1];
         const Amp xj = in[c];

@@ -2139,10 +2139,9 @@ paces_status paces_adjoint_backward(paces_sim* s, const double* gbar,
       e = adj_frozen_step(s, i, z.tmap, z.p0, st);
       if (e) break;
       const int64_t n1 = s->nS;
-      for (int sl = 0; sl < D && !e; ++sl)
-        if (hipMemcpyAsync(z.col + int64_t(sl) * n1, s->col + int64_t(sl) * s->cap,
-                           size_t(n1) * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
-          e = fail(PACES_E_HIP, "copy failed");
+      if (hipMemcpyAsync(z.col, s->col, size_t(n1) * D * 4,
+                         hipMemcpyDeviceToDevice, st) != hipSuccess)
+        e = fail(PACES_E_HIP, "copy failed");
       const Side& c = s->side[s->cur];
       if (!e && (hipMemcpyAsync(z.pay, c.pay, size_t(n1) * 8,
                                 hipMemcpyDeviceToDevice, st) != hipSuccess ||
