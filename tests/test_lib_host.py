@@ -99,3 +99,9 @@ def test_allocator_needs_both_functions():
     import ctypes as C
     f = P._ALLOC_FN(lambda n, s, u: None)
     assert P.lib().paces_set_allocator(f, None, None) == 1
+
+
+def test_library_abi_matches_header():
+    src = open(os.path.join(ROOT, "include", "paces.h")).read()
+    want = int(re.search(r"#define PACES_ABI_VERSION (\d+)", src).group(1))
+    assert P.lib().paces_abi_version() == want
