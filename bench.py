@@ -278,11 +278,15 @@ def form_adjoint(args, stream):
 
 
 def source_hash():
+    """Hash of the step kernels' code, comments and blank lines ignored."""
     import hashlib
     h = hashlib.sha256()
     for f in ["kernels.hip", "device.hpp", "kernels.hpp", "common.hpp"]:
-        with open(os.path.join(ROOT, "paper_2603_07341_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2603_07341_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = line.split("//")[0].rstrip()
+                if code:
+                    h.update((code + "\n").encode())
     return h.hexdigest()[:16]
 
 

@@ -29,8 +29,9 @@
  *    (App. "Lossless bit-level compression of state information").
  *  - Amplitudes at the boundary are interleaved FP64 (re, im) pairs; in
  *    FP32 mode they are widened on export and rounded on import.
- *  - Row order of states returned by the library is unspecified but
- *    deterministic; compare sets after sorting.
+ *  - Row order of states returned by the library is unspecified and may
+ *    differ between runs (hash-table races decide it); compare sets after
+ *    sorting.  Amplitudes per basis state are reproduced bit for bit.
  *  - Device errors (hash-table or capacity overflow, non-finite norm,
  *    series longer than k_max_terms) are latched and reported by the next
  *    call that synchronises; the sim then refuses further steps

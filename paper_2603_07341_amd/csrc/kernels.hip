@@ -6,9 +6,10 @@
 // grid-stride grids, clamp counts to the allocated capacity and latch
 // overflows, and every kernel after a latching one returns at once when the
 // latch is set, so a failed step touches nothing out of bounds and leaves
-// the previous state intact for a retry.  Reductions are deterministic:
-// fixed lane-to-row mapping, wave shuffles in a fixed order, per-block
-// partials summed in block order.
+// the previous state intact for a retry.  Sums over rows use a fixed
+// lane-to-row mapping, wave shuffles in a fixed order and per-block
+// partials summed in block order; population and per-realization bins use
+// LDS atomics, whose order within a block is not fixed.
 //
 // Stages (paper: Sec. "Formal operator representation and notes on
 // parallelization"):
@@ -16,8 +17,10 @@
 //              (Sec. "Truncation & post-adaptation detruncation")
 //   expand     k rounds of neighbour generation on packed keys with
 //              insert-if-absent into an HBM hash table (Eqs. (def_neighbor_k),
-//              (H_eff)); candidates resolve duplicates by the smallest
-//              candidate id, so the row order is deterministic
+//              (H_eff)); the candidate whose compare-and-swap claims a key
+//              owns it, so new rows are numbered in an order that may vary
+//              between runs while every amplitude, taken per basis state,
+//              is reproduced bit for bit
 //   transfer   old amplitudes moved to their rows in the new set, weight of
 //              the dropped rows summed (post-adaptation detruncation)
 //   build      ELL columns come out of the expansion; values are implied by
