@@ -27,7 +27,8 @@ class _Desc(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("k", C.c_int32), ("k_init", C.c_int32),
                 ("theta", C.c_double), ("max_terms", C.c_int32),
-                ("max_states", C.c_int64), ("q_nom", C.c_int64)]
+                ("max_states", C.c_int64), ("q_nom", C.c_int64),
+                ("krylov_order", C.c_int32)]
 
 
 _lib = None
@@ -135,6 +136,7 @@ class Sim:
         p.max_terms = max_terms
         p.max_states = int(run.get("max_states", 0))
         p.q_nom = int(run.get("q_nom", 0))
+        p.krylov_order = int(run.get("krylov_order", 0))
         exc = np.ascontiguousarray(exc, dtype=np.int32)
         occ = np.ascontiguousarray(occ, dtype=np.uint16)
         coef = np.ascontiguousarray(coef, dtype=np.float64)
@@ -236,6 +238,30 @@ def expmv(rowptr, cols, vals, dt, emin, emax, v, max_terms=200):
     return vout.view(np.complex128), terms.value
 
 
+def lanczos(rowptr, cols, vals, dt, order, v):
+    """Krylov propagator of order `order` on a CSR matrix: returns
+    (v_out, basis [dim, n], alpha [dim], beta [dim], (e_lo, e_hi))."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int64)
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    vin = np.ascontiguousarray(np.asarray(v, dtype=np.complex128)).view(np.float64)
+    n = len(rowptr) - 1
+    vout = np.zeros(2 * n, dtype=np.float64)
+    basis = np.zeros(2 * n * (order + 1), dtype=np.float64)
+    alpha = np.zeros(order + 1, dtype=np.float64)
+    beta = np.zeros(order + 1, dtype=np.float64)
+    dim = C.c_int32()
+    er = np.zeros(2, dtype=np.float64)
+    _check(lib().orc_lanczos(C.c_int64(n), _p(rowptr, C.c_int64), _p(cols, C.c_int64),
+                             _p(vals, C.c_double), C.c_double(dt), C.c_int32(order),
+                             _p(vin, C.c_double), _p(vout, C.c_double),
+                             _p(basis, C.c_double), _p(alpha, C.c_double),
+                             _p(beta, C.c_double), C.byref(dim), _p(er, C.c_double)))
+    d = dim.value
+    B = basis.view(np.complex128).reshape(order + 1, n)[:d]
+    return vout.view(np.complex128), B, alpha[:d], beta[:max(d, 1)], tuple(er)
+
+
 def param_names(model_params):
     """Names of the gradient entries: J per axis, g and omega per mode,
     eps per site."""
@@ -258,6 +284,7 @@ class Frozen:
         p.max_terms = max_terms
         p.max_states = int(run.get("max_states", 0))
         p.q_nom = int(run.get("q_nom", 0))
+        p.krylov_order = int(run.get("krylov_order", 0))
         exc = np.ascontiguousarray(exc, dtype=np.int32)
         occ = np.ascontiguousarray(occ, dtype=np.uint16)
         coef = np.ascontiguousarray(coef, dtype=np.float64)

@@ -17,7 +17,9 @@
 //                 effective Hilbert space".
 //   step          Sec. "Formal operator representation and notes on
 //                 parallelization": psi -> Q exp(-i P H P dt) psi.
-//   propagator    App. "The action of the exponential of a sparse matrix".
+//   propagator    App. "The action of the exponential of a sparse matrix";
+//                 the Krylov alternative of App. "Series-based
+//                 exponentiation compared to a Lanczos algorithm".
 //   key codec     App. "Lossless bit-level compression of state information".
 //   observables   Eq. (RMSD) populations; Eq. (init_state_spec) overlap.
 //
@@ -422,6 +424,148 @@ double weight(const cplx& c) {
   return a + b;
 }
 
+// ---------------------------------------------------------------------------
+// Eigen-decomposition of a symmetric n x n matrix by cyclic Jacobi
+// rotations (Golub & Van Loan, "Matrix Computations", the symmetric Schur
+// decomposition and the cyclic Jacobi method).  a is row-major and is
+// overwritten; on return its diagonal holds the eigenvalues and the columns
+// of q the eigenvectors.
+// ---------------------------------------------------------------------------
+void jacobi_eigen(int n, std::vector<double>& a, std::vector<double>& q) {
+  q.assign(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) q[size_t(i) * n + i] = 1.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0, all = 0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        const double v = a[size_t(i) * n + j] * a[size_t(i) * n + j];
+        all += v;
+        if (i != j) off += v;
+      }
+    if (off == 0.0 || off <= 1e-36 * all) break;
+    for (int p = 0; p < n; ++p)
+      for (int r = p + 1; r < n; ++r) {
+        const double apr = a[size_t(p) * n + r];
+        if (apr == 0.0) continue;
+        // rotation J with J_pp = J_rr = c, J_pr = s, J_rp = -s that zeroes
+        // the (p, r) entry of J^T A J
+        const double tau = (a[size_t(r) * n + r] - a[size_t(p) * n + p]) / (2 * apr);
+        const double t = (tau >= 0 ? 1.0 : -1.0) /
+                         (std::fabs(tau) + std::sqrt(tau * tau + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {  // A J: columns p and r
+          const double akp = a[size_t(k) * n + p], akr = a[size_t(k) * n + r];
+          a[size_t(k) * n + p] = c * akp - s * akr;
+          a[size_t(k) * n + r] = s * akp + c * akr;
+        }
+        for (int k = 0; k < n; ++k) {  // J^T (A J): rows p and r
+          const double apk = a[size_t(p) * n + k], ark = a[size_t(r) * n + k];
+          a[size_t(p) * n + k] = c * apk - s * ark;
+          a[size_t(r) * n + k] = s * apk + c * ark;
+        }
+        for (int k = 0; k < n; ++k) {  // Q J
+          const double qkp = q[size_t(k) * n + p], qkr = q[size_t(k) * n + r];
+          q[size_t(k) * n + p] = c * qkp - s * qkr;
+          q[size_t(k) * n + r] = s * qkp + c * qkr;
+        }
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Krylov (Lanczos) propagator of App. "Series-based exponentiation compared
+// to a Lanczos algorithm": exp(-i H dt) v ~ V exp(-i T dt) V^dag v, V an
+// orthonormal basis of the Krylov space span{v, Hv, .., H^p v} and
+// T = V^dag H V tridiagonal.  Order p in the paper's sense: the order-2
+// propagator works in span{v, Hv, H^2 v}, so the space has p + 1
+// dimensions.  The basis comes from the three-term recurrence
+//   v_0 = v / beta_0, beta_0 = |v|,
+//   alpha_j = <v_j|H|v_j>,
+//   r = H v_j - alpha_j v_j - beta_j v_{j-1},  beta_{j+1} = |r|,
+//   v_{j+1} = r / beta_{j+1}.
+// Readings where the paper is silent:
+//   * the basis stops early (breakdown: the space is invariant, so the
+//     result is exact) when beta_{j+1} <= 1e-11 |H v_j|; beta_0 = 0 gives
+//     the zero vector and dimension 0;
+//   * no re-orthogonalisation, as in the plain recurrence.
+// With V^dag v = beta_0 e_1 the result is beta_0 sum_j u_j v_j where
+// u = exp(-i T dt) e_1 = Q exp(-i L dt) Q^T e_1 from the eigen-
+// decomposition T = Q L Q^T.  e_lo / e_hi: Gershgorin interval of T,
+// widened by 1e-12 of its magnitude like that of H.
+// ---------------------------------------------------------------------------
+struct KrylovOut {
+  int dim = 0;
+  std::vector<std::vector<cplx>> V;
+  std::vector<double> alpha, beta;  // beta[0] = |v|; beta[j] couples j-1, j
+  double e_lo = 0, e_hi = 0;
+};
+
+int lanczos_expmv(const CSR& H, double dt, int order,
+                  const std::vector<cplx>& v, std::vector<cplx>& out,
+                  KrylovOut& ko) {
+  if (order < 1) return fail("Krylov order must be at least 1");
+  const int nmax = order + 1;
+  ko = KrylovOut();
+  double b0 = 0;
+  for (const cplx& c : v) b0 += weight(c);
+  b0 = std::sqrt(b0);
+  ko.beta.push_back(b0);
+  out.assign(H.n, cplx(0, 0));
+  if (b0 == 0.0) return 0;
+  std::vector<cplx> v0(H.n), hv, r(H.n);
+  for (int64_t i = 0; i < H.n; ++i) v0[i] = v[i] / b0;
+  ko.V.push_back(v0);
+  for (int j = 0; j < nmax; ++j) {
+    const std::vector<cplx>& vj = ko.V[j];
+    spmv(H, vj, hv);
+    double a = 0;
+    for (int64_t i = 0; i < H.n; ++i) a += (std::conj(vj[i]) * hv[i]).real();
+    ko.alpha.push_back(a);
+    if (j + 1 == nmax) break;
+    double rn = 0, hn = 0;
+    for (int64_t i = 0; i < H.n; ++i) {
+      r[i] = hv[i] - a * vj[i];
+      if (j > 0) r[i] -= ko.beta[j] * ko.V[j - 1][i];
+      rn += weight(r[i]);
+      hn += weight(hv[i]);
+    }
+    if (rn <= 1e-22 * hn) break;  // invariant subspace
+    const double b = std::sqrt(rn);
+    ko.beta.push_back(b);
+    std::vector<cplx> next(H.n);
+    for (int64_t i = 0; i < H.n; ++i) next[i] = r[i] / b;
+    ko.V.push_back(next);
+  }
+  const int n = int(ko.alpha.size());
+  ko.dim = n;
+  std::vector<double> T(size_t(n) * n, 0.0), Q;
+  double lo = 0, hi = 0;
+  for (int j = 0; j < n; ++j) {
+    T[size_t(j) * n + j] = ko.alpha[j];
+    double rad = 0;
+    if (j > 0) {
+      T[size_t(j) * n + j - 1] = T[size_t(j - 1) * n + j] = ko.beta[j];
+      rad += std::fabs(ko.beta[j]);
+    }
+    if (j + 1 < n) rad += std::fabs(ko.beta[j + 1]);
+    const double l = ko.alpha[j] - rad, h = ko.alpha[j] + rad;
+    lo = j == 0 ? l : std::min(lo, l);
+    hi = j == 0 ? h : std::max(hi, h);
+  }
+  const double pad = 1e-12 * (std::fabs(hi) + std::fabs(lo));
+  ko.e_lo = lo - pad;
+  ko.e_hi = hi + pad;
+  jacobi_eigen(n, T, Q);
+  for (int j = 0; j < n; ++j) {
+    cplx u(0, 0);
+    for (int k = 0; k < n; ++k)
+      u += Q[size_t(j) * n + k] * std::exp(cplx(0.0, -T[size_t(k) * n + k] * dt)) *
+           Q[size_t(k)];
+    for (int64_t i = 0; i < H.n; ++i) out[i] += b0 * u * ko.V[j][i];
+  }
+  return 0;
+}
+
 struct Obs {
   double f[ORC_OBS_NFIELDS];
   std::vector<double> pop;
@@ -432,6 +576,7 @@ struct Params {
   int k = 2, k_init = 2, max_terms = 200;
   int64_t max_states = 0;  // cap on |S| (0 = none)
   int64_t q_nom = 0;       // fixed-size truncation (0 = threshold)
+  int krylov_order = 0;    // > 0: Lanczos propagator of this order
 };
 
 // ---------------------------------------------------------------------------
@@ -574,7 +719,16 @@ int sim_step(Sim& sim) {
   build_csr(m, ball, H);
   std::vector<cplx> out;
   int terms = 0;
-  if (expmv(H, sim.p.dt, sim.p.max_terms, phi, out, terms)) return 1;
+  double e_lo = H.emin, e_hi = H.emax;
+  if (sim.p.krylov_order > 0) {
+    KrylovOut ko;
+    if (lanczos_expmv(H, sim.p.dt, sim.p.krylov_order, phi, out, ko)) return 1;
+    terms = ko.dim;
+    e_lo = ko.e_lo;
+    e_hi = ko.e_hi;
+  } else if (expmv(H, sim.p.dt, sim.p.max_terms, phi, out, terms)) {
+    return 1;
+  }
   sim.S = ball;
   sim.psi = out;
   sim.M = M;
@@ -615,8 +769,8 @@ int sim_step(Sim& sim) {
   o.f[ORC_OBS_NS] = double(ball.size());
   o.f[ORC_OBS_NM] = double(M.size());
   o.f[ORC_OBS_TERMS] = double(terms);
-  o.f[ORC_OBS_EMIN] = H.emin;
-  o.f[ORC_OBS_EMAX] = H.emax;
+  o.f[ORC_OBS_EMIN] = e_lo;
+  o.f[ORC_OBS_EMAX] = e_hi;
   sim.obs.push_back(o);
   return 0;
 }
@@ -1090,6 +1244,11 @@ int orc_sim_create(const void* mp, const orc_params* p, int64_t n,
     return fail("bad q_nom");
   }
   s->p.q_nom = p->q_nom;
+  if (p->krylov_order < 0 || p->krylov_order > 63) {
+    delete s;
+    return fail("bad krylov_order");
+  }
+  s->p.krylov_order = p->krylov_order;
   if (load_state(*m, n, keys.data(), coef, s->S, s->psi)) {
     delete s;
     return 1;
@@ -1229,10 +1388,48 @@ int orc_expmv(int64_t n, const int64_t* rowptr, const int64_t* cols,
   return 0;
 }
 
+int orc_lanczos(int64_t n, const int64_t* rowptr, const int64_t* cols,
+                const double* vals, double dt, int32_t order,
+                const double* v_in, double* v_out, double* basis,
+                double* alpha, double* beta, int32_t* dim, double* e_range) {
+  if (n < 0 || !rowptr || !v_in || !v_out) return fail("bad arguments");
+  CSR H;
+  H.n = n;
+  H.rowptr.assign(rowptr, rowptr + n + 1);
+  H.cols.assign(cols, cols + rowptr[n]);
+  H.vals.assign(vals, vals + rowptr[n]);
+  std::vector<cplx> v(n), out;
+  for (int64_t i = 0; i < n; ++i) v[i] = cplx(v_in[2 * i], v_in[2 * i + 1]);
+  KrylovOut ko;
+  if (lanczos_expmv(H, dt, order, v, out, ko)) return 1;
+  for (int64_t i = 0; i < n; ++i) {
+    v_out[2 * i] = out[i].real();
+    v_out[2 * i + 1] = out[i].imag();
+  }
+  for (int j = 0; j < ko.dim; ++j) {
+    if (basis)
+      for (int64_t i = 0; i < n; ++i) {
+        basis[2 * (int64_t(j) * n + i)] = ko.V[j][i].real();
+        basis[2 * (int64_t(j) * n + i) + 1] = ko.V[j][i].imag();
+      }
+    if (alpha) alpha[j] = ko.alpha[j];
+  }
+  if (beta)
+    for (size_t j = 0; j < ko.beta.size(); ++j) beta[j] = ko.beta[j];
+  if (dim) *dim = ko.dim;
+  if (e_range) {
+    e_range[0] = ko.e_lo;
+    e_range[1] = ko.e_hi;
+  }
+  return 0;
+}
+
 int orc_frozen_record(const void* mp, const orc_params* p, int64_t n,
                       const int32_t* exc, const uint16_t* occ,
                       const double* coef, int64_t n_steps, void** out) {
   if (!mp || !out || n_steps < 0) return fail("bad arguments");
+  if (p && p->krylov_order != 0)
+    return fail("the adjoint gradient differentiates the series propagator");
   void* sp = nullptr;
   if (orc_sim_create(mp, p, n, exc, occ, coef, &sp)) return 1;
   Sim* sim = static_cast<Sim*>(sp);

@@ -55,6 +55,9 @@ typedef struct {
   int64_t q_nom;         /* > 0: after the first step M is the q_nom
                             heaviest rows (same order as the cap) instead
                             of the threshold; exclusive with max_states     */
+  int32_t krylov_order;  /* 0: series propagator; p in 1..63: Lanczos
+                            propagator in the (p+1)-dimensional Krylov
+                            space (see orc_lanczos)                          */
 } orc_params;
 
 /* Observables recorded after each step (field order of orc_sim_obs). */
@@ -126,6 +129,20 @@ int orc_expmv(int64_t n, const int64_t* rowptr, const int64_t* cols,
               const double* vals, double dt, double emin, double emax,
               int32_t max_terms, const double* v_in, double* v_out,
               int32_t* terms);
+
+/* Krylov (Lanczos) propagator of order p for a caller-given CSR H:
+ * v_out ~ V exp(-i T dt) V^dag v_in in span{v, Hv, .., H^p v} (App.
+ * "Series-based exponentiation compared to a Lanczos algorithm").
+ * basis[dim][n] receives the orthonormal Lanczos vectors (interleaved
+ * complex; room for p+1 vectors), alpha[dim] the diagonal of T,
+ * beta[dim] the norms (beta[0] = |v_in|, beta[j] couples v_{j-1} and v_j),
+ * dim the dimension reached (smaller than p+1 after a breakdown) and
+ * e_range[2] the padded Gershgorin interval of T.  Output pointers other
+ * than v_out may be NULL. */
+int orc_lanczos(int64_t n, const int64_t* rowptr, const int64_t* cols,
+                const double* vals, double dt, int32_t order,
+                const double* v_in, double* v_out, double* basis,
+                double* alpha, double* beta, int32_t* dim, double* e_range);
 
 /* Adjoint gradient on a frozen sequence of sets (Form (3)).
  * orc_frozen_record runs n_steps ordinary steps from the initial state and
