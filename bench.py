@@ -14,8 +14,9 @@ algorithmic bytes per launch |S| (4A + 4D + 16) over its HIP-event
 duration on the step's stream.
 cpu_baseline: the CPU oracle continued from the GPU state at the start of
 the timed window, for a bounded number of steps.
-forms: the three extra forms against plain FP64 single-realization runs on
-the same GPU: complex64 amplitudes on the same window; 64 disorder
+forms: the extra forms against plain FP64 single-realization runs on the
+same GPU: complex64 amplitudes on the same window; the order-10 Krylov
+propagator on the same window from the same state; 64 disorder
 realizations of the 6x6 lattice in one sim against realizations run one
 after another; the adjoint gradient of the 12-site ring against its plain
 forward run (time ratio).
@@ -48,6 +49,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=40)
     ap.add_argument("--batch-singles", type=int, default=8)
     ap.add_argument("--adjoint-steps", type=int, default=200)
+    ap.add_argument("--krylov-order", type=int, default=10)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (a "
                          "known-size reference for hardware byte counters)")
@@ -85,9 +87,11 @@ def main():
     tuning = sim.autotune(steps=2, stream=stream) if args.tune == "auto" else sim.tuning()
     torch.cuda.synchronize()
     nS0 = sim.size(stream)
+    forms = not args.no_forms and args.config == "ring16" and args.precision == 64
     cpu_state = None
-    if not args.no_cpu:
+    if not args.no_cpu or forms:
         cpu_state = sim.state(stream)
+    t_start = float(sim.series(sim.num_records() - 1, 1, stream)[0, 0])
     nrec0 = sim.num_records()
     print("timing %d steps from |S| = %d" % (args.steps, nS0), file=sys.stderr,
           flush=True)
@@ -146,14 +150,16 @@ def main():
         "tuning": tuning,
         "terms_per_step": float(rec[:, 9].mean()),
     }
-    if not args.no_forms and args.config == "ring16" and args.precision == 64:
+    if forms:
         del sim
         out["forms"] = {
             "fp32": form_fp32(args, rec, elapsed, stream),
+            "krylov": form_krylov(args, cpu_state, t_start, rec, elapsed,
+                                  stream),
             "batched": form_batched(args, stream),
             "adjoint": form_adjoint(args, stream),
         }
-    if cpu_state is not None:
+    if cpu_state is not None and not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(params, run, cpu_state, cfg,
                                            args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -190,6 +196,48 @@ def form_fp32(args, rec64, el64, stream):
             "max_abs_err_autocorr_vs_fp64": float(np.max(np.abs(a32 - a64))),
             "max_rel_err_norm_vs_fp64": float(np.max(np.abs(rec[:, 1] / rec64[:, 1] - 1))),
             "S_mean_fp32_over_fp64": float(rec[:, 7].sum() / rec64[:, 7].sum())}
+
+
+def form_krylov(args, state, t_start, rec_ref, el_ref, stream):
+    """The timed window again with the order-10 Krylov (Lanczos) propagator
+    in place of the series, from the same state: throughput against the
+    series run, deviation of a(t) from it, and the roofline of the Lanczos
+    SpMV (its algorithmic bytes per row 2A + 4D + 8: w_j and H w_j once
+    each, the columns and the payload)."""
+    import numpy as np
+    import paper_2603_07341_amd as P
+    import workloads as WL
+    order = args.krylov_order
+    cfg = dict(WL.CONFIGS["ring16"], precision=64)
+    m = P.Model(WL.model_params(cfg))
+    run = dict(WL.run_params(cfg), krylov_order=order)
+    s = P.Sim(m, run, *WL.initial_state(cfg), stream=stream)
+    keys, amps = state
+    s.set_state(keys, amps, t_start, stream=stream)
+    print("krylov: order %d, %d steps from |S| = %d" % (order, args.steps,
+                                                        len(keys)),
+          file=sys.stderr, flush=True)
+    s.profile(True)
+    s.profile_reset()
+    _, el = timed(lambda: s.step(args.steps, stream=stream))
+    prof = s.profile_get(stream)
+    s.profile(False)
+    rec = s.series(0, args.steps, stream)
+    n = prof["launches"]["krylov"]
+    ms = prof["ms"]["krylov"] / max(n, 1)
+    ach = prof["krylov_bytes"] / max(n, 1) / (ms * 1e-3) / 1e9 if n else 0.0
+    a = rec[:, 3] + 1j * rec[:, 4]
+    a_ref = rec_ref[:, 3] + 1j * rec_ref[:, 4]
+    return {"order": order, "value": float(rec[:, 7].sum()) / el,
+            "unit": "updates/s", "ms_per_step": el * 1e3 / args.steps,
+            "time_vs_series": el / el_ref,
+            "max_abs_err_autocorr_vs_series": float(np.max(np.abs(a - a_ref))),
+            "max_rel_err_norm_vs_series": float(np.max(np.abs(rec[:, 1] / rec_ref[:, 1] - 1))),
+            "stage_ms": {k: round(v, 3) for k, v in prof["ms"].items()},
+            "spmv_roofline": {"bound": "hbm", "achieved": ach,
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": ach / HBM_PEAK_GBS, "launches": n,
+                              "avg_ms": ms}}
 
 
 def form_batched(args, stream):

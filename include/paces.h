@@ -31,7 +31,10 @@
  *    FP32 mode they are widened on export and rounded on import.
  *  - Row order of states returned by the library is unspecified and may
  *    differ between runs (hash-table races decide it); compare sets after
- *    sorting.  Amplitudes per basis state are reproduced bit for bit.
+ *    sorting.  Amplitudes per basis state are reproduced bit for bit with
+ *    the series propagator; the Krylov propagator's inner products are
+ *    sums over rows in that order, so its amplitudes repeat only within
+ *    rounding.
  *  - Device errors (hash-table or capacity overflow, non-finite norm,
  *    series longer than k_max_terms) are latched and reported by the next
  *    call that synchronises; the sim then refuses further steps
@@ -58,7 +61,7 @@
 extern "C" {
 #endif
 
-#define PACES_ABI_VERSION 8
+#define PACES_ABI_VERSION 9
 
 typedef enum {
   PACES_OK = 0,
@@ -121,6 +124,18 @@ typedef struct {
                           heaviest rows of each realization's set in the
                           same order as the state cap, and theta is not
                           used.  Exclusive with max_states.               */
+  int32_t krylov_order;/* 0: Chebyshev series propagator.  p in 1..63:
+                          Krylov (Lanczos) propagator of order p (paper:
+                          App. "Series-based exponentiation compared to a
+                          Lanczos algorithm"), psi' = V exp(-i T dt) V^dag
+                          phi in span{phi, H phi, .., H^p phi}, built by
+                          the three-term recurrence without
+                          re-orthogonalisation; the basis stops early
+                          when |w_j| <= 1e-11 |H v_{j-1}| (1e-6 in FP32).
+                          Holds p extra vectors of the row capacity; the
+                          record's K is the dimension used and E_min /
+                          E_max the padded Gershgorin interval of T.  Not
+                          with the adjoint entry points.                  */
 } paces_run_params;
 
 #define PACES_OBS_ENERGY 1u /* <psi|H_eff|psi> per step (one extra SpMV
@@ -129,8 +144,10 @@ typedef struct {
 typedef struct {
   double t, norm2, energy, autocorr_re, autocorr_im, mass_step, mass_total;
   int64_t n_S, n_M;
-  int32_t K;           /* Chebyshev terms used by the step                 */
-  double E_min, E_max; /* padded Gershgorin bounds of H_eff                */
+  int32_t K;           /* Chebyshev terms used by the step (Krylov
+                          propagator: dimension of the Krylov space)       */
+  double E_min, E_max; /* padded Gershgorin bounds of H_eff (Krylov: of
+                          the tridiagonal T)                               */
   const double* pop;   /* [N] exciton populations; owned by the sim,
                           valid until the next call on it                  */
 } paces_obs;
@@ -249,13 +266,16 @@ typedef enum {
   PACES_STAGE_PROPAGATE = 4,/* all Clenshaw launches                      */
   PACES_STAGE_OBSERVE = 5,
   PACES_STAGE_TERM = 6,     /* middle Clenshaw launches only              */
-  PACES_NUM_STAGES = 7
+  PACES_STAGE_KRYLOV = 7,   /* Lanczos SpMV launches except the last      */
+  PACES_NUM_STAGES = 8
 } paces_stage;
 typedef struct {
   double ms[PACES_NUM_STAGES];      /* summed event time                  */
   int64_t launches[PACES_NUM_STAGES];
   double term_bytes;                /* algorithmic bytes of the timed
                                        middle Clenshaw launches          */
+  double krylov_bytes;              /* algorithmic bytes of the timed
+                                       Lanczos SpMV launches             */
   double rows_steps;                /* sum over steps of |S|              */
 } paces_profile;
 paces_status paces_profile_enable(paces_sim* s, int32_t on);
@@ -270,8 +290,9 @@ paces_status paces_profile_reset(paces_sim* s);
  * site), paces_num_params entries in that order.  The sets of the recorded
  * run are held fixed (each step is then linear in psi); the gradient is
  * the discrete adjoint of that frozen-set propagation.  Needs one
- * realization, FP64 amplitudes and every J_axis, g_nu nonzero (so that the
- * ELL holds every lattice edge); otherwise PACES_E_UNSUPPORTED. */
+ * realization, FP64 amplitudes, the series propagator and every J_axis,
+ * g_nu nonzero (so that the ELL holds every lattice edge); otherwise
+ * PACES_E_UNSUPPORTED. */
 int32_t paces_num_params(const paces_model* m);
 /* Run n_steps steps from a new sim (no step taken yet), keeping the
  * selected set of every step and the state every ckpt_every steps (device

@@ -22,7 +22,7 @@ OBS_FIELDS = ["t", "norm2", "energy", "a_re", "a_im", "mass_step",
               "mass_total", "n_S", "n_M", "K", "E_min", "E_max"]
 SET_M, SET_S, SET_FRONTIER = 0, 1, 2
 STAGES = ["select", "expand", "transfer", "build", "propagate", "observe",
-          "term"]
+          "term", "krylov"]
 STATUS = {0: "OK", 1: "E_ARG", 2: "E_OOM", 3: "E_CAPACITY", 4: "E_NONFINITE",
           5: "E_PROPAGATOR", 6: "E_HIP", 7: "E_STATE", 8: "E_UNSUPPORTED"}
 
@@ -60,7 +60,8 @@ class _Run(C.Structure):
                 ("theta", C.c_double), ("cap_states", C.c_int64),
                 ("precision", C.c_int32), ("tol", C.c_double),
                 ("k_max_terms", C.c_int32), ("obs_mask", C.c_uint32),
-                ("max_states", C.c_int64), ("q_nom", C.c_int64)]
+                ("max_states", C.c_int64), ("q_nom", C.c_int64),
+                ("krylov_order", C.c_int32)]
 
 
 class _Obs(C.Structure):
@@ -73,8 +74,9 @@ class _Obs(C.Structure):
 
 
 class _Profile(C.Structure):
-    _fields_ = [("ms", C.c_double * 7), ("launches", C.c_int64 * 7),
-                ("term_bytes", C.c_double), ("rows_steps", C.c_double)]
+    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8),
+                ("term_bytes", C.c_double), ("krylov_bytes", C.c_double),
+                ("rows_steps", C.c_double)]
 
 
 class _Tuning(C.Structure):
@@ -224,6 +226,7 @@ class Sim:
         r.obs_mask = obs_mask
         r.max_states = int(run.get("max_states", 0))
         r.q_nom = int(run.get("q_nom", 0))
+        r.krylov_order = int(run.get("krylov_order", 0))
         exc = np.ascontiguousarray(exc, dtype=np.int32)
         occ = np.ascontiguousarray(occ, dtype=np.uint16)
         coef = np.ascontiguousarray(coef, dtype=np.float64)
@@ -374,7 +377,8 @@ class Sim:
         _check(lib().paces_profile_get(self.h, C.byref(p), _stream(stream)))
         return {"ms": dict(zip(STAGES, list(p.ms))),
                 "launches": dict(zip(STAGES, list(p.launches))),
-                "term_bytes": p.term_bytes, "rows_steps": p.rows_steps}
+                "term_bytes": p.term_bytes, "krylov_bytes": p.krylov_bytes,
+                "rows_steps": p.rows_steps}
 
     def tuning(self):
         t = _Tuning()

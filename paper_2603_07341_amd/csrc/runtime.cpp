@@ -30,6 +30,7 @@
 #include "adjoint.hpp"
 #include "cap.hpp"
 #include "kernels.hpp"
+#include "lanczos.hpp"
 
 using namespace paces;
 
@@ -288,6 +289,12 @@ struct paces_sim {
   int32_t* p0_last = nullptr;  // [R][n0] rows of the initial states in S
   AdjRecord* adj = nullptr;
 
+  // Krylov propagator (krylov_order > 0)
+  LanczosState* lz = nullptr;   // [R]
+  double* lz_part = nullptr;    // per-block partials of the Lanczos SpMV
+  double* lz_energy = nullptr;  // [R] <phi|H|phi>
+  std::vector<void*> kry;       // basis vectors 2 .. order, row capacity
+
   // state cap (max_states per realization)
   uint32_t* ball = nullptr;       // [R] rows of the new set per realization
   bool cap_active = false;        // the step runs with a cut selection
@@ -395,6 +402,8 @@ void free_rows(paces_sim* s) {
   dfree(s->midx);
   dfree(s->scan_tmp);
   dfree(s->e_row);
+  for (auto& v : s->kry) dev_free(v);
+  s->kry.clear();
 }
 
 void free_cand(paces_sim* s) {
@@ -457,6 +466,8 @@ paces_status grow(paces_sim* s, int64_t new_cap, hipStream_t st) {
   dfree(s->midx);
   dfree(s->scan_tmp);
   dfree(s->e_row);
+  for (auto& v : s->kry) dev_free(v);
+  s->kry.clear();
   Side nsd[2]{};
   for (int q = 0; q < 2; ++q) {
     ST_TRY(dalloc(&nsd[q].keys, new_cap * m->Wi));
@@ -491,6 +502,13 @@ paces_status grow(paces_sim* s, int64_t new_cap, hipStream_t st) {
   ST_TRY(dalloc(&s->midx, new_cap));
   ST_TRY(dalloc(&s->scan_tmp, scan_tmp_words(new_cap)));
   if (m->R > 1) ST_TRY(dalloc(&s->e_row, new_cap));
+  // Krylov basis: w_0 = phi and w_1 = the second Clenshaw buffer; the
+  // remaining order - 1 vectors here
+  for (int j = 2; j <= s->p.krylov_order; ++j) {
+    void* q = nullptr;
+    ST_TRY(dev_alloc(&q, size_t(new_cap) * s->A));
+    s->kry.push_back(q);
+  }
   HIP_TRY(hipStreamSynchronize(st));
   dfree(old.keys);
   dfree(old.pay);
@@ -654,13 +672,47 @@ void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st,
                             fz ? fz->tmap : nullptr, s->err, st);
     n_mass = R == 1 ? fold_sum(s->mass_part, np, s->mass_fold, s->err, st) : np;
   }
+  const bool want_e = (s->p.obs_mask & PACES_OBS_ENERGY) != 0;
+  if (s->p.krylov_order > 0) {
+    // Krylov propagator: nk SpMVs with their folds, nk - 1 recurrence
+    // passes, the small exponential and the combination into b0
+    Stage sg(s, PACES_STAGE_PROPAGATE, st);
+    const int nk = s->p.krylov_order + 1;
+    KrylovVecs kv{};
+    kv.w[0] = s->vec[s->iphi];
+    for (int j = 1; j < nk; ++j)
+      kv.w[j] = j == 1 ? s->vec[s->ib1] : s->kry[j - 2];
+    const double brk = s->prec == 64 ? kLzBreak64 : kLzBreak32;
+    lz_begin(s->lz, R, s->err, st);
+    for (int j = 0; j < nk; ++j) {
+      const bool last = j == nk - 1;
+      void* out = last ? nullptr : kv.w[j + 1];
+      int np = 0;
+      if (!last) {
+        Stage tg(s, PACES_STAGE_KRYLOV, st, j);
+        np = lz_spmv(dm, s->prec, j, est, s->ctl, s->col, sn, s->lz, kv.w[j],
+                     out, s->lz_part, s->err, st);
+      } else {
+        np = lz_spmv(dm, s->prec, j, est, s->ctl, s->col, sn, s->lz, kv.w[j],
+                     out, s->lz_part, s->err, st);
+      }
+      lz_fold(j, s->lz_part, np, R, brk * brk, s->lz, s->lz_energy, s->err,
+              st);
+      if (!last)
+        lz_orth(dm, s->prec, j, est, s->ctl, sn.pay, s->lz, kv.w[j + 1],
+                kv.w[j], j > 0 ? kv.w[j - 1] : nullptr, s->err, st);
+    }
+    lz_small(R, s->p.dt, s->p.tol, s->p.k_max_terms, s->lz, s->cc, s->ctl,
+             s->err, st);
+    lz_combine(dm, s->prec, est, s->ctl, sn.pay, s->lz, kv, nk,
+               s->vec[s->ib0], s->err, st);
+  } else {
   {
     Stage sg(s, PACES_STAGE_BUILD, st);
     bounds_and_coef(dm, sn, s->col, s->cap, est, s->ctl, s->p.dt, s->p.tol,
                     s->p.k_max_terms, s->launched, s->bnd_part, s->cc, s->err,
                     st);
   }
-  const bool want_e = (s->p.obs_mask & PACES_OBS_ENERGY) != 0;
   {
     Stage sg(s, PACES_STAGE_PROPAGATE, st);
     int np = 0;
@@ -675,20 +727,25 @@ void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st,
     }
     if (want_e && R == 1) n_e = fold_sum(s->e_part, np, s->e_fold, s->err, st);
   }
+  }
+  const bool krylov = s->p.krylov_order > 0;
   {
     Stage sg(s, PACES_STAGE_OBSERVE, st);
     const int n_pop = pop_norm(s->prec, m->N, R, s->th2, est, s->ctl,
                                s->vec[s->ib0], sn.pay,
-                               want_e && R > 1 ? s->e_row : nullptr,
+                               want_e && R > 1 && !krylov ? s->e_row : nullptr,
                                s->n2_part, s->en_part, s->pop_part,
                                s->scan_tmp, s->cnt + R, s->err, st);
     autocorr(dm, Wi, s->prec, s->keys0, s->amps0, s->n0, s->table, s->tmask,
              sn.keys, s->vec[s->ib0], s->a2, fz ? fz->p0map : s->p0_last,
              s->err, st);
-    obs_final(m->N, R, want_e ? 1 : 0, s->p.dt, n_mass, n_e, n_pop,
+    obs_final(m->N, R, want_e && !krylov ? 1 : 0, s->p.dt, n_mass, n_e, n_pop,
               R == 1 ? s->mass_fold : s->mass_part, s->n2_part, s->e_fold,
               s->en_part, s->pop_part, s->a2, s->cc, s->ctl, s->cnt,
               s->mass_tot, s->ring, s->rec_doubles, s->ring_cap, s->err, st);
+    if (want_e && krylov)
+      lz_record_energy(R, s->lz_energy, s->ctl, s->ring, s->rec_doubles,
+                       s->ring_cap, s->err, st);
     end_step(s->ctl, R, s->ring, s->rec_doubles, s->mass_tot, s->err, st);
   }
 }
@@ -702,7 +759,7 @@ paces_status launch_step_graph(paces_sim* s, int64_t est, bool counted,
       int64_t(s->gen), s->cur, s->ipsi, s->iphi, s->ib0, s->ib1,
       s->fresh ? 1 : 0, counted ? 1 : 0, s->fresh ? s->p.k_init : s->p.k,
       s->launched, s->K_last, est, std::min(bucket(s->nS), s->cap),
-      int64_t(s->tmask), s->tune.term_rows};
+      int64_t(s->tmask), s->tune.term_rows, s->p.krylov_order};
   for (auto& g : s->graphs)
     if (g.key == key) {
       g.used = ++s->graph_clock;
@@ -947,7 +1004,10 @@ paces_status do_step(paces_sim* s, hipStream_t st,
       const int K = int(c.kmax);
       // classify the timed Clenshaw launches of this step
       const double rowb = 4.0 * double(s->A) + 4.0 * m->D + (m->V > 2 ? 16 : 8);
+      // Lanczos SpMV: w_j and z once each, the columns and the payload
+      const double rowk = 2.0 * double(s->A) + 4.0 * m->D + (m->V > 2 ? 16 : 8);
       for (auto& ev : s->pending) {
+        if (ev.stage == PACES_STAGE_KRYLOV) ev.bytes = double(c.n_new) * rowk;
         if (ev.stage == PACES_STAGE_TERM) {
           if (ev.kk >= 1 && ev.kk <= K - 3) {
             ev.bytes = double(c.n_new) * rowb;
@@ -1145,6 +1205,9 @@ namespace {
 
 paces_status adj_supported(const paces_sim* s) {
   const paces_model* m = s->m;
+  if (s->p.krylov_order > 0)
+    return fail(PACES_E_UNSUPPORTED,
+                "the adjoint differentiates the series propagator");
   if (m->R != 1 || s->prec != 64)
     return fail(PACES_E_UNSUPPORTED,
                 "the adjoint needs one realization and FP64 amplitudes");
@@ -1535,7 +1598,8 @@ paces_status paces_init_state(const paces_model* m, const paces_run_params* p,
       p->k_max_terms > kMaxTerms || p->tol < 0 || p->cap_states < 0 ||
       p->max_states < 0 || p->max_states >= (int64_t(1) << 31) ||
       p->q_nom < 0 || p->q_nom >= (int64_t(1) << 31) ||
-      (p->q_nom > 0 && p->max_states > 0))
+      (p->q_nom > 0 && p->max_states > 0) || p->krylov_order < 0 ||
+      p->krylov_order >= kMaxKrylov)
     return fail(PACES_E_ARG, "bad run parameters");
   const int R = m->R;
   if (n * R > (int64_t(1) << 30)) return fail(PACES_E_ARG, "too many states");
@@ -1592,6 +1656,11 @@ paces_status paces_init_state(const paces_model* m, const paces_run_params* p,
       dalloc(&s->ball, R) ||
       dalloc(&s->keys0, nt * m->Wi) ||
       dalloc(&s->amps0, 2 * nt))
+    return cleanup(PACES_E_OOM);
+  if (p->krylov_order > 0 &&
+      (dalloc(&s->lz, R) || dalloc(&s->lz_energy, R) ||
+       dalloc(&s->lz_part, 3 * std::max<int64_t>(kLzGrid1,
+                                                 int64_t(kPartBlocks) * R))))
     return cleanup(PACES_E_OOM);
   double* q = s->parts;
   s->mass_part = q;  q += sz_mass;
@@ -1652,6 +1721,9 @@ paces_status paces_free_sim(paces_sim* s) {
   dfree(s->keys0);
   dfree(s->amps0);
   dfree(s->ring);
+  dfree(s->lz);
+  dfree(s->lz_part);
+  dfree(s->lz_energy);
   drop_pending(s);
   for (auto& e : s->events) {
     (void)hipEventDestroy(e.a);
@@ -1858,6 +1930,7 @@ paces_status paces_profile_get(paces_sim* s, paces_profile* out,
     s->acc.ms[e.stage] += ms;
     s->acc.launches[e.stage] += 1;
     if (e.stage == PACES_STAGE_TERM) s->acc.term_bytes += e.bytes;
+    if (e.stage == PACES_STAGE_KRYLOV) s->acc.krylov_bytes += e.bytes;
     (void)hipEventDestroy(e.a);
     (void)hipEventDestroy(e.b);
   }

@@ -1,0 +1,204 @@
+"""Krylov (Lanczos) propagator on the GPU vs the CPU oracle, through the C
+ABI (paper: App. "Series-based exponentiation compared to a Lanczos
+algorithm").
+
+Both sides run the order-p propagator on the same H_eff: key sets must
+agree bit for bit, amplitudes within 1e-10 relative (FP64) or 1e-5 (FP32),
+observables within tol * (|o| + scale), the Krylov dimension exactly and
+the Gershgorin interval of T within the same relative tolerance.  Where
+the Krylov space is invariant the step is the exact exponential, so it
+must also match the series propagator; batched realizations must match
+single runs."""
+import numpy as np
+import pytest
+
+import paper_2603_07341_amd as P
+from oracle import oracle as O
+from tests.gpu_helpers import (assert_same_set, check_obs, oracle_state,
+                               rel_err, sort_rows)
+import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+
+def pair(name, order, **over):
+    cfg = dict(WL.CONFIGS[name])
+    cfg.update(over)
+    params = WL.model_params(cfg)
+    run = dict(WL.run_params(cfg), krylov_order=order)
+    init = WL.initial_state(cfg)
+    return cfg, P.Sim(P.Model(params), run, *init), O.Sim(O.Model(params), run, *init)
+
+
+def check_step(gs, os_, tol):
+    for which in (O.SET_M, O.SET_S):
+        assert_same_set(gs.get_set(which), os_.get_set(which), "set %d" % which)
+    gk, ga = sort_rows(*gs.state())
+    ok, oa = os_.state()
+    assert np.array_equal(gk, ok)
+    assert rel_err(ga, oa) <= tol, rel_err(ga, oa)
+    go, oo = gs.observations()[-1], os_.observations()[-1]
+    check_obs(go, oo, tol, width=oo["E_max"] - oo["E_min"])
+    assert go["K"] == oo["terms"]
+    for f in ("E_min", "E_max"):
+        assert go[f] == pytest.approx(oo[f], rel=tol, abs=1e-12), f
+
+
+@pytest.mark.parametrize("name,steps,order", [("ring16", 12, 10),
+                                              ("ring12", 10, 5),
+                                              ("sq6x6", 4, 8),
+                                              ("cube4", 3, 6)])
+def test_single_step_parity(name, steps, order):
+    keys, amps, t = oracle_state(name, steps)
+    cfg, gs, os_ = pair(name, order, precision=64)
+    gs.set_state(keys, amps, t)
+    os_.set_state(keys, amps, t)
+    gs.step(1)
+    os_.step(1)
+    check_step(gs, os_, 1e-10)
+    assert gs.observations()[-1]["K"] == order + 1
+
+
+@pytest.mark.parametrize("order", [1, 2, 10])
+def test_multi_step_runs_match_oracle(order):
+    cfg, gs, os_ = pair("ring12", order, extent=[6, 1, 1], cutoff=[4],
+                        theta=1e-6)
+    for _ in range(15):
+        gs.step(1)
+        os_.step(1)
+        check_step(gs, os_, 1e-10)
+
+
+@pytest.mark.parametrize("name,steps", [("ring16", 12), ("sq6x6", 4)])
+def test_single_step_parity_fp32(name, steps):
+    keys, amps, t = oracle_state(name, steps)
+    amps = amps.astype(np.complex64).astype(np.complex128)
+    cfg, gs, os_ = pair(name, 8, precision=32)
+    gs.set_state(keys, amps, t)
+    os_.set_state(keys, amps, t)
+    gs.step(1)
+    os_.step(1)
+    check_step(gs, os_, 1e-5)
+
+
+def test_invariant_space_equals_series_propagator():
+    # 3-site ring, cutoff 1: 24 states in all, so order 30 spans every
+    # H_eff of the run (the basis may or may not stop early) and the step is
+    # the exact exponential: GPU Krylov == GPU series == oracle series
+    over = dict(extent=[3, 1, 1], cutoff=[1], k=1, k_init=1, theta=1e-10)
+    cfg = dict(WL.CONFIGS["ring4"])
+    cfg.update(over)
+    params = WL.model_params(cfg)
+    init = WL.initial_state(cfg)
+    run = WL.run_params(cfg)
+    gk_ = P.Sim(P.Model(params), dict(run, krylov_order=30), *init)
+    gc = P.Sim(P.Model(params), run, *init)
+    oc = O.Sim(O.Model(params), run, *init)
+    for _ in range(8):
+        for s in (gk_, gc, oc):
+            s.step(1)
+        ak, aa = sort_rows(*gk_.state())
+        ck, ca = sort_rows(*gc.state())
+        ok, oa = oc.state()
+        assert np.array_equal(ak, ok) and np.array_equal(ck, ok)
+        assert np.abs(aa - oa).max() <= 1e-11
+        assert np.abs(ca - oa).max() <= 1e-11
+    assert 1 <= gk_.observations()[-1]["K"] <= 31
+
+
+def test_high_order_converges_to_series_propagator():
+    cfg = dict(WL.CONFIGS["ring12"])
+    cfg.update(theta=0.0, extent=[6, 1, 1], cutoff=[4], dt=0.05)
+    params = WL.model_params(cfg)
+    init = WL.initial_state(cfg)
+    run = WL.run_params(cfg)
+    a = P.Sim(P.Model(params), dict(run, krylov_order=24), *init)
+    b = P.Sim(P.Model(params), run, *init)
+    a.step(10)
+    b.step(10)
+    ak, aa = sort_rows(*a.state())
+    bk, ba = sort_rows(*b.state())
+    assert np.array_equal(ak, bk)
+    assert np.abs(aa - ba).max() <= 1e-11
+
+
+def test_batched_realizations_match_single_runs():
+    cfg = dict(WL.CONFIGS["sq6x6"])
+    cfg.update(precision=64)
+    R, steps, order = 4, 5, 6
+    init = WL.initial_state(cfg)
+    run = dict(WL.run_params(cfg), krylov_order=order)
+    bs = P.Sim(P.Model(WL.batch_params(cfg, R)), run, *init)
+    bs.step(steps)
+    brec = bs.series()
+    bk, ba, breal = bs.state(with_real=True)
+    for r in range(R):
+        s = P.Sim(P.Model(WL.model_params(cfg, r)), run, *init)
+        s.step(steps)
+        sk, sa = sort_rows(*s.state())
+        sel = breal == r
+        rk, ra = sort_rows(bk[sel], ba[sel])
+        assert np.array_equal(rk, sk), r
+        assert rel_err(ra, sa) <= 1e-12, r
+        srec = s.series()
+        assert np.array_equal(brec[:, r, 0], srec[:, 0])
+        assert np.array_equal(brec[:, r, 7:10], srec[:, 7:10])  # n_S, n_M, K
+        assert np.allclose(brec[:, r, 1:7], srec[:, 1:7], rtol=1e-12, atol=1e-13)
+        assert np.allclose(brec[:, r, 10:], srec[:, 10:], rtol=1e-12, atol=1e-13)
+
+
+def test_graph_replay_matches_eager():
+    outs = []
+    for graph in (0, 1):
+        cfg, gs, _ = pair("ring16", 6)
+        t = gs.tuning()
+        gs.set_tuning(graph=graph, table_shift=t["table_shift"],
+                      term_rows=t["term_rows"])
+        gs.step(12)
+        outs.append((sort_rows(*gs.state()), gs.series()))
+    (k0, a0), r0 = outs[0]
+    (k1, a1), r1 = outs[1]
+    assert np.array_equal(k0, k1)
+    assert np.abs(a0 - a1).max() <= 1e-13
+    assert np.allclose(r0, r1, rtol=1e-12, atol=1e-14)
+
+
+def test_profile_counts_the_krylov_launches():
+    cfg, gs, _ = pair("ring16", 7)
+    gs.step(2)
+    gs.profile(True)
+    gs.profile_reset()
+    gs.step(3)
+    prof = gs.profile_get()
+    assert prof["launches"]["krylov"] == 3 * 7  # every SpMV but the last
+    assert prof["krylov_bytes"] > 0 and prof["ms"]["krylov"] > 0
+    assert prof["launches"]["term"] == 0
+
+
+def test_empty_set_and_zero_state():
+    keys, amps, t = oracle_state("ring16", 5)
+    cfg, gs, os_ = pair("ring16", 4, theta=10.0)
+    gs.set_state(keys, amps, t)
+    os_.set_state(keys, amps, t)
+    gs.step(1)
+    os_.step(1)
+    assert gs.size() == 0 and os_.size() == 0
+    assert gs.observations()[-1]["K"] == 0 == os_.observations()[-1]["terms"]
+    cfg, gs, os_ = pair("ring16", 4, theta=0.0)
+    zero = np.zeros(len(amps), dtype=np.complex128)
+    gs.set_state(keys, zero, t)
+    os_.set_state(keys, zero, t)
+    gs.step(1)
+    os_.step(1)
+    gk, ga = sort_rows(*gs.state())
+    ok, oa = os_.state()
+    assert np.array_equal(gk, ok)
+    assert np.all(ga == 0) and np.all(oa == 0)
+    assert gs.observations()[-1]["K"] == 0
+
+
+def test_adjoint_rejects_the_krylov_propagator():
+    cfg, gs, _ = pair("ring12", 4)
+    with pytest.raises(P.PacesError) as ei:
+        gs.adjoint_forward(3)
+    assert ei.value.status == 8

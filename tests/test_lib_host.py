@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(lib, name), name
     assert sorted(P.EXPORTS) == declared
-    assert lib.paces_abi_version() == 8
+    assert lib.paces_abi_version() == 9
 
 
 @pytest.mark.parametrize("name", ["ring4", "ring16", "sq6x6", "cube4", "ring12"])
@@ -105,3 +105,13 @@ def test_library_abi_matches_header():
     src = open(os.path.join(ROOT, "include", "paces.h")).read()
     want = int(re.search(r"#define PACES_ABI_VERSION (\d+)", src).group(1))
     assert P.lib().paces_abi_version() == want
+
+
+@pytest.mark.parametrize("order", [-1, 64])
+def test_krylov_order_out_of_range_is_rejected_before_device_work(order):
+    cfg = dict(WL.CONFIGS["ring4"])
+    m = P.Model(WL.model_params(cfg))
+    run = dict(WL.run_params(cfg), krylov_order=order)
+    with pytest.raises(P.PacesError) as ei:
+        P.Sim(m, run, *WL.initial_state(cfg))
+    assert ei.value.status == 1
