@@ -3,10 +3,10 @@ exponentiation compared to a Lanczos algorithm".
 
 Checked against what the paper and the mathematics fix, not against the
 oracle itself:
-  * the paper's worked example: the Lanczos vectors V_4 of the
-    tight-binding chain (golden fixture), and its counting statements
+  * the paper's worked examples: the Lanczos vectors V_4 of the
+    tight-binding chain (golden fixture), its counting statements
     (|V_n| has n^2 + 2n non-zero entries; H_eff^(n-1) has 3 + 2(n-1)
-    states);
+    states), and the overlaps of higher Krylov vectors with H_eff^(2);
   * the Krylov projection computed through an independent basis (QR of
     the power vectors) and a library exponential;
   * exactness when the Krylov space is invariant (breakdown), against a
@@ -114,6 +114,52 @@ def test_lanczos_vector_counts_follow_the_papers_closed_forms(n):
     assert np.count_nonzero(np.abs(B) > 1e-13) == n * n + 2 * n
     for k in range(n):
         assert np.count_nonzero(np.abs(B[k]) > 1e-13) == 2 * k + 3
+
+
+def test_krylov_example_overlaps_with_heff2():
+    # Sec. "Relation to Krylov subspaces": psi = (|n-1> + |n+1>)/sqrt(2) on
+    # an (effectively infinite) tight-binding chain.  K^3 is spanned by the
+    # three printed vectors; v_4 is proportional to |n-4> + 2/3 (|n-2> - |n>
+    # + |n+2>) + |n+4>; the unit vector (|n-2> - |n> + |n+2>)/sqrt(3) of
+    # H_eff^(2) = span{|n-3> .. |n+3>} overlaps v_4 by sqrt(2/5); v_5, v_7
+    # are orthogonal to H_eff^(2); the largest overlaps of its unit sphere
+    # with v_6 and v_8 are sqrt(6/35) and sqrt(2/21)
+    L, c, k = 41, 20, 8
+    cfg = chain_cfg(L)
+    cfg.update(k=k, k_init=k)
+    m = O.Model(WL.model_params(cfg))
+    coef = [1 / np.sqrt(2), 0.0, 1 / np.sqrt(2), 0.0]
+    s = O.Sim(m, WL.run_params(cfg), [c - 1, c + 1], [0] * (2 * L), coef)
+    s.step(1)
+    keys, _ = s.state()
+    sites, _ = m.unpack(keys)
+    rp, cols, vals = s.csr()
+    _, B, _, _, _ = O.lanczos(rp, cols, vals, 0.01, 8, s.phi())
+    assert B.shape[0] == 9
+    V = np.zeros((9, L), dtype=np.complex128)  # V[j] = v_{j+1}
+    for row, site in enumerate(sites):
+        V[:, site] = B[:, row]
+    printed = np.zeros((3, L))
+    printed[0, [c - 1, c + 1]] = 1
+    printed[1, [c - 2, c, c + 2]] = [1, 2, 1]
+    printed[2, [c - 3, c - 1, c + 1, c + 3]] = [1, 3, 3, 1]
+    Q, _ = np.linalg.qr(printed.T)
+    P3 = Q @ Q.T
+    for j in range(3):
+        np.testing.assert_allclose(P3 @ V[j], V[j], atol=1e-14)
+    v4 = np.zeros(L)
+    v4[[c - 4, c + 4]] = 1
+    v4[[c - 2, c, c + 2]] = [2 / 3, -2 / 3, 2 / 3]
+    v4 /= np.linalg.norm(v4)
+    assert abs(abs(np.vdot(v4, V[3])) - 1) < 1e-14
+    u = np.zeros(L)
+    u[[c - 2, c, c + 2]] = np.array([1, -1, 1]) / np.sqrt(3)
+    assert abs(np.vdot(u, V[3])) == pytest.approx(np.sqrt(2 / 5), rel=1e-13)
+    win = slice(c - 3, c + 4)
+    assert np.linalg.norm(V[4][win]) < 1e-14
+    assert np.linalg.norm(V[6][win]) < 1e-14
+    assert np.linalg.norm(V[5][win]) == pytest.approx(np.sqrt(6 / 35), rel=1e-13)
+    assert np.linalg.norm(V[7][win]) == pytest.approx(np.sqrt(2 / 21), rel=1e-13)
 
 
 def random_sym(n, seed, density=1.0):
