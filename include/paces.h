@@ -256,8 +256,12 @@ paces_status paces_get_set(paces_sim* s, int32_t which, int32_t round,
  * of paces_get_set(PACES_SET_S); amps[2*nS].  Synchronises. */
 paces_status paces_get_phi(paces_sim* s, double* amps, void* hip_stream);
 
-/* Per-stage timing with HIP events recorded on the step's stream around
- * every stage launch group.  Enabling costs a few microseconds per stage. */
+/* Timing with HIP events on the step's stream.  Level 1: events around
+ * every stage launch group (each marker costs the stream a few
+ * microseconds) plus the timed kernels below; level 2: only the timed
+ * kernels (each Clenshaw launch, each Lanczos SpMV but the last), whose
+ * events their own dispatch records, which adds no idle time.  Level 0:
+ * off.  Profiling turns graph replay off. */
 typedef enum {
   PACES_STAGE_SELECT = 0,
   PACES_STAGE_EXPAND = 1,   /* expansion rounds incl. the lookup pass     */
@@ -278,7 +282,7 @@ typedef struct {
                                        Lanczos SpMV launches             */
   double rows_steps;                /* sum over steps of |S|              */
 } paces_profile;
-paces_status paces_profile_enable(paces_sim* s, int32_t on);
+paces_status paces_profile_enable(paces_sim* s, int32_t level);
 /* Resolves pending events (synchronises) and returns the totals. */
 paces_status paces_profile_get(paces_sim* s, paces_profile* out,
                                void* hip_stream);

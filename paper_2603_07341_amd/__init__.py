@@ -366,8 +366,12 @@ class Sim:
         _check(lib().paces_get_phi(self.h, _p(amps, C.c_double), _stream(stream)))
         return amps.view(np.complex128)
 
-    def profile(self, on=True):
-        _check(lib().paces_profile_enable(self.h, C.c_int32(1 if on else 0)))
+    def profile(self, on=True, kernels_only=False):
+        """Event timing: every stage and the timed kernels, or (kernels_only)
+        just the Clenshaw / Lanczos SpMV launches, timed by their own
+        dispatches."""
+        level = 0 if not on else (2 if kernels_only else 1)
+        _check(lib().paces_profile_enable(self.h, C.c_int32(level)))
 
     def profile_reset(self):
         _check(lib().paces_profile_reset(self.h))

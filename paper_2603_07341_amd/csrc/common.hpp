@@ -2,6 +2,7 @@
 // kernels: launch-shape helpers, grid-stride indices, deterministic wave and
 // block reductions, Bessel functions of the first kind.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -60,6 +61,19 @@ inline int grid_for(int64_t bound, int64_t cap = kMaxGrid) {
   if (g > cap) g = cap;
   return int(g);
 }
+// Launch of a kBlock-thread kernel on s.  With events the dispatch itself
+// records its start and stop (no marker packets between launches), so
+// timing a kernel costs no idle time on the stream.
+template <typename... K, typename... A>
+inline void launch_ev(void (*kern)(K...), int grid, hipStream_t s,
+                      hipEvent_t ev_a, hipEvent_t ev_b, A... args) {
+  if (ev_a)
+    hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, ev_a, ev_b,
+                          0u, K(args)...);
+  else
+    kern<<<grid, kBlock, 0, s>>>(K(args)...);
+}
+
 // Grid for a kernel striding over tiles of kTile items.
 inline int tiles_for(int64_t bound) {
   int64_t g = cdiv(bound, kTile);

@@ -1062,14 +1062,26 @@ __global__ void __launch_bounds__(kBlock)
 
 // Commit the step on the device: time, cumulative discarded weight per
 // realization, record count and the row count of the current set.
+// The last kernel of a step also mirrors the counts and the error latch into
+// mapped pinned host memory, so the host reads them after one stream
+// synchronisation without copy dispatches.
 __global__ void k_end_step(StepCtl* ctl, int Rn, const double* ring,
-                           int rec_doubles, double* mass_tot, const int* err) {
-  if (*err) return;
-  const double* rec = ring + int64_t(ctl->nrec) * Rn * rec_doubles;
-  for (int r = 0; r < Rn; ++r) mass_tot[r] = rec[int64_t(r) * rec_doubles + 6];
-  ctl->t = rec[0];
-  ctl->n_old = ctl->n_new;
-  ctl->nrec += 1;
+                           int rec_doubles, double* mass_tot, const int* err,
+                           uint32_t* h_ctl, int* h_err) {
+  const int e = *err;
+  if (threadIdx.x == 0 && !e) {
+    const double* rec = ring + int64_t(ctl->nrec) * Rn * rec_doubles;
+    for (int r = 0; r < Rn; ++r) mass_tot[r] = rec[int64_t(r) * rec_doubles + 6];
+    ctl->t = rec[0];
+    ctl->n_old = ctl->n_new;
+    ctl->nrec += 1;
+  }
+  __syncthreads();
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(ctl);
+  for (int i = threadIdx.x; i < int(sizeof(StepCtl) / 4); i += blockDim.x)
+    h_ctl[i] = src[i];
+  if (threadIdx.x == 0) *h_err = e;
+  __threadfence_system();
 }
 
 __global__ void k_clear_u32(uint32_t* p, int n) {
@@ -1231,7 +1243,9 @@ void bounds_and_coef(const DevModel& m, const Side& n, const int32_t* col,
                      int64_t cap, int64_t est, StepCtl* ctl, double dt,
                      double tol, int k_max, int launched, double* part,
                      ChebCoef* cc, int* err, hipStream_t s) {
-  const int g = m.R > 1 ? std::min(grid_for(est), kPartBlocks) : grid_for(est);
+  // a bounded grid: each block reduces many rows, and k_coef folds few
+  // partials
+  const int g = std::min(grid_for(est), kPartBlocks);
   k_bounds<<<g, kBlock, 0, s>>>(m, n.pay, n.tot, col, cap, ctl, part, err);
   k_coef<<<m.R, kBlock, 0, s>>>(part, g, m.R, dt, tol, k_max, launched, cc,
                                 ctl, err);
@@ -1247,28 +1261,28 @@ int cheb_term(const DevModel& m, int prec, int kk, bool energy, bool mid,
               int64_t est, const StepCtl* ctl, const int32_t* col, int64_t cap,
               const Side& n, const ChebCoef* cc, const void* phi, void* b0,
               void* b1, double* e_part, double* e_row, int* err,
-              hipStream_t s) {
+              hipEvent_t ev_a, hipEvent_t ev_b, hipStream_t s) {
   const int e = energy ? 1 : 0;
   const int g = grid_for(est);
   if (m.R > 1) {
     if (prec == 64) {
       PACES_DISPATCH_SHAPE(m.ndim, m.V,
-          k_cheb_batch<double, A, B><<<g, kBlock, 0, s>>>(
-              m, kk, e, ctl, err, col, cap, n.pay, n.tot, cc,
-              (const double2*)phi, (double2*)b0, (double2*)b1, e_row));
+          launch_ev(k_cheb_batch<double, A, B>, g, s, ev_a, ev_b,
+                    m, kk, e, ctl, err, col, cap, n.pay, n.tot, cc,
+                    (const double2*)phi, (double2*)b0, (double2*)b1, e_row));
     } else {
       PACES_DISPATCH_SHAPE(m.ndim, m.V,
-          k_cheb_batch<float, A, B><<<g, kBlock, 0, s>>>(
-              m, kk, e, ctl, err, col, cap, n.pay, n.tot, cc,
-              (const float2*)phi, (float2*)b0, (float2*)b1, e_row));
+          launch_ev(k_cheb_batch<float, A, B>, g, s, ev_a, ev_b,
+                    m, kk, e, ctl, err, col, cap, n.pay, n.tot, cc,
+                    (const float2*)phi, (float2*)b0, (float2*)b1, e_row));
     }
     return g;
   }
 #define PACES_TERM(R, AMP, MIDV)                                              \
   PACES_DISPATCH_SHAPE(m.ndim, m.V,                                           \
-      k_cheb_term<R, A, B, MIDV><<<g, kBlock, 0, s>>>(                        \
-          m, kk, e, ctl, err, col, cap, n.pay, n.tot, cc, (const AMP*)phi,    \
-          (AMP*)b0, (AMP*)b1, e_part))
+      launch_ev(k_cheb_term<R, A, B, MIDV>, g, s, ev_a, ev_b,                 \
+                m, kk, e, ctl, err, col, cap, n.pay, n.tot, cc,               \
+                (const AMP*)phi, (AMP*)b0, (AMP*)b1, e_part))
   if (prec == 64) {
     if (mid) { PACES_TERM(double, double2, true); } else { PACES_TERM(double, double2, false); }
   } else {
@@ -1314,8 +1328,12 @@ void autocorr(const DevModel& m, int Wi, int prec, const uint64_t* keys0,
 }
 
 void end_step(StepCtl* ctl, int R, const double* ring, int rec_doubles,
-              double* mass_tot, int* err, hipStream_t s) {
-  k_end_step<<<1, 1, 0, s>>>(ctl, R, ring, rec_doubles, mass_tot, err);
+              double* mass_tot, int* err, StepCtl* h_ctl_dev, int* h_err_dev,
+              hipStream_t s) {
+  static_assert(sizeof(StepCtl) % 4 == 0, "StepCtl is copied as 32-bit words");
+  k_end_step<<<1, 64, 0, s>>>(ctl, R, ring, rec_doubles, mass_tot, err,
+                              reinterpret_cast<uint32_t*>(h_ctl_dev),
+                              h_err_dev);
 }
 
 void obs_final(int N, int R, int want_energy, double dt, int n_mass, int n_e,

@@ -120,12 +120,13 @@ int fold_sum(const double* in, int n, double* out, int* err, hipStream_t s);
 // Clenshaw launch for index kk (see kernels.hip); buffers b[0], b[1].
 // Returns the number of energy partials (written by the first launch).
 // mid: the launch is expected to be a middle term (selects a kernel name).
-// Batched sims (R > 1) leave the energy per row in e_row.
+// Batched sims (R > 1) leave the energy per row in e_row.  ev_a / ev_b
+// (may be null): events the dispatch records at its start and stop.
 int cheb_term(const DevModel& m, int prec, int kk, bool energy, bool mid,
               int64_t est, const StepCtl* ctl, const int32_t* col, int64_t cap,
               const Side& n, const ChebCoef* cc, const void* phi, void* b0,
               void* b1, double* e_part, double* e_row, int* err,
-              hipStream_t s);
+              hipEvent_t ev_a, hipEvent_t ev_b, hipStream_t s);
 // |psi|^2 and exciton populations as per-block partials (returns their
 // count, at most kPartBlocks), plus the next step's select counts.
 int pop_norm(int prec, int N, int R, double th2, int64_t est,
@@ -140,9 +141,12 @@ void autocorr(const DevModel& m, int Wi, int prec, const uint64_t* keys0,
               uint64_t mask, const uint64_t* keys, const void* psi,
               double* out2, int32_t* p0map, int* err, hipStream_t s);
 // Commit a successful step on the device: time, discarded weight per
-// realization, record count and the row count of the current set.
+// realization, record count and the row count of the current set; then
+// mirror *ctl and *err into mapped pinned host memory (device addresses
+// h_ctl_dev, h_err_dev), also when an error is latched.
 void end_step(StepCtl* ctl, int R, const double* ring, int rec_doubles,
-              double* mass_tot, int* err, hipStream_t s);
+              double* mass_tot, int* err, StepCtl* h_ctl_dev, int* h_err_dev,
+              hipStream_t s);
 // Reduce partials into observation record ctl->nrec (skipped when an error
 // is latched, so a repeated step records once).
 void obs_final(int N, int R, int want_energy, double dt, int n_mass, int n_e,

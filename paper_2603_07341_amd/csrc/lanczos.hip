@@ -363,18 +363,19 @@ void lz_begin(LanczosState* st, int R, const int* err, hipStream_t s) {
 int lz_spmv(const DevModel& m, int prec, int j, int64_t est,
             const StepCtl* ctl, const int32_t* col, const Side& n,
             const LanczosState* st, const void* in, void* out, double* part,
-            const int* err, hipStream_t s) {
+            const int* err, hipEvent_t ev_a, hipEvent_t ev_b,
+            hipStream_t s) {
   const int g = grid_for(est, m.R == 1 ? kLzGrid1 : kPartBlocks);
   if (prec == 64) {
     PACES_DISPATCH_SHAPE(m.ndim, m.V,
-        k_lz_spmv<double, A, B><<<g, kBlock, 0, s>>>(
-            m, j, ctl, err, col, n.pay, n.tot, st, (const double2*)in,
-            (double2*)out, part));
+        launch_ev(k_lz_spmv<double, A, B>, g, s, ev_a, ev_b,
+                  m, j, ctl, err, col, n.pay, n.tot, st, (const double2*)in,
+                  (double2*)out, part));
   } else {
     PACES_DISPATCH_SHAPE(m.ndim, m.V,
-        k_lz_spmv<float, A, B><<<g, kBlock, 0, s>>>(
-            m, j, ctl, err, col, n.pay, n.tot, st, (const float2*)in,
-            (float2*)out, part));
+        launch_ev(k_lz_spmv<float, A, B>, g, s, ev_a, ev_b,
+                  m, j, ctl, err, col, n.pay, n.tot, st, (const float2*)in,
+                  (float2*)out, part));
   }
   return g;
 }

@@ -47,11 +47,13 @@ struct KrylovVecs {
 void lz_begin(LanczosState* st, int R, const int* err, hipStream_t s);
 // SpMV j over the rows of realizations still building their basis;
 // out = H w_j (null for the last iteration).  part: per-block partials
-// [grid][R][3]; returns the grid used (<= kPartBlocks).
+// [grid][R][3]; returns the grid used.  ev_a / ev_b (may be null): events
+// the dispatch records at its start and stop.
 int lz_spmv(const DevModel& m, int prec, int j, int64_t est,
             const StepCtl* ctl, const int32_t* col, const Side& n,
             const LanczosState* st, const void* in, void* out, double* part,
-            const int* err, hipStream_t s);
+            const int* err, hipEvent_t ev_a, hipEvent_t ev_b,
+            hipStream_t s);
 // Fold the partials of SpMV j into alpha_j, beta_j, |H v_j|^2 per
 // realization (energy[r] = <phi|H|phi> from j = 0).  brk2 = brk^2.
 void lz_fold(int j, const double* part, int nparts, int R, double brk2,

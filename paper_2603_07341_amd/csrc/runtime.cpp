@@ -324,11 +324,13 @@ struct paces_sim {
   int K_last = 0;
   int k_last = 0;           // neighbour order of the last step
   int latched = 0;
-  StepCtl* h_ctl = nullptr;  // pinned
-  int* h_err = nullptr;      // pinned
+  StepCtl* h_ctl = nullptr;  // pinned, mapped
+  int* h_err = nullptr;      // pinned, mapped
+  StepCtl* d_hctl = nullptr;  // device addresses of h_ctl / h_err
+  int* d_herr = nullptr;
   std::vector<double> pop_host;
 
-  bool prof = false;
+  int prof = 0;  // 0 off, 1 stages and kernels, 2 timed kernels only
   std::vector<EventPair> pending, events;
   paces_profile acc{};
 
@@ -365,17 +367,32 @@ struct Stage {
   hipEvent_t a{}, b{};
   Stage(paces_sim* s_, int stage_, hipStream_t st_, int kk_ = -1)
       : s(s_), stage(stage_), kk(kk_), st(st_) {
-    if (s->prof) {
+    if (s->prof == 1) {
       (void)hipEventCreate(&a);
       (void)hipEventCreate(&b);
       (void)hipEventRecord(a, st);
     }
   }
   ~Stage() {
-    if (s->prof) {
+    if (s->prof == 1) {
       (void)hipEventRecord(b, st);
       s->pending.push_back({stage, kk, a, b, 0.0});
     }
+  }
+};
+
+// Start / stop events of one timed kernel, recorded by its own dispatch
+// (any profiling level); queued for classification after the step.
+struct KernelTiming {
+  hipEvent_t a{}, b{};
+  KernelTiming(paces_sim* s, int stage, int kk) {
+    if (!s->prof) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      if (a) (void)hipEventDestroy(a);
+      a = b = nullptr;
+      return;
+    }
+    s->pending.push_back({stage, kk, a, b, 0.0});
   }
 };
 
@@ -689,12 +706,12 @@ void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st,
       void* out = last ? nullptr : kv.w[j + 1];
       int np = 0;
       if (!last) {
-        Stage tg(s, PACES_STAGE_KRYLOV, st, j);
+        KernelTiming kt(s, PACES_STAGE_KRYLOV, j);
         np = lz_spmv(dm, s->prec, j, est, s->ctl, s->col, sn, s->lz, kv.w[j],
-                     out, s->lz_part, s->err, st);
+                     out, s->lz_part, s->err, kt.a, kt.b, st);
       } else {
         np = lz_spmv(dm, s->prec, j, est, s->ctl, s->col, sn, s->lz, kv.w[j],
-                     out, s->lz_part, s->err, st);
+                     out, s->lz_part, s->err, nullptr, nullptr, st);
       }
       lz_fold(j, s->lz_part, np, R, brk * brk, s->lz, s->lz_energy, s->err,
               st);
@@ -717,13 +734,14 @@ void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st,
     Stage sg(s, PACES_STAGE_PROPAGATE, st);
     int np = 0;
     for (int kk = s->launched - 1; kk >= 0; --kk) {
-      Stage tg(s, PACES_STAGE_TERM, st, kk);
+      KernelTiming kt(s, PACES_STAGE_TERM, kk);
       const bool mid = s->K_last >= 4 && kk >= 1 && kk <= s->K_last - 3;
       np = cheb_term(dm, s->prec, kk, want_e, mid,
                      std::max<int64_t>(1, est / s->tune.term_rows), s->ctl,
                      s->col, s->cap,
                      sn, s->cc, s->vec[s->iphi], s->vec[s->ib0],
-                     s->vec[s->ib1], s->e_part, s->e_row, s->err, st);
+                     s->vec[s->ib1], s->e_part, s->e_row, s->err, kt.a, kt.b,
+                     st);
     }
     if (want_e && R == 1) n_e = fold_sum(s->e_part, np, s->e_fold, s->err, st);
   }
@@ -746,7 +764,8 @@ void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st,
     if (want_e && krylov)
       lz_record_energy(R, s->lz_energy, s->ctl, s->ring, s->rec_doubles,
                        s->ring_cap, s->err, st);
-    end_step(s->ctl, R, s->ring, s->rec_doubles, s->mass_tot, s->err, st);
+    end_step(s->ctl, R, s->ring, s->rec_doubles, s->mass_tot, s->err,
+             s->d_hctl, s->d_herr, st);
   }
 }
 
@@ -969,8 +988,9 @@ paces_status do_step(paces_sim* s, hipStream_t st,
                      const FrozenStep* fz = nullptr) {
   const paces_model* m = s->m;
   // keep room for the new set: growth of the set per step stays well below
-  // the factor used here in the workloads; an overflow is caught anyway
-  if (s->nS > s->cap / 2) ST_TRY(grow(s, 3 * s->nS, st));
+  // the factor used here in the workloads; an overflow is caught anyway.
+  // Growth to 4 |S| makes the next one due only when the set has doubled.
+  if (s->nS > s->cap / 2) ST_TRY(grow(s, 4 * s->nS, st));
   ST_TRY(ensure_ring(s, st));
   const int64_t est = std::min<int64_t>(
       s->cap, bucket(std::max<int64_t>(s->nS + s->nS / 2, s->nS + 65536)));
@@ -993,10 +1013,8 @@ paces_status do_step(paces_sim* s, hipStream_t st,
       ST_TRY(launch_step_graph(s, est, counted, st));
     else
       enqueue_step(s, est, counted, st, fz);
-    HIP_TRY(hipMemcpyAsync(s->h_ctl, s->ctl, sizeof(StepCtl),
-                           hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(s->h_err, s->err, sizeof(int), hipMemcpyDeviceToHost,
-                           st));
+    // the step's last kernel mirrored the counts and the latch into h_ctl
+    // and h_err
     HIP_TRY(hipStreamSynchronize(st));
     const int e = *s->h_err;
     if (e == 0) {
@@ -1640,10 +1658,19 @@ paces_status paces_init_state(const paces_model* m, const paces_run_params* p,
     paces_free_sim(s);
     return st_;
   };
-  if (hipHostMalloc(reinterpret_cast<void**>(&s->h_ctl), sizeof(StepCtl)) !=
-          hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&s->h_err), 64) != hipSuccess)
+  // coherent mapped host memory: the step's last kernel writes the counts
+  // there directly
+  const unsigned hflags = hipHostMallocMapped | hipHostMallocCoherent;
+  if (hipHostMalloc(reinterpret_cast<void**>(&s->h_ctl), sizeof(StepCtl),
+                    hflags) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&s->h_err), 64, hflags) !=
+          hipSuccess)
     return cleanup(fail(PACES_E_OOM, "pinned host allocation failed"));
+  if (hipHostGetDevicePointer(reinterpret_cast<void**>(&s->d_hctl), s->h_ctl,
+                              0) != hipSuccess ||
+      hipHostGetDevicePointer(reinterpret_cast<void**>(&s->d_herr), s->h_err,
+                              0) != hipSuccess)
+    return cleanup(fail(PACES_E_HIP, "no device address for pinned memory"));
   // per-block partials of the row kernels (layouts in kernels.hpp)
   const int64_t blk = R == 1 ? kMaxPartials : int64_t(kPartBlocks) * R;
   const int64_t sz_mass = blk, sz_e = R == 1 ? kMaxPartials : 0,
@@ -1915,7 +1942,8 @@ paces_status paces_get_phi(paces_sim* s, double* amps, void* hip_stream) {
 
 paces_status paces_profile_enable(paces_sim* s, int32_t on) {
   if (!s) return fail(PACES_E_ARG, "bad arguments");
-  s->prof = on != 0;
+  if (on < 0 || on > 2) return fail(PACES_E_ARG, "profiling level 0, 1 or 2");
+  s->prof = on;
   return PACES_OK;
 }
 
@@ -2251,7 +2279,8 @@ paces_status paces_adjoint_backward(paces_sim* s, const double* gbar,
       adj_conj_coef(z.cc, ccj, st);
       for (int kk = a.K - 1; kk >= 0; --kk)
         cheb_term(dm, 64, kk, false, false, n1, s->ctl, z.col, n1, sd, ccj,
-                  lamA, b0, b1, nullptr, nullptr, s->err, st);
+                  lamA, b0, b1, nullptr, nullptr, s->err, nullptr, nullptr,
+                  st);
       // lambda_i = T_i^T mu + gbar_i psi0
       adj_back(ns, z.tmap, b0, lamB, s->err, st);
       const int32_t* p0 = i == start ? R.ck_p0[q] : slot[i - 1 - start].p0;
@@ -2308,8 +2337,8 @@ paces_status paces_autotune(paces_sim* s, int32_t steps, paces_tuning* chosen,
   if (!s || steps < 1 || steps > 64) return fail(PACES_E_ARG, "bad arguments");
   if (s->latched) return fail(PACES_E_STATE, "sim is in an error state");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  const bool prof = s->prof;
-  s->prof = false;
+  const int prof = s->prof;
+  s->prof = 0;
   Snapshot z;
   paces_status r = take_snapshot(s, z, st);
   const paces_tuning start = s->tune;

@@ -77,3 +77,29 @@ def test_step_log_writes_every_record(tmp_path, monkeypatch):
     for line in rows:
         step, r = int(line[0]), int(line[1])
         assert np.array_equal(line[2:], rec[step, r])
+
+
+@pytest.mark.parametrize("kernels_only", [False, True])
+def test_profile_levels_time_the_clenshaw_launches(kernels_only):
+    # level 1 times every stage and each Clenshaw launch; level 2 only the
+    # Clenshaw launches (events recorded by their own dispatches).  Middle
+    # terms carry their algorithmic bytes; results do not change.
+    cfg = dict(WL.CONFIGS["ring16"])
+    m = P.Model(WL.model_params(cfg))
+    a = P.Sim(m, WL.run_params(cfg), *WL.initial_state(cfg))
+    b = P.Sim(m, WL.run_params(cfg), *WL.initial_state(cfg))
+    a.step(20)
+    b.step(20)
+    a.profile(True, kernels_only=kernels_only)
+    a.profile_reset()
+    a.step(3)
+    b.step(3)
+    prof = a.profile_get()
+    K = a.observations()[-1]["K"]
+    assert prof["launches"]["term"] >= 3 * max(K - 3, 0) > 0
+    assert prof["term_bytes"] > 0 and prof["ms"]["term"] > 0
+    staged = prof["launches"]["expand"] > 0
+    assert staged == (not kernels_only)
+    ka, aa = a.state()
+    kb, bb = b.state()
+    assert np.array_equal(sort_rows(ka, aa)[1], sort_rows(kb, bb)[1])
