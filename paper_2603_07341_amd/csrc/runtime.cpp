@@ -76,6 +76,35 @@ paces_status dalloc(T** p, int64_t count) {
   *p = static_cast<T*>(q);
   return PACES_OK;
 }
+// Aligned sub-arrays of one device block: list the pieces, then carve.
+struct Pieces {
+  std::vector<std::pair<void**, size_t>> list;
+  template <typename T>
+  void add(T** p, int64_t count) {
+    list.push_back({reinterpret_cast<void**>(p),
+                    size_t(std::max<int64_t>(count, 1)) * sizeof(T)});
+  }
+  void add_bytes(void** p, size_t bytes) {
+    list.push_back({p, std::max<size_t>(bytes, 1)});
+  }
+  static size_t round(size_t b) { return (b + 255) & ~size_t(255); }
+  // One allocation for every piece; pointers are written only on success.
+  paces_status carve(void** block) {
+    size_t total = 0;
+    for (auto& q : list) total += round(q.second);
+    void* b = nullptr;
+    const paces_status e = dev_alloc(&b, total);
+    if (e) return e;
+    char* c = static_cast<char*>(b);
+    for (auto& q : list) {
+      *q.first = c;
+      c += round(q.second);
+    }
+    *block = b;
+    return PACES_OK;
+  }
+};
+
 template <typename T>
 void dfree(T*& p) {
   if (p) dev_free(p);
@@ -289,6 +318,12 @@ struct paces_sim {
   int32_t* p0_last = nullptr;  // [R][n0] rows of the initial states in S
   AdjRecord* adj = nullptr;
 
+  // device blocks that hold several arrays each (one allocation and one
+  // free per growth instead of one per array)
+  void* rows_block = nullptr;  // row arrays except the hash table
+  void* cand_block = nullptr;  // candidate buffers of the expansion rounds
+  void* cap_block = nullptr;   // per-row buffers of the state cap
+
   // Krylov propagator (krylov_order > 0)
   LanczosState* lz = nullptr;   // [R]
   double* lz_part = nullptr;    // per-block partials of the Lanczos SpMV
@@ -405,32 +440,37 @@ void drop_pending(paces_sim* s) {
 }
 
 void free_rows(paces_sim* s) {
-  for (int q = 0; q < 2; ++q) {
-    dfree(s->side[q].keys);
-    dfree(s->side[q].pay);
-    dfree(s->side[q].tot);
-  }
-  for (auto& v : s->vec) {
-    if (v) dev_free(v);
-    v = nullptr;
-  }
-  dfree(s->col);
-  dfree(s->table);
-  dfree(s->midx);
-  dfree(s->scan_tmp);
-  dfree(s->e_row);
-  for (auto& v : s->kry) dev_free(v);
+  if (s->rows_block) dev_free(s->rows_block);
+  s->rows_block = nullptr;
+  for (int q = 0; q < 2; ++q) s->side[q] = Side{};
+  for (auto& v : s->vec) v = nullptr;
+  s->col = nullptr;
+  s->midx = nullptr;
+  s->scan_tmp = nullptr;
+  s->e_row = nullptr;
   s->kry.clear();
+  dfree(s->table);
 }
 
 void free_cand(paces_sim* s) {
-  dfree(s->rb.c_slot);
-  dfree(s->rb.c_ref);
-  dfree(s->rb.crow);
-  dfree(s->rb.tile_cnt);
-  dfree(s->rb.tile_base);
-  dfree(s->rb.scan_tmp);
-  s->rb.cand_cap = 0;
+  if (s->cand_block) dev_free(s->cand_block);
+  s->cand_block = nullptr;
+  s->rb = RoundBufs{};
+}
+
+paces_status alloc_cand(paces_sim* s, int64_t want) {
+  free_cand(s);
+  const int64_t tiles = want / 256 + 2;
+  Pieces pc;
+  pc.add(&s->rb.c_slot, want);
+  pc.add(&s->rb.c_ref, want);
+  pc.add(&s->rb.crow, want);
+  pc.add(&s->rb.tile_cnt, tiles);
+  pc.add(&s->rb.tile_base, tiles);
+  pc.add(&s->rb.scan_tmp, scan_tmp_words(tiles));
+  ST_TRY(pc.carve(&s->cand_block));
+  s->rb.cand_cap = want;
+  return PACES_OK;
 }
 
 uint64_t table_size_for(int64_t cap, int shift) {
@@ -465,90 +505,65 @@ paces_status grow(paces_sim* s, int64_t new_cap, hipStream_t st) {
   new_cap = std::min<int64_t>((new_cap + 255) / 256 * 256, (int64_t(1) << 31) - 256);
   if (new_cap <= s->cap && s->cap > 0)
     return fail(PACES_E_CAPACITY, "row capacity limit (2^31 rows) reached");
-  Side old = s->side[s->cur];
-  void* old_psi = s->vec[s->ipsi];
-  for (int q = 0; q < 2; ++q) {
-    if (q == s->cur) continue;
-    dfree(s->side[q].keys);
-    dfree(s->side[q].pay);
-    dfree(s->side[q].tot);
-  }
-  for (int v = 0; v < 4; ++v)
-    if (v != s->ipsi && s->vec[v]) {
-      dev_free(s->vec[v]);
-      s->vec[v] = nullptr;
-    }
-  dfree(s->col);
-  dfree(s->table);
-  dfree(s->midx);
-  dfree(s->scan_tmp);
-  dfree(s->e_row);
-  for (auto& v : s->kry) dev_free(v);
-  s->kry.clear();
+  // every row array but the table in one block; the current set and psi
+  // are copied over before the old block goes
   Side nsd[2]{};
+  void* nvec[4] = {nullptr, nullptr, nullptr, nullptr};
+  int32_t* ncol = nullptr;
+  uint32_t *nmidx = nullptr, *nscan = nullptr;
+  double* nerow = nullptr;
+  // Krylov basis: w_0 = phi and w_1 = the second Clenshaw buffer; the
+  // remaining order - 1 vectors here
+  std::vector<void*> nkry(std::max(0, s->p.krylov_order - 1), nullptr);
+  Pieces pc;
   for (int q = 0; q < 2; ++q) {
-    ST_TRY(dalloc(&nsd[q].keys, new_cap * m->Wi));
-    ST_TRY(dalloc(&nsd[q].pay, new_cap));
-    ST_TRY(dalloc(&nsd[q].tot, new_cap));
+    pc.add(&nsd[q].keys, new_cap * m->Wi);
+    pc.add(&nsd[q].pay, new_cap);
+    pc.add(&nsd[q].tot, new_cap);
   }
-  for (int v = 0; v < 4; ++v) {
-    void* q = nullptr;
-    ST_TRY(dev_alloc(&q, size_t(new_cap) * s->A));
-    if (v == s->ipsi) {
-      if (s->nS > 0)
-        HIP_TRY(hipMemcpyAsync(q, old_psi, size_t(s->nS) * s->A,
-                               hipMemcpyDeviceToDevice, st));
-    }
-    s->vec[v] = q;
-  }
+  for (int v = 0; v < 4; ++v) pc.add_bytes(&nvec[v], size_t(new_cap) * s->A);
+  pc.add(&ncol, new_cap * m->D);
+  pc.add(&nmidx, new_cap);
+  pc.add(&nscan, scan_tmp_words(new_cap));
+  if (m->R > 1) pc.add(&nerow, new_cap);
+  for (auto& v : nkry) pc.add_bytes(&v, size_t(new_cap) * s->A);
+  void* block = nullptr;
+  ST_TRY(pc.carve(&block));
   if (s->nS > 0) {
+    const Side& o = s->side[s->cur];
     Side& c = nsd[s->cur];
-    HIP_TRY(hipMemcpyAsync(c.keys, old.keys, size_t(s->nS) * m->Wi * 8,
+    HIP_TRY(hipMemcpyAsync(c.keys, o.keys, size_t(s->nS) * m->Wi * 8,
                            hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipMemcpyAsync(c.pay, old.pay, size_t(s->nS) * 8,
+    HIP_TRY(hipMemcpyAsync(c.pay, o.pay, size_t(s->nS) * 8,
                            hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipMemcpyAsync(c.tot, old.tot, size_t(s->nS) * 8,
+    HIP_TRY(hipMemcpyAsync(c.tot, o.tot, size_t(s->nS) * 8,
                            hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(nvec[s->ipsi], s->vec[s->ipsi],
+                           size_t(s->nS) * s->A, hipMemcpyDeviceToDevice, st));
   }
-  ST_TRY(dalloc(&s->col, new_cap * m->D));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (s->rows_block) dev_free(s->rows_block);
+  s->rows_block = block;
+  s->side[0] = nsd[0];
+  s->side[1] = nsd[1];
+  for (int v = 0; v < 4; ++v) s->vec[v] = nvec[v];
+  s->col = ncol;
+  s->midx = nmidx;
+  s->scan_tmp = nscan;
+  s->e_row = nerow;
+  s->kry = nkry;
+  s->cap = new_cap;
+  s->counts_valid = false;
+  dfree(s->table);
   const uint64_t P = table_size_for(new_cap, s->tune.table_shift);
   ST_TRY(dalloc(&s->table, int64_t(P)));
   s->tmask_alloc = P - 1;
   s->tmask = P - 1;
-  s->counts_valid = false;
-  ST_TRY(dalloc(&s->midx, new_cap));
-  ST_TRY(dalloc(&s->scan_tmp, scan_tmp_words(new_cap)));
-  if (m->R > 1) ST_TRY(dalloc(&s->e_row, new_cap));
-  // Krylov basis: w_0 = phi and w_1 = the second Clenshaw buffer; the
-  // remaining order - 1 vectors here
-  for (int j = 2; j <= s->p.krylov_order; ++j) {
-    void* q = nullptr;
-    ST_TRY(dev_alloc(&q, size_t(new_cap) * s->A));
-    s->kry.push_back(q);
-  }
-  HIP_TRY(hipStreamSynchronize(st));
-  dfree(old.keys);
-  dfree(old.pay);
-  dfree(old.tot);
-  if (old_psi) dev_free(old_psi);
-  s->side[0] = nsd[0];
-  s->side[1] = nsd[1];
-  s->cap = new_cap;
   // candidate buffers: half the worst case to start with; grown on demand
   const int64_t want = std::min<int64_t>(std::max<int64_t>(new_cap * m->D / 2,
                                                            int64_t(1) << 16),
                                          (int64_t(1) << 31) - 1);
-  if (want > s->rb.cand_cap) {
-    free_cand(s);
-    const int64_t tiles = want / 256 + 2;
-    ST_TRY(dalloc(&s->rb.c_slot, want));
-    ST_TRY(dalloc(&s->rb.c_ref, want));
-    ST_TRY(dalloc(&s->rb.crow, want));
-    ST_TRY(dalloc(&s->rb.tile_cnt, tiles));
-    ST_TRY(dalloc(&s->rb.tile_base, tiles));
-    ST_TRY(dalloc(&s->rb.scan_tmp, scan_tmp_words(tiles)));
-    s->rb.cand_cap = want;
-  }
+  if (want > s->rb.cand_cap) ST_TRY(alloc_cand(s, want));
   return PACES_OK;
 }
 
@@ -560,16 +575,7 @@ paces_status grow_cand(paces_sim* s, hipStream_t st) {
   if (want <= s->rb.cand_cap)
     return fail(PACES_E_CAPACITY, "candidate capacity limit reached");
   HIP_TRY(hipStreamSynchronize(st));
-  free_cand(s);
-  const int64_t tiles = want / 256 + 2;
-  ST_TRY(dalloc(&s->rb.c_slot, want));
-  ST_TRY(dalloc(&s->rb.c_ref, want));
-  ST_TRY(dalloc(&s->rb.crow, want));
-  ST_TRY(dalloc(&s->rb.tile_cnt, tiles));
-  ST_TRY(dalloc(&s->rb.tile_base, tiles));
-  ST_TRY(dalloc(&s->rb.scan_tmp, scan_tmp_words(tiles)));
-  s->rb.cand_cap = want;
-  return PACES_OK;
+  return alloc_cand(s, want);
 }
 
 paces_status ensure_ring(paces_sim* s, hipStream_t st) {
@@ -814,16 +820,16 @@ paces_status launch_step_graph(paces_sim* s, int64_t est, bool counted,
 paces_status cap_buffers(paces_sim* s) {
   const int R = s->m->R;
   if (s->cap_buf < s->cap) {
-    dfree(s->keep);
-    dfree(s->midx_full);
-    dfree(s->cap_w);
-    dfree(s->cap_h);
-    dfree(s->cap_status);
-    ST_TRY(dalloc(&s->keep, s->cap));
-    ST_TRY(dalloc(&s->midx_full, s->cap));
-    ST_TRY(dalloc(&s->cap_w, s->cap));
-    ST_TRY(dalloc(&s->cap_h, s->cap));
-    ST_TRY(dalloc(&s->cap_status, s->cap));
+    if (s->cap_block) dev_free(s->cap_block);
+    s->cap_block = nullptr;
+    s->cap_buf = 0;
+    Pieces pc;
+    pc.add(&s->keep, s->cap);
+    pc.add(&s->midx_full, s->cap);
+    pc.add(&s->cap_w, s->cap);
+    pc.add(&s->cap_h, s->cap);
+    pc.add(&s->cap_status, s->cap);
+    ST_TRY(pc.carve(&s->cap_block));
     s->cap_buf = s->cap;
   }
   if (!s->cap_hist) {
@@ -1736,11 +1742,7 @@ paces_status paces_free_sim(paces_sim* s) {
   dfree(s->mass_tot);
   dfree(s->p0_last);
   dfree(s->ball);
-  dfree(s->keep);
-  dfree(s->midx_full);
-  dfree(s->cap_w);
-  dfree(s->cap_h);
-  dfree(s->cap_status);
+  if (s->cap_block) dev_free(s->cap_block);
   dfree(s->cap_hist);
   dfree(s->cap_mode);
   dfree(s->cap_dstar);
