@@ -10,8 +10,9 @@ exactly `--steps` steps are timed between stream synchronisations.
 
 value = sum over timed steps of |S| / wall time (basis-state updates/s).
 roofline: the middle Clenshaw term kernel (the dominant kernel), its
-algorithmic bytes per launch |S| (4A + 4D + 16) over its HIP-event
-duration on the step's stream.
+algorithmic bytes per launch |S| (4A + 4D + 8) over its HIP-event
+duration on the step's stream, from one middle launch per timed step whose
+dispatch records the events.
 cpu_baseline: the CPU oracle continued from the GPU state at the start of
 the timed window, for a bounded number of steps.
 forms: the extra forms against plain FP64 single-realization runs on the
@@ -96,8 +97,8 @@ def main():
     nrec0 = sim.num_records()
     print("timing %d steps from |S| = %d" % (args.steps, nS0), file=sys.stderr,
           flush=True)
-    # the timed window times only the Clenshaw launches, by events their own
-    # dispatches record (no marker packets on the stream)
+    # the timed window times one middle Clenshaw launch per step, by events
+    # its own dispatch records (no stage markers on the stream)
     sim.profile(True, kernels_only=True)
     sim.profile_reset()
     torch.cuda.synchronize()
@@ -154,6 +155,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_cheb_term (middle Clenshaw term)",
                      "launches": n_term, "avg_ms": term_ms,
+                     "sampling": "one middle launch per timed step",
                      "bytes_per_launch": term_bytes,
                      "bytes_per_row": row_bytes},
         "stage_ms_per_step": stage_ms,

@@ -257,11 +257,12 @@ paces_status paces_get_set(paces_sim* s, int32_t which, int32_t round,
 paces_status paces_get_phi(paces_sim* s, double* amps, void* hip_stream);
 
 /* Timing with HIP events on the step's stream.  Level 1: events around
- * every stage launch group (each marker costs the stream a few
- * microseconds) plus the timed kernels below; level 2: only the timed
- * kernels (each Clenshaw launch, each Lanczos SpMV but the last), whose
- * events their own dispatch records, which adds no idle time.  Level 0:
- * off.  Profiling turns graph replay off. */
+ * every stage launch group plus every timed kernel (each Clenshaw launch,
+ * each Lanczos SpMV but the last), whose events their own dispatch
+ * records; level 2: one timed kernel per step (launch index 1: a middle
+ * Clenshaw term whenever K >= 4, the second Lanczos SpMV).  Every event
+ * costs the stream a few microseconds of idle time, hence level 2 for
+ * timing whole runs.  Level 0: off.  Profiling turns graph replay off. */
 typedef enum {
   PACES_STAGE_SELECT = 0,
   PACES_STAGE_EXPAND = 1,   /* expansion rounds incl. the lookup pass     */

@@ -416,12 +416,15 @@ struct Stage {
   }
 };
 
-// Start / stop events of one timed kernel, recorded by its own dispatch
-// (any profiling level); queued for classification after the step.
+// Start / stop events of one timed kernel, recorded by its own dispatch;
+// queued for classification after the step.  Level 1 times every such
+// launch, level 2 one per step (index 1: a middle Clenshaw term whenever
+// the series has four or more terms, the second Lanczos SpMV), since each
+// timed dispatch still costs the stream some idle time.
 struct KernelTiming {
   hipEvent_t a{}, b{};
   KernelTiming(paces_sim* s, int stage, int kk) {
-    if (!s->prof) return;
+    if (!s->prof || (s->prof == 2 && kk != 1)) return;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
       if (a) (void)hipEventDestroy(a);
       a = b = nullptr;

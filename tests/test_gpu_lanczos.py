@@ -171,6 +171,10 @@ def test_profile_counts_the_krylov_launches():
     gs.step(3)
     prof = gs.profile_get()
     assert prof["launches"]["krylov"] == 3 * 7  # every SpMV but the last
+    gs.profile(True, kernels_only=True)
+    gs.profile_reset()
+    gs.step(2)
+    assert gs.profile_get()["launches"]["krylov"] == 2  # one per step
     assert prof["krylov_bytes"] > 0 and prof["ms"]["krylov"] > 0
     assert prof["launches"]["term"] == 0
 
