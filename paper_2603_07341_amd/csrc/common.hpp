@@ -47,7 +47,11 @@ namespace {
 
 constexpr int kItems = 8;
 constexpr int kTile = kBlock * kItems;
-constexpr int kMaxGrid = kMaxPartials;
+// Grid-stride kernels launch at most this many blocks (4M threads, several
+// times what the 256 CUs hold): blocks beyond the work are dispatched only
+// to exit, and with grids sized from a row estimate they cost the
+// expansion rounds about a sixth of their time.
+constexpr int kMaxGrid = 16384;
 constexpr int kFold = 256;  // blocks of the second reduction level
 
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) {
