@@ -443,8 +443,10 @@ __global__ void __launch_bounds__(kBlock)
     slot_row_info<W>(m, k, py, tot[p], s, np, nt);
     pay[row] = np;
     tot[row] = nt;
-    const uint64_t e = table[c_slot[c]];
-    table[c_slot[c]] = (e & 0xFFFFFFFF00000000ull) | uint64_t(row);
+    // the slot holds (tag | candidate); the tag follows from the key, so
+    // the entry is rewritten without reading it back
+    table[c_slot[c]] =
+        (uint64_t(hash_tag(key_hash<W>(m, k))) << 32) | uint64_t(row);
     crow[c] = uint32_t(row);
     col[p * D + s] = int32_t(row);
     Amp z;
