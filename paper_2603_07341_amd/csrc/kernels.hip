@@ -241,14 +241,16 @@ __device__ __forceinline__ void count_flush(int R, uint32_t* lds,
 
 // ---- insert rows into the cleared table -------------------------------------
 // Row i of the new set is row midx[i] of the old one (keys_o given) or is
-// already in place (rehash after growth, keys_o null).
-template <int W>
+// already in place (rehash after growth, keys_o null).  With phi given, the
+// row's amplitude moves along (the transfer then skips rows of M).
+template <int W, typename Amp>
 __global__ void __launch_bounds__(kBlock)
     k_insert_rows(DevModel m, const uint64_t* keys_o, const uint64_t* pay_o,
                   const uint64_t* tot_o, const uint32_t* midx,
                   const uint32_t* nptr, int64_t n_fixed, uint64_t* keys_n,
                   uint64_t* pay_n, uint64_t* tot_n, uint64_t* table,
-                  uint64_t mask, uint32_t* cnt_r, int* err) {
+                  uint64_t mask, uint32_t* cnt_r, const Amp* psi_o, Amp* phi,
+                  int* err) {
   __shared__ uint32_t bins[kMaxReal];
   if (*err) return;
   for (int r = threadIdx.x; r < m.R; r += blockDim.x) bins[r] = 0;
@@ -262,6 +264,7 @@ __global__ void __launch_bounds__(kBlock)
       store_key<W>(keys_n, i, k);
       pay_n[i] = pay_o[r];
       tot_n[i] = tot_o[r];
+      if (phi) phi[i] = psi_o[r];
       if (cnt_r) atomicAdd(&bins[pay_real(pay_o[r])], 1u);
     } else {
       load_key<W>(keys_n, i, k);
@@ -495,12 +498,16 @@ __global__ void __launch_bounds__(kBlock)
 
 // ---- transfer ---------------------------------------------------------------
 
+// Old row i goes to its row of the new set, or counts as discarded weight.
+// skip 1 (threshold selection) and 2 (preset flags keep[i]): rows of M are
+// already in place (insert) and are passed over.
 template <int W, typename Amp>
 __global__ void __launch_bounds__(kBlock)
     k_transfer(DevModel m, const uint64_t* keys_o, const Amp* psi_o,
                const StepCtl* ctl, const uint64_t* table, uint64_t mask,
                const uint64_t* keys_n, Amp* phi, double* mass_part,
-               int32_t* tmap, const int* err) {
+               int32_t* tmap, int skip, double th2, const uint8_t* keep,
+               const int* err) {
   __shared__ double bins[kMaxReal];
   if (*err) return;
   const int R = m.R;
@@ -511,10 +518,11 @@ __global__ void __launch_bounds__(kBlock)
   const int64_t n_old = ctl->n_old;
   double lost = 0;
   for (int64_t i = gtid(); i < n_old; i += gstride()) {
+    const Amp v = psi_o[i];
+    if ((skip == 1 && weight(v) >= th2) || (skip == 2 && keep[i])) continue;
     uint64_t k[W];
     load_key<W>(keys_o, i, k);
     const int64_t r = table_find<W>(table, mask, keys_n, k, key_hash<W>(m, k));
-    const Amp v = psi_o[i];
     if (tmap) tmap[i] = int32_t(r);
     if (r >= 0)
       phi[r] = v;
@@ -1159,13 +1167,22 @@ void select_flags(const uint8_t* keep, StepCtl* ctl, uint32_t* midx,
   k_flag_write<<<g, kBlock, 0, s>>>(keep, ctl, tmp, midx);
 }
 
-void insert_rows(const DevModel& m, int Wi, const Side& o, const Side& n,
-                 const uint32_t* midx, const StepCtl* ctl, uint64_t* table,
-                 uint64_t mask, uint32_t* cnt_m, int* err, hipStream_t s) {
+void insert_rows(const DevModel& m, int Wi, int prec, const Side& o,
+                 const Side& n, const uint32_t* midx, const StepCtl* ctl,
+                 uint64_t* table, uint64_t mask, uint32_t* cnt_m,
+                 const void* psi_o, void* phi, int* err, hipStream_t s) {
   const int g = grid_for(int64_t(mask + 1) / 2);
-  PACES_DISPATCH_W(Wi, k_insert_rows<WW><<<g, kBlock, 0, s>>>(
-                           m, o.keys, o.pay, o.tot, midx, &ctl->nM, 0, n.keys,
-                           n.pay, n.tot, table, mask, cnt_m, err));
+  if (prec == 64) {
+    PACES_DISPATCH_W(Wi, k_insert_rows<WW, double2><<<g, kBlock, 0, s>>>(
+                             m, o.keys, o.pay, o.tot, midx, &ctl->nM, 0,
+                             n.keys, n.pay, n.tot, table, mask, cnt_m,
+                             (const double2*)psi_o, (double2*)phi, err));
+  } else {
+    PACES_DISPATCH_W(Wi, k_insert_rows<WW, float2><<<g, kBlock, 0, s>>>(
+                             m, o.keys, o.pay, o.tot, midx, &ctl->nM, 0,
+                             n.keys, n.pay, n.tot, table, mask, cnt_m,
+                             (const float2*)psi_o, (float2*)phi, err));
+  }
 }
 
 void rehash_rows(const DevModel& m, int Wi, const Side& n, uint32_t* midx,
@@ -1173,10 +1190,10 @@ void rehash_rows(const DevModel& m, int Wi, const Side& n, uint32_t* midx,
                  hipStream_t s) {
   (void)midx;
   if (rows <= 0) return;
-  PACES_DISPATCH_W(Wi, k_insert_rows<WW><<<grid_for(rows), kBlock, 0, s>>>(
+  PACES_DISPATCH_W(Wi, k_insert_rows<WW, double2><<<grid_for(rows), kBlock, 0, s>>>(
                            m, nullptr, nullptr, nullptr, nullptr, nullptr,
                            rows, n.keys, n.pay, n.tot, table, mask, nullptr,
-                           err));
+                           nullptr, nullptr, err));
 }
 
 void expand_round(const DevModel& m, int Wi, int prec, const Side& n, int r,
@@ -1226,17 +1243,19 @@ int part_grid(int64_t rows) { return grid_for(rows); }
 int transfer(const DevModel& m, int Wi, int prec, const Side& o,
              const void* psi_o, int64_t n_old, const StepCtl* ctl,
              const uint64_t* table, uint64_t mask, const uint64_t* keys_n,
-             void* phi, double* mass_part, int32_t* tmap, int* err,
-             hipStream_t s) {
+             void* phi, double* mass_part, int32_t* tmap, int skip, double th2,
+             const uint8_t* keep, int* err, hipStream_t s) {
   const int g = m.R > 1 ? std::min(grid_for(n_old), kPartBlocks) : grid_for(n_old);
   if (prec == 64) {
     PACES_DISPATCH_W(Wi, k_transfer<WW, double2><<<g, kBlock, 0, s>>>(
                              m, o.keys, (const double2*)psi_o, ctl, table, mask,
-                             keys_n, (double2*)phi, mass_part, tmap, err));
+                             keys_n, (double2*)phi, mass_part, tmap, skip, th2,
+                             keep, err));
   } else {
     PACES_DISPATCH_W(Wi, k_transfer<WW, float2><<<g, kBlock, 0, s>>>(
                              m, o.keys, (const float2*)psi_o, ctl, table, mask,
-                             keys_n, (float2*)phi, mass_part, tmap, err));
+                             keys_n, (float2*)phi, mass_part, tmap, skip, th2,
+                             keep, err));
   }
   return g;
 }

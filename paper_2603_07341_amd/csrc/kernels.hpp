@@ -80,9 +80,11 @@ void select_rows(int prec, const void* psi, double th2, bool select_all,
 void select_flags(const uint8_t* keep, StepCtl* ctl, uint32_t* midx,
                   uint32_t* tmp, int64_t cap, int* err, hipStream_t s);
 // Rows 0..nM-1 of the new side are M; inserted into the cleared table.
-void insert_rows(const DevModel& m, int Wi, const Side& o, const Side& n,
-                 const uint32_t* midx, const StepCtl* ctl, uint64_t* table,
-                 uint64_t mask, uint32_t* cnt_m, int* err, hipStream_t s);
+// phi (may be null) receives their amplitudes from psi_o.
+void insert_rows(const DevModel& m, int Wi, int prec, const Side& o,
+                 const Side& n, const uint32_t* midx, const StepCtl* ctl,
+                 uint64_t* table, uint64_t mask, uint32_t* cnt_m,
+                 const void* psi_o, void* phi, int* err, hipStream_t s);
 // Rebuild the table from rows [0, n) of a side (after growth).
 void rehash_rows(const DevModel& m, int Wi, const Side& n, uint32_t* midx,
                  int64_t rows, uint64_t* table, uint64_t mask, int* err,
@@ -103,12 +105,14 @@ void lookup_last(const DevModel& m, int Wi, const Side& n, int k,
 // Number of per-block partials written by a kernel over `rows` rows.
 int part_grid(int64_t rows);
 // Returns the number of mass partials written.  tmap (may be null) gets
-// the new row of every old row, -1 if dropped.
+// the new row of every old row, -1 if dropped (then skip must be 0).
+// skip: 0 every old row; 1 rows with weight < th2 only; 2 rows with
+// keep[row] == 0 only -- the rows of M, placed by insert_rows.
 int transfer(const DevModel& m, int Wi, int prec, const Side& o,
              const void* psi_o, int64_t n_old, const StepCtl* ctl,
              const uint64_t* table, uint64_t mask, const uint64_t* keys_n,
-             void* phi, double* mass_part, int32_t* tmap, int* err,
-             hipStream_t s);
+             void* phi, double* mass_part, int32_t* tmap, int skip, double th2,
+             const uint8_t* keep, int* err, hipStream_t s);
 // Gershgorin bounds + Chebyshev coefficients per realization (cc[R]);
 // latches if some K_r exceeds the launches enqueued.
 void bounds_and_coef(const DevModel& m, const Side& n, const int32_t* col,

@@ -677,8 +677,9 @@ void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st,
       row_info(dm, Wi, sn.keys, fz->nM, sn.pay, sn.tot, st);
       rehash_rows(dm, Wi, sn, nullptr, fz->nM, s->table, s->tmask, s->err, st);
     } else {
-      insert_rows(dm, Wi, so, sn, s->midx, s->ctl, s->table, s->tmask,
-                  s->cnt, s->err, st);
+      insert_rows(dm, Wi, s->prec, so, sn, s->midx, s->ctl, s->table,
+                  s->tmask, s->cnt, s->vec[s->ipsi], s->vec[s->iphi], s->err,
+                  st);
     }
     for (int r = 1; r <= k; ++r)
       expand_round(dm, Wi, s->prec, sn, r, s->ctl, s->cap, est, s->table,
@@ -692,10 +693,14 @@ void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st,
   int n_mass = 0, n_e = 0;
   {
     Stage sg(s, PACES_STAGE_TRANSFER, st);
+    // rows of M were placed with their amplitudes by the insert; the
+    // frozen replay maps every old row
+    const int skip = fz ? 0 : (s->cap_active ? 2 : (s->fresh ? 0 : 1));
     const int np = transfer(dm, Wi, s->prec, so, s->vec[s->ipsi],
                             bucket(s->nS), s->ctl, s->table, s->tmask, sn.keys,
                             s->vec[s->iphi], s->mass_part,
-                            fz ? fz->tmap : nullptr, s->err, st);
+                            fz ? fz->tmap : nullptr, skip, s->th2, s->keep,
+                            s->err, st);
     n_mass = R == 1 ? fold_sum(s->mass_part, np, s->mass_fold, s->err, st) : np;
   }
   const bool want_e = (s->p.obs_mask & PACES_OBS_ENERGY) != 0;
