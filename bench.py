@@ -111,11 +111,13 @@ def main():
     rec = sim.series(nrec0, args.steps, stream)
     # per-stage breakdown from a few further steps with stage events (not
     # part of the timed window)
+    nrec1 = sim.num_records()
     sim.profile(True)
     sim.profile_reset()
     sim.step(args.stage_steps, stream=stream)
     sprof = sim.profile_get(stream)
     sim.profile(False)
+    srec = sim.series(nrec1, args.stage_steps, stream)
     elapsed = t1 - t0
     updates = float(rec[:, 7].sum())
     value = updates / elapsed
@@ -161,6 +163,9 @@ def main():
         "stage_ms_per_step": stage_ms,
         "stage_ms_note": "%d further steps after the timed window, with "
                          "stage events" % args.stage_steps,
+        "stages": stage_bandwidth(model, A, sprof, srec,
+                                  float(rec[-1, 7]), args.stage_steps,
+                                  copy_peak_gbs()),
         "tuning": tuning,
         "terms_per_step": float(rec[:, 9].mean()),
     }
@@ -177,6 +182,70 @@ def main():
         out["cpu_baseline"] = cpu_baseline(params, run, cpu_state, cfg,
                                            args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def copy_peak_gbs(mib=1024, reps=5):
+    """Measured device-copy bandwidth in this run (read + write bytes of a
+    plain torch copy of `mib` MiB, best of `reps`), a practical peak beside
+    the 8 TB/s specification."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    del src, dst
+    return 2.0 * mib * (1 << 20) / (best * 1e-3) / 1e9
+
+
+def stage_bandwidth(model, A, sprof, srec, n_old0, steps, copy_gbs):
+    """Effective bandwidth per stage over the stage-event steps: algorithmic
+    bytes (compulsory streams, each once per pass; gathers counted as cache
+    hits) from the steps' own counts, over the stage's event time.
+      select        n_old (A + 1) + 4 |M|
+      expand+build  |S| (8W + D (8 + 8W + 4) + rho (8W + 16)),
+                    rho = net growth of S / |S| (a lower bound on new rows)
+      transfer      n_old (16W + 8 + 2A)
+      propagate     |S| K (4A + 4D + 8)  (Clenshaw)
+      observe       |S| 2A"""
+    W, D = model.W, model.D
+    nS = srec[:, 7]
+    nM = srec[:, 8]
+    K = srec[:, 9]
+    n_old = [n_old0] + list(nS[:-1])
+    by = {"select": 0.0, "expand+build": 0.0, "transfer": 0.0,
+          "propagate": 0.0, "observe": 0.0}
+    for s in range(steps):
+        rho = max(0.0, nS[s] - n_old[s]) / max(nS[s], 1.0)
+        by["select"] += n_old[s] * (A + 1) + 4 * nM[s]
+        by["expand+build"] += nS[s] * (8 * W + D * (8 + 8 * W + 4) + rho * (8 * W + 16))
+        by["transfer"] += n_old[s] * (16 * W + 8 + 2 * A)
+        by["propagate"] += nS[s] * K[s] * (4 * A + 4 * D + 8)
+        by["observe"] += nS[s] * 2 * A
+    ms = dict(sprof["ms"])
+    ms["expand+build"] = ms["expand"] + ms["build"]
+    out = {"copy_peak_gbs": copy_gbs, "unit": "GB/s"}
+    tb = tt = 0.0
+    for k, b in by.items():
+        t = ms[k] * 1e-3
+        tb += b
+        tt += t
+        g = b / t / 1e9 if t > 0 else 0.0
+        out[k] = {"bytes_per_step": b / steps, "ms_per_step": ms[k] / steps,
+                  "effective": g, "frac_spec": g / HBM_PEAK_GBS,
+                  "frac_copy": g / copy_gbs}
+    g = tb / tt / 1e9 if tt > 0 else 0.0
+    out["total"] = {"effective": g, "frac_spec": g / HBM_PEAK_GBS,
+                    "frac_copy": g / copy_gbs}
+    return out
 
 
 def timed(fn):
