@@ -28,7 +28,7 @@ class _Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("k", C.c_int32), ("k_init", C.c_int32),
                 ("theta", C.c_double), ("max_terms", C.c_int32),
                 ("max_states", C.c_int64), ("q_nom", C.c_int64),
-                ("krylov_order", C.c_int32)]
+                ("krylov_order", C.c_int32), ("taylor_order", C.c_int32)]
 
 
 _lib = None
@@ -137,6 +137,7 @@ class Sim:
         p.max_states = int(run.get("max_states", 0))
         p.q_nom = int(run.get("q_nom", 0))
         p.krylov_order = int(run.get("krylov_order", 0))
+        p.taylor_order = int(run.get("taylor_order", 0))
         exc = np.ascontiguousarray(exc, dtype=np.int32)
         occ = np.ascontiguousarray(occ, dtype=np.uint16)
         coef = np.ascontiguousarray(coef, dtype=np.float64)
@@ -262,6 +263,34 @@ def lanczos(rowptr, cols, vals, dt, order, v):
     return vout.view(np.complex128), B, alpha[:d], beta[:max(d, 1)], tuple(er)
 
 
+def taylor_theta(m):
+    lib().orc_taylor_theta.restype = C.c_double
+    return lib().orc_taylor_theta(C.c_int32(m))
+
+
+def taylor_select(norm):
+    m, s = C.c_int32(), C.c_int32()
+    _check(lib().orc_taylor_select(C.c_double(norm), C.byref(m), C.byref(s)))
+    return m.value, s.value
+
+
+def taylor(rowptr, cols, vals, dt, emin, emax, order, v):
+    """Truncated Taylor propagator (order -1: degree and substeps chosen);
+    returns (v_out, matrix-vector products)."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int64)
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    vin = np.ascontiguousarray(np.asarray(v, dtype=np.complex128)).view(np.float64)
+    n = len(rowptr) - 1
+    vout = np.zeros(2 * n, dtype=np.float64)
+    mvs = C.c_int32()
+    _check(lib().orc_taylor(C.c_int64(n), _p(rowptr, C.c_int64), _p(cols, C.c_int64),
+                            _p(vals, C.c_double), C.c_double(dt), C.c_double(emin),
+                            C.c_double(emax), C.c_int32(order), _p(vin, C.c_double),
+                            _p(vout, C.c_double), C.byref(mvs)))
+    return vout.view(np.complex128), mvs.value
+
+
 def param_names(model_params):
     """Names of the gradient entries: J per axis, g and omega per mode,
     eps per site."""
@@ -285,6 +314,7 @@ class Frozen:
         p.max_states = int(run.get("max_states", 0))
         p.q_nom = int(run.get("q_nom", 0))
         p.krylov_order = int(run.get("krylov_order", 0))
+        p.taylor_order = int(run.get("taylor_order", 0))
         exc = np.ascontiguousarray(exc, dtype=np.int32)
         occ = np.ascontiguousarray(occ, dtype=np.uint16)
         coef = np.ascontiguousarray(coef, dtype=np.float64)

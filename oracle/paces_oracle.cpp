@@ -473,6 +473,119 @@ void jacobi_eigen(int n, std::vector<double>& a, std::vector<double>& q) {
 }
 
 // ---------------------------------------------------------------------------
+// Truncated Taylor propagator with the degree and substep choice of Al-Mohy
+// & Higham ("Computing the action of the matrix exponential", SIAM J. Sci.
+// Comput. 33, 2011), the method App. "The action of the exponential of a
+// sparse matrix" names, and the fixed-order series of App. "An effective
+// Hilbert space up to neighbor order m = 2 is not equivalent to a
+// second-order Taylor expansion".
+//
+// Backward-error threshold theta_m: with T_m the degree-m Taylor polynomial
+// of exp, exp(-x) T_m(x) = exp(h(x)), h(x) = sum_{k > m} c_k x^k, and
+// theta_m = max { theta : sum_k |c_k| theta^(k-1) <= 2^-53 }.  The c_k come
+// from the power series of g = exp(-x) T_m(x) (g_0 = 1, g_1..g_m = 0) by
+// the logarithm recurrence k h_k = k g_k - sum_{j<k} j h_j g_(k-j), kept to
+// degree m + 120 in long double; theta by bisection.
+//
+// Readings where the method leaves a choice: A = -i (H - b) dt with b the
+// centre of the padded Gershgorin interval and ||A|| bounded by its half
+// width a times dt (the bound every norm estimate of the method may be
+// replaced by); (m, s) = argmin over m = 1..55 of m * max(1, ceil(a dt /
+// theta_m)), the smallest m on ties; no early termination of the series.
+// Fixed order N: one substep of N terms.  The result carries exp(-i b dt).
+// ---------------------------------------------------------------------------
+constexpr int kTaylorMaxDeg = 55;
+
+double taylor_theta(int m) {
+  const int M = m + 121;
+  std::vector<long double> g(M + 1, 0.0L), h(M + 1, 0.0L);
+  for (int k = 0; k <= M; ++k) {
+    long double sum = 0;
+    for (int j = 0; j <= std::min(k, m); ++j) {
+      long double t = 1;  // (-1)^(k-j) / ((k-j)! j!)
+      for (int q = 1; q <= k - j; ++q) t /= q;
+      for (int q = 1; q <= j; ++q) t /= q;
+      sum += ((k - j) & 1) ? -t : t;
+    }
+    g[k] = k == 0 ? 1.0L : (k <= m ? 0.0L : sum);
+  }
+  for (int k = 1; k <= M; ++k) {
+    long double acc = 0;
+    for (int j = 1; j < k; ++j) acc += j * h[j] * g[k - j];
+    h[k] = g[k] - acc / k;
+  }
+  const long double tol = std::ldexp(1.0L, -53);
+  auto excess = [&](long double th) {
+    long double sum = 0, p = 1;  // p = th^(k-1)
+    for (int k = 1; k <= M; ++k) {
+      if (k > m) sum += std::fabs(h[k]) * p;
+      p *= th;
+    }
+    return sum - tol;
+  };
+  long double lo = 0, hi = 1;
+  while (excess(hi) < 0) hi *= 2;
+  for (int it = 0; it < 200; ++it) {
+    const long double mid = 0.5L * (lo + hi);
+    if (excess(mid) < 0) lo = mid; else hi = mid;
+  }
+  return double(lo);
+}
+
+const std::vector<double>& taylor_thetas() {
+  static const std::vector<double> t = [] {
+    std::vector<double> v(kTaylorMaxDeg + 1, 0.0);
+    for (int m = 1; m <= kTaylorMaxDeg; ++m) v[m] = taylor_theta(m);
+    return v;
+  }();
+  return t;
+}
+
+void taylor_select(double norm, int& m_out, int& s_out) {
+  const std::vector<double>& th = taylor_thetas();
+  double best = INFINITY;
+  m_out = 1;
+  s_out = 1;
+  for (int m = 1; m <= kTaylorMaxDeg; ++m) {
+    const double sd = std::max(1.0, std::ceil(norm / th[m]));
+    if (m * sd < best) {
+      best = m * sd;
+      m_out = m;
+      s_out = int(sd);
+    }
+  }
+}
+
+// order > 0: fixed order, one substep; order < 0: (m, s) chosen as above.
+int taylor_expmv(const CSR& H, double dt, int order,
+                 const std::vector<cplx>& v, std::vector<cplx>& out,
+                 int& mvs) {
+  const double b = 0.5 * (H.emax + H.emin), a = 0.5 * (H.emax - H.emin);
+  int m = order, s = 1;
+  if (order <= 0) taylor_select(a * dt, m, s);
+  std::vector<cplx> f = v, term, y;
+  mvs = 0;
+  for (int sub = 0; sub < s; ++sub) {
+    term = f;
+    std::vector<cplx> acc = f;
+    for (int j = 1; j <= m; ++j) {
+      spmv(H, term, y);
+      const cplx fac(0.0, -dt / (double(s) * j));
+      for (int64_t i = 0; i < H.n; ++i) {
+        term[i] = fac * (y[i] - b * term[i]);
+        acc[i] += term[i];
+      }
+      ++mvs;
+    }
+    f = acc;
+  }
+  const cplx phase = std::exp(cplx(0.0, -b * dt));
+  out.resize(H.n);
+  for (int64_t i = 0; i < H.n; ++i) out[i] = phase * f[i];
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
 // Krylov (Lanczos) propagator of App. "Series-based exponentiation compared
 // to a Lanczos algorithm": exp(-i H dt) v ~ V exp(-i T dt) V^dag v, V an
 // orthonormal basis of the Krylov space span{v, Hv, .., H^p v} and
@@ -577,6 +690,7 @@ struct Params {
   int64_t max_states = 0;  // cap on |S| (0 = none)
   int64_t q_nom = 0;       // fixed-size truncation (0 = threshold)
   int krylov_order = 0;    // > 0: Lanczos propagator of this order
+  int taylor_order = 0;    // -1: Taylor with (m, s) chosen; N > 0: N terms
 };
 
 // ---------------------------------------------------------------------------
@@ -720,7 +834,10 @@ int sim_step(Sim& sim) {
   std::vector<cplx> out;
   int terms = 0;
   double e_lo = H.emin, e_hi = H.emax;
-  if (sim.p.krylov_order > 0) {
+  if (sim.p.taylor_order != 0) {
+    if (taylor_expmv(H, sim.p.dt, sim.p.taylor_order, phi, out, terms))
+      return 1;
+  } else if (sim.p.krylov_order > 0) {
     KrylovOut ko;
     if (lanczos_expmv(H, sim.p.dt, sim.p.krylov_order, phi, out, ko)) return 1;
     terms = ko.dim;
@@ -1249,6 +1366,12 @@ int orc_sim_create(const void* mp, const orc_params* p, int64_t n,
     return fail("bad krylov_order");
   }
   s->p.krylov_order = p->krylov_order;
+  if (p->taylor_order < -1 || p->taylor_order > 60 ||
+      (p->taylor_order != 0 && p->krylov_order != 0)) {
+    delete s;
+    return fail("bad taylor_order");
+  }
+  s->p.taylor_order = p->taylor_order;
   if (load_state(*m, n, keys.data(), coef, s->S, s->psi)) {
     delete s;
     return 1;
@@ -1424,11 +1547,49 @@ int orc_lanczos(int64_t n, const int64_t* rowptr, const int64_t* cols,
   return 0;
 }
 
+double orc_taylor_theta(int32_t m) {
+  if (m < 1 || m > kTaylorMaxDeg) return -1.0;
+  return taylor_thetas()[m];
+}
+
+int orc_taylor_select(double norm, int32_t* m, int32_t* s) {
+  if (!(norm >= 0) || !m || !s) return fail("bad arguments");
+  int mm = 0, ss = 0;
+  taylor_select(norm, mm, ss);
+  *m = mm;
+  *s = ss;
+  return 0;
+}
+
+int orc_taylor(int64_t n, const int64_t* rowptr, const int64_t* cols,
+               const double* vals, double dt, double emin, double emax,
+               int32_t order, const double* v_in, double* v_out,
+               int32_t* mvs) {
+  if (n < 0 || !rowptr || !v_in || !v_out) return fail("bad arguments");
+  CSR H;
+  H.n = n;
+  H.rowptr.assign(rowptr, rowptr + n + 1);
+  H.cols.assign(cols, cols + rowptr[n]);
+  H.vals.assign(vals, vals + rowptr[n]);
+  H.emin = emin;
+  H.emax = emax;
+  std::vector<cplx> v(n), out;
+  for (int64_t i = 0; i < n; ++i) v[i] = cplx(v_in[2 * i], v_in[2 * i + 1]);
+  int t = 0;
+  if (taylor_expmv(H, dt, order, v, out, t)) return 1;
+  for (int64_t i = 0; i < n; ++i) {
+    v_out[2 * i] = out[i].real();
+    v_out[2 * i + 1] = out[i].imag();
+  }
+  if (mvs) *mvs = t;
+  return 0;
+}
+
 int orc_frozen_record(const void* mp, const orc_params* p, int64_t n,
                       const int32_t* exc, const uint16_t* occ,
                       const double* coef, int64_t n_steps, void** out) {
   if (!mp || !out || n_steps < 0) return fail("bad arguments");
-  if (p && p->krylov_order != 0)
+  if (p && (p->krylov_order != 0 || p->taylor_order != 0))
     return fail("the adjoint gradient differentiates the series propagator");
   void* sp = nullptr;
   if (orc_sim_create(mp, p, n, exc, occ, coef, &sp)) return 1;

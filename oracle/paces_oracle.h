@@ -58,6 +58,10 @@ typedef struct {
   int32_t krylov_order;  /* 0: series propagator; p in 1..63: Lanczos
                             propagator in the (p+1)-dimensional Krylov
                             space (see orc_lanczos)                          */
+  int32_t taylor_order;  /* 0: off; -1: truncated Taylor series with the
+                            degree and substeps of Al-Mohy & Higham; N in
+                            1..60: N terms in one step (see orc_taylor);
+                            exclusive with krylov_order                      */
 } orc_params;
 
 /* Observables recorded after each step (field order of orc_sim_obs). */
@@ -143,6 +147,19 @@ int orc_lanczos(int64_t n, const int64_t* rowptr, const int64_t* cols,
                 const double* vals, double dt, int32_t order,
                 const double* v_in, double* v_out, double* basis,
                 double* alpha, double* beta, int32_t* dim, double* e_range);
+
+/* Truncated Taylor propagator (the source states the method): the
+ * backward-error threshold theta_m of the degree-m series at unit
+ * roundoff 2^-53 (m in 1..55, else -1), the (degree, substeps) choice for
+ * a given bound of ||A||, and the propagator itself for a caller-given CSR
+ * H with Gershgorin interval [emin, emax]: order -1 chooses (m, s), order
+ * N > 0 takes N terms in one step; mvs = matrix-vector products used. */
+double orc_taylor_theta(int32_t m);
+int orc_taylor_select(double norm, int32_t* m, int32_t* s);
+int orc_taylor(int64_t n, const int64_t* rowptr, const int64_t* cols,
+               const double* vals, double dt, double emin, double emax,
+               int32_t order, const double* v_in, double* v_out,
+               int32_t* mvs);
 
 /* Adjoint gradient on a frozen sequence of sets (Form (3)).
  * orc_frozen_record runs n_steps ordinary steps from the initial state and
