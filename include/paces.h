@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define PACES_ABI_VERSION 9
+#define PACES_ABI_VERSION 10
 
 typedef enum {
   PACES_OK = 0,
@@ -77,6 +77,10 @@ typedef enum {
 
 const char* paces_last_error(void);
 int32_t paces_abi_version(void);
+/* theta_m of the truncated Taylor propagator (taylor_order): the largest
+ * theta for which the degree-m series of exp on ||A|| <= theta has relative
+ * backward error at most 2^-53; m in 1..55, else -1.  Host only. */
+double paces_taylor_theta(int32_t m);
 
 typedef struct paces_model paces_model; /* immutable after load */
 typedef struct paces_sim paces_sim;     /* owns the device state of a run */
@@ -136,6 +140,21 @@ typedef struct {
                           record's K is the dimension used and E_min /
                           E_max the padded Gershgorin interval of T.  Not
                           with the adjoint entry points.                  */
+  int32_t taylor_order;/* 0: off.  -1: truncated Taylor series (paper: App.
+                          "The action of the exponential of a sparse
+                          matrix"), psi' = exp(-i b dt) [T_m(A/s)]^s phi,
+                          A = -i (H - b) dt, b the centre of the padded
+                          Gershgorin interval; degree m and substeps s
+                          minimise m s subject to s >= a dt / theta_m (a
+                          the half width, theta_m the degree-m backward
+                          error threshold at 2^-53, paces_taylor_theta)
+                          (Al-Mohy & Higham 2011).  N in 1..60: N terms in
+                          one step (App. "An effective Hilbert space up to
+                          neighbor order m = 2 is not equivalent to a
+                          second-order Taylor expansion"; not unitary).
+                          The record's K is m s.  Holds three extra vectors
+                          of the row capacity.  Exclusive with
+                          krylov_order; not with the adjoint entry points. */
 } paces_run_params;
 
 #define PACES_OBS_ENERGY 1u /* <psi|H_eff|psi> per step (one extra SpMV

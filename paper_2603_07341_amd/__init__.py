@@ -28,7 +28,8 @@ STATUS = {0: "OK", 1: "E_ARG", 2: "E_OOM", 3: "E_CAPACITY", 4: "E_NONFINITE",
 
 # Every symbol include/paces.h declares.
 EXPORTS = [
-    "paces_last_error", "paces_abi_version", "paces_record_doubles",
+    "paces_last_error", "paces_abi_version", "paces_taylor_theta",
+    "paces_record_doubles",
     "paces_load_model", "paces_free_model", "paces_model_info",
     "paces_pack_keys", "paces_unpack_keys", "paces_init_state",
     "paces_free_sim", "paces_step", "paces_observe", "paces_num_records",
@@ -61,7 +62,7 @@ class _Run(C.Structure):
                 ("precision", C.c_int32), ("tol", C.c_double),
                 ("k_max_terms", C.c_int32), ("obs_mask", C.c_uint32),
                 ("max_states", C.c_int64), ("q_nom", C.c_int64),
-                ("krylov_order", C.c_int32)]
+                ("krylov_order", C.c_int32), ("taylor_order", C.c_int32)]
 
 
 class _Obs(C.Structure):
@@ -98,6 +99,7 @@ def lib():
         _lib = C.CDLL(LIB_PATH)
         _lib.paces_last_error.restype = C.c_char_p
         _lib.paces_abi_version.restype = C.c_int32
+        _lib.paces_taylor_theta.restype = C.c_double
         _lib.paces_record_doubles.restype = C.c_int32
         _lib.paces_num_params.restype = C.c_int32
     return _lib
@@ -227,6 +229,7 @@ class Sim:
         r.max_states = int(run.get("max_states", 0))
         r.q_nom = int(run.get("q_nom", 0))
         r.krylov_order = int(run.get("krylov_order", 0))
+        r.taylor_order = int(run.get("taylor_order", 0))
         exc = np.ascontiguousarray(exc, dtype=np.int32)
         occ = np.ascontiguousarray(occ, dtype=np.uint16)
         coef = np.ascontiguousarray(coef, dtype=np.float64)
@@ -437,6 +440,12 @@ class Sim:
         _check(lib().paces_adjoint_backward(self.h, _p(gb, C.c_double),
                                             _p(g, C.c_double), _stream(stream)))
         return g
+
+
+def taylor_theta(m):
+    """Backward-error threshold theta_m of the degree-m Taylor series (the
+    Taylor propagator's degree choice); -1 outside 1..55."""
+    return lib().paces_taylor_theta(C.c_int32(m))
 
 
 def theta_of(params):

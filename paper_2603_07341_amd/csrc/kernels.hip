@@ -1260,6 +1260,14 @@ int transfer(const DevModel& m, int Wi, int prec, const Side& o,
   return g;
 }
 
+int bounds_part(const DevModel& m, const Side& n, const int32_t* col,
+                int64_t cap, int64_t est, const StepCtl* ctl, double* part,
+                const int* err, hipStream_t s) {
+  const int g = std::min(grid_for(est), kPartBlocks);
+  k_bounds<<<g, kBlock, 0, s>>>(m, n.pay, n.tot, col, cap, ctl, part, err);
+  return g;
+}
+
 void bounds_and_coef(const DevModel& m, const Side& n, const int32_t* col,
                      int64_t cap, int64_t est, StepCtl* ctl, double dt,
                      double tol, int k_max, int launched, double* part,

@@ -119,6 +119,11 @@ void bounds_and_coef(const DevModel& m, const Side& n, const int32_t* col,
                      int64_t cap, int64_t est, StepCtl* ctl, double dt,
                      double tol, int k_max, int launched, double* part,
                      ChebCoef* cc, int* err, hipStream_t s);
+// Gershgorin bounds only: per-block (lo, hi) per realization into
+// part[block][R][2]; returns the number of blocks.
+int bounds_part(const DevModel& m, const Side& n, const int32_t* col,
+                int64_t cap, int64_t est, const StepCtl* ctl, double* part,
+                const int* err, hipStream_t s);
 // Fold n per-block partials to at most 256 (deterministic); returns count.
 int fold_sum(const double* in, int n, double* out, int* err, hipStream_t s);
 // Clenshaw launch for index kk (see kernels.hip); buffers b[0], b[1].

@@ -31,6 +31,7 @@
 #include "cap.hpp"
 #include "kernels.hpp"
 #include "lanczos.hpp"
+#include "taylor.hpp"
 
 using namespace paces;
 
@@ -329,6 +330,10 @@ struct paces_sim {
   double* lz_part = nullptr;    // per-block partials of the Lanczos SpMV
   double* lz_energy = nullptr;  // [R] <phi|H|phi>
   std::vector<void*> kry;       // basis vectors 2 .. order, row capacity
+                                // (Taylor: the second term and two sums)
+  // truncated Taylor propagator (taylor_order != 0)
+  TaylorPlan* tplan = nullptr;  // [R]
+  double* thetas = nullptr;     // [kTaylorMaxDeg + 1]
 
   // state cap (max_states per realization)
   uint32_t* ball = nullptr;       // [R] rows of the new set per realization
@@ -516,8 +521,11 @@ paces_status grow(paces_sim* s, int64_t new_cap, hipStream_t st) {
   uint32_t *nmidx = nullptr, *nscan = nullptr;
   double* nerow = nullptr;
   // Krylov basis: w_0 = phi and w_1 = the second Clenshaw buffer; the
-  // remaining order - 1 vectors here
-  std::vector<void*> nkry(std::max(0, s->p.krylov_order - 1), nullptr);
+  // remaining order - 1 vectors here.  Taylor: one more term buffer and the
+  // two substep sums.
+  const int n_extra = s->p.krylov_order > 0 ? s->p.krylov_order - 1
+                                            : (s->p.taylor_order != 0 ? 3 : 0);
+  std::vector<void*> nkry(n_extra, nullptr);
   Pieces pc;
   for (int q = 0; q < 2; ++q) {
     pc.add(&nsd[q].keys, new_cap * m->Wi);
@@ -704,7 +712,38 @@ void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st,
     n_mass = R == 1 ? fold_sum(s->mass_part, np, s->mass_fold, s->err, st) : np;
   }
   const bool want_e = (s->p.obs_mask & PACES_OBS_ENERGY) != 0;
-  if (s->p.krylov_order > 0) {
+  if (s->p.taylor_order != 0) {
+    // truncated Taylor series: bounds and plan, then the term launches
+    // (launch L is term L mod m + 1 of substep L / m)
+    {
+      Stage sg(s, PACES_STAGE_BUILD, st);
+      const int nb = bounds_part(dm, sn, s->col, s->cap, est, s->ctl,
+                                 s->bnd_part, s->err, st);
+      taylor_plan(R, s->bnd_part, nb, s->p.dt, s->p.taylor_order, s->thetas,
+                  s->p.k_max_terms, s->launched, s->tplan, s->cc, s->ctl,
+                  s->err, st);
+    }
+    Stage sg(s, PACES_STAGE_PROPAGATE, st);
+    void* bufB[2] = {s->vec[s->ib1], s->kry[0]};
+    void* bufF[2] = {s->kry[1], s->kry[2]};
+    int np = 0;
+    // the adaptive series is exact to rounding, so the energy of phi is
+    // that of the result; the fixed order needs its own pass
+    const bool fixed = s->p.taylor_order > 0;
+    for (int L = 0; L < s->launched; ++L) {
+      KernelTiming kt(s, PACES_STAGE_TERM, L);
+      const int g = taylor_term(dm, s->prec, L, want_e && !fixed, s->p.dt,
+                                std::max<int64_t>(1, est / s->tune.term_rows),
+                                s->ctl, s->col, sn, s->tplan,
+                                s->vec[s->iphi], bufB, bufF, s->vec[s->ib0],
+                                s->e_part, s->e_row, s->err, kt.a, kt.b, st);
+      if (L == 0) np = g;
+    }
+    if (want_e && fixed)
+      np = taylor_energy(dm, s->prec, est, s->ctl, s->col, sn, s->vec[s->ib0],
+                         s->e_part, s->e_row, s->err, st);
+    if (want_e && R == 1) n_e = fold_sum(s->e_part, np, s->e_fold, s->err, st);
+  } else if (s->p.krylov_order > 0) {
     // Krylov propagator: nk SpMVs with their folds, nk - 1 recurrence
     // passes, the small exponential and the combination into b0
     Stage sg(s, PACES_STAGE_PROPAGATE, st);
@@ -792,7 +831,8 @@ paces_status launch_step_graph(paces_sim* s, int64_t est, bool counted,
       int64_t(s->gen), s->cur, s->ipsi, s->iphi, s->ib0, s->ib1,
       s->fresh ? 1 : 0, counted ? 1 : 0, s->fresh ? s->p.k_init : s->p.k,
       s->launched, s->K_last, est, std::min(bucket(s->nS), s->cap),
-      int64_t(s->tmask), s->tune.term_rows, s->p.krylov_order};
+      int64_t(s->tmask), s->tune.term_rows, s->p.krylov_order,
+      s->p.taylor_order};
   for (auto& g : s->graphs)
     if (g.key == key) {
       g.used = ++s->graph_clock;
@@ -1237,7 +1277,7 @@ namespace {
 
 paces_status adj_supported(const paces_sim* s) {
   const paces_model* m = s->m;
-  if (s->p.krylov_order > 0)
+  if (s->p.krylov_order > 0 || s->p.taylor_order != 0)
     return fail(PACES_E_UNSUPPORTED,
                 "the adjoint differentiates the series propagator");
   if (m->R != 1 || s->prec != 64)
@@ -1439,6 +1479,11 @@ int32_t paces_record_doubles(const paces_model* m) {
   return m ? kObsFields + m->N : 0;
 }
 
+double paces_taylor_theta(int32_t m) {
+  if (m < 1 || m > kTaylorMaxDeg) return -1.0;
+  return taylor_thetas_host()[m];
+}
+
 paces_status paces_load_model(const paces_model_desc* d, paces_model** out) {
   if (!d || !out) return fail(PACES_E_ARG, "null argument");
   *out = nullptr;
@@ -1631,7 +1676,9 @@ paces_status paces_init_state(const paces_model* m, const paces_run_params* p,
       p->max_states < 0 || p->max_states >= (int64_t(1) << 31) ||
       p->q_nom < 0 || p->q_nom >= (int64_t(1) << 31) ||
       (p->q_nom > 0 && p->max_states > 0) || p->krylov_order < 0 ||
-      p->krylov_order >= kMaxKrylov)
+      p->krylov_order >= kMaxKrylov || p->taylor_order < -1 ||
+      p->taylor_order > 60 ||
+      (p->taylor_order != 0 && p->krylov_order != 0))
     return fail(PACES_E_ARG, "bad run parameters");
   const int R = m->R;
   if (n * R > (int64_t(1) << 30)) return fail(PACES_E_ARG, "too many states");
@@ -1698,6 +1745,14 @@ paces_status paces_init_state(const paces_model* m, const paces_run_params* p,
       dalloc(&s->keys0, nt * m->Wi) ||
       dalloc(&s->amps0, 2 * nt))
     return cleanup(PACES_E_OOM);
+  if (p->taylor_order != 0) {
+    if (dalloc(&s->tplan, R) || dalloc(&s->thetas, kTaylorMaxDeg + 1))
+      return cleanup(PACES_E_OOM);
+    if (hipMemcpy(s->thetas, taylor_thetas_host(),
+                  sizeof(double) * (kTaylorMaxDeg + 1),
+                  hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(fail(PACES_E_HIP, "upload failed"));
+  }
   if (p->krylov_order > 0 &&
       (dalloc(&s->lz, R) || dalloc(&s->lz_energy, R) ||
        dalloc(&s->lz_part, 3 * std::max<int64_t>(kLzGrid1,
@@ -1761,6 +1816,8 @@ paces_status paces_free_sim(paces_sim* s) {
   dfree(s->lz);
   dfree(s->lz_part);
   dfree(s->lz_energy);
+  dfree(s->tplan);
+  dfree(s->thetas);
   drop_pending(s);
   for (auto& e : s->events) {
     (void)hipEventDestroy(e.a);

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(lib, name), name
     assert sorted(P.EXPORTS) == declared
-    assert lib.paces_abi_version() == 9
+    assert lib.paces_abi_version() == 10
 
 
 @pytest.mark.parametrize("name", ["ring4", "ring16", "sq6x6", "cube4", "ring12"])
@@ -114,4 +114,23 @@ def test_krylov_order_out_of_range_is_rejected_before_device_work(order):
     run = dict(WL.run_params(cfg), krylov_order=order)
     with pytest.raises(P.PacesError) as ei:
         P.Sim(m, run, *WL.initial_state(cfg))
+    assert ei.value.status == 1
+
+
+@pytest.mark.parametrize("m", [1, 2, 5, 13, 34, 55])
+def test_library_taylor_thresholds_match_exact_definition(m):
+    # the library's own computation (host code, no GPU) against the exact
+    # rational computation of the oracle pins
+    from tests.test_oracle_taylor import theta
+    assert P.taylor_theta(m) == pytest.approx(theta(m), rel=1e-9)
+    assert P.taylor_theta(0) == -1.0 and P.taylor_theta(56) == -1.0
+
+
+@pytest.mark.parametrize("over", [dict(taylor_order=-2), dict(taylor_order=61),
+                                  dict(taylor_order=-1, krylov_order=3)])
+def test_taylor_order_validation(over):
+    cfg = dict(WL.CONFIGS["ring4"])
+    m = P.Model(WL.model_params(cfg))
+    with pytest.raises(P.PacesError) as ei:
+        P.Sim(m, dict(WL.run_params(cfg), **over), *WL.initial_state(cfg))
     assert ei.value.status == 1
