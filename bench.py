@@ -17,7 +17,8 @@ cpu_baseline: the CPU oracle continued from the GPU state at the start of
 the timed window, for a bounded number of steps.
 forms: the extra forms against plain FP64 single-realization runs on the
 same GPU: complex64 amplitudes on the same window; the order-10 Krylov
-propagator on the same window from the same state; 64 disorder
+propagator and the truncated Taylor series on the same window from the
+same state; 64 disorder
 realizations of the 6x6 lattice in one sim against realizations run one
 after another; the adjoint gradient of the 12-site ring against its plain
 forward run (time ratio).
@@ -175,6 +176,8 @@ def main():
             "fp32": form_fp32(args, rec, elapsed, stream),
             "krylov": form_krylov(args, cpu_state, t_start, rec, elapsed,
                                   stream),
+            "taylor": form_taylor(args, cpu_state, t_start, rec, elapsed,
+                                  stream),
             "batched": form_batched(args, stream),
             "adjoint": form_adjoint(args, stream),
         }
@@ -318,6 +321,47 @@ def form_krylov(args, state, t_start, rec_ref, el_ref, stream):
             "max_rel_err_norm_vs_series": float(np.max(np.abs(rec[:, 1] / rec_ref[:, 1] - 1))),
             "spmv_ms_total": round(prof["ms"]["krylov"], 3),
             "spmv_roofline": {"bound": "hbm", "achieved": ach,
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": ach / HBM_PEAK_GBS, "launches": n,
+                              "avg_ms": ms}}
+
+
+def form_taylor(args, state, t_start, rec_ref, el_ref, stream):
+    """The timed window again with the truncated Taylor propagator (degree
+    and substeps chosen per step as Al-Mohy & Higham do) in place of the
+    Chebyshev series, from the same state: throughput and deviation of a(t)
+    against the series run; its term launches have the Clenshaw term's
+    streams (4A + 4D + 8 bytes per row), timed one per step."""
+    import numpy as np
+    import paper_2603_07341_amd as P
+    import workloads as WL
+    cfg = dict(WL.CONFIGS["ring16"], precision=64)
+    m = P.Model(WL.model_params(cfg))
+    run = dict(WL.run_params(cfg), taylor_order=-1)
+    s = P.Sim(m, run, *WL.initial_state(cfg), stream=stream)
+    keys, amps = state
+    s.set_state(keys, amps, t_start, stream=stream)
+    print("taylor: %d steps from |S| = %d" % (args.steps, len(keys)),
+          file=sys.stderr, flush=True)
+    s.profile(True, kernels_only=True)
+    s.profile_reset()
+    _, el = timed(lambda: s.step(args.steps, stream=stream))
+    prof = s.profile_get(stream)
+    s.profile(False)
+    rec = s.series(0, args.steps, stream)
+    n = prof["launches"]["term"]
+    ms = prof["ms"]["term"] / max(n, 1)
+    ach = prof["term_bytes"] / max(n, 1) / (ms * 1e-3) / 1e9 if n else 0.0
+    a = rec[:, 3] + 1j * rec[:, 4]
+    a_ref = rec_ref[:, 3] + 1j * rec_ref[:, 4]
+    return {"value": float(rec[:, 7].sum()) / el, "unit": "updates/s",
+            "ms_per_step": el * 1e3 / args.steps,
+            "time_vs_series": el / el_ref,
+            "products_per_step": float(rec[:, 9].mean()),
+            "chebyshev_terms_per_step": float(rec_ref[:, 9].mean()),
+            "max_abs_err_autocorr_vs_series": float(np.max(np.abs(a - a_ref))),
+            "max_rel_err_norm_vs_series": float(np.max(np.abs(rec[:, 1] / rec_ref[:, 1] - 1))),
+            "term_roofline": {"bound": "hbm", "achieved": ach,
                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": ach / HBM_PEAK_GBS, "launches": n,
                               "avg_ms": ms}}
