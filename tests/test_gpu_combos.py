@@ -1,0 +1,64 @@
+"""The propagators combined with the truncation rules and a
+piecewise-constant Hamiltonian, GPU vs oracle through the C ABI: the state
+cap and the fixed-size truncation select the same sets whatever the
+propagator, and a model switch between steps reaches every propagator."""
+import numpy as np
+import pytest
+
+import paper_2603_07341_amd as P
+from oracle import oracle as O
+from tests.gpu_helpers import assert_same_set, check_obs, rel_err, sort_rows
+import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+BASE = dict(extent=[6, 1, 1], cutoff=[4], theta=1e-6, k=2, k_init=2)
+PROPAGATORS = [{}, dict(krylov_order=8), dict(taylor_order=-1)]
+
+
+def pair(run_over, **over):
+    cfg = dict(WL.CONFIGS["ring12"])
+    cfg.update(BASE)
+    cfg.update(over)
+    p = WL.model_params(cfg)
+    run = dict(WL.run_params(cfg), **run_over)
+    init = WL.initial_state(cfg)
+    return cfg, P.Sim(P.Model(p), run, *init), O.Sim(O.Model(p), run, *init)
+
+
+def check(gs, os_, tol=1e-10, series_K=True):
+    for which in (O.SET_M, O.SET_S):
+        assert_same_set(gs.get_set(which), os_.get_set(which), "set %d" % which)
+    gk, ga = sort_rows(*gs.state())
+    ok, oa = os_.state()
+    assert np.array_equal(gk, ok)
+    assert rel_err(ga, oa) <= tol
+    go, oo = gs.observations()[-1], os_.observations()[-1]
+    check_obs(go, oo, tol, width=oo["E_max"] - oo["E_min"])
+
+
+@pytest.mark.parametrize("prop", PROPAGATORS)
+@pytest.mark.parametrize("trunc", [dict(max_states=400), dict(q_nom=60)])
+def test_truncation_rules_with_every_propagator(prop, trunc):
+    cfg, gs, os_ = pair(dict(prop, **trunc))
+    for _ in range(10):
+        gs.step(1)
+        os_.step(1)
+        check(gs, os_)
+        if "max_states" in trunc:
+            assert gs.observations()[-1]["n_S"] <= trunc["max_states"]
+
+
+@pytest.mark.parametrize("prop", PROPAGATORS)
+def test_model_switch_with_every_propagator(prop):
+    cfg, gs, os_ = pair(prop)
+    gs.step(4)
+    os_.step(4)
+    q = WL.model_params(dict(WL.CONFIGS["ring12"], **BASE), J=[-0.6], g=[1.4])
+    gm2, om2 = P.Model(q), O.Model(q)
+    gs.set_model(gm2)
+    os_.set_model(om2)
+    for _ in range(4):
+        gs.step(1)
+        os_.step(1)
+        check(gs, os_)
