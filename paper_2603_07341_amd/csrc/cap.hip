@@ -122,19 +122,40 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// Digit histogram of the open rows per realization.  Up to kLdsReal
+// realizations the block counts in LDS and adds each nonzero bin once: the
+// leading weight digits are shared by almost every row, and global atomics
+// on those few bins serialise the whole pass.
+constexpr int kLdsReal = 32;  // 32 * 256 counters = 32 KiB of LDS
+
 template <int Wi>
 __global__ void __launch_bounds__(kBlock)
     k_cap_hist(DevModel m, int W, int pass, const uint32_t* midx, int64_t nM,
                const uint64_t* keys, const uint64_t* pay,
                const uint64_t* wkey, const uint64_t* hkey,
                const uint8_t* status, uint32_t* hist) {
+  __shared__ uint32_t bins[kLdsReal * 256];
+  const bool lds = m.R <= kLdsReal;
+  if (lds) {
+    for (int q = threadIdx.x; q < m.R * 256; q += blockDim.x) bins[q] = 0;
+    __syncthreads();
+  }
   for (int64_t j = gtid(); j < nM; j += gstride()) {
     if (status[j] != 0) continue;
     const int64_t i = midx[j];
     uint64_t k[Wi] = {};
     if (pass >= 16) load_key<Wi>(keys, i, k);
     const int d = cap_digit<Wi>(pass, wkey[j], hkey[j], k, W, m.B);
-    atomicAdd(&hist[pay_real(pay[i]) * 256 + d], 1u);
+    const int b = pay_real(pay[i]) * 256 + d;
+    if (lds)
+      atomicAdd(&bins[b], 1u);
+    else
+      atomicAdd(&hist[b], 1u);
+  }
+  if (lds) {
+    __syncthreads();
+    for (int q = threadIdx.x; q < m.R * 256; q += blockDim.x)
+      if (bins[q]) atomicAdd(&hist[q], bins[q]);
   }
 }
 

@@ -19,6 +19,14 @@ constexpr int kMaxV = 4;    // modes per site
 constexpr int kMaxD = 14;   // 2*3 hops + 2*4 exciton-phonon slots
 constexpr int kBlock = 256;
 constexpr uint64_t kEmpty = ~0ull;       // free hash slot
+// Longest probe sequence an insert may take.  An insert that would go
+// further latches kErrTableFull (the step is repeated with a larger
+// table), so every key of a completed table lies within kMaxProbe slots of
+// its home and a lookup can stop there.  At the load factors the host
+// keeps (at most 1/2) sequences this long do not occur; when a set outgrows
+// its estimate the table fills up and the latch fires early instead of
+// after a walk through the whole table.
+constexpr uint64_t kMaxProbe = 4096;
 constexpr uint32_t kCand = 0x80000000u;  // ref names a candidate, not a row
 constexpr uint32_t kNone = 0xFFFFFFFFu;  // no slot / no column
 constexpr int kGsqStride = 256;          // g*sqrt(n) table row length
@@ -266,7 +274,7 @@ __device__ __forceinline__ int64_t table_find(const uint64_t* table,
                                               uint64_t h) {
   const uint32_t tag = hash_tag(h);
   uint64_t i = h & mask;
-  for (uint64_t probes = 0; probes <= mask; ++probes) {
+  for (uint64_t probes = 0; probes <= mask && probes < kMaxProbe; ++probes) {
     const uint64_t e = table[i];
     if (e == kEmpty) return -1;
     if (uint32_t(e >> 32) == tag) {

@@ -273,7 +273,7 @@ __global__ void __launch_bounds__(kBlock)
     const uint64_t mine = (uint64_t(hash_tag(h)) << 32) | uint64_t(i);
     uint64_t s = h & mask;
     bool done = false;
-    for (uint64_t p = 0; p <= mask; ++p) {
+    for (uint64_t p = 0; p <= mask && p < kMaxProbe; ++p) {
       if (table[s] == kEmpty &&
           atomicCAS((unsigned long long*)(table + s), (unsigned long long)kEmpty,
                     (unsigned long long)mine) == kEmpty) {
@@ -359,7 +359,8 @@ __global__ void __launch_bounds__(kBlock)
             (uint64_t(tag) << 32) | uint64_t(kCand | uint32_t(c));
         uint64_t i = h & mask;
         bool done = false;
-        for (uint64_t probes = 0; probes <= mask; ++probes) {
+        for (uint64_t probes = 0; probes <= mask && probes < kMaxProbe;
+             ++probes) {
           uint64_t e = table[i];
           if (e == kEmpty) {
             const uint64_t old = atomicCAS((unsigned long long*)(table + i),
