@@ -53,6 +53,15 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=200)
     ap.add_argument("--krylov-order", type=int, default=10)
     ap.add_argument("--stage-steps", type=int, default=5)
+    ap.add_argument("--paper-1d", type=float, default=None, metavar="G",
+                    help="instead of the benchmark, run the paper's 1D "
+                         "calculation at coupling G (its table of 1D runs: "
+                         "N, d_pho, q_nom per g; m_init 10, m 2, dt 0.05, "
+                         "t = 50) and print one JSON line with its wall "
+                         "time and q_true / q_nom")
+    ap.add_argument("--q-nom", type=float, default=None,
+                    help="q_nom of --paper-1d (default: the paper's)")
+    ap.add_argument("--paper-steps", type=int, default=1000)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (a "
                          "known-size reference for hardware byte counters)")
@@ -69,6 +78,9 @@ def main():
     import workloads as WL
 
     torch.cuda.set_device(0)
+    if args.paper_1d is not None:
+        print(json.dumps(paper_1d(args)), flush=True)
+        return
     if args.calib_copy_mib:
         n = args.calib_copy_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -185,6 +197,50 @@ def main():
         out["cpu_baseline"] = cpu_baseline(params, run, cpu_state, cfg,
                                            args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def paper_1d(args):
+    """One of the paper's 1D runs with its own parameters (open chain, one
+    exciton at the centre, J = omega = 1, fixed-size truncation q_nom,
+    m_init = 10, m = 2, dt = 0.05): wall time of the steps, updates/s and
+    q_true / q_nom = |S| / |M| once |M| = q_nom."""
+    import numpy as np
+    import torch
+    import paper_2603_07341_amd as P
+    import workloads as WL
+    cfg = WL.paper_1d(args.paper_1d, args.q_nom)
+    q = cfg["q_nom"]
+    run = dict(WL.run_params(cfg), cap_hint=int(12.5 * q))
+    stream = torch.cuda.current_stream()
+    sim = P.Sim(P.Model(WL.model_params(cfg)), run, *WL.initial_state(cfg),
+                stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < args.paper_steps:
+        n = min(50, args.paper_steps - done)
+        sim.step(n, stream=stream)
+        done += n
+        last = sim.series(done - 1, 1, stream)[0]
+        print("paper-1d g %g: step %d, |S| %d, |M| %d, %.1f s" % (
+            args.paper_1d, done, last[7], last[8], time.perf_counter() - t0),
+            file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    rec = sim.series(0, args.paper_steps, stream)
+    sat = rec[:, 8] >= q
+    ratio = rec[sat, 7] / rec[sat, 8]
+    tail = rec[-100:]
+    return {"workload": "paper 1D run: g %g, N %d, d_pho %d, q_nom %d, "
+                        "m_init 10, m 2, dt 0.05, %d steps" % (
+                            args.paper_1d, WL.n_sites(cfg), cfg["cutoff"][0] + 1,
+                            q, args.paper_steps),
+            "seconds": el, "updates_per_s": float(rec[:, 7].sum()) / el,
+            "S_max": int(rec[:, 7].max()),
+            "q_true_over_q_nom_mean": float(ratio.mean()) if len(ratio) else None,
+            "q_true_over_q_nom_last100": float((tail[:, 7] / tail[:, 8]).mean()),
+            "final_norm2": float(rec[-1, 1]), "final_t": float(rec[-1, 0]),
+            "terms_per_step": float(rec[:, 9].mean())}
 
 
 def copy_peak_gbs(mib=1024, reps=5):

@@ -84,6 +84,26 @@ CONFIGS = {
         init="bloch", max_states=0, ckpt_every=50),
 }
 
+# The paper's 1D benchmark runs (App. "Parameters & runtimes", table of the
+# 1D calculations): open chains, J = omega = 1, m_init = 10, m = 2,
+# dt = 0.05 up to t = 50 (1000 steps), fixed-size truncation q_nom, one
+# exciton at the centre with the vibrational vacuum.  Per g: (N, d_pho,
+# q_nom).
+PAPER_1D = {1.0: (75, 16, 25e6), 1.5: (75, 16, 25e6), 2.0: (51, 64, 25e6),
+            2.5: (25, 64, 32e6), 3.0: (25, 64, 32e6), 3.5: (25, 64, 32e6),
+            4.0: (25, 64, 32e6)}
+
+
+def paper_1d(g, q_nom=None):
+    """Workload dict of the paper's 1D run at coupling g (q_nom may be
+    overridden); the run uses q_nom, so theta is 0."""
+    N, d, q = PAPER_1D[g]
+    return dict(_lattice(1, [N], [0]), n_modes=1, cutoff=[d - 1],
+                omega=[1.0], g=[g], J=[1.0], eps_sigma=0.0, eps_seed=None,
+                n_real=1, dt=0.05, steps=1000, k=2, k_init=10, theta=0.0,
+                precision=64, init="local", site=N // 2, max_states=0,
+                q_nom=int(q if q_nom is None else q_nom))
+
 
 def n_sites(cfg):
     e = cfg["extent"]
@@ -139,6 +159,7 @@ def initial_state(cfg, kind=None, site=0):
     occ is a flat site-major list of N*V occupations per term; coef holds
     interleaved (re, im) pairs."""
     kind = kind or cfg["init"]
+    site = cfg.get("site", site)
     n = n_sites(cfg)
     V = cfg["n_modes"]
     if kind == "local":
@@ -159,7 +180,8 @@ def run_params(cfg, **override):
     c.update(override)
     return {"dt": c["dt"], "k": c["k"], "k_init": c["k_init"],
             "theta": c["theta"], "precision": c["precision"],
-            "max_states": c.get("max_states", 0)}
+            "max_states": c.get("max_states", 0),
+            "q_nom": c.get("q_nom", 0)}
 
 
 def random_amplitudes(seed, n):
