@@ -61,7 +61,14 @@ def main():
                          "time and q_true / q_nom")
     ap.add_argument("--q-nom", type=float, default=None,
                     help="q_nom of --paper-1d (default: the paper's)")
-    ap.add_argument("--paper-steps", type=int, default=1000)
+    ap.add_argument("--paper-steps", type=int, default=None,
+                    help="steps of --paper-1d / --paper-agg (default: the "
+                         "paper's, 1000 / 2000)")
+    ap.add_argument("--paper-agg", default=None, metavar="DIMS",
+                    help="instead of the benchmark, run the paper's "
+                         "aggregate calculation on lattice DIMS (e.g. 64, "
+                         "8x8, 2x2x2), H aggregate unless --paper-kind J")
+    ap.add_argument("--paper-kind", default="H", choices=["H", "J"])
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (a "
                          "known-size reference for hardware byte counters)")
@@ -78,8 +85,8 @@ def main():
     import workloads as WL
 
     torch.cuda.set_device(0)
-    if args.paper_1d is not None:
-        print(json.dumps(paper_1d(args)), flush=True)
+    if args.paper_1d is not None or args.paper_agg is not None:
+        print(json.dumps(paper_run(args)), flush=True)
         return
     if args.calib_copy_mib:
         n = args.calib_copy_mib * (1 << 20) // 8
@@ -199,16 +206,26 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def paper_1d(args):
-    """One of the paper's 1D runs with its own parameters (open chain, one
-    exciton at the centre, J = omega = 1, fixed-size truncation q_nom,
-    m_init = 10, m = 2, dt = 0.05): wall time of the steps, updates/s and
-    q_true / q_nom = |S| / |M| once |M| = q_nom."""
-    import numpy as np
+def paper_run(args):
+    """One of the paper's own calculations with its own parameters: a row
+    of its table of 1D runs (--paper-1d g: open chain, one exciton at the
+    centre, J = omega = 1, m_init 10, m 2, dt 0.05, t = 50) or an aggregate
+    (--paper-agg: g 0.71, J +-0.55, d_pho 16, k=0 Bloch start, t = 100),
+    both with fixed-size truncation q_nom.  Reports the wall time of the
+    steps, updates/s and q_true / q_nom = |S| / |M| once |M| = q_nom."""
     import torch
     import paper_2603_07341_amd as P
     import workloads as WL
-    cfg = WL.paper_1d(args.paper_1d, args.q_nom)
+    if args.paper_1d is not None:
+        cfg = WL.paper_1d(args.paper_1d, args.q_nom)
+        what = "paper 1D run: g %g, N %d, d_pho %d" % (
+            args.paper_1d, WL.n_sites(cfg), cfg["cutoff"][0] + 1)
+    else:
+        ext = [int(x) for x in args.paper_agg.split("x")]
+        cfg = WL.paper_aggregate(ext, args.paper_kind, args.q_nom)
+        what = "paper %s-aggregate run: %s lattice (periodic %s), d_pho 16" % (
+            args.paper_kind, args.paper_agg, cfg["periodic"][:len(ext)])
+    steps = args.paper_steps or cfg["steps"]
     q = cfg["q_nom"]
     run = dict(WL.run_params(cfg), cap_hint=int(12.5 * q))
     stream = torch.cuda.current_stream()
@@ -217,29 +234,28 @@ def paper_1d(args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0
-    while done < args.paper_steps:
-        n = min(50, args.paper_steps - done)
+    while done < steps:
+        n = min(50, steps - done)
         sim.step(n, stream=stream)
         done += n
         last = sim.series(done - 1, 1, stream)[0]
-        print("paper-1d g %g: step %d, |S| %d, |M| %d, %.1f s" % (
-            args.paper_1d, done, last[7], last[8], time.perf_counter() - t0),
+        print("%s: step %d, |S| %d, |M| %d, %.1f s" % (
+            what, done, last[7], last[8], time.perf_counter() - t0),
             file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    rec = sim.series(0, args.paper_steps, stream)
+    rec = sim.series(0, steps, stream)
     sat = rec[:, 8] >= q
     ratio = rec[sat, 7] / rec[sat, 8]
     tail = rec[-100:]
-    return {"workload": "paper 1D run: g %g, N %d, d_pho %d, q_nom %d, "
-                        "m_init 10, m 2, dt 0.05, %d steps" % (
-                            args.paper_1d, WL.n_sites(cfg), cfg["cutoff"][0] + 1,
-                            q, args.paper_steps),
+    return {"workload": "%s, q_nom %d, m_init %d, m %d, dt %g, %d steps" % (
+                what, q, cfg["k_init"], cfg["k"], cfg["dt"], steps),
             "seconds": el, "updates_per_s": float(rec[:, 7].sum()) / el,
             "S_max": int(rec[:, 7].max()),
             "q_true_over_q_nom_mean": float(ratio.mean()) if len(ratio) else None,
             "q_true_over_q_nom_last100": float((tail[:, 7] / tail[:, 8]).mean()),
-            "final_norm2": float(rec[-1, 1]), "final_t": float(rec[-1, 0]),
+            "final_norm2": float(rec[-1, 1]),
+            "norm_loss": float(1.0 - rec[-1, 1]), "final_t": float(rec[-1, 0]),
             "terms_per_step": float(rec[:, 9].mean())}
 
 

@@ -94,6 +94,24 @@ PAPER_1D = {1.0: (75, 16, 25e6), 1.5: (75, 16, 25e6), 2.0: (51, 64, 25e6),
             4.0: (25, 64, 32e6)}
 
 
+def paper_aggregate(extent, kind="H", q_nom=None):
+    """Workload dict of the paper's aggregate runs (App. "Parameters &
+    runtimes": g = 0.71, J = +0.55 (H) or -0.55 (J), d_pho = 16, m = 2,
+    dt = 0.05 to t = 100 (2000 steps), q_nom = 16e6; m_init = 10 for the 1D
+    and 2D lattices, 6 for the 3D ones), started from the dipole-excited k=0
+    Bloch state of <mu(t) mu(0)>.  Reading: periodic boundaries wherever an
+    extent is at least 3 (the paper does not state them)."""
+    ext = list(extent)
+    nd = len(ext)
+    per = [1 if e >= 3 else 0 for e in ext]
+    J = 0.55 if kind == "H" else -0.55
+    return dict(_lattice(nd, ext, per), n_modes=1, cutoff=[15], omega=[1.0],
+                g=[0.71], J=[J] * nd, eps_sigma=0.0, eps_seed=None, n_real=1,
+                dt=0.05, steps=2000, k=2, k_init=6 if nd == 3 else 10,
+                theta=0.0, precision=64, init="bloch", max_states=0,
+                q_nom=int(16e6 if q_nom is None else q_nom))
+
+
 def paper_1d(g, q_nom=None):
     """Workload dict of the paper's 1D run at coupling g (q_nom may be
     overridden); the run uses q_nom, so theta is 0."""
