@@ -69,6 +69,9 @@ def main():
                          "aggregate calculation on lattice DIMS (e.g. 64, "
                          "8x8, 2x2x2), H aggregate unless --paper-kind J")
     ap.add_argument("--paper-kind", default="H", choices=["H", "J"])
+    ap.add_argument("--paper-periodic", action="store_true",
+                    help="--paper-agg with periodic boundaries wherever an "
+                         "extent is >= 3 (default: open)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (a "
                          "known-size reference for hardware byte counters)")
@@ -222,7 +225,8 @@ def paper_run(args):
             args.paper_1d, WL.n_sites(cfg), cfg["cutoff"][0] + 1)
     else:
         ext = [int(x) for x in args.paper_agg.split("x")]
-        cfg = WL.paper_aggregate(ext, args.paper_kind, args.q_nom)
+        cfg = WL.paper_aggregate(ext, args.paper_kind, args.q_nom,
+                                 periodic=args.paper_periodic)
         what = "paper %s-aggregate run: %s lattice (periodic %s), d_pho 16" % (
             args.paper_kind, args.paper_agg, cfg["periodic"][:len(ext)])
     steps = args.paper_steps or cfg["steps"]

@@ -89,10 +89,14 @@ struct Pieces {
     list.push_back({p, std::max<size_t>(bytes, 1)});
   }
   static size_t round(size_t b) { return (b + 255) & ~size_t(255); }
+  size_t total() const {
+    size_t t = 0;
+    for (auto& q : list) t += round(q.second);
+    return t;
+  }
   // One allocation for every piece; pointers are written only on success.
   paces_status carve(void** block) {
-    size_t total = 0;
-    for (auto& q : list) total += round(q.second);
+    const size_t total = this->total();
     void* b = nullptr;
     const paces_status e = dev_alloc(&b, total);
     if (e) return e;
@@ -324,6 +328,8 @@ struct paces_sim {
   void* rows_block = nullptr;  // row arrays except the hash table
   void* cand_block = nullptr;  // candidate buffers of the expansion rounds
   void* cap_block = nullptr;   // per-row buffers of the state cap
+  size_t rows_bytes = 0, cand_bytes = 0, capb_bytes = 0;  // their sizes
+  bool mem_capped = false;  // the last growth was cut to fit the device
 
   // Krylov propagator (krylov_order > 0)
   LanczosState* lz = nullptr;   // [R]
@@ -450,6 +456,7 @@ void drop_pending(paces_sim* s) {
 void free_rows(paces_sim* s) {
   if (s->rows_block) dev_free(s->rows_block);
   s->rows_block = nullptr;
+  s->rows_bytes = 0;
   for (int q = 0; q < 2; ++q) s->side[q] = Side{};
   for (auto& v : s->vec) v = nullptr;
   s->col = nullptr;
@@ -463,6 +470,7 @@ void free_rows(paces_sim* s) {
 void free_cand(paces_sim* s) {
   if (s->cand_block) dev_free(s->cand_block);
   s->cand_block = nullptr;
+  s->cand_bytes = 0;
   s->rb = RoundBufs{};
 }
 
@@ -477,6 +485,7 @@ paces_status alloc_cand(paces_sim* s, int64_t want) {
   pc.add(&s->rb.tile_base, tiles);
   pc.add(&s->rb.scan_tmp, scan_tmp_words(tiles));
   ST_TRY(pc.carve(&s->cand_block));
+  s->cand_bytes = pc.total();
   s->rb.cand_cap = want;
   return PACES_OK;
 }
@@ -503,66 +512,117 @@ void drop_graphs(paces_sim* s) {
   s->graphs.clear();
 }
 
+int64_t cand_want(const paces_model* m, int64_t cap) {
+  // candidate buffers: half the worst case to start with; grown on demand
+  return std::min<int64_t>(std::max<int64_t>(cap * m->D / 2, int64_t(1) << 16),
+                           (int64_t(1) << 31) - 1);
+}
+
+// Pieces of the row block for cap rows: both sides' keys and row data, the
+// four amplitude vectors, the ELL columns, the selection and its scan, the
+// per-row energies of batched sims and the extra propagator vectors.
+struct RowBlock {
+  Side sd[2]{};
+  void* vec[4] = {nullptr, nullptr, nullptr, nullptr};
+  int32_t* col = nullptr;
+  uint32_t *midx = nullptr, *scan = nullptr;
+  double* erow = nullptr;
+  std::vector<void*> kry;
+  Pieces pc;
+  RowBlock(const paces_sim* s, int64_t cap) {
+    const paces_model* m = s->m;
+    // Krylov basis: w_0 = phi and w_1 = the second Clenshaw buffer; the
+    // remaining order - 1 vectors here.  Taylor: one more term buffer and
+    // the two substep sums.
+    const int n_extra = s->p.krylov_order > 0 ? s->p.krylov_order - 1
+                                              : (s->p.taylor_order != 0 ? 3 : 0);
+    kry.assign(n_extra, nullptr);
+    for (int q = 0; q < 2; ++q) {
+      pc.add(&sd[q].keys, cap * m->Wi);
+      pc.add(&sd[q].pay, cap);
+      pc.add(&sd[q].tot, cap);
+    }
+    for (int v = 0; v < 4; ++v) pc.add_bytes(&vec[v], size_t(cap) * s->A);
+    pc.add(&col, cap * m->D);
+    pc.add(&midx, cap);
+    pc.add(&scan, scan_tmp_words(cap));
+    if (m->R > 1) pc.add(&erow, cap);
+    for (auto& v : kry) pc.add_bytes(&v, size_t(cap) * s->A);
+  }
+};
+
+// Whether a capacity of cap rows fits the device: the new row block while
+// the old one is still alive (the current set is copied across), then the
+// table, the candidate and state-cap buffers once the old blocks are gone.
+// Only checked for the library's own allocator (the caller's may cache).
+bool fits_device(const paces_sim* s, int64_t cap) {
+  if (g_allocator.alloc) return true;
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) return true;
+  const double margin = double(size_t(2) << 30) + 0.02 * double(tot);
+  const double block = double(RowBlock(s, cap).pc.total());
+  if (block > double(fr) - margin) return false;
+  const int64_t want = cand_want(s->m, cap);
+  const double cand = want > s->rb.cand_cap ? 12.0 * double(want)
+                                            : double(s->cand_bytes);
+  const bool capbuf = s->p.q_nom > 0 || s->p.max_states > 0;
+  const double after =
+      block + 8.0 * double(table_size_for(cap, s->tune.table_shift)) + cand +
+      (capbuf ? 22.0 * double(cap) : 0.0);
+  const double back = double(s->rows_bytes) + double(s->cand_bytes) +
+                      double(s->capb_bytes) + 8.0 * double(s->tmask_alloc + 1);
+  return after <= double(fr) + back - margin;
+}
+
 // Reallocate every row array for new_cap rows, keeping the current set
 // (side cur, rows [0, nS)) and its amplitudes.  Everything else is rebuilt
-// by the next step.
-paces_status grow(paces_sim* s, int64_t new_cap, hipStream_t st) {
+// by the next step.  Where new_cap rows do not fit the device the capacity
+// is cut, down to min_cap (then the allocation is tried as asked).
+paces_status grow(paces_sim* s, int64_t new_cap, int64_t min_cap,
+                  hipStream_t st) {
   const paces_model* m = s->m;
   drop_graphs(s);
   ++s->gen;
-  new_cap = std::min<int64_t>((new_cap + 255) / 256 * 256, (int64_t(1) << 31) - 256);
+  auto round_cap = [](int64_t c) {
+    return std::min<int64_t>((c + 255) / 256 * 256, (int64_t(1) << 31) - 256);
+  };
+  new_cap = round_cap(new_cap);
+  min_cap = std::min(round_cap(std::max(min_cap, s->cap + 1)), new_cap);
   if (new_cap <= s->cap && s->cap > 0)
     return fail(PACES_E_CAPACITY, "row capacity limit (2^31 rows) reached");
+  const int64_t asked = new_cap;
+  while (new_cap > min_cap && !fits_device(s, new_cap))
+    new_cap = std::max(min_cap, round_cap(new_cap - new_cap / 8));
+  s->mem_capped = new_cap < asked;
   // every row array but the table in one block; the current set and psi
   // are copied over before the old block goes
-  Side nsd[2]{};
-  void* nvec[4] = {nullptr, nullptr, nullptr, nullptr};
-  int32_t* ncol = nullptr;
-  uint32_t *nmidx = nullptr, *nscan = nullptr;
-  double* nerow = nullptr;
-  // Krylov basis: w_0 = phi and w_1 = the second Clenshaw buffer; the
-  // remaining order - 1 vectors here.  Taylor: one more term buffer and the
-  // two substep sums.
-  const int n_extra = s->p.krylov_order > 0 ? s->p.krylov_order - 1
-                                            : (s->p.taylor_order != 0 ? 3 : 0);
-  std::vector<void*> nkry(n_extra, nullptr);
-  Pieces pc;
-  for (int q = 0; q < 2; ++q) {
-    pc.add(&nsd[q].keys, new_cap * m->Wi);
-    pc.add(&nsd[q].pay, new_cap);
-    pc.add(&nsd[q].tot, new_cap);
-  }
-  for (int v = 0; v < 4; ++v) pc.add_bytes(&nvec[v], size_t(new_cap) * s->A);
-  pc.add(&ncol, new_cap * m->D);
-  pc.add(&nmidx, new_cap);
-  pc.add(&nscan, scan_tmp_words(new_cap));
-  if (m->R > 1) pc.add(&nerow, new_cap);
-  for (auto& v : nkry) pc.add_bytes(&v, size_t(new_cap) * s->A);
+  RowBlock nb(s, new_cap);
   void* block = nullptr;
-  ST_TRY(pc.carve(&block));
+  ST_TRY(nb.pc.carve(&block));
   if (s->nS > 0) {
     const Side& o = s->side[s->cur];
-    Side& c = nsd[s->cur];
+    Side& c = nb.sd[s->cur];
     HIP_TRY(hipMemcpyAsync(c.keys, o.keys, size_t(s->nS) * m->Wi * 8,
                            hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(c.pay, o.pay, size_t(s->nS) * 8,
                            hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(c.tot, o.tot, size_t(s->nS) * 8,
                            hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipMemcpyAsync(nvec[s->ipsi], s->vec[s->ipsi],
+    HIP_TRY(hipMemcpyAsync(nb.vec[s->ipsi], s->vec[s->ipsi],
                            size_t(s->nS) * s->A, hipMemcpyDeviceToDevice, st));
   }
   HIP_TRY(hipStreamSynchronize(st));
   if (s->rows_block) dev_free(s->rows_block);
   s->rows_block = block;
-  s->side[0] = nsd[0];
-  s->side[1] = nsd[1];
-  for (int v = 0; v < 4; ++v) s->vec[v] = nvec[v];
-  s->col = ncol;
-  s->midx = nmidx;
-  s->scan_tmp = nscan;
-  s->e_row = nerow;
-  s->kry = nkry;
+  s->rows_bytes = nb.pc.total();
+  s->side[0] = nb.sd[0];
+  s->side[1] = nb.sd[1];
+  for (int v = 0; v < 4; ++v) s->vec[v] = nb.vec[v];
+  s->col = nb.col;
+  s->midx = nb.midx;
+  s->scan_tmp = nb.scan;
+  s->e_row = nb.erow;
+  s->kry = nb.kry;
   s->cap = new_cap;
   s->counts_valid = false;
   dfree(s->table);
@@ -570,10 +630,7 @@ paces_status grow(paces_sim* s, int64_t new_cap, hipStream_t st) {
   ST_TRY(dalloc(&s->table, int64_t(P)));
   s->tmask_alloc = P - 1;
   s->tmask = P - 1;
-  // candidate buffers: half the worst case to start with; grown on demand
-  const int64_t want = std::min<int64_t>(std::max<int64_t>(new_cap * m->D / 2,
-                                                           int64_t(1) << 16),
-                                         (int64_t(1) << 31) - 1);
+  const int64_t want = cand_want(m, new_cap);
   if (want > s->rb.cand_cap) ST_TRY(alloc_cand(s, want));
   return PACES_OK;
 }
@@ -622,7 +679,7 @@ paces_status upload_state(paces_sim* s, int64_t n,
   const paces_model* m = s->m;
   if (n > s->cap) {
     s->nS = 0;
-    ST_TRY(grow(s, std::max<int64_t>(2 * n, 2 * s->cap), st));
+    ST_TRY(grow(s, std::max<int64_t>(2 * n, 2 * s->cap), n, st));
   }
   Side& sc = s->side[s->cur];
   if (n > 0) {
@@ -871,6 +928,7 @@ paces_status cap_buffers(paces_sim* s) {
     if (s->cap_block) dev_free(s->cap_block);
     s->cap_block = nullptr;
     s->cap_buf = 0;
+    s->capb_bytes = 0;
     Pieces pc;
     pc.add(&s->keep, s->cap);
     pc.add(&s->midx_full, s->cap);
@@ -878,6 +936,7 @@ paces_status cap_buffers(paces_sim* s) {
     pc.add(&s->cap_h, s->cap);
     pc.add(&s->cap_status, s->cap);
     ST_TRY(pc.carve(&s->cap_block));
+    s->capb_bytes = pc.total();
     s->cap_buf = s->cap;
   }
   if (!s->cap_hist) {
@@ -1044,7 +1103,11 @@ paces_status do_step(paces_sim* s, hipStream_t st,
   // keep room for the new set: growth of the set per step stays well below
   // the factor used here in the workloads; an overflow is caught anyway.
   // Growth to 4 |S| makes the next one due only when the set has doubled.
-  if (s->nS > s->cap / 2) ST_TRY(grow(s, 4 * s->nS, st));
+  // A capacity cut to fit the device grows again only when the step's
+  // estimate no longer fits it.
+  const int64_t need = s->nS + std::max<int64_t>(s->nS / 2, 65536);
+  if (s->nS > s->cap / 2 && (!s->mem_capped || need > s->cap))
+    ST_TRY(grow(s, 4 * s->nS, need, st));
   ST_TRY(ensure_ring(s, st));
   const int64_t est = std::min<int64_t>(
       s->cap, bucket(std::max<int64_t>(s->nS + s->nS / 2, s->nS + 65536)));
@@ -1121,7 +1184,7 @@ paces_status do_step(paces_sim* s, hipStream_t st,
       if (s->tmask < s->tmask_alloc)
         s->tmask = 2 * s->tmask + 1;
       else
-        ST_TRY(grow(s, 2 * s->cap, st));
+        ST_TRY(grow(s, 2 * s->cap, s->cap + s->cap / 4, st));
       continue;
     }
     if (e & kErrCapacity) {
@@ -1130,7 +1193,7 @@ paces_status do_step(paces_sim* s, hipStream_t st,
       if (int64_t(c.r_rows) * m->D >= s->rb.cand_cap - m->D)
         ST_TRY(grow_cand(s, st));
       else
-        ST_TRY(grow(s, 2 * s->cap, st));
+        ST_TRY(grow(s, 2 * s->cap, s->cap + s->cap / 4, st));
       continue;
     }
     return check_latch_code(s, e);
@@ -1190,7 +1253,7 @@ paces_status take_snapshot(paces_sim* s, Snapshot& z, hipStream_t st) {
 paces_status restore_snapshot(paces_sim* s, const Snapshot& z,
                               hipStream_t st) {
   const paces_model* m = s->m;
-  if (z.n > s->cap) ST_TRY(grow(s, 2 * z.n, st));
+  if (z.n > s->cap) ST_TRY(grow(s, 2 * z.n, z.n, st));
   const Side& c = s->side[s->cur];
   if (z.n > 0) {
     HIP_TRY(hipMemcpyAsync(c.keys, z.keys, size_t(z.n) * m->Wi * 8,
@@ -1773,7 +1836,8 @@ paces_status paces_init_state(const paces_model* m, const paces_run_params* p,
       hipMemsetAsync(s->cnt, 0, size_t(2 * R) * 4, st) != hipSuccess)
     return cleanup(fail(PACES_E_HIP, "memset failed"));
   const int64_t cap0 = std::max<int64_t>({p->cap_states, 4 * nt, 1 << 16});
-  paces_status g = grow(s, cap0, st);
+  paces_status g =
+      grow(s, cap0, std::max<int64_t>(4 * nt, int64_t(1) << 16), st);
   if (g) return cleanup(g);
   g = ensure_ring(s, st);
   if (g) return cleanup(g);
