@@ -105,3 +105,25 @@ def test_profile_levels_time_the_clenshaw_launches(kernels_only):
     ka, aa = a.state()
     kb, bb = b.state()
     assert np.array_equal(sort_rows(ka, aa)[1], sort_rows(kb, bb)[1])
+
+
+def test_capacity_beyond_the_device_is_cut_to_fit():
+    # a row-capacity hint of 2^31 rows (several hundred GB of row arrays)
+    # is cut to what the device holds instead of failing with E_OOM; the
+    # run is the same as with the automatic capacity
+    cfg = WL.CONFIGS["ring16"]
+    m = P.Model(WL.model_params(cfg))
+    torch.cuda.empty_cache()
+    free0 = torch.cuda.mem_get_info()[0]
+    big = P.Sim(m, dict(WL.run_params(cfg), cap_hint=2 ** 31),
+                *WL.initial_state(cfg))
+    assert torch.cuda.mem_get_info()[0] < free0
+    big.step(6)
+    kb, ab = sort_rows(*big.state())
+    big.close()
+    ref = P.Sim(m, WL.run_params(cfg), *WL.initial_state(cfg))
+    ref.step(6)
+    kr, ar = sort_rows(*ref.state())
+    ref.close()
+    assert np.array_equal(kb, kr)
+    assert np.array_equal(ab, ar)
