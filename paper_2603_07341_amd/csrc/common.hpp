@@ -87,13 +87,19 @@ inline int tiles_for(int64_t bound) {
 }
 
 // |c|^2 as fl(fl(re*re) + fl(im*im)) in FP64 (FP32 amplitudes widened
-// first), compared with theta^2: the same predicate on every path.
+// first), compared with theta^2 and ranked by the truncation: the same
+// predicate on every path.  HIP device code contracts a*b + c into an FMA
+// by default (and __dmul_rn / __dadd_rn are plain operators there), which
+// rounds once instead of twice and can reorder weights one ulp apart, so
+// contraction is switched off here.
 __device__ __forceinline__ double weight(double2 c) {
-  return __dadd_rn(__dmul_rn(c.x, c.x), __dmul_rn(c.y, c.y));
+#pragma clang fp contract(off)
+  return c.x * c.x + c.y * c.y;
 }
 __device__ __forceinline__ double weight(float2 c) {
+#pragma clang fp contract(off)
   const double x = c.x, y = c.y;
-  return __dadd_rn(__dmul_rn(x, x), __dmul_rn(y, y));
+  return x * x + y * y;
 }
 __device__ __forceinline__ double2 widen(double2 c) { return c; }
 __device__ __forceinline__ double2 widen(float2 c) {

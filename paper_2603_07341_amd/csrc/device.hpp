@@ -259,9 +259,10 @@ __device__ __forceinline__ void slot_row_info(const DevModel& m,
 // term by term.
 __device__ __forceinline__ double row_diag(const DevModel& m, uint64_t pay,
                                            uint64_t tot) {
+#pragma clang fp contract(off)
   double d = m.eps[pay_real(pay) * m.N + pay_site(pay)];
   for (int nu = 0; nu < m.V; ++nu)
-    d = __dadd_rn(d, __dmul_rn(m.omega[nu], double(row_total(m.V, pay, tot, nu))));
+    d = d + m.omega[nu] * double(row_total(m.V, pay, tot, nu));
   return d;
 }
 
