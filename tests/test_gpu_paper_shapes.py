@@ -67,3 +67,22 @@ def test_paper_shape_steps_match_oracle(name, make):
         compare(gs, os_, prev["mass_total"], "%s step %d" % (name, step))
     # the truncation is active by the last step
     assert gs.observations()[-1]["n_M"] == cfg["q_nom"]
+
+
+@pytest.mark.parametrize("extent,kind", [([3, 3], "J"), ([2, 2, 2], "H"),
+                                         ([8], "H")])
+def test_zero_coupling_signal_follows_the_electronic_lines(extent, kind):
+    # g = 0: the method's a(t) is the electronic signal of the lattice,
+    # computed here by exact diagonalization of the hopping matrix
+    from paper_2603_07341_amd import spectra
+    cfg = WL.paper_aggregate(extent, kind, q_nom=10_000)
+    cfg["g"] = [0.0]
+    gs = P.Sim(P.Model(WL.model_params(cfg)), WL.run_params(cfg),
+               *WL.initial_state(cfg))
+    gs.step(60)
+    rec = gs.series()
+    t = rec[:, 0]
+    a = rec[:, 3] + 1j * rec[:, 4]
+    E, f = spectra.electronic_lines(extent, cfg["J"])
+    assert np.abs(a - spectra.electronic_signal(E, f, t)).max() < 1e-12
+    assert rec[-1, 7] == WL.n_sites(cfg)

@@ -66,3 +66,77 @@ def test_rmsd_on_rings():
     assert abs(spectra.exciton_rmsd(u, ext, per) - np.sqrt(np.mean(d ** 2) - np.mean(d) ** 2)) < 1e-14
     pt = np.stack([p, u])
     assert spectra.exciton_rmsd(pt, ext, per).shape == (2,)
+
+
+def test_electronic_lines_periodic_ring_has_one_bright_state():
+    # the uniform state is the k = 0 eigenstate of a ring: one line at 2J
+    E, f = spectra.electronic_lines([12], [0.55], [1])
+    assert abs(f.sum() - 1.0) < 1e-13
+    k = np.argmax(f)
+    assert abs(E[k] - 1.1) < 1e-13 and abs(f[k] - 1.0) < 1e-13
+    assert np.allclose(np.sort(E), np.sort(2 * 0.55 * np.cos(2 * np.pi * np.arange(12) / 12)),
+                       atol=1e-13)
+
+
+def open_chain_lines(N, J):
+    """Closed form of the open chain: E_n = 2 J cos(n pi / (N+1)) with
+    eigenvectors sqrt(2/(N+1)) sin(j n pi / (N+1)), j, n = 1..N."""
+    n = np.arange(1, N + 1)
+    E = 2 * J * np.cos(n * np.pi / (N + 1))
+    j = np.arange(1, N + 1)
+    amp = np.sqrt(2.0 / (N + 1)) * np.sin(np.outer(j, n) * np.pi / (N + 1)).sum(axis=0)
+    return E, amp ** 2 / N
+
+
+def test_electronic_lines_open_chain_closed_form():
+    N, J = 64, -0.55
+    E, f = spectra.electronic_lines([N], [J])
+    Ec, fc = open_chain_lines(N, J)
+    o = np.argsort(Ec)
+    assert np.allclose(E, Ec[o], atol=1e-12)
+    assert np.allclose(f, fc[o], atol=1e-12)
+    # only odd n are bright; the band-edge line carries
+    # 2 cot^2(pi / (2 (N+1))) / (N (N+1)), about 8 / pi^2 for long chains
+    assert abs(fc[0] - 2 / np.tan(np.pi / (2 * (N + 1))) ** 2 / (N * (N + 1))) < 1e-12
+    assert abs(fc[0] - 8 / np.pi ** 2) < 0.02
+    assert np.all(fc[1::2] < 1e-20)
+
+
+def test_electronic_lines_square_lattice_is_a_product():
+    # open L x L: E = E_x + E_y, f = f_x f_y (separable hopping)
+    L, Jx, Jy = 5, 0.55, 0.3
+    E, f = spectra.electronic_lines([L, L], [Jx, Jy])
+    ex, fx = open_chain_lines(L, Jx)
+    ey, fy = open_chain_lines(L, Jy)
+    Ep = (ex[:, None] + ey[None, :]).ravel()
+    fp = (fx[:, None] * fy[None, :]).ravel()
+    # compare the bright lines (degenerate eigenvectors mix only among
+    # equal energies, so sum strengths per distinct energy)
+    def per_energy(E, f):
+        out = {}
+        for e, w in zip(np.round(E, 9), f):
+            out[e] = out.get(e, 0.0) + w
+        return out
+    a, b = per_energy(E, f), per_energy(Ep, fp)
+    assert set(a) == set(b)
+    assert all(abs(a[k] - b[k]) < 1e-12 for k in a)
+
+
+def test_oracle_at_zero_coupling_follows_the_electronic_lines():
+    # g = 0 never creates phonons, so a(t) of the method (oracle, exact
+    # series) is the electronic signal of the open 3 x 3 aggregate
+    cfg = WL.paper_aggregate([3, 3], "J", q_nom=10_000)
+    cfg["g"] = [0.0]
+    s = O.Sim(O.Model(WL.model_params(cfg)), WL.run_params(cfg),
+              *WL.initial_state(cfg))
+    s.step(40)
+    obs = s.observations()
+    a = np.array([o["a_re"] + 1j * o["a_im"] for o in obs])
+    t = np.array([o["t"] for o in obs])
+    E, f = spectra.electronic_lines([3, 3], cfg["J"])
+    assert np.abs(a - spectra.electronic_signal(E, f, t)).max() < 1e-12
+    assert obs[-1]["n_S"] == 9
+    # and the damped transform of the recorded signal approaches the
+    # Lorentzian lines as T grows (here only checked for the line positions)
+    bright = E[f > 1e-3]
+    assert len(bright) >= 2  # an open 3 x 3 lattice has several bright states
