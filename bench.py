@@ -69,6 +69,12 @@ def main():
                          "aggregate calculation on lattice DIMS (e.g. 64, "
                          "8x8, 2x2x2), H aggregate unless --paper-kind J")
     ap.add_argument("--paper-kind", default="H", choices=["H", "J"])
+    ap.add_argument("--paper-krylov", type=int, default=0, metavar="P",
+                    help="--paper-1d / --paper-agg with the order-P Krylov "
+                         "propagator instead of the series")
+    ap.add_argument("--paper-save", default=None, metavar="FILE",
+                    help="save the run's per-step records (.npy, fields as "
+                         "in the library's observation record)")
     ap.add_argument("--paper-periodic", action="store_true",
                     help="--paper-agg with periodic boundaries wherever an "
                          "extent is >= 3 (default: open)")
@@ -216,6 +222,7 @@ def paper_run(args):
     (--paper-agg: g 0.71, J +-0.55, d_pho 16, k=0 Bloch start, t = 100),
     both with fixed-size truncation q_nom.  Reports the wall time of the
     steps, updates/s and q_true / q_nom = |S| / |M| once |M| = q_nom."""
+    import numpy as np
     import torch
     import paper_2603_07341_amd as P
     import workloads as WL
@@ -231,7 +238,10 @@ def paper_run(args):
             args.paper_kind, args.paper_agg, cfg["periodic"][:len(ext)])
     steps = args.paper_steps or cfg["steps"]
     q = cfg["q_nom"]
-    run = dict(WL.run_params(cfg), cap_hint=int(12.5 * q))
+    run = dict(WL.run_params(cfg), cap_hint=int(12.5 * q),
+               krylov_order=args.paper_krylov)
+    if args.paper_krylov:
+        what += ", order-%d Krylov propagator" % args.paper_krylov
     stream = torch.cuda.current_stream()
     sim = P.Sim(P.Model(WL.model_params(cfg)), run, *WL.initial_state(cfg),
                 stream=stream)
@@ -249,6 +259,8 @@ def paper_run(args):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     rec = sim.series(0, steps, stream)
+    if args.paper_save:
+        np.save(args.paper_save, rec)
     sat = rec[:, 8] >= q
     ratio = rec[sat, 7] / rec[sat, 8]
     tail = rec[-100:]
