@@ -83,9 +83,8 @@ def main():
                          "known-size reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU "
-              "path (see DESIGN.md for how the step would shard)",
-              file=sys.stderr)
+        print("bench.py runs on one GPU only: the library drives one GPU "
+              "per process and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

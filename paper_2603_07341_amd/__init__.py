@@ -94,7 +94,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(
-                "libpaces.so is not built; run __graft_entry__.build() or "
+                "libpaces.so is not built; run "
                 "python paper_2603_07341_amd/build.py")
         _lib = C.CDLL(LIB_PATH)
         _lib.paces_last_error.restype = C.c_char_p
