@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(kBlock)
   for (int64_t i = gtid(); i < n; i += gstride()) p[i] = uint32_t(i);
 }
 
-__global__ void k_cap_judge(const uint32_t* ball, int R, int64_t cap,
+__global__ void k_cap_over(const uint32_t* ball, int R, int64_t cap,
                             int* err) {
   if (*err) return;
   bool over = false;
@@ -212,7 +212,7 @@ void cap_check(const DevModel& m, const StepCtl* ctl, const uint64_t* pay,
   k_cap_zero<<<1, kBlock, 0, s>>>(ball, m.R, err);
   const int g = m.R == 1 ? 1 : std::min(grid_for(est), 2048);
   k_cap_count<<<g, kBlock, 0, s>>>(m, ctl, pay, ball, err);
-  k_cap_judge<<<1, kBlock, 0, s>>>(ball, m.R, cap, err);
+  k_cap_over<<<1, kBlock, 0, s>>>(ball, m.R, cap, err);
 }
 
 void count_per_real(const DevModel& m, const uint64_t* pay, int64_t n,
