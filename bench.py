@@ -72,6 +72,10 @@ def main():
     ap.add_argument("--paper-krylov", type=int, default=0, metavar="P",
                     help="--paper-1d / --paper-agg with the order-P Krylov "
                          "propagator instead of the series")
+    ap.add_argument("--paper-taylor", type=int, default=0, metavar="N",
+                    help="--paper-1d / --paper-agg with the truncated Taylor "
+                         "propagator: N > 0 a fixed order, -1 the adaptive "
+                         "degree and substep choice")
     ap.add_argument("--paper-save", default=None, metavar="FILE",
                     help="save the run's per-step records (.npy, fields as "
                          "in the library's observation record)")
@@ -238,9 +242,13 @@ def paper_run(args):
     steps = args.paper_steps or cfg["steps"]
     q = cfg["q_nom"]
     run = dict(WL.run_params(cfg), cap_hint=int(12.5 * q),
-               krylov_order=args.paper_krylov)
+               krylov_order=args.paper_krylov, taylor_order=args.paper_taylor)
     if args.paper_krylov:
         what += ", order-%d Krylov propagator" % args.paper_krylov
+    if args.paper_taylor:
+        what += ", %s Taylor propagator" % (
+            "adaptive" if args.paper_taylor < 0 else
+            "order-%d" % args.paper_taylor)
     stream = torch.cuda.current_stream()
     sim = P.Sim(P.Model(WL.model_params(cfg)), run, *WL.initial_state(cfg),
                 stream=stream)
