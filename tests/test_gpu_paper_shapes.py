@@ -86,3 +86,30 @@ def test_zero_coupling_signal_follows_the_electronic_lines(extent, kind):
     E, f = spectra.electronic_lines(extent, cfg["J"])
     assert np.abs(a - spectra.electronic_signal(E, f, t)).max() < 1e-12
     assert rec[-1, 7] == WL.n_sites(cfg)
+
+
+@pytest.mark.parametrize("prop", [dict(krylov_order=10), dict(taylor_order=-1)],
+                         ids=["krylov10", "taylor"])
+@pytest.mark.parametrize("name,make", CASES[:1] + CASES[3:],
+                         ids=[CASES[0][0], CASES[3][0]])
+def test_paper_shape_alternative_propagators_match_oracle(name, make, prop):
+    # the paper's Krylov comparison runs order 10 on the g = 4 benchmark;
+    # the same stepping from the GPU state as above
+    cfg = make()
+    params = WL.model_params(cfg)
+    run = dict(WL.run_params(cfg), **prop)
+    init = WL.initial_state(cfg)
+    gs = P.Sim(P.Model(params), run, *init)
+    os_ = O.Sim(O.Model(params), run, *init)
+    gs.step(1)
+    os_.step(1)
+    compare(gs, os_, 0.0, "%s step 0" % name)
+    for step in range(1, 5):
+        keys, amps = gs.state()
+        prev = gs.observations()[-1]
+        gs.step(1)
+        os_ = O.Sim(O.Model(params), run, *init)
+        os_.set_state(keys, amps, prev["t"])
+        os_.step(1)
+        compare(gs, os_, prev["mass_total"], "%s step %d" % (name, step))
+        assert gs.observations()[-1]["K"] == os_.observations()[-1]["terms"]
