@@ -270,13 +270,14 @@ def paper_run(args):
         np.save(args.paper_save, rec)
     sat = rec[:, 8] >= q
     ratio = rec[sat, 7] / rec[sat, 8]
-    tail = rec[-100:]
+    tail = rec[sat][-100:]  # the last 100 steps with |M| = q_nom
     return {"workload": "%s, q_nom %d, m_init %d, m %d, dt %g, %d steps" % (
                 what, q, cfg["k_init"], cfg["k"], cfg["dt"], steps),
             "seconds": el, "updates_per_s": float(rec[:, 7].sum()) / el,
             "S_max": int(rec[:, 7].max()),
             "q_true_over_q_nom_mean": float(ratio.mean()) if len(ratio) else None,
-            "q_true_over_q_nom_last100": float((tail[:, 7] / tail[:, 8]).mean()),
+            "q_true_over_q_nom_last100":
+                float((tail[:, 7] / tail[:, 8]).mean()) if len(tail) else None,
             "final_norm2": float(rec[-1, 1]),
             "norm_loss": float(1.0 - rec[-1, 1]), "final_t": float(rec[-1, 0]),
             "terms_per_step": float(rec[:, 9].mean())}
