@@ -10,7 +10,7 @@ import pytest
 
 import paper_2603_07341_amd as P
 from oracle import oracle as O
-from tests.gpu_helpers import check_obs, rel_err, sort_rows
+from tests.gpu_helpers import assert_amps, check_series, rel_err, sort_rows
 import workloads as WL
 
 pytestmark = pytest.mark.gpu
@@ -46,7 +46,7 @@ def compare_to_single(cfg, bs, brec, r, steps, amp_tol):
     sk, sa = sort_rows(*s.state())
     rk, ra = part(bk, ba, breal, r)
     assert np.array_equal(rk, sk), "realization %d: key set" % r
-    assert rel_err(ra, sa) <= amp_tol, ("realization %d" % r, rel_err(ra, sa))
+    assert_amps(ra, sa, amp_tol, steps=steps, what="realization %d" % r)
     srec = s.series()
     # time, counts, K and the Gershgorin interval are exact
     assert np.array_equal(brec[:, r, 0], srec[:, 0])
@@ -104,9 +104,9 @@ def test_batched_matches_oracle(name, R, steps, over, tol):
         ok, oa = os_.state()
         rk, ra = part(bk, ba, breal, r)
         assert np.array_equal(rk, ok)
-        assert rel_err(ra, oa) <= tol
-        for g, o in zip(bs.observations(r), os_.observations()):
-            check_obs(g, o, tol, width=o["E_max"] - o["E_min"])
+        assert_amps(ra, oa, tol, steps=steps)
+        check_series(bs.observations(r), os_.observations(), tol,
+                     cfg["theta"], len(exc))
 
 
 def test_identical_realizations_give_identical_states():

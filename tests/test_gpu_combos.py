@@ -7,7 +7,8 @@ import pytest
 
 import paper_2603_07341_amd as P
 from oracle import oracle as O
-from tests.gpu_helpers import assert_same_set, check_obs, rel_err, sort_rows
+from tests.gpu_helpers import (assert_amps, assert_same_set, check_obs,
+                               dropped, sort_rows)
 import workloads as WL
 
 pytestmark = pytest.mark.gpu
@@ -26,25 +27,28 @@ def pair(run_over, **over):
     return cfg, P.Sim(P.Model(p), run, *init), O.Sim(O.Model(p), run, *init)
 
 
-def check(gs, os_, tol=1e-10, series_K=True):
+def check(gs, os_, prev, steps, tol=1e-10):
+    """prev: the oracle's state before the step; steps: steps run."""
     for which in (O.SET_M, O.SET_S):
         assert_same_set(gs.get_set(which), os_.get_set(which), "set %d" % which)
     gk, ga = sort_rows(*gs.state())
     ok, oa = os_.state()
     assert np.array_equal(gk, ok)
-    assert rel_err(ga, oa) <= tol
+    assert_amps(ga, oa, tol, steps=steps)
     go, oo = gs.observations()[-1], os_.observations()[-1]
-    check_obs(go, oo, tol, width=oo["E_max"] - oo["E_min"])
+    check_obs(go, oo, tol, width=oo["E_max"] - oo["E_min"],
+              drop=dropped(prev[0], prev[1], ok), steps_before=steps - 1)
 
 
 @pytest.mark.parametrize("prop", PROPAGATORS)
 @pytest.mark.parametrize("trunc", [dict(max_states=400), dict(q_nom=60)])
 def test_truncation_rules_with_every_propagator(prop, trunc):
     cfg, gs, os_ = pair(dict(prop, **trunc))
-    for _ in range(10):
+    for i in range(10):
+        prev = os_.state()
         gs.step(1)
         os_.step(1)
-        check(gs, os_)
+        check(gs, os_, prev, i + 1)
         if "max_states" in trunc:
             assert gs.observations()[-1]["n_S"] <= trunc["max_states"]
 
@@ -58,7 +62,8 @@ def test_model_switch_with_every_propagator(prop):
     gm2, om2 = P.Model(q), O.Model(q)
     gs.set_model(gm2)
     os_.set_model(om2)
-    for _ in range(4):
+    for i in range(4):
+        prev = os_.state()
         gs.step(1)
         os_.step(1)
-        check(gs, os_)
+        check(gs, os_, prev, 5 + i)

@@ -17,7 +17,8 @@ import pytest
 
 import paper_2603_07341_amd as P
 from oracle import oracle as O
-from tests.gpu_helpers import assert_same_set, check_obs, rel_err, sort_rows
+from tests.gpu_helpers import (assert_amps, assert_same_set, check_obs,
+                               dropped, sort_rows)
 import workloads as WL
 
 pytestmark = pytest.mark.gpu
@@ -40,10 +41,11 @@ def gpu_result(gs):
     return out
 
 
-def compare_step(res, gobs, prev_mass_total, os_, tol, realization=0):
+def compare_step(res, gobs, prev_mass_total, os_, tol, prev, realization=0):
     """The GPU result of one realization against the oracle's step from the
-    same state.  The oracle sim starts there, so its cumulative discarded
-    weight is shifted by the GPU's total before the step."""
+    same state prev = (keys, amps).  The oracle sim starts there, so its
+    cumulative discarded weight is shifted by the GPU's total before the
+    step."""
     for which in (O.SET_M, O.SET_S):
         g, greal = res[which]
         assert_same_set(g[greal == realization], os_.get_set(which),
@@ -53,10 +55,11 @@ def compare_step(res, gobs, prev_mass_total, os_, tol, realization=0):
     gk, ga = sort_rows(k[sel], a[sel])
     ok, oa = os_.state()
     assert np.array_equal(gk, ok)
-    assert rel_err(ga, oa) <= tol, rel_err(ga, oa)
+    assert_amps(ga, oa, tol)
     oo = dict(os_.observations()[-1])
     oo["mass_total"] += prev_mass_total
-    check_obs(gobs, oo, tol, width=oo["E_max"] - oo["E_min"])
+    check_obs(gobs, oo, tol, width=oo["E_max"] - oo["E_min"],
+              drop=dropped(prev[0], prev[1], ok))
     return len(gk)
 
 
@@ -74,7 +77,7 @@ def test_ring16_bench_window_step_matches_oracle():
     gs.profile(False)
     os_ = oracle_step_from(cfg, params, keys, amps, prev["t"])
     n = compare_step(gpu_result(gs), gs.observations()[-1],
-                     prev["mass_total"], os_, 1e-10)
+                     prev["mass_total"], os_, 1e-10, (keys, amps))
     assert n > 4_000_000
     # the Krylov form: an order-10 step from the same state
     gk = P.Sim(P.Model(params), dict(WL.run_params(cfg), krylov_order=10),
@@ -83,7 +86,8 @@ def test_ring16_bench_window_step_matches_oracle():
     gk.step(1)
     os_ = oracle_step_from(cfg, params, keys, amps, prev["t"],
                            krylov_order=10)
-    compare_step(gpu_result(gk), gk.observations()[-1], 0.0, os_, 1e-10)
+    compare_step(gpu_result(gk), gk.observations()[-1], 0.0, os_, 1e-10,
+                 (keys, amps))
 
 
 def test_sq6x6_batched_full_width_step_matches_oracle():
@@ -102,4 +106,4 @@ def test_sq6x6_batched_full_width_step_matches_oracle():
         os_ = oracle_step_from(cfg, WL.model_params(cfg, r), keys[sel],
                                amps[sel], rec[-1, r, 0])
         compare_step(res, bs.observations(realization=r)[-1], rec[-1, r, 6],
-                     os_, 1e-5, realization=r)
+                     os_, 1e-5, (keys[sel], amps[sel]), realization=r)

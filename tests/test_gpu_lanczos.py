@@ -14,8 +14,9 @@ import pytest
 
 import paper_2603_07341_amd as P
 from oracle import oracle as O
-from tests.gpu_helpers import (assert_same_set, check_obs, oracle_state,
-                               rel_err, sort_rows)
+from tests.gpu_helpers import (assert_amps, assert_same_set, check_obs,
+                               dropped, oracle_state, rel_err,
+                               sort_rows)
 import workloads as WL
 
 pytestmark = pytest.mark.gpu
@@ -30,15 +31,19 @@ def pair(name, order, **over):
     return cfg, P.Sim(P.Model(params), run, *init), O.Sim(O.Model(params), run, *init)
 
 
-def check_step(gs, os_, tol):
+def check_step(gs, os_, tol, prev=None, steps=1):
+    """prev: the oracle's state the step started from (keys, amps), for
+    the rows it dropped; steps: steps since the common state."""
     for which in (O.SET_M, O.SET_S):
         assert_same_set(gs.get_set(which), os_.get_set(which), "set %d" % which)
     gk, ga = sort_rows(*gs.state())
     ok, oa = os_.state()
     assert np.array_equal(gk, ok)
-    assert rel_err(ga, oa) <= tol, rel_err(ga, oa)
+    assert_amps(ga, oa, tol, steps=steps)
     go, oo = gs.observations()[-1], os_.observations()[-1]
-    check_obs(go, oo, tol, width=oo["E_max"] - oo["E_min"])
+    drop = dropped(prev[0], prev[1], ok) if prev is not None else None
+    check_obs(go, oo, tol, width=oo["E_max"] - oo["E_min"], drop=drop,
+              steps_before=steps - 1)
     assert go["K"] == oo["terms"]
     for f in ("E_min", "E_max"):
         assert go[f] == pytest.approx(oo[f], rel=tol, abs=1e-12), f
@@ -55,7 +60,7 @@ def test_single_step_parity(name, steps, order):
     os_.set_state(keys, amps, t)
     gs.step(1)
     os_.step(1)
-    check_step(gs, os_, 1e-10)
+    check_step(gs, os_, 1e-10, prev=(keys, amps))
     assert gs.observations()[-1]["K"] == order + 1
 
 
@@ -63,10 +68,11 @@ def test_single_step_parity(name, steps, order):
 def test_multi_step_runs_match_oracle(order):
     cfg, gs, os_ = pair("ring12", order, extent=[6, 1, 1], cutoff=[4],
                         theta=1e-6)
-    for _ in range(15):
+    for i in range(15):
+        prev = os_.state()
         gs.step(1)
         os_.step(1)
-        check_step(gs, os_, 1e-10)
+        check_step(gs, os_, 1e-10, prev=prev, steps=i + 1)
 
 
 @pytest.mark.parametrize("name,steps", [("ring16", 12), ("sq6x6", 4)])
@@ -78,7 +84,7 @@ def test_single_step_parity_fp32(name, steps):
     os_.set_state(keys, amps, t)
     gs.step(1)
     os_.step(1)
-    check_step(gs, os_, 1e-5)
+    check_step(gs, os_, 1e-5, prev=(keys, amps))
 
 
 def test_invariant_space_equals_series_propagator():
@@ -139,7 +145,7 @@ def test_batched_realizations_match_single_runs():
         sel = breal == r
         rk, ra = sort_rows(bk[sel], ba[sel])
         assert np.array_equal(rk, sk), r
-        assert rel_err(ra, sa) <= 1e-12, r
+        assert_amps(ra, sa, 1e-12, steps=steps, what="realization %d" % r)
         srec = s.series()
         assert np.array_equal(brec[:, r, 0], srec[:, 0])
         assert np.array_equal(brec[:, r, 7:10], srec[:, 7:10])  # n_S, n_M, K

@@ -19,7 +19,8 @@ import pytest
 
 import paper_2603_07341_amd as P
 from oracle import oracle as O
-from tests.gpu_helpers import assert_same_set, check_obs, rel_err, sort_rows
+from tests.gpu_helpers import (assert_amps, assert_same_set, check_obs,
+                               dropped, sort_rows)
 import workloads as WL
 
 pytestmark = pytest.mark.gpu
@@ -32,18 +33,21 @@ CASES = [
 ]
 
 
-def compare(gs, os_, prev_mass_total, what):
+def compare(gs, os_, prev_mass_total, what, prev=None):
+    """One step from a common state; prev: that state (keys, amps), or
+    None for the first step (nothing dropped)."""
     for which in (O.SET_M, O.SET_S):
         assert_same_set(gs.get_set(which), os_.get_set(which),
                         "%s set %d" % (what, which))
     gk, ga = sort_rows(*gs.state())
     ok, oa = os_.state()
     assert np.array_equal(gk, ok), what
-    assert rel_err(ga, oa) <= 1e-10, (what, rel_err(ga, oa))
+    assert_amps(ga, oa, 1e-10, what=what)
     go, oo = gs.observations()[-1], dict(os_.observations()[-1])
     oo["mass_total"] += prev_mass_total
     assert go["n_S"] == oo["n_S"] and go["n_M"] == oo["n_M"], what
-    check_obs(go, oo, 1e-10, width=oo["E_max"] - oo["E_min"])
+    drop = dropped(prev[0], prev[1], ok) if prev is not None else (0, 0.0)
+    check_obs(go, oo, 1e-10, width=oo["E_max"] - oo["E_min"], drop=drop)
 
 
 @pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
@@ -64,7 +68,8 @@ def test_paper_shape_steps_match_oracle(name, make):
         os_ = O.Sim(O.Model(params), run, *init)
         os_.set_state(keys, amps, prev["t"])
         os_.step(1)
-        compare(gs, os_, prev["mass_total"], "%s step %d" % (name, step))
+        compare(gs, os_, prev["mass_total"], "%s step %d" % (name, step),
+                prev=(keys, amps))
     # the truncation is active by the last step
     assert gs.observations()[-1]["n_M"] == cfg["q_nom"]
 
@@ -111,5 +116,6 @@ def test_paper_shape_alternative_propagators_match_oracle(name, make, prop):
         os_ = O.Sim(O.Model(params), run, *init)
         os_.set_state(keys, amps, prev["t"])
         os_.step(1)
-        compare(gs, os_, prev["mass_total"], "%s step %d" % (name, step))
+        compare(gs, os_, prev["mass_total"], "%s step %d" % (name, step),
+                prev=(keys, amps))
         assert gs.observations()[-1]["K"] == os_.observations()[-1]["terms"]

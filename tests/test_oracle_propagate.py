@@ -217,3 +217,91 @@ def test_piecewise_constant_hamiltonian_matches_dense_products():
     exc, occ = ma.unpack(keys)
     idx = [brute.state_index(pa, int(j), list(o)) for j, o in zip(exc, occ)]
     assert np.max(np.abs(amps - ref[idx])) <= 1e-12
+
+
+def _differs(pop, ref, tol):
+    return np.max(np.abs(pop - ref)) > tol
+
+
+def test_populations_match_dense_expm_per_site():
+    """P(j) of Eq. (RMSD) (the exciton population of site j) against the
+    dense-expm state summed over the phonon configurations of each site.
+    Site energies break the ring's reflection symmetry, so a permuted,
+    shifted or mirrored binning fails."""
+    cfg = WL.CONFIGS["ring4"]
+    p = dict(WL.model_params(cfg), eps=[0.0, 0.35, -0.2, 0.15])
+    m = O.Model(p)
+    exc, occ, coef = WL.initial_state(cfg)
+    steps = 40
+    H, exact = ring4_exact(p, steps, 0.05)
+    s = O.Sim(m, dict(WL.run_params(cfg), dt=0.05, theta=0.0, k=4,
+                      k_init=60), exc, occ, coef)
+    s.step(steps)
+    obs = s.observations()
+    N = 4
+    for i in (0, 9, 19, 39):
+        ref = (np.abs(exact[i]) ** 2).reshape(N, -1).sum(axis=1)
+        pop = obs[i]["pop"]
+        assert np.max(np.abs(pop - ref)) <= 1e-12, (i, pop, ref)
+    # the check separates every other assignment of bins to sites
+    ref = (np.abs(exact[-1]) ** 2).reshape(N, -1).sum(axis=1)
+    pop = obs[-1]["pop"]
+    for perm in [np.roll(np.arange(N), 1), np.roll(np.arange(N), -1),
+                 np.array([0, 3, 2, 1]), np.arange(N)[::-1]]:
+        assert _differs(pop[perm], ref, 1e-6), perm
+
+
+def test_populations_match_free_exciton_closed_form():
+    """P(j) = |c_j(t)|^2 for g = 0 on a ring, from a start spread over two
+    sites with a relative phase (no reflection symmetry):
+    c_j(t) = sum_{j0} c_{j0} N^-1 sum_q exp(i q (j - j0)) exp(-i (eps + 2 J
+    cos q) t)."""
+    N, eps, J = 7, -0.2, 0.9
+    starts = [(2, 0.6), (3, 0.8j)]
+    p = make(ndim=1, extent=[N], periodic=[1], cutoff=[1], g=(0.0,), J=(J,),
+             eps=[eps] * N)
+    m = O.Model(p)
+    coef = []
+    for _, c in starts:
+        coef += [c.real, c.imag] if isinstance(c, complex) else [c, 0.0]
+    s = O.Sim(m, {"dt": 0.03, "k": 4, "k_init": 4, "theta": 0.0},
+              [j for j, _ in starts], [0] * (N * len(starts)), coef)
+    s.step(50)
+    qs = 2 * np.pi * np.arange(N) / N
+    for o in s.observations()[9::10]:
+        t = o["t"]
+        ref = np.zeros(N)
+        for j in range(N):
+            c = sum(c0 * np.sum(np.exp(1j * qs * (j - j0)) *
+                                np.exp(-1j * (eps + 2 * J * np.cos(qs)) * t)) / N
+                    for j0, c0 in starts)
+            ref[j] = abs(c) ** 2
+        assert np.max(np.abs(o["pop"] - ref)) <= 1e-12, (t, o["pop"], ref)
+        for perm in [np.roll(np.arange(N), 1), np.roll(np.arange(N), -1),
+                     (5 - np.arange(N)) % N]:
+            assert _differs(o["pop"][perm], ref, 1e-4), (t, perm)
+
+
+def test_gershgorin_bounds_from_dense_restriction():
+    """E_min / E_max: Gershgorin discs of the dense Hamiltonian restricted to
+    the step's set (rows and columns of the states in S), padded by 1e-12
+    (|E_max| + |E_min|)."""
+    cfg = WL.CONFIGS["ring4"]
+    p = dict(WL.model_params(cfg), eps=[0.0, 0.35, -0.2, 0.15])
+    m = O.Model(p)
+    exc, occ, coef = WL.initial_state(cfg)
+    s = O.Sim(m, WL.run_params(cfg), exc, occ, coef)
+    Hd = brute.dense_hamiltonian(p)
+    for step in range(6):
+        s.step(1)
+        keys, _ = s.state()
+        e, o = m.unpack(keys)
+        idx = [brute.state_index(p, int(e[i]), o[i]) for i in range(len(e))]
+        Hs = Hd[np.ix_(idx, idx)]
+        rad = np.abs(Hs).sum(axis=1) - np.abs(np.diag(Hs))
+        lo = float(np.min(np.diag(Hs) - rad))
+        hi = float(np.max(np.diag(Hs) + rad))
+        pad = 1e-12 * (abs(hi) + abs(lo))
+        ob = s.observations()[-1]
+        assert abs(ob["E_min"] - (lo - pad)) <= 1e-13 * (abs(lo) + 1), step
+        assert abs(ob["E_max"] - (hi + pad)) <= 1e-13 * (abs(hi) + 1), step
