@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define PACES_ABI_VERSION 10
+#define PACES_ABI_VERSION 11
 
 typedef enum {
   PACES_OK = 0,
@@ -226,6 +226,55 @@ paces_status paces_free_sim(paces_sim* s);
  * every step's records are appended to it as CSV lines
  * "step,realization,<12 fields>,<N populations>". */
 paces_status paces_step(paces_sim* s, int64_t n_steps, void* hip_stream);
+/* One stage of a step, for callers that drive or inspect the stages
+ * separately (paper: Sec. "Formal operator representation and notes on
+ * parallelization" splits the step into these operations).  stage is
+ * PACES_STAGE_SELECT .. PACES_STAGE_OBSERVE; a step is the six stages in
+ * that order, and running them gives exactly what paces_step(s, 1) gives
+ * (same sets, amplitudes and record).  SELECT starts a new staged step
+ * (abandoning one in progress); any other stage out of order is
+ * PACES_E_STATE.  The current state is replaced only when OBSERVE completes,
+ * so an abandoned staged step leaves it intact; paces_step and
+ * paces_set_state abandon it too.
+ *   SELECT     M from the current state (threshold, state cap or q_nom)
+ *   EXPAND     the new set: k rounds of neighbour generation merged in the
+ *              hash table, the ELL columns of H_eff; synchronises, and
+ *              repeats SELECT + EXPAND with more room (or a cut selection
+ *              under a state cap) until the set fits
+ *   TRANSFER   phi = psi restricted to the new set, the discarded weight
+ *   BUILD      Gershgorin bounds and the propagator's coefficients or plan
+ *   PROPAGATE  psi' = exp(-i H_eff dt) phi; synchronises first to size the
+ *              series from the coefficients
+ *   OBSERVE    observables into the record; synchronises and completes the
+ *              step
+ * With theta = 0 and k = 0, a state loaded by paces_set_state is propagated
+ * on exactly its own set (M = S, no new states): exp(-i H_S dt) applied to
+ * the given amplitudes.  Device errors are returned by the stage that
+ * synchronises after them. */
+paces_status paces_run_stage(paces_sim* s, int32_t stage, void* hip_stream);
+
+/* Propagation of a state given on its own set, without a sim: psi =
+ * exp(-i H_S dt) phi, H_S the Hamiltonian of Eq. (holstein) restricted to
+ * the n states of dev_keys (Eq. (H_eff) with S the given set), computed as
+ * a step's PROPAGATE stage does: ELL columns by hash lookup, padded
+ * Gershgorin bounds, Chebyshev series by Clenshaw's recurrence with the
+ * step's default tail tolerance (App. "The action of the exponential of a
+ * sparse matrix" for the series approach).
+ *   dev_keys  device uint64 [n][W], canonical keys (as paces_pack_keys
+ *             makes them); distinct, every field in range
+ *   dev_phi   device complex128 [n] (interleaved re, im), row order of
+ *             dev_keys
+ *   dev_psi   device complex128 [n] output, same order; must not alias
+ *             dev_phi
+ * Models with one realization only (else PACES_E_UNSUPPORTED).  A key out
+ * of range or repeated is found on the device and returns PACES_E_ARG.
+ * Work memory (about 60-120 bytes per row) comes from the library's
+ * allocator for the call.  Runs on hip_stream and synchronises it before
+ * returning. */
+paces_status paces_expmv(const paces_model* m, int64_t n, const void* dev_keys,
+                         const void* dev_phi, double dt, void* dev_psi,
+                         void* hip_stream);
+
 /* Piecewise-constant H(t): later steps of the sim use model m, which must
  * have the sim's shape (lattice, modes, cutoffs, realizations); only J,
  * g, omega and eps may differ.  The caller keeps m alive while the sim
@@ -307,6 +356,11 @@ paces_status paces_profile_enable(paces_sim* s, int32_t level);
 paces_status paces_profile_get(paces_sim* s, paces_profile* out,
                                void* hip_stream);
 paces_status paces_profile_reset(paces_sim* s);
+/* Enqueue one empty kernel dispatch (k_mark) on the stream: in kernel
+ * traces and hardware-counter runs, where event markers are not recorded,
+ * a pair of marks brackets a region of interest in dispatch order.  tag is
+ * not recorded.  Asynchronous. */
+paces_status paces_profile_mark(int32_t tag, void* hip_stream);
 
 /* Form (3): adjoint gradient.  For a real loss L of the autocorrelation
  * a_s = <psi0|psi_s>, s = 0..n (s = 0 the initial state), the gradient
@@ -325,6 +379,12 @@ int32_t paces_num_params(const paces_model* m);
 paces_status paces_adjoint_forward(paces_sim* s, int64_t n_steps,
                                    int32_t ckpt_every, double* a,
                                    void* hip_stream);
+/* As paces_adjoint_forward, with a_s written to device memory dev_a
+ * (complex128 [n_steps + 1], interleaved re, im) on the stream, e.g. a
+ * torch tensor; the host never sees the series.  Synchronises. */
+paces_status paces_adjoint_forward_dev(paces_sim* s, int64_t n_steps,
+                                       int32_t ckpt_every, void* dev_a,
+                                       void* hip_stream);
 /* Replay the recorded run on its frozen sets with model m (NULL: the
  * sim's own; otherwise a model of the same shape, e.g. with perturbed
  * parameters) and return a[2*(n+1)].  The sim's state is left as after the
@@ -339,6 +399,12 @@ paces_status paces_adjoint_replay(paces_sim* s, const paces_model* m,
  * Synchronises. */
 paces_status paces_adjoint_backward(paces_sim* s, const double* gbar,
                                     double* grad, void* hip_stream);
+
+/* As paces_adjoint_backward, with gbar (complex128 [n + 1]) read from and
+ * the gradient (f64 [paces_num_params]) written to device memory.
+ * Synchronises. */
+paces_status paces_adjoint_backward_dev(paces_sim* s, const void* dev_gbar,
+                                        void* dev_grad, void* hip_stream);
 
 /* Launch tuning.  Results do not depend on it: per-key amplitudes, sets
  * and counts are identical for every setting (sums only to rounding of

@@ -186,6 +186,12 @@ class Sim:
         _check(lib().orc_sim_set_state(self.h, C.c_int64(n), _p(keys, C.c_uint64),
                                        _p(amps, C.c_double), C.c_double(t)))
 
+    def set_prev_counts(self, nS, nM):
+        """|S| and |M| of the step that led to the loaded state (the state
+        cap's q rule)."""
+        _check(lib().orc_sim_set_prev_counts(self.h, C.c_int64(int(nS)),
+                                             C.c_int64(int(nM))))
+
     def get_set(self, which, rnd=0):
         n = C.c_int64()
         _check(lib().orc_sim_get_set(self.h, C.c_int32(which), C.c_int32(rnd),
@@ -261,6 +267,16 @@ def lanczos(rowptr, cols, vals, dt, order, v):
     d = dim.value
     B = basis.view(np.complex128).reshape(order + 1, n)[:d]
     return vout.view(np.complex128), B, alpha[:d], beta[:max(d, 1)], tuple(er)
+
+
+def set_threads(n):
+    """Threads of the oracle's row loops (timing only)."""
+    _check(lib().orc_set_threads(C.c_int32(int(n))))
+
+
+def threads():
+    lib().orc_threads.restype = C.c_int32
+    return int(lib().orc_threads())
 
 
 def taylor_theta(m):

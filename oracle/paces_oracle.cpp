@@ -35,6 +35,8 @@
 #include <string>
 #include <vector>
 
+#include <omp.h>
+
 namespace {
 
 using cplx = std::complex<double>;
@@ -1171,6 +1173,14 @@ extern "C" {
 
 const char* orc_last_error(void) { return g_err.c_str(); }
 
+// Threads of the row loops (results do not depend on them).
+int orc_set_threads(int32_t n) {
+  if (n < 1) return 1;
+  omp_set_num_threads(n);
+  return 0;
+}
+int32_t orc_threads(void) { return omp_get_max_threads(); }
+
 int orc_pack_fields(int32_t nfields, const int32_t* widths,
                     const uint64_t* values, int32_t W, uint64_t* out) {
   if (nfields < 0 || W < 1) return fail("bad arguments");
@@ -1405,6 +1415,17 @@ int orc_sim_set_state(void* sp, int64_t n, const uint64_t* keys,
   s->psi = psi;
   s->t = t;
   s->fresh = false;
+  return 0;
+}
+
+// Counts of the step before a loaded state (the state cap's q rule, App.
+// "How to weight states for truncation" as read for a fixed cap): as if
+// the state had been reached by a step with these |S| and |M|.
+int orc_sim_set_prev_counts(void* sp, int64_t nS, int64_t nM) {
+  Sim* s = static_cast<Sim*>(sp);
+  if (!s || nS < 0 || nM < 0) return fail("bad arguments");
+  s->prev_nS = nS;
+  s->prev_nM = nM;
   return 0;
 }
 

@@ -79,6 +79,10 @@ const char* orc_last_error(void);
 /* Generic bit-field packer of the compression appendix: fields given most
  * significant first, packed without gaps and right-aligned in W 64-bit
  * words, word 0 most significant. */
+/* Threads of the row loops (timing only; results do not depend on it). */
+int orc_set_threads(int32_t n);
+int32_t orc_threads(void);
+
 int orc_pack_fields(int32_t nfields, const int32_t* widths,
                     const uint64_t* values, int32_t W, uint64_t* out);
 
@@ -111,6 +115,9 @@ int orc_sim_set_model(void* s, const void* m);
  * next step selects from it with the threshold and neighbour order k. */
 int orc_sim_set_state(void* s, int64_t n, const uint64_t* keys,
                       const double* amps, double t);
+/* Counts |S|, |M| of the step that led to the loaded state, used by the
+ * state cap's q rule as if that step had been run here. */
+int orc_sim_set_prev_counts(void* sim, int64_t nS, int64_t nM);
 int orc_sim_size(const void* s, int64_t* nS);
 /* Current state as sorted keys and interleaved (re, im) amplitudes. */
 int orc_sim_get_state(const void* s, uint64_t* keys, double* amps);

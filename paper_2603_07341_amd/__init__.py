@@ -39,6 +39,8 @@ EXPORTS = [
     "paces_autotune", "paces_num_params", "paces_adjoint_forward",
     "paces_adjoint_replay", "paces_adjoint_backward", "paces_set_allocator",
     "paces_model_key_words", "paces_series_field", "paces_set_model",
+    "paces_run_stage", "paces_adjoint_forward_dev", "paces_adjoint_backward_dev",
+    "paces_profile_mark", "paces_expmv",
 ]
 
 
@@ -190,6 +192,33 @@ class Model:
             _lib.paces_free_model(self.h)
             self.h = None
 
+    def expmv(self, keys, phi, dt, out=None, stream=None):
+        """psi = exp(-i H_S dt) phi on the set S of the given canonical
+        keys (paces_expmv).  keys: int64 cuda tensor [n, W] holding the
+        uint64 words; phi: complex128 cuda tensor [n]; returns psi (a new
+        tensor, or `out`)."""
+        return self._expmv(lib().paces_expmv, keys, phi, dt, out, stream)
+
+    def _expmv(self, fn, keys, phi, dt, out, stream):
+        n = phi.numel()
+        if keys.dtype != torch.int64 or not keys.is_cuda or \
+                not keys.is_contiguous() or keys.numel() != n * self.W:
+            raise ValueError("keys must be a contiguous int64 cuda tensor of "
+                             "n * W words")
+        if phi.dtype != torch.complex128 or not phi.is_cuda or \
+                not phi.is_contiguous():
+            raise ValueError("phi must be a contiguous complex128 cuda tensor")
+        if out is None:
+            out = torch.empty_like(phi)
+        elif out.dtype != torch.complex128 or not out.is_cuda or \
+                not out.is_contiguous() or out.numel() != n:
+            raise ValueError("out must be a contiguous complex128 cuda tensor "
+                             "of n entries")
+        _check(fn(self.h, C.c_int64(n), C.c_void_p(keys.data_ptr()),
+                  C.c_void_p(phi.data_ptr()), C.c_double(dt),
+                  C.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
     def pack(self, exc, occ):
         exc = np.ascontiguousarray(exc, dtype=np.int32)
         occ = np.ascontiguousarray(occ, dtype=np.uint16)
@@ -256,6 +285,12 @@ class Sim:
 
     def step(self, n=1, stream=None):
         _check(lib().paces_step(self.h, C.c_int64(n), _stream(stream)))
+
+    def run_stage(self, stage, stream=None):
+        """One stage of a step: a name of STAGES[:6] or its index; the six
+        in order make one step."""
+        idx = STAGES.index(stage) if isinstance(stage, str) else int(stage)
+        _check(lib().paces_run_stage(self.h, C.c_int32(idx), _stream(stream)))
 
     def observe(self, realization=0, stream=None):
         o = _Obs()
@@ -422,6 +457,36 @@ class Sim:
         self._adj_steps = steps
         return a.view(np.complex128)
 
+    def adjoint_forward_dev(self, steps, out, ckpt_every=50, stream=None):
+        """As adjoint_forward, writing a into `out` (a contiguous
+        complex128 device tensor of steps + 1 entries)."""
+        if out.dtype != torch.complex128 or not out.is_cuda or \
+                not out.is_contiguous() or out.numel() != steps + 1:
+            raise ValueError("out must be a contiguous complex128 cuda tensor "
+                             "of steps + 1 entries")
+        _check(lib().paces_adjoint_forward_dev(
+            self.h, C.c_int64(steps), C.c_int32(ckpt_every),
+            C.c_void_p(out.data_ptr()), _stream(stream)))
+        self._adj_steps = steps
+        return out
+
+    def adjoint_backward_dev(self, gbar, out, stream=None):
+        """As adjoint_backward with gbar (complex128 cuda tensor) and the
+        gradient `out` (float64 cuda tensor of n_params entries) on the
+        device."""
+        if gbar.dtype != torch.complex128 or not gbar.is_cuda or \
+                not gbar.is_contiguous() or gbar.numel() != self._adj_steps + 1:
+            raise ValueError("gbar must be a contiguous complex128 cuda tensor "
+                             "with one entry per recorded a_s")
+        if out.dtype != torch.float64 or not out.is_cuda or \
+                not out.is_contiguous() or out.numel() != self.model.n_params:
+            raise ValueError("out must be a contiguous float64 cuda tensor of "
+                             "n_params entries")
+        _check(lib().paces_adjoint_backward_dev(
+            self.h, C.c_void_p(gbar.data_ptr()), C.c_void_p(out.data_ptr()),
+            _stream(stream)))
+        return out
+
     def adjoint_replay(self, model=None, stream=None):
         """a[s] of the recorded run replayed on its frozen sets with
         `model` (default: the sim's own)."""
@@ -440,6 +505,12 @@ class Sim:
         _check(lib().paces_adjoint_backward(self.h, _p(gb, C.c_double),
                                             _p(g, C.c_double), _stream(stream)))
         return g
+
+
+def profile_mark(tag=0, stream=None):
+    """One empty kernel dispatch (k_mark) on the stream, a marker for
+    kernel traces and counter runs."""
+    _check(lib().paces_profile_mark(C.c_int32(tag), _stream(stream)))
 
 
 def taylor_theta(m):
@@ -471,10 +542,13 @@ def params_with_theta(params, theta):
 if torch is not None:
     class AutocorrFn(torch.autograd.Function):
         """a = AutocorrFn.apply(theta, params, run, init, steps, ckpt_every):
-        the autocorrelation a_s = <psi0|psi_s>, s = 0..steps (complex128,
-        on the CPU), of a run with model parameters theta (float64 [P]:
-        J per axis, g and omega per mode, eps per site).  Backward is the
-        adjoint gradient on the forward run's frozen sets."""
+        the autocorrelation a_s = <psi0|psi_s>, s = 0..steps (complex128 on
+        the current GPU), of a run with model parameters theta (float64
+        [P]: J per axis, g and omega per mode, eps per site).  Backward is
+        the adjoint gradient on the forward run's frozen sets; a, the
+        incoming gradient and dL/dtheta stay in device memory (the
+        gradient is returned on theta's device).  The model tables are
+        built on the host from theta's values."""
 
         @staticmethod
         def forward(ctx, theta, params, run, init, steps, ckpt_every=50):
@@ -482,13 +556,17 @@ if torch is not None:
             model = Model(p)
             exc, occ, coef = init
             sim = Sim(model, run, exc, occ, coef)
-            a = sim.adjoint_forward(steps, ckpt_every)
-            ctx.sim, ctx.model = sim, model
-            return torch.from_numpy(a.copy())
+            a = torch.empty(steps + 1, dtype=torch.complex128, device="cuda")
+            sim.adjoint_forward_dev(steps, a, ckpt_every)
+            ctx.sim, ctx.model, ctx.theta_device = sim, model, theta.device
+            return a
 
         @staticmethod
         def backward(ctx, grad_a):
             # torch passes 2 dL/d conj(a) for a complex output
-            gbar = grad_a.detach().cpu().numpy().astype(np.complex128) / 2
-            g = ctx.sim.adjoint_backward(gbar)
-            return (torch.from_numpy(g), None, None, None, None, None)
+            gbar = (grad_a.detach().to(device="cuda", dtype=torch.complex128)
+                    / 2).contiguous()
+            g = torch.empty(ctx.model.n_params, dtype=torch.float64,
+                            device="cuda")
+            ctx.sim.adjoint_backward_dev(gbar, g)
+            return (g.to(ctx.theta_device), None, None, None, None, None)

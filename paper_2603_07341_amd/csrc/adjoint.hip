@@ -284,8 +284,9 @@ __global__ void __launch_bounds__(kBlock)
 
 __global__ void __launch_bounds__(kBlock)
     k_adj_add_psi0(int64_t n0, const int32_t* p0, const double* amps0,
-                   double gr, double gi, double2* lam, const int* err) {
+                   const double* g, double2* lam, const int* err) {
   if (*err) return;
+  const double gr = g[0], gi = g[1];
   for (int64_t q = gtid(); q < n0; q += gstride()) {
     const int32_t r = p0[q];
     if (r < 0) continue;
@@ -378,11 +379,9 @@ void adj_back(int64_t n, const int32_t* tmap, const double2* mu,
 }
 
 void adj_add_psi0(int64_t n0, const int32_t* p0, const double* amps0,
-                  double g_re, double g_im, double2* lam, int* err,
-                  hipStream_t s) {
+                  const double* g, double2* lam, int* err, hipStream_t s) {
   if (n0 <= 0) return;
-  k_adj_add_psi0<<<grid_for(n0), kBlock, 0, s>>>(n0, p0, amps0, g_re, g_im,
-                                                 lam, err);
+  k_adj_add_psi0<<<grid_for(n0), kBlock, 0, s>>>(n0, p0, amps0, g, lam, err);
 }
 
 void adj_permute(const DevModel& m, int Wi, const uint64_t* keys_in,

@@ -55,8 +55,7 @@ void adj_back(int64_t n, const int32_t* tmap, const double2* mu,
               double2* lam, int* err, hipStream_t s);
 // lam[p0[q]] += g * psi0_q for q < n0 (rows -1 skipped).
 void adj_add_psi0(int64_t n0, const int32_t* p0, const double* amps0,
-                  double g_re, double g_im, double2* lam, int* err,
-                  hipStream_t s);
+                  const double* g, double2* lam, int* err, hipStream_t s);
 // out[row of key i in the table] = in[i] for the n keys of `keys_in`.
 void adj_permute(const DevModel& m, int Wi, const uint64_t* keys_in,
                  int64_t n, const uint64_t* table, uint64_t mask,

@@ -39,6 +39,8 @@ enum : int {
   kErrTerms = 8,       // series longer than the allowed maximum
   kErrNeedTerms = 16,  // more series launches needed than enqueued
   kErrCap = 32,        // a realization's new set exceeds the state cap
+  kErrChunks = 64,     // a round's frontier needs more candidate chunks
+  kErrInput = 128,     // a given key is out of range or repeated
 };
 
 // Model constants passed by value to every kernel.

@@ -48,6 +48,64 @@ __global__ void __launch_bounds__(kBlock)
   for (int64_t i = gtid(); i < n; i += gstride()) p[i] = v;
 }
 
+// A dispatch that does nothing: a marker that kernel traces and counter
+// runs show in stream order.
+__global__ void k_mark(int tag) { (void)tag; }
+
+// ---- a given set of states (stateless propagation) --------------------------
+// Canonical keys of W words to the internal width Wi >= W (leading zero
+// words; one realization, so no realization bits).
+__global__ void __launch_bounds__(kBlock)
+    k_pad_keys(int W, int Wi, const uint64_t* in, uint64_t* out, int64_t n) {
+  const int64_t total = n * Wi;
+  for (int64_t e = gtid(); e < total; e += gstride()) {
+    const int64_t i = e / Wi;
+    const int w = int(e % Wi) - (Wi - W);
+    out[e] = w >= 0 ? in[i * W + w] : 0ull;
+  }
+}
+
+// Counts of a step whose set is rows [0, n) in place: frontier 0 is the
+// whole set.
+__global__ void k_set_begin(StepCtl* ctl, int* err, uint32_t n) {
+  *err = 0;
+  ctl->n_old = n;
+  ctl->nM = n;
+  ctl->fstart[0] = 0;
+  ctl->fstart[1] = n;
+  ctl->n_new = n;
+  ctl->kmax = 0;
+  ctl->r_need = 0;
+}
+
+// Every row's key names a basis state (site below N, occupations within
+// the cutoffs, no bits above the state's B bits) and finds itself in the
+// table (no other row holds the same key); else kErrInput.
+template <int W>
+__global__ void __launch_bounds__(kBlock)
+    k_check_set(DevModel m, const uint64_t* keys, int64_t n,
+                const uint64_t* table, uint64_t mask, int* err) {
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    uint64_t k[W];
+    load_key<W>(keys, i, k);
+    bool ok = true;
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      const int lo = 64 * (W - 1 - q);  // bit position of the word's bit 0
+      if (lo + 64 <= m.B) continue;
+      const uint64_t above = lo >= m.B ? ~0ull : ~((uint64_t(1) << (m.B - lo)) - 1);
+      ok &= (k[q] & above) == 0;
+    }
+    const int j = int(k[W - 1] & ((uint64_t(1) << m.bj) - 1));
+    ok &= j < m.N;
+    for (int s = 0; s < m.N && ok; ++s)
+      for (int nu = 0; nu < m.V; ++nu)
+        ok &= int(get_field<W>(k, field_off(m, s, nu), m.bnu[nu])) <= m.cut[nu];
+    if (ok) ok = table_find<W>(table, mask, keys, k, key_hash<W>(m, k)) == i;
+    if (!ok) atomicOr(err, kErrInput);
+  }
+}
+
 __global__ void k_begin_step(StepCtl* ctl, int* err, uint32_t* cnt, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) cnt[i] = 0u;
   if (threadIdx.x == 0) {
@@ -56,6 +114,7 @@ __global__ void k_begin_step(StepCtl* ctl, int* err, uint32_t* cnt, int n) {
     ctl->nM = 0;
     ctl->n_new = 0;
     ctl->kmax = 0;
+    ctl->r_need = 0;
   }
 }
 
@@ -288,32 +347,46 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ---- expansion round --------------------------------------------------------
-// Parameters of round r: frontier r-1 and the row count so far.
-__global__ void k_round_prep(StepCtl* ctl, int r, int D, int64_t cand_cap,
-                             int* err) {
+// Parameters of chunk `chunk` of round r: parents [f0 + chunk * per,
+// f0 + (chunk + 1) * per) of frontier r-1 = [f0, f1), per = cand_cap / D.
+// The first chunk starts the row count of the round at fstart[r]; the last
+// one enqueued latches kErrChunks when parents are left over.
+__global__ void k_round_prep(StepCtl* ctl, int r, int chunk, int last, int D,
+                             int64_t cand_cap, int* err) {
   if (*err) return;
-  const uint32_t f0 = ctl->fstart[r - 1];
-  int64_t rows = int64_t(ctl->fstart[r]) - f0;
-  if (rows * D > cand_cap) {
-    atomicOr(err, kErrCapacity);
-    rows = cand_cap / D;
+  const int64_t f0 = ctl->fstart[r - 1], f1 = ctl->fstart[r];
+  const int64_t per = cand_cap / D;
+  const int64_t start = f0 + int64_t(chunk) * per;
+  int64_t rows = f1 - start;
+  if (rows < 0) rows = 0;
+  if (rows > per) {
+    if (last) {
+      atomicOr(err, kErrChunks);
+      const uint32_t need = uint32_t(cdiv(f1 - f0, per));
+      if (need > ctl->r_need) ctl->r_need = need;
+    }
+    rows = per;
   }
-  ctl->r_f0 = f0;
+  ctl->r_f0 = uint32_t(start < f1 ? start : f1);
   ctl->r_rows = uint32_t(rows);
   ctl->r_ncand = uint32_t(rows * D);
   ctl->r_ntiles = uint32_t(cdiv(rows * D, kBlock));
-  ctl->r_ncur = ctl->fstart[r];
+  if (chunk == 0) ctl->r_ncur = ctl->fstart[r];
   ctl->r_total = 0;
 }
 
-__global__ void k_round_finish(StepCtl* ctl, int r, int64_t cap, int* err) {
+// The chunk's new rows join the set; after the last chunk they close
+// frontier r.
+__global__ void k_round_finish(StepCtl* ctl, int r, int last, int64_t cap,
+                               int* err) {
   if (*err) return;
   int64_t n = int64_t(ctl->r_ncur) + ctl->r_total;
   if (n > cap) {
     atomicOr(err, kErrCapacity);
     n = cap;
   }
-  ctl->fstart[r + 1] = uint32_t(n);
+  ctl->r_ncur = uint32_t(n);
+  if (last) ctl->fstart[r + 1] = uint32_t(n);
 }
 
 // Probe: insert-if-absent of candidate c = (parent f0 + c / D, slot c % D).
@@ -324,7 +397,8 @@ __global__ void k_round_finish(StepCtl* ctl, int r, int64_t cap, int* err) {
 // the compare-and-swap.  Outcomes per candidate:
 //   structural zero      col = -1
 //   key already a row    col = that row
-//   owner                c_ref = kOwner, c_slot = table slot
+//   owner                c_ref = kOwner, c_slot = probe distance of the
+//                        claimed slot from the key's home
 //   key owned by c2      c_ref = c2 (column linked after the commit)
 // Candidates are processed in tiles of one block; the owners of each tile
 // are counted into tile_cnt so that new rows are numbered by a scan.
@@ -368,7 +442,7 @@ __global__ void __launch_bounds__(kBlock)
                                            (unsigned long long)mine);
             if (old == kEmpty) {
               rref = kOwner;
-              c_slot[c] = uint32_t(i);
+              c_slot[c] = uint32_t(probes);
               owner = 1;
               done = true;
               break;
@@ -416,7 +490,7 @@ template <int W, typename Amp>
 __global__ void __launch_bounds__(kBlock)
     k_expand_commit(DevModel m, uint64_t* keys, uint64_t* pay, uint64_t* tot,
                     const StepCtl* ctl, int64_t cap, uint64_t* table,
-                    const uint32_t* c_slot, const uint32_t* c_ref,
+                    uint64_t mask, const uint32_t* c_slot, const uint32_t* c_ref,
                     const uint32_t* tile_base, uint32_t* crow, int32_t* col,
                     Amp* phi, int* err) {
   if (*err) return;
@@ -447,10 +521,11 @@ __global__ void __launch_bounds__(kBlock)
     slot_row_info<W>(m, k, py, tot[p], s, np, nt);
     pay[row] = np;
     tot[row] = nt;
-    // the slot holds (tag | candidate); the tag follows from the key, so
-    // the entry is rewritten without reading it back
-    table[c_slot[c]] =
-        (uint64_t(hash_tag(key_hash<W>(m, k))) << 32) | uint64_t(row);
+    // the slot holds (tag | candidate); the tag and the home follow from
+    // the key, so the entry is rewritten without reading it back
+    const uint64_t h = key_hash<W>(m, k);
+    table[((h & mask) + c_slot[c]) & mask] =
+        (uint64_t(hash_tag(h)) << 32) | uint64_t(row);
     crow[c] = uint32_t(row);
     col[p * D + s] = int32_t(row);
     Amp z;
@@ -1132,6 +1207,26 @@ void fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
   k_fill_u64<<<grid_for(n), kBlock, 0, s>>>(p, n, v);
 }
 
+void mark(int tag, hipStream_t s) { k_mark<<<1, 64, 0, s>>>(tag); }
+
+void pad_keys(int W, int Wi, const uint64_t* in, uint64_t* out, int64_t n,
+              hipStream_t s) {
+  if (n <= 0) return;
+  k_pad_keys<<<grid_for(n * Wi), kBlock, 0, s>>>(W, Wi, in, out, n);
+}
+
+void set_begin(StepCtl* ctl, int* err, int64_t n, hipStream_t s) {
+  k_set_begin<<<1, 1, 0, s>>>(ctl, err, uint32_t(n));
+}
+
+void check_set(const DevModel& m, int Wi, const uint64_t* keys, int64_t n,
+               const uint64_t* table, uint64_t mask, int* err,
+               hipStream_t s) {
+  if (n <= 0) return;
+  PACES_DISPATCH_W(Wi, k_check_set<WW><<<grid_for(n), kBlock, 0, s>>>(
+                           m, keys, n, table, mask, err));
+}
+
 void begin_step(StepCtl* ctl, int* err, uint32_t* cnt, int R,
                 hipStream_t s) {
   k_begin_step<<<1, kBlock, 0, s>>>(ctl, err, cnt, 2 * R);
@@ -1200,11 +1295,13 @@ void rehash_rows(const DevModel& m, int Wi, const Side& n, uint32_t* midx,
 void expand_round(const DevModel& m, int Wi, int prec, const Side& n, int r,
                   StepCtl* ctl, int64_t cap, int64_t est, uint64_t* table,
                   uint64_t mask, const RoundBufs& rb, int32_t* col, void* phi,
-                  int* err, hipStream_t s) {
+                  int chunks, int* err, hipStream_t s) {
   const int D = m.D;
   const int64_t nc_bound = std::min<int64_t>(rb.cand_cap, est * D);
   const int g = grid_for(nc_bound);
-  k_round_prep<<<1, 1, 0, s>>>(ctl, r, D, rb.cand_cap, err);
+  for (int q = 0; q < chunks; ++q) {
+  const int last = q == chunks - 1 ? 1 : 0;
+  k_round_prep<<<1, 1, 0, s>>>(ctl, r, q, last, D, rb.cand_cap, err);
   PACES_DISPATCH_W(Wi, k_expand_probe<WW><<<g, kBlock, 0, s>>>(
                            m, n.keys, n.pay, ctl, cap, table, mask, rb.c_slot,
                            rb.c_ref, rb.tile_cnt, col, err));
@@ -1217,17 +1314,18 @@ void expand_round(const DevModel& m, int Wi, int prec, const Side& n, int r,
                                      rb.tile_base, err);
   if (prec == 64) {
     PACES_DISPATCH_W(Wi, k_expand_commit<WW, double2><<<g, kBlock, 0, s>>>(
-                             m, n.keys, n.pay, n.tot, ctl, cap, table,
+                             m, n.keys, n.pay, n.tot, ctl, cap, table, mask,
                              rb.c_slot, rb.c_ref, rb.tile_base, rb.crow, col,
                              (double2*)phi, err));
   } else {
     PACES_DISPATCH_W(Wi, k_expand_commit<WW, float2><<<g, kBlock, 0, s>>>(
-                             m, n.keys, n.pay, n.tot, ctl, cap, table,
+                             m, n.keys, n.pay, n.tot, ctl, cap, table, mask,
                              rb.c_slot, rb.c_ref, rb.tile_base, rb.crow, col,
                              (float2*)phi, err));
   }
   k_expand_link<<<g, kBlock, 0, s>>>(D, ctl, cap, rb.c_ref, rb.crow, col, err);
-  k_round_finish<<<1, 1, 0, s>>>(ctl, r, cap, err);
+  k_round_finish<<<1, 1, 0, s>>>(ctl, r, last, cap, err);
+  }
 }
 
 void lookup_last(const DevModel& m, int Wi, const Side& n, int k,

@@ -38,8 +38,10 @@ struct StepCtl {
   uint32_t nM;                        // selected rows
   uint32_t fstart[kMaxRounds + 2];    // frontier r: [fstart[r], fstart[r+1])
   uint32_t n_new;                     // rows of the new set
-  // current expansion round
+  // current chunk of the current expansion round: parents [r_f0, r_f0 +
+  // r_rows) of the frontier; r_ncur the rows of the set so far
   uint32_t r_f0, r_rows, r_ncand, r_ntiles, r_ncur, r_total;
+  uint32_t r_need;                    // chunks the largest round needs
   uint32_t kmax;                      // largest K over realizations
   uint32_t nrec;                      // steps recorded (R records each)
   double t;                           // time after the last completed step
@@ -47,7 +49,8 @@ struct StepCtl {
 
 // Buffers of one expansion round.
 struct RoundBufs {
-  uint32_t* c_slot;     // [cand] table slot of owning candidates
+  uint32_t* c_slot;     // [cand] probe distance of owning candidates from
+                        // the key's home slot (below kMaxProbe)
   uint32_t* c_ref;      // [cand] outcome of the probe
   uint32_t* crow;       // [cand] row of owning candidates
   uint32_t* tile_cnt;   // [cand / 256] owners per tile of candidates
@@ -66,6 +69,18 @@ int supported_words(int W);  // internal word count >= W, or 0
 int64_t scan_tmp_words(int64_t n);
 
 void fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
+// One empty dispatch (kernel k_mark) on the stream.
+void mark(int tag, hipStream_t s);
+// A given set of n states as the rows of a step: keys padded from W to Wi
+// words; control counts with frontier 0 = rows [0, n) and the latch
+// cleared; every key valid and distinct (else kErrInput), after the rows
+// are in the table.
+void pad_keys(int W, int Wi, const uint64_t* in, uint64_t* out, int64_t n,
+              hipStream_t s);
+void set_begin(StepCtl* ctl, int* err, int64_t n, hipStream_t s);
+void check_set(const DevModel& m, int Wi, const uint64_t* keys, int64_t n,
+               const uint64_t* table, uint64_t mask, int* err,
+               hipStream_t s);
 
 // Start of a step: clear the latch, reset the counters (cnt: 2R
 // per-realization row counts, |M_r| then |S_r|).
@@ -91,12 +106,15 @@ void rehash_rows(const DevModel& m, int Wi, const Side& n, uint32_t* midx,
                  hipStream_t s);
 // Expansion round r (1..k): frontier r-1 emits its slots; new rows are
 // appended and become frontier r.  Writes the parents' ELL columns and
-// zeroes phi of the new rows.
+// zeroes phi of the new rows.  The frontier is taken in `chunks` chunks of
+// at most cand_cap / D parents each (one after another, each sees the rows
+// the previous ones added); a frontier larger than that latches kErrChunks
+// with the chunk count it needs in ctl->r_need.
 // est: host estimate of the new set's rows, used only to size grids.
 void expand_round(const DevModel& m, int Wi, int prec, const Side& n, int r,
                   StepCtl* ctl, int64_t cap, int64_t est, uint64_t* table,
                   uint64_t mask, const RoundBufs& rb, int32_t* col, void* phi,
-                  int* err, hipStream_t s);
+                  int chunks, int* err, hipStream_t s);
 // Columns of frontier k (lookup only); sets ctl->n_new.
 void lookup_last(const DevModel& m, int Wi, const Side& n, int k,
                  StepCtl* ctl, int64_t est, const uint64_t* table,

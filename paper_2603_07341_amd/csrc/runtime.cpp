@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <memory>
 #include <mutex>
 #include <unordered_map>
 #include <cmath>
@@ -304,6 +305,12 @@ struct paces_sim {
   uint32_t* midx = nullptr;
   uint32_t* scan_tmp = nullptr;  // select
   RoundBufs rb{};
+  int chunks = 1;  // candidate chunks per expansion round
+
+  // a step run stage by stage (paces_run_stage)
+  int staged_next = 0;   // the stage expected next
+  int64_t staged_est = 0;
+  int staged_mass = 0, staged_e = 0;  // partial counts handed on
 
   StepCtl* ctl = nullptr;
   int* err = nullptr;
@@ -512,10 +519,20 @@ void drop_graphs(paces_sim* s) {
   s->graphs.clear();
 }
 
+// Largest candidate buffer (entries, 12 bytes each plus tile counts); a
+// round with more candidates runs in chunks of this size.
+constexpr int64_t kCandMax = int64_t(1) << 29;
+
 int64_t cand_want(const paces_model* m, int64_t cap) {
   // candidate buffers: half the worst case to start with; grown on demand
   return std::min<int64_t>(std::max<int64_t>(cap * m->D / 2, int64_t(1) << 16),
-                           (int64_t(1) << 31) - 1);
+                           kCandMax);
+}
+
+// Bytes per row of the state carried across a growth: keys, payload,
+// totals and psi of the current side.
+size_t carried_bytes(const paces_sim* s) {
+  return size_t(s->m->Wi) * 8 + 16 + s->A;
 }
 
 // Pieces of the row block for cap rows: both sides' keys and row data, the
@@ -551,24 +568,25 @@ struct RowBlock {
   }
 };
 
-// Whether a capacity of cap rows fits the device: the new row block while
-// the old one is still alive (the current set is copied across), then the
-// table, the candidate and state-cap buffers once the old blocks are gone.
-// Only checked for the library's own allocator (the caller's may cache).
+// Whether a capacity of cap rows fits the device.  A growth parks the
+// current set in a compact temporary block and frees the old row block and
+// table before it allocates the new ones, so the peak is the temporary plus
+// the new row block, table, candidate and state-cap buffers.  Only checked
+// for the library's own allocator (the caller's may cache).
 bool fits_device(const paces_sim* s, int64_t cap) {
   if (g_allocator.alloc) return true;
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) return true;
   const double margin = double(size_t(2) << 30) + 0.02 * double(tot);
   const double block = double(RowBlock(s, cap).pc.total());
-  if (block > double(fr) - margin) return false;
   const int64_t want = cand_want(s->m, cap);
   const double cand = want > s->rb.cand_cap ? 12.0 * double(want)
                                             : double(s->cand_bytes);
   const bool capbuf = s->p.q_nom > 0 || s->p.max_states > 0;
+  const double temp = double(s->nS) * double(carried_bytes(s));
   const double after =
       block + 8.0 * double(table_size_for(cap, s->tune.table_shift)) + cand +
-      (capbuf ? 22.0 * double(cap) : 0.0);
+      (capbuf ? 22.0 * double(cap) : 0.0) + temp;
   const double back = double(s->rows_bytes) + double(s->cand_bytes) +
                       double(s->capb_bytes) + 8.0 * double(s->tmask_alloc + 1);
   return after <= double(fr) + back - margin;
@@ -594,25 +612,64 @@ paces_status grow(paces_sim* s, int64_t new_cap, int64_t min_cap,
   while (new_cap > min_cap && !fits_device(s, new_cap))
     new_cap = std::max(min_cap, round_cap(new_cap - new_cap / 8));
   s->mem_capped = new_cap < asked;
-  // every row array but the table in one block; the current set and psi
-  // are copied over before the old block goes
-  RowBlock nb(s, new_cap);
-  void* block = nullptr;
-  ST_TRY(nb.pc.carve(&block));
-  if (s->nS > 0) {
+  // The current set and psi are parked in a compact block while the old
+  // row block, table and candidate buffers are released, then copied into
+  // the new row block (every row array but the table, in one block).
+  const int64_t n = s->nS;
+  const size_t kb = size_t(n) * m->Wi * 8, ab = size_t(n) * s->A;
+  uint8_t* park = nullptr;
+  if (n > 0) {
+    void* q = nullptr;
+    ST_TRY(dev_alloc(&q, kb + 16 * size_t(n) + ab + 1024));
+    park = static_cast<uint8_t*>(q);
     const Side& o = s->side[s->cur];
-    Side& c = nb.sd[s->cur];
-    HIP_TRY(hipMemcpyAsync(c.keys, o.keys, size_t(s->nS) * m->Wi * 8,
+    HIP_TRY(hipMemcpyAsync(park, o.keys, kb, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(park + kb, o.pay, size_t(n) * 8,
                            hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipMemcpyAsync(c.pay, o.pay, size_t(s->nS) * 8,
+    HIP_TRY(hipMemcpyAsync(park + kb + 8 * size_t(n), o.tot, size_t(n) * 8,
                            hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipMemcpyAsync(c.tot, o.tot, size_t(s->nS) * 8,
+    HIP_TRY(hipMemcpyAsync(park + kb + 16 * size_t(n), s->vec[s->ipsi], ab,
                            hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipMemcpyAsync(nb.vec[s->ipsi], s->vec[s->ipsi],
-                           size_t(s->nS) * s->A, hipMemcpyDeviceToDevice, st));
   }
   HIP_TRY(hipStreamSynchronize(st));
   if (s->rows_block) dev_free(s->rows_block);
+  s->rows_block = nullptr;
+  s->rows_bytes = 0;
+  dfree(s->table);
+  const int64_t want_c = cand_want(m, new_cap);
+  if (want_c > s->rb.cand_cap) free_cand(s);
+  // (RowBlock holds the addresses of its own members: built in place)
+  std::unique_ptr<RowBlock> nbp(new RowBlock(s, new_cap));
+  void* block = nullptr;
+  paces_status got = nbp->pc.carve(&block);
+  if (got != PACES_OK && min_cap < new_cap) {
+    new_cap = min_cap;
+    s->mem_capped = true;
+    nbp.reset(new RowBlock(s, new_cap));
+    got = nbp->pc.carve(&block);
+  }
+  RowBlock& nb = *nbp;
+  if (got != PACES_OK) {
+    // the set is gone with the old block: the sim needs a new state
+    if (park) dev_free(park);
+    free_rows(s);
+    s->cap = 0;
+    s->nS = 0;
+    s->latched = kErrCapacity;
+    return fail(PACES_E_OOM, "row arrays do not fit the device");
+  }
+  if (n > 0) {
+    Side& c = nb.sd[s->cur];
+    HIP_TRY(hipMemcpyAsync(c.keys, park, kb, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c.pay, park + kb, size_t(n) * 8,
+                           hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c.tot, park + kb + 8 * size_t(n), size_t(n) * 8,
+                           hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(nb.vec[s->ipsi], park + kb + 16 * size_t(n), ab,
+                           hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    dev_free(park);
+  }
   s->rows_block = block;
   s->rows_bytes = nb.pc.total();
   s->side[0] = nb.sd[0];
@@ -625,25 +682,26 @@ paces_status grow(paces_sim* s, int64_t new_cap, int64_t min_cap,
   s->kry = nb.kry;
   s->cap = new_cap;
   s->counts_valid = false;
-  dfree(s->table);
   const uint64_t P = table_size_for(new_cap, s->tune.table_shift);
   ST_TRY(dalloc(&s->table, int64_t(P)));
   s->tmask_alloc = P - 1;
   s->tmask = P - 1;
-  const int64_t want = cand_want(m, new_cap);
-  if (want > s->rb.cand_cap) ST_TRY(alloc_cand(s, want));
+  if (want_c > s->rb.cand_cap) ST_TRY(alloc_cand(s, want_c));
   return PACES_OK;
 }
 
-paces_status grow_cand(paces_sim* s, hipStream_t st) {
+// More candidate room for a round whose frontier overflowed the chunks of
+// the step: larger buffers up to kCandMax, then more chunks per round.
+paces_status more_chunks(paces_sim* s, hipStream_t st) {
   drop_graphs(s);
   ++s->gen;
-  const int64_t want =
-      std::min<int64_t>(2 * s->rb.cand_cap, (int64_t(1) << 31) - 1);
-  if (want <= s->rb.cand_cap)
-    return fail(PACES_E_CAPACITY, "candidate capacity limit reached");
-  HIP_TRY(hipStreamSynchronize(st));
-  return alloc_cand(s, want);
+  if (s->rb.cand_cap < kCandMax) {
+    HIP_TRY(hipStreamSynchronize(st));
+    return alloc_cand(s, std::min<int64_t>(2 * s->rb.cand_cap, kCandMax));
+  }
+  const int need = int(std::min<uint32_t>(s->h_ctl->r_need, 1u << 16));
+  s->chunks = std::max(s->chunks + 1, need);
+  return PACES_OK;
 }
 
 paces_status ensure_ring(paces_sim* s, hipStream_t st) {
@@ -711,99 +769,136 @@ struct FrozenStep {
   int32_t* p0map;  // [n0] rows of the initial states (may be null)
 };
 
-void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st,
-                  const FrozenStep* fz = nullptr) {
+// Partial results a step hands from one stage to the next.
+struct StepLocals {
+  int n_mass = 0, n_e = 0;
+};
+
+int step_order(const paces_sim* s, const FrozenStep* fz) {
+  return fz ? fz->k : (s->fresh ? s->p.k_init : s->p.k);
+}
+
+// select: clear the step's counters and latch, then M (threshold, preset
+// flags of a state cap, or a frozen record).
+void stage_select(paces_sim* s, bool counted, hipStream_t st,
+                  const FrozenStep* fz) {
+  const int R = s->m->R;
+  begin_step(s->ctl, s->err, s->cnt, R, st);
+  Stage sg(s, PACES_STAGE_SELECT, st);
+  if (fz)
+    adj_set_frozen(s->ctl, s->cnt, uint32_t(fz->nM), s->err, st);
+  else if (s->cap_active)
+    select_flags(s->keep, s->ctl, s->midx, s->scan_tmp,
+                 std::min(bucket(s->nS), s->cap), s->err, st);
+  else
+    select_rows(s->prec, s->vec[s->ipsi], s->th2, s->fresh, counted, s->ctl,
+                s->midx, s->scan_tmp, std::min(bucket(s->nS), s->cap), s->err,
+                st);
+}
+
+// expand + merge + build of the columns: M into the cleared table, k
+// rounds, the lookup pass of the last frontier, the state-cap check.
+void stage_expand(paces_sim* s, int64_t est, hipStream_t st,
+                  const FrozenStep* fz) {
   const paces_model* m = s->m;
   const DevModel& dm = m->dm;
-  const int Wi = m->Wi, R = m->R;
-  const int old = s->cur, nw = 1 - s->cur;
-  const int k = fz ? fz->k : (s->fresh ? s->p.k_init : s->p.k);
-  const Side so = s->side[old], sn = s->side[nw];
-  begin_step(s->ctl, s->err, s->cnt, R, st);
-  {
-    Stage sg(s, PACES_STAGE_SELECT, st);
-    if (fz)
-      adj_set_frozen(s->ctl, s->cnt, uint32_t(fz->nM), s->err, st);
-    else if (s->cap_active)
-      select_flags(s->keep, s->ctl, s->midx, s->scan_tmp,
-                   std::min(bucket(s->nS), s->cap), s->err, st);
-    else
-      select_rows(s->prec, s->vec[s->ipsi], s->th2, s->fresh, counted,
-                  s->ctl, s->midx, s->scan_tmp,
-                  std::min(bucket(s->nS), s->cap), s->err, st);
+  const int Wi = m->Wi;
+  const int k = step_order(s, fz);
+  const Side so = s->side[s->cur], sn = s->side[1 - s->cur];
+  Stage sg(s, PACES_STAGE_EXPAND, st);
+  fill_u64(s->table, int64_t(s->tmask + 1), kEmpty, st);
+  if (fz) {
+    if (fz->nM > 0)
+      (void)hipMemcpyAsync(sn.keys, fz->mkeys, size_t(fz->nM) * Wi * 8,
+                           hipMemcpyDeviceToDevice, st);
+    row_info(dm, Wi, sn.keys, fz->nM, sn.pay, sn.tot, st);
+    rehash_rows(dm, Wi, sn, nullptr, fz->nM, s->table, s->tmask, s->err, st);
+  } else {
+    insert_rows(dm, Wi, s->prec, so, sn, s->midx, s->ctl, s->table, s->tmask,
+                s->cnt, s->vec[s->ipsi], s->vec[s->iphi], s->err, st);
   }
-  {
-    Stage sg(s, PACES_STAGE_EXPAND, st);
-    fill_u64(s->table, int64_t(s->tmask + 1), kEmpty, st);
-    if (fz) {
-      if (fz->nM > 0)
-        (void)hipMemcpyAsync(sn.keys, fz->mkeys, size_t(fz->nM) * Wi * 8,
-                             hipMemcpyDeviceToDevice, st);
-      row_info(dm, Wi, sn.keys, fz->nM, sn.pay, sn.tot, st);
-      rehash_rows(dm, Wi, sn, nullptr, fz->nM, s->table, s->tmask, s->err, st);
-    } else {
-      insert_rows(dm, Wi, s->prec, so, sn, s->midx, s->ctl, s->table,
-                  s->tmask, s->cnt, s->vec[s->ipsi], s->vec[s->iphi], s->err,
-                  st);
-    }
-    for (int r = 1; r <= k; ++r)
-      expand_round(dm, Wi, s->prec, sn, r, s->ctl, s->cap, est, s->table,
-                   s->tmask, s->rb, s->col, s->vec[s->iphi], s->err, st);
-    lookup_last(dm, Wi, sn, k, s->ctl, est, s->table, s->tmask, s->col,
-                s->cap, s->err, st);
-    if (s->p.max_states > 0)
-      cap_check(dm, s->ctl, sn.pay, est, s->p.max_states, s->ball, s->err,
-                st);
-  }
-  int n_mass = 0, n_e = 0;
-  {
-    Stage sg(s, PACES_STAGE_TRANSFER, st);
-    // rows of M were placed with their amplitudes by the insert; the
-    // frozen replay maps every old row
-    const int skip = fz ? 0 : (s->cap_active ? 2 : (s->fresh ? 0 : 1));
-    const int np = transfer(dm, Wi, s->prec, so, s->vec[s->ipsi],
-                            bucket(s->nS), s->ctl, s->table, s->tmask, sn.keys,
-                            s->vec[s->iphi], s->mass_part,
-                            fz ? fz->tmap : nullptr, skip, s->th2, s->keep,
-                            s->err, st);
-    n_mass = R == 1 ? fold_sum(s->mass_part, np, s->mass_fold, s->err, st) : np;
-  }
-  const bool want_e = (s->p.obs_mask & PACES_OBS_ENERGY) != 0;
+  for (int r = 1; r <= k; ++r)
+    expand_round(dm, Wi, s->prec, sn, r, s->ctl, s->cap, est, s->table,
+                 s->tmask, s->rb, s->col, s->vec[s->iphi], s->chunks, s->err,
+                 st);
+  lookup_last(dm, Wi, sn, k, s->ctl, est, s->table, s->tmask, s->col, s->cap,
+              s->err, st);
+  if (s->p.max_states > 0)
+    cap_check(dm, s->ctl, sn.pay, est, s->p.max_states, s->ball, s->err, st);
+}
+
+// transfer: old amplitudes into phi, discarded weight.
+void stage_transfer(paces_sim* s, hipStream_t st, const FrozenStep* fz,
+                    StepLocals& L) {
+  const paces_model* m = s->m;
+  const int R = m->R;
+  const Side so = s->side[s->cur], sn = s->side[1 - s->cur];
+  Stage sg(s, PACES_STAGE_TRANSFER, st);
+  // rows of M were placed with their amplitudes by the insert; the frozen
+  // replay maps every old row
+  const int skip = fz ? 0 : (s->cap_active ? 2 : (s->fresh ? 0 : 1));
+  const int np = transfer(m->dm, m->Wi, s->prec, so, s->vec[s->ipsi],
+                          bucket(s->nS), s->ctl, s->table, s->tmask, sn.keys,
+                          s->vec[s->iphi], s->mass_part,
+                          fz ? fz->tmap : nullptr, skip, s->th2, s->keep,
+                          s->err, st);
+  L.n_mass = R == 1 ? fold_sum(s->mass_part, np, s->mass_fold, s->err, st)
+                    : np;
+}
+
+// build: spectral bounds and the propagator's coefficients or plan (the
+// Krylov propagator builds its small matrix inside the propagation).
+void stage_build(paces_sim* s, int64_t est, hipStream_t st) {
+  const paces_model* m = s->m;
+  const Side sn = s->side[1 - s->cur];
+  if (s->p.krylov_order > 0) return;
+  Stage sg(s, PACES_STAGE_BUILD, st);
   if (s->p.taylor_order != 0) {
-    // truncated Taylor series: bounds and plan, then the term launches
-    // (launch L is term L mod m + 1 of substep L / m)
-    {
-      Stage sg(s, PACES_STAGE_BUILD, st);
-      const int nb = bounds_part(dm, sn, s->col, s->cap, est, s->ctl,
-                                 s->bnd_part, s->err, st);
-      taylor_plan(R, s->bnd_part, nb, s->p.dt, s->p.taylor_order, s->thetas,
-                  s->p.k_max_terms, s->launched, s->tplan, s->cc, s->ctl,
-                  s->err, st);
-    }
-    Stage sg(s, PACES_STAGE_PROPAGATE, st);
+    const int nb = bounds_part(m->dm, sn, s->col, s->cap, est, s->ctl,
+                               s->bnd_part, s->err, st);
+    taylor_plan(m->R, s->bnd_part, nb, s->p.dt, s->p.taylor_order, s->thetas,
+                s->p.k_max_terms, s->launched, s->tplan, s->cc, s->ctl,
+                s->err, st);
+  } else {
+    bounds_and_coef(m->dm, sn, s->col, s->cap, est, s->ctl, s->p.dt, s->p.tol,
+                    s->p.k_max_terms, s->launched, s->bnd_part, s->cc, s->err,
+                    st);
+  }
+}
+
+// propagate: psi' = exp(-i H dt) phi into vector ib0.
+void stage_propagate(paces_sim* s, int64_t est, hipStream_t st,
+                     StepLocals& L) {
+  const paces_model* m = s->m;
+  const DevModel& dm = m->dm;
+  const int R = m->R;
+  const Side sn = s->side[1 - s->cur];
+  const bool want_e = (s->p.obs_mask & PACES_OBS_ENERGY) != 0;
+  Stage sg(s, PACES_STAGE_PROPAGATE, st);
+  if (s->p.taylor_order != 0) {
+    // truncated Taylor series: launch L is term L mod m + 1 of substep L / m
     void* bufB[2] = {s->vec[s->ib1], s->kry[0]};
     void* bufF[2] = {s->kry[1], s->kry[2]};
     int np = 0;
     // the adaptive series is exact to rounding, so the energy of phi is
     // that of the result; the fixed order needs its own pass
     const bool fixed = s->p.taylor_order > 0;
-    for (int L = 0; L < s->launched; ++L) {
-      KernelTiming kt(s, PACES_STAGE_TERM, L);
-      const int g = taylor_term(dm, s->prec, L, want_e && !fixed, s->p.dt,
+    for (int l = 0; l < s->launched; ++l) {
+      KernelTiming kt(s, PACES_STAGE_TERM, l);
+      const int g = taylor_term(dm, s->prec, l, want_e && !fixed, s->p.dt,
                                 std::max<int64_t>(1, est / s->tune.term_rows),
                                 s->ctl, s->col, sn, s->tplan,
                                 s->vec[s->iphi], bufB, bufF, s->vec[s->ib0],
                                 s->e_part, s->e_row, s->err, kt.a, kt.b, st);
-      if (L == 0) np = g;
+      if (l == 0) np = g;
     }
     if (want_e && fixed)
       np = taylor_energy(dm, s->prec, est, s->ctl, s->col, sn, s->vec[s->ib0],
                          s->e_part, s->e_row, s->err, st);
-    if (want_e && R == 1) n_e = fold_sum(s->e_part, np, s->e_fold, s->err, st);
+    if (want_e && R == 1) L.n_e = fold_sum(s->e_part, np, s->e_fold, s->err, st);
   } else if (s->p.krylov_order > 0) {
     // Krylov propagator: nk SpMVs with their folds, nk - 1 recurrence
     // passes, the small exponential and the combination into b0
-    Stage sg(s, PACES_STAGE_PROPAGATE, st);
     const int nk = s->p.krylov_order + 1;
     KrylovVecs kv{};
     kv.w[0] = s->vec[s->iphi];
@@ -834,49 +929,59 @@ void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st,
     lz_combine(dm, s->prec, est, s->ctl, sn.pay, s->lz, kv, nk,
                s->vec[s->ib0], s->err, st);
   } else {
-  {
-    Stage sg(s, PACES_STAGE_BUILD, st);
-    bounds_and_coef(dm, sn, s->col, s->cap, est, s->ctl, s->p.dt, s->p.tol,
-                    s->p.k_max_terms, s->launched, s->bnd_part, s->cc, s->err,
-                    st);
-  }
-  {
-    Stage sg(s, PACES_STAGE_PROPAGATE, st);
     int np = 0;
     for (int kk = s->launched - 1; kk >= 0; --kk) {
       KernelTiming kt(s, PACES_STAGE_TERM, kk);
       const bool mid = s->K_last >= 4 && kk >= 1 && kk <= s->K_last - 3;
       np = cheb_term(dm, s->prec, kk, want_e, mid,
                      std::max<int64_t>(1, est / s->tune.term_rows), s->ctl,
-                     s->col, s->cap,
-                     sn, s->cc, s->vec[s->iphi], s->vec[s->ib0],
-                     s->vec[s->ib1], s->e_part, s->e_row, s->err, kt.a, kt.b,
-                     st);
+                     s->col, s->cap, sn, s->cc, s->vec[s->iphi],
+                     s->vec[s->ib0], s->vec[s->ib1], s->e_part, s->e_row,
+                     s->err, kt.a, kt.b, st);
     }
-    if (want_e && R == 1) n_e = fold_sum(s->e_part, np, s->e_fold, s->err, st);
+    if (want_e && R == 1) L.n_e = fold_sum(s->e_part, np, s->e_fold, s->err, st);
   }
-  }
+}
+
+// observe: norm, energy, a(t), populations into the record ring; commit
+// the step's counts on the device and mirror them to the host.
+void stage_observe(paces_sim* s, int64_t est, hipStream_t st,
+                   const FrozenStep* fz, const StepLocals& L) {
+  const paces_model* m = s->m;
+  const DevModel& dm = m->dm;
+  const int R = m->R;
+  const Side sn = s->side[1 - s->cur];
+  const bool want_e = (s->p.obs_mask & PACES_OBS_ENERGY) != 0;
   const bool krylov = s->p.krylov_order > 0;
-  {
-    Stage sg(s, PACES_STAGE_OBSERVE, st);
-    const int n_pop = pop_norm(s->prec, m->N, R, s->th2, est, s->ctl,
-                               s->vec[s->ib0], sn.pay,
-                               want_e && R > 1 && !krylov ? s->e_row : nullptr,
-                               s->n2_part, s->en_part, s->pop_part,
-                               s->scan_tmp, s->cnt + R, s->err, st);
-    autocorr(dm, Wi, s->prec, s->keys0, s->amps0, s->n0, s->table, s->tmask,
-             sn.keys, s->vec[s->ib0], s->a2, fz ? fz->p0map : s->p0_last,
-             s->err, st);
-    obs_final(m->N, R, want_e && !krylov ? 1 : 0, s->p.dt, n_mass, n_e, n_pop,
-              R == 1 ? s->mass_fold : s->mass_part, s->n2_part, s->e_fold,
-              s->en_part, s->pop_part, s->a2, s->cc, s->ctl, s->cnt,
-              s->mass_tot, s->ring, s->rec_doubles, s->ring_cap, s->err, st);
-    if (want_e && krylov)
-      lz_record_energy(R, s->lz_energy, s->ctl, s->ring, s->rec_doubles,
-                       s->ring_cap, s->err, st);
-    end_step(s->ctl, R, s->ring, s->rec_doubles, s->mass_tot, s->err,
-             s->d_hctl, s->d_herr, st);
-  }
+  Stage sg(s, PACES_STAGE_OBSERVE, st);
+  const int n_pop = pop_norm(s->prec, m->N, R, s->th2, est, s->ctl,
+                             s->vec[s->ib0], sn.pay,
+                             want_e && R > 1 && !krylov ? s->e_row : nullptr,
+                             s->n2_part, s->en_part, s->pop_part, s->scan_tmp,
+                             s->cnt + R, s->err, st);
+  autocorr(dm, m->Wi, s->prec, s->keys0, s->amps0, s->n0, s->table, s->tmask,
+           sn.keys, s->vec[s->ib0], s->a2, fz ? fz->p0map : s->p0_last,
+           s->err, st);
+  obs_final(m->N, R, want_e && !krylov ? 1 : 0, s->p.dt, L.n_mass, L.n_e,
+            n_pop, R == 1 ? s->mass_fold : s->mass_part, s->n2_part,
+            s->e_fold, s->en_part, s->pop_part, s->a2, s->cc, s->ctl, s->cnt,
+            s->mass_tot, s->ring, s->rec_doubles, s->ring_cap, s->err, st);
+  if (want_e && krylov)
+    lz_record_energy(R, s->lz_energy, s->ctl, s->ring, s->rec_doubles,
+                     s->ring_cap, s->err, st);
+  end_step(s->ctl, R, s->ring, s->rec_doubles, s->mass_tot, s->err, s->d_hctl,
+           s->d_herr, st);
+}
+
+void enqueue_step(paces_sim* s, int64_t est, bool counted, hipStream_t st,
+                  const FrozenStep* fz = nullptr) {
+  StepLocals L;
+  stage_select(s, counted, st, fz);
+  stage_expand(s, est, st, fz);
+  stage_transfer(s, st, fz, L);
+  stage_build(s, est, st);
+  stage_propagate(s, est, st, L);
+  stage_observe(s, est, st, fz, L);
 }
 
 // Replay the captured graph of this step's launch sequence, capturing it
@@ -889,7 +994,7 @@ paces_status launch_step_graph(paces_sim* s, int64_t est, bool counted,
       s->fresh ? 1 : 0, counted ? 1 : 0, s->fresh ? s->p.k_init : s->p.k,
       s->launched, s->K_last, est, std::min(bucket(s->nS), s->cap),
       int64_t(s->tmask), s->tune.term_rows, s->p.krylov_order,
-      s->p.taylor_order};
+      s->p.taylor_order, s->chunks};
   for (auto& g : s->graphs)
     if (g.key == key) {
       g.used = ++s->graph_clock;
@@ -1095,11 +1200,11 @@ paces_status topq_cut(paces_sim* s, hipStream_t st) {
   return PACES_OK;
 }
 
-// One step: enqueue, read back the counts, repeat with more room when a
-// capacity was exceeded.
-paces_status do_step(paces_sim* s, hipStream_t st,
-                     const FrozenStep* fz = nullptr) {
-  const paces_model* m = s->m;
+// Host preparation of a step: room for the new set, the record ring, the
+// launch estimate and the part of the table the step probes, and the
+// fixed-size truncation's selection.  Returns the estimate.
+paces_status prepare_step(paces_sim* s, hipStream_t st, bool frozen,
+                          int64_t* est_out) {
   // keep room for the new set: growth of the set per step stays well below
   // the factor used here in the workloads; an overflow is caught anyway.
   // Growth to 4 |S| makes the next one due only when the set has doubled.
@@ -1121,7 +1226,76 @@ paces_status do_step(paces_sim* s, hipStream_t st,
     s->tmask = std::min<uint64_t>(P - 1, s->tmask_alloc);
   }
   s->cap_active = false;
-  if (s->p.q_nom > 0 && !s->fresh && !fz) ST_TRY(qnom_select(s, st));
+  if (s->p.q_nom > 0 && !s->fresh && !frozen) ST_TRY(qnom_select(s, st));
+  *est_out = est;
+  return PACES_OK;
+}
+
+// Host side of a completed step (the device counts are in *h_ctl).
+void finish_step(paces_sim* s, const FrozenStep* fz) {
+  const paces_model* m = s->m;
+  const StepCtl& c = *s->h_ctl;
+  const int K = int(c.kmax);
+  // classify the timed Clenshaw launches of this step
+  const double rowb = 4.0 * double(s->A) + 4.0 * m->D + (m->V > 2 ? 16 : 8);
+  // Lanczos SpMV: w_j and z once each, the columns and the payload
+  const double rowk = 2.0 * double(s->A) + 4.0 * m->D + (m->V > 2 ? 16 : 8);
+  for (auto& ev : s->pending) {
+    if (ev.stage == PACES_STAGE_KRYLOV) ev.bytes = double(c.n_new) * rowk;
+    if (ev.stage == PACES_STAGE_TERM) {
+      if (ev.kk >= 1 && ev.kk <= K - 3) {
+        ev.bytes = double(c.n_new) * rowb;
+      } else {
+        (void)hipEventDestroy(ev.a);
+        (void)hipEventDestroy(ev.b);
+        ev.stage = -1;
+        continue;
+      }
+    }
+    s->events.push_back(ev);
+  }
+  s->pending.clear();
+  s->h = c;
+  s->nS = c.n_new;
+  s->cur = 1 - s->cur;
+  std::swap(s->ipsi, s->ib0);
+  s->k_last = step_order(s, fz);
+  s->fresh = false;
+  s->have_sets = true;
+  s->K_last = K;
+  s->launched = std::max(4, std::min(K + 2, kMaxTerms));
+  s->acc.rows_steps += double(c.n_new);
+  s->counts_valid = true;
+  s->cap_active = false;
+}
+
+// After an attempt that latched e: make the room or the selection the
+// repeated attempt needs, or return the error.
+paces_status handle_latch(paces_sim* s, int e, hipStream_t st) {
+  if (e == kErrCap) return cap_select(s, st);
+  if (e & (kErrTerms | kErrNonFinite)) return check_latch_code(s, e);
+  if (e & kErrNeedTerms) {
+    s->launched = std::min(int(s->h_ctl->kmax) + 2, kMaxTerms);
+    return PACES_OK;
+  }
+  if (e & kErrTableFull) {
+    if (s->tmask < s->tmask_alloc) {
+      s->tmask = 2 * s->tmask + 1;
+      return PACES_OK;
+    }
+    return grow(s, 2 * s->cap, s->cap + s->cap / 4, st);
+  }
+  if (e & kErrChunks) return more_chunks(s, st);
+  if (e & kErrCapacity) return grow(s, 2 * s->cap, s->cap + s->cap / 4, st);
+  return check_latch_code(s, e);
+}
+
+// One step: enqueue, read back the counts, repeat with more room when a
+// capacity was exceeded.
+paces_status do_step(paces_sim* s, hipStream_t st,
+                     const FrozenStep* fz = nullptr) {
+  int64_t est = 0;
+  ST_TRY(prepare_step(s, st, fz != nullptr, &est));
   const bool graph = s->tune.graph && !s->prof && !fz && !s->cap_active;
   for (int attempt = 0; attempt < 40; ++attempt) {
     const bool counted = s->counts_valid && attempt == 0 && !fz &&
@@ -1135,70 +1309,24 @@ paces_status do_step(paces_sim* s, hipStream_t st,
     HIP_TRY(hipStreamSynchronize(st));
     const int e = *s->h_err;
     if (e == 0) {
-      const StepCtl& c = *s->h_ctl;
-      const int K = int(c.kmax);
-      // classify the timed Clenshaw launches of this step
-      const double rowb = 4.0 * double(s->A) + 4.0 * m->D + (m->V > 2 ? 16 : 8);
-      // Lanczos SpMV: w_j and z once each, the columns and the payload
-      const double rowk = 2.0 * double(s->A) + 4.0 * m->D + (m->V > 2 ? 16 : 8);
-      for (auto& ev : s->pending) {
-        if (ev.stage == PACES_STAGE_KRYLOV) ev.bytes = double(c.n_new) * rowk;
-        if (ev.stage == PACES_STAGE_TERM) {
-          if (ev.kk >= 1 && ev.kk <= K - 3) {
-            ev.bytes = double(c.n_new) * rowb;
-          } else {
-            (void)hipEventDestroy(ev.a);
-            (void)hipEventDestroy(ev.b);
-            ev.stage = -1;
-            continue;
-          }
-        }
-        s->events.push_back(ev);
-      }
-      s->pending.clear();
-      s->h = c;
-      s->nS = c.n_new;
-      s->cur = 1 - s->cur;
-      std::swap(s->ipsi, s->ib0);
-      s->k_last = fz ? fz->k : (s->fresh ? s->p.k_init : s->p.k);
-      s->fresh = false;
-      s->have_sets = true;
-      s->K_last = K;
-      s->launched = std::max(4, std::min(K + 2, kMaxTerms));
-      s->acc.rows_steps += double(c.n_new);
-      s->counts_valid = true;
-      s->cap_active = false;
+      finish_step(s, fz);
       return PACES_OK;
     }
     drop_pending(s);
-    if (e == kErrCap) {
-      ST_TRY(cap_select(s, st));
-      continue;
-    }
-    if (e & (kErrTerms | kErrNonFinite)) return check_latch_code(s, e);
-    if (e & kErrNeedTerms) {
-      s->launched = std::min(int(s->h_ctl->kmax) + 2, kMaxTerms);
-      continue;
-    }
-    if (e & kErrTableFull) {
-      if (s->tmask < s->tmask_alloc)
-        s->tmask = 2 * s->tmask + 1;
-      else
-        ST_TRY(grow(s, 2 * s->cap, s->cap + s->cap / 4, st));
-      continue;
-    }
-    if (e & kErrCapacity) {
-      // a clamped round or a full row array: grow whichever is short
-      const StepCtl& c = *s->h_ctl;
-      if (int64_t(c.r_rows) * m->D >= s->rb.cand_cap - m->D)
-        ST_TRY(grow_cand(s, st));
-      else
-        ST_TRY(grow(s, 2 * s->cap, s->cap + s->cap / 4, st));
-      continue;
-    }
-    return check_latch_code(s, e);
+    ST_TRY(handle_latch(s, e, st));
   }
   return fail(PACES_E_CAPACITY, "step did not fit after repeated growth");
+}
+
+// Counts and latch of a step in progress, read while it is incomplete.
+paces_status read_latch(paces_sim* s, hipStream_t st, int* e) {
+  HIP_TRY(hipMemcpyAsync(s->h_ctl, s->ctl, sizeof(StepCtl),
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(s->h_err, s->err, sizeof(int), hipMemcpyDeviceToHost,
+                         st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *e = *s->h_err;
+  return PACES_OK;
 }
 
 // Copy of the current state and the host mirror, for trial steps.
@@ -1528,6 +1656,118 @@ paces_status ensure_device_tables(paces_model* m) {
   return PACES_OK;
 }
 
+// ---- exp(-i H_S dt) phi on a given set (paces_expmv) ------------------------
+// Work memory for n rows: model tables, step control, latch, Chebyshev
+// coefficients, Gershgorin partials, internal keys (when the canonical
+// width needs padding), payload and totals, ELL columns, the second
+// Clenshaw vector and the hash table (at least twice the rows).
+struct ExpmvLayout {
+  size_t nbr = 0, gsq = 0, eps = 0, ctl = 0, err = 0, cc = 0, part = 0;
+  size_t keys = 0, pay = 0, tot = 0, col = 0, b1 = 0, table = 0, total = 0;
+  uint64_t P = 0;
+};
+
+ExpmvLayout expmv_layout(const paces_model* m, int64_t n) {
+  ExpmvLayout L;
+  size_t off = 0;
+  auto put = [&](size_t bytes) {
+    const size_t at = off;
+    off += (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
+    return at;
+  };
+  L.nbr = put(m->nbr.size() * 4);
+  L.gsq = put(m->gsq.size() * 8);
+  L.eps = put(m->eps.size() * 8);
+  L.ctl = put(sizeof(StepCtl));
+  L.err = put(sizeof(int));
+  L.cc = put(sizeof(ChebCoef));
+  L.part = put(size_t(2) * kPartBlocks * 8);
+  L.keys = m->Wi != m->W ? put(size_t(n) * m->Wi * 8) : 0;
+  L.pay = put(size_t(n) * 8);
+  L.tot = put(size_t(n) * 8);
+  L.col = put(size_t(n) * m->D * 4);
+  L.b1 = put(size_t(n) * 16);
+  L.P = table_size_for(n, 1);
+  L.table = put(size_t(L.P) * 8);
+  L.total = off;
+  return L;
+}
+
+// Status of a latch read back after the propagation on a given set.
+paces_status expmv_latch(int e) {
+  if (!e) return PACES_OK;
+  if (e & kErrInput)
+    return fail(PACES_E_ARG, "a key is out of range or repeated");
+  if (e & kErrTerms)
+    return fail(PACES_E_PROPAGATOR, "series needs more than 128 terms");
+  if (e & kErrNonFinite) return fail(PACES_E_NONFINITE, "spectrum not finite");
+  return fail(PACES_E_CAPACITY, "hash table overflow");
+}
+
+// The propagation of a step on a set given as n canonical keys, with the
+// work memory `work` laid out by expmv_layout.  Synchronises.
+paces_status expmv_run(const paces_model* m, int64_t n, const uint64_t* keys,
+                       const void* phi, double dt, void* psi, uint8_t* work,
+                       hipStream_t st) {
+  const ExpmvLayout L = expmv_layout(m, n);
+  DevModel dm = m->dm;
+  dm.nbr = reinterpret_cast<const int32_t*>(work + L.nbr);
+  dm.gsq = reinterpret_cast<const double*>(work + L.gsq);
+  dm.eps = reinterpret_cast<const double*>(work + L.eps);
+  HIP_TRY(hipMemcpyAsync(work + L.nbr, m->nbr.data(), m->nbr.size() * 4,
+                         hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(work + L.gsq, m->gsq.data(), m->gsq.size() * 8,
+                         hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(work + L.eps, m->eps.data(), m->eps.size() * 8,
+                         hipMemcpyHostToDevice, st));
+  StepCtl* ctl = reinterpret_cast<StepCtl*>(work + L.ctl);
+  int* err = reinterpret_cast<int*>(work + L.err);
+  ChebCoef* cc = reinterpret_cast<ChebCoef*>(work + L.cc);
+  double* part = reinterpret_cast<double*>(work + L.part);
+  uint64_t* table = reinterpret_cast<uint64_t*>(work + L.table);
+  Side sd;
+  sd.keys = const_cast<uint64_t*>(keys);
+  if (m->Wi != m->W) {
+    sd.keys = reinterpret_cast<uint64_t*>(work + L.keys);
+    pad_keys(m->W, m->Wi, keys, sd.keys, n, st);
+  }
+  sd.pay = reinterpret_cast<uint64_t*>(work + L.pay);
+  sd.tot = reinterpret_cast<uint64_t*>(work + L.tot);
+  int32_t* col = reinterpret_cast<int32_t*>(work + L.col);
+  const uint64_t mask = L.P - 1;
+  set_begin(ctl, err, n, st);
+  row_info(dm, m->Wi, sd.keys, n, sd.pay, sd.tot, st);
+  fill_u64(table, int64_t(L.P), kEmpty, st);
+  rehash_rows(dm, m->Wi, sd, nullptr, n, table, mask, err, st);
+  check_set(dm, m->Wi, sd.keys, n, table, mask, err, st);
+  lookup_last(dm, m->Wi, sd, 0, ctl, n, table, mask, col, n, err, st);
+  bounds_and_coef(dm, sd, col, n, n, ctl, dt, 1e-16, kMaxTerms, kMaxTerms,
+                  part, cc, err, st);
+  StepCtl hc{};
+  int he = 0;
+  HIP_TRY(hipMemcpyAsync(&hc, ctl, sizeof(StepCtl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&he, err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  ST_TRY(expmv_latch(he));
+  for (int kk = std::max(1, int(hc.kmax)) - 1; kk >= 0; --kk)
+    cheb_term(dm, 64, kk, false, false, n, ctl, col, n, sd, cc, phi, psi,
+              work + L.b1, nullptr, nullptr, err, nullptr, nullptr, st);
+  HIP_TRY(hipMemcpyAsync(&he, err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return expmv_latch(he);
+}
+
+paces_status expmv_args(const paces_model* m, int64_t n, const void* keys,
+                        const void* phi, double dt, const void* psi) {
+  if (!m || n < 0 || (n > 0 && (!keys || !phi || !psi)) || !std::isfinite(dt))
+    return fail(PACES_E_ARG, "bad arguments");
+  if (n > (int64_t(1) << 31) - 256) return fail(PACES_E_ARG, "too many rows");
+  if (n > 0 && phi == psi) return fail(PACES_E_ARG, "psi must not alias phi");
+  if (m->R != 1)
+    return fail(PACES_E_UNSUPPORTED, "a model with one realization is needed");
+  return PACES_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1658,6 +1898,22 @@ paces_status paces_load_model(const paces_model_desc* d, paces_model** out) {
 
   *out = m;
   return PACES_OK;
+}
+
+paces_status paces_expmv(const paces_model* m, int64_t n, const void* dev_keys,
+                         const void* dev_phi, double dt, void* dev_psi,
+                         void* hip_stream) {
+  ST_TRY(expmv_args(m, n, dev_keys, dev_phi, dt, dev_psi));
+  if (n == 0) return PACES_OK;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  void* work = nullptr;
+  ST_TRY(dev_alloc(&work, expmv_layout(m, n).total));
+  const paces_status e =
+      expmv_run(m, n, static_cast<const uint64_t*>(dev_keys), dev_phi, dt,
+                dev_psi, static_cast<uint8_t*>(work), st);
+  (void)hipStreamSynchronize(st);
+  dev_free(work);
+  return e;
 }
 
 paces_status paces_free_model(paces_model* m) {
@@ -1901,6 +2157,7 @@ paces_status paces_step(paces_sim* s, int64_t n_steps, void* hip_stream) {
   if (s->latched) return fail(PACES_E_STATE, "sim is in an error state");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const char* log = std::getenv("PACES_LOG");
+  s->staged_next = 0;  // a staged step in progress is abandoned
   for (int64_t i = 0; i < n_steps; ++i) {
     paces_status r = do_step(s, st);
     if (r != PACES_OK) {
@@ -1909,6 +2166,92 @@ paces_status paces_step(paces_sim* s, int64_t n_steps, void* hip_stream) {
     }
     if (log && *log && std::strcmp(log, "0") != 0) ST_TRY(log_step(s, log, st));
   }
+  return PACES_OK;
+}
+
+paces_status paces_run_stage(paces_sim* s, int32_t stage, void* hip_stream) {
+  if (!s) return fail(PACES_E_ARG, "bad arguments");
+  if (stage < PACES_STAGE_SELECT || stage > PACES_STAGE_OBSERVE)
+    return fail(PACES_E_ARG, "stage must be select .. observe");
+  if (s->latched) return fail(PACES_E_STATE, "sim is in an error state");
+  static const char* names[] = {"select", "expand", "transfer", "build",
+                                "propagate", "observe"};
+  if (stage != PACES_STAGE_SELECT && stage != s->staged_next)
+    return fail(PACES_E_STATE, std::string("stages run in order; expected ") +
+                                   names[s->staged_next]);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  StepLocals L;
+  L.n_mass = s->staged_mass;
+  L.n_e = s->staged_e;
+  switch (stage) {
+    case PACES_STAGE_SELECT: {
+      s->staged_next = 0;
+      ST_TRY(prepare_step(s, st, false, &s->staged_est));
+      stage_select(s, false, st, nullptr);
+      break;
+    }
+    case PACES_STAGE_EXPAND: {
+      // the sizes of the new set are known only now: repeat select +
+      // expand with more room (or a cut selection) until they fit
+      int e = 0;
+      for (int attempt = 0;; ++attempt) {
+        if (attempt > 0) stage_select(s, false, st, nullptr);
+        stage_expand(s, s->staged_est, st, nullptr);
+        ST_TRY(read_latch(s, st, &e));
+        if (!e) break;
+        drop_pending(s);
+        const int retry = kErrTableFull | kErrCapacity | kErrChunks | kErrCap;
+        if (attempt >= 40 || (e & ~retry)) {
+          s->staged_next = 0;
+          return check_latch_code(s, e);
+        }
+        paces_status h = handle_latch(s, e, st);
+        if (h) {
+          s->staged_next = 0;
+          return h;
+        }
+      }
+      break;
+    }
+    case PACES_STAGE_TRANSFER:
+      stage_transfer(s, st, nullptr, L);
+      break;
+    case PACES_STAGE_BUILD:
+      // the number of series launches is set from the coefficients below
+      s->launched = kMaxTerms;
+      stage_build(s, s->staged_est, st);
+      break;
+    case PACES_STAGE_PROPAGATE: {
+      int e = 0;
+      ST_TRY(read_latch(s, st, &e));
+      if (e) {
+        s->staged_next = 0;
+        drop_pending(s);
+        return check_latch_code(s, e);
+      }
+      s->launched = std::max(1, int(s->h_ctl->kmax));
+      stage_propagate(s, s->staged_est, st, L);
+      break;
+    }
+    case PACES_STAGE_OBSERVE: {
+      stage_observe(s, s->staged_est, st, nullptr, L);
+      HIP_TRY(hipStreamSynchronize(st));
+      s->staged_next = 0;
+      const int e = *s->h_err;
+      if (e) {
+        drop_pending(s);
+        return check_latch_code(s, e);
+      }
+      finish_step(s, nullptr);
+      const char* log = std::getenv("PACES_LOG");
+      if (log && *log && std::strcmp(log, "0") != 0)
+        ST_TRY(log_step(s, log, st));
+      return PACES_OK;
+    }
+  }
+  s->staged_mass = L.n_mass;
+  s->staged_e = L.n_e;
+  s->staged_next = stage + 1;
   return PACES_OK;
 }
 
@@ -2020,6 +2363,7 @@ paces_status paces_set_state(paces_sim* s, int64_t n, const uint64_t* keys,
   ST_TRY(upload_state(s, n, ik, amps, st));
   s->fresh = false;
   s->have_sets = false;
+  s->staged_next = 0;
   s->counts_valid = false;
   return PACES_OK;
 }
@@ -2095,6 +2439,12 @@ paces_status paces_profile_get(paces_sim* s, paces_profile* out,
   }
   s->events.clear();
   *out = s->acc;
+  return PACES_OK;
+}
+
+paces_status paces_profile_mark(int32_t tag, void* hip_stream) {
+  paces::mark(tag, static_cast<hipStream_t>(hip_stream));
+  HIP_TRY(hipGetLastError());
   return PACES_OK;
 }
 
@@ -2238,6 +2588,22 @@ paces_status paces_adjoint_forward(paces_sim* s, int64_t n_steps,
   return PACES_OK;
 }
 
+paces_status paces_adjoint_forward_dev(paces_sim* s, int64_t n_steps,
+                                       int32_t ckpt_every, void* dev_a,
+                                       void* hip_stream) {
+  if (!dev_a) return fail(PACES_E_ARG, "bad arguments");
+  ST_TRY(paces_adjoint_forward(s, n_steps, ckpt_every, nullptr, hip_stream));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  // a_0 from the host record, a_1..a_n straight from the device records
+  double* out = static_cast<double*>(dev_a);
+  HIP_TRY(hipMemcpyAsync(out, s->adj->a.data(), 16, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpy2DAsync(out + 2, 16, s->ring + 3,
+                           size_t(s->rec_doubles) * 8, 16, size_t(n_steps),
+                           hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return PACES_OK;
+}
+
 paces_status paces_adjoint_replay(paces_sim* s, const paces_model* model,
                                   double* a_out, void* hip_stream) {
   if (!s || !a_out) return fail(PACES_E_ARG, "bad arguments");
@@ -2262,11 +2628,10 @@ paces_status paces_adjoint_replay(paces_sim* s, const paces_model* model,
   return e ? e : e2;
 }
 
-paces_status paces_adjoint_backward(paces_sim* s, const double* gbar,
-                                    double* grad_out, void* hip_stream) {
-  if (!s || !gbar || !grad_out) return fail(PACES_E_ARG, "bad arguments");
-  if (!s->adj) return fail(PACES_E_STATE, "no adjoint record");
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+// Backward sweep of the adjoint gradient; gbar[2 (n + 1)] and grad[P] are
+// device arrays (grad is overwritten).
+paces_status adjoint_backward(paces_sim* s, const double* gbar, double* grad,
+                              hipStream_t st) {
   AdjRecord& R = *s->adj;
   const paces_model* m = s->m;
   const DevModel& dm = m->dm;
@@ -2286,7 +2651,7 @@ paces_status paces_adjoint_backward(paces_sim* s, const double* gbar,
   }
   WorkSpace buf;  // freed on return
   double2 *lamA, *lamB, *b0, *b1, *tx1, *ty1, *accx, *accy, *cn;
-  double *part, *grad, *tau, *w;
+  double *part, *tau, *w;
   ChebCoef* ccj;
   ST_TRY(buf.get(&lamA, maxn));
   ST_TRY(buf.get(&lamB, maxn));
@@ -2298,7 +2663,6 @@ paces_status paces_adjoint_backward(paces_sim* s, const double* gbar,
   ST_TRY(buf.get(&accy, int64_t(nqmax) * maxn));
   ST_TRY(buf.get(&cn, int64_t(kMaxNodes) * kMaxTerms));
   ST_TRY(buf.get(&part, int64_t(1024) * P));
-  ST_TRY(buf.get(&grad, P));
   ST_TRY(buf.get(&tau, int64_t(kMaxNodes + 1) * kMaxNodes));
   ST_TRY(buf.get(&w, int64_t(kMaxNodes + 1) * kMaxNodes));
   ST_TRY(buf.get(&ccj, 1));
@@ -2390,8 +2754,8 @@ paces_status paces_adjoint_backward(paces_sim* s, const double* gbar,
     const int64_t nend = R.steps[end - 1].n_new;
     if (q == nseg - 1) {
       adj_zero(lamA, nend, st);
-      adj_add_psi0(n0, slot[end - 1 - start].p0, s->amps0, gbar[2 * R.n],
-                   gbar[2 * R.n + 1], lamA, s->err, st);
+      adj_add_psi0(n0, slot[end - 1 - start].p0, s->amps0, gbar + 2 * R.n,
+                   lamA, s->err, st);
     } else {
       // lamA holds lambda_end in the order of checkpoint q+1
       adj_permute(dm, m->Wi, R.ck[q + 1]->keys, nend, s->table, s->tmask,
@@ -2415,8 +2779,7 @@ paces_status paces_adjoint_backward(paces_sim* s, const double* gbar,
       // lambda_i = T_i^T mu + gbar_i psi0
       adj_back(ns, z.tmap, b0, lamB, s->err, st);
       const int32_t* p0 = i == start ? R.ck_p0[q] : slot[i - 1 - start].p0;
-      adj_add_psi0(n0, p0, s->amps0, gbar[2 * i], gbar[2 * i + 1], lamB,
-                   s->err, st);
+      adj_add_psi0(n0, p0, s->amps0, gbar + 2 * i, lamB, s->err, st);
       // mu and phi at the quadrature nodes, contracted with dH/dtheta
       const int nqi = nq[i];
       adj_node_coef(z.cc, s->p.dt, tau + nqi * kMaxNodes, nqi, s->p.tol, cn,
@@ -2436,14 +2799,38 @@ paces_status paces_adjoint_backward(paces_sim* s, const double* gbar,
     HIP_TRY(hipStreamSynchronize(st));
     if (*s->h_err) e = fail(PACES_E_STATE, "device error in the adjoint sweep");
   }
-  if (!e) {
-    HIP_TRY(hipMemcpyAsync(grad_out, grad, size_t(P) * 8,
-                           hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-  }
+  if (!e) HIP_TRY(hipStreamSynchronize(st));
   release_store();
   paces_status e2 = restore_snapshot(s, *R.fin, st);
   return e ? e : e2;
+}
+
+paces_status paces_adjoint_backward(paces_sim* s, const double* gbar,
+                                    double* grad_out, void* hip_stream) {
+  if (!s || !gbar || !grad_out) return fail(PACES_E_ARG, "bad arguments");
+  if (!s->adj) return fail(PACES_E_STATE, "no adjoint record");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int P = paces_num_params(s->m);
+  WorkSpace buf;  // freed on return
+  double *g_dev, *grad;
+  ST_TRY(buf.get(&g_dev, 2 * (s->adj->n + 1)));
+  ST_TRY(buf.get(&grad, P));
+  HIP_TRY(hipMemcpyAsync(g_dev, gbar, size_t(2 * (s->adj->n + 1)) * 8,
+                         hipMemcpyHostToDevice, st));
+  ST_TRY(adjoint_backward(s, g_dev, grad, st));
+  HIP_TRY(hipMemcpyAsync(grad_out, grad, size_t(P) * 8, hipMemcpyDeviceToHost,
+                         st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return PACES_OK;
+}
+
+paces_status paces_adjoint_backward_dev(paces_sim* s, const void* dev_gbar,
+                                        void* dev_grad, void* hip_stream) {
+  if (!s || !dev_gbar || !dev_grad) return fail(PACES_E_ARG, "bad arguments");
+  if (!s->adj) return fail(PACES_E_STATE, "no adjoint record");
+  return adjoint_backward(s, static_cast<const double*>(dev_gbar),
+                          static_cast<double*>(dev_grad),
+                          static_cast<hipStream_t>(hip_stream));
 }
 
 paces_status paces_get_tuning(paces_sim* s, paces_tuning* out) {

@@ -117,7 +117,11 @@ def test_checkpoint_interval_does_not_change_gradient():
         assert np.allclose(g, grads[0], rtol=1e-12, atol=1e-14 * np.max(np.abs(grads[0])))
 
 
-def test_autograd_function_gives_the_adjoint_gradient():
+@pytest.mark.parametrize("device", ["cuda", "cpu"])
+def test_autograd_function_gives_the_adjoint_gradient(device):
+    """AutocorrFn keeps a(t), the incoming gradient and dL/dtheta on the
+    GPU (device-buffer adjoint entry points) and returns the gradient on
+    theta's device; against the oracle's gradient."""
     import torch
     name, steps, ckpt, over = CASES["ring"]
     cfg = dict(WL.CONFIGS[name])
@@ -125,17 +129,46 @@ def test_autograd_function_gives_the_adjoint_gradient():
     p = WL.model_params(cfg)
     run = WL.run_params(cfg)
     init = WL.initial_state(cfg)
-    theta = torch.tensor(P.theta_of(p), dtype=torch.float64, requires_grad=True)
+    theta = torch.tensor(P.theta_of(p), dtype=torch.float64, device=device,
+                         requires_grad=True)
     a = P.AutocorrFn.apply(theta, p, run, init, steps, ckpt)
     assert a.dtype == torch.complex128 and a.shape == (steps + 1,)
-    tau = torch.from_numpy(target(a.detach().numpy()))
+    assert a.is_cuda
+    a_host = a.detach().cpu().numpy()
+    tau = torch.from_numpy(target(a_host)).to(a.device)
     loss = ((a - tau).abs() ** 2).sum()
     loss.backward()
+    assert theta.grad.device == theta.device
     om = O.Model(p)
     f = O.Frozen(om, run, *init, steps)
-    _, g_orc = f.grad(om, a.detach().numpy() - tau.numpy())
-    g = theta.grad.numpy()
+    _, g_orc = f.grad(om, a_host - tau.cpu().numpy())
+    g = theta.grad.cpu().numpy()
     assert np.max(np.abs(g - g_orc)) <= 1e-8 * np.max(np.abs(g_orc))
+
+
+def test_device_buffer_adjoint_matches_host_buffers():
+    """paces_adjoint_forward_dev / backward_dev against the host-buffer
+    entry points on the same recorded run: a bit for bit, the gradient
+    bit for bit (same kernels, same order)."""
+    import torch
+    name, steps, ckpt, over = CASES["ring"]
+    cfg = dict(WL.CONFIGS[name])
+    cfg.update(over)
+    p = WL.model_params(cfg)
+    init = WL.initial_state(cfg)
+    hs = P.Sim(P.Model(p), WL.run_params(cfg), *init)
+    a_h = hs.adjoint_forward(steps, ckpt)
+    ds = P.Sim(P.Model(p), WL.run_params(cfg), *init)
+    a_d = torch.empty(steps + 1, dtype=torch.complex128, device="cuda")
+    ds.adjoint_forward_dev(steps, a_d, ckpt)
+    assert np.array_equal(a_d.cpu().numpy(), a_h)
+    gbar = (a_h - target(a_h))
+    g_h = hs.adjoint_backward(gbar)
+    g_d = torch.zeros(ds.model.n_params, dtype=torch.float64, device="cuda")
+    ds.adjoint_backward_dev(torch.from_numpy(gbar).to("cuda"), g_d)
+    assert np.array_equal(g_d.cpu().numpy(), g_h)
+    with pytest.raises(ValueError):
+        ds.adjoint_backward_dev(torch.from_numpy(gbar), g_d)
 
 
 def test_adjoint_rejects_what_it_does_not_support():

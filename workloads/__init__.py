@@ -217,3 +217,29 @@ def random_amplitudes(seed, n):
         ph = 2.0 * math.pi * u2
         out += [mag * math.cos(ph), mag * math.sin(ph)]
     return out
+
+
+def phonon_ball_state(cfg, n_max, seed=7):
+    """Every basis state of a single-mode lattice with at most n_max phonons
+    in total (any exciton site), with seeded complex normal amplitudes
+    normalised to one: (exc, occ, coef) as for initial_state.  A set that
+    is closed under hopping and cut at a total phonon number, of size
+    N * C(N + n_max, n_max)."""
+    import itertools
+    import numpy as np
+    N = n_sites(cfg)
+    cut = cfg["cutoff"][0]
+    vecs = []
+    for n in range(n_max + 1):
+        for combo in itertools.combinations_with_replacement(range(N), n):
+            v = np.bincount(np.asarray(combo, dtype=np.int64), minlength=N)
+            if v.max(initial=0) <= cut:
+                vecs.append(v)
+    occ1 = np.asarray(vecs, dtype=np.uint16)
+    exc = np.repeat(np.arange(N, dtype=np.int32), len(occ1))
+    occ = np.tile(occ1, (N, 1))
+    rng = np.random.default_rng(seed)
+    c = rng.standard_normal(len(exc)) + 1j * rng.standard_normal(len(exc))
+    c /= np.linalg.norm(c)
+    coef = np.ascontiguousarray(c.astype(np.complex128)).view(np.float64)
+    return exc, occ, coef
