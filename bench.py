@@ -5,23 +5,31 @@ g 1.2, J -1, cutoff 12, k=0 Bloch start, dt 0.01, neighbour order 4,
 amplitude threshold 1e-8, complex128), synthetic inputs only.  A "step" is
 one full time step of the hot path: select, expand (4 rounds), merge,
 transfer, build, Chebyshev propagation and observables.  The run starts
-from the initial state; `--warmup` steps grow the subspace untimed, then
-exactly `--steps` steps are timed between stream synchronisations.
+from the initial state and takes untimed steps until |S| reaches --grow-to
+(default 1e7, where the set no longer fits the last-level cache), runs the
+library's launch autotuner, `--warmup` more untimed steps, then exactly
+`--steps` steps timed between stream synchronisations.
 
 value = sum over timed steps of |S| / wall time (basis-state updates/s).
-roofline: the middle Clenshaw term kernel (the dominant kernel), its
-algorithmic bytes per launch |S| (4A + 4D + 8) over its HIP-event
-duration on the step's stream, from one middle launch per timed step whose
-dispatch records the events.
+roofline: the middle Clenshaw term kernel (the dominant kernel): achieved
+= |S| (5A + 4D + 12) bytes per launch (the per-row, per-term bytes of a
+Chebyshev term: three vector streams of a forward recurrence plus an
+accumulator read and written, the columns and the diagonal) over its
+HIP-event duration on the step's stream, from one middle launch per timed
+step whose dispatch records the events; the kernel's own streams (Clenshaw
+form, 4A + 4D + 8) are reported beside it.  traffic: HBM bytes per launch
+counted on this very window (FETCH_SIZE + WRITE_SIZE) in the committed
+summary of rocprofv3 runs of the default command, when it matches the
+current kernels and window.
 cpu_baseline: the CPU oracle continued from the GPU state at the start of
-the timed window, for a bounded number of steps.
+the timed window on all its threads for a bounded time, and one step on
+one thread.
 forms: the extra forms against plain FP64 single-realization runs on the
 same GPU: complex64 amplitudes on the same window; the order-10 Krylov
 propagator and the truncated Taylor series on the same window from the
-same state; 64 disorder
-realizations of the 6x6 lattice in one sim against realizations run one
-after another; the adjoint gradient of the 12-site ring against its plain
-forward run (time ratio).
+same state; 64 disorder realizations of the 6x6 lattice in one sim against
+realizations run one after another; the adjoint gradient of the 12-site
+ring against its plain forward run (time ratio).
 """
 import argparse
 import json
@@ -38,12 +46,19 @@ HBM_PEAK_GBS = 8000.0
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=130)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--grow-to", type=float, default=1e7,
+                    help="untimed steps from the initial state until |S| "
+                         "reaches this, before the autotuner, --warmup and "
+                         "the timed --steps")
+    ap.add_argument("--grow-max", type=int, default=1000)
     ap.add_argument("--config", default="ring16")
     ap.add_argument("--precision", type=int, default=64)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cpu-single", action="store_true",
+                    help="skip the one-thread oracle step of the CPU baseline")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--tune", default="auto", choices=["auto", "none"],
                     help="run the library's launch autotuner on the warmed-up "
@@ -69,6 +84,14 @@ def main():
                          "aggregate calculation on lattice DIMS (e.g. 64, "
                          "8x8, 2x2x2), H aggregate unless --paper-kind J")
     ap.add_argument("--paper-kind", default="H", choices=["H", "J"])
+    ap.add_argument("--cube4-cap", type=float, default=None, metavar="CAP",
+                    help="instead of the benchmark, run the 3D workload "
+                         "(4x4x4 periodic cubic lattice, two modes, complex64) "
+                         "with a state cap of CAP from its start until the "
+                         "cap binds, then --cube4-steps more steps, and print "
+                         "one JSON line with the times and counts")
+    ap.add_argument("--cube4-steps", type=int, default=10)
+    ap.add_argument("--cube4-max", type=int, default=400)
     ap.add_argument("--paper-krylov", type=int, default=0, metavar="P",
                     help="--paper-1d / --paper-agg with the order-P Krylov "
                          "propagator instead of the series")
@@ -82,9 +105,6 @@ def main():
     ap.add_argument("--paper-periodic", action="store_true",
                     help="--paper-agg with periodic boundaries wherever an "
                          "extent is >= 3 (default: open)")
-    ap.add_argument("--calib-copy-mib", type=int, default=0,
-                    help="run one plain device copy of this size first (a "
-                         "known-size reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library drives one GPU "
@@ -100,13 +120,9 @@ def main():
     if args.paper_1d is not None or args.paper_agg is not None:
         print(json.dumps(paper_run(args)), flush=True)
         return
-    if args.calib_copy_mib:
-        n = args.calib_copy_mib * (1 << 20) // 8
-        src = torch.ones(n, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    if args.cube4_cap is not None:
+        print(json.dumps(cube4_run(args)), flush=True)
+        return
     cfg = dict(WL.CONFIGS[args.config])
     cfg["precision"] = args.precision
     params = WL.model_params(cfg)
@@ -114,11 +130,18 @@ def main():
     exc, occ, coef = WL.initial_state(cfg)
     model = P.Model(params)
     stream = torch.cuda.current_stream()
+    # a plain 1 GiB device copy between the first two marks: the known-size
+    # reference of the hardware byte counters
+    P.profile_mark(0, stream)
+    copy_once(1024)
+    P.profile_mark(1, stream)
     sim = P.Sim(model, run, exc, occ, coef, stream=stream)
+    grown = grow_until(sim, args.grow_to, args.grow_max, stream)
+    print("grown %d steps to |S| = %d" % (grown, sim.size(stream)),
+          file=sys.stderr, flush=True)
+    tuning = sim.autotune(steps=2, stream=stream) if args.tune == "auto" else sim.tuning()
     print("warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
     sim.step(args.warmup, stream=stream)
-    torch.cuda.synchronize()
-    tuning = sim.autotune(steps=2, stream=stream) if args.tune == "auto" else sim.tuning()
     torch.cuda.synchronize()
     nS0 = sim.size(stream)
     forms = not args.no_forms and args.config == "ring16" and args.precision == 64
@@ -130,14 +153,17 @@ def main():
     print("timing %d steps from |S| = %d" % (args.steps, nS0), file=sys.stderr,
           flush=True)
     # the timed window times one middle Clenshaw launch per step, by events
-    # its own dispatch records (no stage markers on the stream)
+    # its own dispatch records (no stage markers on the stream); marks 2
+    # and 3 bracket it for kernel traces and counter runs
     sim.profile(True, kernels_only=True)
     sim.profile_reset()
     torch.cuda.synchronize()
+    P.profile_mark(2, stream)
     t0 = time.perf_counter()
     sim.step(args.steps, stream=stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    P.profile_mark(3, stream)
     prof = sim.profile_get(stream)
     sim.profile(False)
     rec = sim.series(nrec0, args.steps, stream)
@@ -157,12 +183,15 @@ def main():
     D = model.D
     n_term = prof["launches"]["term"]
     term_ms = prof["ms"]["term"] / max(n_term, 1)
-    term_bytes = prof["term_bytes"] / max(n_term, 1)
-    achieved = term_bytes / (term_ms * 1e-3) / 1e9 if n_term else 0.0
+    kern_row = 4 * A + 4 * D + (8 if model.V <= 2 else 16)
+    rows_per_launch = prof["term_bytes"] / max(n_term, 1) / kern_row
+    spec_row = 5 * A + 4 * D + 12
+    achieved = spec_row * rows_per_launch / (term_ms * 1e-3) / 1e9 if n_term else 0.0
+    achieved_k = kern_row * rows_per_launch / (term_ms * 1e-3) / 1e9 if n_term else 0.0
     stage_ms = {k: round(v / args.stage_steps, 4) for k, v in sprof["ms"].items()}
-    row_bytes = 4 * A + 4 * D + (8 if model.V <= 2 else 16)
-    traffic = committed_traffic(args.config, args.precision,
-                                term_bytes / row_bytes if n_term else 0.0)
+    window = {"grown_steps": grown, "warmup": args.warmup, "steps": args.steps,
+              "S_start": int(nS0), "S_end": int(rec[-1, 7])}
+    wprof = committed_window_profile(args, window)
     out = {
         "metric": "basis-state updates/s (|S|*steps/s)",
         "value": value,
@@ -181,30 +210,40 @@ def main():
                                    args.config, WL.n_sites(cfg), cfg["cutoff"][0],
                                    cfg["g"][0], cfg["J"][0], cfg["k"],
                                    cfg["theta"], cfg["dt"]),
-                   "timed_steps": [args.warmup, args.warmup + args.steps],
+                   "grown_steps": grown, "grow_to": args.grow_to,
+                   "timed_steps": [grown + args.warmup,
+                                   grown + args.warmup + args.steps],
                    "S_start": int(nS0), "S_end": int(rec[-1, 7]),
                    "S_mean": updates / args.steps},
         "roofline": {"bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": wprof["traffic_per_launch"] if wprof else None,
                      "kernel": "k_cheb_term (middle Clenshaw term)",
                      "launches": n_term, "avg_ms": term_ms,
                      "sampling": "one middle launch per timed step",
-                     "bytes_per_launch": term_bytes,
-                     "bytes_per_row": row_bytes},
+                     "rows_per_launch": rows_per_launch,
+                     "bytes_per_row": spec_row,
+                     "bytes_per_row_rule": "5A + 4D + 12 per row and term "
+                                           "(forward recurrence with an "
+                                           "accumulator)",
+                     "kernel_bytes_per_row": kern_row,
+                     "achieved_kernel_bytes": achieved_k,
+                     "frac_kernel_bytes": achieved_k / HBM_PEAK_GBS,
+                     "traffic_source": wprof["source"] if wprof else None},
         "stage_ms_per_step": stage_ms,
         "stage_ms_note": "%d further steps after the timed window, with "
                          "stage events" % args.stage_steps,
         "stages": stage_bandwidth(model, A, sprof, srec,
                                   float(rec[-1, 7]), args.stage_steps,
-                                  copy_peak_gbs()),
+                                  copy_peak_gbs(), wprof),
         "tuning": tuning,
         "terms_per_step": float(rec[:, 9].mean()),
     }
     if forms:
         del sim
         out["forms"] = {
-            "fp32": form_fp32(args, rec, elapsed, stream),
+            "fp32": form_fp32(args, grown, rec, elapsed, stream),
             "krylov": form_krylov(args, cpu_state, t_start, rec, elapsed,
                                   stream),
             "taylor": form_taylor(args, cpu_state, t_start, rec, elapsed,
@@ -214,8 +253,38 @@ def main():
         }
     if cpu_state is not None and not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(params, run, cpu_state, cfg,
-                                           args.cpu_seconds)
+                                           args.cpu_seconds,
+                                           not args.no_cpu_single, t_start)
     print(json.dumps(out), flush=True)
+
+
+def grow_until(sim, target, max_steps, stream):
+    """Untimed steps from the initial state until |S| >= target (at most
+    max_steps); returns the number taken."""
+    n = 0
+    while n < max_steps and sim.size(stream) < target:
+        sim.step(1, stream=stream)
+        n += 1
+    return n
+
+
+def copy_once(mib):
+    """One plain device copy of `mib` MiB (read + write), timed by events;
+    returns its bandwidth in GB/s."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    dst.copy_(src)
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b)
+    del src, dst
+    return 2.0 * mib * (1 << 20) / (ms * 1e-3) / 1e9
 
 
 def paper_run(args):
@@ -283,6 +352,60 @@ def paper_run(args):
             "terms_per_step": float(rec[:, 9].mean())}
 
 
+def cube4_run(args):
+    """The 3D workload under its state cap: untimed steps from the start
+    until |S| reaches 90% of the cap (or --cube4-max steps), then
+    --cube4-steps steps timed.  Reports updates/s over the timed steps,
+    the counts, whether every step kept |S| <= cap, and the device memory
+    the sim holds."""
+    import numpy as np
+    import torch
+    import paper_2603_07341_amd as P
+    import workloads as WL
+    cfg = dict(WL.CONFIGS["cube4"])
+    cap = int(args.cube4_cap)
+    run = dict(WL.run_params(cfg), max_states=cap)
+    stream = torch.cuda.current_stream()
+    sim = P.Sim(P.Model(WL.model_params(cfg)), run, *WL.initial_state(cfg),
+                stream=stream)
+    t0 = time.perf_counter()
+    n = 0
+    while n < args.cube4_max:
+        sim.step(1, stream=stream)
+        n += 1
+        last = sim.series(n - 1, 1, stream)[0]
+        if n % 10 == 0 or last[7] >= 0.9 * cap:
+            print("cube4: step %d, |S| %d, |M| %d, %.1f s" % (
+                n, last[7], last[8], time.perf_counter() - t0),
+                file=sys.stderr, flush=True)
+        if last[7] >= 0.9 * cap:
+            break
+    grow_s = time.perf_counter() - t0
+    free0, total = torch.cuda.mem_get_info()
+    _, el = timed(lambda: sim.step(args.cube4_steps, stream=stream))
+    free1, _ = torch.cuda.mem_get_info()
+    rec = sim.series(0, sim.num_records(), stream)
+    tail = rec[n:]
+    print("cube4: %d timed steps, %.2f s" % (args.cube4_steps, el),
+          file=sys.stderr, flush=True)
+    return {"workload": "cube4: 4x4x4 periodic cubic Holstein lattice, modes "
+                        "(1, 1, c 15) and (0.2, 0.5, c 31), J -0.5, k 2, "
+                        "theta 1e-7, dt 0.01, complex64, state cap %d" % cap,
+            "grow_steps": n, "grow_s": grow_s,
+            "timed_steps": args.cube4_steps, "timed_s": el,
+            "ms_per_step": el * 1e3 / args.cube4_steps,
+            "updates_per_s": float(tail[:, 7].sum()) / el,
+            "S_timed": [int(tail[0, 7]), int(tail[-1, 7])],
+            "M_timed": [int(tail[0, 8]), int(tail[-1, 8])],
+            "S_max_all_steps": int(rec[:, 7].max()),
+            "cap_respected": bool(np.all(rec[:, 7] <= cap)),
+            "norm2_end": float(rec[-1, 1]), "mass_total_end": float(rec[-1, 6]),
+            "device_gib_in_use": [(total - free0) / 2 ** 30,
+                                  (total - free1) / 2 ** 30],
+            "device_gib_total": total / 2 ** 30,
+            "terms_per_step": float(tail[:, 9].mean())}
+
+
 def copy_peak_gbs(mib=1024, reps=5):
     """Measured device-copy bandwidth in this run (read + write bytes of a
     plain torch copy of `mib` MiB, best of `reps`), a practical peak beside
@@ -305,10 +428,13 @@ def copy_peak_gbs(mib=1024, reps=5):
     return 2.0 * mib * (1 << 20) / (best * 1e-3) / 1e9
 
 
-def stage_bandwidth(model, A, sprof, srec, n_old0, steps, copy_gbs):
+def stage_bandwidth(model, A, sprof, srec, n_old0, steps, copy_gbs, wprof):
     """Effective bandwidth per stage over the stage-event steps: algorithmic
     bytes (compulsory streams, each once per pass; gathers counted as cache
-    hits) from the steps' own counts, over the stage's event time.
+    hits) from the steps' own counts, over the stage's event time.  With a
+    committed counter profile of this window, each stage also gets its
+    achieved rate: counted HBM bytes (FETCH_SIZE + WRITE_SIZE, calibrated)
+    over kernel time, both per step of the window.
       select        n_old (A + 1) + 4 |M|
       expand+build  |S| (8W + D (8 + 8W + 4) + rho (8W + 16)),
                     rho = net growth of S / |S| (a lower bound on new rows)
@@ -341,6 +467,13 @@ def stage_bandwidth(model, A, sprof, srec, n_old0, steps, copy_gbs):
         out[k] = {"bytes_per_step": b / steps, "ms_per_step": ms[k] / steps,
                   "effective": g, "frac_spec": g / HBM_PEAK_GBS,
                   "frac_copy": g / copy_gbs}
+        st = (wprof or {}).get("stages", {}).get(k)
+        if st and st["kernel_ms"] > 0:
+            ach = st["bytes"] / (st["kernel_ms"] * 1e-3) / 1e9
+            out[k].update({"counted_bytes_per_step": st["bytes"],
+                           "kernel_ms_per_step": st["kernel_ms"],
+                           "achieved": ach,
+                           "achieved_frac_spec": ach / HBM_PEAK_GBS})
     g = tb / tt / 1e9 if tt > 0 else 0.0
     out["total"] = {"effective": g, "frac_spec": g / HBM_PEAK_GBS,
                     "frac_copy": g / copy_gbs}
@@ -356,17 +489,20 @@ def timed(fn):
     return r, time.perf_counter() - t0
 
 
-def form_fp32(args, rec64, el64, stream):
-    """The same window with complex64 amplitudes (FP64 scalars and sums);
-    errors of a(t) and the norm against the FP64 run."""
+def form_fp32(args, grown, rec64, el64, stream):
+    """The same window with complex64 amplitudes (FP64 scalars and sums):
+    the same number of growth and warm-up steps from the initial state,
+    then the timed steps; errors of a(t) and the norm against the FP64
+    run."""
     import numpy as np
     import paper_2603_07341_amd as P
     import workloads as WL
     cfg = dict(WL.CONFIGS["ring16"], precision=32)
     m = P.Model(WL.model_params(cfg))
     s = P.Sim(m, WL.run_params(cfg), *WL.initial_state(cfg), stream=stream)
-    print("fp32: warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
-    s.step(args.warmup, stream=stream)
+    print("fp32: %d + %d steps" % (grown, args.warmup), file=sys.stderr,
+          flush=True)
+    s.step(grown + args.warmup, stream=stream)
     n0 = s.num_records()
     _, el = timed(lambda: s.step(args.steps, stream=stream))
     rec = s.series(n0, args.steps, stream)
@@ -549,64 +685,105 @@ def form_adjoint(args, stream):
 
 
 def source_hash():
-    """Hash of the step kernels' code, comments and blank lines ignored."""
-    import hashlib
-    h = hashlib.sha256()
-    for f in ["kernels.hip", "device.hpp", "kernels.hpp", "common.hpp"]:
-        with open(os.path.join(ROOT, "paper_2603_07341_amd", "csrc", f)) as fh:
-            for line in fh:
-                code = line.split("//")[0].rstrip()
-                if code:
-                    h.update((code + "\n").encode())
-    return h.hexdigest()[:16]
+    from paper_2603_07341_amd.profile_summary import source_hash as h
+    return h()
 
 
-def committed_traffic(config, precision, rows_per_launch):
-    """HBM bytes per middle-term launch from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, calibrated with a plain copy), or None when
-    the kernel sources changed since the counters were taken or the
-    workload differs."""
-    path = os.path.join(ROOT, "profiles", "cheb_term_ring16_traffic.txt")
-    if config != "ring16" or precision != 64 or not os.path.exists(path):
+WINDOW_PROFILE = os.path.join("profiles", "cheb_term_ring16_window.txt")
+
+
+def committed_window_profile(args, window):
+    """Counter figures of this very window from the committed summary of
+    the default command's rocprofv3 runs: the middle Clenshaw term's HBM
+    bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) and counted
+    bytes and kernel time per stage.  None unless the summary was taken on
+    the current kernel sources (comments ignored) and on the same window
+    (growth, warm-up and timed steps, |S| at both ends)."""
+    path = os.path.join(ROOT, WINDOW_PROFILE)
+    if args.config != "ring16" or args.precision != 64 or not os.path.exists(path):
         return None
-    vals = {}
+    vals, stages = {}, {}
     with open(path) as fh:
         for line in fh:
-            if "sha256[:16]" in line:
-                vals["sha"] = line.rsplit(":", 1)[1].strip()
-            elif line.startswith(("fetch_bytes_per_row:", "write_bytes_per_row:")):
-                k, v = line.split(":")
-                vals[k] = float(v)
-    if vals.get("sha") != source_hash() or len(vals) < 3:
+            if ":" not in line or line.startswith("#"):
+                continue
+            k, v = line.split(":", 1)
+            k, v = k.strip(), v.strip()
+            if k.startswith("stage "):
+                name, what = k[6:].rsplit(" ", 1)
+                stages.setdefault(name, {})[what] = float(v)
+            else:
+                vals[k] = v
+    try:
+        ok = (vals.get("kernel_sha") == source_hash() and
+              all(int(vals.get("window_" + f, -1)) == window[f]
+                  for f in ("grown_steps", "warmup", "steps", "S_start",
+                            "S_end")))
+        if not ok:
+            return None
+        return {"traffic_per_launch": float(vals["mid_term_bytes_per_launch"]),
+                "stages": {k: {"bytes": v["bytes"], "kernel_ms": v["kernel_ms"]}
+                           for k, v in stages.items()
+                           if "bytes" in v and "kernel_ms" in v},
+                "source": WINDOW_PROFILE}
+    except (KeyError, ValueError):
         return None
-    return (vals["fetch_bytes_per_row"] + vals["write_bytes_per_row"]) * rows_per_launch
 
 
-def cpu_baseline(params, run, state, cfg, budget_s):
-    """The CPU oracle continued from the GPU state for as many whole steps
-    as fit in the budget (at least one)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(params, run, state, cfg, budget_s, single, t_start):
+    """The CPU oracle continued from the GPU state at the start of the timed
+    window (the same |S| range): on all the threads the oracle runs with,
+    for as many whole steps as fit in the budget (at least one); then, with
+    one thread, one step from the same state."""
     from oracle import oracle as O
     import workloads as WL
     keys, amps = state
     om = O.Model(params)
     exc, occ, coef = WL.initial_state(cfg)
-    s = O.Sim(om, run, exc, occ, coef)
-    s.set_state(keys, amps, 0.0)
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        s.step(1)
-        n += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    el = time.perf_counter() - t0
-    upd = sum(o["n_S"] for o in s.observations())
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": upd / el, "unit": "updates/s", "cores": cores,
-            "kind": "oracle",
-            "sample": "%d step(s) continued from the GPU state at the start "
-                      "of the timed window (|S| %d -> %d), %.1f s" % (
-                          n, len(keys), int(s.observations()[-1]["n_S"]), el)}
+
+    def leg(max_s, max_steps):
+        s = O.Sim(om, run, exc, occ, coef)
+        s.set_state(keys, amps, t_start)
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            s.step(1)
+            n += 1
+            if n >= max_steps or time.perf_counter() - t0 >= max_s:
+                break
+        el = time.perf_counter() - t0
+        upd = sum(o["n_S"] for o in s.observations())
+        return upd / el, n, el, int(s.observations()[-1]["n_S"])
+
+    cores = O.threads()
+    v, n, el, s_end = leg(budget_s, 1 << 30)
+    out = {"value": v, "unit": "updates/s", "cores": cores, "kind": "oracle",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+           "sample": "%d step(s) continued from the GPU state at the start "
+                     "of the timed window (|S| %d -> %d), %.1f s on %d "
+                     "threads" % (n, len(keys), s_end, el, cores)}
+    if single:
+        O.set_threads(1)
+        try:
+            v1, n1, el1, s1 = leg(0.0, 1)
+        finally:
+            O.set_threads(cores)
+        out["single_thread"] = {
+            "value": v1, "unit": "updates/s", "cores": 1,
+            "sample": "1 step from the same state (|S| %d -> %d), %.1f s" % (
+                len(keys), s1, el1)}
+    return out
 
 
 if __name__ == "__main__":
