@@ -121,12 +121,15 @@ def dropped(prev_keys, prev_amps, new_keys):
 
 
 def check_obs(go, oo, tol, width=None, N=None, drop=None, steps_before=0,
-              mass_total_bound=None):
+              mass_total_bound=None, mass_prior=0.0):
     """Observables within tol * (|o| + s_o): s_o = 1 for norm and
     autocorrelation, the spectral width for the energy, 1/N for P(j).
     With drop = (n_drop, cmax) given, the discarded weight of the step (and
     the cumulative one, within mass_total_bound when given) is held to the
-    bound of mass_bound instead of tol * (|o| + 1)."""
+    bound of mass_bound instead of tol * (|o| + 1); the cumulative weight
+    of a run that has diverged for several steps also carries mass_prior,
+    the sum of the earlier steps' bounds.  Returns the step's bound (0
+    without drop)."""
     for f in ["norm2", "a_re", "a_im"]:
         assert abs(go[f] - oo[f]) <= tol * (abs(oo[f]) + 1.0), (f, go[f], oo[f])
     if drop is not None:
@@ -134,7 +137,7 @@ def check_obs(go, oo, tol, width=None, N=None, drop=None, steps_before=0,
         assert abs(go["mass_step"] - oo["mass_step"]) <= b, \
             ("mass_step", go["mass_step"], oo["mass_step"], b)
         bt = b if mass_total_bound is None else mass_total_bound
-        bt += 4.0 * unit_roundoff(1e-10) * abs(oo["mass_total"])
+        bt += mass_prior + 4.0 * unit_roundoff(1e-10) * abs(oo["mass_total"])
         assert abs(go["mass_total"] - oo["mass_total"]) <= bt, \
             ("mass_total", go["mass_total"], oo["mass_total"], bt)
     else:
@@ -147,6 +150,7 @@ def check_obs(go, oo, tol, width=None, N=None, drop=None, steps_before=0,
         assert go[f] == oo[f], (f, go[f], oo[f])
     sN = 1.0 / len(oo["pop"])
     assert np.all(np.abs(go["pop"] - oo["pop"]) <= tol * (np.abs(oo["pop"]) + sN))
+    return b if drop is not None else 0.0
 
 
 def check_series(gobs, oobs, tol, theta, n_first, first_diverged=0):

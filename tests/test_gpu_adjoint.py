@@ -148,8 +148,9 @@ def test_autograd_function_gives_the_adjoint_gradient(device):
 
 def test_device_buffer_adjoint_matches_host_buffers():
     """paces_adjoint_forward_dev / backward_dev against the host-buffer
-    entry points on the same recorded run: a bit for bit, the gradient
-    bit for bit (same kernels, same order)."""
+    entry points on the same recorded run: a bit for bit (no reduction
+    feeds it), the gradient to rounding (the per-site sums of the epsilon
+    components are LDS atomics, whose order is not fixed)."""
     import torch
     name, steps, ckpt, over = CASES["ring"]
     cfg = dict(WL.CONFIGS[name])
@@ -166,7 +167,8 @@ def test_device_buffer_adjoint_matches_host_buffers():
     g_h = hs.adjoint_backward(gbar)
     g_d = torch.zeros(ds.model.n_params, dtype=torch.float64, device="cuda")
     ds.adjoint_backward_dev(torch.from_numpy(gbar).to("cuda"), g_d)
-    assert np.array_equal(g_d.cpu().numpy(), g_h)
+    g_d = g_d.cpu().numpy()
+    assert np.max(np.abs(g_d - g_h)) <= 1e-13 * np.max(np.abs(g_h))
     with pytest.raises(ValueError):
         ds.adjoint_backward_dev(torch.from_numpy(gbar), g_d)
 

@@ -42,6 +42,7 @@ def test_capped_steps_match_oracle(cap, over):
     _, _, free = pair(0, **over)
     free.step(12)
     assert max(o["n_S"] for o in free.observations()) > cap  # the cap binds
+    acc = 0.0
     for step in range(12):
         prev = os_.state()
         gs.step(1)
@@ -55,8 +56,9 @@ def test_capped_steps_match_oracle(cap, over):
         ok, oa = os_.state()
         assert np.array_equal(gk, ok)
         assert_amps(ga, oa, 1e-10, steps=step + 1)
-        check_obs(go, oo, 1e-10, width=oo["E_max"] - oo["E_min"],
-                  drop=dropped(prev[0], prev[1], ok), steps_before=step)
+        acc += check_obs(go, oo, 1e-10, width=oo["E_max"] - oo["E_min"],
+                         drop=dropped(prev[0], prev[1], ok), steps_before=step,
+                         mass_prior=acc)
 
 
 def test_cap_binds_and_matches_uncapped_until_it_does():

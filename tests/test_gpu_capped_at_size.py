@@ -38,6 +38,8 @@ def grow_until_capped(sim, R, cap, max_steps, settle=3):
     for step in range(max_steps):
         sim.step(1)
         last = records(sim, sim.num_records() - 1, 1)[0]
+        print("step %d: |S| per realization %s" % (step, last[:, 7].astype(np.int64)),
+              flush=True)
         if np.all(last[:, 7] >= 0.9 * cap):
             break
     else:
@@ -56,6 +58,8 @@ def redo_capped_step(sim, params, cfg, run, r, cap):
     sel = real == r
     k0, a0 = keys[sel], amps[sel]
     sim.step(1)
+    print("oracle redoes one step of realization %d from %d rows" % (r, len(k0)),
+          flush=True)
     os_ = O.Sim(O.Model(params), run, *WL.initial_state(cfg))
     os_.set_state(k0, a0, rec[-1, r, 0])
     os_.set_prev_counts(rec[-1, r, 7], rec[-1, r, 8])

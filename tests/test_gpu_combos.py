@@ -27,8 +27,10 @@ def pair(run_over, **over):
     return cfg, P.Sim(P.Model(p), run, *init), O.Sim(O.Model(p), run, *init)
 
 
-def check(gs, os_, prev, steps, tol=1e-10):
-    """prev: the oracle's state before the step; steps: steps run."""
+def check(gs, os_, prev, steps, tol=1e-10, mass_prior=0.0):
+    """prev: the oracle's state before the step; steps: steps run;
+    mass_prior: the earlier steps' discarded-weight bounds.  Returns the
+    step's bound."""
     for which in (O.SET_M, O.SET_S):
         assert_same_set(gs.get_set(which), os_.get_set(which), "set %d" % which)
     gk, ga = sort_rows(*gs.state())
@@ -36,19 +38,21 @@ def check(gs, os_, prev, steps, tol=1e-10):
     assert np.array_equal(gk, ok)
     assert_amps(ga, oa, tol, steps=steps)
     go, oo = gs.observations()[-1], os_.observations()[-1]
-    check_obs(go, oo, tol, width=oo["E_max"] - oo["E_min"],
-              drop=dropped(prev[0], prev[1], ok), steps_before=steps - 1)
+    return check_obs(go, oo, tol, width=oo["E_max"] - oo["E_min"],
+                     drop=dropped(prev[0], prev[1], ok), steps_before=steps - 1,
+                     mass_prior=mass_prior)
 
 
 @pytest.mark.parametrize("prop", PROPAGATORS)
 @pytest.mark.parametrize("trunc", [dict(max_states=400), dict(q_nom=60)])
 def test_truncation_rules_with_every_propagator(prop, trunc):
     cfg, gs, os_ = pair(dict(prop, **trunc))
+    acc = 0.0
     for i in range(10):
         prev = os_.state()
         gs.step(1)
         os_.step(1)
-        check(gs, os_, prev, i + 1)
+        acc += check(gs, os_, prev, i + 1, mass_prior=acc)
         if "max_states" in trunc:
             assert gs.observations()[-1]["n_S"] <= trunc["max_states"]
 

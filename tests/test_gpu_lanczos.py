@@ -31,9 +31,10 @@ def pair(name, order, **over):
     return cfg, P.Sim(P.Model(params), run, *init), O.Sim(O.Model(params), run, *init)
 
 
-def check_step(gs, os_, tol, prev=None, steps=1):
+def check_step(gs, os_, tol, prev=None, steps=1, mass_prior=0.0):
     """prev: the oracle's state the step started from (keys, amps), for
-    the rows it dropped; steps: steps since the common state."""
+    the rows it dropped; steps: steps since the common state; mass_prior:
+    the earlier steps' discarded-weight bounds.  Returns the step's bound."""
     for which in (O.SET_M, O.SET_S):
         assert_same_set(gs.get_set(which), os_.get_set(which), "set %d" % which)
     gk, ga = sort_rows(*gs.state())
@@ -42,11 +43,12 @@ def check_step(gs, os_, tol, prev=None, steps=1):
     assert_amps(ga, oa, tol, steps=steps)
     go, oo = gs.observations()[-1], os_.observations()[-1]
     drop = dropped(prev[0], prev[1], ok) if prev is not None else None
-    check_obs(go, oo, tol, width=oo["E_max"] - oo["E_min"], drop=drop,
-              steps_before=steps - 1)
+    b = check_obs(go, oo, tol, width=oo["E_max"] - oo["E_min"], drop=drop,
+                  steps_before=steps - 1, mass_prior=mass_prior)
     assert go["K"] == oo["terms"]
     for f in ("E_min", "E_max"):
         assert go[f] == pytest.approx(oo[f], rel=tol, abs=1e-12), f
+    return b
 
 
 @pytest.mark.parametrize("name,steps,order", [("ring16", 12, 10),
@@ -68,11 +70,13 @@ def test_single_step_parity(name, steps, order):
 def test_multi_step_runs_match_oracle(order):
     cfg, gs, os_ = pair("ring12", order, extent=[6, 1, 1], cutoff=[4],
                         theta=1e-6)
+    acc = 0.0
     for i in range(15):
         prev = os_.state()
         gs.step(1)
         os_.step(1)
-        check_step(gs, os_, 1e-10, prev=prev, steps=i + 1)
+        acc += check_step(gs, os_, 1e-10, prev=prev, steps=i + 1,
+                          mass_prior=acc)
 
 
 @pytest.mark.parametrize("name,steps", [("ring16", 12), ("sq6x6", 4)])
