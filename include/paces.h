@@ -275,6 +275,23 @@ paces_status paces_expmv(const paces_model* m, int64_t n, const void* dev_keys,
                          const void* dev_phi, double dt, void* dev_psi,
                          void* hip_stream);
 
+/* paces_expmv without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, result and checks as
+ * paces_expmv; the work memory is a static device array of 64 MiB
+ * (67108864 bytes) per GPU, held until the process ends, instead of the
+ * allocator.  A set whose work memory (64-128 bytes per row plus a hash
+ * table of at least two slots of 8 bytes per row; about 600 000 rows of
+ * ring16 keys) exceeds it returns PACES_E_CAPACITY before any device work.
+ * Calls on one GPU share that array: calls that overlap in time on the same
+ * GPU (other host threads, other streams) race and give wrong results;
+ * serialise them.  Every call clears what it reads back (control block,
+ * error latch, hash table) itself.  Runs on hip_stream and synchronises it
+ * before returning. */
+paces_status paces_expmv_static(const paces_model* m, int64_t n,
+                                const void* dev_keys, const void* dev_phi,
+                                double dt, void* dev_psi, void* hip_stream);
+
 /* Piecewise-constant H(t): later steps of the sim use model m, which must
  * have the sim's shape (lattice, modes, cutoffs, realizations); only J,
  * g, omega and eps may differ.  The caller keeps m alive while the sim

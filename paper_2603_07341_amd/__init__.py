@@ -40,7 +40,7 @@ EXPORTS = [
     "paces_adjoint_replay", "paces_adjoint_backward", "paces_set_allocator",
     "paces_model_key_words", "paces_series_field", "paces_set_model",
     "paces_run_stage", "paces_adjoint_forward_dev", "paces_adjoint_backward_dev",
-    "paces_profile_mark", "paces_expmv",
+    "paces_profile_mark", "paces_expmv", "paces_expmv_static",
 ]
 
 
@@ -198,6 +198,13 @@ class Model:
         uint64 words; phi: complex128 cuda tensor [n]; returns psi (a new
         tensor, or `out`)."""
         return self._expmv(lib().paces_expmv, keys, phi, dt, out, stream)
+
+    def expmv_static(self, keys, phi, dt, out=None, stream=None):
+        """expmv without allocation (paces_expmv_static): the library's work
+        memory is a fixed 64 MiB device array; larger sets raise
+        PacesError (PACES_E_CAPACITY).  Pass `out` to allocate nothing on
+        this side either."""
+        return self._expmv(lib().paces_expmv_static, keys, phi, dt, out, stream)
 
     def _expmv(self, fn, keys, phi, dt, out, stream):
         n = phi.numel()

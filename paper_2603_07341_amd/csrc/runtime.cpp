@@ -1757,6 +1757,35 @@ paces_status expmv_run(const paces_model* m, int64_t n, const uint64_t* keys,
   return expmv_latch(he);
 }
 
+// Work memory of paces_expmv_static: one file-scope array, which every GPU
+// the library runs on holds until the process ends.  Host code never uses
+// the array's name as an address: each device's copy is found once by
+// hipGetSymbolAddress with that device current and kept in g_static_work.
+constexpr size_t kStaticWorkBytes = size_t(64) << 20;
+static __device__ __align__(256) uint8_t scratch[kStaticWorkBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_work[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`.
+paces_status static_work(void** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(PACES_E_UNSUPPORTED, "device index beyond the static table");
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (!g_static_work[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(PACES_E_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                   hipGetErrorString(e));
+    g_static_work[dev] = p;
+  }
+  *out = g_static_work[dev];
+  return PACES_OK;
+}
+
 paces_status expmv_args(const paces_model* m, int64_t n, const void* keys,
                         const void* phi, double dt, const void* psi) {
   if (!m || n < 0 || (n > 0 && (!keys || !phi || !psi)) || !std::isfinite(dt))
@@ -1914,6 +1943,24 @@ paces_status paces_expmv(const paces_model* m, int64_t n, const void* dev_keys,
   (void)hipStreamSynchronize(st);
   dev_free(work);
   return e;
+}
+
+paces_status paces_expmv_static(const paces_model* m, int64_t n,
+                                const void* dev_keys, const void* dev_phi,
+                                double dt, void* dev_psi, void* hip_stream) {
+  ST_TRY(expmv_args(m, n, dev_keys, dev_phi, dt, dev_psi));
+  if (n == 0) return PACES_OK;
+  const size_t need = expmv_layout(m, n).total;
+  if (need > kStaticWorkBytes)
+    return fail(PACES_E_CAPACITY,
+                std::to_string(n) + " rows need " + std::to_string(need) +
+                    " bytes of work memory, above the static " +
+                    std::to_string(kStaticWorkBytes) + " bytes");
+  void* work = nullptr;
+  ST_TRY(static_work(&work));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  return expmv_run(m, n, static_cast<const uint64_t*>(dev_keys), dev_phi, dt,
+                   dev_psi, static_cast<uint8_t*>(work), st);
 }
 
 paces_status paces_free_model(paces_model* m) {
