@@ -66,6 +66,10 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=40)
     ap.add_argument("--batch-singles", type=int, default=8)
     ap.add_argument("--adjoint-steps", type=int, default=200)
+    ap.add_argument("--long-steps", type=int, default=500,
+                    help="steps of the complex64 vs complex128 long run")
+    ap.add_argument("--long-cap", type=float, default=2e6,
+                    help="state cap of the long run")
     ap.add_argument("--krylov-order", type=int, default=10)
     ap.add_argument("--stage-steps", type=int, default=5)
     ap.add_argument("--paper-1d", type=float, default=None, metavar="G",
@@ -244,6 +248,7 @@ def main():
         del sim
         out["forms"] = {
             "fp32": form_fp32(args, grown, rec, elapsed, stream),
+            "fp32_long": form_fp32_long(args, stream),
             "krylov": form_krylov(args, cpu_state, t_start, rec, elapsed,
                                   stream),
             "taylor": form_taylor(args, cpu_state, t_start, rec, elapsed,
@@ -474,6 +479,17 @@ def stage_bandwidth(model, A, sprof, srec, n_old0, steps, copy_gbs, wprof):
                            "kernel_ms_per_step": st["kernel_ms"],
                            "achieved": ach,
                            "achieved_frac_spec": ach / HBM_PEAK_GBS})
+    # steps that expand from the previous graph move the rows, phi and the
+    # dropped weight inside the expansion: the transfer stage keeps only
+    # the fold of the weight, so the two are also given together
+    b = by["expand+build"] + by["transfer"]
+    t = (ms["expand+build"] + ms["transfer"]) * 1e-3
+    g = b / t / 1e9 if t > 0 else 0.0
+    out["expand+transfer+build"] = {
+        "bytes_per_step": b / steps,
+        "ms_per_step": (ms["expand+build"] + ms["transfer"]) / steps,
+        "effective": g, "frac_spec": g / HBM_PEAK_GBS,
+        "frac_copy": g / copy_gbs}
     g = tb / tt / 1e9 if tt > 0 else 0.0
     out["total"] = {"effective": g, "frac_spec": g / HBM_PEAK_GBS,
                     "frac_copy": g / copy_gbs}
@@ -514,6 +530,70 @@ def form_fp32(args, grown, rec64, el64, stream):
             "max_abs_err_autocorr_vs_fp64": float(np.max(np.abs(a32 - a64))),
             "max_rel_err_norm_vs_fp64": float(np.max(np.abs(rec[:, 1] / rec64[:, 1] - 1))),
             "S_mean_fp32_over_fp64": float(rec[:, 7].sum() / rec64[:, 7].sum())}
+
+
+def form_fp32_long(args, stream):
+    """complex64 against complex128 over a long run of the same workload
+    under a state cap (the free run passes 1e8 states near step 270, so the
+    long run is held at the benchmark's window size): both from the initial
+    state in lockstep; the first step whose set differs (count, selection
+    or spectral bounds, which depend on the set alone; the sets themselves
+    at the end), the weight of the symmetric difference of the two sets
+    there, and the largest errors of a(t) and the norm before it."""
+    import numpy as np
+    import paper_2603_07341_amd as P
+    import workloads as WL
+    n, cap = args.long_steps, int(args.long_cap)
+    sims = {}
+    for prec in (64, 32):
+        cfg = dict(WL.CONFIGS["ring16"], precision=prec)
+        run = dict(WL.run_params(cfg), max_states=cap)
+        sims[prec] = P.Sim(P.Model(WL.model_params(cfg)), run,
+                           *WL.initial_state(cfg), stream=stream)
+    print("fp32 long: %d steps, state cap %d" % (n, cap), file=sys.stderr,
+          flush=True)
+    first, sym = None, None
+    da = dn = 0.0
+    t0 = time.perf_counter()
+    for i in range(n):
+        for prec in (64, 32):
+            sims[prec].step(1, stream=stream)
+        r64 = sims[64].series(i, 1, stream)[0]
+        r32 = sims[32].series(i, 1, stream)[0]
+        same = (r64[7] == r32[7] and r64[8] == r32[8] and r64[10] == r32[10]
+                and r64[11] == r32[11])
+        if first is None and not same:
+            first = i + 1
+            k64, a64 = sims[64].state(stream)
+            k32, a32 = sims[32].state(stream)
+            row = np.dtype((np.void, 8 * k64.shape[1]))
+            v64 = np.ascontiguousarray(k64).view(row).ravel()
+            v32 = np.ascontiguousarray(k32).view(row).ravel()
+            only64 = ~np.isin(v64, v32)
+            only32 = ~np.isin(v32, v64)
+            sym = {"step": first, "S_fp64": int(len(k64)), "S_fp32": int(len(k32)),
+                   "rows_only_fp64": int(only64.sum()),
+                   "rows_only_fp32": int(only32.sum()),
+                   "weight_only_fp64": float(np.sum(np.abs(a64[only64]) ** 2)),
+                   "weight_only_fp32": float(np.sum(np.abs(a32[only32]) ** 2))}
+        if first is None:
+            da = max(da, float(abs((r32[3] + 1j * r32[4]) - (r64[3] + 1j * r64[4]))))
+            dn = max(dn, float(abs(r32[1] / r64[1] - 1)))
+    el = time.perf_counter() - t0
+    k64, _ = sims[64].state(stream)
+    k32, _ = sims[32].state(stream)
+    s64 = {bytes(r) for r in np.ascontiguousarray(k64)}
+    s32 = {bytes(r) for r in np.ascontiguousarray(k32)}
+    rec = sims[64].series(0, n, stream)
+    return {"steps": n, "state_cap": cap, "seconds_both": el,
+            "S_end_fp64": int(len(k64)), "S_end_fp32": int(len(k32)),
+            "cap_binds_from_step": int(np.argmax(rec[:, 7] > 0.9 * cap)) + 1
+            if np.any(rec[:, 7] > 0.9 * cap) else None,
+            "first_divergent_step": first,
+            "symmetric_difference_there": sym,
+            "sets_equal_at_end": s64 == s32,
+            "max_abs_err_autocorr_before_divergence": da,
+            "max_rel_err_norm_before_divergence": dn}
 
 
 def form_krylov(args, state, t_start, rec_ref, el_ref, stream):
@@ -636,9 +716,11 @@ def form_batched(args, stream):
 def form_adjoint(args, stream):
     """Adjoint gradient of L = sum_t |a(t) - tau(t)|^2 on the 12-site ring
     (checkpoint every 50; 200 steps by default, by which |S| passes 9e6 and
-    keeps growing): time of the recorded forward and of the backward sweep
-    (segment replays included) against a plain forward run of the same
-    steps, and a central-difference check of two gradient entries."""
+    keeps growing), tau the a(t) of a free run with perturbed parameters (J
+    + 0.05, g - 0.05, omega + 0.02, eps + N(0, 0.02)): time of the recorded
+    forward and of the backward sweep (segment replays included) against a
+    plain forward run of the same steps, and central differences (h = 1e-6)
+    of the frozen-set replay along every parameter against the gradient."""
     import numpy as np
     import paper_2603_07341_amd as P
     import workloads as WL
@@ -648,6 +730,12 @@ def form_adjoint(args, stream):
     init = WL.initial_state(cfg)
     print("adjoint: %d steps, checkpoint every %d" % (n, ck), file=sys.stderr,
           flush=True)
+    st = P.Sim(P.Model(WL.adjoint_target_params(cfg)), WL.run_params(cfg),
+               *init, stream=stream)
+    st.step(n, stream=stream)
+    rt = st.series(0, n, stream)
+    tau = np.concatenate([[1.0 + 0j], rt[:, 3] + 1j * rt[:, 4]])
+    del st
     s0 = P.Sim(P.Model(p), WL.run_params(cfg), *init, stream=stream)
     _, el_plain = timed(lambda: s0.step(n, stream=stream))
     S_end = int(s0.observe(stream=stream)["n_S"])
@@ -659,29 +747,41 @@ def form_adjoint(args, stream):
     a, el_fwd = timed(lambda: s.adjoint_forward(n, ck, stream=stream))
     print("adjoint: recorded forward %.2f s" % el_fwd, file=sys.stderr,
           flush=True)
-    rng = np.random.default_rng(43)
-    tau = a * np.exp(1j * 0.05 * rng.standard_normal(len(a)))
     g, el_bwd = timed(lambda: s.adjoint_backward(a - tau, stream=stream))
     print("adjoint: backward %.2f s" % el_bwd, file=sys.stderr, flush=True)
-    # self-check on this run: central differences of the frozen-set replay
-    # along J and eps_0 against the adjoint gradient
+    # central differences of the frozen-set replay along every parameter
     loss = lambda aa: float(np.sum(np.abs(aa - tau) ** 2))
     theta = P.theta_of(p)
-    fd_err = {}
-    for k, name in ((0, "J0"), (len(theta) - m.N, "eps0")):
-        h = 1e-4
-        lp = loss(s.adjoint_replay(P.Model(P.params_with_theta(
-            p, theta + h * (np.arange(len(theta)) == k))), stream=stream))
-        lm = loss(s.adjoint_replay(P.Model(P.params_with_theta(
-            p, theta - h * (np.arange(len(theta)) == k))), stream=stream))
-        fd_err[name] = abs((lp - lm) / (2 * h) - g[k]) / max(abs(g[k]), 1e-300)
+    h = 1e-6
+    fd = np.zeros(len(theta))
+    t0 = time.perf_counter()
+    for k in range(len(theta)):
+        e = h * (np.arange(len(theta)) == k)
+        lp = loss(s.adjoint_replay(P.Model(P.params_with_theta(p, theta + e)),
+                                   stream=stream))
+        lm = loss(s.adjoint_replay(P.Model(P.params_with_theta(p, theta - e)),
+                                   stream=stream))
+        fd[k] = (lp - lm) / (2 * h)
+    el_fd = time.perf_counter() - t0
+    scale = np.maximum(np.abs(g), 1e-2 * np.max(np.abs(g)))
+    rel = np.abs(fd - g) / scale
+    names = (["J%d" % a for a in range(p["ndim"])] +
+             ["g%d" % v for v in range(p["n_modes"])] +
+             ["omega%d" % v for v in range(p["n_modes"])] +
+             ["eps%d" % j for j in range(m.N)])
     return {"steps": n, "ckpt_every": ck, "S_end": S_end,
+            "target": "a(t) of a free run with J + 0.05, g - 0.05, "
+                      "omega + 0.02, eps + N(0, 0.02) (seed 43)",
+            "loss": loss(a),
             "plain_forward_s": el_plain, "recorded_forward_s": el_fwd,
             "backward_s": el_bwd,
             "adjoint_over_forward": el_bwd / el_plain,
             "forward_plus_backward_over_forward": (el_fwd + el_bwd) / el_plain,
             "grad_inf_norm": float(np.max(np.abs(g))),
-            "fd_rel_err": fd_err}
+            "fd_h": h, "fd_seconds": el_fd,
+            "fd_rel_err_max": float(np.max(rel)),
+            "fd_rel_err_rule": "|fd_p - g_p| / max(|g_p|, 1e-2 max|g|)",
+            "fd_rel_err": {nm: float(x) for nm, x in zip(names, rel)}}
 
 
 def source_hash():

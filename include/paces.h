@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define PACES_ABI_VERSION 11
+#define PACES_ABI_VERSION 12
 
 typedef enum {
   PACES_OK = 0,
@@ -436,8 +436,11 @@ typedef struct {
                           table stays in the last-level cache, a larger
                           one shortens probe chains                       */
   int32_t term_rows;   /* rows per thread of the Clenshaw grid: 1,2,4,8  */
+  int32_t warm;        /* 1: a step expands from the previous step's graph
+                          (its ELL columns and hash table) where one is
+                          there; 0: every step expands from scratch      */
 } paces_tuning;
-/* Default {0, 1, 1}. */
+/* Default {0, 1, 1, 1}. */
 paces_status paces_get_tuning(paces_sim* s, paces_tuning* out);
 /* May reallocate the hash table (synchronises). */
 paces_status paces_set_tuning(paces_sim* s, const paces_tuning* t,

@@ -84,7 +84,7 @@ class _Profile(C.Structure):
 
 class _Tuning(C.Structure):
     _fields_ = [("graph", C.c_int32), ("table_shift", C.c_int32),
-                ("term_rows", C.c_int32)]
+                ("term_rows", C.c_int32), ("warm", C.c_int32)]
 
 
 _lib = None
@@ -433,15 +433,16 @@ class Sim:
         t = _Tuning()
         _check(lib().paces_get_tuning(self.h, C.byref(t)))
         return {"graph": t.graph, "table_shift": t.table_shift,
-                "term_rows": t.term_rows}
+                "term_rows": t.term_rows, "warm": t.warm}
 
     def set_tuning(self, graph=None, table_shift=None, term_rows=None,
-                   stream=None):
+                   warm=None, stream=None):
         cur = self.tuning()
         t = _Tuning()
         t.graph = cur["graph"] if graph is None else int(graph)
         t.table_shift = cur["table_shift"] if table_shift is None else table_shift
         t.term_rows = cur["term_rows"] if term_rows is None else term_rows
+        t.warm = cur["warm"] if warm is None else int(warm)
         _check(lib().paces_set_tuning(self.h, C.byref(t), _stream(stream)))
 
     def autotune(self, steps=3, stream=None):
@@ -451,7 +452,7 @@ class Sim:
         _check(lib().paces_autotune(self.h, C.c_int32(steps), C.byref(t),
                                     _stream(stream)))
         return {"graph": t.graph, "table_shift": t.table_shift,
-                "term_rows": t.term_rows}
+                "term_rows": t.term_rows, "warm": t.warm}
 
     # ---- adjoint gradient (Form (3)) ----
     def adjoint_forward(self, steps, ckpt_every=50, stream=None):

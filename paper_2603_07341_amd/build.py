@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpaces.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["kernels.hip", "adjoint.hip", "cap.hip", "lanczos.hip", "taylor.hip",
+SOURCES = ["kernels.hip", "warm.hip", "adjoint.hip", "cap.hip", "lanczos.hip", "taylor.hip",
            "runtime.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

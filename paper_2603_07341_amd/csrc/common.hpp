@@ -232,6 +232,15 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v,
   return base + x - v;
 }
 
+// Per-realization integer counters (deterministic: integer sums commute):
+// LDS bins per block, one global add per nonzero bin.
+__device__ __forceinline__ void count_flush(int R, uint32_t* lds,
+                                            uint32_t* global) {
+  __syncthreads();
+  for (int r = threadIdx.x; r < R; r += blockDim.x)
+    if (lds[r]) atomicAdd(&global[r], lds[r]);
+}
+
 // J_k(x) by its power series sum_j (-1)^j (x/2)^(2j+k) / (j! (j+k)!); for
 // x <= 2 every term shrinks and no cancellation occurs.
 __device__ double bessel_series(double x, int k) {

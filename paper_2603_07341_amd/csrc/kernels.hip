@@ -289,14 +289,6 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// Per-realization integer counters (deterministic: integer sums commute):
-// LDS bins per block, one global add per nonzero bin.
-__device__ __forceinline__ void count_flush(int R, uint32_t* lds,
-                                            uint32_t* global) {
-  __syncthreads();
-  for (int r = threadIdx.x; r < R; r += blockDim.x)
-    if (lds[r]) atomicAdd(&global[r], lds[r]);
-}
 
 // ---- insert rows into the cleared table -------------------------------------
 // Row i of the new set is row midx[i] of the old one (keys_o given) or is
@@ -1326,6 +1318,20 @@ void expand_round(const DevModel& m, int Wi, int prec, const Side& n, int r,
   k_expand_link<<<g, kBlock, 0, s>>>(D, ctl, cap, rb.c_ref, rb.crow, col, err);
   k_round_finish<<<1, 1, 0, s>>>(ctl, r, last, cap, err);
   }
+}
+
+void tile_scan(const uint32_t* cnt, const uint32_t* ntiles, int64_t bound,
+               uint32_t* tmp, uint32_t* base, uint32_t* total, int* err,
+               hipStream_t s) {
+  const int gt = tiles_for(bound);
+  k_scan_reduce<<<gt, kBlock, 0, s>>>(cnt, ntiles, tmp, err);
+  k_scan_bsum<<<1, kBlock, 0, s>>>(tmp, ntiles, total, nullptr, err);
+  k_scan_apply<<<gt, kBlock, 0, s>>>(cnt, ntiles, tmp, base, err);
+}
+
+void tile_sums_scan(uint32_t* bsum, const uint32_t* nrows, uint32_t* total,
+                    int* err, hipStream_t s) {
+  k_scan_bsum<<<1, kBlock, 0, s>>>(bsum, nrows, total, nullptr, err);
 }
 
 void lookup_last(const DevModel& m, int Wi, const Side& n, int k,

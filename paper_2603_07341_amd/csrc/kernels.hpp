@@ -44,6 +44,14 @@ struct StepCtl {
   uint32_t r_need;                    // chunks the largest round needs
   uint32_t kmax;                      // largest K over realizations
   uint32_t nrec;                      // steps recorded (R records each)
+  // expansion from the previous step's graph (warm.hpp): new states of
+  // round r are rows [gstart[r], gstart[r+1]) of the new set; w_noc
+  // candidates of the round come from old rows, the rest from the new
+  // states of the round before (first row w_f0); w_nkeep old rows stay;
+  // w_moved is set once the hash table holds the new rows; w_tomb counts
+  // the table entries of dropped rows turned into tombstones by this step
+  uint32_t gstart[kMaxRounds + 2];
+  uint32_t n_staged, w_noc, w_f0, w_nkeep, w_moved, w_tomb;
   double t;                           // time after the last completed step
 };
 
@@ -59,10 +67,15 @@ struct RoundBufs {
   int64_t cand_cap;     // candidates the buffers hold
 };
 
+// Row arrays of one set.  col (ELL columns, D per row) and dist (distance
+// of the row from the step's selection, 0..k) describe the set a step
+// built; dist is written by steps that expand from the previous graph.
 struct Side {
   uint64_t* keys;
   uint64_t* pay;
   uint64_t* tot;
+  int32_t* col;
+  uint8_t* dist;
 };
 
 int supported_words(int W);  // internal word count >= W, or 0
@@ -115,6 +128,16 @@ void expand_round(const DevModel& m, int Wi, int prec, const Side& n, int r,
                   StepCtl* ctl, int64_t cap, int64_t est, uint64_t* table,
                   uint64_t mask, const RoundBufs& rb, int32_t* col, void* phi,
                   int chunks, int* err, hipStream_t s);
+// Exclusive scan of cnt[0, *ntiles) (at most `bound` entries) into base,
+// the total into *total; tmp holds scan_tmp_words(bound) words.
+void tile_scan(const uint32_t* cnt, const uint32_t* ntiles, int64_t bound,
+               uint32_t* tmp, uint32_t* base, uint32_t* total, int* err,
+               hipStream_t s);
+// In place: bsum holds one count per tile of kTile rows over *nrows rows
+// (written by a kernel of the select layout); exclusive scan, total into
+// *total.
+void tile_sums_scan(uint32_t* bsum, const uint32_t* nrows, uint32_t* total,
+                    int* err, hipStream_t s);
 // Columns of frontier k (lookup only); sets ctl->n_new.
 void lookup_last(const DevModel& m, int Wi, const Side& n, int k,
                  StepCtl* ctl, int64_t est, const uint64_t* table,

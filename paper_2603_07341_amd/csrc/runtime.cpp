@@ -33,6 +33,7 @@
 #include "kernels.hpp"
 #include "lanczos.hpp"
 #include "taylor.hpp"
+#include "warm.hpp"
 
 using namespace paces;
 
@@ -298,7 +299,6 @@ struct paces_sim {
   int cur = 0;      // side holding the current set S
   void* vec[4] = {nullptr, nullptr, nullptr, nullptr};
   int ipsi = 0, iphi = 1, ib0 = 2, ib1 = 3;
-  int32_t* col = nullptr;
   uint64_t* table = nullptr;
   uint64_t tmask = 0;        // probe mask of the current step
   uint64_t tmask_alloc = 0;  // allocated table size - 1
@@ -306,6 +306,16 @@ struct paces_sim {
   uint32_t* scan_tmp = nullptr;  // select
   RoundBufs rb{};
   int chunks = 1;  // candidate chunks per expansion round
+
+  // expansion from the previous step's graph (warm.hpp)
+  WarmBufs wb{};
+  bool graph_ok = false;   // side cur holds complete columns and the table
+                           // maps its keys to its rows (probed over tmask)
+  bool warm_step = false;  // the step being run expands from that graph
+  bool last_warm = false;  // the last completed step did
+  int64_t tomb = 0;        // tombstones in the table since it was built
+  int warm_np = 0;         // partial blocks of the dropped weight
+  uint32_t* dcount = nullptr;  // [1] a count read back by the host
 
   // a step run stage by stage (paces_run_stage)
   int staged_next = 0;   // the stage expected next
@@ -388,7 +398,7 @@ struct paces_sim {
   paces_profile acc{};
 
   // launch tuning and captured step graphs
-  paces_tuning tune{0, 1, 1};
+  paces_tuning tune{0, 1, 1, 1};
   hipStream_t cap_stream = nullptr;  // capture only; never runs work
   uint64_t gen = 0;                  // bumped whenever a buffer moves
   struct GraphEntry {
@@ -466,7 +476,9 @@ void free_rows(paces_sim* s) {
   s->rows_bytes = 0;
   for (int q = 0; q < 2; ++q) s->side[q] = Side{};
   for (auto& v : s->vec) v = nullptr;
-  s->col = nullptr;
+  s->wb.remap = nullptr;
+  s->wb.wmask = nullptr;
+  s->graph_ok = false;
   s->midx = nullptr;
   s->scan_tmp = nullptr;
   s->e_row = nullptr;
@@ -479,6 +491,7 @@ void free_cand(paces_sim* s) {
   s->cand_block = nullptr;
   s->cand_bytes = 0;
   s->rb = RoundBufs{};
+  s->wb.wlist = nullptr;
 }
 
 paces_status alloc_cand(paces_sim* s, int64_t want) {
@@ -488,6 +501,7 @@ paces_status alloc_cand(paces_sim* s, int64_t want) {
   pc.add(&s->rb.c_slot, want);
   pc.add(&s->rb.c_ref, want);
   pc.add(&s->rb.crow, want);
+  pc.add(&s->wb.wlist, want);
   pc.add(&s->rb.tile_cnt, tiles);
   pc.add(&s->rb.tile_base, tiles);
   pc.add(&s->rb.scan_tmp, scan_tmp_words(tiles));
@@ -519,7 +533,7 @@ void drop_graphs(paces_sim* s) {
   s->graphs.clear();
 }
 
-// Largest candidate buffer (entries, 12 bytes each plus tile counts); a
+// Largest candidate buffer (entries, 20 bytes each plus tile counts); a
 // round with more candidates runs in chunks of this size.
 constexpr int64_t kCandMax = int64_t(1) << 29;
 
@@ -541,8 +555,9 @@ size_t carried_bytes(const paces_sim* s) {
 struct RowBlock {
   Side sd[2]{};
   void* vec[4] = {nullptr, nullptr, nullptr, nullptr};
-  int32_t* col = nullptr;
   uint32_t *midx = nullptr, *scan = nullptr;
+  uint32_t* remap = nullptr;
+  uint16_t* wmask = nullptr;
   double* erow = nullptr;
   std::vector<void*> kry;
   Pieces pc;
@@ -558,10 +573,13 @@ struct RowBlock {
       pc.add(&sd[q].keys, cap * m->Wi);
       pc.add(&sd[q].pay, cap);
       pc.add(&sd[q].tot, cap);
+      pc.add(&sd[q].col, cap * m->D);
+      pc.add(&sd[q].dist, cap);
     }
     for (int v = 0; v < 4; ++v) pc.add_bytes(&vec[v], size_t(cap) * s->A);
-    pc.add(&col, cap * m->D);
     pc.add(&midx, cap);
+    pc.add(&remap, cap);
+    pc.add(&wmask, cap);
     pc.add(&scan, scan_tmp_words(cap));
     if (m->R > 1) pc.add(&erow, cap);
     for (auto& v : kry) pc.add_bytes(&v, size_t(cap) * s->A);
@@ -580,7 +598,7 @@ bool fits_device(const paces_sim* s, int64_t cap) {
   const double margin = double(size_t(2) << 30) + 0.02 * double(tot);
   const double block = double(RowBlock(s, cap).pc.total());
   const int64_t want = cand_want(s->m, cap);
-  const double cand = want > s->rb.cand_cap ? 12.0 * double(want)
+  const double cand = want > s->rb.cand_cap ? 20.0 * double(want)
                                             : double(s->cand_bytes);
   const bool capbuf = s->p.q_nom > 0 || s->p.max_states > 0;
   const double temp = double(s->nS) * double(carried_bytes(s));
@@ -675,7 +693,9 @@ paces_status grow(paces_sim* s, int64_t new_cap, int64_t min_cap,
   s->side[0] = nb.sd[0];
   s->side[1] = nb.sd[1];
   for (int v = 0; v < 4; ++v) s->vec[v] = nb.vec[v];
-  s->col = nb.col;
+  s->wb.remap = nb.remap;
+  s->wb.wmask = nb.wmask;
+  s->graph_ok = false;  // columns and table are rebuilt by the next step
   s->midx = nb.midx;
   s->scan_tmp = nb.scan;
   s->e_row = nb.erow;
@@ -753,6 +773,7 @@ paces_status upload_state(paces_sim* s, int64_t n,
   }
   s->nS = n;
   s->h.n_old = uint32_t(n);
+  s->graph_ok = false;  // no columns yet: the next step expands from scratch
   return push_ctl(s, st);
 }
 
@@ -794,12 +815,45 @@ void stage_select(paces_sim* s, bool counted, hipStream_t st,
     select_rows(s->prec, s->vec[s->ipsi], s->th2, s->fresh, counted, s->ctl,
                 s->midx, s->scan_tmp, std::min(bucket(s->nS), s->cap), s->err,
                 st);
+  if (s->warm_step)
+    warm_begin(s->m->dm, s->ctl, s->midx, s->side[s->cur], s->cnt, s->nS,
+               s->err, st);
+}
+
+// expand + merge + build of the columns from the previous step's graph:
+// k rounds of the breadth-first search, the new set's size, the old rows
+// moved behind the new ones (with phi and the dropped weight), the
+// state-cap check, the columns, and the table rewritten to the new rows.
+void stage_expand_warm(paces_sim* s, int64_t est, hipStream_t st) {
+  const paces_model* m = s->m;
+  const DevModel& dm = m->dm;
+  const int Wi = m->Wi;
+  const int k = s->p.k;
+  const Side so = s->side[s->cur], sn = s->side[1 - s->cur];
+  Stage sg(s, PACES_STAGE_EXPAND, st);
+  for (int r = 1; r <= k; ++r)
+    warm_round(dm, Wi, s->prec, so, sn, r, s->ctl, s->cap, s->nS, est,
+               s->table, s->tmask, s->rb, s->wb, s->scan_tmp,
+               s->vec[s->iphi], s->err, st);
+  warm_count(so, k, s->ctl, s->nS, s->cap, s->scan_tmp, s->err, st);
+  s->warm_np = warm_compact(dm, Wi, s->prec, so, sn, k, s->ctl, s->nS,
+                            s->vec[s->ipsi], s->vec[s->iphi], s->scan_tmp,
+                            s->wb, s->mass_part, s->err, st);
+  if (s->p.max_states > 0)
+    cap_check(dm, s->ctl, sn.pay, est, s->p.max_states, s->ball, s->err, st);
+  warm_columns(dm, Wi, so, sn, s->ctl, s->nS, est, s->table, s->tmask, s->wb,
+               s->err, st);
+  warm_retable(s->ctl, s->table, s->tmask, s->wb.remap, s->err, st);
 }
 
 // expand + merge + build of the columns: M into the cleared table, k
 // rounds, the lookup pass of the last frontier, the state-cap check.
 void stage_expand(paces_sim* s, int64_t est, hipStream_t st,
                   const FrozenStep* fz) {
+  if (s->warm_step && !fz) {
+    stage_expand_warm(s, est, st);
+    return;
+  }
   const paces_model* m = s->m;
   const DevModel& dm = m->dm;
   const int Wi = m->Wi;
@@ -819,9 +873,9 @@ void stage_expand(paces_sim* s, int64_t est, hipStream_t st,
   }
   for (int r = 1; r <= k; ++r)
     expand_round(dm, Wi, s->prec, sn, r, s->ctl, s->cap, est, s->table,
-                 s->tmask, s->rb, s->col, s->vec[s->iphi], s->chunks, s->err,
+                 s->tmask, s->rb, sn.col, s->vec[s->iphi], s->chunks, s->err,
                  st);
-  lookup_last(dm, Wi, sn, k, s->ctl, est, s->table, s->tmask, s->col, s->cap,
+  lookup_last(dm, Wi, sn, k, s->ctl, est, s->table, s->tmask, sn.col, s->cap,
               s->err, st);
   if (s->p.max_states > 0)
     cap_check(dm, s->ctl, sn.pay, est, s->p.max_states, s->ball, s->err, st);
@@ -834,6 +888,13 @@ void stage_transfer(paces_sim* s, hipStream_t st, const FrozenStep* fz,
   const int R = m->R;
   const Side so = s->side[s->cur], sn = s->side[1 - s->cur];
   Stage sg(s, PACES_STAGE_TRANSFER, st);
+  if (s->warm_step && !fz) {
+    // phi and the dropped weight came with the rows from the expansion
+    L.n_mass = R == 1 ? fold_sum(s->mass_part, s->warm_np, s->mass_fold,
+                                 s->err, st)
+                      : s->warm_np;
+    return;
+  }
   // rows of M were placed with their amplitudes by the insert; the frozen
   // replay maps every old row
   const int skip = fz ? 0 : (s->cap_active ? 2 : (s->fresh ? 0 : 1));
@@ -854,13 +915,13 @@ void stage_build(paces_sim* s, int64_t est, hipStream_t st) {
   if (s->p.krylov_order > 0) return;
   Stage sg(s, PACES_STAGE_BUILD, st);
   if (s->p.taylor_order != 0) {
-    const int nb = bounds_part(m->dm, sn, s->col, s->cap, est, s->ctl,
+    const int nb = bounds_part(m->dm, sn, sn.col, s->cap, est, s->ctl,
                                s->bnd_part, s->err, st);
     taylor_plan(m->R, s->bnd_part, nb, s->p.dt, s->p.taylor_order, s->thetas,
                 s->p.k_max_terms, s->launched, s->tplan, s->cc, s->ctl,
                 s->err, st);
   } else {
-    bounds_and_coef(m->dm, sn, s->col, s->cap, est, s->ctl, s->p.dt, s->p.tol,
+    bounds_and_coef(m->dm, sn, sn.col, s->cap, est, s->ctl, s->p.dt, s->p.tol,
                     s->p.k_max_terms, s->launched, s->bnd_part, s->cc, s->err,
                     st);
   }
@@ -887,13 +948,13 @@ void stage_propagate(paces_sim* s, int64_t est, hipStream_t st,
       KernelTiming kt(s, PACES_STAGE_TERM, l);
       const int g = taylor_term(dm, s->prec, l, want_e && !fixed, s->p.dt,
                                 std::max<int64_t>(1, est / s->tune.term_rows),
-                                s->ctl, s->col, sn, s->tplan,
+                                s->ctl, sn.col, sn, s->tplan,
                                 s->vec[s->iphi], bufB, bufF, s->vec[s->ib0],
                                 s->e_part, s->e_row, s->err, kt.a, kt.b, st);
       if (l == 0) np = g;
     }
     if (want_e && fixed)
-      np = taylor_energy(dm, s->prec, est, s->ctl, s->col, sn, s->vec[s->ib0],
+      np = taylor_energy(dm, s->prec, est, s->ctl, sn.col, sn, s->vec[s->ib0],
                          s->e_part, s->e_row, s->err, st);
     if (want_e && R == 1) L.n_e = fold_sum(s->e_part, np, s->e_fold, s->err, st);
   } else if (s->p.krylov_order > 0) {
@@ -912,10 +973,10 @@ void stage_propagate(paces_sim* s, int64_t est, hipStream_t st,
       int np = 0;
       if (!last) {
         KernelTiming kt(s, PACES_STAGE_KRYLOV, j);
-        np = lz_spmv(dm, s->prec, j, est, s->ctl, s->col, sn, s->lz, kv.w[j],
+        np = lz_spmv(dm, s->prec, j, est, s->ctl, sn.col, sn, s->lz, kv.w[j],
                      out, s->lz_part, s->err, kt.a, kt.b, st);
       } else {
-        np = lz_spmv(dm, s->prec, j, est, s->ctl, s->col, sn, s->lz, kv.w[j],
+        np = lz_spmv(dm, s->prec, j, est, s->ctl, sn.col, sn, s->lz, kv.w[j],
                      out, s->lz_part, s->err, nullptr, nullptr, st);
       }
       lz_fold(j, s->lz_part, np, R, brk * brk, s->lz, s->lz_energy, s->err,
@@ -935,7 +996,7 @@ void stage_propagate(paces_sim* s, int64_t est, hipStream_t st,
       const bool mid = s->K_last >= 4 && kk >= 1 && kk <= s->K_last - 3;
       np = cheb_term(dm, s->prec, kk, want_e, mid,
                      std::max<int64_t>(1, est / s->tune.term_rows), s->ctl,
-                     s->col, s->cap, sn, s->cc, s->vec[s->iphi],
+                     sn.col, s->cap, sn, s->cc, s->vec[s->iphi],
                      s->vec[s->ib0], s->vec[s->ib1], s->e_part, s->e_row,
                      s->err, kt.a, kt.b, st);
     }
@@ -994,7 +1055,7 @@ paces_status launch_step_graph(paces_sim* s, int64_t est, bool counted,
       s->fresh ? 1 : 0, counted ? 1 : 0, s->fresh ? s->p.k_init : s->p.k,
       s->launched, s->K_last, est, std::min(bucket(s->nS), s->cap),
       int64_t(s->tmask), s->tune.term_rows, s->p.krylov_order,
-      s->p.taylor_order, s->chunks};
+      s->p.taylor_order, s->chunks, s->warm_step ? 1 : 0};
   for (auto& g : s->graphs)
     if (g.key == key) {
       g.used = ++s->graph_clock;
@@ -1216,10 +1277,17 @@ paces_status prepare_step(paces_sim* s, hipStream_t st, bool frozen,
   ST_TRY(ensure_ring(s, st));
   const int64_t est = std::min<int64_t>(
       s->cap, bucket(std::max<int64_t>(s->nS + s->nS / 2, s->nS + 65536)));
-  // probe only as much of the table as the step needs (load factor at most
-  // 2^-table_shift for a new set up to the estimate); the table clear
+  // expand from the previous step's graph when it is there and its table
+  // (probed over the same part, tombstones included) has room for a new
+  // set up to the estimate at load factor 2^-table_shift
+  s->warm_step =
+      s->tune.warm && s->graph_ok && !s->fresh && !frozen &&
+      s->cap <= kWarmMaxRows &&
+      (uint64_t(est + s->tomb) << s->tune.table_shift) <= s->tmask + 1;
+  // else probe only as much of the table as the step needs (load factor at
+  // most 2^-table_shift for a new set up to the estimate); the table clear
   // costs with it
-  {
+  if (!s->warm_step) {
     uint64_t P = 1024;
     while (P < (uint64_t(est) << s->tune.table_shift) && P <= s->tmask_alloc)
       P <<= 1;
@@ -1255,6 +1323,11 @@ void finish_step(paces_sim* s, const FrozenStep* fz) {
     s->events.push_back(ev);
   }
   s->pending.clear();
+  // the table now maps the new set (rebuilt by an expansion from scratch,
+  // rewritten by one from the previous graph)
+  s->tomb = s->warm_step ? s->tomb + int64_t(c.w_tomb) : 0;
+  s->last_warm = s->warm_step;
+  s->graph_ok = true;
   s->h = c;
   s->nS = c.n_new;
   s->cur = 1 - s->cur;
@@ -1267,6 +1340,26 @@ void finish_step(paces_sim* s, const FrozenStep* fz) {
   s->acc.rows_steps += double(c.n_new);
   s->counts_valid = true;
   s->cap_active = false;
+}
+
+// A staged step in progress is dropped.  Once a warm expansion has run, the
+// table maps the unfinished step's set: the next step starts from scratch.
+void abandon_staged(paces_sim* s) {
+  if (s->staged_next > PACES_STAGE_EXPAND && s->warm_step) s->graph_ok = false;
+  s->staged_next = 0;
+}
+
+// After a warm attempt that latched: the table back to the previous set's
+// when the attempt stopped before rewriting it, else (and for every error
+// but the state cap's) the repeated attempt expands from scratch.
+void warm_after_latch(paces_sim* s, int e, hipStream_t st) {
+  if (!s->warm_step) return;
+  if (s->h_ctl->w_moved) {
+    s->graph_ok = false;
+    return;
+  }
+  warm_unstage(s->table, s->tmask, st);
+  if (e != kErrCap) s->graph_ok = false;
 }
 
 // After an attempt that latched e: make the room or the selection the
@@ -1313,7 +1406,9 @@ paces_status do_step(paces_sim* s, hipStream_t st,
       return PACES_OK;
     }
     drop_pending(s);
+    warm_after_latch(s, e, st);
     ST_TRY(handle_latch(s, e, st));
+    s->warm_step = s->warm_step && s->graph_ok;
   }
   return fail(PACES_E_CAPACITY, "step did not fit after repeated growth");
 }
@@ -1403,6 +1498,7 @@ paces_status restore_snapshot(paces_sim* s, const Snapshot& z,
   s->k_last = z.k_last;
   s->have_sets = false;
   s->counts_valid = false;
+  s->graph_ok = false;
   s->latched = 0;
   return push_ctl(s, st);
 }
@@ -1415,6 +1511,7 @@ paces_status resize_table(paces_sim* s, hipStream_t st) {
   drop_graphs(s);
   ++s->gen;
   dfree(s->table);
+  s->graph_ok = false;
   ST_TRY(dalloc(&s->table, int64_t(P)));
   s->tmask_alloc = P - 1;
   s->tmask = P - 1;
@@ -1422,7 +1519,8 @@ paces_status resize_table(paces_sim* s, hipStream_t st) {
 }
 
 paces_status check_tuning(const paces_tuning* t) {
-  if (!t || (t->graph != 0 && t->graph != 1) || t->table_shift < 0 ||
+  if (!t || (t->graph != 0 && t->graph != 1) || (t->warm != 0 && t->warm != 1) ||
+      t->table_shift < 0 ||
       t->table_shift > 3 ||
       (t->term_rows != 1 && t->term_rows != 2 && t->term_rows != 4 &&
        t->term_rows != 8))
@@ -1511,9 +1609,21 @@ paces_status adj_keep_m(paces_sim* s, int64_t nM, hipStream_t st) {
     R.mkeys = q;
     R.mcap = nc;
   }
-  if (nM > 0)
+  if (nM > 0 && s->last_warm) {
+    // rows of M are those at distance 0, anywhere in the set
+    const Side& c = s->side[s->cur];
+    uint32_t got = 0;
+    rows_at_distance(Wi, c.keys, c.dist, s->nS, 0, R.mkeys + R.mused * Wi,
+                     s->dcount, s->scan_tmp, s->err, st);
+    s->counts_valid = false;
+    HIP_TRY(hipMemcpyAsync(&got, s->dcount, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (int64_t(got) != nM)
+      return fail(PACES_E_STATE, "selection rows do not match their count");
+  } else if (nM > 0) {
     HIP_TRY(hipMemcpyAsync(R.mkeys + R.mused * Wi, s->side[s->cur].keys,
                            size_t(nM) * Wi * 8, hipMemcpyDeviceToDevice, st));
+  }
   R.mused += nM;
   return PACES_OK;
 }
@@ -2107,7 +2217,7 @@ paces_status paces_init_state(const paces_model* m, const paces_run_params* p,
   if (dalloc(&s->ctl, 1) || dalloc(&s->err, 1) || dalloc(&s->parts, nparts) ||
       dalloc(&s->cc, R) || dalloc(&s->a2, 2 * R) || dalloc(&s->cnt, 2 * R) ||
       dalloc(&s->mass_tot, R) || dalloc(&s->p0_last, nt) ||
-      dalloc(&s->ball, R) ||
+      dalloc(&s->ball, R) || dalloc(&s->dcount, 1) ||
       dalloc(&s->keys0, nt * m->Wi) ||
       dalloc(&s->amps0, 2 * nt))
     return cleanup(PACES_E_OOM);
@@ -2172,6 +2282,7 @@ paces_status paces_free_sim(paces_sim* s) {
   dfree(s->mass_tot);
   dfree(s->p0_last);
   dfree(s->ball);
+  dfree(s->dcount);
   if (s->cap_block) dev_free(s->cap_block);
   dfree(s->cap_hist);
   dfree(s->cap_mode);
@@ -2204,7 +2315,7 @@ paces_status paces_step(paces_sim* s, int64_t n_steps, void* hip_stream) {
   if (s->latched) return fail(PACES_E_STATE, "sim is in an error state");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const char* log = std::getenv("PACES_LOG");
-  s->staged_next = 0;  // a staged step in progress is abandoned
+  abandon_staged(s);
   for (int64_t i = 0; i < n_steps; ++i) {
     paces_status r = do_step(s, st);
     if (r != PACES_OK) {
@@ -2232,7 +2343,7 @@ paces_status paces_run_stage(paces_sim* s, int32_t stage, void* hip_stream) {
   L.n_e = s->staged_e;
   switch (stage) {
     case PACES_STAGE_SELECT: {
-      s->staged_next = 0;
+      abandon_staged(s);
       ST_TRY(prepare_step(s, st, false, &s->staged_est));
       stage_select(s, false, st, nullptr);
       break;
@@ -2252,11 +2363,13 @@ paces_status paces_run_stage(paces_sim* s, int32_t stage, void* hip_stream) {
           s->staged_next = 0;
           return check_latch_code(s, e);
         }
+        warm_after_latch(s, e, st);
         paces_status h = handle_latch(s, e, st);
         if (h) {
           s->staged_next = 0;
           return h;
         }
+        s->warm_step = s->warm_step && s->graph_ok;
       }
       break;
     }
@@ -2434,13 +2547,39 @@ paces_status paces_get_set(paces_sim* s, int32_t which, int32_t round,
   } else {
     return fail(PACES_E_ARG, "unknown set");
   }
-  *n = b - a;
-  if ((!keys && !real) || b == a) return PACES_OK;
   const paces_model* m = s->m;
+  const Side& c = s->side[s->cur];
+  uint64_t* gathered = nullptr;
+  if (s->last_warm && which != PACES_SET_S && s->nS > 0) {
+    // a step from the previous graph leaves M and the frontiers spread over
+    // the set: gather the rows at that distance
+    const int d = which == PACES_SET_M ? 0 : round;
+    uint32_t got = 0;
+    ST_TRY(dalloc(&gathered, s->nS * m->Wi));
+    rows_at_distance(m->Wi, c.keys, c.dist, s->nS, d, gathered, s->dcount,
+                     s->scan_tmp, s->err, st);
+    s->counts_valid = false;
+    if (hipMemcpyAsync(&got, s->dcount, 4, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      dfree(gathered);
+      return fail(PACES_E_HIP, "copy failed");
+    }
+    a = 0;
+    b = got;
+  }
+  *n = b - a;
+  if ((!keys && !real) || b == a) {
+    dfree(gathered);
+    return PACES_OK;
+  }
   std::vector<uint64_t> ik(size_t(b - a) * m->Wi), ck;
-  HIP_TRY(hipMemcpyAsync(ik.data(), s->side[s->cur].keys + a * m->Wi,
-                         ik.size() * 8, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  const uint64_t* src = gathered ? gathered : c.keys + a * m->Wi;
+  const hipError_t ce = hipMemcpyAsync(ik.data(), src, ik.size() * 8,
+                                       hipMemcpyDeviceToHost, st);
+  const hipError_t se = hipStreamSynchronize(st);
+  dfree(gathered);
+  if (ce != hipSuccess || se != hipSuccess) return fail(PACES_E_HIP, "copy failed");
   if (!keys) ck.resize(size_t(b - a) * m->W);
   to_canonical(m, b - a, ik.data(), keys ? keys : ck.data(), real);
   return PACES_OK;
@@ -2522,6 +2661,9 @@ paces_status paces_set_model(paces_sim* s, const paces_model* m) {
     drop_graphs(s);  // kernels take the model's values by value
     delete s->adj;   // a recorded adjoint run assumes one model
     s->adj = nullptr;
+    // a coupling that becomes zero or nonzero changes which slots exist:
+    // the next step expands from scratch
+    s->graph_ok = false;
   }
   s->m = m;
   return PACES_OK;
@@ -2782,7 +2924,7 @@ paces_status adjoint_backward(paces_sim* s, const double* gbar, double* grad,
       e = adj_frozen_step(s, i, z.tmap, z.p0, st);
       if (e) break;
       const int64_t n1 = s->nS;
-      if (hipMemcpyAsync(z.col, s->col, size_t(n1) * D * 4,
+      if (hipMemcpyAsync(z.col, s->side[s->cur].col, size_t(n1) * D * 4,
                          hipMemcpyDeviceToDevice, st) != hipSuccess)
         e = fail(PACES_E_HIP, "copy failed");
       const Side& c = s->side[s->cur];
@@ -2916,7 +3058,7 @@ paces_status paces_autotune(paces_sim* s, int32_t steps, paces_tuning* chosen,
   for (int g = 0; g < 2 && r == PACES_OK; ++g)
     for (int sh = 0; sh <= 2 && r == PACES_OK; ++sh)
       for (int tr : {1, 2, 4}) {
-        paces_tuning t{g, sh, tr};
+        paces_tuning t{g, sh, tr, start.warm};
         r = paces_set_tuning(s, &t, hip_stream);
         if (r == PACES_OK) r = restore_snapshot(s, z, st);
         // one untimed step (captures the graph), then the timed ones

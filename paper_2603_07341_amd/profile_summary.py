@@ -34,8 +34,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 MID = "k_cheb_term<double, 1, 1, true>"
 GIB = float(1 << 30)
 
-# first kernel of each stage of a step, in dispatch order
+# first kernel of each stage of a step, in dispatch order (a step from the
+# previous graph starts its expansion with k_warm_old and moves the rows
+# and phi there: its transfer stage is only the fold of the dropped weight,
+# counted with the expansion)
 STAGE_START = [("k_begin_step", "select"), ("k_fill_u64", "expand+build"),
+               ("k_warm_old", "expand+build"),
                ("k_transfer", "transfer"), ("k_bounds", "build"),
                ("k_cheb_term", "propagate"), ("k_pop_norm", "observe")]
 
@@ -43,7 +47,8 @@ STAGE_START = [("k_begin_step", "select"), ("k_fill_u64", "expand+build"),
 def source_hash():
     """Hash of the step kernels' code, comments and blank lines ignored."""
     h = hashlib.sha256()
-    for f in ["kernels.hip", "device.hpp", "kernels.hpp", "common.hpp"]:
+    for f in ["kernels.hip", "warm.hip", "device.hpp", "kernels.hpp",
+              "warm.hpp", "common.hpp"]:
         with open(os.path.join(HERE, "csrc", f)) as fh:
             for line in fh:
                 code = line.split("//")[0].rstrip()

@@ -170,6 +170,19 @@ def batch_params(cfg, n_real=None, first=0, **override):
     return p
 
 
+def adjoint_target_params(cfg):
+    """Model parameters of the run whose a(t) is the adjoint workload's
+    target: J + 0.05 per axis, g - 0.05 and omega + 0.02 per mode, and
+    site energies shifted by N(0, 0.02) draws of seed 43."""
+    p = model_params(cfg)
+    nd, V = cfg["ndim"], cfg["n_modes"]
+    p["J"] = [x + 0.05 if a < nd else x for a, x in enumerate(p["J"])]
+    p["g"] = [x - 0.05 if nu < V else x for nu, x in enumerate(p["g"])]
+    p["omega"] = [x + 0.02 if nu < V else x for nu, x in enumerate(p["omega"])]
+    p["eps"] = [e + d for e, d in zip(p["eps"], normals(43, n_sites(cfg), 0.02))]
+    return p
+
+
 def initial_state(cfg, kind=None, site=0):
     """(exc, occ, coef) of the initial state.
 
