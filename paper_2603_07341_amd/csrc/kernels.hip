@@ -141,19 +141,31 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // Single block: exclusive scan of the tile sums in place; the grand total
-// goes to *out1 (and *out2 when given).
+// goes to *out1 (and *out2 when given).  Each lane takes kScanRun
+// consecutive sums per pass, so one pass covers kBlock * kScanRun tiles.
+constexpr int kScanRun = 16;
 __global__ void __launch_bounds__(kBlock)
     k_scan_bsum(uint32_t* bsum, const uint32_t* nptr, uint32_t* out1,
                 uint32_t* out2, const int* err) {
   if (*err) return;
   const int64_t nb = cdiv(int64_t(*nptr), kTile);
   uint32_t carry = 0;
-  for (int64_t c = 0; c < nb; c += kBlock) {
-    const int64_t e = c + threadIdx.x;
-    const uint32_t v = e < nb ? bsum[e] : 0u;
+  for (int64_t c = 0; c < nb; c += int64_t(kBlock) * kScanRun) {
+    const int64_t e0 = c + int64_t(threadIdx.x) * kScanRun;
+    uint32_t v[kScanRun];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanRun; ++j) {
+      v[j] = e0 + j < nb ? bsum[e0 + j] : 0u;
+      sum += v[j];
+    }
     uint32_t tot;
-    const uint32_t off = block_excl_scan(v, &tot) + carry;
-    if (e < nb) bsum[e] = off;
+    uint32_t off = block_excl_scan(sum, &tot) + carry;
+#pragma unroll
+    for (int j = 0; j < kScanRun; ++j) {
+      if (e0 + j < nb) bsum[e0 + j] = off;
+      off += v[j];
+    }
     carry += tot;
   }
   if (threadIdx.x == 0) {

@@ -476,7 +476,8 @@ void free_rows(paces_sim* s) {
   s->rows_bytes = 0;
   for (int q = 0; q < 2; ++q) s->side[q] = Side{};
   for (auto& v : s->vec) v = nullptr;
-  s->wb.remap = nullptr;
+  s->wb.kbits = nullptr;
+  s->wb.kpre = nullptr;
   s->wb.wmask = nullptr;
   s->graph_ok = false;
   s->midx = nullptr;
@@ -556,7 +557,8 @@ struct RowBlock {
   Side sd[2]{};
   void* vec[4] = {nullptr, nullptr, nullptr, nullptr};
   uint32_t *midx = nullptr, *scan = nullptr;
-  uint32_t* remap = nullptr;
+  uint64_t* kbits = nullptr;
+  uint32_t* kpre = nullptr;
   uint16_t* wmask = nullptr;
   double* erow = nullptr;
   std::vector<void*> kry;
@@ -578,7 +580,8 @@ struct RowBlock {
     }
     for (int v = 0; v < 4; ++v) pc.add_bytes(&vec[v], size_t(cap) * s->A);
     pc.add(&midx, cap);
-    pc.add(&remap, cap);
+    pc.add(&kbits, cap / 64 + 1);
+    pc.add(&kpre, cap / 64 + 1);
     pc.add(&wmask, cap);
     pc.add(&scan, scan_tmp_words(cap));
     if (m->R > 1) pc.add(&erow, cap);
@@ -693,7 +696,8 @@ paces_status grow(paces_sim* s, int64_t new_cap, int64_t min_cap,
   s->side[0] = nb.sd[0];
   s->side[1] = nb.sd[1];
   for (int v = 0; v < 4; ++v) s->vec[v] = nb.vec[v];
-  s->wb.remap = nb.remap;
+  s->wb.kbits = nb.kbits;
+  s->wb.kpre = nb.kpre;
   s->wb.wmask = nb.wmask;
   s->graph_ok = false;  // columns and table are rebuilt by the next step
   s->midx = nb.midx;
@@ -843,7 +847,7 @@ void stage_expand_warm(paces_sim* s, int64_t est, hipStream_t st) {
     cap_check(dm, s->ctl, sn.pay, est, s->p.max_states, s->ball, s->err, st);
   warm_columns(dm, Wi, so, sn, s->ctl, s->nS, est, s->table, s->tmask, s->wb,
                s->err, st);
-  warm_retable(s->ctl, s->table, s->tmask, s->wb.remap, s->err, st);
+  warm_retable(s->ctl, s->table, s->tmask, s->wb, s->err, st);
 }
 
 // expand + merge + build of the columns: M into the cleared table, k

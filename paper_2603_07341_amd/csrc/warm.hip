@@ -111,13 +111,12 @@ __global__ void __launch_bounds__(kBlock)
 // writer writes r, and no row at distance r-1 is written in round r), the
 // slots whose neighbour lies outside the old set go to wmask and are
 // counted per tile.  Write pass: those slots as candidates, in tile order.
-template <bool WRITE>
+template <bool WRITE, int D>
 __global__ void __launch_bounds__(kBlock)
     k_warm_old(DevModel m, int r, const StepCtl* ctl, const uint64_t* pay_o,
                const int32_t* col_o, uint8_t* dist, uint16_t* wmask,
                uint32_t* bsum, uint64_t* wlist, int64_t cand_cap, int* err) {
   if (*err) return;
-  const int D = m.D;
   const uint8_t front = uint8_t(r - 1);
   const int64_t n = ctl->n_old, ntiles = cdiv(n, kTile);
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -131,8 +130,11 @@ __global__ void __launch_bounds__(kBlock)
           msk = wmask[e];
         } else {
           const uint64_t p = pay_o[e];
+          int32_t cs[D];
+          load_cols<D>(col_o + e * D, cs);
+#pragma unroll
           for (int s = 0; s < D; ++s) {
-            const int32_t c = col_o[e * D + s];
+            const int32_t c = cs[s];
             if (c >= 0) {
               if (dist[c] > r) dist[c] = uint8_t(r);
             } else if (slot_live(m, p, s)) {
@@ -377,16 +379,32 @@ __global__ void k_warm_sizes(StepCtl* ctl, int64_t cap, int* err) {
   ctl->n_new = uint32_t(n);
 }
 
+// New row of old row c from the keep map: the old rows that stay, one bit
+// each in words of 64 rows, with the count of rows kept before each word
+// (12 bytes per 64 rows, small enough to stay in the L2 cache where a row
+// map of 4 bytes per row would not).  kNone for a dropped row.
+struct KeepMap {
+  const uint64_t* bits;
+  const uint32_t* pre;
+  uint32_t base;  // rows of the new set before the first old row
+  __device__ __forceinline__ uint32_t row_of(int64_t c) const {
+    const uint64_t w = bits[c >> 6];
+    const int b = int(c & 63);
+    if (!((w >> b) & 1ull)) return kNone;
+    return base + pre[c >> 6] + uint32_t(__popcll(w & ((1ull << b) - 1ull)));
+  }
+};
+
 // Old rows that stay move behind the staged rows in their old order: key,
 // payload, totals (when the payload does not hold them), distance, phi =
-// psi; every old row's new row (kNone if dropped) into remap; the weight of
-// the dropped rows into per-block partials.
+// psi; the keep map (one ballot per wave of 64 consecutive rows); the
+// weight of the dropped rows into per-block partials.
 template <int W, typename Amp>
 __global__ void __launch_bounds__(kBlock)
     k_warm_compact(DevModel m, int k, const StepCtl* ctl, Side o, Side n,
                    const Amp* psi_o, Amp* phi, const uint32_t* bsum,
-                   uint32_t* remap, double* mass_part, int copy_tot,
-                   const int* err) {
+                   uint64_t* kbits, uint32_t* kpre, double* mass_part,
+                   int copy_tot, const int* err) {
   __shared__ double bins[kMaxReal];
   if (*err) return;
   const int R = m.R;
@@ -396,6 +414,7 @@ __global__ void __launch_bounds__(kBlock)
   }
   const int64_t nold = ctl->n_old, base = ctl->n_staged;
   const int64_t ntiles = cdiv(nold, kTile);
+  const int lane = threadIdx.x & 63;
   double lost = 0;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     uint32_t run = bsum[t];
@@ -407,23 +426,27 @@ __global__ void __launch_bounds__(kBlock)
       uint32_t tot;
       const uint32_t off = block_excl_scan(keep ? 1u : 0u, &tot) + run;
       run += tot;
+      // lanes of a wave hold 64 consecutive rows, the first at a multiple
+      // of 64: its ballot is the word of the keep map
+      const uint64_t word = __ballot(keep);
+      if (lane == 0 && e < nold) {
+        kbits[e >> 6] = word;
+        kpre[e >> 6] = off;
+      }
       if (e >= nold) continue;
       const Amp v = psi_o[e];
       if (keep) {
         const int64_t row = base + off;
-        remap[e] = uint32_t(row);
 #pragma unroll
         for (int w = 0; w < W; ++w) n.keys[row * W + w] = o.keys[e * W + w];
         n.pay[row] = o.pay[e];
         if (copy_tot) n.tot[row] = o.tot[e];
         n.dist[row] = d;
         phi[row] = v;
+      } else if (R > 1) {
+        atomicAdd(&bins[pay_real(o.pay[e])], weight(v));
       } else {
-        remap[e] = kNone;
-        if (R > 1)
-          atomicAdd(&bins[pay_real(o.pay[e])], weight(v));
-        else
-          lost += weight(v);
+        lost += weight(v);
       }
     }
   }
@@ -437,54 +460,46 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// Columns of the old rows that stay: a column into the old set through
-// remap (-1 if that row was dropped); a structurally nonzero slot without
-// a column (neighbour outside the old set) is in the new set only as a
-// staged row.
-template <int W>
+// Columns of the old rows that stay: a column into the old set through the
+// keep map (-1 if that row was dropped).  A slot without a column (its
+// neighbour is outside the old set) is -1 here; if that neighbour is a new
+// row, the new row's own lookup of this row sets it (k_warm_cols_new).
+template <int D>
 __global__ void __launch_bounds__(kBlock)
-    k_warm_cols_old(DevModel m, const StepCtl* ctl, Side o, Side n,
-                    const uint64_t* table, uint64_t mask,
-                    const uint32_t* remap, const int* err) {
+    k_warm_cols_old(const StepCtl* ctl, const int32_t* __restrict__ col_o,
+                    int32_t* __restrict__ col_n, KeepMap km, const int* err) {
   if (*err) return;
-  const int D = m.D;
+  km.base = ctl->n_staged;
   const int64_t nold = ctl->n_old;
   for (int64_t e = gtid(); e < nold; e += gstride()) {
-    const uint32_t row = remap[e];
+    const uint32_t row = km.row_of(e);
     if (row == kNone) continue;
-    const uint64_t p = o.pay[e];
-    bool have_key = false;
-    uint64_t par[W];
+    int32_t c[D];
+    load_cols<D>(col_o + e * D, c);
+#pragma unroll
     for (int s = 0; s < D; ++s) {
-      const int32_t c = o.col[e * D + s];
       int32_t out = -1;
-      if (c >= 0) {
-        const uint32_t v = remap[c];
+      if (c[s] >= 0) {
+        const uint32_t v = km.row_of(c[s]);
         out = v == kNone ? -1 : int32_t(v);
-      } else if (slot_live(m, p, s)) {
-        if (!have_key) {
-          load_key<W>(o.keys, e, par);
-          have_key = true;
-        }
-        uint64_t k[W];
-        slot_target<W>(m, par, p, s, k);
-        const Found f =
-            warm_find<W>(table, mask, o.keys, n.keys, k, key_hash<W>(m, k));
-        if (f.row >= 0 && f.staged) out = int32_t(f.row);
       }
-      n.col[int64_t(row) * D + s] = out;
+      col_n[int64_t(row) * D + s] = out;
     }
   }
 }
 
-// Columns of the staged rows by lookup: an old row through remap, a staged
-// row as it is.
+// Columns of the staged rows by lookup: an old row through the keep map, a
+// staged row as it is.  An edge is found from both ends with slots s and s
+// ^ 1 (a hop and the opposite hop, a lowering and the raising at the same
+// site), so a staged row also sets the column of an old row that stays
+// toward it, which k_warm_cols_old left at -1 (it runs first).
 template <int W>
 __global__ void __launch_bounds__(kBlock)
     k_warm_cols_new(DevModel m, const StepCtl* ctl, Side o, Side n,
-                    const uint64_t* table, uint64_t mask,
-                    const uint32_t* remap, const int* err) {
+                    const uint64_t* table, uint64_t mask, KeepMap km,
+                    const int* err) {
   if (*err) return;
+  km.base = ctl->n_staged;
   const int D = m.D;
   const int64_t ns = ctl->n_staged;
   for (int64_t c = gtid(); c < ns * D; c += gstride()) {
@@ -500,8 +515,11 @@ __global__ void __launch_bounds__(kBlock)
         if (f.staged) {
           out = int32_t(f.row);
         } else {
-          const uint32_t v = remap[f.row];
-          out = v == kNone ? -1 : int32_t(v);
+          const uint32_t v = km.row_of(f.row);
+          if (v != kNone) {
+            out = int32_t(v);
+            n.col[int64_t(v) * D + (s ^ 1)] = int32_t(q);
+          }
         }
       }
     }
@@ -510,30 +528,39 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // The table in place: old rows to their new rows (tombstones for dropped
-// ones), staged rows to plain rows.
+// ones), staged rows to plain rows.  Two entries per lane (16-byte loads
+// and stores; the table has a power-of-two size of at least 1024).
+__device__ __forceinline__ uint64_t retable_entry(uint64_t e, const KeepMap& km,
+                                                  uint32_t& tombs) {
+  if (e == kEmpty || uint32_t(e >> 32) == 0xFFFFFFFFu) return e;
+  const uint32_t v = uint32_t(e);
+  const uint64_t hi = e & 0xFFFFFFFF00000000ull;
+  if (v & kCand) return e;  // none are left once every round committed
+  if (v & kStaged) return hi | uint64_t(v & ~kStaged);
+  const uint32_t nv = km.row_of(v);
+  if (nv == kNone) {
+    ++tombs;
+    return kTomb;
+  }
+  return hi | uint64_t(nv);
+}
+
+typedef uint64_t v2u64 __attribute__((ext_vector_type(2)));
+
 __global__ void __launch_bounds__(kBlock)
-    k_warm_retable(StepCtl* ctl, uint64_t* table, uint64_t mask,
-                   const uint32_t* remap, const int* err) {
+    k_warm_retable(StepCtl* ctl, uint64_t* table, uint64_t mask, KeepMap km,
+                   const int* err) {
   if (*err) return;
-  const int64_t P = int64_t(mask) + 1;
+  km.base = ctl->n_staged;
+  const int64_t P2 = (int64_t(mask) + 1) / 2;
+  v2u64* t2 = reinterpret_cast<v2u64*>(table);
   uint32_t tombs = 0;
-  for (int64_t i = gtid(); i < P; i += gstride()) {
-    const uint64_t e = table[i];
-    if (e == kEmpty || uint32_t(e >> 32) == 0xFFFFFFFFu) continue;
-    const uint32_t v = uint32_t(e);
-    const uint64_t hi = e & 0xFFFFFFFF00000000ull;
-    if (v & kCand) continue;  // none are left once every round committed
-    if (v & kStaged) {
-      table[i] = hi | uint64_t(v & ~kStaged);
-    } else {
-      const uint32_t nv = remap[v];
-      if (nv == kNone) {
-        table[i] = kTomb;
-        ++tombs;
-      } else {
-        table[i] = hi | uint64_t(nv);
-      }
-    }
+  for (int64_t i = gtid(); i < P2; i += gstride()) {
+    const v2u64 e = __builtin_nontemporal_load(t2 + i);
+    v2u64 o;
+    o.x = retable_entry(e.x, km, tombs);
+    o.y = retable_entry(e.y, km, tombs);
+    if (o.x != e.x || o.y != e.y) __builtin_nontemporal_store(o, t2 + i);
   }
   uint32_t tot;
   block_excl_scan(tombs, &tot);
@@ -608,13 +635,23 @@ void warm_round(const DevModel& m, int Wi, int prec, const Side& o,
                 void* phi, int* err, hipStream_t s) {
   const int D = m.D;
   const int go = tiles_for(n_old);
-  k_warm_old<false><<<go, kBlock, 0, s>>>(m, r, ctl, o.pay, o.col, o.dist,
-                                          wb.wmask, scan_tmp, wb.wlist,
-                                          rb.cand_cap, err);
+#define PACES_WARM_OLD(WRITE)                                                 \
+  switch (D) {                                                                \
+    case 4: k_warm_old<WRITE, 4><<<go, kBlock, 0, s>>>(PACES_WARM_OLD_ARGS); break;   \
+    case 6: k_warm_old<WRITE, 6><<<go, kBlock, 0, s>>>(PACES_WARM_OLD_ARGS); break;   \
+    case 8: k_warm_old<WRITE, 8><<<go, kBlock, 0, s>>>(PACES_WARM_OLD_ARGS); break;   \
+    case 10: k_warm_old<WRITE, 10><<<go, kBlock, 0, s>>>(PACES_WARM_OLD_ARGS); break; \
+    case 12: k_warm_old<WRITE, 12><<<go, kBlock, 0, s>>>(PACES_WARM_OLD_ARGS); break; \
+    case 14: k_warm_old<WRITE, 14><<<go, kBlock, 0, s>>>(PACES_WARM_OLD_ARGS); break; \
+    default: break;                                                           \
+  }
+#define PACES_WARM_OLD_ARGS \
+  m, r, ctl, o.pay, o.col, o.dist, wb.wmask, scan_tmp, wb.wlist, rb.cand_cap, err
+  PACES_WARM_OLD(false)
   tile_sums_scan(scan_tmp, &ctl->n_old, &ctl->w_noc, err, s);
-  k_warm_old<true><<<go, kBlock, 0, s>>>(m, r, ctl, o.pay, o.col, o.dist,
-                                         wb.wmask, scan_tmp, wb.wlist,
-                                         rb.cand_cap, err);
+  PACES_WARM_OLD(true)
+#undef PACES_WARM_OLD_ARGS
+#undef PACES_WARM_OLD
   k_warm_prep<<<1, 1, 0, s>>>(ctl, r, D, rb.cand_cap, err);
   // candidates: at most the old set's slots plus the new set's
   const int64_t nc_bound = std::min<int64_t>(rb.cand_cap, (n_old + est) * D);
@@ -656,31 +693,44 @@ int warm_compact(const DevModel& m, int Wi, int prec, const Side& o,
   if (prec == 64) {
     PACES_DISPATCH_W(Wi, k_warm_compact<WW, double2><<<g, kBlock, 0, s>>>(
                              m, k, ctl, o, n, (const double2*)psi_o,
-                             (double2*)phi, scan_tmp, wb.remap, mass_part,
-                             copy_tot, err));
+                             (double2*)phi, scan_tmp, wb.kbits, wb.kpre,
+                             mass_part, copy_tot, err));
   } else {
     PACES_DISPATCH_W(Wi, k_warm_compact<WW, float2><<<g, kBlock, 0, s>>>(
                              m, k, ctl, o, n, (const float2*)psi_o,
-                             (float2*)phi, scan_tmp, wb.remap, mass_part,
-                             copy_tot, err));
+                             (float2*)phi, scan_tmp, wb.kbits, wb.kpre,
+                             mass_part, copy_tot, err));
   }
   return g;
 }
+
+namespace {
+KeepMap keep_map(const WarmBufs& wb) { return KeepMap{wb.kbits, wb.kpre, 0u}; }
+}  // namespace
 
 void warm_columns(const DevModel& m, int Wi, const Side& o, const Side& n,
                   const StepCtl* ctl, int64_t n_old, int64_t est,
                   const uint64_t* table, uint64_t mask, const WarmBufs& wb,
                   int* err, hipStream_t s) {
-  PACES_DISPATCH_W(Wi, k_warm_cols_old<WW><<<grid_for(n_old), kBlock, 0, s>>>(
-                           m, ctl, o, n, table, mask, wb.remap, err));
+  const int g = grid_for(n_old);
+  switch (m.D) {
+    case 2: k_warm_cols_old<2><<<g, kBlock, 0, s>>>(ctl, o.col, n.col, keep_map(wb), err); break;
+    case 4: k_warm_cols_old<4><<<g, kBlock, 0, s>>>(ctl, o.col, n.col, keep_map(wb), err); break;
+    case 6: k_warm_cols_old<6><<<g, kBlock, 0, s>>>(ctl, o.col, n.col, keep_map(wb), err); break;
+    case 8: k_warm_cols_old<8><<<g, kBlock, 0, s>>>(ctl, o.col, n.col, keep_map(wb), err); break;
+    case 10: k_warm_cols_old<10><<<g, kBlock, 0, s>>>(ctl, o.col, n.col, keep_map(wb), err); break;
+    case 12: k_warm_cols_old<12><<<g, kBlock, 0, s>>>(ctl, o.col, n.col, keep_map(wb), err); break;
+    case 14: k_warm_cols_old<14><<<g, kBlock, 0, s>>>(ctl, o.col, n.col, keep_map(wb), err); break;
+    default: break;
+  }
   PACES_DISPATCH_W(Wi, k_warm_cols_new<WW><<<grid_for(est * m.D), kBlock, 0, s>>>(
-                           m, ctl, o, n, table, mask, wb.remap, err));
+                           m, ctl, o, n, table, mask, keep_map(wb), err));
 }
 
 void warm_retable(StepCtl* ctl, uint64_t* table, uint64_t mask,
-                  const uint32_t* remap, int* err, hipStream_t s) {
-  k_warm_retable<<<grid_for(int64_t(mask) + 1), kBlock, 0, s>>>(ctl, table, mask,
-                                                                remap, err);
+                  const WarmBufs& wb, int* err, hipStream_t s) {
+  k_warm_retable<<<grid_for((int64_t(mask) + 1) / 2), kBlock, 0, s>>>(
+      ctl, table, mask, keep_map(wb), err);
 }
 
 void warm_unstage(uint64_t* table, uint64_t mask, hipStream_t s) {

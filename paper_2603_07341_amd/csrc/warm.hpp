@@ -37,7 +37,8 @@ struct WarmBufs {
                     // that come from old rows
   uint16_t* wmask;  // [rows] slots of an old frontier row whose neighbour
                     // is outside the old set
-  uint32_t* remap;  // [rows] new row of each old row, kNone if dropped
+  uint64_t* kbits;  // [rows / 64] old rows that stay, one bit each
+  uint32_t* kpre;   // [rows / 64] old rows that stay before each word
 };
 
 // Distances of the old rows: 0 on M (midx[0, nM)), kFar elsewhere; |M| per
@@ -61,18 +62,18 @@ void warm_round(const DevModel& m, int Wi, int prec, const Side& o,
 // n_new, with kErrCapacity when they exceed cap.
 void warm_count(const Side& o, int k, StepCtl* ctl, int64_t n_old,
                 int64_t cap, uint32_t* scan_tmp, int* err, hipStream_t s);
-// Old rows into the new set: keys, payload (and totals when copy_tot),
-// distance, phi = psi; weight of the dropped rows into per-block partials
-// (one double per block, or R per block for several realizations).
-// Returns the number of partial blocks.
+// Old rows into the new set: keys, payload (and totals when the payload
+// does not hold them), distance, phi = psi, the keep map; weight of the
+// dropped rows into per-block partials (one double per block, or R per
+// block for several realizations).  Returns the number of partial blocks.
 int warm_compact(const DevModel& m, int Wi, int prec, const Side& o,
                  const Side& n, int k, const StepCtl* ctl, int64_t n_old,
                  const void* psi_o, void* phi, const uint32_t* scan_tmp,
                  const WarmBufs& wb, double* mass_part, int* err,
                  hipStream_t s);
-// Columns of the new set: old rows by remapping theirs (a slot whose
-// neighbour was outside the old set is looked up among the staged rows),
-// staged rows by table lookup.
+// Columns of the new set: old rows by remapping theirs through the keep
+// map, staged rows by table lookup (which also sets the columns of old
+// rows toward staged rows).
 void warm_columns(const DevModel& m, int Wi, const Side& o, const Side& n,
                   const StepCtl* ctl, int64_t n_old, int64_t est,
                   const uint64_t* table, uint64_t mask, const WarmBufs& wb,
@@ -80,7 +81,7 @@ void warm_columns(const DevModel& m, int Wi, const Side& o, const Side& n,
 // The table rewritten in place to rows of the new set (sets w_moved and
 // counts new tombstones into w_tomb).
 void warm_retable(StepCtl* ctl, uint64_t* table, uint64_t mask,
-                  const uint32_t* remap, int* err, hipStream_t s);
+                  const WarmBufs& wb, int* err, hipStream_t s);
 // Staged and candidate entries back to empty slots, whatever the latch:
 // the table of the previous set as it was before the step.
 void warm_unstage(uint64_t* table, uint64_t mask, hipStream_t s);
