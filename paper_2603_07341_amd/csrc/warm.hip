@@ -85,15 +85,22 @@ __global__ void __launch_bounds__(kBlock)
                 const int* err) {
   __shared__ uint32_t bins[kMaxReal];
   if (*err) return;
-  for (int r = threadIdx.x; r < m.R; r += blockDim.x) bins[r] = 0;
-  __syncthreads();
   const int64_t nM = ctl->nM;
-  for (int64_t i = gtid(); i < nM; i += gstride()) {
-    const uint32_t r = midx[i];
-    dist[r] = 0;
-    atomicAdd(&bins[pay_real(pay_o[r])], 1u);
+  if (m.R == 1) {
+    // one realization: |M| is the selection's count (cnt_m was cleared by
+    // the step's start)
+    for (int64_t i = gtid(); i < nM; i += gstride()) dist[midx[i]] = 0;
+    if (gtid() == 0) cnt_m[0] = uint32_t(nM);
+  } else {
+    for (int r = threadIdx.x; r < m.R; r += blockDim.x) bins[r] = 0;
+    __syncthreads();
+    for (int64_t i = gtid(); i < nM; i += gstride()) {
+      const uint32_t r = midx[i];
+      dist[r] = 0;
+      atomicAdd(&bins[pay_real(pay_o[r])], 1u);
+    }
+    count_flush(m.R, bins, cnt_m);
   }
-  count_flush(m.R, bins, cnt_m);
   if (gtid() == 0) {
     ctl->n_staged = 0;
     ctl->gstart[0] = 0;

@@ -21,9 +21,15 @@ steps, |S| at both ends, from the bench's JSON line) are the same.
 
     python -m paper_2603_07341_amd.profile_summary --trace DIR --fetch DIR \
         --write DIR --bench-json FILE --command CMD --out FILE
+
+The dispatches of a run between the copy's first mark and the window's
+last mark can be kept as a small CSV (`... extract trace DIR OUT`,
+`... extract FETCH_SIZE DIR OUT`, `... extract WRITE_SIZE DIR OUT`) and
+given to --trace / --fetch / --write in place of the folders.
 """
 import argparse
 import csv
+import re
 import glob
 import hashlib
 import json
@@ -78,10 +84,21 @@ def _between(disp, lo, hi):
     return [d for d in disp if a < d["id"] < b]
 
 
+_KNAME = re.compile(r"k_\w+(?:<[^()]*>)?")
+
+
+def short_name(name):
+    """Kernel name without return type, namespaces and parameter list
+    ("k_cheb_term<double, 1, 1, true>"); names of other kernels as given."""
+    m = _KNAME.search(name)
+    return m.group(0) if m else name
+
+
 def trace_dispatches(folder):
     out = []
     for r in _csv(folder, "kernel_trace.csv"):
-        out.append({"id": int(r["Dispatch_Id"]), "name": r["Kernel_Name"],
+        out.append({"id": int(r["Dispatch_Id"]),
+                    "name": short_name(r["Kernel_Name"]),
                     "ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
     return sorted(out, key=lambda d: d["id"])
 
@@ -92,9 +109,41 @@ def counter_dispatches(folder, counter):
         if r["Counter_Name"] != counter:
             continue
         i = int(r["Dispatch_Id"])
-        d = out.setdefault(i, {"id": i, "name": r["Kernel_Name"], "kib": 0.0})
+        d = out.setdefault(i, {"id": i, "name": short_name(r["Kernel_Name"]),
+                               "kib": 0.0})
         d["kib"] += float(r["Counter_Value"])
     return sorted(out.values(), key=lambda d: d["id"])
+
+
+def write_window_rows(folder, kind, counter, path):
+    """The dispatches between marks 0 and 3 of one run as a small CSV (id,
+    name, value: ns or KiB), so that the summary can be redone from them."""
+    disp = (trace_dispatches(folder) if kind == "trace"
+            else counter_dispatches(folder, counter))
+    key = "ns" if kind == "trace" else "kib"
+    marks = [d for d in disp if "k_mark" in d["name"]]
+    if len(marks) < 4:
+        raise SystemExit("found %d marks, need 4" % len(marks))
+    lo, hi = marks[0]["id"], marks[3]["id"]
+    with open(path, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["id", "name", key])
+        for d in disp:
+            if lo <= d["id"] <= hi:
+                w.writerow([d["id"], d["name"], d[key]])
+
+
+def read_window_rows(path):
+    seen, out = set(), []
+    with open(path, newline="") as fh:
+        r = csv.DictReader(fh)
+        key = [f for f in r.fieldnames if f in ("ns", "kib")][0]
+        for x in r:
+            i = int(x["id"])
+            if i not in seen:  # one row per dispatch
+                seen.add(i)
+                out.append({"id": i, "name": x["name"], key: float(x[key])})
+    return sorted(out, key=lambda d: d["id"])
 
 
 def stage_of(names):
@@ -118,18 +167,29 @@ def per_kernel(disp, key):
     return agg
 
 
+def _load(path, kind, counter=None):
+    if os.path.isfile(path):
+        return read_window_rows(path)
+    return (trace_dispatches(path) if kind == "trace"
+            else counter_dispatches(path, counter))
+
+
 def summarize(args):
-    trace = trace_dispatches(args.trace)
-    fetch = counter_dispatches(args.fetch, "FETCH_SIZE")
-    write = counter_dispatches(args.write, "WRITE_SIZE")
+    trace = _load(args.trace, "trace")
+    fetch = _load(args.fetch, "counter", "FETCH_SIZE")
+    write = _load(args.write, "counter", "WRITE_SIZE")
     with open(args.bench_json) as fh:
         line = [l for l in fh if l.strip().startswith("{")][-1]
     bench = json.loads(line)
     steps = int(bench["steps"])
     cfg = bench["config"]
-    # calibration: the copy between marks 0 and 1 moves 1 GiB each way
-    cf = sum(d["kib"] for d in _between(fetch, 0, 1)) * 1024.0
-    cw = sum(d["kib"] for d in _between(write, 0, 1)) * 1024.0
+    # calibration: the copy between marks 0 and 1 moves 1 GiB each way (the
+    # fill that makes its source also lies between the marks: only the
+    # copy dispatch counts)
+    cf = sum(d["kib"] for d in _between(fetch, 0, 1)
+             if "copyBuffer" in d["name"]) * 1024.0
+    cw = sum(d["kib"] for d in _between(write, 0, 1)
+             if "copyBuffer" in d["name"]) * 1024.0
     sf, sw = GIB / cf, GIB / cw
     tw, fw, ww = (_between(trace, 2, 3), _between(fetch, 2, 3),
                   _between(write, 2, 3))
@@ -192,11 +252,16 @@ def summarize(args):
     L.append("")
     L.append("## whole process (rocprofv3 --stats of the trace run), top kernels")
     try:
-        stats = _csv(args.trace, "kernel_stats.csv")
+        if args.stats and os.path.isfile(args.stats):
+            with open(args.stats, newline="") as fh:
+                stats = list(csv.DictReader(fh))
+        else:
+            stats = _csv(args.stats or args.trace, "kernel_stats.csv")
         L.append("   %-44s %8s %12s %10s %7s" % ("kernel", "calls", "total ms", "avg us", "%"))
         for r in stats[:25]:
             L.append("   %-44s %8s %12.3f %10.1f %7.2f" % (
-                r["Name"][:44], r["Calls"], float(r["TotalDurationNs"]) / 1e6,
+                short_name(r["Name"])[:44], r["Calls"],
+                float(r["TotalDurationNs"]) / 1e6,
                 float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
     except (SystemExit, KeyError) as e:
         L.append("   (no stats table: %s)" % e)
@@ -207,10 +272,24 @@ def summarize(args):
 
 
 def main(argv=None):
+    argv = sys.argv[1:] if argv is None else argv
+    if argv and argv[0] == "extract":
+        # extract trace DIR OUT | extract FETCH_SIZE DIR OUT | extract WRITE_SIZE DIR OUT
+        what, folder, out = argv[1], argv[2], argv[3]
+        if what == "trace":
+            write_window_rows(folder, "trace", None, out)
+        else:
+            write_window_rows(folder, "counter", what, out)
+        return
     ap = argparse.ArgumentParser()
-    ap.add_argument("--trace", required=True)
+    ap.add_argument("--trace", required=True,
+                    help="rocprofv3 output folder, or a window CSV written "
+                         "by --extract")
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
+    ap.add_argument("--stats", default=None,
+                    help="folder holding the trace run's kernel_stats.csv "
+                         "(default: --trace)")
     ap.add_argument("--bench-json", required=True)
     ap.add_argument("--command", required=True)
     ap.add_argument("--title", default="Timed window of the ring16 bench step "
