@@ -240,7 +240,8 @@ def main():
                          "stage events" % args.stage_steps,
         "stages": stage_bandwidth(model, A, sprof, srec,
                                   float(rec[-1, 7]), args.stage_steps,
-                                  copy_peak_gbs(), wprof),
+                                  copy_peak_gbs(), wprof,
+                                  bool(tuning.get("warm", 0))),
         "tuning": tuning,
         "terms_per_step": float(rec[:, 9].mean()),
     }
@@ -433,7 +434,8 @@ def copy_peak_gbs(mib=1024, reps=5):
     return 2.0 * mib * (1 << 20) / (best * 1e-3) / 1e9
 
 
-def stage_bandwidth(model, A, sprof, srec, n_old0, steps, copy_gbs, wprof):
+def stage_bandwidth(model, A, sprof, srec, n_old0, steps, copy_gbs, wprof,
+                    in_place=False):
     """Effective bandwidth per stage over the stage-event steps: algorithmic
     bytes (compulsory streams, each once per pass; gathers counted as cache
     hits) from the steps' own counts, over the stage's event time.  With a
@@ -445,7 +447,10 @@ def stage_bandwidth(model, A, sprof, srec, n_old0, steps, copy_gbs, wprof):
                     rho = net growth of S / |S| (a lower bound on new rows)
       transfer      n_old (16W + 8 + 2A)
       propagate     |S| K (4A + 4D + 8)  (Clenshaw)
-      observe       |S| 2A"""
+      observe       |S| 2A
+    Steps that expand in place (from the previous step's graph) turn psi
+    into phi and drop rows inside the expansion, so their transfer stage
+    has no rate of its own: it is reported with the expansion only."""
     W, D = model.W, model.D
     nS = srec[:, 7]
     nM = srec[:, 8]
@@ -468,6 +473,12 @@ def stage_bandwidth(model, A, sprof, srec, n_old0, steps, copy_gbs, wprof):
         t = ms[k] * 1e-3
         tb += b
         tt += t
+        if in_place and k == "transfer":
+            out[k] = {"bytes_per_step": None, "ms_per_step": ms[k] / steps,
+                      "effective": None,
+                      "note": "inside the in-place expansion; see "
+                              "expand+transfer+build"}
+            continue
         g = b / t / 1e9 if t > 0 else 0.0
         out[k] = {"bytes_per_step": b / steps, "ms_per_step": ms[k] / steps,
                   "effective": g, "frac_spec": g / HBM_PEAK_GBS,
@@ -479,9 +490,9 @@ def stage_bandwidth(model, A, sprof, srec, n_old0, steps, copy_gbs, wprof):
                            "kernel_ms_per_step": st["kernel_ms"],
                            "achieved": ach,
                            "achieved_frac_spec": ach / HBM_PEAK_GBS})
-    # steps that expand from the previous graph move the rows, phi and the
-    # dropped weight inside the expansion: the transfer stage keeps only
-    # the fold of the weight, so the two are also given together
+    # steps that expand in place make phi and the dropped weight inside the
+    # expansion: the transfer stage keeps only the fold of the weight, so
+    # the two are also given together
     b = by["expand+build"] + by["transfer"]
     t = (ms["expand+build"] + ms["transfer"]) * 1e-3
     g = b / t / 1e9 if t > 0 else 0.0

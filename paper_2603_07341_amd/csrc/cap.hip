@@ -74,12 +74,13 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 __global__ void __launch_bounds__(kBlock)
-    k_count_real(DevModel m, const uint64_t* pay, int64_t n, uint32_t* out) {
+    k_count_real(DevModel m, const uint64_t* pay, const uint32_t* idx,
+                 int64_t n, uint32_t* out) {
   __shared__ uint32_t bins[kMaxReal];
   for (int r = threadIdx.x; r < m.R; r += blockDim.x) bins[r] = 0;
   __syncthreads();
   for (int64_t i = gtid(); i < n; i += gstride())
-    atomicAdd(&bins[pay_real(pay[i])], 1u);
+    atomicAdd(&bins[pay_real(pay[idx ? int64_t(idx[i]) : i])], 1u);
   __syncthreads();
   for (int r = threadIdx.x; r < m.R; r += blockDim.x)
     if (bins[r]) atomicAdd(&out[r], bins[r]);
@@ -216,10 +217,11 @@ void cap_check(const DevModel& m, const StepCtl* ctl, const uint64_t* pay,
 }
 
 void count_per_real(const DevModel& m, const uint64_t* pay, int64_t n,
-                    uint32_t* out, hipStream_t s) {
+                    uint32_t* out, hipStream_t s, const uint32_t* idx) {
   (void)hipMemsetAsync(out, 0, size_t(m.R) * 4, s);
   if (n <= 0) return;
-  k_count_real<<<std::min(grid_for(n), 2048), kBlock, 0, s>>>(m, pay, n, out);
+  k_count_real<<<std::min(grid_for(n), 2048), kBlock, 0, s>>>(m, pay, idx, n,
+                                                              out);
 }
 
 void iota_u32(uint32_t* p, int64_t n, hipStream_t s) {

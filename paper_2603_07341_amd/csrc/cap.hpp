@@ -23,7 +23,8 @@ void cap_check(const DevModel& m, const StepCtl* ctl, const uint64_t* pay,
 // Rows of a set per realization (out[R], cleared first; eager use only:
 // the clear is a memset).
 void count_per_real(const DevModel& m, const uint64_t* pay, int64_t n,
-                    uint32_t* out, hipStream_t s);
+                    uint32_t* out, hipStream_t s,
+                    const uint32_t* idx = nullptr);
 // p[i] = i for i < n.
 void iota_u32(uint32_t* p, int64_t n, hipStream_t s);
 // Per selected row j (row midx[j] of the old side): status 1 (kept) for

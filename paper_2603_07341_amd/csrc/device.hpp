@@ -29,6 +29,10 @@ constexpr uint64_t kEmpty = ~0ull;       // free hash slot
 constexpr uint64_t kMaxProbe = 4096;
 constexpr uint32_t kCand = 0x80000000u;  // ref names a candidate, not a row
 constexpr uint32_t kNone = 0xFFFFFFFFu;  // no slot / no column
+// Distance byte of a row that is a hole: a row of an in-place step's set
+// whose state was dropped (no key in the table, amplitude 0, no columns,
+// and no column of another row points at it).
+constexpr uint8_t kHole = 0xFE;
 constexpr int kGsqStride = 256;          // g*sqrt(n) table row length
 
 // Device error latch bits.

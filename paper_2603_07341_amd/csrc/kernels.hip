@@ -52,6 +52,8 @@ __global__ void __launch_bounds__(kBlock)
 // runs show in stream order.
 __global__ void k_mark(int tag) { (void)tag; }
 
+__global__ void k_clear_err(int* err) { *err = 0; }
+
 // ---- a given set of states (stateless propagation) --------------------------
 // Canonical keys of W words to the internal width Wi >= W (leading zero
 // words; one realization, so no realization bits).
@@ -115,6 +117,7 @@ __global__ void k_begin_step(StepCtl* ctl, int* err, uint32_t* cnt, int n) {
     ctl->n_new = 0;
     ctl->kmax = 0;
     ctl->r_need = 0;
+    ctl->w_moved = 0;  // an in-place step has not committed
   }
 }
 
@@ -195,17 +198,23 @@ __global__ void __launch_bounds__(kBlock)
 
 // ---- select -----------------------------------------------------------------
 
+// Rows that are holes (dist == kHole, left by dropped rows of in-place
+// steps) are never selected; dist may be null (no holes).
+__device__ __forceinline__ bool is_hole(const uint8_t* dist, int64_t e) {
+  return dist && dist[e] == kHole;
+}
+
 template <typename Amp>
 __global__ void __launch_bounds__(kBlock)
-    k_select_count(const Amp* psi, const StepCtl* ctl, double th2,
-                   uint32_t* bsum) {
+    k_select_count(const Amp* psi, const uint8_t* dist, const StepCtl* ctl,
+                   double th2, uint32_t* bsum) {
   const int64_t n = ctl->n_old, ntiles = cdiv(n, kTile);
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     uint32_t v = 0;
 #pragma unroll
     for (int q = 0; q < kItems; ++q) {
       const int64_t e = t * kTile + q * kBlock + threadIdx.x;
-      if (e < n && weight(psi[e]) >= th2) ++v;
+      if (e < n && weight(psi[e]) >= th2 && !is_hole(dist, e)) ++v;
     }
     uint32_t tot;
     block_excl_scan(v, &tot);
@@ -217,15 +226,15 @@ __global__ void __launch_bounds__(kBlock)
 // then one block scan per run of kBlock rows.
 template <typename Amp>
 __global__ void __launch_bounds__(kBlock)
-    k_select_write(const Amp* psi, const StepCtl* ctl, double th2,
-                   const uint32_t* bsum, uint32_t* midx) {
+    k_select_write(const Amp* psi, const uint8_t* dist, const StepCtl* ctl,
+                   double th2, const uint32_t* bsum, uint32_t* midx) {
   const int64_t n = ctl->n_old, ntiles = cdiv(n, kTile);
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     uint32_t run = bsum[t];
 #pragma unroll
     for (int q = 0; q < kItems; ++q) {
       const int64_t e = t * kTile + q * kBlock + threadIdx.x;
-      const bool keep = e < n && weight(psi[e]) >= th2;
+      const bool keep = e < n && weight(psi[e]) >= th2 && !is_hole(dist, e);
       uint32_t tot;
       const uint32_t off = block_excl_scan(keep ? 1u : 0u, &tot) + run;
       if (keep) midx[off] = uint32_t(e);
@@ -583,7 +592,8 @@ __global__ void __launch_bounds__(kBlock)
 // already in place (insert) and are passed over.
 template <int W, typename Amp>
 __global__ void __launch_bounds__(kBlock)
-    k_transfer(DevModel m, const uint64_t* keys_o, const Amp* psi_o,
+    k_transfer(DevModel m, const uint64_t* keys_o, const uint8_t* o_dist,
+               const Amp* psi_o,
                const StepCtl* ctl, const uint64_t* table, uint64_t mask,
                const uint64_t* keys_n, Amp* phi, double* mass_part,
                int32_t* tmap, int skip, double th2, const uint8_t* keep,
@@ -598,6 +608,10 @@ __global__ void __launch_bounds__(kBlock)
   const int64_t n_old = ctl->n_old;
   double lost = 0;
   for (int64_t i = gtid(); i < n_old; i += gstride()) {
+    if (is_hole(o_dist, i)) {
+      if (tmap) tmap[i] = -1;
+      continue;
+    }
     const Amp v = psi_o[i];
     if ((skip == 1 && weight(v) >= th2) || (skip == 2 && keep[i])) continue;
     uint64_t k[W];
@@ -636,8 +650,8 @@ __device__ __forceinline__ double dbl_of(long long o) {
 // block the (lo, hi) of each realization go to part[block][r][2].
 __global__ void __launch_bounds__(kBlock)
     k_bounds(DevModel m, const uint64_t* pay, const uint64_t* tot,
-             const int32_t* col, int64_t cap, const StepCtl* ctl,
-             double* part, const int* err) {
+             const uint8_t* dist, const int32_t* col, int64_t cap,
+             const StepCtl* ctl, double* part, const int* err) {
   __shared__ long long blo[kMaxReal], bhi[kMaxReal];
   if (*err) return;
   const int R = m.R;
@@ -651,6 +665,7 @@ __global__ void __launch_bounds__(kBlock)
   const int64_t n = ctl->n_new;
   double lo = INFINITY, hi = -INFINITY;
   for (int64_t r = gtid(); r < n; r += gstride()) {
+    if (is_hole(dist, r)) continue;
     const uint64_t p = pay[r];
     double rad = 0;
     for (int s = 0; s < m.D; ++s)
@@ -972,6 +987,7 @@ template <typename R>
 __global__ void __launch_bounds__(kBlock)
     k_pop_norm(int N, int Rn, double th2, const StepCtl* ctl,
                const typename VecT<R>::T* psi, const uint64_t* pay,
+               const uint8_t* dist,
                const double* e_row, double* n2_part, double* en_part,
                double* pop_part, uint32_t* sel_bsum, uint32_t* cnt_s,
                const int* err) {
@@ -998,7 +1014,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int q = 0; q < kItems; ++q) {
       const int64_t e = t * kTile + q * kBlock + threadIdx.x;
-      if (e < n) {
+      if (e < n && !is_hole(dist, e)) {
         const double w = weight(psi[e]);
         const uint64_t p = pay[e];
         keep += w >= th2 ? 1u : 0u;
@@ -1213,6 +1229,8 @@ void fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
 
 void mark(int tag, hipStream_t s) { k_mark<<<1, 64, 0, s>>>(tag); }
 
+void clear_latch(int* err, hipStream_t s) { k_clear_err<<<1, 1, 0, s>>>(err); }
+
 void pad_keys(int W, int Wi, const uint64_t* in, uint64_t* out, int64_t n,
               hipStream_t s) {
   if (n <= 0) return;
@@ -1236,9 +1254,9 @@ void begin_step(StepCtl* ctl, int* err, uint32_t* cnt, int R,
   k_begin_step<<<1, kBlock, 0, s>>>(ctl, err, cnt, 2 * R);
 }
 
-void select_rows(int prec, const void* psi, double th2, bool select_all,
-                 bool counted, StepCtl* ctl, uint32_t* midx, uint32_t* tmp,
-                 int64_t cap, int* err, hipStream_t s) {
+void select_rows(int prec, const void* psi, const uint8_t* dist, double th2,
+                 bool select_all, bool counted, StepCtl* ctl, uint32_t* midx,
+                 uint32_t* tmp, int64_t cap, int* err, hipStream_t s) {
   if (select_all) {
     k_select_all<<<grid_for(cap), kBlock, 0, s>>>(ctl, midx);
     return;
@@ -1246,16 +1264,16 @@ void select_rows(int prec, const void* psi, double th2, bool select_all,
   const int g = tiles_for(cap);
   if (!counted) {
     if (prec == 64)
-      k_select_count<double2><<<g, kBlock, 0, s>>>((const double2*)psi, ctl, th2, tmp);
+      k_select_count<double2><<<g, kBlock, 0, s>>>((const double2*)psi, dist, ctl, th2, tmp);
     else
-      k_select_count<float2><<<g, kBlock, 0, s>>>((const float2*)psi, ctl, th2, tmp);
+      k_select_count<float2><<<g, kBlock, 0, s>>>((const float2*)psi, dist, ctl, th2, tmp);
   }
   k_scan_bsum<<<1, kBlock, 0, s>>>(tmp, &ctl->n_old, &ctl->nM, &ctl->fstart[1],
                                    err);
   if (prec == 64)
-    k_select_write<double2><<<g, kBlock, 0, s>>>((const double2*)psi, ctl, th2, tmp, midx);
+    k_select_write<double2><<<g, kBlock, 0, s>>>((const double2*)psi, dist, ctl, th2, tmp, midx);
   else
-    k_select_write<float2><<<g, kBlock, 0, s>>>((const float2*)psi, ctl, th2, tmp, midx);
+    k_select_write<float2><<<g, kBlock, 0, s>>>((const float2*)psi, dist, ctl, th2, tmp, midx);
 }
 
 void select_flags(const uint8_t* keep, StepCtl* ctl, uint32_t* midx,
@@ -1365,12 +1383,12 @@ int transfer(const DevModel& m, int Wi, int prec, const Side& o,
   const int g = m.R > 1 ? std::min(grid_for(n_old), kPartBlocks) : grid_for(n_old);
   if (prec == 64) {
     PACES_DISPATCH_W(Wi, k_transfer<WW, double2><<<g, kBlock, 0, s>>>(
-                             m, o.keys, (const double2*)psi_o, ctl, table, mask,
+                             m, o.keys, o.dist, (const double2*)psi_o, ctl, table, mask,
                              keys_n, (double2*)phi, mass_part, tmap, skip, th2,
                              keep, err));
   } else {
     PACES_DISPATCH_W(Wi, k_transfer<WW, float2><<<g, kBlock, 0, s>>>(
-                             m, o.keys, (const float2*)psi_o, ctl, table, mask,
+                             m, o.keys, o.dist, (const float2*)psi_o, ctl, table, mask,
                              keys_n, (float2*)phi, mass_part, tmap, skip, th2,
                              keep, err));
   }
@@ -1381,7 +1399,7 @@ int bounds_part(const DevModel& m, const Side& n, const int32_t* col,
                 int64_t cap, int64_t est, const StepCtl* ctl, double* part,
                 const int* err, hipStream_t s) {
   const int g = std::min(grid_for(est), kPartBlocks);
-  k_bounds<<<g, kBlock, 0, s>>>(m, n.pay, n.tot, col, cap, ctl, part, err);
+  k_bounds<<<g, kBlock, 0, s>>>(m, n.pay, n.tot, n.dist, col, cap, ctl, part, err);
   return g;
 }
 
@@ -1392,7 +1410,7 @@ void bounds_and_coef(const DevModel& m, const Side& n, const int32_t* col,
   // a bounded grid: each block reduces many rows, and k_coef folds few
   // partials
   const int g = std::min(grid_for(est), kPartBlocks);
-  k_bounds<<<g, kBlock, 0, s>>>(m, n.pay, n.tot, col, cap, ctl, part, err);
+  k_bounds<<<g, kBlock, 0, s>>>(m, n.pay, n.tot, n.dist, col, cap, ctl, part, err);
   k_coef<<<m.R, kBlock, 0, s>>>(part, g, m.R, dt, tol, k_max, launched, cc,
                                 ctl, err);
 }
@@ -1440,6 +1458,7 @@ int cheb_term(const DevModel& m, int prec, int kk, bool energy, bool mid,
 
 int pop_norm(int prec, int N, int R, double th2, int64_t est,
              const StepCtl* ctl, const void* psi, const uint64_t* pay,
+             const uint8_t* dist,
              const double* e_row, double* n2_part, double* en_part,
              double* pop_part, uint32_t* sel_bsum, uint32_t* cnt_s, int* err,
              hipStream_t s) {
@@ -1449,11 +1468,11 @@ int pop_norm(int prec, int N, int R, double th2, int64_t est,
   const int g = R > 1 ? std::min(tiles_for(est), 1024) : tiles_for(est);
   if (prec == 64)
     k_pop_norm<double><<<g, kBlock, lds, s>>>(
-        N, R, th2, ctl, (const double2*)psi, pay, e_row, n2_part, en_part,
+        N, R, th2, ctl, (const double2*)psi, pay, dist, e_row, n2_part, en_part,
         pop_part, sel_bsum, cnt_s, err);
   else
     k_pop_norm<float><<<g, kBlock, lds, s>>>(
-        N, R, th2, ctl, (const float2*)psi, pay, e_row, n2_part, en_part,
+        N, R, th2, ctl, (const float2*)psi, pay, dist, e_row, n2_part, en_part,
         pop_part, sel_bsum, cnt_s, err);
   return g;
 }

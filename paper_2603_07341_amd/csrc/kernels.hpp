@@ -52,6 +52,9 @@ struct StepCtl {
   // the table entries of dropped rows turned into tombstones by this step
   uint32_t gstart[kMaxRounds + 2];
   uint32_t n_staged, w_noc, w_f0, w_nkeep, w_moved, w_tomb;
+  // in-place steps: holes of the set at the step's start (the free list's
+  // length) and the set's live rows after the step (n_new is its row range)
+  uint32_t nfree, n_live;
   double t;                           // time after the last completed step
 };
 
@@ -84,6 +87,8 @@ int64_t scan_tmp_words(int64_t n);
 void fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
 // One empty dispatch (kernel k_mark) on the stream.
 void mark(int tag, hipStream_t s);
+// The error latch cleared on the stream.
+void clear_latch(int* err, hipStream_t s);
 // A given set of n states as the rows of a step: keys padded from W to Wi
 // words; control counts with frontier 0 = rows [0, n) and the latch
 // cleared; every key valid and distinct (else kErrInput), after the rows
@@ -98,12 +103,13 @@ void check_set(const DevModel& m, int Wi, const uint64_t* keys, int64_t n,
 // Start of a step: clear the latch, reset the counters (cnt: 2R
 // per-realization row counts, |M_r| then |S_r|).
 void begin_step(StepCtl* ctl, int* err, uint32_t* cnt, int R, hipStream_t s);
-// Rows of ctl->n_old with weight >= th2, ascending, into midx; ctl->nM.
+// Rows of ctl->n_old with weight >= th2 that are not holes (dist may be
+// null), ascending, into midx; ctl->nM.
 // select_all: the first step takes every row.
 // counted: tmp already holds the per-tile counts (from pop_norm).
-void select_rows(int prec, const void* psi, double th2, bool select_all,
-                 bool counted, StepCtl* ctl, uint32_t* midx, uint32_t* tmp,
-                 int64_t cap, int* err, hipStream_t s);
+void select_rows(int prec, const void* psi, const uint8_t* dist, double th2,
+                 bool select_all, bool counted, StepCtl* ctl, uint32_t* midx,
+                 uint32_t* tmp, int64_t cap, int* err, hipStream_t s);
 // Rows of ctl->n_old with keep[row] != 0, ascending, into midx; ctl->nM.
 void select_flags(const uint8_t* keep, StepCtl* ctl, uint32_t* midx,
                   uint32_t* tmp, int64_t cap, int* err, hipStream_t s);
@@ -181,6 +187,7 @@ int cheb_term(const DevModel& m, int prec, int kk, bool energy, bool mid,
 // count, at most kPartBlocks), plus the next step's select counts.
 int pop_norm(int prec, int N, int R, double th2, int64_t est,
              const StepCtl* ctl, const void* psi, const uint64_t* pay,
+             const uint8_t* dist,
              const double* e_row, double* n2_part, double* en_part,
              double* pop_part, uint32_t* sel_bsum, uint32_t* cnt_s, int* err,
              hipStream_t s);

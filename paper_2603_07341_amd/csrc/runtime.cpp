@@ -311,10 +311,17 @@ struct paces_sim {
   WarmBufs wb{};
   bool graph_ok = false;   // side cur holds complete columns and the table
                            // maps its keys to its rows (probed over tmask)
-  bool warm_step = false;  // the step being run expands from that graph
+  bool warm_step = false;  // the step being run expands from that graph,
+                           // in place on side cur
   bool last_warm = false;  // the last completed step did
+  int nside = 1;           // side the step being run builds its set on
+  bool swapped = false;    // the in-place step made psi its phi (ipsi and
+                           // iphi exchanged at its transfer)
   int64_t tomb = 0;        // tombstones in the table since it was built
   int warm_np = 0;         // partial blocks of the dropped weight
+  int warm_nmass = 0;      // the step's folded weight partials
+  int64_t nlive = 0;       // live rows of side cur; nS is its row range
+  bool has_holes = false;  // side cur has holes (nlive < nS)
   uint32_t* dcount = nullptr;  // [1] a count read back by the host
 
   // a step run stage by stage (paces_run_stage)
@@ -401,10 +408,17 @@ struct paces_sim {
   paces_tuning tune{0, 1, 1, 1};
   hipStream_t cap_stream = nullptr;  // capture only; never runs work
   uint64_t gen = 0;                  // bumped whenever a buffer moves
+  // What enqueueing a step leaves on the host (buffer roles, partial
+  // counts); a graph replay sets it as its capture did.
+  struct HostFx {
+    int ipsi, iphi, warm_np, warm_nmass;
+    bool swapped;
+  };
   struct GraphEntry {
     std::vector<int64_t> key;
     hipGraphExec_t exec;
     uint64_t used;
+    HostFx fx;
   };
   std::vector<GraphEntry> graphs;
   uint64_t graph_clock = 0;
@@ -476,8 +490,7 @@ void free_rows(paces_sim* s) {
   s->rows_bytes = 0;
   for (int q = 0; q < 2; ++q) s->side[q] = Side{};
   for (auto& v : s->vec) v = nullptr;
-  s->wb.kbits = nullptr;
-  s->wb.kpre = nullptr;
+  s->wb.freel = nullptr;
   s->wb.wmask = nullptr;
   s->graph_ok = false;
   s->midx = nullptr;
@@ -557,8 +570,7 @@ struct RowBlock {
   Side sd[2]{};
   void* vec[4] = {nullptr, nullptr, nullptr, nullptr};
   uint32_t *midx = nullptr, *scan = nullptr;
-  uint64_t* kbits = nullptr;
-  uint32_t* kpre = nullptr;
+  uint32_t* freel = nullptr;
   uint16_t* wmask = nullptr;
   double* erow = nullptr;
   std::vector<void*> kry;
@@ -580,8 +592,7 @@ struct RowBlock {
     }
     for (int v = 0; v < 4; ++v) pc.add_bytes(&vec[v], size_t(cap) * s->A);
     pc.add(&midx, cap);
-    pc.add(&kbits, cap / 64 + 1);
-    pc.add(&kpre, cap / 64 + 1);
+    pc.add(&freel, cap);
     pc.add(&wmask, cap);
     pc.add(&scan, scan_tmp_words(cap));
     if (m->R > 1) pc.add(&erow, cap);
@@ -636,21 +647,33 @@ paces_status grow(paces_sim* s, int64_t new_cap, int64_t min_cap,
   // The current set and psi are parked in a compact block while the old
   // row block, table and candidate buffers are released, then copied into
   // the new row block (every row array but the table, in one block).
-  const int64_t n = s->nS;
+  // Holes of an in-place step are left out.
+  const int64_t n = s->nlive;
   const size_t kb = size_t(n) * m->Wi * 8, ab = size_t(n) * s->A;
   uint8_t* park = nullptr;
   if (n > 0) {
     void* q = nullptr;
-    ST_TRY(dev_alloc(&q, kb + 16 * size_t(n) + ab + 1024));
+    ST_TRY(dev_alloc(&q, kb + 16 * size_t(n) + ab + 4 * size_t(n) + 1024));
     park = static_cast<uint8_t*>(q);
     const Side& o = s->side[s->cur];
-    HIP_TRY(hipMemcpyAsync(park, o.keys, kb, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipMemcpyAsync(park + kb, o.pay, size_t(n) * 8,
-                           hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipMemcpyAsync(park + kb + 8 * size_t(n), o.tot, size_t(n) * 8,
-                           hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipMemcpyAsync(park + kb + 16 * size_t(n), s->vec[s->ipsi], ab,
-                           hipMemcpyDeviceToDevice, st));
+    if (s->has_holes) {
+      uint32_t* idx = reinterpret_cast<uint32_t*>(park + kb + 16 * size_t(n) + ab);
+      rows_at_distance(m->Wi, o.keys, o.dist, s->nS, -1, nullptr, idx,
+                       s->dcount, s->scan_tmp, s->err, st);
+      gather_rows(m->Wi, s->A, o, s->vec[s->ipsi], idx, n,
+                  reinterpret_cast<uint64_t*>(park),
+                  reinterpret_cast<uint64_t*>(park + kb),
+                  reinterpret_cast<uint64_t*>(park + kb + 8 * size_t(n)),
+                  park + kb + 16 * size_t(n), st);
+    } else {
+      HIP_TRY(hipMemcpyAsync(park, o.keys, kb, hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemcpyAsync(park + kb, o.pay, size_t(n) * 8,
+                             hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemcpyAsync(park + kb + 8 * size_t(n), o.tot, size_t(n) * 8,
+                             hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemcpyAsync(park + kb + 16 * size_t(n), s->vec[s->ipsi], ab,
+                             hipMemcpyDeviceToDevice, st));
+    }
   }
   HIP_TRY(hipStreamSynchronize(st));
   if (s->rows_block) dev_free(s->rows_block);
@@ -676,6 +699,8 @@ paces_status grow(paces_sim* s, int64_t new_cap, int64_t min_cap,
     free_rows(s);
     s->cap = 0;
     s->nS = 0;
+    s->nlive = 0;
+    s->has_holes = false;
     s->latched = kErrCapacity;
     return fail(PACES_E_OOM, "row arrays do not fit the device");
   }
@@ -688,16 +713,18 @@ paces_status grow(paces_sim* s, int64_t new_cap, int64_t min_cap,
                            hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(nb.vec[s->ipsi], park + kb + 16 * size_t(n), ab,
                            hipMemcpyDeviceToDevice, st));
+    dist_fill(c.dist, n, 0, st);
     HIP_TRY(hipStreamSynchronize(st));
     dev_free(park);
   }
+  s->nS = n;
+  s->has_holes = false;
   s->rows_block = block;
   s->rows_bytes = nb.pc.total();
   s->side[0] = nb.sd[0];
   s->side[1] = nb.sd[1];
   for (int v = 0; v < 4; ++v) s->vec[v] = nb.vec[v];
-  s->wb.kbits = nb.kbits;
-  s->wb.kpre = nb.kpre;
+  s->wb.freel = nb.freel;
   s->wb.wmask = nb.wmask;
   s->graph_ok = false;  // columns and table are rebuilt by the next step
   s->midx = nb.midx;
@@ -761,6 +788,8 @@ paces_status upload_state(paces_sim* s, int64_t n,
   const paces_model* m = s->m;
   if (n > s->cap) {
     s->nS = 0;
+    s->nlive = 0;
+    s->has_holes = false;
     ST_TRY(grow(s, std::max<int64_t>(2 * n, 2 * s->cap), n, st));
   }
   Side& sc = s->side[s->cur];
@@ -772,10 +801,13 @@ paces_status upload_state(paces_sim* s, int64_t n,
     HIP_TRY(hipMemcpyAsync(tmp, amps, size_t(n) * 16, hipMemcpyHostToDevice, st));
     amps_from_f64(s->prec, tmp, s->vec[s->ipsi], n, st);
     row_info(m->dm, m->Wi, sc.keys, n, sc.pay, sc.tot, st);
+    dist_fill(sc.dist, n, 0, st);  // every row live
     HIP_TRY(hipStreamSynchronize(st));
     dfree(tmp);
   }
   s->nS = n;
+  s->nlive = n;
+  s->has_holes = false;
   s->h.n_old = uint32_t(n);
   s->graph_ok = false;  // no columns yet: the next step expands from scratch
   return push_ctl(s, st);
@@ -816,38 +848,34 @@ void stage_select(paces_sim* s, bool counted, hipStream_t st,
     select_flags(s->keep, s->ctl, s->midx, s->scan_tmp,
                  std::min(bucket(s->nS), s->cap), s->err, st);
   else
-    select_rows(s->prec, s->vec[s->ipsi], s->th2, s->fresh, counted, s->ctl,
-                s->midx, s->scan_tmp, std::min(bucket(s->nS), s->cap), s->err,
-                st);
+    select_rows(s->prec, s->vec[s->ipsi], s->side[s->cur].dist, s->th2,
+                s->fresh, counted, s->ctl, s->midx, s->scan_tmp,
+                std::min(bucket(s->nS), s->cap), s->err, st);
   if (s->warm_step)
-    warm_begin(s->m->dm, s->ctl, s->midx, s->side[s->cur], s->cnt, s->nS,
-               s->err, st);
+    warm_begin(s->m->dm, s->ctl, s->midx, s->side[s->cur], s->wb, s->cnt,
+               s->nS, s->scan_tmp, s->err, st);
 }
 
-// expand + merge + build of the columns from the previous step's graph:
-// k rounds of the breadth-first search, the new set's size, the old rows
-// moved behind the new ones (with phi and the dropped weight), the
-// state-cap check, the columns, and the table rewritten to the new rows.
+// expand + merge + build of the columns from the previous step's graph, in
+// place: k rounds of the breadth-first search (found states take holes or
+// rows past the range), the new set's sizes with the state-cap check, then
+// the commit: unreached rows become holes (with the dropped weight), found
+// states get their columns and their table entries.
 void stage_expand_warm(paces_sim* s, int64_t est, hipStream_t st) {
   const paces_model* m = s->m;
   const DevModel& dm = m->dm;
   const int Wi = m->Wi;
   const int k = s->p.k;
-  const Side so = s->side[s->cur], sn = s->side[1 - s->cur];
+  const Side c = s->side[s->cur];
   Stage sg(s, PACES_STAGE_EXPAND, st);
   for (int r = 1; r <= k; ++r)
-    warm_round(dm, Wi, s->prec, so, sn, r, s->ctl, s->cap, s->nS, est,
-               s->table, s->tmask, s->rb, s->wb, s->scan_tmp,
-               s->vec[s->iphi], s->err, st);
-  warm_count(so, k, s->ctl, s->nS, s->cap, s->scan_tmp, s->err, st);
-  s->warm_np = warm_compact(dm, Wi, s->prec, so, sn, k, s->ctl, s->nS,
-                            s->vec[s->ipsi], s->vec[s->iphi], s->scan_tmp,
-                            s->wb, s->mass_part, s->err, st);
-  if (s->p.max_states > 0)
-    cap_check(dm, s->ctl, sn.pay, est, s->p.max_states, s->ball, s->err, st);
-  warm_columns(dm, Wi, so, sn, s->ctl, s->nS, est, s->table, s->tmask, s->wb,
-               s->err, st);
-  warm_retable(s->ctl, s->table, s->tmask, s->wb, s->err, st);
+    warm_round(dm, Wi, s->prec, c, r, s->ctl, s->cap, s->nS, est, s->table,
+               s->tmask, s->rb, s->wb, s->scan_tmp, s->vec[s->ipsi], s->err,
+               st);
+  warm_sizes(dm, c, k, s->ctl, est, s->p.max_states, s->ball, s->err, st);
+  s->warm_np = warm_commit(dm, Wi, s->prec, c, k, s->ctl, s->nS, est,
+                           s->table, s->tmask, s->wb, s->vec[s->ipsi],
+                           s->mass_part, s->err, st);
 }
 
 // expand + merge + build of the columns: M into the cleared table, k
@@ -883,6 +911,7 @@ void stage_expand(paces_sim* s, int64_t est, hipStream_t st,
               s->err, st);
   if (s->p.max_states > 0)
     cap_check(dm, s->ctl, sn.pay, est, s->p.max_states, s->ball, s->err, st);
+  dist_of_rounds(s->ctl, k, sn.dist, est, st);
 }
 
 // transfer: old amplitudes into phi, discarded weight.
@@ -893,10 +922,16 @@ void stage_transfer(paces_sim* s, hipStream_t st, const FrozenStep* fz,
   const Side so = s->side[s->cur], sn = s->side[1 - s->cur];
   Stage sg(s, PACES_STAGE_TRANSFER, st);
   if (s->warm_step && !fz) {
-    // phi and the dropped weight came with the rows from the expansion
+    // the in-place expansion left phi in psi's buffer (kept amplitudes,
+    // zeros elsewhere) and the dropped weight in partials
     L.n_mass = R == 1 ? fold_sum(s->mass_part, s->warm_np, s->mass_fold,
                                  s->err, st)
                       : s->warm_np;
+    s->warm_nmass = L.n_mass;
+    if (!s->swapped) {
+      std::swap(s->ipsi, s->iphi);
+      s->swapped = true;
+    }
     return;
   }
   // rows of M were placed with their amplitudes by the insert; the frozen
@@ -915,7 +950,7 @@ void stage_transfer(paces_sim* s, hipStream_t st, const FrozenStep* fz,
 // Krylov propagator builds its small matrix inside the propagation).
 void stage_build(paces_sim* s, int64_t est, hipStream_t st) {
   const paces_model* m = s->m;
-  const Side sn = s->side[1 - s->cur];
+  const Side sn = s->side[s->nside];
   if (s->p.krylov_order > 0) return;
   Stage sg(s, PACES_STAGE_BUILD, st);
   if (s->p.taylor_order != 0) {
@@ -937,7 +972,7 @@ void stage_propagate(paces_sim* s, int64_t est, hipStream_t st,
   const paces_model* m = s->m;
   const DevModel& dm = m->dm;
   const int R = m->R;
-  const Side sn = s->side[1 - s->cur];
+  const Side sn = s->side[s->nside];
   const bool want_e = (s->p.obs_mask & PACES_OBS_ENERGY) != 0;
   Stage sg(s, PACES_STAGE_PROPAGATE, st);
   if (s->p.taylor_order != 0) {
@@ -1015,12 +1050,12 @@ void stage_observe(paces_sim* s, int64_t est, hipStream_t st,
   const paces_model* m = s->m;
   const DevModel& dm = m->dm;
   const int R = m->R;
-  const Side sn = s->side[1 - s->cur];
+  const Side sn = s->side[s->nside];
   const bool want_e = (s->p.obs_mask & PACES_OBS_ENERGY) != 0;
   const bool krylov = s->p.krylov_order > 0;
   Stage sg(s, PACES_STAGE_OBSERVE, st);
   const int n_pop = pop_norm(s->prec, m->N, R, s->th2, est, s->ctl,
-                             s->vec[s->ib0], sn.pay,
+                             s->vec[s->ib0], sn.pay, sn.dist,
                              want_e && R > 1 && !krylov ? s->e_row : nullptr,
                              s->n2_part, s->en_part, s->pop_part, s->scan_tmp,
                              s->cnt + R, s->err, st);
@@ -1064,6 +1099,11 @@ paces_status launch_step_graph(paces_sim* s, int64_t est, bool counted,
     if (g.key == key) {
       g.used = ++s->graph_clock;
       HIP_TRY(hipGraphLaunch(g.exec, st));
+      s->ipsi = g.fx.ipsi;
+      s->iphi = g.fx.iphi;
+      s->warm_np = g.fx.warm_np;
+      s->warm_nmass = g.fx.warm_nmass;
+      s->swapped = g.fx.swapped;
       return PACES_OK;
     }
   if (!s->cap_stream)
@@ -1087,7 +1127,9 @@ paces_status launch_step_graph(paces_sim* s, int64_t est, bool counted,
     (void)hipGraphExecDestroy(old->exec);
     s->graphs.erase(old);
   }
-  s->graphs.push_back({key, exec, ++s->graph_clock});
+  const paces_sim::HostFx fx{s->ipsi, s->iphi, s->warm_np, s->warm_nmass,
+                             s->swapped};
+  s->graphs.push_back({key, exec, ++s->graph_clock, fx});
   HIP_TRY(hipGraphLaunch(exec, st));
   return PACES_OK;
 }
@@ -1126,13 +1168,22 @@ paces_status qnom_select(paces_sim* s, hipStream_t st) {
   const paces_model* m = s->m;
   const int R = m->R;
   ST_TRY(cap_buffers(s));
-  s->nM_full = s->nS;
-  iota_u32(s->midx_full, s->nS, st);
+  // every live row of the set
+  const Side& c = s->side[s->cur];
+  s->nM_full = s->nlive;
+  if (s->has_holes) {
+    rows_at_distance(m->Wi, c.keys, c.dist, s->nS, -1, nullptr, s->midx_full,
+                     s->dcount, s->scan_tmp, s->err, st);
+    s->counts_valid = false;
+  } else {
+    iota_u32(s->midx_full, s->nS, st);
+  }
   std::vector<uint32_t> cnt(R, 0);
   if (R == 1) {
-    cnt[0] = uint32_t(s->nS);
+    cnt[0] = uint32_t(s->nlive);
   } else {
-    count_per_real(m->dm, s->side[s->cur].pay, s->nS, s->ball, st);
+    count_per_real(m->dm, c.pay, s->nM_full, s->ball, st,
+                   s->has_holes ? s->midx_full : nullptr);
     HIP_TRY(hipMemcpyAsync(cnt.data(), s->ball, size_t(R) * 4,
                            hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1288,6 +1339,8 @@ paces_status prepare_step(paces_sim* s, hipStream_t st, bool frozen,
       s->tune.warm && s->graph_ok && !s->fresh && !frozen &&
       s->cap <= kWarmMaxRows &&
       (uint64_t(est + s->tomb) << s->tune.table_shift) <= s->tmask + 1;
+  s->nside = s->warm_step ? s->cur : 1 - s->cur;
+  s->swapped = false;
   // else probe only as much of the table as the step needs (load factor at
   // most 2^-table_shift for a new set up to the estimate); the table clear
   // costs with it
@@ -1334,8 +1387,11 @@ void finish_step(paces_sim* s, const FrozenStep* fz) {
   s->graph_ok = true;
   s->h = c;
   s->nS = c.n_new;
-  s->cur = 1 - s->cur;
+  s->nlive = s->warm_step ? int64_t(c.n_live) : int64_t(c.n_new);
+  s->has_holes = s->nlive < s->nS;
+  s->cur = s->nside;
   std::swap(s->ipsi, s->ib0);
+  s->swapped = false;
   s->k_last = step_order(s, fz);
   s->fresh = false;
   s->have_sets = true;
@@ -1346,24 +1402,33 @@ void finish_step(paces_sim* s, const FrozenStep* fz) {
   s->cap_active = false;
 }
 
-// A staged step in progress is dropped.  Once a warm expansion has run, the
-// table maps the unfinished step's set: the next step starts from scratch.
-void abandon_staged(paces_sim* s) {
-  if (s->staged_next > PACES_STAGE_EXPAND && s->warm_step) s->graph_ok = false;
+// A staged step in progress is dropped.  An in-place step whose expansion
+// has run cannot be: its set is already the new one while the amplitudes
+// are still phi.
+paces_status abandon_staged(paces_sim* s) {
+  if (s->staged_next > PACES_STAGE_EXPAND && s->warm_step)
+    return fail(PACES_E_STATE,
+                "a staged in-place step is half done: run its remaining "
+                "stages");
   s->staged_next = 0;
+  return PACES_OK;
 }
 
-// After a warm attempt that latched: the table back to the previous set's
-// when the attempt stopped before rewriting it, else (and for every error
-// but the state cap's) the repeated attempt expands from scratch.
-void warm_after_latch(paces_sim* s, int e, hipStream_t st) {
-  if (!s->warm_step) return;
-  if (s->h_ctl->w_moved) {
-    s->graph_ok = false;
-    return;
+// After a latched attempt of an in-place step.  Before the commit the
+// table and the rows are put back as they were, and the repeated attempt
+// expands from scratch unless the state cap asks for a cut selection.
+// Returns true when the step has committed: then only the propagation and
+// the observables can be repeated.
+bool warm_after_latch(paces_sim* s, int e, hipStream_t st) {
+  if (!s->warm_step) return false;
+  if (s->h_ctl->w_moved) return true;
+  warm_unstage(s->ctl, s->side[s->cur], s->wb, s->table, s->tmask, s->nS, st);
+  if (s->swapped) {
+    std::swap(s->ipsi, s->iphi);
+    s->swapped = false;
   }
-  warm_unstage(s->table, s->tmask, st);
   if (e != kErrCap) s->graph_ok = false;
+  return false;
 }
 
 // After an attempt that latched e: make the room or the selection the
@@ -1394,13 +1459,20 @@ paces_status do_step(paces_sim* s, hipStream_t st,
   int64_t est = 0;
   ST_TRY(prepare_step(s, st, fz != nullptr, &est));
   const bool graph = s->tune.graph && !s->prof && !fz && !s->cap_active;
+  bool tail_only = false;  // an in-place step repeats its propagation
+  StepLocals tail;
   for (int attempt = 0; attempt < 40; ++attempt) {
     const bool counted = s->counts_valid && attempt == 0 && !fz &&
                          !s->cap_active;
-    if (graph && attempt == 0)
+    if (tail_only) {
+      clear_latch(s->err, st);
+      stage_propagate(s, est, st, tail);
+      stage_observe(s, est, st, nullptr, tail);
+    } else if (graph && attempt == 0) {
       ST_TRY(launch_step_graph(s, est, counted, st));
-    else
+    } else {
       enqueue_step(s, est, counted, st, fz);
+    }
     // the step's last kernel mirrored the counts and the latch into h_ctl
     // and h_err
     HIP_TRY(hipStreamSynchronize(st));
@@ -1410,9 +1482,21 @@ paces_status do_step(paces_sim* s, hipStream_t st,
       return PACES_OK;
     }
     drop_pending(s);
-    warm_after_latch(s, e, st);
+    if (warm_after_latch(s, e, st)) {
+      // committed in place: more series launches are all it can ask for
+      if (e != kErrNeedTerms) {
+        s->latched = e;
+        return check_latch_code(s, e);
+      }
+      s->launched = std::min(int(s->h_ctl->kmax) + 2, kMaxTerms);
+      tail_only = true;
+      tail.n_mass = s->warm_nmass;
+      tail.n_e = 0;
+      continue;
+    }
     ST_TRY(handle_latch(s, e, st));
     s->warm_step = s->warm_step && s->graph_ok;
+    s->nside = s->warm_step ? s->cur : 1 - s->cur;
   }
   return fail(PACES_E_CAPACITY, "step did not fit after repeated growth");
 }
@@ -1448,15 +1532,26 @@ struct Snapshot {
 
 paces_status take_snapshot(paces_sim* s, Snapshot& z, hipStream_t st) {
   const paces_model* m = s->m;
-  const int64_t n = std::max<int64_t>(s->nS, 1);
+  const int64_t n = std::max<int64_t>(s->nlive, 1);
   ST_TRY(dalloc(&z.keys, n * m->Wi));
   ST_TRY(dalloc(&z.pay, n));
   ST_TRY(dalloc(&z.tot, n));
   ST_TRY(dalloc(&z.mass_tot, m->R));
   ST_TRY(dev_alloc(&z.psi, size_t(n) * s->A));
   const Side& c = s->side[s->cur];
-  z.n = s->nS;
-  if (s->nS > 0) {
+  z.n = s->nlive;
+  if (s->has_holes && s->nlive > 0) {
+    // the live rows only, in row order
+    uint32_t* idx = nullptr;
+    ST_TRY(dalloc(&idx, s->nlive));
+    rows_at_distance(m->Wi, c.keys, c.dist, s->nS, -1, nullptr, idx,
+                     s->dcount, s->scan_tmp, s->err, st);
+    s->counts_valid = false;
+    gather_rows(m->Wi, s->A, c, s->vec[s->ipsi], idx, s->nlive, z.keys,
+                z.pay, z.tot, z.psi, st);
+    HIP_TRY(hipStreamSynchronize(st));
+    dfree(idx);
+  } else if (s->nS > 0) {
     HIP_TRY(hipMemcpyAsync(z.keys, c.keys, size_t(s->nS) * m->Wi * 8,
                            hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(z.pay, c.pay, size_t(s->nS) * 8,
@@ -1470,6 +1565,8 @@ paces_status take_snapshot(paces_sim* s, Snapshot& z, hipStream_t st) {
                          hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
   z.h = s->h;
+  z.h.n_old = uint32_t(z.n);  // the compact rows are the set a step starts from
+  z.h.n_new = uint32_t(z.n);
   z.fresh = s->fresh;
   z.launched = s->launched;
   z.K_last = s->K_last;
@@ -1491,11 +1588,14 @@ paces_status restore_snapshot(paces_sim* s, const Snapshot& z,
                            hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(s->vec[s->ipsi], z.psi, size_t(z.n) * s->A,
                            hipMemcpyDeviceToDevice, st));
+    dist_fill(c.dist, z.n, 0, st);
   }
   HIP_TRY(hipMemcpyAsync(s->mass_tot, z.mass_tot, size_t(m->R) * 8,
                          hipMemcpyDeviceToDevice, st));
   s->h = z.h;
   s->nS = z.n;
+  s->nlive = z.n;
+  s->has_holes = false;
   s->fresh = z.fresh;
   s->launched = z.launched;
   s->K_last = z.K_last;
@@ -1618,7 +1718,7 @@ paces_status adj_keep_m(paces_sim* s, int64_t nM, hipStream_t st) {
     const Side& c = s->side[s->cur];
     uint32_t got = 0;
     rows_at_distance(Wi, c.keys, c.dist, s->nS, 0, R.mkeys + R.mused * Wi,
-                     s->dcount, s->scan_tmp, s->err, st);
+                     nullptr, s->dcount, s->scan_tmp, s->err, st);
     s->counts_valid = false;
     HIP_TRY(hipMemcpyAsync(&got, s->dcount, 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1839,7 +1939,7 @@ paces_status expmv_run(const paces_model* m, int64_t n, const uint64_t* keys,
   ChebCoef* cc = reinterpret_cast<ChebCoef*>(work + L.cc);
   double* part = reinterpret_cast<double*>(work + L.part);
   uint64_t* table = reinterpret_cast<uint64_t*>(work + L.table);
-  Side sd;
+  Side sd{};
   sd.keys = const_cast<uint64_t*>(keys);
   if (m->Wi != m->W) {
     sd.keys = reinterpret_cast<uint64_t*>(work + L.keys);
@@ -1898,6 +1998,63 @@ paces_status static_work(void** out) {
   }
   *out = g_static_work[dev];
   return PACES_OK;
+}
+
+// The live rows of side cur in row order (holes left out): canonical keys
+// and realizations, and an amplitude vector (psi or phi) widened to FP64
+// interleaved.  Synchronises.
+paces_status export_rows(paces_sim* s, const void* vec, uint64_t* keys,
+                         double* amps, int32_t* real, hipStream_t st) {
+  const paces_model* m = s->m;
+  const Side& c = s->side[s->cur];
+  const int64_t n = s->nlive;
+  uint32_t* idx = nullptr;
+  uint64_t* gk = nullptr;
+  uint8_t* ga = nullptr;
+  double* tmp = nullptr;
+  paces_status r = PACES_OK;
+  const uint64_t* ksrc = c.keys;
+  const void* asrc = vec;
+  if (s->has_holes) {
+    r = dalloc(&idx, n);
+    if (!r) r = dalloc(&gk, n * m->Wi);
+    if (!r) r = dev_alloc(reinterpret_cast<void**>(&ga), size_t(n) * s->A);
+    if (!r) {
+      rows_at_distance(m->Wi, c.keys, c.dist, s->nS, -1, nullptr, idx,
+                       s->dcount, s->scan_tmp, s->err, st);
+      s->counts_valid = false;
+      gather_rows(m->Wi, s->A, c, vec, idx, n, gk, nullptr, nullptr, ga, st);
+      ksrc = gk;
+      asrc = ga;
+    }
+  }
+  if (!r && (keys || real)) {
+    std::vector<uint64_t> ik(size_t(n) * m->Wi), ck;
+    if (hipMemcpyAsync(ik.data(), ksrc, ik.size() * 8, hipMemcpyDeviceToHost,
+                       st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      r = fail(PACES_E_HIP, "copy failed");
+    } else {
+      if (!keys) ck.resize(size_t(n) * m->W);
+      to_canonical(m, n, ik.data(), keys ? keys : ck.data(), real);
+    }
+  }
+  if (!r && amps) {
+    r = dalloc(&tmp, 2 * n);
+    if (!r) {
+      amps_to_f64(s->prec, asrc, tmp, n, st);
+      if (hipMemcpyAsync(amps, tmp, size_t(n) * 16, hipMemcpyDeviceToHost,
+                         st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        r = fail(PACES_E_HIP, "copy failed");
+    }
+  }
+  (void)hipStreamSynchronize(st);
+  dfree(tmp);
+  dfree(idx);
+  dfree(gk);
+  if (ga) dev_free(ga);
+  return r;
 }
 
 paces_status expmv_args(const paces_model* m, int64_t n, const void* keys,
@@ -2319,7 +2476,7 @@ paces_status paces_step(paces_sim* s, int64_t n_steps, void* hip_stream) {
   if (s->latched) return fail(PACES_E_STATE, "sim is in an error state");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const char* log = std::getenv("PACES_LOG");
-  abandon_staged(s);
+  ST_TRY(abandon_staged(s));
   for (int64_t i = 0; i < n_steps; ++i) {
     paces_status r = do_step(s, st);
     if (r != PACES_OK) {
@@ -2347,7 +2504,7 @@ paces_status paces_run_stage(paces_sim* s, int32_t stage, void* hip_stream) {
   L.n_e = s->staged_e;
   switch (stage) {
     case PACES_STAGE_SELECT: {
-      abandon_staged(s);
+      ST_TRY(abandon_staged(s));
       ST_TRY(prepare_step(s, st, false, &s->staged_est));
       stage_select(s, false, st, nullptr);
       break;
@@ -2367,13 +2524,18 @@ paces_status paces_run_stage(paces_sim* s, int32_t stage, void* hip_stream) {
           s->staged_next = 0;
           return check_latch_code(s, e);
         }
-        warm_after_latch(s, e, st);
+        if (warm_after_latch(s, e, st)) {
+          s->staged_next = 0;
+          s->latched = e;
+          return check_latch_code(s, e);
+        }
         paces_status h = handle_latch(s, e, st);
         if (h) {
           s->staged_next = 0;
           return h;
         }
         s->warm_step = s->warm_step && s->graph_ok;
+        s->nside = s->warm_step ? s->cur : 1 - s->cur;
       }
       break;
     }
@@ -2428,7 +2590,7 @@ paces_status paces_observe(paces_sim* s, int32_t realization, paces_obs* out,
   std::memset(out, 0, sizeof(*out));
   if (s->h.nrec == 0) {
     out->t = s->h.t;
-    out->n_S = s->nS;
+    out->n_S = s->nlive;
     std::fill(s->pop_host.begin(), s->pop_host.end(), 0.0);
     out->pop = s->pop_host.data();
     return PACES_OK;
@@ -2480,26 +2642,9 @@ paces_status paces_get_state(paces_sim* s, int64_t* n, uint64_t* keys,
   if (!s || !n) return fail(PACES_E_ARG, "bad arguments");
   if (s->latched) return fail(PACES_E_STATE, "sim is in an error state");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  *n = s->nS;
-  const paces_model* m = s->m;
-  if ((keys || real) && s->nS > 0) {
-    std::vector<uint64_t> ik(size_t(s->nS) * m->Wi), ck;
-    HIP_TRY(hipMemcpyAsync(ik.data(), s->side[s->cur].keys, ik.size() * 8,
-                           hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    if (!keys) ck.resize(size_t(s->nS) * m->W);
-    to_canonical(m, s->nS, ik.data(), keys ? keys : ck.data(), real);
-  }
-  if (amps && s->nS > 0) {
-    double* tmp = nullptr;
-    ST_TRY(dalloc(&tmp, 2 * s->nS));
-    amps_to_f64(s->prec, s->vec[s->ipsi], tmp, s->nS, st);
-    HIP_TRY(hipMemcpyAsync(amps, tmp, size_t(s->nS) * 16, hipMemcpyDeviceToHost,
-                           st));
-    HIP_TRY(hipStreamSynchronize(st));
-    dfree(tmp);
-  }
-  return PACES_OK;
+  *n = s->nlive;
+  if ((!keys && !real && !amps) || s->nlive == 0) return PACES_OK;
+  return export_rows(s, s->vec[s->ipsi], keys, amps, real, st);
 }
 
 paces_status paces_set_state(paces_sim* s, int64_t n, const uint64_t* keys,
@@ -2554,14 +2699,17 @@ paces_status paces_get_set(paces_sim* s, int32_t which, int32_t round,
   const paces_model* m = s->m;
   const Side& c = s->side[s->cur];
   uint64_t* gathered = nullptr;
-  if (s->last_warm && which != PACES_SET_S && s->nS > 0) {
+  const bool spread =
+      which == PACES_SET_S ? s->has_holes : (s->last_warm || s->has_holes);
+  if (spread && s->nS > 0) {
     // a step from the previous graph leaves M and the frontiers spread over
-    // the set: gather the rows at that distance
-    const int d = which == PACES_SET_M ? 0 : round;
+    // the row range, and holes in it: gather the rows at that distance (every
+    // live row for S)
+    const int d = which == PACES_SET_S ? -1 : which == PACES_SET_M ? 0 : round;
     uint32_t got = 0;
     ST_TRY(dalloc(&gathered, s->nS * m->Wi));
-    rows_at_distance(m->Wi, c.keys, c.dist, s->nS, d, gathered, s->dcount,
-                     s->scan_tmp, s->err, st);
+    rows_at_distance(m->Wi, c.keys, c.dist, s->nS, d, gathered, nullptr,
+                     s->dcount, s->scan_tmp, s->err, st);
     s->counts_valid = false;
     if (hipMemcpyAsync(&got, s->dcount, 4, hipMemcpyDeviceToHost, st) !=
             hipSuccess ||
@@ -2594,15 +2742,8 @@ paces_status paces_get_phi(paces_sim* s, double* amps, void* hip_stream) {
   if (!s->have_sets)
     return fail(PACES_E_STATE, "no step has run since the state was set");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  if (s->nS == 0) return PACES_OK;
-  double* tmp = nullptr;
-  ST_TRY(dalloc(&tmp, 2 * s->nS));
-  amps_to_f64(s->prec, s->vec[s->iphi], tmp, s->nS, st);
-  HIP_TRY(hipMemcpyAsync(amps, tmp, size_t(s->nS) * 16, hipMemcpyDeviceToHost,
-                         st));
-  HIP_TRY(hipStreamSynchronize(st));
-  dfree(tmp);
-  return PACES_OK;
+  if (s->nlive == 0) return PACES_OK;
+  return export_rows(s, s->vec[s->iphi], nullptr, amps, nullptr, st);
 }
 
 paces_status paces_profile_enable(paces_sim* s, int32_t on) {
@@ -2755,7 +2896,7 @@ paces_status paces_adjoint_forward(paces_sim* s, int64_t n_steps,
     AdjStep& a = R.steps[i];
     a.nM = s->h.nM;
     a.k = s->k_last;
-    a.n_new = s->nS;
+    a.n_new = s->nlive;
     a.K = s->K_last;
     a.moff = R.mused;
     e = adj_keep_m(s, a.nM, st);

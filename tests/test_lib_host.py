@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(lib, name), name
     assert sorted(P.EXPORTS) == declared
-    assert lib.paces_abi_version() == 11
+    assert lib.paces_abi_version() == 12
 
 
 @pytest.mark.parametrize("name", ["ring4", "ring16", "sq6x6", "cube4", "ring12"])
