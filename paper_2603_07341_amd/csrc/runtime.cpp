@@ -318,6 +318,9 @@ struct paces_sim {
   bool swapped = false;    // the in-place step made psi its phi (ipsi and
                            // iphi exchanged at its transfer)
   int64_t tomb = 0;        // tombstones in the table since it was built
+  int64_t warm_off_cap = -1;  // row capacity at which an in-place step ran
+                              // out of rows (none from the previous graph
+                              // until the capacity changes)
   int warm_np = 0;         // partial blocks of the dropped weight
   int warm_nmass = 0;      // the step's folded weight partials
   int64_t nlive = 0;       // live rows of side cur; nS is its row range
@@ -659,7 +662,7 @@ paces_status grow(paces_sim* s, int64_t new_cap, int64_t min_cap,
     if (s->has_holes) {
       uint32_t* idx = reinterpret_cast<uint32_t*>(park + kb + 16 * size_t(n) + ab);
       rows_at_distance(m->Wi, o.keys, o.dist, s->nS, -1, nullptr, idx,
-                       s->dcount, s->scan_tmp, s->err, st);
+                       s->dcount, s->scan_tmp, st);
       gather_rows(m->Wi, s->A, o, s->vec[s->ipsi], idx, n,
                   reinterpret_cast<uint64_t*>(park),
                   reinterpret_cast<uint64_t*>(park + kb),
@@ -716,6 +719,15 @@ paces_status grow(paces_sim* s, int64_t new_cap, int64_t min_cap,
     dist_fill(c.dist, n, 0, st);
     HIP_TRY(hipStreamSynchronize(st));
     dev_free(park);
+  }
+  if (n != s->nS) {
+    // holes were left out: the device's row count of the set (read by the
+    // selection and the transfer of the step being repeated) follows
+    const uint32_t n32 = uint32_t(n);
+    HIP_TRY(hipMemcpyAsync(&s->ctl->n_old, &n32, 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    s->h.n_old = n32;
+    s->h.n_new = n32;
   }
   s->nS = n;
   s->has_holes = false;
@@ -1173,7 +1185,7 @@ paces_status qnom_select(paces_sim* s, hipStream_t st) {
   s->nM_full = s->nlive;
   if (s->has_holes) {
     rows_at_distance(m->Wi, c.keys, c.dist, s->nS, -1, nullptr, s->midx_full,
-                     s->dcount, s->scan_tmp, s->err, st);
+                     s->dcount, s->scan_tmp, st);
     s->counts_valid = false;
   } else {
     iota_u32(s->midx_full, s->nS, st);
@@ -1316,6 +1328,16 @@ paces_status topq_cut(paces_sim* s, hipStream_t st) {
   return PACES_OK;
 }
 
+// An expansion from scratch probes only as much of the table as the step
+// needs (load factor at most 2^-table_shift for a new set up to the
+// estimate); the table clear costs with it.
+void cold_table_mask(paces_sim* s, int64_t est) {
+  uint64_t P = 1024;
+  while (P < (uint64_t(est) << s->tune.table_shift) && P <= s->tmask_alloc)
+    P <<= 1;
+  s->tmask = std::min<uint64_t>(P - 1, s->tmask_alloc);
+}
+
 // Host preparation of a step: room for the new set, the record ring, the
 // launch estimate and the part of the table the step probes, and the
 // fixed-size truncation's selection.  Returns the estimate.
@@ -1337,19 +1359,11 @@ paces_status prepare_step(paces_sim* s, hipStream_t st, bool frozen,
   // set up to the estimate at load factor 2^-table_shift
   s->warm_step =
       s->tune.warm && s->graph_ok && !s->fresh && !frozen &&
-      s->cap <= kWarmMaxRows &&
+      s->cap <= kWarmMaxRows && s->cap != s->warm_off_cap &&
       (uint64_t(est + s->tomb) << s->tune.table_shift) <= s->tmask + 1;
   s->nside = s->warm_step ? s->cur : 1 - s->cur;
   s->swapped = false;
-  // else probe only as much of the table as the step needs (load factor at
-  // most 2^-table_shift for a new set up to the estimate); the table clear
-  // costs with it
-  if (!s->warm_step) {
-    uint64_t P = 1024;
-    while (P < (uint64_t(est) << s->tune.table_shift) && P <= s->tmask_alloc)
-      P <<= 1;
-    s->tmask = std::min<uint64_t>(P - 1, s->tmask_alloc);
-  }
+  if (!s->warm_step) cold_table_mask(s, est);
   s->cap_active = false;
   if (s->p.q_nom > 0 && !s->fresh && !frozen) ST_TRY(qnom_select(s, st));
   *est_out = est;
@@ -1482,6 +1496,7 @@ paces_status do_step(paces_sim* s, hipStream_t st,
       return PACES_OK;
     }
     drop_pending(s);
+    const bool was_warm = s->warm_step;
     if (warm_after_latch(s, e, st)) {
       // committed in place: more series launches are all it can ask for
       if (e != kErrNeedTerms) {
@@ -1494,8 +1509,23 @@ paces_status do_step(paces_sim* s, hipStream_t st,
       tail.n_e = 0;
       continue;
     }
+    if (was_warm && e == kErrCapacity) {
+      // in place the old rows hold their places until the commit, so the
+      // new set needs more rows than from scratch (where only the new set
+      // is written): repeat from scratch before growing, and stay there
+      // while the capacity is this one (a state cap that cuts every step
+      // would overflow it every time)
+      s->warm_off_cap = s->cap;
+      s->warm_step = false;
+      s->nside = 1 - s->cur;
+      cold_table_mask(s, est);
+      continue;
+    }
     ST_TRY(handle_latch(s, e, st));
-    s->warm_step = s->warm_step && s->graph_ok;
+    if (s->warm_step && !s->graph_ok) {
+      s->warm_step = false;
+      cold_table_mask(s, est);
+    }
     s->nside = s->warm_step ? s->cur : 1 - s->cur;
   }
   return fail(PACES_E_CAPACITY, "step did not fit after repeated growth");
@@ -1545,7 +1575,7 @@ paces_status take_snapshot(paces_sim* s, Snapshot& z, hipStream_t st) {
     uint32_t* idx = nullptr;
     ST_TRY(dalloc(&idx, s->nlive));
     rows_at_distance(m->Wi, c.keys, c.dist, s->nS, -1, nullptr, idx,
-                     s->dcount, s->scan_tmp, s->err, st);
+                     s->dcount, s->scan_tmp, st);
     s->counts_valid = false;
     gather_rows(m->Wi, s->A, c, s->vec[s->ipsi], idx, s->nlive, z.keys,
                 z.pay, z.tot, z.psi, st);
@@ -1718,7 +1748,7 @@ paces_status adj_keep_m(paces_sim* s, int64_t nM, hipStream_t st) {
     const Side& c = s->side[s->cur];
     uint32_t got = 0;
     rows_at_distance(Wi, c.keys, c.dist, s->nS, 0, R.mkeys + R.mused * Wi,
-                     nullptr, s->dcount, s->scan_tmp, s->err, st);
+                     nullptr, s->dcount, s->scan_tmp, st);
     s->counts_valid = false;
     HIP_TRY(hipMemcpyAsync(&got, s->dcount, 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -2021,7 +2051,7 @@ paces_status export_rows(paces_sim* s, const void* vec, uint64_t* keys,
     if (!r) r = dev_alloc(reinterpret_cast<void**>(&ga), size_t(n) * s->A);
     if (!r) {
       rows_at_distance(m->Wi, c.keys, c.dist, s->nS, -1, nullptr, idx,
-                       s->dcount, s->scan_tmp, s->err, st);
+                       s->dcount, s->scan_tmp, st);
       s->counts_valid = false;
       gather_rows(m->Wi, s->A, c, vec, idx, n, gk, nullptr, nullptr, ga, st);
       ksrc = gk;
@@ -2524,17 +2554,29 @@ paces_status paces_run_stage(paces_sim* s, int32_t stage, void* hip_stream) {
           s->staged_next = 0;
           return check_latch_code(s, e);
         }
+        const bool was_warm = s->warm_step;
         if (warm_after_latch(s, e, st)) {
           s->staged_next = 0;
           s->latched = e;
           return check_latch_code(s, e);
+        }
+        if (was_warm && e == kErrCapacity) {
+          // as in paces_step: from scratch before growing
+          s->warm_off_cap = s->cap;
+          s->warm_step = false;
+          s->nside = 1 - s->cur;
+          cold_table_mask(s, s->staged_est);
+          continue;
         }
         paces_status h = handle_latch(s, e, st);
         if (h) {
           s->staged_next = 0;
           return h;
         }
-        s->warm_step = s->warm_step && s->graph_ok;
+        if (s->warm_step && !s->graph_ok) {
+          s->warm_step = false;
+          cold_table_mask(s, s->staged_est);
+        }
         s->nside = s->warm_step ? s->cur : 1 - s->cur;
       }
       break;
@@ -2709,7 +2751,7 @@ paces_status paces_get_set(paces_sim* s, int32_t which, int32_t round,
     uint32_t got = 0;
     ST_TRY(dalloc(&gathered, s->nS * m->Wi));
     rows_at_distance(m->Wi, c.keys, c.dist, s->nS, d, gathered, nullptr,
-                     s->dcount, s->scan_tmp, s->err, st);
+                     s->dcount, s->scan_tmp, st);
     s->counts_valid = false;
     if (hipMemcpyAsync(&got, s->dcount, 4, hipMemcpyDeviceToHost, st) !=
             hipSuccess ||

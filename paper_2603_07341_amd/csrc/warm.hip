@@ -747,18 +747,22 @@ void dist_fill(uint8_t* dist, int64_t n, uint8_t v, hipStream_t s) {
 
 void rows_at_distance(int Wi, const uint64_t* keys, const uint8_t* dist,
                       int64_t n, int d, uint64_t* out, uint32_t* rows,
-                      uint32_t* count, uint32_t* tmp, int* err, hipStream_t s) {
+                      uint32_t* count, uint32_t* tmp, hipStream_t s) {
   if (n <= 0) {
     k_u32_set<<<1, 1, 0, s>>>(count, 0);
     return;
   }
   const int g = tiles_for(n);
   // the kernels read the row count from device memory: the last word of
-  // tmp, past the tile sums
+  // tmp, past the tile sums; the word before it is a clear latch for the
+  // scan, which skips its work when its latch is set (the sim's own may
+  // hold the error of a step that is being repeated)
   uint32_t* nrows = tmp + scan_tmp_words(n) - 1;
+  int* clear = reinterpret_cast<int*>(tmp + scan_tmp_words(n) - 2);
   k_u32_set<<<1, 1, 0, s>>>(nrows, n);
+  k_u32_set<<<1, 1, 0, s>>>(reinterpret_cast<uint32_t*>(clear), 0);
   k_dist_count<<<g, kBlock, 0, s>>>(dist, nrows, d, tmp);
-  tile_sums_scan(tmp, nrows, count, err, s);
+  tile_sums_scan(tmp, nrows, count, clear, s);
   k_dist_write<<<g, kBlock, 0, s>>>(Wi, keys, dist, nrows, d, tmp, out, rows);
 }
 

@@ -101,10 +101,10 @@ void dist_fill(uint8_t* dist, int64_t n, uint8_t v, hipStream_t s);
 // Keys of the rows [0, n) whose distance is d (d < 0: every live row), in
 // row order, into out (Wi words each; null: none); their rows into rows
 // (may be null); their count into *count (device).  tmp: scan space of
-// scan_tmp_words(n) words; err: the sim's latch (clear).
+// scan_tmp_words(n) words.  Works whatever the sim's latch holds.
 void rows_at_distance(int Wi, const uint64_t* keys, const uint8_t* dist,
                       int64_t n, int d, uint64_t* out, uint32_t* rows,
-                      uint32_t* count, uint32_t* tmp, int* err, hipStream_t s);
+                      uint32_t* count, uint32_t* tmp, hipStream_t s);
 // Gather rows idx[0, n) of a set (keys, payload, totals and the amplitude,
 // A bytes each) into dense arrays (any output may be null).
 void gather_rows(int Wi, size_t A, const Side& c, const void* psi,

@@ -41,9 +41,9 @@ MID = "k_cheb_term<double, 1, 1, true>"
 GIB = float(1 << 30)
 
 # first kernel of each stage of a step, in dispatch order (a step from the
-# previous graph starts its expansion with k_warm_old and moves the rows
-# and phi there: its transfer stage is only the fold of the dropped weight,
-# counted with the expansion)
+# previous graph starts its expansion with k_warm_old and turns psi into
+# phi in place there: its transfer stage is only the fold of the dropped
+# weight, counted with the expansion)
 STAGE_START = [("k_begin_step", "select"), ("k_fill_u64", "expand+build"),
                ("k_warm_old", "expand+build"),
                ("k_transfer", "transfer"), ("k_bounds", "build"),

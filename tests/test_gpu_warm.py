@@ -121,3 +121,23 @@ def test_warm_steps_across_a_growth_and_a_state_reload():
     assert np.array_equal(aw, ac)
     rw, rc = warm.series(), cold.series()
     assert np.array_equal(rw[..., EXACT], rc[..., EXACT])
+
+
+def test_warm_steps_under_a_state_cap_that_binds_every_step():
+    """Under a state cap that cuts nearly every step, an in-place step can
+    need more rows than the capacity (the old rows keep their places until
+    the commit) where a step from scratch fits: that step repeats from
+    scratch instead of growing the row arrays step after step.  The run
+    stays equal to the one from scratch throughout."""
+    warm, cold = pair("ring16", 1, dict(precision=32, max_states=200000,
+                                        cap_hint=250000))
+    for i in range(300):
+        warm.step(1)
+        cold.step(1)
+        rw, rc = warm.series(i, 1), cold.series(i, 1)
+        assert np.array_equal(rw[..., EXACT], rc[..., EXACT]), i
+        assert rw[0, 7] <= 200000, i
+    kw, aw = full_state(warm)
+    kc, ac = full_state(cold)
+    assert np.array_equal(kw, kc)
+    assert np.array_equal(aw, ac)
