@@ -1212,8 +1212,10 @@ paces_status qnom_select(paces_sim* s, hipStream_t st) {
 // ascending, key ascending) with q = floor(cap |M_prev| / |S_prev|) from
 // the last record (floor(cap / (D+1)) without one), and on every further
 // overflow q <- floor(9 min(q, |M|) cap / (10 |ball|)); the full selection
-// of the step is kept for the repeated cuts.
-paces_status cap_select(paces_sim* s, hipStream_t st) {
+// of the step is kept for the repeated cuts.  over: the ball outgrew the
+// row capacity before it was counted (first cut of one realization only,
+// whose q needs no ball count).
+paces_status cap_select(paces_sim* s, hipStream_t st, bool over) {
   const paces_model* m = s->m;
   const int R = m->R;
   const int64_t cap = s->p.max_states;
@@ -1223,6 +1225,8 @@ paces_status cap_select(paces_sim* s, hipStream_t st) {
   HIP_TRY(hipMemcpyAsync(cnt.data(), s->cnt, size_t(R) * 4,
                          hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  // the ball outgrew the rows: it was not counted, but it is over the cap
+  if (over) std::fill(ball.begin(), ball.end(), ~0u);
   if (!s->cap_active) {
     ST_TRY(cap_buffers(s));
     s->nM_full = s->h_ctl->nM;
@@ -1347,10 +1351,21 @@ paces_status prepare_step(paces_sim* s, hipStream_t st, bool frozen,
   // the factor used here in the workloads; an overflow is caught anyway.
   // Growth to 4 |S| makes the next one due only when the set has doubled.
   // A capacity cut to fit the device grows again only when the step's
-  // estimate no longer fits it.
-  const int64_t need = s->nS + std::max<int64_t>(s->nS / 2, 65536);
-  if (s->nS > s->cap / 2 && (!s->mem_capped || need > s->cap))
-    ST_TRY(grow(s, 4 * s->nS, need, st));
+  // estimate no longer fits it.  Under a state cap no set holds more than
+  // R * max_states rows: that plus an eighth (holes of in-place steps) is
+  // all the capacity such a run grows to; a ball beyond it is cut (or, for
+  // several realizations, grows the rows when it is met).
+  int64_t need = s->nS + std::max<int64_t>(s->nS / 2, 65536);
+  int64_t want = 4 * s->nS;
+  if (s->p.max_states > 0) {
+    const int64_t top = int64_t(s->m->R) * s->p.max_states;
+    const int64_t lim = top + std::max<int64_t>(top / 8, 65536);
+    need = std::min(need, lim);
+    want = std::min(want, lim);
+  }
+  if (s->nS > s->cap / 2 && s->cap < want &&
+      (!s->mem_capped || need > s->cap))
+    ST_TRY(grow(s, want, need, st));
   ST_TRY(ensure_ring(s, st));
   const int64_t est = std::min<int64_t>(
       s->cap, bucket(std::max<int64_t>(s->nS + s->nS / 2, s->nS + 65536)));
@@ -1445,10 +1460,20 @@ bool warm_after_latch(paces_sim* s, int e, hipStream_t st) {
   return false;
 }
 
+// An attempt from scratch that ran out of rows under the state cap of one
+// realization, before any cut: the capacity holds the cap, so the ball is
+// over it, and the first cut (q from the last record) needs no ball count.
+// The step is cut instead of growing the rows for a ball it will not keep.
+bool overflow_over_cap(const paces_sim* s, int e, bool was_warm,
+                       const FrozenStep* fz) {
+  return e == kErrCapacity && !was_warm && !fz && !s->cap_active &&
+         s->m->R == 1 && s->p.max_states > 0 && s->cap >= s->p.max_states;
+}
+
 // After an attempt that latched e: make the room or the selection the
 // repeated attempt needs, or return the error.
 paces_status handle_latch(paces_sim* s, int e, hipStream_t st) {
-  if (e == kErrCap) return cap_select(s, st);
+  if (e == kErrCap) return cap_select(s, st, false);
   if (e & (kErrTerms | kErrNonFinite)) return check_latch_code(s, e);
   if (e & kErrNeedTerms) {
     s->launched = std::min(int(s->h_ctl->kmax) + 2, kMaxTerms);
@@ -1519,6 +1544,10 @@ paces_status do_step(paces_sim* s, hipStream_t st,
       s->warm_step = false;
       s->nside = 1 - s->cur;
       cold_table_mask(s, est);
+      continue;
+    }
+    if (overflow_over_cap(s, e, was_warm, fz)) {
+      ST_TRY(cap_select(s, st, true));
       continue;
     }
     ST_TRY(handle_latch(s, e, st));
@@ -2568,7 +2597,9 @@ paces_status paces_run_stage(paces_sim* s, int32_t stage, void* hip_stream) {
           cold_table_mask(s, s->staged_est);
           continue;
         }
-        paces_status h = handle_latch(s, e, st);
+        paces_status h = overflow_over_cap(s, e, was_warm, nullptr)
+                             ? cap_select(s, st, true)
+                             : handle_latch(s, e, st);
         if (h) {
           s->staged_next = 0;
           return h;
