@@ -647,7 +647,10 @@ __device__ __forceinline__ double dbl_of(long long o) {
 }
 
 // Gershgorin interval per realization: rows stride over a fixed grid; per
-// block the (lo, hi) of each realization go to part[block][r][2].
+// block the (lo, hi) of each realization go to part[block][r][2].  DT: the
+// slot count at compile time (a row's columns in one vector load), or 0
+// for m.D at run time; the radius sums the slots in order either way.
+template <int DT>
 __global__ void __launch_bounds__(kBlock)
     k_bounds(DevModel m, const uint64_t* pay, const uint64_t* tot,
              const uint8_t* dist, const int32_t* col, int64_t cap,
@@ -666,10 +669,18 @@ __global__ void __launch_bounds__(kBlock)
   double lo = INFINITY, hi = -INFINITY;
   for (int64_t r = gtid(); r < n; r += gstride()) {
     if (is_hole(dist, r)) continue;
-    const uint64_t p = pay[r];
+    const uint64_t p = ld_stream(pay + r);
     double rad = 0;
-    for (int s = 0; s < m.D; ++s)
-      if (col[r * m.D + s] >= 0) rad += fabs(slot_value(m, p, s));
+    if constexpr (DT > 0) {
+      int32_t cs[DT];
+      load_cols<DT>(col + r * DT, cs);
+#pragma unroll
+      for (int s = 0; s < DT; ++s)
+        if (cs[s] >= 0) rad += fabs(slot_value(m, p, s));
+    } else {
+      for (int s = 0; s < m.D; ++s)
+        if (col[r * m.D + s] >= 0) rad += fabs(slot_value(m, p, s));
+    }
     const double d = row_diag(m, p, m.V > 2 ? tot[r] : 0);
     if (R > 1) {
       atomicMin(&blo[pay_real(p)], ord_of(d - rad));
@@ -1395,11 +1406,29 @@ int transfer(const DevModel& m, int Wi, int prec, const Side& o,
   return g;
 }
 
+namespace {
+void launch_bounds_kernel(const DevModel& m, const Side& n, const int32_t* col,
+                          int64_t cap, int g, const StepCtl* ctl, double* part,
+                          const int* err, hipStream_t s) {
+#define PACES_BOUNDS(DT) \
+  k_bounds<DT><<<g, kBlock, 0, s>>>(m, n.pay, n.tot, n.dist, col, cap, ctl, part, err)
+  switch (m.D) {
+    case 4: PACES_BOUNDS(4); break;
+    case 6: PACES_BOUNDS(6); break;
+    case 8: PACES_BOUNDS(8); break;
+    case 10: PACES_BOUNDS(10); break;
+    case 12: PACES_BOUNDS(12); break;
+    default: PACES_BOUNDS(0); break;
+  }
+#undef PACES_BOUNDS
+}
+}  // namespace
+
 int bounds_part(const DevModel& m, const Side& n, const int32_t* col,
                 int64_t cap, int64_t est, const StepCtl* ctl, double* part,
                 const int* err, hipStream_t s) {
   const int g = std::min(grid_for(est), kPartBlocks);
-  k_bounds<<<g, kBlock, 0, s>>>(m, n.pay, n.tot, n.dist, col, cap, ctl, part, err);
+  launch_bounds_kernel(m, n, col, cap, g, ctl, part, err, s);
   return g;
 }
 
@@ -1410,7 +1439,7 @@ void bounds_and_coef(const DevModel& m, const Side& n, const int32_t* col,
   // a bounded grid: each block reduces many rows, and k_coef folds few
   // partials
   const int g = std::min(grid_for(est), kPartBlocks);
-  k_bounds<<<g, kBlock, 0, s>>>(m, n.pay, n.tot, n.dist, col, cap, ctl, part, err);
+  launch_bounds_kernel(m, n, col, cap, g, ctl, part, err, s);
   k_coef<<<m.R, kBlock, 0, s>>>(part, g, m.R, dt, tol, k_max, launched, cc,
                                 ctl, err);
 }
