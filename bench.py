@@ -188,7 +188,11 @@ def main():
     n_term = prof["launches"]["term"]
     term_ms = prof["ms"]["term"] / max(n_term, 1)
     kern_row = 4 * A + 4 * D + (8 if model.V <= 2 else 16)
-    rows_per_launch = prof["term_bytes"] / max(n_term, 1) / kern_row
+    # the launch runs over the set's row range, which after in-place steps
+    # may hold holes of dropped states; the algorithmic bytes count the
+    # states of the set (one timed launch per step: the window's mean |S|)
+    rows_range = prof["term_bytes"] / max(n_term, 1) / kern_row
+    rows_per_launch = float(rec[:, 7].mean())
     spec_row = 5 * A + 4 * D + 12
     achieved = spec_row * rows_per_launch / (term_ms * 1e-3) / 1e9 if n_term else 0.0
     achieved_k = kern_row * rows_per_launch / (term_ms * 1e-3) / 1e9 if n_term else 0.0
@@ -227,6 +231,7 @@ def main():
                      "launches": n_term, "avg_ms": term_ms,
                      "sampling": "one middle launch per timed step",
                      "rows_per_launch": rows_per_launch,
+                     "row_range_per_launch": rows_range,
                      "bytes_per_row": spec_row,
                      "bytes_per_row_rule": "5A + 4D + 12 per row and term "
                                            "(forward recurrence with an "
@@ -238,6 +243,8 @@ def main():
         "stage_ms_per_step": stage_ms,
         "stage_ms_note": "%d further steps after the timed window, with "
                          "stage events" % args.stage_steps,
+        "row_range_over_states": float(sprof["rows_steps"]) /
+                                 max(float(srec[:, 7].sum()), 1.0),
         "stages": stage_bandwidth(model, A, sprof, srec,
                                   float(rec[-1, 7]), args.stage_steps,
                                   copy_peak_gbs(), wprof,
@@ -341,8 +348,16 @@ def paper_run(args):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     rec = sim.series(0, steps, stream)
-    if args.paper_save:
-        np.save(args.paper_save, rec)
+    # the row range the kernels run over against the states of the set
+    # (holes of in-place steps), over two further steps outside the timing
+    sim.profile(True, kernels_only=True)
+    sim.profile_reset()
+    sim.step(2, stream=stream)
+    extra = sim.series(steps, 2, stream)
+    range_over_live = sim.profile_get(stream)["rows_steps"] / float(extra[:, 7].sum())
+    sim.profile(False)
+    if args.paper_save:  # every record, the two further steps included
+        np.save(args.paper_save, sim.series(0, steps + 2, stream))
     sat = rec[:, 8] >= q
     ratio = rec[sat, 7] / rec[sat, 8]
     tail = rec[sat][-100:]  # the last 100 steps with |M| = q_nom
@@ -355,7 +370,8 @@ def paper_run(args):
                 float((tail[:, 7] / tail[:, 8]).mean()) if len(tail) else None,
             "final_norm2": float(rec[-1, 1]),
             "norm_loss": float(1.0 - rec[-1, 1]), "final_t": float(rec[-1, 0]),
-            "terms_per_step": float(rec[:, 9].mean())}
+            "terms_per_step": float(rec[:, 9].mean()),
+            "row_range_over_states_after": range_over_live}
 
 
 def cube4_run(args):

@@ -437,8 +437,13 @@ typedef struct {
                           one shortens probe chains                       */
   int32_t term_rows;   /* rows per thread of the Clenshaw grid: 1,2,4,8  */
   int32_t warm;        /* 1: a step expands from the previous step's graph
-                          (its ELL columns and hash table) where one is
-                          there; 0: every step expands from scratch      */
+                          (its ELL columns and hash table) in place where
+                          one is there, and from scratch again once the
+                          states placed into holes since the last such
+                          step reach a tenth of the set (which restores
+                          the breadth-first row order the SpMV gathers
+                          favour); 2: in place without that relayout;
+                          0: every step expands from scratch             */
 } paces_tuning;
 /* Default {0, 1, 1, 1}. */
 paces_status paces_get_tuning(paces_sim* s, paces_tuning* out);

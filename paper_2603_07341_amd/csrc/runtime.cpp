@@ -318,6 +318,8 @@ struct paces_sim {
   bool swapped = false;    // the in-place step made psi its phi (ipsi and
                            // iphi exchanged at its transfer)
   int64_t tomb = 0;        // tombstones in the table since it was built
+  int64_t scattered = 0;   // found states placed in holes since the set was
+                           // last laid out from scratch
   int64_t warm_off_cap = -1;  // row capacity at which an in-place step ran
                               // out of rows (none from the previous graph
                               // until the capacity changes)
@@ -1332,6 +1334,10 @@ paces_status topq_cut(paces_sim* s, hipStream_t st) {
   return PACES_OK;
 }
 
+// Fraction of the set placed into holes by in-place steps after which the
+// next step lays the set out from scratch (tuning warm = 1).
+constexpr double kRelayout = 0.1;
+
 // An expansion from scratch probes only as much of the table as the step
 // needs (load factor at most 2^-table_shift for a new set up to the
 // estimate); the table clear costs with it.
@@ -1372,9 +1378,16 @@ paces_status prepare_step(paces_sim* s, hipStream_t st, bool frozen,
   // expand from the previous step's graph when it is there and its table
   // (probed over the same part, tombstones included) has room for a new
   // set up to the estimate at load factor 2^-table_shift
+  // A step from scratch lays the set out in breadth-first order from M
+  // (a row's neighbours sit in the same or the next layer at a matching
+  // place); in-place steps put found states into holes wherever drops left
+  // them, which loosens that order.  Once as many states as kRelayout of
+  // the set went into holes, the next step is from scratch again.
   s->warm_step =
       s->tune.warm && s->graph_ok && !s->fresh && !frozen &&
       s->cap <= kWarmMaxRows && s->cap != s->warm_off_cap &&
+      (s->tune.warm == 2 ||
+       double(s->scattered) <= kRelayout * double(s->nlive)) &&
       (uint64_t(est + s->tomb) << s->tune.table_shift) <= s->tmask + 1;
   s->nside = s->warm_step ? s->cur : 1 - s->cur;
   s->swapped = false;
@@ -1412,6 +1425,8 @@ void finish_step(paces_sim* s, const FrozenStep* fz) {
   // the table now maps the new set (rebuilt by an expansion from scratch,
   // rewritten by one from the previous graph)
   s->tomb = s->warm_step ? s->tomb + int64_t(c.w_tomb) : 0;
+  s->scattered =
+      s->warm_step ? s->scattered + int64_t(std::min(c.n_staged, c.nfree)) : 0;
   s->last_warm = s->warm_step;
   s->graph_ok = true;
   s->h = c;
@@ -1682,7 +1697,7 @@ paces_status resize_table(paces_sim* s, hipStream_t st) {
 }
 
 paces_status check_tuning(const paces_tuning* t) {
-  if (!t || (t->graph != 0 && t->graph != 1) || (t->warm != 0 && t->warm != 1) ||
+  if (!t || (t->graph != 0 && t->graph != 1) || (t->warm < 0 || t->warm > 2) ||
       t->table_shift < 0 ||
       t->table_shift > 3 ||
       (t->term_rows != 1 && t->term_rows != 2 && t->term_rows != 4 &&

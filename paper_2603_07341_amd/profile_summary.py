@@ -271,8 +271,78 @@ def summarize(args):
     return text
 
 
+def summarize_tail(args):
+    """The last launches of one kernel in a whole run (kernel trace and the
+    two counter runs of the same command), against the states of the steps
+    they belong to (records saved by the run): time, counted bytes per
+    launch and per state, and the rate by the algorithmic bytes per state."""
+    import numpy as np
+    trace = trace_dispatches(args.trace)
+    fetch = {d["id"]: d for d in counter_dispatches(args.fetch, "FETCH_SIZE")}
+    write = {d["id"]: d for d in counter_dispatches(args.write, "WRITE_SIZE")}
+    t_k = [d for d in trace if d["name"] == args.kernel]
+    f_k = [d for d in sorted(fetch.values(), key=lambda d: d["id"])
+           if d["name"] == args.kernel]
+    w_k = [d for d in sorted(write.values(), key=lambda d: d["id"])
+           if d["name"] == args.kernel]
+    n = min(args.last, len(t_k), len(f_k), len(w_k))
+    if n == 0:
+        raise SystemExit("no launches of %s" % args.kernel)
+    us = sum(d["ns"] for d in t_k[-n:]) / n / 1e3
+    fb = sum(d["kib"] for d in f_k[-n:]) / n * 1024.0 * args.fetch_scale
+    wb = sum(d["kib"] for d in w_k[-n:]) / n * 1024.0 * args.write_scale
+    rec = np.load(args.records)
+    rows = float(rec[-args.steps:, 7].mean())
+    L = ["# %s" % args.title, "#",
+         "# commands (each its own run; cd /tmp && export TMPDIR=/tmp first):",
+         "#   rocprofv3 --kernel-trace --stats --output-format csv -d <out> -o run -- %s" % args.command,
+         "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out> -o run -- %s" % args.command,
+         "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out> -o run -- %s" % args.command,
+         "# summary: python -m paper_2603_07341_amd.profile_summary tail (this file's figures)",
+         "# counter scales: fetch x %.3f, write x %.3f (a plain 1 GiB copy on the same GPU)"
+         % (args.fetch_scale, args.write_scale),
+         "kernel_sha: %s" % source_hash(),
+         "kernel: %s" % args.kernel,
+         "launches_used: %d (the last of %d)" % (n, len(t_k)),
+         "steps_used: %d (the last of %d), mean states %.0f" % (args.steps, len(rec), rows),
+         "avg_us: %.1f" % us,
+         "counted_fetch_bytes_per_launch: %.0f" % fb,
+         "counted_write_bytes_per_launch: %.0f" % wb,
+         "counted_bytes_per_state: %.1f" % ((fb + wb) / rows),
+         "counted_rate_tbs: %.2f" % ((fb + wb) / (us * 1e-6) / 1e12),
+         "algorithmic_bytes_per_state: %d" % args.alg_bytes,
+         "algorithmic_rate_tbs: %.2f" % (args.alg_bytes * rows / (us * 1e-6) / 1e12),
+         "algorithmic_frac_of_8tbs: %.3f" % (args.alg_bytes * rows / (us * 1e-6) / 8e12),
+         "", "## whole run, top kernels by trace time",
+         "   %-44s %6s %11s %9s" % ("kernel", "calls", "total ms", "avg us")]
+    agg = per_kernel(trace, "ns")
+    for name, (c, ns) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:16]:
+        L.append("   %-44s %6d %11.1f %9.1f" % (name[:44], c, ns / 1e6, ns / c / 1e3))
+    out = "\n".join(L) + "\n"
+    with open(args.out, "w") as fh:
+        fh.write(out)
+    return out
+
+
 def main(argv=None):
     argv = sys.argv[1:] if argv is None else argv
+    if argv and argv[0] == "tail":
+        ap = argparse.ArgumentParser()
+        ap.add_argument("--trace", required=True)
+        ap.add_argument("--fetch", required=True)
+        ap.add_argument("--write", required=True)
+        ap.add_argument("--records", required=True)
+        ap.add_argument("--kernel", default=MID)
+        ap.add_argument("--last", type=int, default=40)
+        ap.add_argument("--steps", type=int, default=5)
+        ap.add_argument("--alg-bytes", type=int, default=108)
+        ap.add_argument("--fetch-scale", type=float, default=2.0)
+        ap.add_argument("--write-scale", type=float, default=1.0)
+        ap.add_argument("--command", required=True)
+        ap.add_argument("--title", required=True)
+        ap.add_argument("--out", required=True)
+        sys.stdout.write(summarize_tail(ap.parse_args(argv[1:])))
+        return
     if argv and argv[0] == "extract":
         # extract trace DIR OUT | extract FETCH_SIZE DIR OUT | extract WRITE_SIZE DIR OUT
         what, folder, out = argv[1], argv[2], argv[3]

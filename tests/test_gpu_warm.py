@@ -1,6 +1,7 @@
-"""Steps that expand from the previous step's graph (tuning warm = 1, the
-default) against steps that expand from scratch (warm = 0), through the C
-ABI.  Both compute B_k(M) and the columns of H_eff on it (Eqs.
+"""Steps that expand from the previous step's graph in place (tuning warm
+= 1, the default, which lays the set out from scratch again after a tenth
+of it went into holes, and warm = 2, in place throughout) against steps
+that expand from scratch (warm = 0), through the C ABI.  Both compute B_k(M) and the columns of H_eff on it (Eqs.
 (def_neighbor_k), (H_eff)); the rows come in another order, while every
 row's arithmetic is the same, so per step: the same set S, the same
 selection M and frontiers, every amplitude taken per basis state bit for
@@ -24,7 +25,7 @@ pytestmark = pytest.mark.gpu
 EXACT = [0, 7, 8, 9, 10, 11]  # t, n_S, n_M, K, E_min, E_max
 
 
-def pair(name, R, run_over, cfg_over=None):
+def pair(name, R, run_over, cfg_over=None, mode=1):
     cfg = dict(WL.CONFIGS[name])
     cfg.update(cfg_over or {})
     params = WL.batch_params(cfg, R) if R > 1 else WL.model_params(cfg)
@@ -34,6 +35,8 @@ def pair(name, R, run_over, cfg_over=None):
     cold = P.Sim(P.Model(params), run, *init)
     cold.set_tuning(warm=0)
     assert warm.tuning()["warm"] == 1 and cold.tuning()["warm"] == 0
+    if mode != 1:
+        warm.set_tuning(warm=mode)
     return warm, cold
 
 
@@ -67,12 +70,15 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("mode", [1, 2], ids=["relayout", "in-place"])
 @pytest.mark.parametrize("name,R,steps,run_over,cfg_over", CASES,
                          ids=["ring16", "ring16-fp32", "sq6x6-R4", "cube4",
                               "krylov", "taylor", "q_nom", "cap"])
 def test_warm_steps_equal_steps_from_scratch(name, R, steps, run_over,
-                                             cfg_over):
-    warm, cold = pair(name, R, run_over, cfg_over)
+                                             cfg_over, mode):
+    """mode 1: the default (in place, from scratch again after a tenth of
+    the set went into holes); mode 2: in place throughout."""
+    warm, cold = pair(name, R, run_over, cfg_over, mode)
     k = WL.CONFIGS[name]["k"]
     krylov = "krylov_order" in run_over
     exact = EXACT[:4] if krylov else EXACT
@@ -130,7 +136,7 @@ def test_warm_steps_under_a_state_cap_that_binds_every_step():
     scratch instead of growing the row arrays step after step.  The run
     stays equal to the one from scratch throughout."""
     warm, cold = pair("ring16", 1, dict(precision=32, max_states=200000,
-                                        cap_hint=250000))
+                                        cap_hint=250000), mode=2)
     for i in range(300):
         warm.step(1)
         cold.step(1)
