@@ -989,6 +989,7 @@ __global__ void __launch_bounds__(kBlock)
 // four waves of a block meet on an address at most four at a time; other
 // shapes share one bin per (realization, site).
 constexpr int kPrivBins = 120;  // N * 64 + 3 doubles fit in 64 KiB
+constexpr int kRegBins = 16;
 
 // Norm, exciton populations, row counts and (batched) energy of psi per
 // realization as per-block partials.  Rows are visited in the select
@@ -1006,6 +1007,12 @@ __global__ void __launch_bounds__(kBlock)
   if (*err) return;
   const int64_t n = ctl->n_new, ntiles = cdiv(n, kTile);
   const bool priv = Rn == 1 && N <= kPrivBins;
+  // up to kRegBins sites: each thread sums its rows' weights per site in
+  // registers and adds them to its lane's LDS bins once at the end
+  const bool regs = priv && N <= kRegBins;
+  double acc[kRegBins];
+#pragma unroll
+  for (int q = 0; q < kRegBins; ++q) acc[q] = 0.0;
   const int npop = priv ? N * 64 : Rn * N;
   double* pop_lds = lds;
   double* n2_lds = lds + npop;          // Rn (batched only)
@@ -1032,10 +1039,15 @@ __global__ void __launch_bounds__(kBlock)
         if (Rn == 1) {
           n2 += w;
           ++rows;
-          if (priv)
+          if (regs) {
+            const int j = pay_site(p);
+#pragma unroll
+            for (int q = 0; q < kRegBins; ++q) acc[q] += q == j ? w : 0.0;
+          } else if (priv) {
             atomicAdd(&pop_lds[pay_site(p) * 64 + (threadIdx.x & 63)], w);
-          else
+          } else {
             atomicAdd(&pop_lds[pay_site(p)], w);
+          }
         } else {
           const int r = pay_real(p);
           atomicAdd(&n2_lds[r], w);
@@ -1048,6 +1060,11 @@ __global__ void __launch_bounds__(kBlock)
     uint32_t tot;
     block_excl_scan(keep, &tot);
     if (threadIdx.x == 0) sel_bsum[t] = tot;
+  }
+  if (regs) {
+#pragma unroll
+    for (int q = 0; q < kRegBins; ++q)
+      if (q < N) atomicAdd(&pop_lds[q * 64 + (threadIdx.x & 63)], acc[q]);
   }
   if (Rn == 1) {
     n2 = block_sum(n2);

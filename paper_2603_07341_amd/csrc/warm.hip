@@ -447,7 +447,9 @@ __global__ void k_warm_range(StepCtl* ctl, int R, uint32_t* ball,
 }
 
 // Live rows of the new set, in total and per realization (counted only
-// when per_real).
+// when per_real).  A thread reads the distances of 16 rows at once (the
+// array's allocation is a multiple of 256 bytes, so the last group stays
+// inside it).
 __global__ void __launch_bounds__(kBlock)
     k_warm_live(DevModel m, int k, StepCtl* ctl, const uint8_t* dist,
                 const uint64_t* pay, int per_real, uint32_t* ball,
@@ -458,12 +460,19 @@ __global__ void __launch_bounds__(kBlock)
     for (int r = threadIdx.x; r < m.R; r += blockDim.x) bins[r] = 0;
     __syncthreads();
   }
-  const int64_t n = ctl->n_new;
+  const int64_t n = ctl->n_new, n16 = cdiv(n, 16);
+  const uint4* d16 = reinterpret_cast<const uint4*>(dist);
   uint32_t live = 0;
-  for (int64_t e = gtid(); e < n; e += gstride()) {
-    if (!kept(dist[e], k)) continue;
-    ++live;
-    if (per_real) atomicAdd(&bins[pay_real(pay[e])], 1u);
+  for (int64_t g = gtid(); g < n16; g += gstride()) {
+    const uint4 v = d16[g];
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int64_t e = g * 16 + q;
+      if (e >= n || !kept(uint8_t(w[q >> 2] >> (8 * (q & 3))), k)) continue;
+      ++live;
+      if (per_real) atomicAdd(&bins[pay_real(pay[e])], 1u);
+    }
   }
   uint32_t tot;
   block_excl_scan(live, &tot);
