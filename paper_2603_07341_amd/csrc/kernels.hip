@@ -1511,7 +1511,9 @@ int pop_norm(int prec, int N, int R, double th2, int64_t est,
   const bool priv = R == 1 && N <= kPrivBins;
   const size_t lds = sizeof(double) * ((priv ? N * 64 : R * N) + 3 * R);
   // batched partials hold R * N populations per block: fewer blocks
-  const int g = R > 1 ? std::min(tiles_for(est), 1024) : tiles_for(est);
+  // a bounded grid: blocks stride over the tiles, so the per-block work
+  // (bins cleared and folded, one count added to the total) is amortised
+  const int g = std::min(tiles_for(est), 1024);
   if (prec == 64)
     k_pop_norm<double><<<g, kBlock, lds, s>>>(
         N, R, th2, ctl, (const double2*)psi, pay, dist, e_row, n2_part, en_part,

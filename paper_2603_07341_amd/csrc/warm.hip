@@ -709,7 +709,8 @@ void warm_sizes(const DevModel& m, const Side& c, int k, StepCtl* ctl,
                 hipStream_t s) {
   k_warm_range<<<1, 1, 0, s>>>(ctl, m.R, ball, err);
   const int per_real = (m.R > 1 || max_states > 0) ? 1 : 0;
-  k_warm_live<<<std::min(grid_for(est), kPartBlocks), kBlock, 0, s>>>(
+  // 16 rows per thread and one count added to the total per block
+  k_warm_live<<<std::min(grid_for(cdiv(est, 16)), 512), kBlock, 0, s>>>(
       m, k, ctl, c.dist, c.pay, per_real, ball, err);
   if (max_states > 0)
     k_warm_cap_judge<<<1, 1, 0, s>>>(m.R, max_states, ball, err);
