@@ -220,8 +220,13 @@ paces_status paces_init_state(const paces_model* m, const paces_run_params* p,
                               void* hip_stream, paces_sim** out);
 paces_status paces_free_sim(paces_sim* s);
 
-/* Advance n_steps time steps (asynchronous on the stream except where the
- * host needs a device count to size the next launch).  With the
+/* Advance n_steps time steps on the stream.  Each step ends with one host
+ * synchronisation: its last kernel mirrors the step's counts and error
+ * latch into mapped host memory, and the host reads them because a row,
+ * table or state-cap overflow is resolved on the host (more room, or a cut
+ * selection) and the step repeated before the next one is enqueued.  The
+ * call returns when the last step is complete; the records stay on the
+ * device (paces_series copies them).  With the
  * environment variable PACES_LOG set to a file name (1: paces_log.csv),
  * every step's records are appended to it as CSV lines
  * "step,realization,<12 fields>,<N populations>". */
