@@ -867,7 +867,7 @@ void stage_select(paces_sim* s, bool counted, hipStream_t st,
                 std::min(bucket(s->nS), s->cap), s->err, st);
   if (s->warm_step)
     warm_begin(s->m->dm, s->ctl, s->midx, s->side[s->cur], s->wb, s->cnt,
-               s->nS, s->scan_tmp, s->err, st);
+               s->nS, s->has_holes, s->scan_tmp, s->err, st);
 }
 
 // expand + merge + build of the columns from the previous step's graph, in
@@ -1108,7 +1108,8 @@ paces_status launch_step_graph(paces_sim* s, int64_t est, bool counted,
       s->fresh ? 1 : 0, counted ? 1 : 0, s->fresh ? s->p.k_init : s->p.k,
       s->launched, s->K_last, est, std::min(bucket(s->nS), s->cap),
       int64_t(s->tmask), s->tune.term_rows, s->p.krylov_order,
-      s->p.taylor_order, s->chunks, s->warm_step ? 1 : 0};
+      s->p.taylor_order, s->chunks, s->warm_step ? 1 : 0,
+      s->has_holes ? 1 : 0};
   for (auto& g : s->graphs)
     if (g.key == key) {
       g.used = ++s->graph_clock;

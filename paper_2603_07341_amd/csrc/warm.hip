@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(kBlock)
 __global__ void __launch_bounds__(kBlock)
     k_warm_mark(DevModel m, StepCtl* ctl, const uint32_t* midx,
                 const uint64_t* pay, uint8_t* dist, uint32_t* cnt_m,
-                const int* err) {
+                int holes, const int* err) {
   __shared__ uint32_t bins[kMaxReal];
   if (*err) return;
   const int64_t nM = ctl->nM;
@@ -180,6 +180,7 @@ __global__ void __launch_bounds__(kBlock)
     count_flush(m.R, bins, cnt_m);
   }
   if (gtid() == 0) {
+    if (!holes) ctl->nfree = 0;
     ctl->n_staged = 0;
     ctl->gstart[0] = 0;
     ctl->gstart[1] = 0;
@@ -645,16 +646,20 @@ __global__ void __launch_bounds__(kBlock)
 
 void warm_begin(const DevModel& m, StepCtl* ctl, const uint32_t* midx,
                 const Side& c, const WarmBufs& wb, uint32_t* cnt_m,
-                int64_t n_old, uint32_t* scan_tmp, int* err, hipStream_t s) {
+                int64_t n_old, bool holes, uint32_t* scan_tmp, int* err,
+                hipStream_t s) {
   k_warm_fill<<<grid_for(cdiv(n_old, 4)), kBlock, 0, s>>>(c.dist, ctl, err);
-  // holes, ascending, into the free list
-  const int g = tiles_for(n_old);
-  k_dist_count<<<g, kBlock, 0, s>>>(c.dist, &ctl->n_old, int(kHole), scan_tmp);
-  tile_sums_scan(scan_tmp, &ctl->n_old, &ctl->nfree, err, s);
-  k_dist_write<<<g, kBlock, 0, s>>>(1, nullptr, c.dist, &ctl->n_old,
-                                    int(kHole), scan_tmp, nullptr, wb.freel);
+  if (holes) {
+    // holes, ascending, into the free list
+    const int g = tiles_for(n_old);
+    k_dist_count<<<g, kBlock, 0, s>>>(c.dist, &ctl->n_old, int(kHole),
+                                      scan_tmp);
+    tile_sums_scan(scan_tmp, &ctl->n_old, &ctl->nfree, err, s);
+    k_dist_write<<<g, kBlock, 0, s>>>(1, nullptr, c.dist, &ctl->n_old,
+                                      int(kHole), scan_tmp, nullptr, wb.freel);
+  }
   k_warm_mark<<<grid_for(n_old), kBlock, 0, s>>>(m, ctl, midx, c.pay, c.dist,
-                                                  cnt_m, err);
+                                                  cnt_m, holes ? 1 : 0, err);
 }
 
 void warm_round(const DevModel& m, int Wi, int prec, const Side& c, int r,

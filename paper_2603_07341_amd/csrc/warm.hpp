@@ -51,11 +51,13 @@ struct WarmBufs {
 };
 
 // Distances of the rows in [0, n_old): kHole kept, 0 on M (midx[0, nM)),
-// kFar elsewhere; the holes into freel (ctl->nfree); |M| per realization
-// into cnt_m; the step's other counts cleared.
+// kFar elsewhere; the holes into freel (ctl->nfree; holes false: the set
+// has none, and the free list is not built); |M| per realization into
+// cnt_m; the step's other counts cleared.
 void warm_begin(const DevModel& m, StepCtl* ctl, const uint32_t* midx,
                 const Side& c, const WarmBufs& wb, uint32_t* cnt_m,
-                int64_t n_old, uint32_t* scan_tmp, int* err, hipStream_t s);
+                int64_t n_old, bool holes, uint32_t* scan_tmp, int* err,
+                hipStream_t s);
 // Round r (1..k): live rows at distance r-1 mark their neighbours inside
 // the set at distance r and hand the slots whose neighbour is outside it
 // on as candidates; states found in round r-1 hand on every slot.
