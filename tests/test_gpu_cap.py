@@ -131,3 +131,66 @@ def test_fixed_size_truncation_matches_oracle(over, R):
         assert_amps(ra, oa, 1e-10, steps=steps)
         for g, o in zip(gs.observations(r), os_.observations()):
             assert g["n_M"] == o["n_M"] and g["n_S"] == o["n_S"]
+
+
+def _ball_size(model, keys, k):
+    """|B_k(keys)| by repeated neighbour sets on the host."""
+    W = keys.shape[1]
+    ball = {tuple(r) for r in keys.tolist()}
+    front = keys
+    for _ in range(k):
+        nb, ex, _, _ = model.neighbors(front)
+        cand = nb[ex].reshape(-1, W)
+        fresh = {tuple(r) for r in cand.tolist()} - ball
+        ball |= fresh
+        front = np.array(sorted(fresh), dtype=np.uint64).reshape(-1, W)
+        if len(front) == 0:
+            break
+    return len(ball)
+
+
+def test_ball_beyond_the_rows_is_cut_like_the_oracle():
+    """ring16 under a cap of 30000 states keeps its row capacity at the
+    initial 65536 (a capped run grows rows only towards the cap), while the
+    ball of the uncut selection grows past that once the cap binds.  Such a
+    step runs out of rows before the ball is counted; the first cut's q
+    comes from the last record, so the step is cut without the count, where
+    the oracle counts the ball and cuts.  After 30 GPU steps, four steps are
+    each redone by the oracle from the GPU state before them (the cut's
+    ties are then decided on the same weights): M and S bit for bit,
+    amplitudes within 1e-10, and the uncut ball, measured on the host from
+    that state, is beyond the rows."""
+    cfg = dict(WL.CONFIGS["ring16"])
+    p = WL.model_params(cfg)
+    cap = 30000
+    run = dict(WL.run_params(cfg), max_states=cap)
+    init = WL.initial_state(cfg)
+    gs = P.Sim(P.Model(p), run, *init)
+    om = O.Model(p)
+    th2 = run["theta"] ** 2
+    gs.step(30)
+    for step in range(4):
+        k0, a0 = gs.state()
+        rec = gs.series(gs.num_records() - 1, 1)[0]
+        keep = (a0.real ** 2 + a0.imag ** 2) >= th2
+        ball = _ball_size(om, k0[keep], cfg["k"])
+        assert ball > 65536, (step, ball)
+        gs.step(1)
+        os_ = O.Sim(om, run, *init)
+        os_.set_state(k0, a0, rec[0])
+        os_.set_prev_counts(rec[7], rec[8])
+        os_.step(1)
+        for which in (O.SET_M, O.SET_S):
+            assert_same_set(gs.get_set(which), os_.get_set(which),
+                            "step %d set %d" % (step, which))
+        gk, ga = sort_rows(*gs.state())
+        ok, oa = os_.state()
+        assert np.array_equal(gk, ok)
+        assert_amps(ga, oa, 1e-10)
+        go = gs.observations()[-1]
+        oo = dict(os_.observations()[-1])
+        oo["mass_total"] += rec[6]
+        assert go["n_S"] <= cap
+        check_obs(go, oo, 1e-10, width=oo["E_max"] - oo["E_min"],
+                  drop=dropped(k0, a0, ok))
+        assert oo["n_M"] < np.count_nonzero(keep)  # the cut was active
