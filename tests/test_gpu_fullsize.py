@@ -1,10 +1,11 @@
 """GPU vs oracle at the benchmark's sizes, in the launch configuration the
 benchmark times.
 
-ring16 (the throughput workload): the GPU runs the 130 warm-up steps of
-the benchmark (|S| 4.3e6), autotunes as the benchmark does and takes one
-more step with the benchmark's profiling level; the oracle takes the same
-step from the same state.  The whole result is compared: M and S bit for
+ring16 (the throughput workload): the GPU grows the set as the benchmark
+does (steps until |S| >= 1e7), autotunes, takes the benchmark's 5 warm-up
+steps and then its first timed step (|S| 1.16e7, an in-place step from the
+previous graph) with the benchmark's profiling level; the oracle takes the
+same step from the same state.  The whole result is compared: M and S bit for
 bit, amplitudes within 1e-10, the record's observables; then the same for
 one order-10 Krylov step (the benchmark's Krylov form).
 
@@ -67,18 +68,24 @@ def test_ring16_bench_window_step_matches_oracle():
     cfg = dict(WL.CONFIGS["ring16"])
     params = WL.model_params(cfg)
     gs = P.Sim(P.Model(params), WL.run_params(cfg), *WL.initial_state(cfg))
-    gs.step(130)
+    grown = 0
+    while gs.size() < 10_000_000 and grown < 400:
+        gs.step(1)
+        grown += 1
     gs.autotune(steps=2)
+    gs.step(5)
     keys, amps = gs.state()
     prev = gs.observations()[-1]
-    assert len(keys) > 4_000_000
+    print("ring16: %d + 5 steps, oracle step from %d rows" % (grown, len(keys)),
+          flush=True)
+    assert len(keys) > 10_000_000
     gs.profile(True, kernels_only=True)
     gs.step(1)
     gs.profile(False)
     os_ = oracle_step_from(cfg, params, keys, amps, prev["t"])
     n = compare_step(gpu_result(gs), gs.observations()[-1],
                      prev["mass_total"], os_, 1e-10, (keys, amps))
-    assert n > 4_000_000
+    assert n > 10_000_000
     # the Krylov form: an order-10 step from the same state
     gk = P.Sim(P.Model(params), dict(WL.run_params(cfg), krylov_order=10),
                *WL.initial_state(cfg))
