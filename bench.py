@@ -721,6 +721,28 @@ def form_batched(args, stream):
     _, el_b = timed(lambda: b.step(n, stream=stream))
     rb = b.series(0, n, stream)
     upd_b = float(rb[:, :, 7].sum())
+    # the batched Clenshaw launch (all realizations in one grid), timed by
+    # its own dispatches over two further steps
+    b.profile(True, kernels_only=True)
+    b.profile_reset()
+    nr = b.num_records()
+    b.step(2, stream=stream)
+    prof = b.profile_get(stream)
+    b.profile(False)
+    r2 = b.series(nr, 2, stream)
+    nl = prof["launches"]["term"]
+    ms = prof["ms"]["term"] / max(nl, 1)
+    A = 8 if cfg.get("precision", 64) == 32 else 16
+    spec_row = 5 * A + 4 * bm.D + 12
+    states = float(r2[:, :, 7].sum()) / 2.0
+    term = {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "launches": nl, "avg_ms": ms, "states_per_launch": states,
+            "bytes_per_state": spec_row,
+            "bytes_per_state_rule": "5A + 4D + 12 per state and term",
+            "achieved": spec_row * states / (ms * 1e-3) / 1e9 if nl else 0.0,
+            "achieved_kernel_bytes":
+                prof["term_bytes"] / max(nl, 1) / (ms * 1e-3) / 1e9 if nl else 0.0}
+    term["frac"] = term["achieved"] / HBM_PEAK_GBS
     del b
     el_s, upd_s = 0.0, 0.0
     for r in range(args.batch_singles):
@@ -737,7 +759,8 @@ def form_batched(args, stream):
             "single_ms_per_step_per_realization": per_real_single * 1e3 / n,
             "speedup_vs_sequential": per_real_single * bm.R / el_b,
             "S_final_total": int(rb[-1, :, 7].sum()),
-            "S_final_min_max": [int(rb[-1, :, 7].min()), int(rb[-1, :, 7].max())]}
+            "S_final_min_max": [int(rb[-1, :, 7].min()), int(rb[-1, :, 7].max())],
+            "term_roofline": term}
 
 
 def form_adjoint(args, stream):
