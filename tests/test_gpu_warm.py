@@ -147,3 +147,48 @@ def test_warm_steps_under_a_state_cap_that_binds_every_step():
     kc, ac = full_state(cold)
     assert np.array_equal(kw, kc)
     assert np.array_equal(aw, ac)
+
+
+def test_in_place_step_repeats_its_propagation_when_the_series_grows():
+    """A 6-site chain (cutoff 12, g 1, dt 0.5) grown from one state with
+    k_init 1 and then k 6: the spectral interval widens so fast that each of
+    the next steps needs more Chebyshev terms than the K + 2 launches the
+    host enqueued from the step before.  An in-place step has committed its
+    set by then, so only its propagation and observables are repeated with
+    more launches.  Every step against the oracle (sets bit for bit,
+    amplitudes within 1e-10, observables) and against steps from scratch."""
+    from tests.gpu_helpers import (assert_amps, assert_same_set, check_obs,
+                                   dropped)
+    cfg = dict(WL.CONFIGS["ring12"])
+    cfg.update(extent=[6, 1, 1], cutoff=[12], g=[1.0], dt=0.5, k_init=1,
+               k=6, theta=1e-7)
+    p = WL.model_params(cfg)
+    run = WL.run_params(cfg)
+    init = WL.initial_state(cfg)
+    warm = P.Sim(P.Model(p), run, *init)
+    warm.set_tuning(warm=2)
+    cold = P.Sim(P.Model(p), run, *init)
+    cold.set_tuning(warm=0)
+    os_ = O.Sim(O.Model(p), run, *init)
+    acc = 0.0
+    for step in range(4):
+        prev = os_.state()
+        warm.step(1)
+        cold.step(1)
+        os_.step(1)
+        rw, rc = warm.series(step, 1), cold.series(step, 1)
+        assert np.array_equal(rw[..., EXACT], rc[..., EXACT]), step
+        for which in (O.SET_M, O.SET_S):  # both sorted by key
+            assert_same_set(set_rows(warm, which)[:, 1:], os_.get_set(which),
+                            "step %d set %d" % (step, which))
+        kw, aw = full_state(warm)
+        ok, oa = os_.state()
+        assert np.array_equal(kw[:, 1:], ok), step
+        assert_amps(aw, oa, 1e-10, steps=step + 1)
+        go, oo = warm.observations()[-1], os_.observations()[-1]
+        acc += check_obs(go, oo, 1e-10, width=oo["E_max"] - oo["E_min"],
+                         drop=dropped(prev[0], prev[1], ok),
+                         steps_before=step, mass_prior=acc)
+    K = warm.series()[:, 9].astype(int)
+    # each step after the first needed more than the K + 2 launches enqueued
+    assert np.all(K[1:] > K[:-1] + 2), K
