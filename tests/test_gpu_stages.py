@@ -63,6 +63,37 @@ def test_stage_order_is_enforced():
     assert s.num_records() == 2
 
 
+def test_half_done_in_place_step_must_be_finished():
+    """Once the expansion stage of an in-place step (one from the previous
+    step's graph) has run, the set is already the new one while the
+    amplitudes are still phi: a full step refuses to abandon it, and
+    finishing its stages gives what a fused step gives.  A staged step that
+    has only selected may be abandoned."""
+    cfg = dict(WL.CONFIGS["ring16"])
+    params = WL.model_params(cfg)
+    run = WL.run_params(cfg)
+    init = WL.initial_state(cfg)
+    a = P.Sim(P.Model(params), run, *init)
+    b = P.Sim(P.Model(params), run, *init)
+    a.step(3)
+    b.step(3)
+    b.run_stage("select")
+    b.step(1)  # abandons the selection
+    a.step(1)
+    b.run_stage("select")
+    b.run_stage("expand")
+    with pytest.raises(P.PacesError) as ei:
+        b.step(1)
+    assert ei.value.status == 7
+    for st in STAGES[2:]:
+        b.run_stage(st)
+    a.step(1)
+    ka, va = sort_rows(*a.state())
+    kb, vb = sort_rows(*b.state())
+    assert np.array_equal(ka, kb) and np.array_equal(va, vb)
+    assert a.num_records() == b.num_records() == 5
+
+
 def test_propagate_oracle_set_at_size():
     """S = every ring16 state with at most 6 phonons (1.19e6 states), phi
     seeded; with theta = 0 and k = 0 the step is exp(-i H_S dt) phi on S.
