@@ -76,7 +76,9 @@ __global__ void __launch_bounds__(kBlock)
     bessel_miller(x, kcap, J);
   }
   __syncthreads();
-  const double thresh = ldexp(tol, -8);
+  // the step's own rule (omitted tail within tol): a node's x is at most
+  // the step's, so its term count is too
+  const double thresh = ldexp(tol, -2);
   double last = 0;
   for (int k = threadIdx.x; k <= kcap; k += blockDim.x)
     if (fabs(J[k]) > thresh) last = fmax(last, double(k));

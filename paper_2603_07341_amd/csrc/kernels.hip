@@ -746,9 +746,11 @@ __global__ void __launch_bounds__(kBlock)
     bessel_miller(x, kcap, J);
   }
   __syncthreads();
-  // K = 1 + the last k with |J_k| above tol * 2^-8 (beyond x the J_k
-  // decrease monotonically, so every later term is below it too)
-  const double thresh = ldexp(tol, -8);
+  // K = 1 + the last k with |J_k| above tol / 4.  Beyond x each J_k is
+  // below half the one before (J_{k+1} / J_k < x / (2k + 2) before the
+  // first zero of J_k), so the omitted tail sum_{k>=K} |c_k| =
+  // 2 sum |J_k| <= 4 |J_K| stays within tol (|T_k| <= 1 on the interval)
+  const double thresh = ldexp(tol, -2);
   double last = 0;
   for (int k = threadIdx.x; k <= kcap; k += blockDim.x)
     if (fabs(J[k]) > thresh) last = fmax(last, double(k));

@@ -249,7 +249,8 @@ __global__ void __launch_bounds__(64)
     bessel_miller(x, kcap, J);
   }
   __syncthreads();
-  const double thresh = ldexp(tol, -8);
+  // the Clenshaw step's rule: terms up to the last |J_k| above tol / 4
+  const double thresh = ldexp(tol, -2);
   double last = 0;
   for (int k = l; k <= kcap; k += 64)
     if (fabs(J[k]) > thresh) last = fmax(last, double(k));
