@@ -65,6 +65,10 @@ def main():
                          "state before timing (results do not depend on it)")
     ap.add_argument("--batch-steps", type=int, default=40)
     ap.add_argument("--batch-singles", type=int, default=8)
+    ap.add_argument("--singles-only", action="store_true",
+                    help=argparse.SUPPRESS)  # the batched form's child runs
+    ap.add_argument("--batched-only", action="store_true",
+                    help=argparse.SUPPRESS)
     ap.add_argument("--adjoint-steps", type=int, default=200)
     ap.add_argument("--long-steps", type=int, default=500,
                     help="steps of the complex64 vs complex128 long run")
@@ -121,6 +125,14 @@ def main():
     import workloads as WL
 
     torch.cuda.set_device(0)
+    if args.singles_only:
+        print(json.dumps(batch_singles(args, torch.cuda.current_stream())),
+              flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps(batch_run(args, torch.cuda.current_stream())),
+              flush=True)
+        return
     if args.paper_1d is not None or args.paper_agg is not None:
         print(json.dumps(paper_run(args)), flush=True)
         return
@@ -706,33 +718,36 @@ def form_taylor(args, state, t_start, rec_ref, el_ref, stream):
                               "avg_ms": ms}}
 
 
-def form_batched(args, stream):
-    """64 disorder realizations of the 6x6 lattice (complex64) in one sim,
-    against single-realization sims of the first few realizations run one
-    after another, both from the initial state for the same steps.  The
-    single runs go first: after a sim of ~10^8 rows is freed, the device
-    allocations of the next sims' growth (inside their timed steps) are
-    several times slower, which would charge the singles for the batch."""
+def batch_singles(args, stream):
+    """Single-realization sims of the first batch_singles realizations of
+    sq6x6, one after another, batch_steps steps each from the initial state:
+    seconds and updates."""
     import paper_2603_07341_amd as P
     import workloads as WL
     cfg = WL.CONFIGS["sq6x6"]
-    n = args.batch_steps
     el_s, upd_s = 0.0, 0.0
     for r in range(args.batch_singles):
         m = P.Model(WL.model_params(cfg, r))
         s = P.Sim(m, WL.run_params(cfg), *WL.initial_state(cfg), stream=stream)
-        _, el = timed(lambda: s.step(n, stream=stream))
+        _, el = timed(lambda: s.step(args.batch_steps, stream=stream))
         el_s += el
-        upd_s += float(s.series(0, n, stream)[:, 7].sum())
+        upd_s += float(s.series(0, args.batch_steps, stream)[:, 7].sum())
         del s
-    per_real_single = el_s / args.batch_singles
+    return {"seconds": el_s, "updates": upd_s}
+
+
+def batch_run(args, stream):
+    """The 64 sq6x6 realizations in one sim, batch_steps steps from the
+    initial state: seconds, updates, the final sizes, and the batched
+    Clenshaw launch's rate over two further steps."""
+    import paper_2603_07341_amd as P
+    import workloads as WL
+    cfg = WL.CONFIGS["sq6x6"]
+    n = args.batch_steps
     bm = P.Model(WL.batch_params(cfg))
     b = P.Sim(bm, WL.run_params(cfg), *WL.initial_state(cfg), stream=stream)
-    print("batched: %d realizations x %d steps" % (bm.R, n), file=sys.stderr,
-          flush=True)
     _, el_b = timed(lambda: b.step(n, stream=stream))
     rb = b.series(0, n, stream)
-    upd_b = float(rb[:, :, 7].sum())
     # the batched Clenshaw launch (all realizations in one grid), timed by
     # its own dispatches over two further steps
     b.profile(True, kernels_only=True)
@@ -755,16 +770,54 @@ def form_batched(args, stream):
             "achieved_kernel_bytes":
                 prof["term_bytes"] / max(nl, 1) / (ms * 1e-3) / 1e9 if nl else 0.0}
     term["frac"] = term["achieved"] / HBM_PEAK_GBS
-    del b
-    return {"realizations": bm.R, "steps": n,
-            "value": upd_b / el_b, "unit": "updates/s",
-            "ms_per_step": el_b * 1e3 / n,
-            "single_value": upd_s / el_s,
-            "single_ms_per_step_per_realization": per_real_single * 1e3 / n,
-            "speedup_vs_sequential": per_real_single * bm.R / el_b,
+    return {"realizations": bm.R, "seconds": el_b,
+            "updates": float(rb[:, :, 7].sum()),
             "S_final_total": int(rb[-1, :, 7].sum()),
             "S_final_min_max": [int(rb[-1, :, 7].min()), int(rb[-1, :, 7].max())],
             "term_roofline": term}
+
+
+def _child(args, flag):
+    """One of the batched form's runs in a fresh process (last stdout line
+    is its JSON)."""
+    import subprocess
+    child = subprocess.run(
+        [sys.executable, os.path.abspath(__file__), flag,
+         "--batch-steps", str(args.batch_steps),
+         "--batch-singles", str(args.batch_singles)],
+        capture_output=True, text=True, timeout=900)
+    if child.returncode != 0:
+        raise RuntimeError("%s run failed: %s" % (flag, child.stderr[-2000:]))
+    return json.loads(child.stdout.strip().splitlines()[-1])
+
+
+def form_batched(args, stream):
+    """64 disorder realizations of the 6x6 lattice (complex64) in one sim,
+    against single-realization sims of the first few realizations run one
+    after another, both from the initial state for the same steps.  Each
+    side runs in a fresh child process: after sims of 10^7 to 10^8 rows
+    have been freed, the device allocations of later sims' growth (inside
+    their timed steps) are several times slower, which would charge either
+    side for the forms run before it."""
+    n = args.batch_steps
+    print("batched: 64 realizations x %d steps, singles x %d" % (
+        n, args.batch_singles), file=sys.stderr, flush=True)
+    single = _child(args, "--singles-only")
+    batch = _child(args, "--batched-only")
+    el_s, upd_s = single["seconds"], single["updates"]
+    per_real_single = el_s / args.batch_singles
+    el_b = batch["seconds"]
+    R = batch["realizations"]
+    return {"realizations": R, "steps": n,
+            "value": batch["updates"] / el_b, "unit": "updates/s",
+            "ms_per_step": el_b * 1e3 / n,
+            "single_value": upd_s / el_s,
+            "single_ms_per_step_per_realization": per_real_single * 1e3 / n,
+            "speedup_vs_sequential": per_real_single * R / el_b,
+            "S_final_total": batch["S_final_total"],
+            "S_final_min_max": batch["S_final_min_max"],
+            "term_roofline": batch["term_roofline"],
+            "processes": "each side in a fresh child process"}
 
 
 def form_adjoint(args, stream):
