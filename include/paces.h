@@ -320,8 +320,9 @@ paces_status paces_series(paces_sim* s, int64_t first, int64_t n,
 paces_status paces_series_field(paces_sim* s, int32_t field, void* dev_out,
                                 int64_t first, int64_t n, void* hip_stream);
 
-/* Current state: *n rows; keys[n*W], amps[2n], real[n] the realization of
- * each row (host; each may be NULL, all NULL to query the size).
+/* Current state: *n states in row order (rows that in-place steps left
+ * empty are skipped); keys[n*W], amps[2n], real[n] the realization of
+ * each state (host; each may be NULL, all NULL to query the size).
  * Synchronises. */
 paces_status paces_get_state(paces_sim* s, int64_t* n, uint64_t* keys,
                              double* amps, int32_t* real, void* hip_stream);
