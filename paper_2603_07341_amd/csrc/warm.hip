@@ -481,7 +481,7 @@ __global__ void __launch_bounds__(kBlock)
   if (per_real) count_flush(m.R, bins, ball);
 }
 
-__global__ void k_warm_cap_judge(int R, int64_t max_states,
+__global__ void k_warm_cap_over(int R, int64_t max_states,
                                  const uint32_t* ball, int* err) {
   if (*err) return;
   for (int r = 0; r < R; ++r)
@@ -718,7 +718,7 @@ void warm_sizes(const DevModel& m, const Side& c, int k, StepCtl* ctl,
   k_warm_live<<<std::min(grid_for(cdiv(est, 16)), 512), kBlock, 0, s>>>(
       m, k, ctl, c.dist, c.pay, per_real, ball, err);
   if (max_states > 0)
-    k_warm_cap_judge<<<1, 1, 0, s>>>(m.R, max_states, ball, err);
+    k_warm_cap_over<<<1, 1, 0, s>>>(m.R, max_states, ball, err);
 }
 
 int warm_commit(const DevModel& m, int Wi, int prec, const Side& c, int k,
